@@ -1,0 +1,258 @@
+"""Pins for the oracle's spaQR factorization, apply, CPQR and GMRES.
+
+Each pin checks the oracle against something other than itself: exactness of
+the factorization at eps = 0 (Section 3: with no sparsification spaQR is
+nested-dissection Householder QR), a dense Householder QR of the whole
+matrix, LAPACK's column-pivoted QR, numpy's dense solve, orthogonality, the
+truncation bound of the ratio rule, and SciPy's GMRES.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from problems import convdiff, config_problem, make_rhs
+from oracle.ordering import order_grid
+from oracle import spaqr, gmres
+from oracle.cpqr import cpqr_ratio, apply_reflectors
+
+
+def _ahat(A, F):
+    Dc = F.Dc
+    Ah = (sp.csr_matrix(A) @ sp.diags(Dc)).tocsr()
+    return Ah[F.perm][:, F.perm].toarray()
+
+
+@pytest.mark.parametrize("dims,L,beta", [((32, 32), 5, (10.0, 10.0)),
+                                          ((8, 8, 8), 4, (20.0, -5.0, 3.0)),
+                                          ((24, 24), 5, (-40.0, 7.0))])
+def test_eps0_exact_solve(dims, L, beta):
+    """eps = 0: M^{-1} = A^{-1} up to roundoff (relative residual <= 1e-13)."""
+    A = convdiff(dims, beta)
+    o = order_grid(dims, L)
+    F = spaqr.factor(A, o, 0.0, check_skipped=True)
+    b = make_rhs(A.shape[0], 2, seed=3)
+    x = spaqr.apply(F, b)
+    res = np.linalg.norm(A @ x - b, axis=0) / np.linalg.norm(b, axis=0)
+    assert res.max() <= 1e-13
+    # the skipped non-ancestor updates are zero up to roundoff (Lemma 2)
+    assert F.max_skipped_update <= 1e-13
+
+
+@pytest.mark.parametrize("dims,L", [((16, 16), 4), ((6, 6, 6), 3)])
+def test_solution_matches_dense_solve(dims, L):
+    A = convdiff(dims, (7.0,) * len(dims))
+    o = order_grid(dims, L)
+    F = spaqr.factor(A, o, 0.0)
+    b = make_rhs(A.shape[0], 1, seed=1)[:, 0]
+    x = spaqr.apply(F, b)
+    xd = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(x - xd) <= 1e-12 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("dims,L", [((16, 16), 4), ((12, 12), 4), ((6, 6, 6), 3)])
+def test_direct_r_matches_dense_qr(dims, L):
+    """No scaling, no sparsification (skip >= L): the assembled block R equals
+    the R of a dense Householder QR of the permuted, pre-scaled matrix up to
+    row signs (QR is unique up to signs; R^T R = A^T A)."""
+    A = convdiff(dims, (5.0, -9.0, 2.0)[:len(dims)])
+    o = order_grid(dims, L)
+    F = spaqr.factor(A, o, 0.0, skip=L + 1)
+    R = spaqr.assembled_r(F)
+    Ah = _ahat(A, F)
+    Rd = np.linalg.qr(Ah, mode="r")
+    assert np.allclose(np.abs(R), np.abs(Rd), rtol=0, atol=1e-12 * np.abs(Rd).max())
+    # and R^T R = A^T A
+    assert np.allclose(R.T @ R, Ah.T @ Ah, atol=1e-12)
+
+
+def test_front_reflectors_orthogonal():
+    A = convdiff((16, 16), (3.0, 4.0))
+    o = order_grid((16, 16), 4)
+    F = spaqr.factor(A, o, 1e-3)
+    worst = 0.0
+    for op in F.ops:
+        V, tau = (op[5], op[6]) if op[0] == "front" else (op[4], op[5])
+        if V.shape[1] == 0:
+            continue
+        Q = apply_reflectors(V, tau, np.eye(V.shape[0]), transpose=False)
+        worst = max(worst, np.abs(Q.T @ Q - np.eye(Q.shape[0])).max())
+    assert worst <= 1e-13
+
+
+def test_qt_preserves_norms():
+    A = convdiff((24, 24), (30.0, -10.0))
+    o = order_grid((24, 24), 5)
+    F = spaqr.factor(A, o, 1e-2)
+    v = make_rhs(A.shape[0], 3, seed=9)
+    w = spaqr.apply_qt(F, v)
+    assert np.allclose(np.linalg.norm(w, axis=0), np.linalg.norm(v, axis=0), rtol=1e-13)
+
+
+def test_scaling_gives_identity_blocks():
+    """After block-diagonal scaling every interface has A_pp = I (Section 2.6):
+    U_pp^T A_pp R_pp^{-1} = I, checked through the stored U and R."""
+    A = convdiff((24, 24), (30.0, -10.0))
+    o = order_grid((24, 24), 5)
+    F = spaqr.factor(A, o, 1e-2)
+    nsc = 0
+    for op in F.ops:
+        if op[0] != "scale":
+            continue
+        V, tau, R = op[4], op[5], op[6]
+        Ui = apply_reflectors(V, tau, np.eye(V.shape[0]), transpose=False)
+        App = Ui @ R
+        Ut = apply_reflectors(V, tau, App, transpose=True)
+        M = sla.solve_triangular(R, Ut.T, trans="T").T
+        assert np.abs(M - np.eye(M.shape[0])).max() <= 1e-12 * max(1.0, np.linalg.cond(R))
+        nsc += 1
+    assert nsc > 0
+
+
+# ----------------------------------------------------------------------------
+# CPQR with the ratio rule (Section 4 setup: |R_ii| / |R_11| >= eps)
+def _decaying(rng, P, m, rate):
+    U, _ = np.linalg.qr(rng.standard_normal((P, P)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    k = min(P, m)
+    s = rate ** np.arange(k)
+    S = np.zeros((P, m))
+    S[np.arange(k), np.arange(k)] = s
+    return U @ S @ Vt.T
+
+
+@pytest.mark.parametrize("P,m,rate,eps", [(30, 80, 0.7, 1e-3), (40, 25, 0.5, 1e-6),
+                                          (12, 200, 0.9, 1e-2), (25, 60, 0.6, 0.0)])
+def test_cpqr_rank_matches_lapack(P, m, rate, eps):
+    rng = np.random.default_rng(P * m)
+    C = _decaying(rng, P, m, rate)
+    r, V, tau, W, rdiag, piv = cpqr_ratio(C, eps)
+    # LAPACK dgeqp3 (norm downdating) under the same rule
+    _, Rl, pl = sla.qr(C, pivoting=True)
+    d = np.abs(np.diag(Rl))
+    if eps == 0.0:
+        rl = min(P, m)
+    else:
+        ok = d >= eps * d[0]
+        rl = int(np.argmin(ok)) if not ok.all() else ok.size
+    assert r == rl
+    assert np.allclose(rdiag, d[:r], rtol=1e-10)
+    assert np.all(np.diff(rdiag) <= 1e-12 * rdiag[0])
+    # Q orthogonal
+    Q = apply_reflectors(V, tau, np.eye(P), transpose=False)
+    assert np.abs(Q.T @ Q - np.eye(P)).max() <= 1e-13
+    # W = first r rows of Q^T C, and the dropped rows obey the stopping rule
+    QtC = apply_reflectors(V, tau, C, transpose=True)
+    assert np.allclose(QtC[:r], W, atol=1e-13 * np.abs(C).max())
+    if eps > 0 and r < min(P, m):
+        dropped = np.linalg.norm(QtC[r:])
+        assert dropped <= math.sqrt(m - r) * eps * rdiag[0] * (1 + 1e-12)
+
+
+def test_cpqr_degenerate():
+    r, V, tau, W, rdiag, piv = cpqr_ratio(np.zeros((5, 0)), 1e-2)
+    assert r == 0 and W.shape == (0, 0)
+    r, *_ = cpqr_ratio(np.zeros((5, 7)), 1e-2)
+    assert r == 0
+    # exact rank 2, eps tiny
+    rng = np.random.default_rng(0)
+    C = rng.standard_normal((6, 2)) @ rng.standard_normal((2, 9))
+    r, *_ = cpqr_ratio(C, 1e-10)
+    assert r == 2
+    # ties resolve to the lowest index
+    r, V, tau, W, rdiag, piv = cpqr_ratio(np.eye(4), 0.5)
+    assert r == 4 and list(piv) == [0, 1, 2, 3]
+
+
+# ----------------------------------------------------------------------------
+def test_preconditioner_error_shrinks_with_eps():
+    """||I - M^{-1} A|| = O(eps) (Section 3.3): it must shrink as eps does."""
+    dims = (20, 20)
+    A = convdiff(dims, (25.0, 12.0))
+    o = order_grid(dims, 5)
+    Ad = A.toarray()
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6):
+        F = spaqr.factor(A, o, eps)
+        MA = spaqr.apply(F, Ad)
+        errs.append(np.linalg.norm(np.eye(A.shape[0]) - MA, 2))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1]
+    E = errs[1]
+    if E < 1:
+        # kappa(M^{-1}A) <= (1 + ||E||) / (1 - ||E||)
+        F = spaqr.factor(A, o, 1e-4)
+        s = np.linalg.svd(spaqr.apply(F, Ad), compute_uv=False)
+        assert s[0] / s[-1] <= (1 + E) / (1 - E) * (1 + 1e-8)
+
+
+def test_gmres_one_iteration_at_eps0():
+    P = config_problem("c1")
+    A = P["A"]
+    o = order_grid(P["dims"], P["levels"])
+    F = spaqr.factor(A, o, 0.0)
+    b = make_rhs(A.shape[0], 1, seed=0)[:, 0]
+    x, it, rel = gmres.fgmres(lambda v: A @ v, lambda v: spaqr.apply(F, v), b, 1e-10)
+    assert it == 1 and np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 1e-12
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-3])
+def test_gmres_matches_scipy(eps):
+    """Iteration counts equal SciPy's GMRES on the right-preconditioned operator
+    A M^{-1} (same Krylov space) within +-1."""
+    dims = (32, 32)
+    A = convdiff(dims, (60.0, -25.0))
+    o = order_grid(dims, 5)
+    F = spaqr.factor(A, o, eps)
+    b = make_rhs(A.shape[0], 1, seed=2)[:, 0]
+    x, it, rel = gmres.fgmres(lambda v: A @ v, lambda v: spaqr.apply(F, v), b, 1e-10)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 1e-10
+    N = A.shape[0]
+    op = spla.LinearOperator((N, N), matvec=lambda u: A @ spaqr.apply(F, u))
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    u, info = spla.gmres(op, b, rtol=1e-10, atol=0.0, restart=100, maxiter=10,
+                         callback=cb, callback_type="pr_norm")
+    assert info == 0
+    assert abs(count[0] - it) <= 1
+
+
+def test_iterations_flat_in_n():
+    """Counts stay nearly flat as the grid grows at eps = 1e-2 (Section 4.2)."""
+    its = []
+    for n in (64, 128, 192):
+        A = convdiff((n, n), (50.0, 50.0))
+        o = order_grid((n, n), max(1, math.ceil(math.log2(n * n / 64))))
+        F = spaqr.factor(A, o, 1e-2)
+        b = make_rhs(A.shape[0], 1, seed=0)[:, 0]
+        _, it, rel = gmres.fgmres(lambda v: A @ v, lambda v: spaqr.apply(F, v), b, 1e-10)
+        assert rel <= 1e-10
+        its.append(it)
+    assert max(its) <= 2 * min(its) + 2
+
+
+def test_symbolic_pattern_invariants():
+    """Blocks only ever join ancestor-related clusters, and the fronts of one
+    colour update disjoint blocks."""
+    dims = (32, 32)
+    A = convdiff(dims, (10.0, 10.0))
+    o = order_grid(dims, 5)
+    F = spaqr.factor(A, o, 1e-3)
+    for k, rec in F.stages.items():
+        st, en, nd, lv = rec["clusters"]
+        for (i, j) in rec["pattern_post"]:
+            a, b = nd[i], nd[j]
+            assert a == b or o.is_ancestor(a, b) or o.is_ancestor(b, a)
+        byc = {}
+        for s, (n1, cols, c) in rec["fronts"].items():
+            touched = {(i, j) for i in n1 for j in cols}
+            for other in byc.get(c, []):
+                assert not (touched & other)
+            byc.setdefault(c, []).append(touched)
