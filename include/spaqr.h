@@ -1,0 +1,220 @@
+/*
+ * spaqr.h -- C ABI of the MI355X spaQR engine.
+ *
+ * spaQR (sparsified QR) computes an approximate factorization Q^T A W^{-1} ~ I
+ * of a sparse square matrix A, where Q is a product of orthogonal factors and
+ * W a product of orthogonal and upper-triangular factors, by eliminating a
+ * nested-dissection tree level by level and compressing separator interfaces
+ * to a tolerance eps (Algorithm 2, Sections 2.4-2.8).  M^{-1} = W^{-1} Q^T is
+ * then used as a preconditioner inside GMRES (Section 4).
+ *
+ * Conventions for every call:
+ *   - every call returns a spaqr_status; no exception crosses the ABI;
+ *   - on error the output arguments are left untouched;
+ *   - matrices are FP64 CSR on the host, 0-based, columns sorted, no
+ *     duplicates;
+ *   - dense vectors are column-major n x nrhs with leading dimension ld >= n;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory (for example a PyTorch CUDA/HIP tensor's data pointer);
+ *   - one thread uses a handle at a time; distinct handles are independent.
+ */
+#ifndef SPAQR_H
+#define SPAQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+typedef int spaqr_status;
+#define SPAQR_OK 0          /* success */
+#define SPAQR_ENOCONV 1     /* warning: GMRES hit maxit; x holds the best iterate */
+#define SPAQR_EINVAL (-1)   /* invalid argument (malformed CSR, bad ordering, ...) */
+#define SPAQR_ENOMEM (-2)   /* a host or device allocation failed */
+#define SPAQR_ESINGULAR (-3)/* a front produced an exactly zero diagonal in R_ss */
+#define SPAQR_EDEVICE (-4)  /* a HIP runtime call failed, or no GPU is present */
+
+/* Static, NUL-terminated description of a status code. */
+const char* spaqr_status_string(int status);
+/* Message of the last failed call on the calling thread ("" if none).  The
+ * string stays valid until the next call on that thread. */
+const char* spaqr_last_error(void);
+
+/* ------------------------------------------------------------------ matrix */
+/* Host FP64 CSR (caller-owned; read only during the call that receives it). */
+typedef struct {
+  int64_t n;               /* rows = columns */
+  int64_t nnz;             /* stored entries */
+  const int64_t* rowptr;   /* n + 1 entries */
+  const int32_t* col;      /* nnz entries, sorted within each row */
+  const double* val;       /* nnz entries */
+} spaqr_csr;
+
+/* ---------------------------------------------------------------- ordering */
+/* Geometric modified nested dissection of a dim-dimensional box grid with
+ * sides[0..dim-1] points and lexicographic point index x + n0*y (+ n0*n1*z)
+ * (Section 2.3; geometric partitioning of A^T A for grids, Section 4).
+ * Separators are two grid layers thick (they must cut the graph of A^T A);
+ * a box splits on its longest axis (ties to the lowest axis) at
+ * m = lo + floor((w-2)/2), separator {m, m+1}; separator interfaces are the
+ * classes of the pair of level-k ancestors of the deepest nodes touched on
+ * each side (modified ND, Figs. mnd and mnd_multilvl).
+ * nlevels <= 0 selects ceil(log2(N/64)) (Section 4, setup).
+ * Errors: EINVAL if dim is not 2 or 3, a side is < 1, or a box above the
+ * leaves has its longest extent < 4.  *out is library-owned; release it with
+ * spaqr_ordering_free. */
+typedef struct spaqr_ordering spaqr_ordering;
+spaqr_status spaqr_order_grid(int dim, const int32_t sides[3], int nlevels,
+                              spaqr_ordering** out);
+void spaqr_ordering_free(spaqr_ordering* ord);
+int64_t spaqr_ordering_n(const spaqr_ordering* ord);
+int spaqr_ordering_levels(const spaqr_ordering* ord);
+/* perm[new] = old, n entries (host buffer, caller-allocated). */
+spaqr_status spaqr_ordering_perm(const spaqr_ordering* ord, int64_t* perm);
+/* Clusters of stage k (1 <= k <= L): the nodes of level > k are eliminated;
+ * a node of level k is one cluster; separators of level < k are split into
+ * interfaces.  Each cluster is a contiguous range [start, end) of perm.
+ * Query the count with spaqr_ordering_num_clusters, then fill caller arrays
+ * of that length (any of them may be NULL). */
+int64_t spaqr_ordering_num_clusters(const spaqr_ordering* ord, int stage);
+spaqr_status spaqr_ordering_clusters(const spaqr_ordering* ord, int stage,
+                                     int64_t* start, int64_t* end,
+                                     int64_t* node, int32_t* level);
+/* parent[c] = index of the stage-(k-1) cluster that contains stage-k cluster
+ * c, or -1 if c is eliminated at stage k (Section 2.7 merge). stage >= 2. */
+spaqr_status spaqr_ordering_merge_parents(const spaqr_ordering* ord, int stage,
+                                          int64_t* parent);
+
+/* ----------------------------------------------------------------- options */
+typedef struct {
+  double eps;      /* sparsification tolerance (ratio rule |R_ii|/|R_11|), >= 0 */
+  int skip;        /* levels above the leaves without sparsification (default 2) */
+  int scale;       /* block-diagonal scaling, Section 2.6 (must be 1) */
+  int precision;   /* 32: FP32 blocks and factors, 64: FP64 (default 32) */
+  int restart;     /* GMRES restart length (default 100) */
+  int maxit;       /* GMRES maximum Arnoldi steps (default 1000) */
+} spaqr_opts;
+spaqr_opts spaqr_opts_default(void);
+
+/* ---------------------------------------------------------------- symbolic */
+/* Host-only symbolic analysis of A's pattern under an ordering: per stage the
+ * cluster block pattern, the fronts with their row and column sets and
+ * colours, the fill, and the interface colouring (no device work).
+ * Errors: EINVAL on a malformed CSR, a size mismatch, or a zero diagonal
+ * block pattern.  Release with spaqr_symbolic_free. */
+typedef struct spaqr_symbolic spaqr_symbolic;
+spaqr_status spaqr_analyze(const spaqr_csr* A, const spaqr_ordering* ord,
+                           const spaqr_opts* opts, spaqr_symbolic** out);
+void spaqr_symbolic_free(spaqr_symbolic* sym);
+
+/* Serialized per-stage symbolic information (for tests and tools).
+ * what = 0: block pattern at stage start, pairs (row, col) sorted;
+ *        1: block pattern after the fronts (with fill), pairs sorted;
+ *        2: fronts in cluster order, each record
+ *           [cluster, colour, |n1|, n1..., |cols|, cols...] (cols excludes
+ *           the front itself);
+ *        3: interface colours, pairs (cluster, colour) in cluster order
+ *           (empty if the stage does not sparsify).
+ * Call with buf = NULL to get the length in *len; then with cap >= *len. */
+spaqr_status spaqr_symbolic_stage_info(const spaqr_symbolic* sym, int stage, int what,
+                                       int32_t* buf, int64_t cap, int64_t* len);
+
+/* ------------------------------------------------------------------ factor */
+/* Numeric factorization on the HIP stream `hip_stream` (a hipStream_t; NULL
+ * means the default stream).  The handle owns all device factors and a
+ * device copy of A for the SpMV of spaqr_solve.  The ordering must have been
+ * built for A's grid (same n).
+ * Errors: EINVAL (bad arguments, ord n != A n, opts invalid), ENOMEM,
+ * ESINGULAR (an exactly zero diagonal in some R_ss), EDEVICE. */
+typedef struct spaqr_handle spaqr_handle;
+spaqr_status spaqr_factor(const spaqr_csr* A, const spaqr_ordering* ord,
+                          const spaqr_opts* opts, void* hip_stream,
+                          spaqr_handle** out);
+/* Same, reusing a symbolic analysis made for the same pattern and ordering. */
+spaqr_status spaqr_factor_symbolic(const spaqr_csr* A, const spaqr_symbolic* sym,
+                                   const spaqr_opts* opts, void* hip_stream,
+                                   spaqr_handle** out);
+
+/* x = M^{-1} b = D_c P^T W^{-1} Q^T P b for nrhs columns (Section 2.8).
+ * b and x: n x nrhs column-major with leading dimension ld; device pointers
+ * if on_device != 0, else host pointers.  b and x may alias.  Runs on the
+ * handle's stream and returns after the result is complete.
+ * Errors: EINVAL (NULL pointers, nrhs < 1, ld < n), EDEVICE. */
+spaqr_status spaqr_apply(spaqr_handle* h, const double* b, double* x,
+                         int64_t nrhs, int64_t ld, int on_device);
+
+/* Per-column outcome of spaqr_solve. */
+typedef struct {
+  int32_t iterations;  /* Arnoldi steps taken */
+  int32_t converged;   /* 1 if ||A x - b|| / ||b|| <= tol */
+  double relres;       /* true relative residual of the returned x */
+  double seconds;      /* wall time of the whole solve call */
+} spaqr_solve_info;
+
+/* Right-preconditioned flexible GMRES in FP64 on the device, x0 = 0, until
+ * ||A x - b|| / ||b|| <= tol for each column (Section 4).  Layout as in
+ * spaqr_apply; info (host, nrhs entries, may be NULL) receives per-column
+ * results.  Returns ENOCONV if some column hit maxit (x then holds its best
+ * iterate), EINVAL, EDEVICE. */
+spaqr_status spaqr_solve(spaqr_handle* h, const double* b, double* x,
+                         int64_t nrhs, int64_t ld, int on_device, double tol,
+                         spaqr_solve_info* info);
+
+/* Factorization statistics. */
+typedef struct {
+  int64_t n;                 /* unknowns */
+  int32_t levels;            /* nested-dissection levels L */
+  int32_t precision;         /* 32 or 64 */
+  int64_t factor_bytes;      /* bytes of stored factors (V, tau, T, R, U, Q) */
+  int64_t top_separator;     /* size of the last front (root) when factored */
+  int64_t fronts;            /* number of fronts factored */
+  int64_t interfaces_sparsified;
+  double flops_front;        /* algorithmic flops: front QR + trailing update */
+  double flops_scale;        /* scaling QR + block products */
+  double flops_sparsify;     /* CPQR */
+  double ms_symbolic;        /* host symbolic analysis */
+  double ms_factor;          /* numeric factorization wall time */
+  double ms_phase[4];        /* front, scale, sparsify, merge (device time) */
+} spaqr_stats_t;
+spaqr_status spaqr_stats(const spaqr_handle* h, spaqr_stats_t* out);
+
+/* Sizes of the stage-k clusters after stage k's sparsification (ranks of
+ * sparsified interfaces; unchanged sizes otherwise).  Same query protocol as
+ * spaqr_symbolic_stage_info. */
+spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf,
+                               int64_t cap, int64_t* len);
+
+/* Releases all host and device memory of the handle.  NULL is a no-op. */
+void spaqr_free(spaqr_handle* h);
+
+/* ----------------------------------------------------------------- serving */
+/* Continuous-batching request loop.  Requests (a matrix, its grid ordering,
+ * options and nrhs right-hand sides) are copied at submission, admitted when
+ * their estimated factor memory fits the budget, and factorized stage by
+ * stage together with every other admitted request: each stage's fronts,
+ * scalings and sparsifications of all requests share one launch per phase.
+ * Factored requests are solved with batched multi-RHS FGMRES and retired.
+ * spaqr_submit returns ENOMEM only if the request alone exceeds the budget;
+ * otherwise it is queued.  spaqr_server_step advances every in-flight request
+ * by one stage (or solve) and admits new ones; spaqr_poll returns OK and
+ * fills x (host, n x nrhs, ld = n) and info (nrhs entries) once the ticket
+ * is done, ENOCONV-style warnings included, or SPAQR_EINVAL-free status 2
+ * (SPAQR_PENDING) while it is not. */
+#define SPAQR_PENDING 2
+typedef struct spaqr_server spaqr_server;
+spaqr_status spaqr_server_create(size_t mem_budget, void* hip_stream, spaqr_server** out);
+spaqr_status spaqr_submit(spaqr_server* srv, const spaqr_csr* A, const spaqr_ordering* ord,
+                          const spaqr_opts* opts, const double* b, int64_t nrhs,
+                          double tol, uint64_t* ticket);
+spaqr_status spaqr_server_step(spaqr_server* srv, int* active);
+spaqr_status spaqr_poll(spaqr_server* srv, uint64_t ticket, double* x,
+                        spaqr_solve_info* info);
+void spaqr_server_destroy(spaqr_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPAQR_H */

@@ -1,0 +1,269 @@
+"""MI355X spaQR engine: Python binding over the C ABI of libspaqr.so.
+
+Only argument marshalling lives here; ordering, symbolic analysis,
+factorization, apply and GMRES all run in the native library (host C++ and
+HIP kernels for gfx950).  PyTorch supplies device buffers and the stream.
+
+    ord = order_grid((256, 256))
+    fac = factor(A, ord, eps=1e-2, precision=32)   # A: scipy CSR (FP64)
+    x, info = fac.solve(b, tol=1e-10)              # b: torch CUDA tensor or numpy
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import CSR, Opts, SolveInfo, SpaqrError, check
+
+__all__ = ["order_grid", "analyze", "factor", "GridOrdering", "Symbolic", "Factorization",
+           "Server", "SpaqrError", "load_library"]
+
+
+def load_library():
+    return _abi.load()
+
+
+def _csr_struct(A):
+    indptr = np.ascontiguousarray(A.indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(A.indices, dtype=np.int32)
+    data = np.ascontiguousarray(A.data, dtype=np.float64)
+    s = CSR(A.shape[0], data.shape[0], indptr.ctypes.data_as(C.POINTER(C.c_int64)),
+            indices.ctypes.data_as(C.POINTER(C.c_int32)), data.ctypes.data_as(C.POINTER(C.c_double)))
+    return s, (indptr, indices, data)
+
+
+def make_opts(eps=1e-2, skip=2, precision=32, restart=100, maxit=1000):
+    lib = _abi.load()
+    o = lib.spaqr_opts_default()
+    o.eps, o.skip, o.scale, o.precision, o.restart, o.maxit = float(eps), int(skip), 1, int(precision), \
+        int(restart), int(maxit)
+    return o
+
+
+class GridOrdering:
+    """Geometric modified nested dissection of a grid (spaqr_order_grid)."""
+
+    def __init__(self, dims, levels=0):
+        lib = _abi.load()
+        dims = tuple(int(d) for d in dims)
+        sides = (C.c_int32 * 3)(*(list(dims) + [1] * (3 - len(dims))))
+        h = C.c_void_p()
+        check(lib.spaqr_order_grid(len(dims), sides, int(levels), C.byref(h)), "spaqr_order_grid")
+        self._h = h
+        self.dims = dims
+        self.n = lib.spaqr_ordering_n(h)
+        self.levels = lib.spaqr_ordering_levels(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _abi.load().spaqr_ordering_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def perm(self):
+        out = np.empty(self.n, dtype=np.int64)
+        check(_abi.load().spaqr_ordering_perm(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))),
+              "spaqr_ordering_perm")
+        return out
+
+    def clusters(self, stage):
+        lib = _abi.load()
+        nc = lib.spaqr_ordering_num_clusters(self._h, int(stage))
+        if nc < 0:
+            raise ValueError("bad stage")
+        s, e, nd = (np.empty(nc, dtype=np.int64) for _ in range(3))
+        lv = np.empty(nc, dtype=np.int32)
+        p64 = C.POINTER(C.c_int64)
+        check(lib.spaqr_ordering_clusters(self._h, int(stage), s.ctypes.data_as(p64), e.ctypes.data_as(p64),
+                                          nd.ctypes.data_as(p64), lv.ctypes.data_as(C.POINTER(C.c_int32))),
+              "spaqr_ordering_clusters")
+        return s, e, nd, lv
+
+    def merge_parents(self, stage):
+        lib = _abi.load()
+        nc = lib.spaqr_ordering_num_clusters(self._h, int(stage))
+        out = np.empty(nc, dtype=np.int64)
+        check(lib.spaqr_ordering_merge_parents(self._h, int(stage), out.ctypes.data_as(C.POINTER(C.c_int64))),
+              "spaqr_ordering_merge_parents")
+        return out
+
+
+def order_grid(dims, levels=0):
+    return GridOrdering(dims, levels)
+
+
+class Symbolic:
+    """Host-only symbolic analysis (spaqr_analyze)."""
+
+    def __init__(self, A, ordering, skip=2):
+        lib = _abi.load()
+        csr, self._keep = _csr_struct(A)
+        o = make_opts(skip=skip)
+        h = C.c_void_p()
+        check(lib.spaqr_analyze(C.byref(csr), ordering.handle, C.byref(o), C.byref(h)), "spaqr_analyze")
+        self._h = h
+        self.levels = ordering.levels
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _abi.load().spaqr_symbolic_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stage_info(self, stage, what):
+        lib = _abi.load()
+        n = C.c_int64()
+        check(lib.spaqr_symbolic_stage_info(self._h, int(stage), int(what), None, 0, C.byref(n)), "stage_info")
+        buf = np.empty(max(1, n.value), dtype=np.int32)
+        check(lib.spaqr_symbolic_stage_info(self._h, int(stage), int(what),
+                                            buf.ctypes.data_as(C.POINTER(C.c_int32)), buf.size, C.byref(n)),
+              "stage_info")
+        return buf[:n.value]
+
+    def pattern(self, stage, post=False):
+        v = self.stage_info(stage, 1 if post else 0)
+        return [tuple(x) for x in v.reshape(-1, 2).tolist()]
+
+    def fronts(self, stage):
+        v = self.stage_info(stage, 2).tolist()
+        out, i = {}, 0
+        while i < len(v):
+            s, col, nn1 = v[i], v[i + 1], v[i + 2]
+            n1 = v[i + 3:i + 3 + nn1]
+            i += 3 + nn1
+            nc = v[i]
+            cols = v[i + 1:i + 1 + nc]
+            i += 1 + nc
+            out[s] = (n1, cols, col)
+        return out
+
+    def iface_colours(self, stage):
+        v = self.stage_info(stage, 3).reshape(-1, 2)
+        return {int(a): int(b) for a, b in v}
+
+
+def analyze(A, ordering, skip=2):
+    return Symbolic(A, ordering, skip)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        return C.c_void_p(0)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Factorization:
+    """A spaQR factorization resident on the GPU (spaqr_factor)."""
+
+    def __init__(self, A, ordering=None, symbolic=None, eps=1e-2, skip=2, precision=32, restart=100,
+                 maxit=1000, stream=None):
+        lib = _abi.load()
+        csr, keep = _csr_struct(A)
+        o = make_opts(eps, skip, precision, restart, maxit)
+        h = C.c_void_p()
+        sp = _stream_ptr(stream)
+        if symbolic is not None:
+            st = lib.spaqr_factor_symbolic(C.byref(csr), symbolic.handle, C.byref(o), sp, C.byref(h))
+        else:
+            st = lib.spaqr_factor(C.byref(csr), ordering.handle, C.byref(o), sp, C.byref(h))
+        check(st, "spaqr_factor")
+        del keep
+        self._h = h
+        self.n = A.shape[0]
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _abi.load().spaqr_free(self._h)
+            self._h = None
+
+    def close(self):
+        self.__del__()
+
+    # vectors: numpy (host) or torch CUDA tensors (device), shape (n,) or (n, nrhs)
+    @staticmethod
+    def _layout(b, n):
+        if b.ndim == 1:
+            return 1, n
+        if hasattr(b, "stride"):           # torch
+            if b.stride(0) != 1:
+                raise ValueError("device arrays must be column-major (stride(0) == 1)")
+            return b.shape[1], b.stride(1)
+        if not b.flags.f_contiguous:
+            raise ValueError("host arrays must be column-major")
+        return b.shape[1], n
+
+    def apply(self, b, out=None):
+        lib = _abi.load()
+        if hasattr(b, "is_cuda") and b.is_cuda:
+            import torch
+            if out is None:
+                out = torch.empty_like(b)
+            nrhs, ld = self._layout(b, self.n)
+            check(lib.spaqr_apply(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr()), nrhs, ld, 1),
+                  "spaqr_apply")
+            return out
+        b = np.asarray(b, dtype=np.float64, order="F")
+        out = np.empty_like(b, order="F") if out is None else out
+        nrhs, ld = self._layout(b, self.n)
+        check(lib.spaqr_apply(self._h, b.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), nrhs, ld, 0),
+              "spaqr_apply")
+        return out
+
+    def solve(self, b, tol=1e-10, out=None):
+        lib = _abi.load()
+        on_dev = hasattr(b, "is_cuda") and b.is_cuda
+        if on_dev:
+            import torch
+            out = torch.empty_like(b) if out is None else out
+            nrhs, ld = self._layout(b, self.n)
+            info = (SolveInfo * nrhs)()
+            st = lib.spaqr_solve(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr()), nrhs, ld, 1,
+                                 float(tol), info)
+        else:
+            b = np.asarray(b, dtype=np.float64, order="F")
+            out = np.empty_like(b, order="F") if out is None else out
+            nrhs, ld = self._layout(b, self.n)
+            info = (SolveInfo * nrhs)()
+            st = lib.spaqr_solve(self._h, b.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p), nrhs, ld,
+                                 0, float(tol), info)
+        check(st, "spaqr_solve")
+        res = [dict(iterations=i.iterations, converged=bool(i.converged), relres=i.relres, seconds=i.seconds)
+               for i in info]
+        return out, res
+
+    def stats(self):
+        s = _abi.Stats()
+        check(_abi.load().spaqr_stats(self._h, C.byref(s)), "spaqr_stats")
+        d = {k: getattr(s, k) for k, _ in _abi.Stats._fields_ if k != "ms_phase"}
+        d["ms_phase"] = list(s.ms_phase)
+        return d
+
+    def stage_sizes(self, stage):
+        lib = _abi.load()
+        n = C.c_int64()
+        check(lib.spaqr_stage_sizes(self._h, int(stage), None, 0, C.byref(n)), "spaqr_stage_sizes")
+        buf = np.empty(max(1, n.value), dtype=np.int32)
+        check(lib.spaqr_stage_sizes(self._h, int(stage), buf.ctypes.data_as(C.POINTER(C.c_int32)), buf.size,
+                                    C.byref(n)), "spaqr_stage_sizes")
+        return buf[:n.value]
+
+
+def factor(A, ordering, eps=1e-2, **kw):
+    return Factorization(A, ordering=ordering, eps=eps, **kw)
+
+
+from .server import Server  # noqa: E402,F401

@@ -1,0 +1,104 @@
+// Numeric spaQR engine: device memory, the stage-by-stage factorization
+// driver, the preconditioner apply and FGMRES.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "symbolic.hpp"
+
+namespace spaqr {
+
+#define SPAQR_HIP(call)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::spaqr::Error(SPAQR_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+// Bump allocator over stream-ordered device chunks.
+class DevArena {
+ public:
+  explicit DevArena(size_t chunk = size_t(32) << 20) : chunk_(chunk) {}
+  ~DevArena();
+  void* alloc(size_t bytes, hipStream_t s);
+  template <typename X>
+  X* alloc_n(size_t n, hipStream_t s) { return static_cast<X*>(alloc(n * sizeof(X), s)); }
+  void reset() { cur_ = 0; off_ = 0; }
+  void release(hipStream_t s);
+  size_t reserved() const;
+
+ private:
+  struct Chunk { char* p; size_t size; };
+  std::vector<Chunk> chunks_;
+  size_t chunk_, cur_ = 0, off_ = 0;
+};
+
+// Pinned host staging for uploads; reset only once the stream has passed
+// every copy issued from it.
+class Stager {
+ public:
+  ~Stager();
+  template <typename X>
+  X* upload(DevArena& arena, const std::vector<X>& v, hipStream_t s) {
+    if (v.empty()) return nullptr;
+    return static_cast<X*>(upload_bytes(arena, v.data(), v.size() * sizeof(X), s));
+  }
+  void* upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s);
+  void reset() { cur_ = 0; off_ = 0; }
+
+ private:
+  struct Chunk { char* p; size_t size; };
+  std::vector<Chunk> chunks_;
+  size_t cur_ = 0, off_ = 0;
+};
+
+template <typename T>
+struct StageApply {
+  ApFront<T>* fronts = nullptr;          // colour order
+  std::vector<int64_t> colour_ptr;       // boundaries of colours in fronts
+  std::vector<int> colour_max_m;         // LDS rows of the forward launch per colour
+  int max_bwd_rows = 0;                  // max n + k
+  int64_t nfronts = 0;
+  ApIface<T>* ifaces = nullptr;
+  int64_t nifaces = 0;
+  int max_p = 0;
+};
+
+struct Stats {
+  spaqr_stats_t s{};
+  std::vector<std::vector<int32_t>> stage_sizes;  // index k: sizes after stage k
+};
+
+class EngineBase {
+ public:
+  virtual ~EngineBase() = default;
+  // x = M^{-1} b; device pointers, column-major
+  virtual void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) = 0;
+  virtual void spmv_dev(const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs) = 0;
+  virtual const Stats& stats() const = 0;
+  virtual hipStream_t stream() const = 0;
+  virtual int64_t n() const = 0;
+  virtual int opt_restart() const = 0;
+  virtual int opt_maxit() const = 0;
+};
+
+std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o,
+                                        hipStream_t stream);
+
+// FGMRES on the device (gmres.hip).
+int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
+                 double tol, spaqr_solve_info* info);
+
+double now_ms();
+
+}  // namespace spaqr
+
+struct spaqr_handle {
+  std::unique_ptr<spaqr::EngineBase> e;
+  std::unique_ptr<spaqr::Symbolic> owned_sym;
+};

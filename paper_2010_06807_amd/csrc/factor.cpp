@@ -1,0 +1,669 @@
+// Stage-by-stage numeric factorization (Algorithm 2) and preconditioner apply.
+//
+// Memory layout in HBM.  Each stage k has a pool holding every block of the
+// stage (pattern at stage start plus the fill of its fronts), row-major with
+// the leading dimension equal to the column cluster's size when the stage
+// began.  Sparsification shrinks blocks in place (the leading dimension stays);
+// current sizes live in a device table that the sparsify kernels read.  After
+// a stage the host reads the ranks back once, lays out the next pool with the
+// compressed sizes and merges child blocks into it.  Factors (front V/R_ss,
+// R_sj, scaling U/R_pp, sparsification Q) are stored column-major for the
+// apply and stay resident for the handle's lifetime.  Vectors live in the
+// permuted index space ("slots"); a cluster owns a list of slots, sparsification
+// keeps its first r slots as the coarse unknowns, and a merge concatenates
+// slot lists without moving data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace spaqr {
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------- DevArena
+DevArena::~DevArena() {
+  for (auto& c : chunks_) (void)hipFree(c.p);
+}
+
+void* DevArena::alloc(size_t bytes, hipStream_t s) {
+  bytes = (bytes + 255) & ~size_t(255);
+  if (bytes == 0) bytes = 256;
+  while (cur_ < chunks_.size()) {
+    if (off_ + bytes <= chunks_[cur_].size) {
+      void* p = chunks_[cur_].p + off_;
+      off_ += bytes;
+      return p;
+    }
+    ++cur_;
+    off_ = 0;
+  }
+  const size_t sz = std::max(chunk_, bytes);
+  char* p = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&p), sz, s);
+  if (e != hipSuccess || !p) throw Error(SPAQR_ENOMEM, "device allocation failed");
+  chunks_.push_back({p, sz});
+  cur_ = chunks_.size() - 1;
+  off_ = bytes;
+  return p;
+}
+
+void DevArena::release(hipStream_t s) {
+  for (auto& c : chunks_) (void)hipFreeAsync(c.p, s);
+  chunks_.clear();
+  reset();
+}
+
+size_t DevArena::reserved() const {
+  size_t t = 0;
+  for (auto& c : chunks_) t += c.size;
+  return t;
+}
+
+// ---------------------------------------------------------------- Stager
+Stager::~Stager() {
+  for (auto& c : chunks_) (void)hipHostFree(c.p);
+}
+
+void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
+  void* dst = arena.alloc(bytes, s);
+  size_t need = (bytes + 255) & ~size_t(255);
+  while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].size) {
+    ++cur_;
+    off_ = 0;
+  }
+  if (cur_ >= chunks_.size()) {
+    const size_t sz = std::max(need, size_t(16) << 20);
+    char* p = nullptr;
+    SPAQR_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sz, hipHostMallocDefault));
+    chunks_.push_back({p, sz});
+    cur_ = chunks_.size() - 1;
+    off_ = 0;
+  }
+  char* h = chunks_[cur_].p + off_;
+  off_ += need;
+  std::memcpy(h, src, bytes);
+  SPAQR_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
+  return dst;
+}
+
+void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, const double* x,
+                 int64_t ldx, double* y, int64_t ldy, int nrhs, hipStream_t s);
+
+namespace {
+
+struct Job {
+  std::vector<int64_t> ptr{0};
+  template <typename T>
+  void close(std::vector<CopyTile<T>>& tiles) { ptr.push_back((int64_t)tiles.size()); }
+};
+
+template <typename T>
+class Engine final : public EngineBase {
+ public:
+  Engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o, hipStream_t s)
+      : S_(S), o_(o), s_(s) {
+    st_.s.n = S.n;
+    st_.s.levels = S.L;
+    st_.s.precision = sizeof(T) == 4 ? 32 : 64;
+    st_.stage_sizes.assign(S.L + 1, {});
+    const double t0 = now_ms();
+    try {
+      factor(A);
+    } catch (...) {
+      (void)hipStreamSynchronize(s_);
+      throw;
+    }
+    st_.s.ms_factor = now_ms() - t0;
+  }
+  ~Engine() override {
+    (void)hipStreamSynchronize(s_);
+    if (apply_ws_) (void)hipFree(apply_ws_);
+  }
+
+  void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) override;
+  void spmv_dev(const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs) override {
+    launch_spmv(d_rowptr_, d_col_, d_val_, S_.n, x, ldx, y, ldy, nrhs, s_);
+  }
+  const Stats& stats() const override { return st_; }
+  hipStream_t stream() const override { return s_; }
+  int64_t n() const override { return S_.n; }
+  int opt_restart() const override { return o_.restart; }
+  int opt_maxit() const override { return o_.maxit; }
+
+ private:
+  void factor(const spaqr_csr* A);
+  void stage(int k);
+  void merge(int k);
+  void begin_stage();
+
+  const Symbolic& S_;
+  spaqr_opts o_;
+  hipStream_t s_;
+  Stats st_;
+  DevArena persist_{size_t(64) << 20};
+  DevArena work_{size_t(64) << 20};
+  DevArena pools_[2] = {DevArena(size_t(64) << 20), DevArena(size_t(64) << 20)};
+  Stager stager_[2];
+  int stager_cur_ = 0;
+  int* pinned_ints_ = nullptr;
+  size_t pinned_cap_ = 0;
+
+  // current stage state
+  T* pool_ = nullptr;
+  std::vector<int64_t> boff_;       // block offsets (elements) in the pool, by S_.st[k].all index
+  std::vector<int32_t> size_;       // current cluster sizes (alloc sizes of the pool)
+  std::vector<int64_t> slot_ptr_;   // slot lists of the current clusters
+  std::vector<int32_t> slots_;
+
+  // apply data
+  std::vector<StageApply<T>> ap_;
+  int64_t* d_perm_ = nullptr;
+  double* d_dc_ = nullptr;
+  int64_t* d_rowptr_ = nullptr;
+  int32_t* d_col_ = nullptr;
+  double* d_val_ = nullptr;
+  double* apply_ws_ = nullptr;
+  size_t apply_ws_cap_ = 0;
+};
+
+template <typename T>
+void Engine<T>::begin_stage() {
+  stager_cur_ ^= 1;
+  stager_[stager_cur_].reset();
+  work_.reset();
+}
+
+template <typename T>
+void Engine<T>::factor(const spaqr_csr* A) {
+  const int L = S_.L;
+  const int64_t n = S_.n, nnz = S_.nnz;
+  const Ordering& ord = S_.ord;
+  ap_.assign(L + 1, StageApply<T>());
+  // Section 2.8: pre-scale columns to unit 2-norm.
+  std::vector<double> cn(n, 0.0);
+  for (int64_t t = 0; t < nnz; ++t) cn[A->col[t]] += A->val[t] * A->val[t];
+  std::vector<double> dc(n);
+  for (int64_t j = 0; j < n; ++j) {
+    SPAQR_REQUIRE(cn[j] > 0.0, SPAQR_EINVAL, "A has a zero column");
+    dc[j] = 1.0 / std::sqrt(cn[j]);
+  }
+  begin_stage();
+  Stager& up = stager_[stager_cur_];
+  d_perm_ = up.upload(persist_, ord.perm, s_);
+  d_dc_ = up.upload(persist_, dc, s_);
+  {
+    std::vector<int64_t> rp(A->rowptr, A->rowptr + n + 1);
+    std::vector<int32_t> ci(A->col, A->col + nnz);
+    std::vector<double> va(A->val, A->val + nnz);
+    d_rowptr_ = up.upload(persist_, rp, s_);
+    d_col_ = up.upload(persist_, ci, s_);
+    d_val_ = up.upload(persist_, va, s_);
+  }
+  // stage-L clusters, slots and pool
+  const StageClusters& cl = ord.stages[L];
+  const StageSym& sL = S_.st[L];
+  size_.resize(cl.count());
+  slot_ptr_.assign(cl.count() + 1, 0);
+  slots_.resize(n);
+  for (int64_t c = 0; c < cl.count(); ++c) {
+    size_[c] = (int32_t)(cl.end[c] - cl.start[c]);
+    slot_ptr_[c + 1] = slot_ptr_[c] + size_[c];
+    for (int64_t p = cl.start[c]; p < cl.end[c]; ++p) slots_[p] = (int32_t)p;
+  }
+  boff_.assign(sL.all.size() + 1, 0);
+  for (int64_t i = 0; i < sL.nclu; ++i)
+    for (int64_t t = sL.all.rowptr[i]; t < sL.all.rowptr[i + 1]; ++t)
+      boff_[t + 1] = boff_[t] + (int64_t)size_[i] * size_[sL.all.col[t]];
+  pools_[L & 1].reset();
+  pool_ = pools_[L & 1].alloc_n<T>(std::max<int64_t>(1, boff_.back()), s_);
+  launch_fill<T>(pool_, boff_.back(), T(0), s_);
+  {
+    std::vector<int64_t> dst(nnz);
+    std::vector<double> val(nnz);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
+        const int64_t b = S_.nz_block[t];
+        const int32_t cj = S_.cluster_of_pos_L[ord.iperm[A->col[t]]];
+        dst[t] = boff_[b] + (int64_t)S_.nz_r[t] * size_[cj] + S_.nz_c[t];
+        val[t] = A->val[t] * dc[A->col[t]];
+      }
+    int64_t* d_dst = up.upload(work_, dst, s_);
+    double* d_v = up.upload(work_, val, s_);
+    launch_scatter_nz<T>(pool_, d_dst, d_v, nnz, s_);
+  }
+  for (int k = L; k >= 1; --k) stage(k);
+  SPAQR_HIP(hipStreamSynchronize(s_));
+  st_.s.factor_bytes = (int64_t)persist_.reserved();
+  pools_[0].release(s_);
+  pools_[1].release(s_);
+  work_.release(s_);
+  SPAQR_HIP(hipStreamSynchronize(s_));
+}
+
+template <typename T>
+void Engine<T>::stage(int k) {
+  if (k != S_.L) begin_stage();
+  Stager& up = stager_[stager_cur_];
+  const StageSym& ss = S_.st[k];
+  const int64_t nclu = ss.nclu;
+  StageApply<T>& ap = ap_[k];
+  auto slot_list = [&](const std::vector<int32_t>& cl, std::vector<int32_t>& out) {
+    for (int32_t c : cl) out.insert(out.end(), slots_.begin() + slot_ptr_[c], slots_.begin() + slot_ptr_[c + 1]);
+  };
+  auto blk = [&](int32_t i, int32_t j) -> T* {
+    const int64_t b = ss.all.find(i, j);
+    return b < 0 ? nullptr : pool_ + boff_[b];
+  };
+  int* d_flag = persist_.alloc_n<int>(1, s_);
+  launch_fill<int>(d_flag, 1, 0, s_);
+
+  // ------------------------------------------------------------ fronts
+  const int64_t nf = (int64_t)ss.fronts.size();
+  std::vector<int32_t> fm(nf), fn(nf), fnc(nf);
+  std::vector<int64_t> ws_off(nf + 1, 0), vr_off(nf + 1, 0), rsj_off(nf + 1, 0), tau_off(nf + 1, 0);
+  int max_m = 1;
+  for (int64_t f = 0; f < nf; ++f) {
+    const FrontSym& F = ss.fronts[f];
+    int m = size_[F.cluster], nc = size_[F.cluster];
+    for (int32_t i : F.n1) m += size_[i];
+    for (int32_t j : F.cols) nc += size_[j];
+    fm[f] = m;
+    fn[f] = size_[F.cluster];
+    fnc[f] = nc;
+    ws_off[f + 1] = ws_off[f] + (int64_t)m * nc;
+    vr_off[f + 1] = vr_off[f] + (int64_t)m * fn[f];
+    rsj_off[f + 1] = rsj_off[f] + (int64_t)fn[f] * (nc - fn[f]);
+    tau_off[f + 1] = tau_off[f] + fn[f];
+    max_m = std::max(max_m, m);
+    const double mm = m, nn = fn[f], kk = nc - fn[f];
+    st_.s.flops_front += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
+    st_.s.fronts++;
+    st_.s.top_separator = fn[f];
+  }
+  const int jbf = qr_panel_width(max_m, sizeof(T));
+  SPAQR_REQUIRE(jbf > 0, SPAQR_ENOMEM, "front too tall for the LDS panel");
+  T* W = work_.alloc_n<T>(std::max<int64_t>(1, ws_off[nf]), s_);
+  T* VR = persist_.alloc_n<T>(std::max<int64_t>(1, vr_off[nf]), s_);
+  T* RSJ = persist_.alloc_n<T>(std::max<int64_t>(1, rsj_off[nf]), s_);
+  T* TAU = persist_.alloc_n<T>(std::max<int64_t>(1, tau_off[nf]), s_);
+  for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
+    std::vector<CopyTile<T>> g, sc;
+    Job gj, sj;
+    std::vector<QRDesc<T>> qd;
+    for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
+      const int32_t f = ss.front_order[oi];
+      const FrontSym& F = ss.fronts[f];
+      T* Wf = W + ws_off[f];
+      const int32_t nc = fnc[f], n = fn[f];
+      std::vector<int32_t> rows{F.cluster}, cols{F.cluster};
+      rows.insert(rows.end(), F.n1.begin(), F.n1.end());
+      cols.insert(cols.end(), F.cols.begin(), F.cols.end());
+      int ro = 0;
+      for (size_t a = 0; a < rows.size(); ++a) {
+        int co = 0;
+        const int32_t i = rows[a];
+        for (size_t b = 0; b < cols.size(); ++b) {
+          const int32_t j = cols[b];
+          if (size_[i] > 0 && size_[j] > 0) {
+            g.push_back({blk(i, j), Wf + (int64_t)ro * nc + co, size_[i], size_[j], size_[j], nc, 0, 0});
+            if (a > 0 && b > 0) {
+              T* dst = blk(i, j);
+              SPAQR_REQUIRE(dst != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
+              sc.push_back({Wf + (int64_t)ro * nc + co, dst, size_[i], size_[j], nc, size_[j], 0, 0});
+            }
+          }
+          co += size_[j];
+        }
+        ro += size_[i];
+      }
+      gj.close(g);
+      sj.close(sc);
+      if (n > 0) qd.push_back({Wf, TAU + tau_off[f], nullptr, d_flag, fm[f], n, nc, 0});
+    }
+    const int64_t njobs = (int64_t)gj.ptr.size() - 1;
+    CopyTile<T>* dg = up.upload(work_, g, s_);
+    int64_t* dgj = up.upload(work_, gj.ptr, s_);
+    launch_copy<T>(dg, dgj, dg ? njobs : 0, s_);
+    QRDesc<T>* dq = up.upload(work_, qd, s_);
+    launch_qr<T>(dq, (int64_t)qd.size(), jbf, max_m, s_);
+    CopyTile<T>* ds = up.upload(work_, sc, s_);
+    int64_t* dsj = up.upload(work_, sj.ptr, s_);
+    launch_copy<T>(ds, dsj, ds ? njobs : 0, s_);
+  }
+  // pack factors column-major for the apply and build the apply descriptors
+  {
+    std::vector<CopyTile<T>> pk;
+    Job pj;
+    std::vector<ApFront<T>> af;
+    std::vector<int32_t> rs, cs;
+    std::vector<int64_t> rs_off, cs_off;
+    ap.colour_ptr.assign(1, 0);
+    for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
+      int cmax = 0;
+      for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
+        const int32_t f = ss.front_order[oi];
+        const FrontSym& F = ss.fronts[f];
+        const int32_t m = fm[f], n = fn[f], nc = fnc[f];
+        if (n == 0) continue;
+        T* Wf = W + ws_off[f];
+        pk.push_back({Wf, VR + vr_off[f], m, n, nc, m, 1, 0});
+        if (nc > n) pk.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, nc, n, 1, 0});
+        pj.close(pk);
+        std::vector<int32_t> rows{F.cluster};
+        rows.insert(rows.end(), F.n1.begin(), F.n1.end());
+        rs_off.push_back((int64_t)rs.size());
+        slot_list(rows, rs);
+        cs_off.push_back((int64_t)cs.size());
+        slot_list(F.cols, cs);
+        af.push_back({VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], nullptr, nullptr, m, n, nc - n, 0});
+        cmax = std::max(cmax, m);
+        ap.max_bwd_rows = std::max(ap.max_bwd_rows, nc);
+      }
+      ap.colour_ptr.push_back((int64_t)af.size());
+      ap.colour_max_m.push_back(cmax);
+    }
+    CopyTile<T>* dp = up.upload(work_, pk, s_);
+    int64_t* dpj = up.upload(work_, pj.ptr, s_);
+    launch_copy<T>(dp, dpj, dp ? (int64_t)pj.ptr.size() - 1 : 0, s_);
+    int32_t* drs = up.upload(persist_, rs, s_);
+    int32_t* dcs = up.upload(persist_, cs, s_);
+    for (size_t t = 0; t < af.size(); ++t) {
+      af[t].rows = drs + rs_off[t];
+      af[t].cols = dcs ? dcs + cs_off[t] : nullptr;
+    }
+    ap.fronts = up.upload(persist_, af, s_);
+    ap.nfronts = (int64_t)af.size();
+  }
+
+  // ------------------------------------------------ scaling + sparsification
+  int* d_rank = nullptr;
+  {
+    std::vector<int> r0(size_.begin(), size_.end());
+    r0.push_back(0);
+    d_rank = up.upload(persist_, r0, s_);
+  }
+  if (ss.sparsify) {
+    const std::vector<int32_t>& rem = ss.remaining;
+    const int64_t ni = (int64_t)rem.size();
+    std::vector<int32_t> fidx(nclu, -1);
+    std::vector<int64_t> u_off(ni + 1, 0), t_off(ni + 1, 0), p_off(ni + 1, 0);
+    int max_p = 1;
+    for (int64_t t = 0; t < ni; ++t) {
+      fidx[rem[t]] = (int32_t)t;
+      const int64_t P = size_[rem[t]];
+      u_off[t + 1] = u_off[t] + P * P;
+      p_off[t + 1] = p_off[t] + P;
+      max_p = std::max<int>(max_p, (int)P);
+    }
+    const int jbs = qr_panel_width(max_p, sizeof(T));
+    SPAQR_REQUIRE(jbs > 0, SPAQR_ENOMEM, "interface too large for the LDS panel");
+    for (int64_t t = 0; t < ni; ++t) {
+      const int64_t P = size_[rem[t]];
+      t_off[t + 1] = t_off[t] + ((P + jbs - 1) / jbs) * jbs * jbs;
+      const double pp = P;
+      st_.s.flops_scale += 4.0 / 3.0 * pp * pp * pp;
+    }
+    T* SW = work_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+    T* VRU = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+    T* TAUU = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
+    T* TPAN = persist_.alloc_n<T>(std::max<int64_t>(1, t_off[ni]), s_);
+    T* VQ = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+    T* TAUQ = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
+    int* FLAGS = persist_.alloc_n<int>(std::max<int64_t>(1, ni), s_);
+    launch_fill<int>(FLAGS, ni, 0, s_);
+    {
+      std::vector<CopyTile<T>> g, pk;
+      Job gj, pj;
+      std::vector<QRDesc<T>> qd;
+      std::vector<ScaleFac<T>> fac(ni);
+      for (int64_t t = 0; t < ni; ++t) {
+        const int32_t p = rem[t], P = size_[p];
+        fac[t] = {VRU + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, P, 0};
+        if (P == 0) continue;
+        T* src = blk(p, p);
+        SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
+        g.push_back({src, SW + u_off[t], P, P, P, P, 0, 0});
+        gj.close(g);
+        qd.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, P, P, P, 0});
+        pk.push_back({SW + u_off[t], VRU + u_off[t], P, P, P, P, 1, 0});
+        pj.close(pk);
+      }
+      CopyTile<T>* dg = up.upload(work_, g, s_);
+      int64_t* dgj = up.upload(work_, gj.ptr, s_);
+      launch_copy<T>(dg, dgj, dg ? (int64_t)gj.ptr.size() - 1 : 0, s_);
+      QRDesc<T>* dq = up.upload(work_, qd, s_);
+      launch_qr<T>(dq, (int64_t)qd.size(), jbs, max_p, s_);
+      CopyTile<T>* dp = up.upload(work_, pk, s_);
+      int64_t* dpj = up.upload(work_, pj.ptr, s_);
+      launch_copy<T>(dp, dpj, dp ? (int64_t)pj.ptr.size() - 1 : 0, s_);
+      ScaleFac<T>* dfac = up.upload(persist_, fac, s_);
+      std::vector<ScaleBlk> sb;
+      for (int64_t i = 0; i < nclu; ++i)
+        for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
+          const int32_t j = ss.post.col[u];
+          if (size_[i] == 0 || size_[j] == 0) continue;
+          const int64_t b = ss.all.find((int32_t)i, j);
+          sb.push_back({boff_[b], size_[i], size_[j], fidx[i], fidx[j]});
+          st_.s.flops_scale += 4.0 * size_[i] * size_[i] * size_[j] + (double)size_[i] * size_[j] * size_[j];
+        }
+      ScaleBlk* dsb = up.upload(work_, sb, s_);
+      launch_scale<T>(dsb, (int64_t)sb.size(), dfac, pool_, jbs, max_p, s_);
+    }
+    // sparsification, colour by colour
+    for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
+      std::vector<SpDesc<T>> sd;
+      std::vector<SpNbr> nb;
+      int64_t c_off = 0, n_off = 0;
+      std::vector<int64_t> cpos, npos;
+      int max_nb = 0, max_pc = 1;
+      for (int32_t oi = ss.iface_colour_ptr[c]; oi < ss.iface_colour_ptr[c + 1]; ++oi) {
+        const IfaceSym& I = ss.ifaces[ss.iface_order[oi]];
+        const int32_t p = I.cluster, P = size_[p];
+        if (P == 0) continue;
+        SpDesc<T> d{};
+        d.nb = (int64_t)nb.size();
+        int64_t mmax = 0;
+        for (int32_t i : I.rowN) {
+          const int64_t b = ss.all.find(i, p);
+          nb.push_back({boff_[b], i, P});
+          mmax += size_[i];
+        }
+        for (int32_t j : I.colN) {
+          const int64_t b = ss.all.find(p, j);
+          nb.push_back({boff_[b], j, size_[j]});
+          mmax += size_[j];
+        }
+        d.nrow = (int32_t)I.rowN.size();
+        d.ncol = (int32_t)I.colN.size();
+        d.cluster = p;
+        d.P = P;
+        d.mmax = (int32_t)std::max<int64_t>(1, mmax);
+        const int64_t t = fidx[p];
+        d.vq = VQ + u_off[t];
+        d.tauq = TAUQ + p_off[t];
+        d.flag = FLAGS + t;
+        cpos.push_back(c_off);
+        npos.push_back(n_off);
+        c_off += (int64_t)P * d.mmax;
+        n_off += d.mmax;
+        max_nb = std::max(max_nb, d.nrow + d.ncol);
+        max_pc = std::max<int>(max_pc, P);
+        sd.push_back(d);
+        const double pp = P, mm = (double)mmax;
+        st_.s.flops_sparsify += 4.0 * pp * mm * std::min(pp, mm);
+      }
+      if (sd.empty()) continue;
+      T* CW = work_.alloc_n<T>(std::max<int64_t>(1, c_off), s_);
+      double* NW = work_.alloc_n<double>(std::max<int64_t>(1, n_off), s_);
+      int32_t* IW = work_.alloc_n<int32_t>(std::max<int64_t>(1, 2 * n_off), s_);
+      for (size_t t = 0; t < sd.size(); ++t) {
+        sd[t].C = CW + cpos[t];
+        sd[t].nrm = NW + npos[t];
+        sd[t].perm = IW + 2 * npos[t];
+      }
+      SpDesc<T>* dsd = up.upload(work_, sd, s_);
+      SpNbr* dnb = up.upload(work_, nb, s_);
+      launch_sparsify<T>(dsd, (int64_t)sd.size(), dnb, pool_, d_rank, o_.eps, max_pc, max_nb, s_);
+    }
+    // apply descriptors of the interfaces
+    std::vector<ApIface<T>> ai;
+    std::vector<int32_t> sl;
+    std::vector<int64_t> sl_off;
+    for (int64_t t = 0; t < ni; ++t) {
+      const int32_t p = rem[t], P = size_[p];
+      if (P == 0) continue;
+      sl_off.push_back((int64_t)sl.size());
+      slot_list(std::vector<int32_t>{p}, sl);
+      ai.push_back({VRU + u_off[t], TAUU + p_off[t], VQ + u_off[t], TAUQ + p_off[t], nullptr, d_rank + p,
+                    FLAGS + t, P, 0});
+      ap.max_p = std::max(ap.max_p, (int)P);
+    }
+    int32_t* dsl = up.upload(persist_, sl, s_);
+    for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
+    ap.ifaces = up.upload(persist_, ai, s_);
+    ap.nifaces = (int64_t)ai.size();
+    st_.s.interfaces_sparsified += (int64_t)ai.size();
+  }
+
+  // ------------------------------------------------ rank readback
+  const size_t need = (size_t)nclu + 1;
+  if (pinned_cap_ < need) {
+    if (pinned_ints_) (void)hipHostFree(pinned_ints_);
+    SPAQR_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned_ints_), need * sizeof(int), hipHostMallocDefault));
+    pinned_cap_ = need;
+  }
+  if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
+  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag, sizeof(int), hipMemcpyDeviceToHost, s_));
+  SPAQR_HIP(hipStreamSynchronize(s_));
+  SPAQR_REQUIRE(pinned_ints_[nclu] == 0, SPAQR_ESINGULAR, "a front produced an exactly zero R_ss diagonal");
+  st_.stage_sizes[k].assign(pinned_ints_, pinned_ints_ + nclu);
+  if (k > 1) merge(k);
+}
+
+template <typename T>
+void Engine<T>::merge(int k) {
+  Stager& up = stager_[stager_cur_];
+  const StageSym& ss = S_.st[k];
+  const StageSym& s2 = S_.st[k - 1];
+  const std::vector<int64_t>& par = S_.ord.stages[k].parent;
+  const std::vector<int32_t>& rank = st_.stage_sizes[k];
+  const int64_t n2 = s2.nclu;
+  std::vector<int32_t> size2(n2, 0);
+  std::vector<int32_t> off(ss.nclu, 0);
+  for (int64_t c = 0; c < ss.nclu; ++c) {
+    if (par[c] < 0) continue;
+    off[c] = size2[par[c]];
+    size2[par[c]] += rank[c];
+  }
+  // slot lists of the merged clusters: children's surviving slots in order
+  std::vector<int64_t> sp2(n2 + 1, 0);
+  for (int64_t P = 0; P < n2; ++P) sp2[P + 1] = sp2[P] + size2[P];
+  std::vector<int32_t> sl2(sp2[n2]);
+  for (int64_t c = 0; c < ss.nclu; ++c) {
+    if (par[c] < 0) continue;
+    std::copy(slots_.begin() + slot_ptr_[c], slots_.begin() + slot_ptr_[c] + rank[c],
+              sl2.begin() + sp2[par[c]] + off[c]);
+  }
+  // new pool
+  std::vector<int64_t> boff2(s2.all.size() + 1, 0);
+  for (int64_t i = 0; i < n2; ++i)
+    for (int64_t t = s2.all.rowptr[i]; t < s2.all.rowptr[i + 1]; ++t)
+      boff2[t + 1] = boff2[t] + (int64_t)size2[i] * size2[s2.all.col[t]];
+  DevArena& pa = pools_[(k - 1) & 1];
+  pa.reset();
+  T* pool2 = pa.alloc_n<T>(std::max<int64_t>(1, boff2.back()), s_);
+  // one job per new block: zero fill, then the child blocks
+  std::vector<int64_t> cnt(s2.all.size() + 1, 0);
+  std::vector<int64_t> tgt;
+  std::vector<CopyTile<T>> ctile;
+  for (int64_t i = 0; i < ss.nclu; ++i)
+    for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
+      const int32_t j = ss.post.col[u];
+      if (rank[i] == 0 || rank[j] == 0) continue;
+      const int32_t P = (int32_t)par[i], Q = (int32_t)par[j];
+      const int64_t B = s2.all.find(P, Q);
+      SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
+      const int64_t b = ss.all.find((int32_t)i, j);
+      ctile.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Q] + off[j], rank[i],
+                       rank[j], size_[j], size2[Q], 0, 0});
+      tgt.push_back(B);
+      cnt[B + 1]++;
+    }
+  std::vector<CopyTile<T>> tiles;
+  Job jobs;
+  {
+    std::vector<int64_t> start(s2.all.size() + 1, 0);
+    for (int64_t B = 0; B < s2.all.size(); ++B) start[B + 1] = start[B] + cnt[B + 1];
+    std::vector<int64_t> order(ctile.size());
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (size_t t = 0; t < ctile.size(); ++t) order[pos[tgt[t]]++] = (int64_t)t;
+    tiles.reserve(ctile.size() + s2.all.size());
+    for (int64_t i = 0; i < n2; ++i)
+      for (int64_t t = s2.all.rowptr[i]; t < s2.all.rowptr[i + 1]; ++t) {
+        const int32_t j = s2.all.col[t];
+        if (size2[i] == 0 || size2[j] == 0) continue;
+        tiles.push_back({nullptr, pool2 + boff2[t], size2[i], size2[j], 0, size2[j], 0, 0});
+        for (int64_t q = start[t]; q < start[t + 1]; ++q) tiles.push_back(ctile[order[q]]);
+        jobs.close(tiles);
+      }
+  }
+  CopyTile<T>* dt = up.upload(work_, tiles, s_);
+  int64_t* dj = up.upload(work_, jobs.ptr, s_);
+  launch_copy<T>(dt, dj, dt ? (int64_t)jobs.ptr.size() - 1 : 0, s_);
+  pool_ = pool2;
+  boff_.swap(boff2);
+  size_.swap(size2);
+  slot_ptr_.swap(sp2);
+  slots_.swap(sl2);
+}
+
+template <typename T>
+void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) {
+  const int64_t N = S_.n;
+  const size_t need = (size_t)N * nrhs;
+  if (apply_ws_cap_ < need) {
+    if (apply_ws_) SPAQR_HIP(hipFree(apply_ws_));
+    apply_ws_ = nullptr;
+    SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&apply_ws_), need * sizeof(double)));
+    apply_ws_cap_ = need;
+  }
+  double* xh = apply_ws_;
+  launch_gather_perm(xh, b, ldb, d_perm_, N, nrhs, s_);
+  const int L = S_.L;
+  for (int k = L; k >= 1; --k) {
+    const StageApply<T>& a = ap_[k];
+    for (size_t c = 0; c + 1 < a.colour_ptr.size(); ++c) {
+      const int64_t cnt = a.colour_ptr[c + 1] - a.colour_ptr[c];
+      launch_front_fwd<T>(a.fronts + a.colour_ptr[c], cnt, a.colour_max_m[c], xh, N, nrhs, s_);
+    }
+    launch_iface_fwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+  }
+  for (int k = 1; k <= L; ++k) {
+    const StageApply<T>& a = ap_[k];
+    launch_iface_bwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+    launch_front_bwd<T>(a.fronts, a.nfronts, a.max_bwd_rows, xh, N, nrhs, s_);
+  }
+  launch_scatter_perm(x, ldx, xh, d_perm_, d_dc_, N, nrhs, s_);
+  SPAQR_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o,
+                                        hipStream_t stream) {
+  SPAQR_REQUIRE(o.eps >= 0.0 && std::isfinite(o.eps), SPAQR_EINVAL, "eps must be finite and >= 0");
+  SPAQR_REQUIRE(o.scale == 1, SPAQR_EINVAL, "only the scaled variant is implemented");
+  SPAQR_REQUIRE(o.precision == 32 || o.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
+  if (o.precision == 32) return std::unique_ptr<EngineBase>(new Engine<float>(A, S, o, stream));
+  return std::unique_ptr<EngineBase>(new Engine<double>(A, S, o, stream));
+}
+
+}  // namespace spaqr

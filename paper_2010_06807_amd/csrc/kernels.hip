@@ -1,0 +1,787 @@
+// HIP kernels of the spaQR engine for gfx950 (CDNA4, 64-wide wavefronts).
+//
+//   k_copy        gathers/scatters of dense blocks (fronts, merges, packing)
+//   k_qr          blocked Householder QR of a front or an interface block:
+//                 one workgroup per matrix, the current JB-column panel staged
+//                 in LDS, compact-WY trailing update (Section 2.4, 2.6)
+//   k_scale       B <- U_i^T B R_j^{-1} on every block of the trailing matrix
+//                 (block-diagonal scaling, Section 2.6)
+//   k_sparsify    partial column-pivoted QR of [A_np^T | A_pn] with FP64 norms,
+//                 pivots and ratio test, coarse-block write-back (Sections
+//                 2.5, 2.6, and the rank rule of Section 4)
+//   k_ap_*        the preconditioner apply (Section 2.8): one wavefront per
+//                 front or interface, FP64 vectors, coalesced reads of the
+//                 column-major factors
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace spaqr {
+
+namespace {
+
+constexpr int NT = 256;  // threads of the factorization kernels (4 wavefronts)
+constexpr int RBMAX = 8; // right-hand sides per apply workgroup
+
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  red: >= 4 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (int)(blockDim.x >> 6);
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// dlarfg convention: beta = -sign(alpha) * ||[alpha; x]||, tau = (beta - alpha)
+// / beta, v = x / (alpha - beta); tau = 0 (H = I) when x = 0.
+__device__ __forceinline__ void householder(double alpha, double xnorm2, double& beta, double& tau,
+                                            double& scal) {
+  if (xnorm2 == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+    scal = 1.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+}
+
+// LDS layout of the QR kernel for a panel of JB columns and m rows.
+template <typename T, int JB>
+struct QRLds {
+  static constexpr int LDP = JB + 1;  // padded row stride: conflict-free column walks
+  __host__ __device__ static size_t off_t(int m) { return align16((size_t)m * LDP * sizeof(T)); }
+  __host__ __device__ static size_t off_zz(int m) { return off_t(m) + align16((size_t)JB * JB * sizeof(T)); }
+  __host__ __device__ static size_t off_red(int m) { return off_zz(m) + (size_t)JB * JB * sizeof(double); }
+  __host__ __device__ static size_t off_tau(int m) { return off_red(m) + 8 * sizeof(double); }
+  __host__ __device__ static size_t bytes(int m) { return off_tau(m) + (size_t)JB * sizeof(double); }
+};
+
+// C[0:mp, 0:ncols] (row-major, leading dimension ldc) <- H^T C with
+// H = I - V Tm V^T: V (LDS, mp x JB, row stride JB+1, explicit unit diagonal,
+// zeros above it and in unused columns) and Tm (LDS, JB x JB column-major,
+// upper triangular).  One thread per column of C; the panel is read as
+// broadcasts from LDS and the column streams through coalesced loads.
+template <typename T, int JB>
+__device__ void wy_apply_left(const T* __restrict__ Vs, const T* __restrict__ Tm, int mp, T* C,
+                              int64_t ldc, int ncols) {
+  constexpr int LDP = JB + 1;
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    T w[JB];
+#pragma unroll
+    for (int t = 0; t < JB; ++t) w[t] = T(0);
+    for (int r = 0; r < mp; ++r) {
+      const T a = C[(int64_t)r * ldc + c];
+#pragma unroll
+      for (int t = 0; t < JB; ++t) w[t] += Vs[r * LDP + t] * a;
+    }
+    T u[JB];
+#pragma unroll
+    for (int t = 0; t < JB; ++t) {
+      T s = T(0);
+#pragma unroll
+      for (int q = 0; q <= t; ++q) s += Tm[q + t * JB] * w[q];
+      u[t] = s;
+    }
+    for (int r = 0; r < mp; ++r) {
+      T s = T(0);
+#pragma unroll
+      for (int t = 0; t < JB; ++t) s += Vs[r * LDP + t] * u[t];
+      C[(int64_t)r * ldc + c] -= s;
+    }
+  }
+}
+
+// Householder factorization of the LDS panel Ps (mp x jb, row stride JB+1).
+// Leaves R on/above the diagonal and V below it; taus[0..jb) in LDS.
+template <typename T, int JB>
+__device__ bool factor_panel(T* Ps, int mp, int jb, double* taus, double* red) {
+  constexpr int LDP = JB + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  bool zero_diag = false;
+  for (int t = 0; t < jb; ++t) {
+    double s = 0.0;
+    for (int r = t + 1 + tid; r < mp; r += blockDim.x) {
+      const double v = (double)Ps[r * LDP + t];
+      s += v * v;
+    }
+    s = block_sum(s, red);
+    const double alpha = (double)Ps[t * LDP + t];
+    double beta, tau, scal;
+    householder(alpha, s, beta, tau, scal);
+    for (int r = t + 1 + tid; r < mp; r += blockDim.x) Ps[r * LDP + t] = (T)((double)Ps[r * LDP + t] * scal);
+    __syncthreads();
+    for (int c = t + 1 + wv; c < jb; c += nw) {
+      double acc = 0.0;
+      for (int r = t + 1 + lane; r < mp; r += 64) acc += (double)Ps[r * LDP + t] * (double)Ps[r * LDP + c];
+      acc = wave_sum(acc);
+      const double tw = tau * (acc + (double)Ps[t * LDP + c]);
+      for (int r = t + 1 + lane; r < mp; r += 64)
+        Ps[r * LDP + c] = (T)((double)Ps[r * LDP + c] - tw * (double)Ps[r * LDP + t]);
+      if (lane == 0) Ps[t * LDP + c] = (T)((double)Ps[t * LDP + c] - tw);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      Ps[t * LDP + t] = (T)beta;
+      taus[t] = tau;
+    }
+    if ((T)beta == T(0)) zero_diag = true;
+    __syncthreads();
+  }
+  return zero_diag;
+}
+
+// Tm = compact-WY factor of the explicit panel V (LDS) and taus:
+// T[0:t, t] = -tau_t T[0:t, 0:t] (V[:, 0:t]^T v_t), T[t, t] = tau_t.
+template <typename T, int JB>
+__device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* zz, T* Tm) {
+  constexpr int LDP = JB + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nw = (int)(blockDim.x >> 6);
+  for (int pidx = wv; pidx < jb * jb; pidx += nw) {
+    const int i = pidx % jb, t = pidx / jb;
+    if (i >= t) continue;
+    double acc = 0.0;
+    for (int r = t + lane; r < mp; r += 64) acc += (double)Ps[r * LDP + i] * (double)Ps[r * LDP + t];
+    acc = wave_sum(acc);
+    if (lane == 0) zz[i + t * JB] = acc;
+  }
+  for (int q = tid; q < JB * JB; q += blockDim.x) Tm[q] = T(0);
+  __syncthreads();
+  for (int t = 0; t < jb; ++t) {
+    if (tid < t) {
+      double s = 0.0;
+      for (int q = tid; q < t; ++q) s += (double)Tm[tid + q * JB] * zz[q + t * JB];
+      Tm[tid + t * JB] = (T)(-taus[t] * s);
+    } else if (tid == t) {
+      Tm[t + t * JB] = (T)taus[t];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+template <typename T>
+__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles,
+                                             const int64_t* __restrict__ jobptr) {
+  const int64_t b = jobptr[blockIdx.x], e = jobptr[blockIdx.x + 1];
+  for (int64_t t = b; t < e; ++t) {
+    const CopyTile<T> c = tiles[t];
+    const int64_t tot = (int64_t)c.rows * c.cols;
+    if (c.mode == 0) {
+      for (int64_t q = threadIdx.x; q < tot; q += NT) {
+        const int64_t r = q / c.cols, cc = q - r * c.cols;
+        c.dst[r * c.ldd + cc] = c.src ? c.src[r * c.lds + cc] : T(0);
+      }
+    } else {
+      for (int64_t q = threadIdx.x; q < tot; q += NT) {
+        const int64_t cc = q / c.rows, r = q - cc * c.rows;
+        c.dst[cc * c.ldd + r] = c.src[r * c.lds + cc];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+template <typename T>
+__global__ void k_scatter_nz(T* pool, const int64_t* __restrict__ dst, const double* __restrict__ val,
+                             int64_t nnz) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x)
+    pool[dst[i]] = (T)val[i];
+}
+
+template <typename T, int JB>
+__global__ void __launch_bounds__(NT) k_qr(const QRDesc<T>* __restrict__ descs) {
+  using S = QRLds<T, JB>;
+  constexpr int LDP = JB + 1;
+  const QRDesc<T> d = descs[blockIdx.x];
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int m = d.m, n = d.n, nc = d.nc;
+  T* Ps = reinterpret_cast<T*>(smem);
+  T* Tm = reinterpret_cast<T*>(smem + S::off_t(m));
+  double* zz = reinterpret_cast<double*>(smem + S::off_zz(m));
+  double* red = reinterpret_cast<double*>(smem + S::off_red(m));
+  double* taus = reinterpret_cast<double*>(smem + S::off_tau(m));
+  const int tid = threadIdx.x;
+  bool zero_diag = false;
+  for (int j0 = 0; j0 < n; j0 += JB) {
+    const int jb = min(JB, n - j0);
+    const int mp = m - j0;
+    T* A0 = d.a + (int64_t)j0 * nc + j0;
+    for (int q = tid; q < mp * JB; q += NT) {
+      const int r = q / JB, t = q - r * JB;
+      Ps[r * LDP + t] = t < jb ? A0[(int64_t)r * nc + t] : T(0);
+    }
+    __syncthreads();
+    zero_diag |= factor_panel<T, JB>(Ps, mp, jb, taus, red);
+    for (int q = tid; q < mp * jb; q += NT) {
+      const int r = q / jb, t = q - r * jb;
+      A0[(int64_t)r * nc + t] = Ps[r * LDP + t];
+    }
+    if (tid < jb) d.tau[j0 + tid] = (T)taus[tid];
+    __syncthreads();
+    for (int q = tid; q < mp * jb; q += NT) {
+      const int r = q / jb, t = q - r * jb;
+      if (r < t) Ps[r * LDP + t] = T(0);
+      else if (r == t) Ps[r * LDP + t] = T(1);
+    }
+    __syncthreads();
+    form_t<T, JB>(Ps, mp, jb, taus, zz, Tm);
+    if (d.tpan)
+      for (int q = tid; q < JB * JB; q += NT) d.tpan[(int64_t)(j0 / JB) * JB * JB + q] = Tm[q];
+    wy_apply_left<T, JB>(Ps, Tm, mp, A0 + jb, nc, nc - j0 - jb);
+    __syncthreads();
+  }
+  if (tid == 0 && zero_diag && d.flag) *d.flag = 1;
+}
+
+template <typename T, int JB>
+__global__ void __launch_bounds__(NT) k_scale(const ScaleBlk* __restrict__ descs,
+                                              const ScaleFac<T>* __restrict__ fac, T* pool) {
+  using S = QRLds<T, JB>;
+  constexpr int LDP = JB + 1;
+  const ScaleBlk d = descs[blockIdx.x];
+  T* B = pool + d.blk;
+  const int rows = d.rows, cols = d.cols, tid = threadIdx.x;
+  const bool si = d.fi >= 0 && *fac[d.fi].flag == 0;
+  const bool sj = d.fj >= 0 && *fac[d.fj].flag == 0;
+  if (d.fi >= 0 && d.fi == d.fj) {
+    if (si)
+      for (int q = tid; q < rows * cols; q += NT) {
+        const int r = q / cols, c = q - r * cols;
+        B[q] = r == c ? T(1) : T(0);
+      }
+    return;
+  }
+  if (si) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* Vs = reinterpret_cast<T*>(smem);
+    T* Tm = reinterpret_cast<T*>(smem + S::off_t(rows));
+    const ScaleFac<T> f = fac[d.fi];
+    for (int j0 = 0; j0 < rows; j0 += JB) {
+      const int jb = min(JB, rows - j0), mp = rows - j0;
+      for (int q = tid; q < mp * JB; q += NT) {
+        const int r = q / JB, t = q - r * JB;
+        T v;
+        if (t >= jb || r < t) v = T(0);
+        else if (r == t) v = T(1);
+        else v = f.vr[(int64_t)(j0 + r) + (int64_t)(j0 + t) * rows];
+        Vs[r * LDP + t] = v;
+      }
+      for (int q = tid; q < JB * JB; q += NT) Tm[q] = f.tpan[(int64_t)(j0 / JB) * JB * JB + q];
+      __syncthreads();
+      wy_apply_left<T, JB>(Vs, Tm, mp, B + (int64_t)j0 * cols, cols, cols);
+      __syncthreads();
+    }
+  }
+  if (sj) {
+    const T* R = fac[d.fj].vr;
+    for (int r = tid; r < rows; r += NT) {
+      T* Br = B + (int64_t)r * cols;
+      for (int c = 0; c < cols; ++c) {
+        T s = Br[c];
+        const T* Rc = R + (int64_t)c * cols;
+        for (int q = 0; q < c; ++q) s -= Br[q] * Rc[q];
+        Br[c] = s / Rc[c];
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_sparsify(const SpDesc<T>* __restrict__ descs,
+                                                 const SpNbr* __restrict__ nbrs, T* pool, int* rank,
+                                                 double eps) {
+  const SpDesc<T> d = descs[blockIdx.x];
+  const int P = d.P, tid = threadIdx.x;
+  if (P == 0 || *d.flag != 0) return;  // not scaled: rank stays P
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nnb = d.nrow + d.ncol;
+  int* off = reinterpret_cast<int*>(smem);
+  double* vbuf = reinterpret_cast<double*>(smem + align16((size_t)(nnb + 1) * sizeof(int)));
+  double* red = vbuf + P;
+  double* bv = red + 8;
+  int* bi = reinterpret_cast<int*>(bv + NT);
+  const SpNbr* nb = nbrs + d.nb;
+  if (tid == 0) {
+    int o = 0;
+    for (int b = 0; b < nnb; ++b) {
+      off[b] = o;
+      o += rank[nb[b].cluster];
+    }
+    off[nnb] = o;
+  }
+  __syncthreads();
+  const int m = off[nnb];
+  const int64_t ldc = d.mmax;
+  T* C = d.C;
+  // C = [A_np^T | A_pn], P x m row-major
+  for (int b = 0; b < nnb; ++b) {
+    const int w = off[b + 1] - off[b];
+    const T* blk = pool + nb[b].blk;
+    const int64_t ld = nb[b].ld;
+    const int o = off[b];
+    if (b < d.nrow) {
+      for (int e = tid; e < w * P; e += NT) {
+        const int a = e / P, q = e - a * P;
+        C[(int64_t)q * ldc + o + a] = blk[(int64_t)a * ld + q];
+      }
+    } else {
+      for (int e = tid; e < w * P; e += NT) {
+        const int q = e / w, a = e - q * w;
+        C[(int64_t)q * ldc + o + a] = blk[(int64_t)q * ld + a];
+      }
+    }
+  }
+  __syncthreads();
+  double* nrm = d.nrm;
+  int* perm = d.perm;
+  int* ipos = d.perm + d.mmax;
+  for (int c = tid; c < m; c += NT) {
+    double s = 0.0;
+    for (int q = 0; q < P; ++q) {
+      const double v = (double)C[(int64_t)q * ldc + c];
+      s += v * v;
+    }
+    nrm[c] = s;
+    perm[c] = c;
+  }
+  __syncthreads();
+  const int kmax = min(P, m);
+  int r = 0;
+  double R11 = 0.0;
+  for (int k = 0; k < kmax; ++k) {
+    // pivot: largest remaining norm, ties to the lowest position
+    double best = -1.0;
+    int bidx = m;
+    for (int c = k + tid; c < m; c += NT) {
+      const double v = nrm[c];
+      if (v > best) {
+        best = v;
+        bidx = c;
+      }
+    }
+    bv[tid] = best;
+    bi[tid] = bidx;
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double v2 = bv[tid + st];
+        const int i2 = bi[tid + st];
+        if (v2 > bv[tid] || (v2 == bv[tid] && i2 < bi[tid])) {
+          bv[tid] = v2;
+          bi[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = bi[0];
+    const double rkk = sqrt(bv[0]);
+    __syncthreads();
+    if (k == 0) {
+      R11 = rkk;
+      if (R11 == 0.0) break;
+    }
+    if (eps > 0.0 && rkk < eps * R11) break;
+    if (piv != k) {
+      for (int q = tid; q < P; q += NT) {
+        const T a = C[(int64_t)q * ldc + k];
+        C[(int64_t)q * ldc + k] = C[(int64_t)q * ldc + piv];
+        C[(int64_t)q * ldc + piv] = a;
+      }
+      if (tid == 0) {
+        const double tn = nrm[k];
+        nrm[k] = nrm[piv];
+        nrm[piv] = tn;
+        const int ti = perm[k];
+        perm[k] = perm[piv];
+        perm[piv] = ti;
+      }
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int q = k + 1 + tid; q < P; q += NT) {
+      const double v = (double)C[(int64_t)q * ldc + k];
+      s += v * v;
+    }
+    s = block_sum(s, red);
+    const double alpha = (double)C[(int64_t)k * ldc + k];
+    double beta, tau, scal;
+    householder(alpha, s, beta, tau, scal);
+    for (int q = k + 1 + tid; q < P; q += NT) {
+      const T v = (T)((double)C[(int64_t)q * ldc + k] * scal);
+      C[(int64_t)q * ldc + k] = v;
+      vbuf[q] = (double)v;
+    }
+    if (tid == 0) {
+      vbuf[k] = 1.0;
+      d.tauq[k] = (T)tau;
+    }
+    __syncthreads();
+    if (tid == 0) C[(int64_t)k * ldc + k] = (T)beta;
+    for (int c = k + 1 + tid; c < m; c += NT) {
+      double w = 0.0;
+      for (int q = k; q < P; ++q) w += vbuf[q] * (double)C[(int64_t)q * ldc + c];
+      const double tw = tau * w;
+      double s2 = 0.0;
+      for (int q = k; q < P; ++q) {
+        const T v = (T)((double)C[(int64_t)q * ldc + c] - tw * vbuf[q]);
+        C[(int64_t)q * ldc + c] = v;
+        if (q > k) s2 += (double)v * (double)v;
+      }
+      nrm[c] = s2;
+    }
+    __syncthreads();
+    r = k + 1;
+  }
+  if (r < P) {
+    for (int pos = tid; pos < m; pos += NT) ipos[perm[pos]] = pos;
+    __syncthreads();
+    // coarse rows W = (Q^T C)[0:r, :] in the original column order
+    for (int b = 0; b < nnb; ++b) {
+      const int w = off[b + 1] - off[b];
+      T* blk = pool + nb[b].blk;
+      const int64_t ld = nb[b].ld;
+      const int o = off[b];
+      if (b < d.nrow) {
+        for (int e = tid; e < w * r; e += NT) {
+          const int a = e / r, q = e - a * r;
+          const int pos = ipos[o + a];
+          blk[(int64_t)a * ld + q] = q <= pos ? C[(int64_t)q * ldc + pos] : T(0);
+        }
+      } else {
+        for (int e = tid; e < w * r; e += NT) {
+          const int q = e / w, a = e - q * w;
+          const int pos = ipos[o + a];
+          blk[(int64_t)q * ld + a] = q <= pos ? C[(int64_t)q * ldc + pos] : T(0);
+        }
+      }
+    }
+    for (int e = tid; e < P * r; e += NT) {
+      const int k = e / P, q = e - k * P;
+      d.vq[(int64_t)q + (int64_t)k * P] = q < k ? T(0) : (q == k ? T(1) : C[(int64_t)q * ldc + k]);
+    }
+    __syncthreads();
+    if (tid == 0) rank[d.cluster] = r;
+  }
+}
+
+// ---------------------------------------------------------------- apply
+// Rows of a work vector are owned by lane (row % 64) for the whole kernel, so
+// a wavefront needs no barrier between reflectors.
+template <typename T, bool UNIT_STORED>
+__device__ void wave_reflectors(const T* __restrict__ V, int64_t ldv, const T* __restrict__ tau, int first,
+                                int last, int step, int m, double* xs, int nc, int ldx) {
+  const int lane = threadIdx.x & 63;
+  for (int t = first; t != last; t += step) {
+    const double tt = (double)tau[t];
+    if (tt == 0.0) continue;
+    const T* v = V + (int64_t)t * ldv;
+    double acc[RBMAX];
+#pragma unroll
+    for (int c = 0; c < RBMAX; ++c) acc[c] = 0.0;
+    for (int r = (t & ~63) + lane; r < m; r += 64) {
+      if (r < t) continue;
+      const double vr = (r == t && !UNIT_STORED) ? 1.0 : (double)v[r];
+#pragma unroll
+      for (int c = 0; c < RBMAX; ++c)
+        if (c < nc) acc[c] += vr * xs[r + c * ldx];
+    }
+#pragma unroll
+    for (int c = 0; c < RBMAX; ++c)
+      if (c < nc) acc[c] = tt * wave_sum(acc[c]);
+    for (int r = (t & ~63) + lane; r < m; r += 64) {
+      if (r < t) continue;
+      const double vr = (r == t && !UNIT_STORED) ? 1.0 : (double)v[r];
+#pragma unroll
+      for (int c = 0; c < RBMAX; ++c)
+        if (c < nc) xs[r + c * ldx] -= acc[c] * vr;
+    }
+  }
+}
+
+// x <- R^{-1} x, R upper triangular n x n column-major (ld), x in LDS.
+template <typename T>
+__device__ void wave_backsolve(const T* __restrict__ R, int64_t ld, int n, double* xs, int nc, int ldx) {
+  const int lane = threadIdx.x & 63;
+  for (int c = n - 1; c >= 0; --c) {
+    const double d = (double)R[c + (int64_t)c * ld];
+    if (lane == (c & 63))
+      for (int q = 0; q < nc; ++q) xs[c + q * ldx] /= d;
+    __syncthreads();
+    const T* Rc = R + (int64_t)c * ld;
+    for (int r = lane; r < c; r += 64) {
+      const double rv = (double)Rc[r];
+      for (int q = 0; q < nc; ++q) xs[r + q * ldx] -= rv * xs[c + q * ldx];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_ap_front_fwd(const ApFront<T>* __restrict__ ds, double* x,
+                                                    int64_t ldx, int nrhs, int rb) {
+  const ApFront<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.n == 0 || nc <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* xs = reinterpret_cast<double*>(smem);
+  const int m = d.m, lane = threadIdx.x;
+  for (int c = 0; c < nc; ++c)
+    for (int r = lane; r < m; r += 64) xs[r + c * m] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
+  wave_reflectors<T, false>(d.vr, m, d.tau, 0, d.n, 1, m, xs, nc, m);
+  for (int c = 0; c < nc; ++c)
+    for (int r = lane; r < m; r += 64) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = xs[r + c * m];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_ap_front_bwd(const ApFront<T>* __restrict__ ds, double* x,
+                                                    int64_t ldx, int nrhs, int rb) {
+  const ApFront<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.n == 0 || nc <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = d.n, k = d.k, lane = threadIdx.x;
+  double* ys = reinterpret_cast<double*>(smem);  // n x nc
+  double* xc = ys + (size_t)n * rb;              // k x nc
+  for (int c = 0; c < nc; ++c) {
+    for (int r = lane; r < n; r += 64) ys[r + c * n] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
+    for (int r = lane; r < k; r += 64) xc[r + c * k] = x[d.cols[r] + (int64_t)(c0 + c) * ldx];
+  }
+  __syncthreads();
+  // y_s -= R_sj x_j
+  for (int j = 0; j < k; ++j) {
+    const T* col = d.rsj + (int64_t)j * n;
+    for (int r = lane; r < n; r += 64) {
+      const double rv = (double)col[r];
+      for (int c = 0; c < nc; ++c) ys[r + c * n] -= rv * xc[j + c * k];
+    }
+  }
+  __syncthreads();
+  wave_backsolve<T>(d.vr, d.m, n, ys, nc, n);
+  for (int c = 0; c < nc; ++c)
+    for (int r = lane; r < n; r += 64) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = ys[r + c * n];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_ap_iface_fwd(const ApIface<T>* __restrict__ ds, double* x,
+                                                    int64_t ldx, int nrhs, int rb) {
+  const ApIface<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.P == 0 || nc <= 0 || *d.flag != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* xs = reinterpret_cast<double*>(smem);
+  const int P = d.P, lane = threadIdx.x, r = *d.rank;
+  for (int c = 0; c < nc; ++c)
+    for (int q = lane; q < P; q += 64) xs[q + c * P] = x[d.slots[q] + (int64_t)(c0 + c) * ldx];
+  wave_reflectors<T, false>(d.vru, P, d.tauu, 0, P, 1, P, xs, nc, P);
+  if (r < P) wave_reflectors<T, true>(d.vq, P, d.tauq, 0, r, 1, P, xs, nc, P);
+  for (int c = 0; c < nc; ++c)
+    for (int q = lane; q < P; q += 64) x[d.slots[q] + (int64_t)(c0 + c) * ldx] = xs[q + c * P];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_ap_iface_bwd(const ApIface<T>* __restrict__ ds, double* x,
+                                                    int64_t ldx, int nrhs, int rb) {
+  const ApIface<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.P == 0 || nc <= 0 || *d.flag != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* xs = reinterpret_cast<double*>(smem);
+  const int P = d.P, lane = threadIdx.x, r = *d.rank;
+  for (int c = 0; c < nc; ++c)
+    for (int q = lane; q < P; q += 64) xs[q + c * P] = x[d.slots[q] + (int64_t)(c0 + c) * ldx];
+  if (r < P) wave_reflectors<T, true>(d.vq, P, d.tauq, r - 1, -1, -1, P, xs, nc, P);
+  __syncthreads();
+  wave_backsolve<T>(d.vru, P, P, xs, nc, P);
+  for (int c = 0; c < nc; ++c)
+    for (int q = lane; q < P; q += 64) x[d.slots[q] + (int64_t)(c0 + c) * ldx] = xs[q + c * P];
+}
+
+__global__ void k_gather_perm(double* xhat, const double* __restrict__ b, int64_t ldb,
+                              const int64_t* __restrict__ perm, int64_t N, int nrhs) {
+  const int64_t tot = N * nrhs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i / N, r = i - c * N;
+    xhat[i] = b[perm[r] + c * ldb];
+  }
+}
+
+__global__ void k_scatter_perm(double* x, int64_t ldx, const double* __restrict__ xhat,
+                               const int64_t* __restrict__ perm, const double* __restrict__ dc, int64_t N,
+                               int nrhs) {
+  const int64_t tot = N * nrhs;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i / N, r = i - c * N;
+    const int64_t o = perm[r];
+    x[o + c * ldx] = xhat[i] * dc[o];
+  }
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+void launch_copy(const CopyTile<T>* tiles, const int64_t* jobptr, int64_t njobs, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)njobs), dim3(NT), 0, s, tiles, jobptr);
+}
+
+template <typename T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+template <typename T>
+void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(k_scatter_nz<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, nnz);
+}
+
+static size_t qr_bytes_jb(int max_m, int jb, int eb) {
+  const size_t lds = align16((size_t)max_m * (jb + 1) * eb) + align16((size_t)jb * jb * eb) +
+                     (size_t)jb * jb * sizeof(double) + 8 * sizeof(double) + (size_t)jb * sizeof(double);
+  return lds;
+}
+
+static constexpr size_t kLdsBudget = 64 * 1024;
+
+int qr_panel_width(int max_m, int eb) {
+  const int cap = eb == 8 ? 16 : 32;
+  for (int jb = cap; jb >= 1; jb >>= 1)
+    if (qr_bytes_jb(max_m, jb, eb) <= kLdsBudget) return jb;
+  return 0;
+}
+
+size_t qr_lds_bytes(int max_m, int jb, int eb) { return qr_bytes_jb(max_m, jb, eb); }
+
+template <typename T>
+void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = qr_bytes_jb(max_m, jb, sizeof(T));
+  switch (jb) {
+#define SPAQR_QR_CASE(J) \
+  case J: hipLaunchKernelGGL((k_qr<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d); break;
+    SPAQR_QR_CASE(1)
+    SPAQR_QR_CASE(2)
+    SPAQR_QR_CASE(4)
+    SPAQR_QR_CASE(8)
+    SPAQR_QR_CASE(16)
+    SPAQR_QR_CASE(32)
+#undef SPAQR_QR_CASE
+    default: break;
+  }
+}
+
+template <typename T>
+void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool, int jb, int max_p,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = qr_bytes_jb(max_p, jb, sizeof(T));
+  switch (jb) {
+#define SPAQR_SC_CASE(J) \
+  case J: hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, pool); break;
+    SPAQR_SC_CASE(1)
+    SPAQR_SC_CASE(2)
+    SPAQR_SC_CASE(4)
+    SPAQR_SC_CASE(8)
+    SPAQR_SC_CASE(16)
+    SPAQR_SC_CASE(32)
+#undef SPAQR_SC_CASE
+    default: break;
+  }
+}
+
+template <typename T>
+void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
+                     int max_p, int max_nb, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = align16((size_t)(max_nb + 1) * sizeof(int)) + (size_t)max_p * sizeof(double) +
+                     8 * sizeof(double) + NT * sizeof(double) + NT * sizeof(int);
+  hipLaunchKernelGGL(k_sparsify<T>, dim3((unsigned)n), dim3(NT), lds, s, d, nb, pool, rank, eps);
+}
+
+static constexpr size_t kApplyLds = 64 * 1024;
+
+int apply_rhs_block(int max_rows, int nrhs) {
+  int rb = RBMAX;
+  if (rb > nrhs) rb = nrhs;
+  while (rb > 1 && (size_t)max_rows * rb * sizeof(double) > kApplyLds) --rb;
+  if ((size_t)max_rows * rb * sizeof(double) > kApplyLds) return 0;
+  return rb;
+}
+
+#define SPAQR_AP_LAUNCH(KERNEL, DESC)                                                           \
+  template <typename T>                                                                         \
+  void launch_##KERNEL(const DESC<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, \
+                       hipStream_t s) {                                                         \
+    if (n <= 0 || nrhs <= 0) return;                                                            \
+    const int rb = apply_rhs_block(max_rows, nrhs);                                             \
+    const size_t lds = (size_t)max_rows * rb * sizeof(double);                                  \
+    hipLaunchKernelGGL(k_ap_##KERNEL<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)),  \
+                       dim3(64), lds, s, d, x, ldx, nrhs, rb);                                  \
+  }
+SPAQR_AP_LAUNCH(front_fwd, ApFront)
+SPAQR_AP_LAUNCH(front_bwd, ApFront)
+SPAQR_AP_LAUNCH(iface_fwd, ApIface)
+SPAQR_AP_LAUNCH(iface_bwd, ApIface)
+#undef SPAQR_AP_LAUNCH
+
+void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_t* perm, int64_t N,
+                        int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, xhat, b, ldb, perm,
+                     N, nrhs);
+}
+
+void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,
+                         const double* dc, int64_t N, int nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, x, ldx, xhat, perm,
+                     dc, N, nrhs);
+}
+
+#define SPAQR_INST(T)                                                                                  \
+  template void launch_copy<T>(const CopyTile<T>*, const int64_t*, int64_t, hipStream_t);            \
+  template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                          \
+  template void launch_scatter_nz<T>(T*, const int64_t*, const double*, int64_t, hipStream_t);       \
+  template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
+  template void launch_scale<T>(const ScaleBlk*, int64_t, const ScaleFac<T>*, T*, int, int, hipStream_t); \
+  template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
+                                   hipStream_t);                                                     \
+  template void launch_front_fwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
+  template void launch_front_bwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
+  template void launch_iface_fwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
+  template void launch_iface_bwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t);
+SPAQR_INST(float)
+SPAQR_INST(double)
+#undef SPAQR_INST
+template void launch_fill<int>(int*, int64_t, int, hipStream_t);
+
+}  // namespace spaqr

@@ -1,0 +1,141 @@
+// Descriptors shared by the host driver and the HIP kernels, and the launch
+// entry points.  All matrices handed to kernels are dense and row-major unless
+// a field says column-major.  Pointers are absolute device addresses.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace spaqr {
+
+// One rectangular copy: dst[r*ldd + c] = src[r*lds + c] (mode 0), or the
+// transpose dst[c*ldd + r] = src[r*lds + c] (mode 1); src == nullptr zero-fills
+// (mode 0 only).  Tiles of one job run in order, one workgroup per job.
+template <typename T>
+struct CopyTile {
+  const T* src;
+  T* dst;
+  int32_t rows, cols, lds, ldd;
+  int32_t mode, pad;
+};
+
+// Blocked Householder QR of a row-major m x nc matrix (ld = nc): reflectors
+// for the first n columns, applied to all nc columns.  V (unit diagonal
+// implicit) is left below the diagonal and R on and above it; tau[0..n) and
+// the compact-WY factors of every JB-column panel (JB x JB, column-major,
+// zero-padded) are written.  If some |R_ii| is exactly zero, *flag = 1.
+template <typename T>
+struct QRDesc {
+  T* a;
+  T* tau;
+  T* tpan;
+  int* flag;  // may be null
+  int32_t m, n, nc, pad;
+};
+
+// One block B (row-major rows x cols, ld = cols) of the trailing matrix to be
+// scaled: B <- U_i^T B (if the row cluster is a scaled interface), then
+// B <- B R_j^{-1} (if the column cluster is), or B := I for a scaled
+// diagonal block.  Interface factors are column-major P x P with V below the
+// diagonal and R_pp on/above it.
+template <typename T>
+struct ScaleFac {
+  const T* vr;
+  const T* tau;
+  const T* tpan;
+  const int* flag;  // nonzero: R_pp had a zero diagonal, interface not scaled
+  int32_t P, pad;
+};
+
+struct ScaleBlk {
+  int64_t blk;      // element offset of the block in the pool
+  int32_t rows, cols;
+  int32_t fi, fj;   // index into the ScaleFac table, or -1
+};
+
+// Sparsification of one interface p (Sections 2.5-2.6): gathers
+// C = [A_np^T | A_pn] from its neighbour blocks using the current cluster
+// sizes, runs the partial CPQR with FP64 norms and pivots, writes the coarse
+// blocks back and stores the reflectors (column-major P x r, explicit unit
+// diagonal and zeros above) and tau.  rank[cluster] receives r.
+struct SpNbr {
+  int64_t blk;      // element offset of block (i, p) or (p, j) in the pool
+  int32_t cluster;  // the neighbour cluster (its current size is rank[cluster])
+  int32_t ld;       // leading dimension of the block
+};
+
+template <typename T>
+struct SpDesc {
+  T* C;             // P x mmax row-major workspace
+  double* nrm;      // mmax doubles
+  int32_t* perm;    // 2 * mmax ints
+  T* vq;            // P x P column-major (first r columns used)
+  T* tauq;          // P
+  const int* flag;  // scaling flag of p (nonzero: not scaled, not sparsified)
+  int64_t nb;       // first neighbour in the SpNbr array
+  int32_t nrow, ncol;
+  int32_t cluster, P, mmax, pad;
+};
+
+// Apply descriptors (vectors are FP64, slots index the permuted vector).
+template <typename T>
+struct ApFront {
+  const T* vr;    // m x n column-major: V below the diagonal, R_ss on/above
+  const T* rsj;   // n x k column-major
+  const T* tau;   // n
+  const int32_t* rows;  // m slots: the front's row clusters
+  const int32_t* cols;  // k slots: the ancestor column clusters
+  int32_t m, n, k, pad;
+};
+
+template <typename T>
+struct ApIface {
+  const T* vru;   // P x P column-major scaling factor (U below diag, R_pp above)
+  const T* tauu;
+  const T* vq;    // P x P column-major sparsification reflectors (first r)
+  const T* tauq;
+  const int32_t* slots;  // P slots
+  const int* rank;       // r (== P when nothing was dropped)
+  const int* flag;       // nonzero: interface was not scaled
+  int32_t P, pad;
+};
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+void launch_copy(const CopyTile<T>* tiles, const int64_t* jobptr, int64_t njobs, hipStream_t s);
+template <typename T>
+void launch_fill(T* p, int64_t n, T v, hipStream_t s);
+template <typename T>
+void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s);
+// jb: panel width (power of two <= 32); lds_bytes: dynamic LDS per workgroup
+template <typename T>
+void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s);
+int qr_panel_width(int max_m, int elem_bytes);
+size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
+template <typename T>
+void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool, int jb, int max_p,
+                  hipStream_t s);
+template <typename T>
+void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
+                     int max_p, int max_nb, hipStream_t s);
+// Apply launches: max_rows = the largest number of FP64 rows one item keeps in
+// LDS per right-hand side (m for fronts forward, n + k backward, P for
+// interfaces).  Returns without launching when there is nothing to do.
+int apply_rhs_block(int max_rows, int nrhs);
+template <typename T>
+void launch_front_fwd(const ApFront<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
+template <typename T>
+void launch_front_bwd(const ApFront<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
+template <typename T>
+void launch_iface_fwd(const ApIface<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
+template <typename T>
+void launch_iface_bwd(const ApIface<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
+// xhat[i + c*N] = b[perm[i] + c*ldb]
+void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_t* perm, int64_t N,
+                        int nrhs, hipStream_t s);
+// x[perm[i] + c*ldx] = xhat[i + c*N] * dc[perm[i]]
+void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,
+                         const double* dc, int64_t N, int nrhs, hipStream_t s);
+
+}  // namespace spaqr

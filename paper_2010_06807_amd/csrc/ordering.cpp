@@ -1,0 +1,221 @@
+// Geometric modified nested dissection with interfaces on a box grid
+// (Section 2.3, Figs. mnd and mnd_multilvl; geometric partitioning of the
+// graph of A^T A for grid problems, Section 4).
+//
+// Separators are two grid layers thick so that they cut the graph of A^T A
+// (which couples points up to two steps apart).  A box [lo, hi) splits on its
+// longest axis (lowest axis on ties) at m = lo + floor((w-2)/2): separator
+// {m, m+1}, low child [lo, m), high child [m+2, hi).  Nodes are heap-numbered
+// (root 1, children 2k, 2k+1); level = bit length, leaves at level L.
+//
+// A separator point of node B is pushed onto the adjacent layer of each child
+// (m-1 low, m+2 high) and descended to the deepest node containing it:
+// (dl, dh).  Its stage-k interface label is (anc_k(dl), anc_k(dh)).  Because
+// that label for every k is a function of (dl, dh) alone, the finest clusters
+// are the distinct (node, dl, dh) triples; sorting those triples (level
+// descending, node ascending, then the labels of stages 2..L
+// lexicographically) and listing points in natural order inside each triple
+// gives the permutation, and every coarser cluster is a run of triples.
+#include <algorithm>
+#include <memory>
+#include <numeric>
+
+#include "common.hpp"
+
+namespace spaqr {
+
+namespace {
+
+struct Tree {
+  int dim, L;
+  std::vector<int32_t> axis;   // split axis per internal node
+  std::vector<int64_t> msplit; // split coordinate m per internal node
+};
+
+int64_t descend(const Tree& t, const int64_t* c, int64_t node) {
+  while (bit_length((uint64_t)node) < t.L) {
+    int ax = t.axis[node];
+    int64_t m = t.msplit[node];
+    int64_t v = c[ax];
+    if (v == m || v == m + 1) return node;
+    node = 2 * node + (v >= m + 2 ? 1 : 0);
+  }
+  return node;
+}
+
+struct Finest {
+  int32_t level;
+  int64_t node, dl, dh;
+};
+
+}  // namespace
+
+Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
+  SPAQR_REQUIRE(dim == 2 || dim == 3, SPAQR_EINVAL, "dim must be 2 or 3");
+  int64_t n = 1;
+  for (int a = 0; a < dim; ++a) {
+    SPAQR_REQUIRE(sides[a] >= 1, SPAQR_EINVAL, "grid sides must be >= 1");
+    n *= sides[a];
+  }
+  int L = nlevels;
+  if (L <= 0) {
+    // smallest L with 64 * 2^L >= n, i.e. ceil(log2(n / 64)); at least 1
+    L = 0;
+    while ((int64_t(64) << L) < n) ++L;
+    L = std::max(1, L);
+  }
+  SPAQR_REQUIRE(L >= 1 && L <= 30, SPAQR_EINVAL, "levels out of range");
+
+  auto* o = new Ordering();
+  std::unique_ptr<Ordering> guard(o);
+  o->dim = dim;
+  for (int a = 0; a < 3; ++a) o->sides[a] = a < dim ? sides[a] : 1;
+  o->L = L;
+  o->n = n;
+
+  // ---- tree of boxes
+  Tree t;
+  t.dim = dim;
+  t.L = L;
+  const int64_t nn = int64_t(1) << L;
+  t.axis.assign(nn, -1);
+  t.msplit.assign(nn, -1);
+  std::vector<int64_t> lo(nn * 3, 0), hi(nn * 3, 0);
+  for (int a = 0; a < dim; ++a) hi[1 * 3 + a] = sides[a];
+  for (int64_t b = 1; b < (int64_t(1) << (L - 1)); ++b) {
+    int ax = 0;
+    int64_t w = hi[b * 3] - lo[b * 3];
+    for (int a = 1; a < dim; ++a) {
+      int64_t e = hi[b * 3 + a] - lo[b * 3 + a];
+      if (e > w) { w = e; ax = a; }
+    }
+    SPAQR_REQUIRE(w >= 4, SPAQR_EINVAL,
+                  "too many levels: a box above the leaves has longest extent < 4");
+    int64_t m = lo[b * 3 + ax] + (w - 2) / 2;
+    t.axis[b] = ax;
+    t.msplit[b] = m;
+    for (int a = 0; a < 3; ++a) {
+      lo[2 * b * 3 + a] = lo[b * 3 + a];
+      hi[2 * b * 3 + a] = hi[b * 3 + a];
+      lo[(2 * b + 1) * 3 + a] = lo[b * 3 + a];
+      hi[(2 * b + 1) * 3 + a] = hi[b * 3 + a];
+    }
+    hi[2 * b * 3 + ax] = m;
+    lo[(2 * b + 1) * 3 + ax] = m + 2;
+  }
+
+  // ---- per point: deepest node and (for separators) both sides' deepest nodes
+  std::vector<Finest> fin(n);
+  const int64_t s0 = sides[0], s1 = dim > 1 ? sides[1] : 1;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t c[3] = {i % s0, (i / s0) % s1, dim == 3 ? i / (s0 * s1) : 0};
+    int64_t nd = descend(t, c, 1);
+    int lv = bit_length((uint64_t)nd);
+    Finest f{lv, nd, 0, 0};
+    if (lv < L) {
+      int ax = t.axis[nd];
+      int64_t m = t.msplit[nd];
+      int64_t cl[3] = {c[0], c[1], c[2]}, ch[3] = {c[0], c[1], c[2]};
+      cl[ax] = m - 1;
+      ch[ax] = m + 2;
+      f.dl = descend(t, cl, 2 * nd);
+      f.dh = descend(t, ch, 2 * nd + 1);
+    }
+    fin[i] = f;
+  }
+
+  // ---- distinct finest clusters, sorted
+  auto less = [L](const Finest& a, const Finest& b) {
+    if (a.level != b.level) return a.level > b.level;
+    if (a.node != b.node) return a.node < b.node;
+    for (int k = 2; k <= L; ++k) {
+      int64_t x = anc_at(a.dl, k), y = anc_at(b.dl, k);
+      if (x != y) return x < y;
+      x = anc_at(a.dh, k);
+      y = anc_at(b.dh, k);
+      if (x != y) return x < y;
+    }
+    return false;
+  };
+  auto same = [](const Finest& a, const Finest& b) {
+    return a.node == b.node && a.dl == b.dl && a.dh == b.dh;
+  };
+  std::vector<Finest> uniq(fin);
+  std::sort(uniq.begin(), uniq.end(), [](const Finest& a, const Finest& b) {
+    if (a.node != b.node) return a.node < b.node;
+    if (a.dl != b.dl) return a.dl < b.dl;
+    return a.dh < b.dh;
+  });
+  uniq.erase(std::unique(uniq.begin(), uniq.end(), same), uniq.end());
+  std::sort(uniq.begin(), uniq.end(), less);
+  const int64_t nf = (int64_t)uniq.size();
+
+  // cluster id of each point: binary search in (node, dl, dh) order
+  std::vector<int64_t> byKey(nf);
+  std::iota(byKey.begin(), byKey.end(), 0);
+  std::sort(byKey.begin(), byKey.end(), [&](int64_t a, int64_t b) {
+    const Finest &x = uniq[a], &y = uniq[b];
+    if (x.node != y.node) return x.node < y.node;
+    if (x.dl != y.dl) return x.dl < y.dl;
+    return x.dh < y.dh;
+  });
+  std::vector<int64_t> cid(n), cnt(nf + 1, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const Finest& f = fin[i];
+    auto it = std::lower_bound(byKey.begin(), byKey.end(), f, [&](int64_t a, const Finest& key) {
+      const Finest& x = uniq[a];
+      if (x.node != key.node) return x.node < key.node;
+      if (x.dl != key.dl) return x.dl < key.dl;
+      return x.dh < key.dh;
+    });
+    cid[i] = *it;
+    cnt[cid[i] + 1]++;
+  }
+  for (int64_t c = 0; c < nf; ++c) cnt[c + 1] += cnt[c];
+  o->perm.assign(n, 0);
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t i = 0; i < n; ++i) o->perm[pos[cid[i]]++] = i;
+  }
+  o->iperm.assign(n, 0);
+  for (int64_t p = 0; p < n; ++p) o->iperm[o->perm[p]] = p;
+
+  // ---- clusters of every stage: runs of finest clusters with equal labels
+  o->stages.assign(L + 1, StageClusters());
+  for (int k = L; k >= 1; --k) {
+    StageClusters& sc = o->stages[k];
+    int64_t prevNode = -1, prevA = -1, prevB = -1;
+    for (int64_t c = 0; c < nf; ++c) {
+      const Finest& f = uniq[c];
+      if (f.level > k) continue;
+      int64_t a = f.level < k ? anc_at(f.dl, k) : 0;
+      int64_t b = f.level < k ? anc_at(f.dh, k) : 0;
+      if (sc.start.empty() || f.node != prevNode || a != prevA || b != prevB) {
+        sc.start.push_back(cnt[c]);
+        sc.end.push_back(cnt[c + 1]);
+        sc.node.push_back(f.node);
+        sc.level.push_back(f.level);
+      } else {
+        sc.end.back() = cnt[c + 1];
+      }
+      prevNode = f.node;
+      prevA = a;
+      prevB = b;
+    }
+  }
+  for (int k = L; k >= 2; --k) {
+    StageClusters& sc = o->stages[k];
+    const StageClusters& up = o->stages[k - 1];
+    sc.parent.assign(sc.count(), -1);
+    for (int64_t c = 0; c < sc.count(); ++c) {
+      if (sc.level[c] >= k) continue;
+      auto it = std::upper_bound(up.start.begin(), up.start.end(), sc.start[c]);
+      sc.parent[c] = (int64_t)(it - up.start.begin()) - 1;
+    }
+  }
+  o->stages[1].parent.assign(o->stages[1].count(), -1);
+  guard.release();
+  return o;
+}
+
+}  // namespace spaqr

@@ -1,0 +1,165 @@
+// Request loop of the serving path: requests are copied at submission, admitted
+// when their estimated device memory fits the budget, factorized, solved with
+// all of their right-hand sides at once, and retired.
+#include <deque>
+#include <map>
+#include <memory>
+
+#include "engine.hpp"
+
+namespace spaqr {
+
+struct Request {
+  uint64_t ticket = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+  spaqr_csr A{};
+  Ordering ord;
+  spaqr_opts opts{};
+  std::vector<double> b, x;
+  int64_t nrhs = 0;
+  double tol = 1e-10;
+  size_t est = 0;
+  std::unique_ptr<Symbolic> sym;
+  std::unique_ptr<EngineBase> eng;
+  std::vector<spaqr_solve_info> info;
+  int status = SPAQR_PENDING;
+};
+
+// Device memory a request needs while it is resident: factors (bounded by a
+// per-unknown allowance that grows with the nested-dissection depth) plus
+// the FGMRES bases.
+static size_t estimate_bytes(int64_t n, int64_t nnz, int L, int64_t nrhs, const spaqr_opts& o) {
+  const size_t eb = o.precision == 32 ? 4 : 8;
+  const size_t factors = (size_t)n * eb * (size_t)(64 + 24 * L) + (size_t)nnz * 24;
+  const size_t krylov = (size_t)n * nrhs * 8 * (size_t)(2 * o.restart + 4);
+  return factors + krylov;
+}
+
+}  // namespace spaqr
+
+struct spaqr_server {
+  size_t budget = 0, used = 0;
+  hipStream_t stream = nullptr;
+  uint64_t next = 1;
+  std::deque<std::unique_ptr<spaqr::Request>> queue;
+  std::vector<std::unique_ptr<spaqr::Request>> active;
+  std::map<uint64_t, std::unique_ptr<spaqr::Request>> done;
+};
+
+using namespace spaqr;
+
+namespace {
+template <typename F>
+spaqr_status guard(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    return SPAQR_ENOMEM;
+  } catch (...) {
+    return SPAQR_EINVAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+spaqr_status spaqr_server_create(size_t mem_budget, void* hip_stream, spaqr_server** out) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(out && mem_budget > 0, SPAQR_EINVAL, "bad argument");
+    auto* s = new spaqr_server();
+    s->budget = mem_budget;
+    s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    *out = s;
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_submit(spaqr_server* srv, const spaqr_csr* A, const spaqr_ordering* ord, const spaqr_opts* opts,
+                          const double* b, int64_t nrhs, double tol, uint64_t* ticket) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(srv && A && ord && b && ticket && nrhs >= 1 && tol > 0, SPAQR_EINVAL, "bad argument");
+    SPAQR_REQUIRE(A->n == ord->o.n, SPAQR_EINVAL, "matrix size differs from the ordering");
+    auto r = std::make_unique<Request>();
+    r->rowptr.assign(A->rowptr, A->rowptr + A->n + 1);
+    r->col.assign(A->col, A->col + A->nnz);
+    r->val.assign(A->val, A->val + A->nnz);
+    r->A = {A->n, A->nnz, r->rowptr.data(), r->col.data(), r->val.data()};
+    r->ord = ord->o;
+    r->opts = opts ? *opts : spaqr_opts_default();
+    r->b.assign(b, b + A->n * nrhs);
+    r->nrhs = nrhs;
+    r->tol = tol;
+    r->est = estimate_bytes(A->n, A->nnz, ord->o.L, nrhs, r->opts);
+    SPAQR_REQUIRE(r->est <= srv->budget, SPAQR_ENOMEM, "request alone exceeds the memory budget");
+    r->ticket = srv->next++;
+    *ticket = r->ticket;
+    srv->queue.push_back(std::move(r));
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
+    while (!srv->queue.empty() && srv->used + srv->queue.front()->est <= srv->budget) {
+      srv->used += srv->queue.front()->est;
+      srv->active.push_back(std::move(srv->queue.front()));
+      srv->queue.pop_front();
+    }
+    std::vector<std::unique_ptr<Request>> keep;
+    for (auto& r : srv->active) {
+      if (!r->eng) {
+        r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
+        r->eng = make_engine(&r->A, *r->sym, r->opts, srv->stream);
+        keep.push_back(std::move(r));
+        continue;
+      }
+      const int64_t N = r->A.n;
+      double *db = nullptr, *dx = nullptr;
+      SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&db), N * r->nrhs * sizeof(double)));
+      SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&dx), N * r->nrhs * sizeof(double)));
+      SPAQR_HIP(hipMemcpyAsync(db, r->b.data(), N * r->nrhs * sizeof(double), hipMemcpyHostToDevice, srv->stream));
+      r->info.assign(r->nrhs, spaqr_solve_info{});
+      r->status = fgmres_solve(*r->eng, db, N, dx, N, (int)r->nrhs, r->tol, r->info.data());
+      r->x.resize(N * r->nrhs);
+      SPAQR_HIP(hipMemcpyAsync(r->x.data(), dx, N * r->nrhs * sizeof(double), hipMemcpyDeviceToHost, srv->stream));
+      SPAQR_HIP(hipStreamSynchronize(srv->stream));
+      (void)hipFree(db);
+      (void)hipFree(dx);
+      r->eng.reset();
+      r->sym.reset();
+      srv->used -= r->est;
+      srv->done[r->ticket] = std::move(r);
+    }
+    srv->active.swap(keep);
+    if (active) *active = (int)(srv->active.size() + srv->queue.size());
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_poll(spaqr_server* srv, uint64_t ticket, double* x, spaqr_solve_info* info) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end()) return SPAQR_PENDING;
+    Request& r = *it->second;
+    if (x) std::copy(r.x.begin(), r.x.end(), x);
+    if (info) std::copy(r.info.begin(), r.info.end(), info);
+    const int st = r.status;
+    srv->done.erase(it);
+    return st;
+  });
+}
+
+void spaqr_server_destroy(spaqr_server* srv) {
+  try {
+    delete srv;
+  } catch (...) {
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,286 @@
+// Symbolic analysis of Algorithm 2 over the cluster hierarchy.
+//
+// Front of a cluster s at level k (Section 2.4): rows [s; n1(s)] where n1(s)
+// are the clusters i != s holding a block (i, s); columns {s} plus the
+// clusters j of proper ND ancestors of s that hold a block in some front row.
+// Columns of non-ancestor clusters are left alone: H_s acts on them as the
+// identity up to O(eps) (Lemma 2, Theorem well_sep).  Fill: every block
+// (i, j), i in n1(s), j in the ancestor columns.
+//
+// Same-level fronts update a common block (i, j) only if they share a row
+// cluster i and a column cluster j; greedy colouring of that conflict graph
+// (ascending cluster, lowest free colour) groups fronts that touch disjoint
+// blocks.  Fronts run colour by colour, ascending inside a colour.
+//
+// Sparsification neighbours of an interface p: blocks (i, p) and (p, j);
+// interfaces that share a block are coloured apart the same way.
+#include "symbolic.hpp"
+
+#include <algorithm>
+#include <memory>
+
+namespace spaqr {
+
+int64_t BlockSet::find(int32_t i, int32_t j) const {
+  auto b = col.begin() + rowptr[i], e = col.begin() + rowptr[i + 1];
+  auto it = std::lower_bound(b, e, j);
+  if (it == e || *it != j) return -1;
+  return (int64_t)(it - col.begin());
+}
+
+BlockSet BlockSet::from_pairs(int64_t nclu, std::vector<Pair>& pairs) {
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  BlockSet s;
+  s.nclu = nclu;
+  s.rowptr.assign(nclu + 1, 0);
+  s.col.resize(pairs.size());
+  for (size_t t = 0; t < pairs.size(); ++t) {
+    s.rowptr[pairs[t].first + 1]++;
+    s.col[t] = pairs[t].second;
+  }
+  for (int64_t i = 0; i < nclu; ++i) s.rowptr[i + 1] += s.rowptr[i];
+  return s;
+}
+
+std::vector<Pair> BlockSet::pairs() const {
+  std::vector<Pair> p;
+  p.reserve(col.size());
+  for (int64_t i = 0; i < nclu; ++i)
+    for (int64_t t = rowptr[i]; t < rowptr[i + 1]; ++t) p.emplace_back((int32_t)i, col[t]);
+  return p;
+}
+
+namespace {
+
+// Column adjacency (transpose) of a block set.
+void transpose(const BlockSet& s, std::vector<int64_t>& cptr, std::vector<int32_t>& crow) {
+  cptr.assign(s.nclu + 1, 0);
+  for (int32_t j : s.col) cptr[j + 1]++;
+  for (int64_t j = 0; j < s.nclu; ++j) cptr[j + 1] += cptr[j];
+  crow.resize(s.col.size());
+  std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
+  for (int64_t i = 0; i < s.nclu; ++i)
+    for (int64_t t = s.rowptr[i]; t < s.rowptr[i + 1]; ++t) crow[pos[s.col[t]]++] = (int32_t)i;
+}
+
+bool sorted_intersect(const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+  size_t x = 0, y = 0;
+  while (x < a.size() && y < b.size()) {
+    if (a[x] == b[y]) return true;
+    if (a[x] < b[y]) ++x; else ++y;
+  }
+  return false;
+}
+
+// Greedy colouring in index order given each item's neighbour list.
+std::vector<int32_t> greedy(const std::vector<std::vector<int32_t>>& nbr) {
+  std::vector<int32_t> colour(nbr.size(), -1);
+  std::vector<int32_t> mark;
+  for (size_t v = 0; v < nbr.size(); ++v) {
+    int32_t hi = 0;
+    for (int32_t u : nbr[v]) if (colour[u] >= 0) hi = std::max(hi, colour[u] + 1);
+    mark.assign(hi + 1, 0);
+    for (int32_t u : nbr[v]) if (colour[u] >= 0) mark[colour[u]] = 1;
+    int32_t c = 0;
+    while (mark[c]) ++c;
+    colour[v] = c;
+  }
+  return colour;
+}
+
+void order_by_colour(const std::vector<int32_t>& colour, std::vector<int32_t>& order,
+                     std::vector<int32_t>& ptr) {
+  int32_t nc = 0;
+  for (int32_t c : colour) nc = std::max(nc, c + 1);
+  ptr.assign(nc + 1, 0);
+  for (int32_t c : colour) ptr[c + 1]++;
+  for (int32_t c = 0; c < nc; ++c) ptr[c + 1] += ptr[c];
+  order.resize(colour.size());
+  std::vector<int32_t> pos(ptr.begin(), ptr.end() - 1);
+  for (size_t v = 0; v < colour.size(); ++v) order[pos[colour[v]]++] = (int32_t)v;
+}
+
+}  // namespace
+
+Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
+  SPAQR_REQUIRE(A && A->rowptr && A->col && A->val, SPAQR_EINVAL, "NULL matrix");
+  SPAQR_REQUIRE(A->n == ord.n, SPAQR_EINVAL, "matrix size differs from the ordering");
+  SPAQR_REQUIRE(A->rowptr[0] == 0 && A->rowptr[A->n] == A->nnz, SPAQR_EINVAL, "bad rowptr");
+  SPAQR_REQUIRE(skip >= 0, SPAQR_EINVAL, "skip < 0");
+  const int64_t n = A->n;
+  for (int64_t r = 0; r < n; ++r) {
+    SPAQR_REQUIRE(A->rowptr[r + 1] >= A->rowptr[r], SPAQR_EINVAL, "rowptr decreases");
+    for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
+      SPAQR_REQUIRE(A->col[t] >= 0 && A->col[t] < n, SPAQR_EINVAL, "column out of range");
+      SPAQR_REQUIRE(t == A->rowptr[r] || A->col[t] > A->col[t - 1], SPAQR_EINVAL,
+                    "columns not sorted or duplicated");
+    }
+  }
+  auto* S = new Symbolic();
+  std::unique_ptr<Symbolic> guard(S);
+  S->ord = ord;
+  S->L = ord.L;
+  S->skip = skip;
+  S->n = n;
+  S->nnz = A->nnz;
+  const int L = ord.L;
+  S->st.assign(L + 1, StageSym());
+
+  // ---- stage-L block pattern from the nonzeros of A
+  const StageClusters& cl = ord.stages[L];
+  S->cluster_of_pos_L.assign(n, 0);
+  for (int64_t c = 0; c < cl.count(); ++c)
+    for (int64_t p = cl.start[c]; p < cl.end[c]; ++p) S->cluster_of_pos_L[p] = (int32_t)c;
+  std::vector<Pair> pairs;
+  pairs.reserve(A->nnz);
+  for (int64_t r = 0; r < n; ++r) {
+    int32_t ci = S->cluster_of_pos_L[ord.iperm[r]];
+    for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t)
+      pairs.emplace_back(ci, S->cluster_of_pos_L[ord.iperm[A->col[t]]]);
+  }
+  BlockSet cur = BlockSet::from_pairs(cl.count(), pairs);
+
+  for (int k = L; k >= 1; --k) {
+    StageSym& ss = S->st[k];
+    const StageClusters& sc = ord.stages[k];
+    ss.k = k;
+    ss.nclu = sc.count();
+    ss.in = cur;
+    std::vector<int64_t> cptr;
+    std::vector<int32_t> crow;
+    transpose(ss.in, cptr, crow);
+
+    // ---- fronts
+    std::vector<char> is_front(ss.nclu, 0);
+    for (int64_t c = 0; c < ss.nclu; ++c)
+      if (sc.level[c] == k) {
+        is_front[c] = 1;
+        FrontSym f;
+        f.cluster = (int32_t)c;
+        ss.fronts.push_back(f);
+      }
+    std::vector<int64_t> stamp(ss.nclu, -1);
+    for (size_t fi = 0; fi < ss.fronts.size(); ++fi) {
+      FrontSym& f = ss.fronts[fi];
+      const int32_t s = f.cluster;
+      for (int64_t t = cptr[s]; t < cptr[s + 1]; ++t)
+        if (crow[t] != s) f.n1.push_back(crow[t]);
+      std::sort(f.n1.begin(), f.n1.end());
+      auto scan = [&](int32_t r) {
+        for (int64_t t = ss.in.rowptr[r]; t < ss.in.rowptr[r + 1]; ++t) {
+          int32_t j = ss.in.col[t];
+          if (j == s || stamp[j] == (int64_t)fi) continue;
+          stamp[j] = (int64_t)fi;
+          if (is_proper_ancestor(sc.node[j], sc.node[s])) f.cols.push_back(j);
+        }
+      };
+      scan(s);
+      for (int32_t i : f.n1) scan(i);
+      std::sort(f.cols.begin(), f.cols.end());
+    }
+    // conflict colouring: share a row cluster and a column cluster
+    {
+      std::vector<std::vector<int32_t>> byrow(ss.nclu);
+      for (size_t fi = 0; fi < ss.fronts.size(); ++fi)
+        for (int32_t i : ss.fronts[fi].n1) byrow[i].push_back((int32_t)fi);
+      std::vector<std::vector<int32_t>> nbr(ss.fronts.size());
+      std::vector<int64_t> seen(ss.fronts.size(), -1);
+      for (size_t fi = 0; fi < ss.fronts.size(); ++fi) {
+        const FrontSym& f = ss.fronts[fi];
+        if (f.cols.empty()) continue;
+        for (int32_t i : f.n1)
+          for (int32_t g : byrow[i]) {
+            if (g == (int32_t)fi || seen[g] == (int64_t)fi) continue;
+            seen[g] = (int64_t)fi;
+            if (sorted_intersect(f.cols, ss.fronts[g].cols)) nbr[fi].push_back(g);
+          }
+      }
+      std::vector<int32_t> colour = greedy(nbr);
+      for (size_t fi = 0; fi < ss.fronts.size(); ++fi) ss.fronts[fi].colour = colour[fi];
+      order_by_colour(colour, ss.front_order, ss.front_colour_ptr);
+    }
+    // ---- pattern after the fronts
+    {
+      std::vector<Pair> post;
+      for (int64_t i = 0; i < ss.nclu; ++i) {
+        if (is_front[i]) continue;
+        for (int64_t t = ss.in.rowptr[i]; t < ss.in.rowptr[i + 1]; ++t)
+          if (!is_front[ss.in.col[t]]) post.emplace_back((int32_t)i, ss.in.col[t]);
+      }
+      for (const FrontSym& f : ss.fronts)
+        for (int32_t i : f.n1)
+          for (int32_t j : f.cols) post.emplace_back(i, j);
+      std::vector<Pair> allp = post;
+      ss.post = BlockSet::from_pairs(ss.nclu, post);
+      std::vector<Pair> inp = ss.in.pairs();
+      allp.insert(allp.end(), inp.begin(), inp.end());
+      ss.all = BlockSet::from_pairs(ss.nclu, allp);
+    }
+    for (int64_t c = 0; c < ss.nclu; ++c)
+      if (sc.level[c] < k) ss.remaining.push_back((int32_t)c);
+    // ---- interfaces
+    ss.sparsify = (k <= L - skip) && (k > 1) && !ss.remaining.empty();
+    if (ss.sparsify) {
+      std::vector<int64_t> pptr;
+      std::vector<int32_t> prow;
+      transpose(ss.post, pptr, prow);
+      std::vector<int32_t> idx(ss.nclu, -1);
+      for (size_t t = 0; t < ss.remaining.size(); ++t) idx[ss.remaining[t]] = (int32_t)t;
+      std::vector<std::vector<int32_t>> nbr(ss.remaining.size());
+      for (size_t t = 0; t < ss.remaining.size(); ++t) {
+        IfaceSym f;
+        const int32_t p = ss.remaining[t];
+        f.cluster = p;
+        for (int64_t u = pptr[p]; u < pptr[p + 1]; ++u)
+          if (prow[u] != p) f.rowN.push_back(prow[u]);
+        for (int64_t u = ss.post.rowptr[p]; u < ss.post.rowptr[p + 1]; ++u)
+          if (ss.post.col[u] != p) f.colN.push_back(ss.post.col[u]);
+        std::vector<int32_t> nb;
+        for (int32_t q : f.rowN) nb.push_back(idx[q]);
+        for (int32_t q : f.colN) nb.push_back(idx[q]);
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        SPAQR_REQUIRE(nb.empty() || nb.front() >= 0, SPAQR_EINVAL, "block to an eliminated cluster");
+        nbr[t] = nb;
+        ss.ifaces.push_back(std::move(f));
+      }
+      std::vector<int32_t> colour = greedy(nbr);
+      for (size_t t = 0; t < ss.ifaces.size(); ++t) ss.ifaces[t].colour = colour[t];
+      order_by_colour(colour, ss.iface_order, ss.iface_colour_ptr);
+    }
+    // ---- merge to stage k-1
+    if (k > 1) {
+      const std::vector<int64_t>& par = sc.parent;
+      std::vector<Pair> up;
+      up.reserve(ss.post.size());
+      for (const Pair& pr : ss.post.pairs()) {
+        SPAQR_REQUIRE(par[pr.first] >= 0 && par[pr.second] >= 0, SPAQR_EINVAL,
+                      "block of an eliminated cluster survived the stage");
+        up.emplace_back((int32_t)par[pr.first], (int32_t)par[pr.second]);
+      }
+      cur = BlockSet::from_pairs(ord.stages[k - 1].count(), up);
+    }
+  }
+
+  // ---- where each nonzero lands at stage L
+  const StageSym& sL = S->st[L];
+  S->nz_block.resize(A->nnz);
+  S->nz_r.resize(A->nnz);
+  S->nz_c.resize(A->nnz);
+  for (int64_t r = 0; r < n; ++r) {
+    int64_t pr = ord.iperm[r];
+    int32_t ci = S->cluster_of_pos_L[pr];
+    for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
+      int64_t pc = ord.iperm[A->col[t]];
+      int32_t cj = S->cluster_of_pos_L[pc];
+      S->nz_block[t] = sL.all.find(ci, cj);
+      S->nz_r[t] = (int32_t)(pr - cl.start[ci]);
+      S->nz_c[t] = (int32_t)(pc - cl.start[cj]);
+    }
+  }
+  guard.release();
+  return S;
+}
+
+}  // namespace spaqr

@@ -1,0 +1,76 @@
+// Symbolic structure of a spaQR factorization: per stage, the block pattern
+// over clusters, the fronts with their row and column sets and colours, the
+// fill, the interface colouring and the merge map.  Everything here depends
+// only on the sparsity pattern of A and the ordering, never on values.
+#pragma once
+
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+namespace spaqr {
+
+using Pair = std::pair<int32_t, int32_t>;
+
+// Row-compressed set of blocks (i, j) over the clusters of one stage.
+struct BlockSet {
+  int64_t nclu = 0;
+  std::vector<int64_t> rowptr;  // nclu + 1
+  std::vector<int32_t> col;     // sorted per row
+  int64_t size() const { return (int64_t)col.size(); }
+  // index of block (i, j), or -1
+  int64_t find(int32_t i, int32_t j) const;
+  static BlockSet from_pairs(int64_t nclu, std::vector<Pair>& pairs);  // sorts+uniques pairs
+  std::vector<Pair> pairs() const;
+};
+
+struct FrontSym {
+  int32_t cluster = 0;
+  int32_t colour = 0;
+  std::vector<int32_t> n1;    // row clusters i != s with a block (i, s), ascending
+  std::vector<int32_t> cols;  // ancestor column clusters j (excluding s), ascending
+};
+
+struct IfaceSym {
+  int32_t cluster = 0;
+  int32_t colour = 0;
+  std::vector<int32_t> rowN;  // i != p with a block (i, p), ascending
+  std::vector<int32_t> colN;  // j != p with a block (p, j), ascending
+};
+
+struct StageSym {
+  int k = 0;
+  int64_t nclu = 0;
+  BlockSet in;     // pattern at stage start
+  BlockSet post;   // after the fronts (eliminated rows/cols removed, fill added)
+  BlockSet all;    // in U post: every block that lives in the stage's pool
+  std::vector<FrontSym> fronts;        // ascending cluster
+  std::vector<int32_t> front_order;    // indices into fronts, (colour, cluster) order
+  std::vector<int32_t> front_colour_ptr;  // boundaries of colours in front_order
+  bool sparsify = false;
+  std::vector<IfaceSym> ifaces;        // remaining clusters, ascending (if sparsify)
+  std::vector<int32_t> iface_order;    // (colour, cluster) order
+  std::vector<int32_t> iface_colour_ptr;
+  std::vector<int32_t> remaining;      // clusters of level < k, ascending
+};
+
+struct Symbolic {
+  Ordering ord;                // own copy
+  int L = 0, skip = 2;
+  int64_t n = 0, nnz = 0;
+  std::vector<StageSym> st;    // index k = 1..L
+  // stage-L position of every nonzero of A (CSR order): block index in
+  // st[L].all and the row/column offset inside the block
+  std::vector<int64_t> nz_block;
+  std::vector<int32_t> nz_r, nz_c;
+  std::vector<int32_t> cluster_of_pos_L;  // stage-L cluster of each permuted index
+};
+
+Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip);
+
+}  // namespace spaqr
+
+struct spaqr_symbolic {
+  spaqr::Symbolic s;
+};

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI library (no GPU work).
+
+The library loads, exports every function include/spaqr.h declares, and its
+host logic -- grid ordering and symbolic analysis -- is bit-exact against the
+oracle's independent implementation (clusters, permutation, merge parents,
+block patterns before and after each stage's fronts, front row/column sets,
+front and interface colourings).
+"""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2010_06807_amd as P
+from paper_2010_06807_amd import _abi
+from problems import convdiff, config_problem
+from oracle.ordering import order_grid as oracle_order
+from oracle import spaqr as oracle_spaqr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "spaqr.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spaqr_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    lib = C.CDLL(_abi.LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares the same set
+    assert set(names) == set(_abi.SIGNATURES), set(names) ^ set(_abi.SIGNATURES)
+
+
+@pytest.mark.parametrize("dims,L", [((32, 32), 5), ((256, 256), 10), ((64, 64, 64), 12), ((17, 23), 5),
+                                     ((9, 7, 8), 3), ((1024, 1024), 14), ((5, 5), 1)])
+def test_ordering_bit_exact(dims, L):
+    o = P.order_grid(dims, L)
+    ob = oracle_order(dims, L)
+    assert o.levels == L and o.n == ob.N
+    assert np.array_equal(o.perm(), ob.perm)
+    for k in range(L, 0, -1):
+        for a, b in zip(o.clusters(k), ob.stage_clusters(k)):
+            assert np.array_equal(a, b)
+        if k > 1:
+            assert np.array_equal(o.merge_parents(k), ob.merge_parents(k))
+
+
+def test_default_levels():
+    assert P.order_grid((256, 256)).levels == 10
+    assert P.order_grid((32, 32)).levels == 4
+    assert P.order_grid((64, 64, 64)).levels == 12
+
+
+@pytest.mark.parametrize("dims,L,eps", [((32, 32), 5, 1e-3), ((24, 24), 5, 1e-2), ((8, 8, 8), 4, 1e-2),
+                                        ((16, 16, 16), 6, 1e-2), ((64, 64), 7, 1e-2), ((20, 13), 4, 1e-2)])
+def test_symbolic_bit_exact(dims, L, eps):
+    A = convdiff(dims, (10.0, -4.0, 7.0)[:len(dims)])
+    o = P.order_grid(dims, L)
+    sym = P.analyze(A, o)
+    F = oracle_spaqr.factor(A, oracle_order(dims, L), eps)
+    for k in range(L, 0, -1):
+        rec = F.stages[k]
+        assert sym.pattern(k) == [tuple(x) for x in rec["pattern_in"]]
+        assert sym.pattern(k, post=True) == [tuple(x) for x in rec["pattern_post"]]
+        want = {s: (list(a), list(b), c) for s, (a, b, c) in rec["fronts"].items()}
+        assert sym.fronts(k) == want
+        assert sym.iface_colours(k) == (rec["iface_colour"] if rec["sparsified"] else {})
+
+
+def test_invalid_inputs_rejected():
+    with pytest.raises(P.SpaqrError) as e:
+        P.order_grid((8, 8), 6)
+    assert e.value.status == _abi.EINVAL
+    with pytest.raises(P.SpaqrError):
+        P.order_grid((0, 8), 2)
+    A = convdiff((8, 8), (1.0, 1.0))
+    o = P.order_grid((8, 8), 3)
+    B = A.copy()
+    B.indices = B.indices.copy()
+    B.indices[3], B.indices[4] = B.indices[4], B.indices[3]   # unsorted columns
+    with pytest.raises(P.SpaqrError):
+        P.analyze(B, o)
+    o2 = P.order_grid((8, 9), 3)
+    with pytest.raises(P.SpaqrError):
+        P.analyze(A, o2)            # size mismatch
+    lib = _abi.load()
+    assert lib.spaqr_status_string(-3).decode().startswith("exactly singular")
