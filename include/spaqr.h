@@ -138,6 +138,25 @@ spaqr_status spaqr_factor_symbolic(const spaqr_csr* A, const spaqr_symbolic* sym
                                    const spaqr_opts* opts, void* hip_stream,
                                    spaqr_handle** out);
 
+/* Device-resident copies of a CSR matrix (HIP device pointers), laid out
+ * exactly like the host spaqr_csr passed beside them. */
+typedef struct {
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} spaqr_csr_dev;
+
+/* Factorization whose matrix values are already resident on the device.
+ * A_pattern supplies n, nnz, rowptr and col on the host (its val may be NULL);
+ * A_dev holds the same CSR in device memory; sym is an analysis of that
+ * pattern.  The values never cross PCIe: the column scaling and the scatter
+ * into the stage blocks run on the device, and the CSR is copied device to
+ * device for the SpMV (A_dev may be freed after the call).
+ * Errors: as spaqr_factor; EINVAL also for a numerically zero column. */
+spaqr_status spaqr_factor_device(const spaqr_csr* A_pattern, const spaqr_csr_dev* A_dev,
+                                 const spaqr_symbolic* sym, const spaqr_opts* opts,
+                                 void* hip_stream, spaqr_handle** out);
+
 /* x = M^{-1} b = D_c P^T W^{-1} Q^T P b for nrhs columns (Section 2.8).
  * b and x: n x nrhs column-major with leading dimension ld; device pointers
  * if on_device != 0, else host pointers.  b and x may alias.  Runs on the
@@ -186,6 +205,17 @@ spaqr_status spaqr_stats(const spaqr_handle* h, spaqr_stats_t* out);
  * spaqr_symbolic_stage_info. */
 spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf,
                                int64_t cap, int64_t* len);
+
+/* Per-kernel timing (HIP events recorded on the launching stream around every
+ * launch) and the algorithmic flops/bytes of those launches.  enable(1, only)
+ * clears the table and starts recording every kernel (only == NULL) or just
+ * the kernel named `only`; enable(0, NULL) stops.  Kernel names:
+ * "front_qr", "scale_qr", "scale_blocks", "sparsify", "copy",
+ * "apply_front_fwd", "apply_front_bwd", "apply_iface_fwd", "apply_iface_bwd".
+ * Unknown names report zero launches. */
+spaqr_status spaqr_profile_enable(int on, const char* only);
+spaqr_status spaqr_profile_query(const char* kernel, int64_t* launches, double* total_ms,
+                                 double* flops, double* bytes);
 
 /* Releases all host and device memory of the handle.  NULL is a no-op. */
 void spaqr_free(spaqr_handle* h);

@@ -18,8 +18,8 @@ import numpy as np
 from . import _abi
 from ._abi import CSR, Opts, SolveInfo, SpaqrError, check
 
-__all__ = ["order_grid", "analyze", "factor", "GridOrdering", "Symbolic", "Factorization",
-           "Server", "SpaqrError", "load_library"]
+__all__ = ["order_grid", "analyze", "factor", "factor_device", "DeviceCSR", "GridOrdering", "Symbolic",
+           "Factorization", "Server", "SpaqrError", "load_library", "profile_enable", "profile_query"]
 
 
 def load_library():
@@ -170,13 +170,18 @@ class Factorization:
     """A spaQR factorization resident on the GPU (spaqr_factor)."""
 
     def __init__(self, A, ordering=None, symbolic=None, eps=1e-2, skip=2, precision=32, restart=100,
-                 maxit=1000, stream=None):
+                 maxit=1000, stream=None, device_csr=None):
         lib = _abi.load()
         csr, keep = _csr_struct(A)
         o = make_opts(eps, skip, precision, restart, maxit)
         h = C.c_void_p()
         sp = _stream_ptr(stream)
-        if symbolic is not None:
+        if device_csr is not None:
+            if symbolic is None:
+                raise ValueError("the device path needs a symbolic analysis")
+            dev = _abi.CSRDev(device_csr.rowptr.data_ptr(), device_csr.col.data_ptr(), device_csr.val.data_ptr())
+            st = lib.spaqr_factor_device(C.byref(csr), C.byref(dev), symbolic.handle, C.byref(o), sp, C.byref(h))
+        elif symbolic is not None:
             st = lib.spaqr_factor_symbolic(C.byref(csr), symbolic.handle, C.byref(o), sp, C.byref(h))
         else:
             st = lib.spaqr_factor(C.byref(csr), ordering.handle, C.byref(o), sp, C.byref(h))
@@ -196,8 +201,8 @@ class Factorization:
     # vectors: numpy (host) or torch CUDA tensors (device), shape (n,) or (n, nrhs)
     @staticmethod
     def _layout(b, n):
-        if b.ndim == 1:
-            return 1, n
+        if b.ndim == 1 or b.shape[1] == 1:
+            return 1, n     # the stride of a single column is irrelevant
         if hasattr(b, "stride"):           # torch
             if b.stride(0) != 1:
                 raise ValueError("device arrays must be column-major (stride(0) == 1)")
@@ -264,6 +269,36 @@ class Factorization:
 
 def factor(A, ordering, eps=1e-2, **kw):
     return Factorization(A, ordering=ordering, eps=eps, **kw)
+
+
+class DeviceCSR:
+    """Device copies (torch CUDA tensors) of a CSR matrix's three arrays."""
+
+    def __init__(self, A, device="cuda:0"):
+        import torch
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(A.indptr, dtype=np.int64)).to(device)
+        self.col = torch.from_numpy(np.ascontiguousarray(A.indices, dtype=np.int32)).to(device)
+        self.val = torch.from_numpy(np.ascontiguousarray(A.data, dtype=np.float64)).to(device)
+
+
+def factor_device(A, symbolic, dcsr, eps=1e-2, **kw):
+    """Factorize with A's values taken from device memory (dcsr: DeviceCSR);
+    A (host) supplies only the pattern the symbolic analysis was made from."""
+    return Factorization(A, symbolic=symbolic, eps=eps, device_csr=dcsr, **kw)
+
+
+def profile_enable(on=True, only=None):
+    """Record per-launch HIP-event timings of every kernel, or only of `only`."""
+    check(_abi.load().spaqr_profile_enable(1 if on else 0, only.encode() if only else None),
+          "spaqr_profile_enable")
+
+
+def profile_query(kernel):
+    n = C.c_int64()
+    ms, fl, by = C.c_double(), C.c_double(), C.c_double()
+    check(_abi.load().spaqr_profile_query(kernel.encode(), C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)),
+          "spaqr_profile_query")
+    return dict(launches=n.value, total_ms=ms.value, flops=fl.value, bytes=by.value)
 
 
 from .server import Server  # noqa: E402,F401

@@ -17,6 +17,10 @@ class CSR(C.Structure):
                 ("col", C.POINTER(C.c_int32)), ("val", C.POINTER(C.c_double))]
 
 
+class CSRDev(C.Structure):
+    _fields_ = [("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("skip", C.c_int), ("scale", C.c_int), ("precision", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int)]
@@ -58,12 +62,16 @@ SIGNATURES = {
     "spaqr_symbolic_stage_info": (C.c_int, [_P, C.c_int, C.c_int, _I32P, C.c_int64, _I64P]),
     "spaqr_factor": (C.c_int, [C.POINTER(CSR), _P, C.POINTER(Opts), _P, C.POINTER(_P)]),
     "spaqr_factor_symbolic": (C.c_int, [C.POINTER(CSR), _P, C.POINTER(Opts), _P, C.POINTER(_P)]),
+    "spaqr_factor_device": (C.c_int, [C.POINTER(CSR), C.POINTER(CSRDev), _P, C.POINTER(Opts), _P,
+                                      C.POINTER(_P)]),
     "spaqr_apply": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_int]),
     "spaqr_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_int, C.c_double,
                               C.POINTER(SolveInfo)]),
     "spaqr_stats": (C.c_int, [_P, C.POINTER(Stats)]),
     "spaqr_stage_sizes": (C.c_int, [_P, C.c_int, _I32P, C.c_int64, _I64P]),
     "spaqr_free": (None, [_P]),
+    "spaqr_profile_enable": (C.c_int, [C.c_int, C.c_char_p]),
+    "spaqr_profile_query": (C.c_int, [C.c_char_p, _I64P, _DP, _DP, _DP]),
     "spaqr_server_create": (C.c_int, [C.c_size_t, _P, C.POINTER(_P)]),
     "spaqr_submit": (C.c_int, [_P, C.POINTER(CSR), _P, C.POINTER(Opts), _P, C.c_int64, C.c_double,
                                C.POINTER(C.c_uint64)]),

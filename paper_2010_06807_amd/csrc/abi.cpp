@@ -170,8 +170,9 @@ spaqr_status spaqr_symbolic_stage_info(const spaqr_symbolic* sym, int stage, int
   });
 }
 
-static spaqr_status factor_impl(const spaqr_csr* A, const Symbolic& S, const spaqr_opts* opts, void* stream,
-                                spaqr_handle** out, std::unique_ptr<Symbolic> owned) {
+static spaqr_status factor_impl(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                const spaqr_opts* opts, void* stream, spaqr_handle** out,
+                                std::unique_ptr<Symbolic> owned) {
   SPAQR_REQUIRE(out, SPAQR_EINVAL, "NULL output");
   require_device();
   spaqr_opts o = opts ? *opts : spaqr_opts_default();
@@ -180,7 +181,7 @@ static spaqr_status factor_impl(const spaqr_csr* A, const Symbolic& S, const spa
   auto h = std::unique_ptr<spaqr_handle>(new spaqr_handle());
   h->owned_sym = std::move(owned);
   const Symbolic& Sref = h->owned_sym ? *h->owned_sym : S;
-  h->e = make_engine(A, Sref, o, reinterpret_cast<hipStream_t>(stream));
+  h->e = make_engine(A, Ad, Sref, o, reinterpret_cast<hipStream_t>(stream));
   *out = h.release();
   return SPAQR_OK;
 }
@@ -193,7 +194,8 @@ spaqr_status spaqr_factor(const spaqr_csr* A, const spaqr_ordering* ord, const s
     std::unique_ptr<Symbolic> s(analyze(A, ord->o, opts ? opts->skip : 2));
     const double ts = now_ms() - t0;
     const Symbolic& ref = *s;
-    spaqr_status st = factor_impl(A, ref, opts, hip_stream, out, std::move(s));
+    SPAQR_REQUIRE(A->val, SPAQR_EINVAL, "NULL values");
+    spaqr_status st = factor_impl(A, nullptr, ref, opts, hip_stream, out, std::move(s));
     if (st == SPAQR_OK) const_cast<Stats&>((*out)->e->stats()).s.ms_symbolic = ts;
     return st;
   });
@@ -204,7 +206,18 @@ spaqr_status spaqr_factor_symbolic(const spaqr_csr* A, const spaqr_symbolic* sym
   return guarded([&]() -> spaqr_status {
     SPAQR_REQUIRE(A && sym && out, SPAQR_EINVAL, "NULL argument");
     SPAQR_REQUIRE(A->n == sym->s.n && A->nnz == sym->s.nnz, SPAQR_EINVAL, "matrix does not match the analysis");
-    return factor_impl(A, sym->s, opts, hip_stream, out, nullptr);
+    SPAQR_REQUIRE(A->val, SPAQR_EINVAL, "NULL values");
+    return factor_impl(A, nullptr, sym->s, opts, hip_stream, out, nullptr);
+  });
+}
+
+spaqr_status spaqr_factor_device(const spaqr_csr* A, const spaqr_csr_dev* Ad, const spaqr_symbolic* sym,
+                                 const spaqr_opts* opts, void* hip_stream, spaqr_handle** out) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(A && Ad && sym && out && A->rowptr && A->col, SPAQR_EINVAL, "NULL argument");
+    SPAQR_REQUIRE(Ad->rowptr && Ad->col && Ad->val, SPAQR_EINVAL, "NULL device array");
+    SPAQR_REQUIRE(A->n == sym->s.n && A->nnz == sym->s.nnz, SPAQR_EINVAL, "matrix does not match the analysis");
+    return factor_impl(A, Ad, sym->s, opts, hip_stream, out, nullptr);
   });
 }
 

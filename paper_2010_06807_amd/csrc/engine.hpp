@@ -67,6 +67,11 @@ struct StageApply {
   ApIface<T>* ifaces = nullptr;
   int64_t nifaces = 0;
   int max_p = 0;
+  // algorithmic work of each apply launch: factor + index bytes (read once per
+  // launch) and per-right-hand-side vector bytes and flops
+  std::vector<double> fwd_fac_bytes, fwd_vec_bytes, fwd_flops;  // per colour
+  double bwd_fac_bytes = 0, bwd_vec_bytes = 0, bwd_flops = 0;
+  double if_fwd_fac_bytes = 0, if_bwd_fac_bytes = 0, if_vec_bytes = 0, if_fwd_flops = 0, if_bwd_flops = 0;
 };
 
 struct Stats {
@@ -87,8 +92,10 @@ class EngineBase {
   virtual int opt_maxit() const = 0;
 };
 
-std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o,
-                                        hipStream_t stream);
+// A: host CSR (the pattern is always read; values only when Ad is null).
+// Ad: optional device copies of the same CSR, used instead of uploading.
+std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                        const spaqr_opts& o, hipStream_t stream);
 
 // FGMRES on the device (gmres.hip).
 int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,

@@ -20,6 +20,7 @@
 #include <cstring>
 
 #include "engine.hpp"
+#include "profile.hpp"
 
 namespace spaqr {
 
@@ -108,7 +109,7 @@ struct Job {
 template <typename T>
 class Engine final : public EngineBase {
  public:
-  Engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o, hipStream_t s)
+  Engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S, const spaqr_opts& o, hipStream_t s)
       : S_(S), o_(o), s_(s) {
     st_.s.n = S.n;
     st_.s.levels = S.L;
@@ -116,7 +117,7 @@ class Engine final : public EngineBase {
     st_.stage_sizes.assign(S.L + 1, {});
     const double t0 = now_ms();
     try {
-      factor(A);
+      factor(A, Ad);
     } catch (...) {
       (void)hipStreamSynchronize(s_);
       throw;
@@ -139,7 +140,7 @@ class Engine final : public EngineBase {
   int opt_maxit() const override { return o_.maxit; }
 
  private:
-  void factor(const spaqr_csr* A);
+  void factor(const spaqr_csr* A, const spaqr_csr_dev* Ad);
   void stage(int k);
   void merge(int k);
   void begin_stage();
@@ -155,6 +156,7 @@ class Engine final : public EngineBase {
   int stager_cur_ = 0;
   int* pinned_ints_ = nullptr;
   size_t pinned_cap_ = 0;
+  int* d_zcol_ = nullptr;  // set by the device column-norm kernel for a zero column
 
   // current stage state
   T* pool_ = nullptr;
@@ -182,24 +184,47 @@ void Engine<T>::begin_stage() {
 }
 
 template <typename T>
-void Engine<T>::factor(const spaqr_csr* A) {
+void Engine<T>::factor(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   const int L = S_.L;
   const int64_t n = S_.n, nnz = S_.nnz;
   const Ordering& ord = S_.ord;
   ap_.assign(L + 1, StageApply<T>());
-  // Section 2.8: pre-scale columns to unit 2-norm.
-  std::vector<double> cn(n, 0.0);
-  for (int64_t t = 0; t < nnz; ++t) cn[A->col[t]] += A->val[t] * A->val[t];
-  std::vector<double> dc(n);
-  for (int64_t j = 0; j < n; ++j) {
-    SPAQR_REQUIRE(cn[j] > 0.0, SPAQR_EINVAL, "A has a zero column");
-    dc[j] = 1.0 / std::sqrt(cn[j]);
-  }
   begin_stage();
   Stager& up = stager_[stager_cur_];
   d_perm_ = up.upload(persist_, ord.perm, s_);
-  d_dc_ = up.upload(persist_, dc, s_);
-  {
+  d_zcol_ = persist_.alloc_n<int>(1, s_);
+  launch_fill<int>(d_zcol_, 1, 0, s_);
+  std::vector<double> dc;
+  if (Ad) {
+    // values already on the device: copy the CSR (device to device) for the
+    // SpMV and compute the column scaling there, in a fixed summation order
+    d_rowptr_ = persist_.alloc_n<int64_t>(n + 1, s_);
+    d_col_ = persist_.alloc_n<int32_t>(std::max<int64_t>(1, nnz), s_);
+    d_val_ = persist_.alloc_n<double>(std::max<int64_t>(1, nnz), s_);
+    SPAQR_HIP(hipMemcpyAsync(d_rowptr_, Ad->rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s_));
+    SPAQR_HIP(hipMemcpyAsync(d_col_, Ad->col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s_));
+    SPAQR_HIP(hipMemcpyAsync(d_val_, Ad->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s_));
+    std::vector<int64_t> cptr(n + 1, 0), cidx(nnz);
+    for (int64_t t = 0; t < nnz; ++t) cptr[A->col[t] + 1]++;
+    for (int64_t j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
+    {
+      std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
+      for (int64_t t = 0; t < nnz; ++t) cidx[pos[A->col[t]]++] = t;
+    }
+    int64_t* d_cptr = up.upload(work_, cptr, s_);
+    int64_t* d_cidx = up.upload(work_, cidx, s_);
+    d_dc_ = persist_.alloc_n<double>(n, s_);
+    launch_colnorm(d_cptr, d_cidx, d_val_, n, d_dc_, d_zcol_, s_);
+  } else {
+    // Section 2.8: pre-scale columns to unit 2-norm.
+    std::vector<double> cn(n, 0.0);
+    for (int64_t t = 0; t < nnz; ++t) cn[A->col[t]] += A->val[t] * A->val[t];
+    dc.resize(n);
+    for (int64_t j = 0; j < n; ++j) {
+      SPAQR_REQUIRE(cn[j] > 0.0, SPAQR_EINVAL, "A has a zero column");
+      dc[j] = 1.0 / std::sqrt(cn[j]);
+    }
+    d_dc_ = up.upload(persist_, dc, s_);
     std::vector<int64_t> rp(A->rowptr, A->rowptr + n + 1);
     std::vector<int32_t> ci(A->col, A->col + nnz);
     std::vector<double> va(A->val, A->val + nnz);
@@ -227,17 +252,14 @@ void Engine<T>::factor(const spaqr_csr* A) {
   launch_fill<T>(pool_, boff_.back(), T(0), s_);
   {
     std::vector<int64_t> dst(nnz);
-    std::vector<double> val(nnz);
     for (int64_t r = 0; r < n; ++r)
       for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
         const int64_t b = S_.nz_block[t];
         const int32_t cj = S_.cluster_of_pos_L[ord.iperm[A->col[t]]];
         dst[t] = boff_[b] + (int64_t)S_.nz_r[t] * size_[cj] + S_.nz_c[t];
-        val[t] = A->val[t] * dc[A->col[t]];
       }
     int64_t* d_dst = up.upload(work_, dst, s_);
-    double* d_v = up.upload(work_, val, s_);
-    launch_scatter_nz<T>(pool_, d_dst, d_v, nnz, s_);
+    launch_scatter_scaled<T>(pool_, d_dst, d_val_, d_col_, d_dc_, nnz, s_);
   }
   for (int k = L; k >= 1; --k) stage(k);
   SPAQR_HIP(hipStreamSynchronize(s_));
@@ -298,6 +320,7 @@ void Engine<T>::stage(int k) {
     std::vector<CopyTile<T>> g, sc;
     Job gj, sj;
     std::vector<QRDesc<T>> qd;
+    double qr_flops = 0.0, qr_bytes = 0.0;
     for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
       const int32_t f = ss.front_order[oi];
       const FrontSym& F = ss.fronts[f];
@@ -326,14 +349,22 @@ void Engine<T>::stage(int k) {
       }
       gj.close(g);
       sj.close(sc);
-      if (n > 0) qd.push_back({Wf, TAU + tau_off[f], nullptr, d_flag, fm[f], n, nc, 0});
+      if (n > 0) {
+        qd.push_back({Wf, TAU + tau_off[f], nullptr, d_flag, fm[f], n, nc, 0});
+        const double mm = fm[f], nn = n, kk = nc - n;
+        qr_flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
+        qr_bytes += 2.0 * mm * nc * sizeof(T);
+      }
     }
     const int64_t njobs = (int64_t)gj.ptr.size() - 1;
     CopyTile<T>* dg = up.upload(work_, g, s_);
     int64_t* dgj = up.upload(work_, gj.ptr, s_);
     launch_copy<T>(dg, dgj, dg ? njobs : 0, s_);
     QRDesc<T>* dq = up.upload(work_, qd, s_);
-    launch_qr<T>(dq, (int64_t)qd.size(), jbf, max_m, s_);
+    {
+      ProfScope ps("front_qr", s_, qr_flops, qr_bytes);
+      launch_qr<T>(dq, (int64_t)qd.size(), jbf, max_m, s_);
+    }
     CopyTile<T>* ds = up.upload(work_, sc, s_);
     int64_t* dsj = up.upload(work_, sj.ptr, s_);
     launch_copy<T>(ds, dsj, ds ? njobs : 0, s_);
@@ -348,6 +379,7 @@ void Engine<T>::stage(int k) {
     ap.colour_ptr.assign(1, 0);
     for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
       int cmax = 0;
+      double ffb = 0, fvb = 0, ffl = 0;
       for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
         const int32_t f = ss.front_order[oi];
         const FrontSym& F = ss.fronts[f];
@@ -366,9 +398,21 @@ void Engine<T>::stage(int k) {
         af.push_back({VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], nullptr, nullptr, m, n, nc - n, 0});
         cmax = std::max(cmax, m);
         ap.max_bwd_rows = std::max(ap.max_bwd_rows, nc);
+        const double mm = m, nn = n, kk = nc - n, eb = sizeof(T);
+        // forward: V below the diagonal + tau + row slots; x rows in and out
+        ffb += (mm * nn - nn * (nn + 1) / 2 + nn) * eb + 4 * mm;
+        fvb += 16 * mm;
+        ffl += 4 * (mm * nn - nn * (nn - 1) / 2);
+        // backward: R_ss upper triangle + R_sj + slots; x_s in/out, x_j in
+        ap.bwd_fac_bytes += (nn * (nn + 1) / 2 + nn * kk) * eb + 4 * (nn + kk);
+        ap.bwd_vec_bytes += 16 * nn + 8 * kk;
+        ap.bwd_flops += nn * nn + 2 * nn * kk;
       }
       ap.colour_ptr.push_back((int64_t)af.size());
       ap.colour_max_m.push_back(cmax);
+      ap.fwd_fac_bytes.push_back(ffb);
+      ap.fwd_vec_bytes.push_back(fvb);
+      ap.fwd_flops.push_back(ffl);
     }
     CopyTile<T>* dp = up.upload(work_, pk, s_);
     int64_t* dpj = up.upload(work_, pj.ptr, s_);
@@ -440,7 +484,15 @@ void Engine<T>::stage(int k) {
       int64_t* dgj = up.upload(work_, gj.ptr, s_);
       launch_copy<T>(dg, dgj, dg ? (int64_t)gj.ptr.size() - 1 : 0, s_);
       QRDesc<T>* dq = up.upload(work_, qd, s_);
-      launch_qr<T>(dq, (int64_t)qd.size(), jbs, max_p, s_);
+      {
+        double fl = 0.0, by = 0.0;
+        for (const QRDesc<T>& q : qd) {
+          fl += 4.0 / 3.0 * (double)q.n * q.n * q.n;
+          by += 2.0 * (double)q.n * q.n * sizeof(T);
+        }
+        ProfScope ps("scale_qr", s_, fl, by);
+        launch_qr<T>(dq, (int64_t)qd.size(), jbs, max_p, s_);
+      }
       CopyTile<T>* dp = up.upload(work_, pk, s_);
       int64_t* dpj = up.upload(work_, pj.ptr, s_);
       launch_copy<T>(dp, dpj, dp ? (int64_t)pj.ptr.size() - 1 : 0, s_);
@@ -455,7 +507,15 @@ void Engine<T>::stage(int k) {
           st_.s.flops_scale += 4.0 * size_[i] * size_[i] * size_[j] + (double)size_[i] * size_[j] * size_[j];
         }
       ScaleBlk* dsb = up.upload(work_, sb, s_);
-      launch_scale<T>(dsb, (int64_t)sb.size(), dfac, pool_, jbs, max_p, s_);
+      {
+        double fl = 0.0, by = 0.0;
+        for (const ScaleBlk& q : sb) {
+          fl += 4.0 * q.rows * q.rows * (double)q.cols + (double)q.rows * q.cols * q.cols;
+          by += 2.0 * q.rows * (double)q.cols * sizeof(T);
+        }
+        ProfScope ps("scale_blocks", s_, fl, by);
+        launch_scale<T>(dsb, (int64_t)sb.size(), dfac, pool_, jbs, max_p, s_);
+      }
     }
     // sparsification, colour by colour
     for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
@@ -511,7 +571,12 @@ void Engine<T>::stage(int k) {
       }
       SpDesc<T>* dsd = up.upload(work_, sd, s_);
       SpNbr* dnb = up.upload(work_, nb, s_);
-      launch_sparsify<T>(dsd, (int64_t)sd.size(), dnb, pool_, d_rank, o_.eps, max_pc, max_nb, s_);
+      {
+        double by = 0.0;
+        for (const SpDesc<T>& q : sd) by += 2.0 * q.P * (double)q.mmax * sizeof(T);
+        ProfScope ps("sparsify", s_, 0.0, by);
+        launch_sparsify<T>(dsd, (int64_t)sd.size(), dnb, pool_, d_rank, o_.eps, max_pc, max_nb, s_);
+      }
     }
     // apply descriptors of the interfaces
     std::vector<ApIface<T>> ai;
@@ -534,7 +599,7 @@ void Engine<T>::stage(int k) {
   }
 
   // ------------------------------------------------ rank readback
-  const size_t need = (size_t)nclu + 1;
+  const size_t need = (size_t)nclu + 2;
   if (pinned_cap_ < need) {
     if (pinned_ints_) (void)hipHostFree(pinned_ints_);
     SPAQR_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned_ints_), need * sizeof(int), hipHostMallocDefault));
@@ -542,9 +607,25 @@ void Engine<T>::stage(int k) {
   }
   if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
   SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag, sizeof(int), hipMemcpyDeviceToHost, s_));
+  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu + 1, d_zcol_, sizeof(int), hipMemcpyDeviceToHost, s_));
   SPAQR_HIP(hipStreamSynchronize(s_));
+  SPAQR_REQUIRE(pinned_ints_[nclu + 1] == 0, SPAQR_EINVAL, "A has a zero column");
   SPAQR_REQUIRE(pinned_ints_[nclu] == 0, SPAQR_ESINGULAR, "a front produced an exactly zero R_ss diagonal");
   st_.stage_sizes[k].assign(pinned_ints_, pinned_ints_ + nclu);
+  if (ss.sparsify) {
+    const double eb = sizeof(T);
+    for (int32_t p : ss.remaining) {
+      const double P = size_[p], r = pinned_ints_[p];
+      if (P == 0) continue;
+      // U below the diagonal + tau, then the kept reflectors of Q
+      const double qel = r < P ? (P * r - r * (r - 1) / 2) : 0.0;
+      ap.if_fwd_fac_bytes += (P * (P - 1) / 2 + P + qel + (r < P ? r : 0)) * eb + 4 * P;
+      ap.if_bwd_fac_bytes += (P * (P + 1) / 2 + qel + (r < P ? r : 0)) * eb + 4 * P;
+      ap.if_vec_bytes += 16 * P;
+      ap.if_fwd_flops += 4 * (P * (P + 1) / 2 + qel);
+      ap.if_bwd_flops += P * P + 4 * qel;
+    }
+  }
   if (k > 1) merge(k);
 }
 
@@ -642,14 +723,25 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
     const StageApply<T>& a = ap_[k];
     for (size_t c = 0; c + 1 < a.colour_ptr.size(); ++c) {
       const int64_t cnt = a.colour_ptr[c + 1] - a.colour_ptr[c];
+      if (cnt == 0) continue;
+      ProfScope ps("apply_front_fwd", s_, a.fwd_flops[c] * nrhs, a.fwd_fac_bytes[c] + a.fwd_vec_bytes[c] * nrhs);
       launch_front_fwd<T>(a.fronts + a.colour_ptr[c], cnt, a.colour_max_m[c], xh, N, nrhs, s_);
     }
-    launch_iface_fwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+    if (a.nifaces) {
+      ProfScope ps("apply_iface_fwd", s_, a.if_fwd_flops * nrhs, a.if_fwd_fac_bytes + a.if_vec_bytes * nrhs);
+      launch_iface_fwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+    }
   }
   for (int k = 1; k <= L; ++k) {
     const StageApply<T>& a = ap_[k];
-    launch_iface_bwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
-    launch_front_bwd<T>(a.fronts, a.nfronts, a.max_bwd_rows, xh, N, nrhs, s_);
+    if (a.nifaces) {
+      ProfScope ps("apply_iface_bwd", s_, a.if_bwd_flops * nrhs, a.if_bwd_fac_bytes + a.if_vec_bytes * nrhs);
+      launch_iface_bwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+    }
+    if (a.nfronts) {
+      ProfScope ps("apply_front_bwd", s_, a.bwd_flops * nrhs, a.bwd_fac_bytes + a.bwd_vec_bytes * nrhs);
+      launch_front_bwd<T>(a.fronts, a.nfronts, a.max_bwd_rows, xh, N, nrhs, s_);
+    }
   }
   launch_scatter_perm(x, ldx, xh, d_perm_, d_dc_, N, nrhs, s_);
   SPAQR_HIP(hipGetLastError());
@@ -657,13 +749,13 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
 
 }  // namespace
 
-std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const Symbolic& S, const spaqr_opts& o,
-                                        hipStream_t stream) {
+std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                        const spaqr_opts& o, hipStream_t stream) {
   SPAQR_REQUIRE(o.eps >= 0.0 && std::isfinite(o.eps), SPAQR_EINVAL, "eps must be finite and >= 0");
   SPAQR_REQUIRE(o.scale == 1, SPAQR_EINVAL, "only the scaled variant is implemented");
   SPAQR_REQUIRE(o.precision == 32 || o.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
-  if (o.precision == 32) return std::unique_ptr<EngineBase>(new Engine<float>(A, S, o, stream));
-  return std::unique_ptr<EngineBase>(new Engine<double>(A, S, o, stream));
+  if (o.precision == 32) return std::unique_ptr<EngineBase>(new Engine<float>(A, Ad, S, o, stream));
+  return std::unique_ptr<EngineBase>(new Engine<double>(A, Ad, S, o, stream));
 }
 
 }  // namespace spaqr

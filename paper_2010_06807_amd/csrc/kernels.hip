@@ -638,6 +638,35 @@ __global__ void k_scatter_perm(double* x, int64_t ldx, const double* __restrict_
   }
 }
 
+// dc[j] = 1 / ||A[:, j]||_2 from the CSR values visited in column order
+// (csc_idx lists, column by column, the CSR positions of each column's
+// entries, so the sum order is fixed).  *zero_col = 1 if a column is zero.
+__global__ void k_colnorm(const int64_t* __restrict__ cptr, const int64_t* __restrict__ cidx,
+                          const double* __restrict__ val, int64_t n, double* __restrict__ dc, int* zero_col) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t t = cptr[j]; t < cptr[j + 1]; ++t) {
+      const double v = val[cidx[t]];
+      s += v * v;
+    }
+    if (s == 0.0) {
+      *zero_col = 1;
+      dc[j] = 0.0;
+    } else {
+      dc[j] = 1.0 / sqrt(s);
+    }
+  }
+}
+
+// pool[dst[t]] = val[t] * dc[col[t]]: the pre-scaled matrix scattered into
+// the stage-L blocks.
+template <typename T>
+__global__ void k_scatter_scaled(T* pool, const int64_t* __restrict__ dst, const double* __restrict__ val,
+                                 const int32_t* __restrict__ col, const double* __restrict__ dc, int64_t nnz) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x)
+    pool[dst[i]] = (T)(val[i] * dc[col[i]]);
+}
+
 int grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   if (g > 65536) g = 65536;
@@ -664,6 +693,18 @@ template <typename T>
 void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
   hipLaunchKernelGGL(k_scatter_nz<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, nnz);
+}
+
+void launch_colnorm(const int64_t* cptr, const int64_t* cidx, const double* val, int64_t n, double* dc,
+                    int* zero_col, hipStream_t s) {
+  hipLaunchKernelGGL(k_colnorm, dim3(grid_for(n, 256)), dim3(256), 0, s, cptr, cidx, val, n, dc, zero_col);
+}
+
+template <typename T>
+void launch_scatter_scaled(T* pool, const int64_t* dst, const double* val, const int32_t* col, const double* dc,
+                           int64_t nnz, hipStream_t s) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(k_scatter_scaled<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, col, dc, nnz);
 }
 
 static size_t qr_bytes_jb(int max_m, int jb, int eb) {
@@ -771,6 +812,8 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_copy<T>(const CopyTile<T>*, const int64_t*, int64_t, hipStream_t);            \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void launch_scatter_nz<T>(T*, const int64_t*, const double*, int64_t, hipStream_t);       \
+  template void launch_scatter_scaled<T>(T*, const int64_t*, const double*, const int32_t*, const double*, \
+                                         int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
   template void launch_scale<T>(const ScaleBlk*, int64_t, const ScaleFac<T>*, T*, int, int, hipStream_t); \
   template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \

@@ -108,6 +108,11 @@ template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T>
 void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s);
+void launch_colnorm(const int64_t* cptr, const int64_t* cidx, const double* val, int64_t n, double* dc,
+                    int* zero_col, hipStream_t s);
+template <typename T>
+void launch_scatter_scaled(T* pool, const int64_t* dst, const double* val, const int32_t* col, const double* dc,
+                           int64_t nnz, hipStream_t s);
 // jb: panel width (power of two <= 32); lds_bytes: dynamic LDS per workgroup
 template <typename T>
 void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s);

@@ -1,0 +1,41 @@
+// Optional per-kernel timing with HIP events on the launching stream, plus the
+// algorithmic work each launch performs (flops and bytes the method itself
+// must move).  Off by default; spaqr_profile_enable() switches it on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace spaqr {
+
+bool prof_on();
+bool prof_wants(const char* name);
+void prof_record(const char* name, hipStream_t s, hipEvent_t a, hipEvent_t b, double flops, double bytes);
+
+struct ProfScope {
+  ProfScope(const char* name, hipStream_t s, double flops, double bytes)
+      : name_(name), s_(s), flops_(flops), bytes_(bytes) {
+    if (prof_wants(name)) {
+      (void)hipEventCreate(&a_);
+      (void)hipEventCreate(&b_);
+      (void)hipEventRecord(a_, s_);
+      live_ = true;
+    }
+  }
+  ~ProfScope() {
+    if (live_) {
+      (void)hipEventRecord(b_, s_);
+      prof_record(name_, s_, a_, b_, flops_, bytes_);
+    }
+  }
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  double flops_, bytes_;
+  hipEvent_t a_{}, b_{};
+  bool live_ = false;
+};
+
+}  // namespace spaqr

@@ -114,7 +114,7 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
     for (auto& r : srv->active) {
       if (!r->eng) {
         r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
-        r->eng = make_engine(&r->A, *r->sym, r->opts, srv->stream);
+        r->eng = make_engine(&r->A, nullptr, *r->sym, r->opts, srv->stream);
         keep.push_back(std::move(r));
         continue;
       }

@@ -170,3 +170,42 @@ def test_c2_fp32_against_oracle():
         res = np.linalg.norm(A @ x.cpu().numpy() - b) / np.linalg.norm(b)
         assert res <= 1e-10
         assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o)), (prec, info, it_o)
+
+
+def test_device_resident_input_matches_host_input():
+    """spaqr_factor_device (values read from HBM, column scaling on the GPU)
+    against spaqr_factor (host values): same ranks, same M^{-1} b."""
+    dims, L = (48, 48), 6
+    A = convdiff(dims, (35.0, -12.0))
+    N = A.shape[0]
+    o = P.order_grid(dims, L)
+    sym = P.analyze(A, o)
+    dA = P.DeviceCSR(A, DEV)
+    for prec in (64, 32):
+        f_host = P.factor(A, o, eps=1e-2, precision=prec)
+        f_dev = P.factor_device(A, sym, dA, eps=1e-2, precision=prec)
+        for k in range(L, 0, -1):
+            assert np.array_equal(f_host.stage_sizes(k), f_dev.stage_sizes(k))
+        b = make_rhs(N, 2, seed=8)
+        xh = f_host.apply(_dev(b)).cpu().numpy()
+        xd = f_dev.apply(_dev(b)).cpu().numpy()
+        tol = 1e-12 if prec == 64 else 1e-4
+        assert np.abs(xh - xd).max() <= tol * np.abs(xh).max()
+
+
+def test_kernel_profiler_counts_launches():
+    dims, L = (32, 32), 5
+    A = convdiff(dims, (10.0, 10.0))
+    P.profile_enable(True)
+    fac = P.factor(A, P.order_grid(dims, L), eps=1e-3, precision=32)
+    fac.apply(_dev(make_rhs(A.shape[0], 1, seed=0)))
+    q = P.profile_query("front_qr")
+    a = P.profile_query("apply_front_fwd")
+    P.profile_enable(False)
+    assert q["launches"] >= L and q["total_ms"] > 0 and q["flops"] > 0
+    assert a["launches"] >= L and a["bytes"] > 0
+    P.profile_enable(True, only="sparsify")
+    P.factor(A, P.order_grid(dims, L), eps=1e-3, precision=32)
+    assert P.profile_query("front_qr")["launches"] == 0
+    assert P.profile_query("sparsify")["launches"] > 0
+    P.profile_enable(False)
