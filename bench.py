@@ -107,11 +107,21 @@ def main():
     b = torch.from_numpy(make_rhs(N, 1, seed=0)).to(dev)
     torch.cuda.synchronize()
 
-    def step(precision):
+    phases = {"order": [], "analyze": [], "factor": [], "solve": []}
+
+    def step(precision, record=False):
+        t0 = time.perf_counter()
         ordg = P.order_grid(dims, L)
+        t1 = time.perf_counter()
         sym = P.analyze(A, ordg)
+        t2 = time.perf_counter()
         fac = P.factor_device(A, sym, dA, eps=args.eps, precision=precision)
+        t3 = time.perf_counter()
         x, info = fac.solve(b, tol=args.tol)
+        t4 = time.perf_counter()
+        if record:
+            for k, v in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
+                phases[k].append(v)
         return fac, x, info
 
     def run(precision, steps, warmup):
@@ -122,7 +132,7 @@ def main():
         t0 = time.perf_counter()
         for _ in range(steps):
             s0 = time.perf_counter()
-            fac, x, info = step(precision)
+            fac, x, info = step(precision, record=precision == 32)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - s0)
             infos.append(info[0])
@@ -175,6 +185,7 @@ def main():
                    "eps": args.eps, "levels": L, "n": N},
         "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99)},
         "gmres_iterations": infos[-1]["iterations"], "relres": res,
+        "phase_ms": {k: round(1e3 * sum(v) / max(1, len(v)), 3) for k, v in phases.items()},
         "fp64_plain": {"value": value64, "ms_per_step": 1e3 * dt64 / args.fp64_steps,
                        "latency_ms": {"p50": 1e3 * pct(lat64, 50), "p99": 1e3 * pct(lat64, 99)},
                        "gmres_iterations": infos64[-1]["iterations"]},

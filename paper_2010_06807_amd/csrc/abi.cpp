@@ -223,7 +223,7 @@ spaqr_status spaqr_factor_device(const spaqr_csr* A, const spaqr_csr_dev* Ad, co
 
 static void to_device(spaqr_handle* h, const double* b, int64_t nrhs, int64_t ld, double** db) {
   const int64_t N = h->e->n();
-  SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(db), (size_t)N * nrhs * sizeof(double)));
+  *db = static_cast<double*>(dev_alloc((size_t)N * nrhs * sizeof(double), h->e->stream()));
   SPAQR_HIP(hipMemcpy2DAsync(*db, N * sizeof(double), b, ld * sizeof(double), N * sizeof(double), nrhs,
                              hipMemcpyHostToDevice, h->e->stream()));
 }
@@ -242,8 +242,7 @@ spaqr_status spaqr_apply(spaqr_handle* h, const double* b, double* x, int64_t nr
       h->e->apply_dev(db, N, db, N, (int)nrhs);
       SPAQR_HIP(hipMemcpy2DAsync(x, ld * sizeof(double), db, N * sizeof(double), N * sizeof(double), nrhs,
                                  hipMemcpyDeviceToHost, s));
-      SPAQR_HIP(hipStreamSynchronize(s));
-      SPAQR_HIP(hipFree(db));
+      dev_free(db, s);
     }
     SPAQR_HIP(hipStreamSynchronize(s));
     return SPAQR_OK;
@@ -264,13 +263,12 @@ spaqr_status spaqr_solve(spaqr_handle* h, const double* b, double* x, int64_t nr
     } else {
       double *db = nullptr, *dx = nullptr;
       to_device(h, b, nrhs, ld, &db);
-      SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&dx), (size_t)N * nrhs * sizeof(double)));
+      dx = static_cast<double*>(dev_alloc((size_t)N * nrhs * sizeof(double), s));
       st = fgmres_solve(*h->e, db, N, dx, N, (int)nrhs, tol, info);
       SPAQR_HIP(hipMemcpy2DAsync(x, ld * sizeof(double), dx, N * sizeof(double), N * sizeof(double), nrhs,
                                  hipMemcpyDeviceToHost, s));
-      SPAQR_HIP(hipStreamSynchronize(s));
-      SPAQR_HIP(hipFree(db));
-      SPAQR_HIP(hipFree(dx));
+      dev_free(db, s);
+      dev_free(dx, s);
     }
     SPAQR_HIP(hipStreamSynchronize(s));
     return st;

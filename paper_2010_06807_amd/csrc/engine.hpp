@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "mem.hpp"
 #include "symbolic.hpp"
 
 namespace spaqr {
@@ -36,6 +37,7 @@ class DevArena {
   struct Chunk { char* p; size_t size; };
   std::vector<Chunk> chunks_;
   size_t chunk_, cur_ = 0, off_ = 0;
+  hipStream_t stream_ = nullptr;  // stream of the allocations (frees are ordered on it)
 };
 
 // Pinned host staging for uploads; reset only once the stream has passed
@@ -52,8 +54,7 @@ class Stager {
   void reset() { cur_ = 0; off_ = 0; }
 
  private:
-  struct Chunk { char* p; size_t size; };
-  std::vector<Chunk> chunks_;
+  std::vector<PinnedChunk> chunks_;
   size_t cur_ = 0, off_ = 0;
 };
 
@@ -63,6 +64,9 @@ struct StageApply {
   std::vector<int64_t> colour_ptr;       // boundaries of colours in fronts
   std::vector<int> colour_max_m;         // LDS rows of the forward launch per colour
   int max_bwd_rows = 0;                  // max n + k
+  int max_n = 0, max_k = 0;              // largest front and ancestor-column widths
+  int jb = 1;                            // QR panel width of the stage's fronts
+  int64_t nifaces_small = 0;             // interfaces of <= 64 unknowns come first
   int64_t nfronts = 0;
   ApIface<T>* ifaces = nullptr;
   int64_t nifaces = 0;

@@ -31,7 +31,7 @@ double now_ms() {
 
 // ---------------------------------------------------------------- DevArena
 DevArena::~DevArena() {
-  for (auto& c : chunks_) (void)hipFree(c.p);
+  for (auto& c : chunks_) dev_free(c.p, stream_);
 }
 
 void* DevArena::alloc(size_t bytes, hipStream_t s) {
@@ -47,9 +47,8 @@ void* DevArena::alloc(size_t bytes, hipStream_t s) {
     off_ = 0;
   }
   const size_t sz = std::max(chunk_, bytes);
-  char* p = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&p), sz, s);
-  if (e != hipSuccess || !p) throw Error(SPAQR_ENOMEM, "device allocation failed");
+  char* p = static_cast<char*>(dev_alloc(sz, s));
+  stream_ = s;
   chunks_.push_back({p, sz});
   cur_ = chunks_.size() - 1;
   off_ = bytes;
@@ -57,7 +56,7 @@ void* DevArena::alloc(size_t bytes, hipStream_t s) {
 }
 
 void DevArena::release(hipStream_t s) {
-  for (auto& c : chunks_) (void)hipFreeAsync(c.p, s);
+  for (auto& c : chunks_) dev_free(c.p, s);
   chunks_.clear();
   reset();
 }
@@ -70,7 +69,7 @@ size_t DevArena::reserved() const {
 
 // ---------------------------------------------------------------- Stager
 Stager::~Stager() {
-  for (auto& c : chunks_) (void)hipHostFree(c.p);
+  for (auto& c : chunks_) pinned_release(c);
 }
 
 void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
@@ -81,10 +80,7 @@ void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipSt
     off_ = 0;
   }
   if (cur_ >= chunks_.size()) {
-    const size_t sz = std::max(need, size_t(16) << 20);
-    char* p = nullptr;
-    SPAQR_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), sz, hipHostMallocDefault));
-    chunks_.push_back({p, sz});
+    chunks_.push_back(pinned_acquire(need));
     cur_ = chunks_.size() - 1;
     off_ = 0;
   }
@@ -111,6 +107,7 @@ class Engine final : public EngineBase {
  public:
   Engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S, const spaqr_opts& o, hipStream_t s)
       : S_(S), o_(o), s_(s) {
+    mem_setup(s_);
     st_.s.n = S.n;
     st_.s.levels = S.L;
     st_.s.precision = sizeof(T) == 4 ? 32 : 64;
@@ -125,8 +122,9 @@ class Engine final : public EngineBase {
     st_.s.ms_factor = now_ms() - t0;
   }
   ~Engine() override {
+    dev_free(apply_ws_, s_);
     (void)hipStreamSynchronize(s_);
-    if (apply_ws_) (void)hipFree(apply_ws_);
+    pinned_release(pinned_);
   }
 
   void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) override;
@@ -154,8 +152,8 @@ class Engine final : public EngineBase {
   DevArena pools_[2] = {DevArena(size_t(64) << 20), DevArena(size_t(64) << 20)};
   Stager stager_[2];
   int stager_cur_ = 0;
+  PinnedChunk pinned_;            // rank readback buffer
   int* pinned_ints_ = nullptr;
-  size_t pinned_cap_ = 0;
   int* d_zcol_ = nullptr;  // set by the device column-norm kernel for a zero column
 
   // current stage state
@@ -316,6 +314,11 @@ void Engine<T>::stage(int k) {
   T* VR = persist_.alloc_n<T>(std::max<int64_t>(1, vr_off[nf]), s_);
   T* RSJ = persist_.alloc_n<T>(std::max<int64_t>(1, rsj_off[nf]), s_);
   T* TAU = persist_.alloc_n<T>(std::max<int64_t>(1, tau_off[nf]), s_);
+  // compact-WY panel factors of every front (used by the forward apply)
+  std::vector<int64_t> tp_off(nf + 1, 0);
+  for (int64_t f = 0; f < nf; ++f) tp_off[f + 1] = tp_off[f] + (int64_t)((fn[f] + jbf - 1) / jbf) * jbf * jbf;
+  T* TPF = persist_.alloc_n<T>(std::max<int64_t>(1, tp_off[nf]), s_);
+  ap.jb = jbf;
   for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
     std::vector<CopyTile<T>> g, sc;
     Job gj, sj;
@@ -350,7 +353,7 @@ void Engine<T>::stage(int k) {
       gj.close(g);
       sj.close(sc);
       if (n > 0) {
-        qd.push_back({Wf, TAU + tau_off[f], nullptr, d_flag, fm[f], n, nc, 0});
+        qd.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag, fm[f], n, nc, 0});
         const double mm = fm[f], nn = n, kk = nc - n;
         qr_flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
         qr_bytes += 2.0 * mm * nc * sizeof(T);
@@ -395,9 +398,12 @@ void Engine<T>::stage(int k) {
         slot_list(rows, rs);
         cs_off.push_back((int64_t)cs.size());
         slot_list(F.cols, cs);
-        af.push_back({VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], nullptr, nullptr, m, n, nc - n, 0});
+        af.push_back({VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], TPF + tp_off[f], nullptr, nullptr, m, n,
+                      nc - n, jbf});
         cmax = std::max(cmax, m);
         ap.max_bwd_rows = std::max(ap.max_bwd_rows, nc);
+        ap.max_n = std::max(ap.max_n, n);
+        ap.max_k = std::max(ap.max_k, nc - n);
         const double mm = m, nn = n, kk = nc - n, eb = sizeof(T);
         // forward: V below the diagonal + tau + row slots; x rows in and out
         ffb += (mm * nn - nn * (nn + 1) / 2 + nn) * eb + 4 * mm;
@@ -552,7 +558,7 @@ void Engine<T>::stage(int k) {
         d.flag = FLAGS + t;
         cpos.push_back(c_off);
         npos.push_back(n_off);
-        c_off += (int64_t)P * d.mmax;
+        c_off += (int64_t)(P <= 64 ? 65 : P) * d.mmax;
         n_off += d.mmax;
         max_nb = std::max(max_nb, d.nrow + d.ncol);
         max_pc = std::max<int>(max_pc, P);
@@ -569,13 +575,28 @@ void Engine<T>::stage(int k) {
         sd[t].nrm = NW + npos[t];
         sd[t].perm = IW + 2 * npos[t];
       }
+      // small interfaces go to the register/LDS kernel (FP32: P <= 64, FP64: P <= 32)
+      constexpr int kSmallP = sizeof(T) == 4 ? 64 : 32;
+      std::stable_partition(sd.begin(), sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
+      int64_t nsmall = 0;
+      int pmax_small = 1, mmax_small = 1;
+      for (const SpDesc<T>& q : sd)
+        if (q.P <= kSmallP) {
+          ++nsmall;
+          pmax_small = std::max<int>(pmax_small, q.P);
+          mmax_small = std::max<int>(mmax_small, q.mmax);
+        }
+      const int pclass = pmax_small <= 16 ? 16 : (pmax_small <= 32 ? 32 : 64);
+      const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
       SpDesc<T>* dsd = up.upload(work_, sd, s_);
       SpNbr* dnb = up.upload(work_, nb, s_);
       {
         double by = 0.0;
         for (const SpDesc<T>& q : sd) by += 2.0 * q.P * (double)q.mmax * sizeof(T);
         ProfScope ps("sparsify", s_, 0.0, by);
-        launch_sparsify<T>(dsd, (int64_t)sd.size(), dnb, pool_, d_rank, o_.eps, max_pc, max_nb, s_);
+        launch_sparsify_small<T>(dsd, nsmall, dnb, pool_, d_rank, o_.eps, pmax_small, max_nb, cmax_small, s_);
+        launch_sparsify<T>(dsd + nsmall, (int64_t)sd.size() - nsmall, dnb, pool_, d_rank, o_.eps, max_pc, max_nb,
+                           s_);
       }
     }
     // apply descriptors of the interfaces
@@ -593,17 +614,20 @@ void Engine<T>::stage(int k) {
     }
     int32_t* dsl = up.upload(persist_, sl, s_);
     for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
+    // interfaces of at most 64 unknowns first (one-wavefront apply kernel)
+    std::stable_partition(ai.begin(), ai.end(), [](const ApIface<T>& q) { return q.P <= 64; });
+    for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= 64 ? 1 : 0;
     ap.ifaces = up.upload(persist_, ai, s_);
     ap.nifaces = (int64_t)ai.size();
     st_.s.interfaces_sparsified += (int64_t)ai.size();
   }
 
   // ------------------------------------------------ rank readback
-  const size_t need = (size_t)nclu + 2;
-  if (pinned_cap_ < need) {
-    if (pinned_ints_) (void)hipHostFree(pinned_ints_);
-    SPAQR_HIP(hipHostMalloc(reinterpret_cast<void**>(&pinned_ints_), need * sizeof(int), hipHostMallocDefault));
-    pinned_cap_ = need;
+  const size_t need = ((size_t)nclu + 2) * sizeof(int);
+  if (pinned_.size < need) {
+    pinned_release(pinned_);
+    pinned_ = pinned_acquire(need);
+    pinned_ints_ = reinterpret_cast<int*>(pinned_.p);
   }
   if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
   SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag, sizeof(int), hipMemcpyDeviceToHost, s_));
@@ -711,9 +735,8 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
   const int64_t N = S_.n;
   const size_t need = (size_t)N * nrhs;
   if (apply_ws_cap_ < need) {
-    if (apply_ws_) SPAQR_HIP(hipFree(apply_ws_));
-    apply_ws_ = nullptr;
-    SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&apply_ws_), need * sizeof(double)));
+    dev_free(apply_ws_, s_);
+    apply_ws_ = static_cast<double*>(dev_alloc(need * sizeof(double), s_));
     apply_ws_cap_ = need;
   }
   double* xh = apply_ws_;
@@ -725,22 +748,24 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
       const int64_t cnt = a.colour_ptr[c + 1] - a.colour_ptr[c];
       if (cnt == 0) continue;
       ProfScope ps("apply_front_fwd", s_, a.fwd_flops[c] * nrhs, a.fwd_fac_bytes[c] + a.fwd_vec_bytes[c] * nrhs);
-      launch_front_fwd<T>(a.fronts + a.colour_ptr[c], cnt, a.colour_max_m[c], xh, N, nrhs, s_);
+      launch_front_fwd_wy<T>(a.fronts + a.colour_ptr[c], cnt, a.jb, a.colour_max_m[c], xh, N, nrhs, s_);
     }
     if (a.nifaces) {
       ProfScope ps("apply_iface_fwd", s_, a.if_fwd_flops * nrhs, a.if_fwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_fwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+      launch_iface_small<T>(a.ifaces, a.nifaces_small, false, xh, N, nrhs, s_);
+      launch_iface_fwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s_);
     }
   }
   for (int k = 1; k <= L; ++k) {
     const StageApply<T>& a = ap_[k];
     if (a.nifaces) {
       ProfScope ps("apply_iface_bwd", s_, a.if_bwd_flops * nrhs, a.if_bwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_bwd<T>(a.ifaces, a.nifaces, a.max_p, xh, N, nrhs, s_);
+      launch_iface_small<T>(a.ifaces, a.nifaces_small, true, xh, N, nrhs, s_);
+      launch_iface_bwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s_);
     }
     if (a.nfronts) {
       ProfScope ps("apply_front_bwd", s_, a.bwd_flops * nrhs, a.bwd_fac_bytes + a.bwd_vec_bytes * nrhs);
-      launch_front_bwd<T>(a.fronts, a.nfronts, a.max_bwd_rows, xh, N, nrhs, s_);
+      launch_front_bwd_reg<T>(a.fronts, a.nfronts, a.max_n, a.max_k, xh, N, nrhs, s_);
     }
   }
   launch_scatter_perm(x, ldx, xh, d_perm_, d_dc_, N, nrhs, s_);

@@ -103,19 +103,13 @@ __global__ void k_zero_cols(double* x, int64_t ldx, int64_t n) {
 
 unsigned gx(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
 
+// Solve-scoped device buffer from the stream-ordered pool.
 struct Dev {
+  hipStream_t s;
   double* p = nullptr;
-  size_t cap = 0;
-  void ensure(size_t n) {
-    if (cap >= n) return;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(1, n) * sizeof(double)));
-    cap = n;
-  }
-  ~Dev() {
-    if (p) (void)hipFree(p);
-  }
+  explicit Dev(hipStream_t st) : s(st) {}
+  void ensure(size_t n) { p = static_cast<double*>(dev_alloc(std::max<size_t>(1, n) * sizeof(double), s)); }
+  ~Dev() { dev_free(p, s); }
 };
 
 }  // namespace
@@ -141,7 +135,7 @@ int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t
   const int m = std::max(1, e.opt_restart());
   const int maxit = std::max(1, e.opt_maxit());
   const int nblk = (int)((N + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
-  Dev V, Z, W, part, hd;
+  Dev V(s), Z(s), W(s), part(s), hd(s);
   V.ensure((size_t)N * (m + 1) * nrhs);
   Z.ensure((size_t)N * m * nrhs);
   W.ensure((size_t)N * nrhs);

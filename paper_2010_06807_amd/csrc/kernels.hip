@@ -14,6 +14,9 @@
 //                 column-major factors
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace spaqr {
@@ -486,6 +489,218 @@ __global__ void __launch_bounds__(NT) k_sparsify(const SpDesc<T>* __restrict__ d
   }
 }
 
+// Sparsification for interfaces of at most PMAX unknowns (every interface of
+// the 2D workloads): the same steps as k_sparsify, organised for small P and
+// wide C.  C is stored column by column with PMAX + 1 rows per column (rows
+// P..PMAX zero), in LDS whenever it fits and in the global workspace
+// otherwise.  One thread per column: during a step a thread loads its whole
+// column into registers from one base address, so the loads overlap instead
+// of forming a dependent chain, and needs no predication.  Pivots, column
+// norms and the ratio test stay in FP64; ties go to the lowest current
+// position (columns are physically swapped).
+template <typename T, int PMAX, int NTH>
+__global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restrict__ descs,
+                                                        const SpNbr* __restrict__ nbrs, T* pool, int* rank,
+                                                        double eps, int lds_c_elems, int max_nb) {
+  constexpr int NW = NTH / 64;
+  constexpr int LDQ = PMAX + 1;
+  const SpDesc<T> d = descs[blockIdx.x];
+  const int P = d.P, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (P == 0 || *d.flag != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* bv = reinterpret_cast<double*>(smem);         // NW
+  double* sc = bv + NW;                                 // 4 scalars
+  int* bi = reinterpret_cast<int*>(sc + 4);             // NW
+  T* vb = reinterpret_cast<T*>(smem + align16((size_t)NW * 8 + 32 + (size_t)NW * 4));  // PMAX
+  int* off = reinterpret_cast<int*>(vb + PMAX);         // max_nb + 1
+  T* Cl = reinterpret_cast<T*>(smem + align16(reinterpret_cast<unsigned char*>(off + max_nb + 1) - smem));
+  const int nnb = d.nrow + d.ncol;
+  const SpNbr* nb = nbrs + d.nb;
+  if (tid == 0) {
+    int o = 0;
+    for (int b = 0; b < nnb; ++b) {
+      off[b] = o;
+      o += rank[nb[b].cluster];
+    }
+    off[nnb] = o;
+  }
+  __syncthreads();
+  const int m = off[nnb];
+  T* C = (int64_t)m * LDQ <= (int64_t)lds_c_elems ? Cl : d.C;
+  // C[:, o + a]: row a of block (i, p) (row neighbour) or column a of block
+  // (p, j) (column neighbour); rows P..PMAX are zero
+  for (int b = 0; b < nnb; ++b) {
+    const int w = off[b + 1] - off[b];
+    const T* blk = pool + nb[b].blk;
+    const int64_t ld = nb[b].ld;
+    T* Cb = C + (int64_t)off[b] * LDQ;
+    const bool rown = b < d.nrow;
+    for (int e = tid; e < w * LDQ; e += NTH) {
+      const int a = e / LDQ, q = e - a * LDQ;
+      T v = T(0);
+      if (q < P) v = rown ? blk[(int64_t)a * ld + q] : blk[(int64_t)q * ld + a];
+      Cb[e] = v;
+    }
+  }
+  __syncthreads();
+  double* nrm = d.nrm;
+  int* perm = d.perm;
+  int* ipos = d.perm + d.mmax;
+  for (int c = tid; c < m; c += NTH) {
+    const T* col = C + (int64_t)c * LDQ;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const double v = (double)col[q];
+      s += v * v;
+    }
+    nrm[c] = s;
+    perm[c] = c;
+  }
+  __syncthreads();
+  const int kmax = min(P, m);
+  int r = 0;
+  double R11 = 0.0;
+  for (int k = 0; k < kmax; ++k) {
+    double best = -1.0;
+    int bidx = m;
+    for (int c = k + tid; c < m; c += NTH) {
+      const double v = nrm[c];
+      if (v > best) {
+        best = v;
+        bidx = c;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(best, o, 64);
+      const int i2 = __shfl_xor(bidx, o, 64);
+      if (v2 > best || (v2 == best && i2 < bidx)) {
+        best = v2;
+        bidx = i2;
+      }
+    }
+    if (lane == 0) {
+      bv[wv] = best;
+      bi[wv] = bidx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b0 = bv[0];
+      int i0 = bi[0];
+      for (int w = 1; w < NW; ++w)
+        if (bv[w] > b0 || (bv[w] == b0 && bi[w] < i0)) {
+          b0 = bv[w];
+          i0 = bi[w];
+        }
+      sc[0] = b0;
+      sc[2] = (double)i0;
+    }
+    __syncthreads();
+    const int piv = (int)sc[2];
+    const double rkk = sqrt(sc[0]);
+    __syncthreads();
+    if (k == 0) {
+      R11 = rkk;
+      if (R11 == 0.0) break;
+    }
+    if (eps > 0.0 && rkk < eps * R11) break;
+    if (piv != k) {
+      T* ck = C + (int64_t)k * LDQ;
+      T* cp = C + (int64_t)piv * LDQ;
+      for (int q = tid; q < PMAX; q += NTH) {
+        const T a = ck[q];
+        ck[q] = cp[q];
+        cp[q] = a;
+      }
+      if (tid == 0) {
+        const double tn = nrm[k];
+        nrm[k] = nrm[piv];
+        nrm[piv] = tn;
+        const int ti = perm[k];
+        perm[k] = perm[piv];
+        perm[piv] = ti;
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+      // Householder of column k (rows k..P-1), one row per lane
+      T* ck = C + (int64_t)k * LDQ;
+      const double x = lane < P ? (double)ck[lane] : 0.0;
+      const double s = wave_sum(lane > k ? x * x : 0.0);
+      const double alpha = __shfl(x, k, 64);
+      double beta, tau, scal;
+      householder(alpha, s, beta, tau, scal);
+      if (lane < PMAX) {
+        T v;
+        if (lane < k) v = T(0);
+        else if (lane == k) v = T(1);
+        else v = lane < P ? (T)(x * scal) : T(0);
+        vb[lane] = v;
+        if (lane > k && lane < P) ck[lane] = v;
+      }
+      if (lane == 0) {
+        ck[k] = (T)beta;
+        sc[1] = tau;
+        d.tauq[k] = (T)tau;
+      }
+    }
+    __syncthreads();
+    const T tau = (T)sc[1];
+    for (int c = k + 1 + tid; c < m; c += NTH) {
+      T* col = C + (int64_t)c * LDQ;
+      T a[PMAX];
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) a[q] = col[q];
+      T w = T(0);
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) w += vb[q] * a[q];
+      const T tw = tau * w;
+      double s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) {
+        a[q] -= tw * vb[q];
+        const double aq = (double)a[q];
+        s2 += q > k ? aq * aq : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q) col[q] = a[q];
+      nrm[c] = s2;
+    }
+    __syncthreads();
+    r = k + 1;
+  }
+  if (r < P) {
+    for (int pos = tid; pos < m; pos += NTH) ipos[perm[pos]] = pos;
+    __syncthreads();
+    for (int b = 0; b < nnb; ++b) {
+      const int w = off[b + 1] - off[b];
+      T* blk = pool + nb[b].blk;
+      const int64_t ld = nb[b].ld;
+      const int o = off[b];
+      if (b < d.nrow) {
+        for (int e = tid; e < w * r; e += NTH) {
+          const int a = e / r, q = e - a * r;
+          const int pos = ipos[o + a];
+          blk[(int64_t)a * ld + q] = q <= pos ? C[(int64_t)pos * LDQ + q] : T(0);
+        }
+      } else {
+        for (int e = tid; e < w * r; e += NTH) {
+          const int q = e / w, a = e - q * w;
+          const int pos = ipos[o + a];
+          blk[(int64_t)q * ld + a] = q <= pos ? C[(int64_t)pos * LDQ + q] : T(0);
+        }
+      }
+    }
+    for (int e = tid; e < P * r; e += NTH) {
+      const int k = e / P, q = e - k * P;
+      d.vq[(int64_t)q + (int64_t)k * P] = q < k ? T(0) : (q == k ? T(1) : C[(int64_t)k * LDQ + q]);
+    }
+    __syncthreads();
+    if (tid == 0) rank[d.cluster] = r;
+  }
+}
+
 // ---------------------------------------------------------------- apply
 // Rows of a work vector are owned by lane (row % 64) for the whole kernel, so
 // a wavefront needs no barrier between reflectors.
@@ -618,6 +833,193 @@ __global__ void __launch_bounds__(64) k_ap_iface_bwd(const ApIface<T>* __restric
     for (int q = lane; q < P; q += 64) x[d.slots[q] + (int64_t)(c0 + c) * ldx] = xs[q + c * P];
 }
 
+// Forward sweep of one colour of fronts, panel by panel with the compact-WY
+// factors stored by the QR: x[rows] <- (I - V_p T_p V_p^T)^T x[rows] for the
+// panels p = 0, 1, ...  Four wavefronts per front; a panel costs one pass of
+// independent loads for V_p^T x and one (cached) pass for the update, instead
+// of two dependent passes per reflector.
+template <typename T, int JB>
+__global__ void __launch_bounds__(256) k_ap_front_fwd_wy(const ApFront<T>* __restrict__ ds, double* x, int64_t ldx,
+                                                        int nrhs, int rb) {
+  const ApFront<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.n == 0 || nc <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int m = d.m, n = d.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* xs = reinterpret_cast<double*>(smem);  // m x nc
+  double* red = xs + (size_t)m * rb;             // 4 x JB
+  double* wb = red + 4 * JB;                     // JB
+  double* ub = wb + JB;                          // JB
+  for (int c = 0; c < nc; ++c)
+    for (int r = tid; r < m; r += 256) xs[r + c * m] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
+  __syncthreads();
+  for (int p0 = 0; p0 < n; p0 += JB) {
+    const int jb = min(JB, n - p0);
+    const T* Vp = d.vr + (int64_t)p0 * m;
+    const T* Tp = d.tpan + (int64_t)(p0 / JB) * JB * JB;
+    for (int c = 0; c < nc; ++c) {
+      double acc[JB];
+#pragma unroll
+      for (int t = 0; t < JB; ++t) acc[t] = 0.0;
+      for (int r = p0 + tid; r < m; r += 256) {
+        const double xr = xs[r + c * m];
+        const int rr = r - p0;
+#pragma unroll
+        for (int t = 0; t < JB; ++t) {
+          const double v = (t >= jb || rr < t) ? 0.0 : (rr == t ? 1.0 : (double)Vp[r + (int64_t)t * m]);
+          acc[t] += v * xr;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const double sv = wave_sum(acc[t]);
+        if (lane == 0) red[wv * JB + t] = sv;
+      }
+      __syncthreads();
+      if (tid < JB) wb[tid] = red[tid] + red[JB + tid] + red[2 * JB + tid] + red[3 * JB + tid];
+      __syncthreads();
+      if (tid < JB) {
+        double u = 0.0;
+        for (int q = 0; q <= tid; ++q) u += (double)Tp[q + tid * JB] * wb[q];
+        ub[tid] = u;
+      }
+      __syncthreads();
+      for (int r = p0 + tid; r < m; r += 256) {
+        const int rr = r - p0;
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < JB; ++t) {
+          const double v = (t >= jb || rr < t) ? 0.0 : (rr == t ? 1.0 : (double)Vp[r + (int64_t)t * m]);
+          s += v * ub[t];
+        }
+        xs[r + c * m] -= s;
+      }
+      __syncthreads();
+    }
+  }
+  for (int c = 0; c < nc; ++c)
+    for (int r = tid; r < m; r += 256) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = xs[r + c * m];
+}
+
+// Backward sweep of the fronts of one level: x_s <- R_ss^{-1} (x_s - R_sj x_j).
+// The R_sj product accumulates in registers (one row per thread, independent
+// loads over j); the triangular solve runs in 64-row blocks from the bottom,
+// each diagonal block by one wavefront with shuffles, the rows above it
+// updated by all threads.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __restrict__ ds, double* x,
+                                                         int64_t ldx, int nrhs, int rb) {
+  const ApFront<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
+  if (d.n == 0 || nc <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int n = d.n, k = d.k, m = d.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* ys = reinterpret_cast<double*>(smem);  // n x nc
+  double* xc = ys + (size_t)n * rb;              // k x nc
+  for (int c = 0; c < nc; ++c) {
+    for (int r = tid; r < n; r += 256) ys[r + c * n] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
+    for (int r = tid; r < k; r += 256) xc[r + c * k] = x[d.cols[r] + (int64_t)(c0 + c) * ldx];
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; ++c)
+    for (int r = tid; r < n; r += 256) {
+      double s = ys[r + c * n];
+#pragma unroll 8
+      for (int j = 0; j < k; ++j) s -= (double)d.rsj[r + (int64_t)j * n] * xc[j + c * k];
+      ys[r + c * n] = s;
+    }
+  __syncthreads();
+  const T* R = d.vr;
+  for (int b0 = ((n - 1) / 64) * 64; b0 >= 0; b0 -= 64) {
+    const int b1 = min(n, b0 + 64);
+    if (wv == 0) {
+      const int row = b0 + lane;
+      double Rrow[64];
+#pragma unroll
+      for (int lc = 0; lc < 64; ++lc)
+        Rrow[lc] = (row < b1 && b0 + lc < b1) ? (double)R[row + (int64_t)(b0 + lc) * m] : 0.0;
+      for (int c = 0; c < nc; ++c) {
+        double yl = row < b1 ? ys[row + c * n] : 0.0;
+#pragma unroll
+        for (int lc = 63; lc >= 0; --lc) {
+          if (b0 + lc < b1) {
+            if (lane == lc) yl = yl / Rrow[lc];
+            const double yc = __shfl(yl, lc, 64);
+            if (lane < lc) yl -= Rrow[lc] * yc;
+          }
+        }
+        if (row < b1) ys[row + c * n] = yl;
+      }
+    }
+    __syncthreads();
+    for (int c = 0; c < nc; ++c)
+      for (int r = tid; r < b0; r += 256) {
+        double s = 0.0;
+        for (int cc = b0; cc < b1; ++cc) s += (double)R[r + (int64_t)cc * m] * ys[cc + c * n];
+        ys[r + c * n] -= s;
+      }
+    __syncthreads();
+  }
+  for (int c = 0; c < nc; ++c)
+    for (int r = tid; r < n; r += 256) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = ys[r + c * n];
+}
+
+// Interfaces of at most 64 unknowns, one wavefront each, row `lane` of the
+// interface in one lane's registers: forward x_p <- Q^T U^T x_p, backward
+// x_p <- R_pp^{-1} Q x_p.  The lane's row of the U/R factor and of the Q
+// reflectors is loaded once (independent loads) and reused for every
+// reflector and every right-hand side.
+template <typename T>
+__global__ void __launch_bounds__(64) k_ap_iface_small(const ApIface<T>* __restrict__ ds, double* x, int64_t ldx,
+                                                      int nrhs, int backward) {
+  const ApIface<T> d = ds[blockIdx.x];
+  const int P = d.P, lane = threadIdx.x;
+  if (P == 0 || *d.flag != 0) return;
+  const int r = *d.rank;
+  const bool hasq = r < P;
+  T urow[64], qrow[64];
+#pragma unroll
+  for (int t = 0; t < 64; ++t) {
+    urow[t] = (lane < P && t < P) ? d.vru[lane + (int64_t)t * P] : T(0);
+    qrow[t] = (hasq && lane < P && t < r) ? d.vq[lane + (int64_t)t * P] : T(0);
+  }
+  for (int c = 0; c < nrhs; ++c) {
+    double xl = lane < P ? x[d.slots[lane] + (int64_t)c * ldx] : 0.0;
+    if (!backward) {
+#pragma unroll
+      for (int t = 0; t < 64; ++t)
+        if (t < P) {
+          const double v = lane == t ? 1.0 : (lane > t ? (double)urow[t] : 0.0);
+          const double dot = wave_sum(v * xl);
+          xl -= (double)d.tauu[t] * dot * v;
+        }
+#pragma unroll
+      for (int t = 0; t < 64; ++t)
+        if (hasq && t < r) {
+          const double v = (double)qrow[t];
+          const double dot = wave_sum(v * xl);
+          xl -= (double)d.tauq[t] * dot * v;
+        }
+    } else {
+#pragma unroll
+      for (int t = 63; t >= 0; --t)
+        if (hasq && t < r) {
+          const double v = (double)qrow[t];
+          const double dot = wave_sum(v * xl);
+          xl -= (double)d.tauq[t] * dot * v;
+        }
+#pragma unroll
+      for (int t = 63; t >= 0; --t)
+        if (t < P) {
+          if (lane == t) xl = xl / (double)urow[t];
+          const double yt = __shfl(xl, t, 64);
+          if (lane < t) xl -= (double)urow[t] * yt;
+        }
+    }
+    if (lane < P) x[d.slots[lane] + (int64_t)c * ldx] = xl;
+  }
+}
+
 __global__ void k_gather_perm(double* xhat, const double* __restrict__ b, int64_t ldb,
                               const int64_t* __restrict__ perm, int64_t N, int nrhs) {
   const int64_t tot = N * nrhs;
@@ -676,28 +1078,38 @@ int grid_for(int64_t n, int block) {
 
 }  // namespace
 
+// Every launcher checks that its kernel was accepted.
+static void check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(SPAQR_EDEVICE, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_copy(const CopyTile<T>* tiles, const int64_t* jobptr, int64_t njobs, hipStream_t s) {
   if (njobs <= 0) return;
   hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)njobs), dim3(NT), 0, s, tiles, jobptr);
+  check_launch("k_copy");
 }
 
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+  check_launch("k_fill");
 }
 
 template <typename T>
 void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
   hipLaunchKernelGGL(k_scatter_nz<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, nnz);
+  check_launch("k_scatter_nz");
 }
 
 void launch_colnorm(const int64_t* cptr, const int64_t* cidx, const double* val, int64_t n, double* dc,
                     int* zero_col, hipStream_t s) {
   hipLaunchKernelGGL(k_colnorm, dim3(grid_for(n, 256)), dim3(256), 0, s, cptr, cidx, val, n, dc, zero_col);
+  check_launch("k_colnorm");
 }
 
 template <typename T>
@@ -705,6 +1117,7 @@ void launch_scatter_scaled(T* pool, const int64_t* dst, const double* val, const
                            int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
   hipLaunchKernelGGL(k_scatter_scaled<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, col, dc, nnz);
+  check_launch("k_scatter_scaled");
 }
 
 static size_t qr_bytes_jb(int max_m, int jb, int eb) {
@@ -738,8 +1151,9 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
     SPAQR_QR_CASE(16)
     SPAQR_QR_CASE(32)
 #undef SPAQR_QR_CASE
-    default: break;
+    default: throw Error(SPAQR_EINVAL, "unsupported QR panel width");
   }
+  check_launch("k_qr");
 }
 
 template <typename T>
@@ -757,8 +1171,50 @@ void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool,
     SPAQR_SC_CASE(16)
     SPAQR_SC_CASE(32)
 #undef SPAQR_SC_CASE
-    default: break;
+    default: throw Error(SPAQR_EINVAL, "unsupported QR panel width");
   }
+  check_launch("k_scale");
+}
+
+// Largest dynamic LDS a workgroup may use on the current device (bytes).
+static size_t device_lds_limit() {
+  static size_t lim = 0;
+  if (!lim) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    lim = (size_t)v;
+  }
+  return lim;
+}
+
+template <typename T, int PMAX, int NTH>
+static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank,
+                                    double eps, int max_nb, size_t c_bytes, hipStream_t s) {
+  constexpr int NW = NTH / 64;
+  const size_t head = align16(align16((size_t)NW * 8 + 32 + (size_t)NW * 4) + PMAX * sizeof(T) +
+                              (size_t)(max_nb + 1) * 4);
+  const size_t lim = std::min<size_t>(device_lds_limit(), 64 * 1024);
+  size_t cb = std::min(c_bytes, lim > head + 1024 ? lim - head - 512 : 0);
+  const int lds_c_elems = (int)(cb / sizeof(T));
+  const size_t lds = head + (size_t)lds_c_elems * sizeof(T);
+  hipLaunchKernelGGL((k_sparsify_small<T, PMAX, NTH>), dim3((unsigned)n), dim3(NTH), lds, s, d, nb, pool, rank,
+                     eps, lds_c_elems, max_nb);
+  check_launch("k_sparsify_small");
+}
+
+template <typename T>
+void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
+                           int pmax, int max_nb, size_t max_c_elems, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t cbytes = max_c_elems * sizeof(T);
+  // thread counts keep the per-thread column in registers without spills
+  constexpr bool F32 = sizeof(T) == 4;
+  if (pmax <= 16) launch_sparsify_small_t<T, 16, 1024>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
+  else if (pmax <= 32) launch_sparsify_small_t<T, 32, F32 ? 1024 : 512>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
+  else if (F32) launch_sparsify_small_t<T, 64, 512>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
+  else throw Error(SPAQR_EINVAL, "FP64 interfaces above 32 unknowns use the generic sparsify kernel");
 }
 
 template <typename T>
@@ -768,6 +1224,7 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, in
   const size_t lds = align16((size_t)(max_nb + 1) * sizeof(int)) + (size_t)max_p * sizeof(double) +
                      8 * sizeof(double) + NT * sizeof(double) + NT * sizeof(int);
   hipLaunchKernelGGL(k_sparsify<T>, dim3((unsigned)n), dim3(NT), lds, s, d, nb, pool, rank, eps);
+  check_launch("k_sparsify");
 }
 
 static constexpr size_t kApplyLds = 64 * 1024;
@@ -786,9 +1243,11 @@ int apply_rhs_block(int max_rows, int nrhs) {
                        hipStream_t s) {                                                         \
     if (n <= 0 || nrhs <= 0) return;                                                            \
     const int rb = apply_rhs_block(max_rows, nrhs);                                             \
+    if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: item too large for LDS");                     \
     const size_t lds = (size_t)max_rows * rb * sizeof(double);                                  \
     hipLaunchKernelGGL(k_ap_##KERNEL<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)),  \
                        dim3(64), lds, s, d, x, ldx, nrhs, rb);                                  \
+    check_launch("k_ap_" #KERNEL);                                                              \
   }
 SPAQR_AP_LAUNCH(front_fwd, ApFront)
 SPAQR_AP_LAUNCH(front_bwd, ApFront)
@@ -796,16 +1255,61 @@ SPAQR_AP_LAUNCH(iface_fwd, ApIface)
 SPAQR_AP_LAUNCH(iface_bwd, ApIface)
 #undef SPAQR_AP_LAUNCH
 
+template <typename T>
+void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, double* x, int64_t ldx, int nrhs,
+                         hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int rb = apply_rhs_block(max_rows + 1, nrhs);
+  if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
+  const size_t lds = ((size_t)max_rows * rb + 6 * 32) * sizeof(double);
+  const dim3 grid((unsigned)n, (unsigned)((nrhs + rb - 1) / rb));
+  switch (jb) {
+#define SPAQR_FW_CASE(J) \
+  case J: hipLaunchKernelGGL((k_ap_front_fwd_wy<T, J>), grid, dim3(256), lds, s, d, x, ldx, nrhs, rb); break;
+    SPAQR_FW_CASE(1)
+    SPAQR_FW_CASE(2)
+    SPAQR_FW_CASE(4)
+    SPAQR_FW_CASE(8)
+    SPAQR_FW_CASE(16)
+    SPAQR_FW_CASE(32)
+#undef SPAQR_FW_CASE
+    default: throw Error(SPAQR_EINVAL, "unsupported panel width in the apply");
+  }
+  check_launch("k_ap_front_fwd_wy");
+}
+
+template <typename T>
+void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
+                          hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  const int rb = apply_rhs_block(max_n + max_k, nrhs);
+  if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
+  const size_t lds = (size_t)(max_n + max_k) * rb * sizeof(double);
+  hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
+                     d, x, ldx, nrhs, rb);
+  check_launch("k_ap_front_bwd_reg");
+}
+
+template <typename T>
+void launch_iface_small(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
+                        hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_ap_iface_small<T>, dim3((unsigned)n), dim3(64), 0, s, d, x, ldx, nrhs, backward ? 1 : 0);
+  check_launch("k_ap_iface_small");
+}
+
 void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_t* perm, int64_t N,
                         int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, xhat, b, ldb, perm,
                      N, nrhs);
+  check_launch("k_gather_perm");
 }
 
 void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,
                          const double* dc, int64_t N, int nrhs, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, x, ldx, xhat, perm,
                      dc, N, nrhs);
+  check_launch("k_scatter_perm");
 }
 
 #define SPAQR_INST(T)                                                                                  \
@@ -818,10 +1322,15 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_scale<T>(const ScaleBlk*, int64_t, const ScaleFac<T>*, T*, int, int, hipStream_t); \
   template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
                                    hipStream_t);                                                     \
+  template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
+                                         size_t, hipStream_t);                                       \
   template void launch_front_fwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_bwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_iface_fwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
-  template void launch_iface_bwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t);
+  template void launch_iface_bwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
+  template void launch_front_fwd_wy<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
+  template void launch_front_bwd_reg<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
+  template void launch_iface_small<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t);
 SPAQR_INST(float)
 SPAQR_INST(double)
 #undef SPAQR_INST

@@ -84,9 +84,10 @@ struct ApFront {
   const T* vr;    // m x n column-major: V below the diagonal, R_ss on/above
   const T* rsj;   // n x k column-major
   const T* tau;   // n
+  const T* tpan;  // compact-WY factor of every jb-reflector panel (jb x jb, column-major)
   const int32_t* rows;  // m slots: the front's row clusters
   const int32_t* cols;  // k slots: the ancestor column clusters
-  int32_t m, n, k, pad;
+  int32_t m, n, k, jb;
 };
 
 template <typename T>
@@ -124,12 +125,29 @@ void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool,
 template <typename T>
 void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
                      int max_p, int max_nb, hipStream_t s);
+// Interfaces of at most 64 unknowns; pmax = the largest P in the launch,
+// max_c_elems = the largest P x m of the launch (C is staged in LDS when it fits).
+template <typename T>
+void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
+                           int pmax, int max_nb, size_t max_c_elems, hipStream_t s);
 // Apply launches: max_rows = the largest number of FP64 rows one item keeps in
 // LDS per right-hand side (m for fronts forward, n + k backward, P for
 // interfaces).  Returns without launching when there is nothing to do.
 int apply_rhs_block(int max_rows, int nrhs);
 template <typename T>
 void launch_front_fwd(const ApFront<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
+// Panel-blocked forward sweep: every front of the launch has panel width jb.
+template <typename T>
+void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, double* x, int64_t ldx, int nrhs,
+                         hipStream_t s);
+// Backward sweep with register-accumulated R_sj products; max_n <= 1024.
+template <typename T>
+void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
+                          hipStream_t s);
+// Interfaces of at most 64 unknowns: one wavefront, one row per lane.
+template <typename T>
+void launch_iface_small(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
+                        hipStream_t s);
 template <typename T>
 void launch_front_bwd(const ApFront<T>* d, int64_t n, int max_rows, double* x, int64_t ldx, int nrhs, hipStream_t s);
 template <typename T>

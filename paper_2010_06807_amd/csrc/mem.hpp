@@ -1,0 +1,25 @@
+// Device and pinned-host memory helpers.  Device memory comes from the
+// stream-ordered allocator with a release threshold high enough that freed
+// blocks are reused instead of being returned to the driver; pinned staging
+// chunks are recycled through a process-wide free list (allocating pinned
+// memory costs milliseconds).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace spaqr {
+
+void mem_setup(hipStream_t s);                    // once per device
+void* dev_alloc(size_t bytes, hipStream_t s);     // stream-ordered, throws ENOMEM
+void dev_free(void* p, hipStream_t s);            // stream-ordered, NULL is a no-op
+
+struct PinnedChunk {
+  char* p = nullptr;
+  size_t size = 0;
+};
+PinnedChunk pinned_acquire(size_t bytes);          // at least `bytes`
+void pinned_release(PinnedChunk c);
+
+}  // namespace spaqr

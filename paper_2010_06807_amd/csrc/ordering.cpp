@@ -124,7 +124,40 @@ Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
     fin[i] = f;
   }
 
-  // ---- distinct finest clusters, sorted
+  // ---- distinct finest clusters: stable radix sort of the packed key
+  // (node, dl, dh), L bits each, keeps points in natural order inside a run
+  SPAQR_REQUIRE(L <= 21, SPAQR_EINVAL, "at most 21 levels");
+  std::vector<uint64_t> key(n);
+  for (int64_t i = 0; i < n; ++i)
+    key[i] = ((uint64_t)fin[i].node << (2 * L)) | ((uint64_t)fin[i].dl << L) | (uint64_t)fin[i].dh;
+  std::vector<int64_t> idx(n), tmp(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  {
+    const int bits = 3 * L + 1;
+    std::vector<int64_t> cnt(1 << 16);
+    for (int sh = 0; sh < bits; sh += 16) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (int64_t i = 0; i < n; ++i) cnt[(key[idx[i]] >> sh) & 0xffff]++;
+      int64_t sum = 0;
+      for (auto& c : cnt) {
+        const int64_t t = c;
+        c = sum;
+        sum += t;
+      }
+      for (int64_t i = 0; i < n; ++i) tmp[cnt[(key[idx[i]] >> sh) & 0xffff]++] = idx[i];
+      idx.swap(tmp);
+    }
+  }
+  // runs of equal keys
+  std::vector<Finest> uniq;
+  std::vector<int64_t> run_start;
+  for (int64_t i = 0; i < n; ++i)
+    if (i == 0 || key[idx[i]] != key[idx[i - 1]]) {
+      uniq.push_back(fin[idx[i]]);
+      run_start.push_back(i);
+    }
+  run_start.push_back(n);
+  const int64_t nf = (int64_t)uniq.size();
   auto less = [L](const Finest& a, const Finest& b) {
     if (a.level != b.level) return a.level > b.level;
     if (a.node != b.node) return a.node < b.node;
@@ -137,45 +170,21 @@ Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
     }
     return false;
   };
-  auto same = [](const Finest& a, const Finest& b) {
-    return a.node == b.node && a.dl == b.dl && a.dh == b.dh;
-  };
-  std::vector<Finest> uniq(fin);
-  std::sort(uniq.begin(), uniq.end(), [](const Finest& a, const Finest& b) {
-    if (a.node != b.node) return a.node < b.node;
-    if (a.dl != b.dl) return a.dl < b.dl;
-    return a.dh < b.dh;
-  });
-  uniq.erase(std::unique(uniq.begin(), uniq.end(), same), uniq.end());
-  std::sort(uniq.begin(), uniq.end(), less);
-  const int64_t nf = (int64_t)uniq.size();
-
-  // cluster id of each point: binary search in (node, dl, dh) order
-  std::vector<int64_t> byKey(nf);
-  std::iota(byKey.begin(), byKey.end(), 0);
-  std::sort(byKey.begin(), byKey.end(), [&](int64_t a, int64_t b) {
-    const Finest &x = uniq[a], &y = uniq[b];
-    if (x.node != y.node) return x.node < y.node;
-    if (x.dl != y.dl) return x.dl < y.dl;
-    return x.dh < y.dh;
-  });
-  std::vector<int64_t> cid(n), cnt(nf + 1, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    const Finest& f = fin[i];
-    auto it = std::lower_bound(byKey.begin(), byKey.end(), f, [&](int64_t a, const Finest& key) {
-      const Finest& x = uniq[a];
-      if (x.node != key.node) return x.node < key.node;
-      if (x.dl != key.dl) return x.dl < key.dl;
-      return x.dh < key.dh;
-    });
-    cid[i] = *it;
-    cnt[cid[i] + 1]++;
-  }
-  for (int64_t c = 0; c < nf; ++c) cnt[c + 1] += cnt[c];
-  o->perm.assign(n, 0);
+  std::vector<int64_t> order(nf);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return less(uniq[x], uniq[y]); });
+  std::vector<int64_t> cnt(nf + 1, 0);
+  o->perm.resize(n);
   {
-    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t i = 0; i < n; ++i) o->perm[pos[cid[i]]++] = i;
+    int64_t p = 0;
+    std::vector<Finest> sorted(nf);
+    for (int64_t c = 0; c < nf; ++c) {
+      const int64_t u = order[c];
+      sorted[c] = uniq[u];
+      for (int64_t i = run_start[u]; i < run_start[u + 1]; ++i) o->perm[p++] = idx[i];
+      cnt[c + 1] = p;
+    }
+    uniq.swap(sorted);
   }
   o->iperm.assign(n, 0);
   for (int64_t p = 0; p < n; ++p) o->iperm[o->perm[p]] = p;

@@ -120,16 +120,16 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
       }
       const int64_t N = r->A.n;
       double *db = nullptr, *dx = nullptr;
-      SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&db), N * r->nrhs * sizeof(double)));
-      SPAQR_HIP(hipMalloc(reinterpret_cast<void**>(&dx), N * r->nrhs * sizeof(double)));
+      db = static_cast<double*>(dev_alloc(N * r->nrhs * sizeof(double), srv->stream));
+      dx = static_cast<double*>(dev_alloc(N * r->nrhs * sizeof(double), srv->stream));
       SPAQR_HIP(hipMemcpyAsync(db, r->b.data(), N * r->nrhs * sizeof(double), hipMemcpyHostToDevice, srv->stream));
       r->info.assign(r->nrhs, spaqr_solve_info{});
       r->status = fgmres_solve(*r->eng, db, N, dx, N, (int)r->nrhs, r->tol, r->info.data());
       r->x.resize(N * r->nrhs);
       SPAQR_HIP(hipMemcpyAsync(r->x.data(), dx, N * r->nrhs * sizeof(double), hipMemcpyDeviceToHost, srv->stream));
       SPAQR_HIP(hipStreamSynchronize(srv->stream));
-      (void)hipFree(db);
-      (void)hipFree(dx);
+      dev_free(db, srv->stream);
+      dev_free(dx, srv->stream);
       r->eng.reset();
       r->sym.reset();
       srv->used -= r->est;

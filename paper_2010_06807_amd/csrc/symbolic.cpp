@@ -29,17 +29,27 @@ int64_t BlockSet::find(int32_t i, int32_t j) const {
 }
 
 BlockSet BlockSet::from_pairs(int64_t nclu, std::vector<Pair>& pairs) {
-  std::sort(pairs.begin(), pairs.end());
-  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  // bucket by row, then sort and deduplicate each (short) row
   BlockSet s;
   s.nclu = nclu;
-  s.rowptr.assign(nclu + 1, 0);
-  s.col.resize(pairs.size());
-  for (size_t t = 0; t < pairs.size(); ++t) {
-    s.rowptr[pairs[t].first + 1]++;
-    s.col[t] = pairs[t].second;
+  std::vector<int64_t> cnt(nclu + 1, 0);
+  for (const Pair& p : pairs) cnt[p.first + 1]++;
+  for (int64_t i = 0; i < nclu; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int32_t> tmp(pairs.size());
+  {
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (const Pair& p : pairs) tmp[pos[p.first]++] = p.second;
   }
-  for (int64_t i = 0; i < nclu; ++i) s.rowptr[i + 1] += s.rowptr[i];
+  s.rowptr.assign(nclu + 1, 0);
+  s.col.clear();
+  s.col.reserve(pairs.size());
+  for (int64_t i = 0; i < nclu; ++i) {
+    auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
+    std::sort(b, e);
+    e = std::unique(b, e);
+    s.col.insert(s.col.end(), b, e);
+    s.rowptr[i + 1] = (int64_t)s.col.size();
+  }
   return s;
 }
 
@@ -133,11 +143,20 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
   for (int64_t c = 0; c < cl.count(); ++c)
     for (int64_t p = cl.start[c]; p < cl.end[c]; ++p) S->cluster_of_pos_L[p] = (int32_t)c;
   std::vector<Pair> pairs;
-  pairs.reserve(A->nnz);
-  for (int64_t r = 0; r < n; ++r) {
-    int32_t ci = S->cluster_of_pos_L[ord.iperm[r]];
-    for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t)
-      pairs.emplace_back(ci, S->cluster_of_pos_L[ord.iperm[A->col[t]]]);
+  {
+    // distinct column clusters of each row cluster, rows visited in perm order
+    std::vector<int64_t> stamp(cl.count(), -1);
+    for (int64_t c = 0; c < cl.count(); ++c)
+      for (int64_t p = cl.start[c]; p < cl.end[c]; ++p) {
+        const int64_t r = ord.perm[p];
+        for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
+          const int32_t cj = S->cluster_of_pos_L[ord.iperm[A->col[t]]];
+          if (stamp[cj] != c) {
+            stamp[cj] = c;
+            pairs.emplace_back((int32_t)c, cj);
+          }
+        }
+      }
   }
   BlockSet cur = BlockSet::from_pairs(cl.count(), pairs);
 
