@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -253,6 +254,306 @@ __global__ void __launch_bounds__(NT) k_qr(const QRDesc<T>* __restrict__ descs) 
     if (d.tpan)
       for (int q = tid; q < JB * JB; q += NT) d.tpan[(int64_t)(j0 / JB) * JB * JB + q] = Tm[q];
     wy_apply_left<T, JB>(Ps, Tm, mp, A0 + jb, nc, nc - j0 - jb);
+    __syncthreads();
+  }
+  if (tid == 0 && zero_diag && d.flag) *d.flag = 1;
+}
+
+// ------------------------------------------------ register-panel front QR
+// 16-byte LDS vectors: JB consecutive values of a row in JB*sizeof(T)/16 reads.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int N = 4;
+  __device__ static void put(const float4& v, float* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+  __device__ static float4 get(const float* o) { return make_float4(o[0], o[1], o[2], o[3]); }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int N = 2;
+  __device__ static void put(const double2& v, double* o) { o[0] = v.x; o[1] = v.y; }
+  __device__ static double2 get(const double* o) { return make_double2(o[0], o[1]); }
+};
+
+template <typename T, int JB>
+__device__ __forceinline__ void lds_load_row(const T* p, T (&out)[JB]) {
+  using V = Vec16<T>;
+  const typename V::type* q = reinterpret_cast<const typename V::type*>(p);
+#pragma unroll
+  for (int i = 0; i < JB / V::N; ++i) V::put(q[i], out + i * V::N);
+}
+
+template <typename T, int JB>
+__device__ __forceinline__ void lds_store_row(T* p, const T (&in)[JB]) {
+  using V = Vec16<T>;
+  typename V::type* q = reinterpret_cast<typename V::type*>(p);
+#pragma unroll
+  for (int i = 0; i < JB / V::N; ++i) q[i] = V::get(in + i * V::N);
+}
+
+// acc += s * row, row read as 16-byte vectors
+template <typename T, int JB>
+__device__ __forceinline__ void lds_axpy_row(const T* p, T s, T (&acc)[JB]) {
+  using V = Vec16<T>;
+  const typename V::type* q = reinterpret_cast<const typename V::type*>(p);
+#pragma unroll
+  for (int i = 0; i < JB / V::N; ++i) {
+    T tmp[V::N];
+    V::put(q[i], tmp);
+#pragma unroll
+    for (int k = 0; k < V::N; ++k) acc[i * V::N + k] += tmp[k] * s;
+  }
+}
+
+// row . u, row read as 16-byte vectors
+template <typename T, int JB>
+__device__ __forceinline__ T lds_dot_row(const T* p, const T (&u)[JB]) {
+  using V = Vec16<T>;
+  const typename V::type* q = reinterpret_cast<const typename V::type*>(p);
+  T s = T(0);
+#pragma unroll
+  for (int i = 0; i < JB / V::N; ++i) {
+    T tmp[V::N];
+    V::put(q[i], tmp);
+#pragma unroll
+    for (int k = 0; k < V::N; ++k) s += tmp[k] * u[i * V::N + k];
+  }
+  return s;
+}
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// Compile-time loop: f(integral_constant<int, I>) for I = 0 .. N-1.  Register
+// arrays indexed this way stay in registers; a runtime index would turn every
+// access into a chain of compares and selects.
+template <int... Is, typename F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, F&& f) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// Exchange with a partner lane for the butterfly levels below.  Distances
+// 16 and 32 go through ds_bpermute; the shorter ones use DPP lane moves
+// inside a row of 16 lanes: row_mirror (lane i <-> 15 - i) pairs lanes that
+// differ in bit 3, row_half_mirror (i <-> 7 - i) lanes that differ in bit 2,
+// quad_perm swaps bit 1 or bit 0.  Each pairing flips exactly the level's own
+// bit among the bits not yet reduced, which is all a butterfly needs.
+template <int OFF>
+__device__ __forceinline__ int dpp_partner(int v) {
+  constexpr int CTRL = OFF == 8 ? 0x140 : (OFF == 4 ? 0x141 : (OFF == 2 ? 0x4E : 0xB1));
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int OFF, typename T>
+__device__ __forceinline__ T xshfl(T v) {
+  if constexpr (OFF >= 16) {
+    return __shfl_xor(v, OFF, 64);
+  } else if constexpr (sizeof(T) == 4) {
+    return __int_as_float(dpp_partner<OFF>(__float_as_int(v)));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_partner<OFF>((int)(b & 0xffffffffLL));
+    const int hi = dpp_partner<OFF>((int)(b >> 32));
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+  }
+}
+
+// Reduce-scatter of H2 = 2 H per-lane values over the wavefront, one
+// butterfly level per call: lanes with bit OFF set keep the upper half.
+template <typename T, int H, int OFF, int JB>
+__device__ __forceinline__ void rs_level(T (&v)[JB], int lane) {
+  if constexpr (H >= 1) {
+    const bool hi = (lane & OFF) != 0;
+    sfor<H>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      const T lo_v = v[i], hi_v = v[i + H];
+      const T send = hi ? lo_v : hi_v;
+      const T keep = hi ? hi_v : lo_v;
+      v[i] = keep + xshfl<OFF>(send);
+    });
+    rs_level<T, H / 2, OFF / 2, JB>(v, lane);
+  }
+}
+
+// On return every lane holds the wave total of value index
+// lane >> (6 - log2 JB).  JB values cost JB - 1 + (6 - log2 JB) shuffles
+// instead of 6 JB.
+template <typename T, int JB>
+__device__ __forceinline__ T wave_reduce_scatter(T (&v)[JB]) {
+  const int lane = threadIdx.x & 63;
+  rs_level<T, JB / 2, 32, JB>(v, lane);
+  T s = v[0];
+  constexpr int OFF0 = 32 >> ilog2c(JB);
+  if constexpr (OFF0 >= 8) s += xshfl<8>(s);
+  if constexpr (OFF0 >= 4) s += xshfl<4>(s);
+  if constexpr (OFF0 >= 2) s += xshfl<2>(s);
+  s += xshfl<1>(s);
+  return s;
+}
+
+// Blocked Householder QR of one front (row-major m x nc, the first n columns
+// pivots), panels of JB columns held in registers: thread tid owns panel rows
+// tid + NT q, q < Q, so m <= NT Q.  For column t of a panel one workgroup
+// reduction yields the whole row t of the Gram matrix of the rows below t:
+// the tail norm (Householder vector, dlarfg convention), the dots with the
+// later panel columns (their update) and the dots with the earlier
+// reflectors (column t of the compact-WY factor T).  One barrier per column.
+// The trailing columns are then updated as C <- C - V T^T (V^T C), one thread
+// per column, V read from LDS as aligned vectors.  Outputs as k_qr: R and V
+// in place, tau, T panels (column-major, JB x JB per panel) and the
+// zero-diagonal flag.
+template <typename T, int JB, int Q>
+__global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ descs) {
+  constexpr int SH = 6 - ilog2c(JB);
+  const QRDesc<T> d = descs[blockIdx.x];
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int m = d.m, n = d.n, nc = d.nc, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  T* Vs = reinterpret_cast<T*>(smem);  // m x JB row-major, explicit unit diagonal
+  T* Ts = Vs + (size_t)m * JB;         // JB x JB, row i of T at i * JB
+  T* red = Ts + JB * JB;               // 2 buffers x 4 waves x JB
+  T* rowt = red + 8 * JB;              // 2 buffers x JB
+  bool zero_diag = false;
+  for (int j0 = 0; j0 < n; j0 += JB) {
+    const int jb = min(JB, n - j0), mp = m - j0;
+    T* A0 = d.a + (int64_t)j0 * nc + j0;
+    T a[Q][JB];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int r = tid + NT * q;
+#pragma unroll
+      for (int c = 0; c < JB; ++c) a[q][c] = (r < mp && c < jb) ? A0[(int64_t)r * nc + c] : T(0);
+    }
+    T trow[JB];
+#pragma unroll
+    for (int c = 0; c < JB; ++c) trow[c] = T(0);
+    sfor<JB>([&](auto TC) {
+      constexpr int t = decltype(TC)::value;
+      if (t >= jb) return;  // uniform
+      constexpr int buf = t & 1;
+      T v[JB];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) v[c] = T(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int r = tid + NT * q;
+        if (r > t && r < mp) {
+          const T x = a[q][t];
+#pragma unroll
+          for (int c = 0; c < JB; ++c) v[c] += x * a[q][c];
+        }
+      }
+      if (tid == t) lds_store_row<T, JB>(rowt + buf * JB, a[0]);
+      const T s = wave_reduce_scatter<T, JB>(v);
+      if ((lane & ((1 << SH) - 1)) == 0) red[(buf * 4 + wv) * JB + (lane >> SH)] = s;
+      __syncthreads();
+      T g[JB], at[JB];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) g[c] = T(0);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) lds_axpy_row<T, JB>(red + (buf * 4 + w) * JB, T(1), g);
+      lds_load_row<T, JB>(rowt + buf * JB, at);
+      double beta, tau, scal;
+      householder((double)at[t], (double)g[t], beta, tau, scal);
+      const T sc = (T)scal, ta = (T)tau;
+      // z_c = v_c . v_t for c < t (T column), coef_c = tau v_t . a_c for c > t
+      T z[JB];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) z[c] = at[c] + sc * g[c];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int r = tid + NT * q;
+        if (r > t && r < mp) {
+          const T x = a[q][t] * sc;
+          a[q][t] = x;
+#pragma unroll
+          for (int c = t + 1; c < JB; ++c) a[q][c] -= (ta * z[c]) * x;
+        }
+      }
+      if (tid == t) {
+        a[0][t] = (T)beta;
+#pragma unroll
+        for (int c = t + 1; c < JB; ++c) a[0][c] -= ta * z[c];
+        d.tau[j0 + t] = ta;
+        trow[t] = ta;
+      }
+      if (tid < t) {
+        T acc = T(0);
+#pragma unroll
+        for (int c = 0; c < t; ++c) acc += trow[c] * z[c];
+        trow[t] = -ta * acc;
+      }
+      if ((T)beta == T(0)) zero_diag = true;
+    });
+    // R and V back to the front, explicit V and T to LDS, T panel out
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int r = tid + NT * q;
+      if (r < mp) {
+        T vrow[JB];
+#pragma unroll
+        for (int c = 0; c < JB; ++c) {
+          if (c < jb) A0[(int64_t)r * nc + c] = a[q][c];
+          vrow[c] = c >= jb ? T(0) : (r > c ? a[q][c] : (r == c ? T(1) : T(0)));
+        }
+        lds_store_row<T, JB>(Vs + (size_t)r * JB, vrow);
+      }
+    }
+    if (tid < JB) {
+      lds_store_row<T, JB>(Ts + tid * JB, trow);
+      if (d.tpan) {
+        T* tp = d.tpan + (int64_t)(j0 / JB) * JB * JB;
+#pragma unroll
+        for (int c = 0; c < JB; ++c) tp[tid + c * JB] = trow[c];
+      }
+    }
+    __syncthreads();
+    // trailing columns: C <- C - V (T^T (V^T C)); four adjacent lanes share a
+    // column, lane part p taking rows p, p + 4, ...
+    const int ncols = nc - j0 - jb, part = tid & 3;
+    for (int cb = tid >> 2; cb < ((ncols + 15) & ~15); cb += NT / 4) {
+      const bool live = cb < ncols;
+      T* Cc = A0 + jb + (live ? cb : 0);
+      T w[JB];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) w[c] = T(0);
+      if (live) {
+        int r = part;
+        for (; r + 28 < mp; r += 32) {
+          T cv[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * nc];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) lds_axpy_row<T, JB>(Vs + (size_t)(r + 4 * e) * JB, cv[e], w);
+        }
+        for (; r < mp; r += 4) lds_axpy_row<T, JB>(Vs + (size_t)r * JB, Cc[(int64_t)r * nc], w);
+      }
+#pragma unroll
+      for (int c = 0; c < JB; ++c) {
+        w[c] += xshfl<1>(w[c]);
+        w[c] += xshfl<2>(w[c]);
+      }
+      if (!live) continue;
+      T u[JB];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) u[c] = T(0);
+#pragma unroll
+      for (int q = 0; q < JB; ++q) lds_axpy_row<T, JB>(Ts + q * JB, w[q], u);
+      int r = part;
+      for (; r + 28 < mp; r += 32) {
+        T cv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * nc];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          Cc[(int64_t)(r + 4 * e) * nc] = cv[e] - lds_dot_row<T, JB>(Vs + (size_t)(r + 4 * e) * JB, u);
+      }
+      for (; r < mp; r += 4) Cc[(int64_t)r * nc] -= lds_dot_row<T, JB>(Vs + (size_t)r * JB, u);
+    }
     __syncthreads();
   }
   if (tid == 0 && zero_diag && d.flag) *d.flag = 1;
@@ -1128,18 +1429,67 @@ static size_t qr_bytes_jb(int max_m, int jb, int eb) {
 
 static constexpr size_t kLdsBudget = 64 * 1024;
 
-int qr_panel_width(int max_m, int eb) {
+// Register-panel QR (k_qr_reg) for matrices of at most NT * Q rows; taller
+// ones use the LDS-panel kernel k_qr.  Returns the panel width and Q (0 when
+// k_qr is used).
+struct QRPlan {
+  int jb, q;
+};
+static QRPlan qr_plan(int max_m, int eb) {
+  if (max_m <= NT) return {16, 1};
+  if (max_m <= 2 * NT) return {16, 2};
+  if (max_m <= 4 * NT) return {eb == 8 ? 8 : 16, 4};
   const int cap = eb == 8 ? 16 : 32;
   for (int jb = cap; jb >= 1; jb >>= 1)
-    if (qr_bytes_jb(max_m, jb, eb) <= kLdsBudget) return jb;
-  return 0;
+    if (qr_bytes_jb(max_m, jb, eb) <= kLdsBudget) return {jb, 0};
+  return {0, 0};
 }
+
+static size_t qr_reg_lds(int max_m, int jb, int eb) { return ((size_t)max_m * jb + (size_t)jb * jb + 10 * jb) * eb; }
+
+// Allow a kernel more than the default 64 KB of dynamic LDS (gfx950: 160 KB
+// per workgroup).  Called before every launch that needs it; the attribute
+// is set once per kernel.
+static void allow_lds(const void* fn, size_t bytes, const char* what) {
+  if (bytes <= 64 * 1024) return;
+  int dev = 0, lim = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lim = 64 * 1024;
+  if (bytes > (size_t)lim) throw Error(SPAQR_ENOMEM, std::string(what) + ": LDS need exceeds the device limit");
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) throw Error(SPAQR_EDEVICE, std::string(what) + ": cannot raise the LDS limit");
+}
+
+int qr_panel_width(int max_m, int eb) { return qr_plan(max_m, eb).jb; }
 
 size_t qr_lds_bytes(int max_m, int jb, int eb) { return qr_bytes_jb(max_m, jb, eb); }
 
 template <typename T>
 void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) {
   if (n <= 0) return;
+  const QRPlan pl = qr_plan(max_m, sizeof(T));
+  if (pl.jb != jb) throw Error(SPAQR_EINVAL, "QR panel width does not match the plan");
+  if (pl.q > 0) {
+    const size_t lds = qr_reg_lds(max_m, jb, sizeof(T));
+#define SPAQR_QRR(J, Q)                                                                      \
+  if (jb == J && pl.q == Q) {                                                               \
+    allow_lds(reinterpret_cast<const void*>(&k_qr_reg<T, J, Q>), lds, "k_qr_reg");          \
+    hipLaunchKernelGGL((k_qr_reg<T, J, Q>), dim3((unsigned)n), dim3(NT), lds, s, d);       \
+    check_launch("k_qr_reg");                                                               \
+    return;                                                                                 \
+  }
+    if constexpr (sizeof(T) == 4) {
+      SPAQR_QRR(16, 1)
+      SPAQR_QRR(16, 2)
+      SPAQR_QRR(16, 4)
+    } else {
+      SPAQR_QRR(16, 1)
+      SPAQR_QRR(16, 2)
+      SPAQR_QRR(8, 4)
+    }
+#undef SPAQR_QRR
+    throw Error(SPAQR_EINVAL, "unsupported register-panel QR shape");
+  }
   const size_t lds = qr_bytes_jb(max_m, jb, sizeof(T));
   switch (jb) {
 #define SPAQR_QR_CASE(J) \
@@ -1163,7 +1513,10 @@ void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool,
   const size_t lds = qr_bytes_jb(max_p, jb, sizeof(T));
   switch (jb) {
 #define SPAQR_SC_CASE(J) \
-  case J: hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, pool); break;
+  case J:                                                                                       \
+    allow_lds(reinterpret_cast<const void*>(&k_scale<T, J>), lds, "k_scale");                 \
+    hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, pool);    \
+    break;
     SPAQR_SC_CASE(1)
     SPAQR_SC_CASE(2)
     SPAQR_SC_CASE(4)
