@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -556,10 +557,8 @@ void Engine<T>::stage(int k) {
         d.vq = VQ + u_off[t];
         d.tauq = TAUQ + p_off[t];
         d.flag = FLAGS + t;
-        cpos.push_back(c_off);
-        npos.push_back(n_off);
-        c_off += (int64_t)(P <= 64 ? 65 : P) * d.mmax;
-        n_off += d.mmax;
+        cpos.push_back(0);
+        npos.push_back(0);
         max_nb = std::max(max_nb, d.nrow + d.ncol);
         max_pc = std::max<int>(max_pc, P);
         sd.push_back(d);
@@ -567,24 +566,62 @@ void Engine<T>::stage(int k) {
         st_.s.flops_sparsify += 4.0 * pp * mm * std::min(pp, mm);
       }
       if (sd.empty()) continue;
+      // interfaces whose columns fit in registers: register CPQR, one launch
+      // per (row class, columns per thread) when one shape does not fit all
+      std::stable_partition(sd.begin(), sd.end(),
+                            [](const SpDesc<T>& q) { return sparsify_reg_cpt(sizeof(T), q.P, q.mmax) > 0; });
+      int64_t nreg = 0;
+      int preg = 1, mreg = 1;
+      for (const SpDesc<T>& q : sd)
+        if (sparsify_reg_cpt(sizeof(T), q.P, q.mmax) > 0) {
+          ++nreg;
+          preg = std::max<int>(preg, q.P);
+          mreg = std::max<int>(mreg, q.mmax);
+        }
+      std::vector<std::array<int64_t, 4>> groups;  // begin, end, pmax, mmax
+      if (nreg > 0 && sparsify_reg_cpt(sizeof(T), preg, mreg) > 0) {
+        groups.push_back({0, nreg, preg, mreg});
+      } else if (nreg > 0) {
+        auto pcls = [](int P) { return P <= 16 ? 0 : (P <= 32 ? 1 : 2); };
+        std::stable_sort(sd.begin(), sd.begin() + nreg,
+                         [&](const SpDesc<T>& x, const SpDesc<T>& y) { return pcls(x.P) < pcls(y.P); });
+        for (int64_t b = 0; b < nreg;) {
+          int64_t e = b;
+          int pm = 1, mm = 1;
+          while (e < nreg && pcls(sd[e].P) == pcls(sd[b].P)) {
+            pm = std::max<int>(pm, sd[e].P);
+            mm = std::max<int>(mm, sd[e].mmax);
+            ++e;
+          }
+          groups.push_back({b, e, pm, mm});
+          b = e;
+        }
+      }
+      for (int64_t t = nreg; t < (int64_t)sd.size(); ++t) {
+        const int64_t P = sd[t].P;
+        cpos[t] = c_off;
+        npos[t] = n_off;
+        c_off += (P <= 64 ? 65 : P) * sd[t].mmax;
+        n_off += sd[t].mmax;
+      }
       T* CW = work_.alloc_n<T>(std::max<int64_t>(1, c_off), s_);
       double* NW = work_.alloc_n<double>(std::max<int64_t>(1, n_off), s_);
       int32_t* IW = work_.alloc_n<int32_t>(std::max<int64_t>(1, 2 * n_off), s_);
-      for (size_t t = 0; t < sd.size(); ++t) {
+      for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
         sd[t].C = CW + cpos[t];
         sd[t].nrm = NW + npos[t];
         sd[t].perm = IW + 2 * npos[t];
       }
-      // small interfaces go to the register/LDS kernel (FP32: P <= 64, FP64: P <= 32)
+      // the rest: small interfaces to the LDS kernel (FP32: P <= 64, FP64: P <= 32), then generic
       constexpr int kSmallP = sizeof(T) == 4 ? 64 : 32;
-      std::stable_partition(sd.begin(), sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
+      std::stable_partition(sd.begin() + nreg, sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
       int64_t nsmall = 0;
       int pmax_small = 1, mmax_small = 1;
-      for (const SpDesc<T>& q : sd)
-        if (q.P <= kSmallP) {
+      for (size_t t = (size_t)nreg; t < sd.size(); ++t)
+        if (sd[t].P <= kSmallP) {
           ++nsmall;
-          pmax_small = std::max<int>(pmax_small, q.P);
-          mmax_small = std::max<int>(mmax_small, q.mmax);
+          pmax_small = std::max<int>(pmax_small, sd[t].P);
+          mmax_small = std::max<int>(mmax_small, sd[t].mmax);
         }
       const int pclass = pmax_small <= 16 ? 16 : (pmax_small <= 32 ? 32 : 64);
       const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
@@ -594,9 +631,12 @@ void Engine<T>::stage(int k) {
         double by = 0.0;
         for (const SpDesc<T>& q : sd) by += 2.0 * q.P * (double)q.mmax * sizeof(T);
         ProfScope ps("sparsify", s_, 0.0, by);
-        launch_sparsify_small<T>(dsd, nsmall, dnb, pool_, d_rank, o_.eps, pmax_small, max_nb, cmax_small, s_);
-        launch_sparsify<T>(dsd + nsmall, (int64_t)sd.size() - nsmall, dnb, pool_, d_rank, o_.eps, max_pc, max_nb,
-                           s_);
+        for (const auto& g : groups)
+          launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, pool_, d_rank, o_.eps, (int)g[2], (int)g[3], max_nb,
+                                 s_);
+        launch_sparsify_small<T>(dsd + nreg, nsmall, dnb, pool_, d_rank, o_.eps, pmax_small, max_nb, cmax_small, s_);
+        launch_sparsify<T>(dsd + nreg + nsmall, (int64_t)sd.size() - nreg - nsmall, dnb, pool_, d_rank, o_.eps,
+                           max_pc, max_nb, s_);
       }
     }
     // apply descriptors of the interfaces

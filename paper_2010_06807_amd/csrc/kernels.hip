@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "common.hpp"
@@ -353,6 +354,8 @@ template <int OFF, typename T>
 __device__ __forceinline__ T xshfl(T v) {
   if constexpr (OFF >= 16) {
     return __shfl_xor(v, OFF, 64);
+  } else if constexpr (std::is_same<T, int>::value) {
+    return dpp_partner<OFF>(v);
   } else if constexpr (sizeof(T) == 4) {
     return __int_as_float(dpp_partner<OFF>(__float_as_int(v)));
   } else {
@@ -1002,6 +1005,207 @@ __global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restr
   }
 }
 
+// Register-resident partial CPQR of C = [A_np^T | A_pn] (Sections 2.5, 2.6;
+// rank rule of Section 4).  Thread tid owns columns tid + SP_NT j, j < CPT,
+// held in registers for the whole factorization (P <= PMAX rows each).
+// Columns are never moved: each carries its current position, and the swap of
+// the pivot with the column at position k only exchanges positions, so the
+// pivot choice (largest FP64 norm, ties to the lowest current position) is
+// the same as with physical swaps.  Per step: local and wavefront argmax,
+// the winning lane of each wavefront stages its column in LDS, one barrier,
+// the workgroup winner is picked, wavefront 0 forms the Householder vector
+// (dlarfg convention) in LDS, a second barrier, then every live column is
+// updated and its tail norm recomputed in FP64.  The pivot column keeps R
+// above the diagonal and becomes beta at row k.  After r steps rows 0..r-1 of
+// every column are W = Q^T C (zero below the diagonal of pivot columns) and
+// go back to the blocks.
+constexpr int SP_NT = 512;
+
+template <typename T, int PMAX, int CPT>
+__global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict__ descs,
+                                                    const SpNbr* __restrict__ nbrs, T* pool, int* rank,
+                                                    double eps, int max_nb) {
+  constexpr int NW = SP_NT / 64;
+  constexpr int VN = Vec16<T>::N;
+  const SpDesc<T> d = descs[blockIdx.x];
+  const int P = d.P, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (P == 0 || *d.flag != 0) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* slot = reinterpret_cast<T*>(smem);                       // 2 x NW x PMAX
+  T* vbuf = slot + 2 * NW * PMAX;                             // PMAX
+  double* cb = reinterpret_cast<double*>(vbuf + PMAX);        // 2 x NW candidate norms
+  double* hs = cb + 2 * NW;                                   // tau, beta
+  int* cpz = reinterpret_cast<int*>(hs + 2);                  // 2 x NW candidate positions
+  int* off = cpz + 2 * NW;                                    // max_nb + 1
+  const int nnb = d.nrow + d.ncol;
+  const SpNbr* nb = nbrs + d.nb;
+  if (tid == 0) {
+    int o = 0;
+    for (int b = 0; b < nnb; ++b) {
+      off[b] = o;
+      o += rank[nb[b].cluster];
+    }
+    off[nnb] = o;
+  }
+  __syncthreads();
+  const int m = off[nnb];
+  T a[CPT][PMAX];
+  double nr[CPT];
+  int pos[CPT], kel[CPT];
+  const T* src[CPT];
+  int64_t sstr[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = tid + SP_NT * j;
+    pos[j] = c;
+    kel[j] = -1;
+    src[j] = nullptr;
+    sstr[j] = 0;
+    if (c < m) {
+      int b = 0;
+      while (off[b + 1] <= c) ++b;
+      const int ai = c - off[b];
+      const T* blk = pool + nb[b].blk;
+      const int64_t ld = nb[b].ld;
+      // row neighbour: row ai of block (i, p); column neighbour: column ai of (p, j)
+      src[j] = b < d.nrow ? blk + (int64_t)ai * ld : blk + ai;
+      sstr[j] = b < d.nrow ? 1 : ld;
+    }
+    double s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      a[j][q] = (src[j] && q < P) ? src[j][q * sstr[j]] : T(0);
+      s2 += (double)a[j][q] * (double)a[j][q];
+    }
+    nr[j] = c < m ? s2 : -1.0;
+  }
+  const int kmax = min(P, m);
+  int r = 0;
+  double R11 = 0.0;
+  for (int k = 0; k < kmax; ++k) {
+    const int buf = k & 1;
+    double best = -1.0;
+    int bp = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+      if (kel[j] < 0 && nr[j] >= 0.0 && (nr[j] > best || (nr[j] == best && pos[j] < bp))) {
+        best = nr[j];
+        bp = pos[j];
+      }
+    double wb = best;
+    int wp = bp;
+    {
+      auto merge = [&](double ob, int op) {
+        if (ob > wb || (ob == wb && op < wp)) {
+          wb = ob;
+          wp = op;
+        }
+      };
+      merge(xshfl<32>(wb), xshfl<32>(wp));
+      merge(xshfl<16>(wb), xshfl<16>(wp));
+      merge(xshfl<8>(wb), xshfl<8>(wp));
+      merge(xshfl<4>(wb), xshfl<4>(wp));
+      merge(xshfl<2>(wb), xshfl<2>(wp));
+      merge(xshfl<1>(wb), xshfl<1>(wp));
+    }
+    if (wp != 0x7fffffff && bp == wp) {
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+        if (kel[j] < 0 && pos[j] == wp) lds_store_row<T, PMAX>(slot + (buf * NW + wv) * PMAX, a[j]);
+    }
+    if (lane == 0) {
+      cb[buf * NW + wv] = wb;
+      cpz[buf * NW + wv] = wp;
+    }
+    __syncthreads();
+    int ws = 0;
+    double gb = cb[buf * NW];
+    int gp = cpz[buf * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double ob = cb[buf * NW + w];
+      const int op = cpz[buf * NW + w];
+      if (ob > gb || (ob == gb && op < gp)) {
+        gb = ob;
+        gp = op;
+        ws = w;
+      }
+    }
+    const double rkk = sqrt(gb);
+    if (k == 0) {
+      R11 = rkk;
+      if (R11 == 0.0) break;
+    }
+    if (eps > 0.0 && rkk < eps * R11) break;
+    if (wv == 0) {
+      const double x = lane < P ? (double)slot[(buf * NW + ws) * PMAX + lane] : 0.0;
+      const double s = wave_sum(lane > k ? x * x : 0.0);
+      const double alpha = __shfl(x, k, 64);
+      double beta, tau, scal;
+      householder(alpha, s, beta, tau, scal);
+      const double v = lane < k ? 0.0 : (lane == k ? 1.0 : x * scal);
+      if (lane < PMAX) vbuf[lane] = (T)v;
+      if (lane < P) d.vq[(int64_t)lane + (int64_t)k * P] = (T)v;
+      if (lane == 0) {
+        hs[0] = tau;
+        hs[1] = beta;
+        d.tauq[k] = (T)tau;
+      }
+    }
+    __syncthreads();
+    const T tau = (T)hs[0], beta = (T)hs[1];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (kel[j] >= 0 || nr[j] < 0.0) continue;
+      if (pos[j] == gp) {
+        // the pivot: beta at row k, reflector storage below (not part of W)
+        kel[j] = k;
+        pos[j] = k;
+#pragma unroll
+        for (int q = 0; q < PMAX; ++q) a[j][q] = q == k ? beta : a[j][q];
+        continue;
+      }
+      if (pos[j] == k) pos[j] = gp;
+      T w = T(0);
+#pragma unroll
+      for (int q0 = 0; q0 < PMAX; q0 += VN) {
+        if (q0 + VN - 1 < k) continue;  // v is zero there (uniform)
+        T vv[VN];
+        Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) w += vv[e] * a[j][q0 + e];
+      }
+      const T tw = tau * w;
+      double s2 = 0.0;
+#pragma unroll
+      for (int q0 = 0; q0 < PMAX; q0 += VN) {
+        if (q0 + VN - 1 < k) continue;
+        T vv[VN];
+        Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
+#pragma unroll
+        for (int e = 0; e < VN; ++e) {
+          a[j][q0 + e] -= tw * vv[e];
+          const double x = (double)a[j][q0 + e];
+          s2 += q0 + e > k ? x * x : 0.0;
+        }
+      }
+      nr[j] = s2;
+    }
+    r = k + 1;
+  }
+  if (r < P) {
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      if (!src[j]) continue;
+      T* dst = const_cast<T*>(src[j]);
+#pragma unroll
+      for (int q = 0; q < PMAX; ++q)
+        if (q < r) dst[q * sstr[j]] = (kel[j] >= 0 && q > kel[j]) ? T(0) : a[j][q];
+    }
+    if (tid == 0) rank[d.cluster] = r;
+  }
+}
+
 // ---------------------------------------------------------------- apply
 // Rows of a work vector are owned by lane (row % 64) for the whole kernel, so
 // a wavefront needs no barrier between reflectors.
@@ -1580,6 +1784,50 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, in
   check_launch("k_sparsify");
 }
 
+// Register CPQR capacity: P <= PMAX and the interface's column bound mmax <=
+// SP_NT * CPT, with PMAX * CPT * sizeof(T) / 4 <= 192 registers per thread.
+int sparsify_reg_cpt(int eb, int pmax, int mmax) {
+  const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
+  if (pmax > 64 || (eb == 8 && pclass == 64)) return 0;
+  const int cpt = (mmax + SP_NT - 1) / SP_NT;
+  const int cap = 192 / (pclass * eb / 4);
+  return cpt <= std::min(cap, 4) ? std::max(cpt, 1) : 0;
+}
+
+template <typename T>
+void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps, int pmax,
+                         int mmax, int max_nb, hipStream_t s) {
+  if (n <= 0) return;
+  const int cpt = sparsify_reg_cpt(sizeof(T), pmax, mmax);
+  if (cpt == 0) throw Error(SPAQR_EINVAL, "interface too large for the register CPQR");
+  const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
+  constexpr int NW = SP_NT / 64;
+  const size_t lds = (size_t)(2 * NW + 1) * pclass * sizeof(T) + (2 * NW + 2) * sizeof(double) +
+                     (size_t)(2 * NW + max_nb + 1) * sizeof(int);
+#define SPAQR_SPR(PM, CP)                                                                                \
+  if (pclass == PM && cpt == CP) {                                                                      \
+    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, pool, rank, \
+                       eps, max_nb);                                                                    \
+    check_launch("k_cpqr_reg");                                                                         \
+    return;                                                                                             \
+  }
+  SPAQR_SPR(16, 1)
+  SPAQR_SPR(16, 2)
+  SPAQR_SPR(16, 3)
+  SPAQR_SPR(16, 4)
+  SPAQR_SPR(32, 1)
+  SPAQR_SPR(32, 2)
+  SPAQR_SPR(32, 3)
+  if constexpr (sizeof(T) == 4) {
+    SPAQR_SPR(32, 4)
+    SPAQR_SPR(64, 1)
+    SPAQR_SPR(64, 2)
+    SPAQR_SPR(64, 3)
+  }
+#undef SPAQR_SPR
+  throw Error(SPAQR_EINVAL, "unsupported register CPQR shape");
+}
+
 static constexpr size_t kApplyLds = 64 * 1024;
 
 int apply_rhs_block(int max_rows, int nrhs) {
@@ -1677,6 +1925,8 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
                                    hipStream_t);                                                     \
   template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
                                          size_t, hipStream_t);                                       \
+  template void launch_sparsify_reg<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, int, \
+                                       hipStream_t);                                                 \
   template void launch_front_fwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_bwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_iface_fwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \

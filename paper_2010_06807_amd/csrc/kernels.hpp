@@ -127,6 +127,12 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, in
                      int max_p, int max_nb, hipStream_t s);
 // Interfaces of at most 64 unknowns; pmax = the largest P in the launch,
 // max_c_elems = the largest P x m of the launch (C is staged in LDS when it fits).
+// Register-resident CPQR (see k_cpqr_reg): columns per thread needed for
+// interfaces of at most pmax unknowns and mmax columns, or 0 if they do not fit.
+int sparsify_reg_cpt(int elem_bytes, int pmax, int mmax);
+template <typename T>
+void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps, int pmax,
+                         int mmax, int max_nb, hipStream_t s);
 template <typename T>
 void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
                            int pmax, int max_nb, size_t max_c_elems, hipStream_t s);
