@@ -97,12 +97,6 @@ void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, i
 
 namespace {
 
-struct Job {
-  std::vector<int64_t> ptr{0};
-  template <typename T>
-  void close(std::vector<CopyTile<T>>& tiles) { ptr.push_back((int64_t)tiles.size()); }
-};
-
 template <typename T>
 class Engine final : public EngineBase {
  public:
@@ -322,7 +316,6 @@ void Engine<T>::stage(int k) {
   ap.jb = jbf;
   for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
     std::vector<CopyTile<T>> g, sc;
-    Job gj, sj;
     std::vector<QRDesc<T>> qd;
     double qr_flops = 0.0, qr_bytes = 0.0;
     for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
@@ -351,8 +344,6 @@ void Engine<T>::stage(int k) {
         }
         ro += size_[i];
       }
-      gj.close(g);
-      sj.close(sc);
       if (n > 0) {
         qd.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag, fm[f], n, nc, 0});
         const double mm = fm[f], nn = n, kk = nc - n;
@@ -360,23 +351,19 @@ void Engine<T>::stage(int k) {
         qr_bytes += 2.0 * mm * nc * sizeof(T);
       }
     }
-    const int64_t njobs = (int64_t)gj.ptr.size() - 1;
     CopyTile<T>* dg = up.upload(work_, g, s_);
-    int64_t* dgj = up.upload(work_, gj.ptr, s_);
-    launch_copy<T>(dg, dgj, dg ? njobs : 0, s_);
+    launch_copy<T>(dg, (int64_t)g.size(), s_);
     QRDesc<T>* dq = up.upload(work_, qd, s_);
     {
       ProfScope ps("front_qr", s_, qr_flops, qr_bytes);
       launch_qr<T>(dq, (int64_t)qd.size(), jbf, max_m, s_);
     }
     CopyTile<T>* ds = up.upload(work_, sc, s_);
-    int64_t* dsj = up.upload(work_, sj.ptr, s_);
-    launch_copy<T>(ds, dsj, ds ? njobs : 0, s_);
+    launch_copy<T>(ds, (int64_t)sc.size(), s_);
   }
   // pack factors column-major for the apply and build the apply descriptors
   {
     std::vector<CopyTile<T>> pk;
-    Job pj;
     std::vector<ApFront<T>> af;
     std::vector<int32_t> rs, cs;
     std::vector<int64_t> rs_off, cs_off;
@@ -392,7 +379,6 @@ void Engine<T>::stage(int k) {
         T* Wf = W + ws_off[f];
         pk.push_back({Wf, VR + vr_off[f], m, n, nc, m, 1, 0});
         if (nc > n) pk.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, nc, n, 1, 0});
-        pj.close(pk);
         std::vector<int32_t> rows{F.cluster};
         rows.insert(rows.end(), F.n1.begin(), F.n1.end());
         rs_off.push_back((int64_t)rs.size());
@@ -422,8 +408,7 @@ void Engine<T>::stage(int k) {
       ap.fwd_flops.push_back(ffl);
     }
     CopyTile<T>* dp = up.upload(work_, pk, s_);
-    int64_t* dpj = up.upload(work_, pj.ptr, s_);
-    launch_copy<T>(dp, dpj, dp ? (int64_t)pj.ptr.size() - 1 : 0, s_);
+    launch_copy<T>(dp, (int64_t)pk.size(), s_);
     int32_t* drs = up.upload(persist_, rs, s_);
     int32_t* dcs = up.upload(persist_, cs, s_);
     for (size_t t = 0; t < af.size(); ++t) {
@@ -472,7 +457,6 @@ void Engine<T>::stage(int k) {
     launch_fill<int>(FLAGS, ni, 0, s_);
     {
       std::vector<CopyTile<T>> g, pk;
-      Job gj, pj;
       std::vector<QRDesc<T>> qd;
       std::vector<ScaleFac<T>> fac(ni);
       for (int64_t t = 0; t < ni; ++t) {
@@ -482,14 +466,11 @@ void Engine<T>::stage(int k) {
         T* src = blk(p, p);
         SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
         g.push_back({src, SW + u_off[t], P, P, P, P, 0, 0});
-        gj.close(g);
         qd.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, P, P, P, 0});
         pk.push_back({SW + u_off[t], VRU + u_off[t], P, P, P, P, 1, 0});
-        pj.close(pk);
       }
       CopyTile<T>* dg = up.upload(work_, g, s_);
-      int64_t* dgj = up.upload(work_, gj.ptr, s_);
-      launch_copy<T>(dg, dgj, dg ? (int64_t)gj.ptr.size() - 1 : 0, s_);
+      launch_copy<T>(dg, (int64_t)g.size(), s_);
       QRDesc<T>* dq = up.upload(work_, qd, s_);
       {
         double fl = 0.0, by = 0.0;
@@ -501,8 +482,7 @@ void Engine<T>::stage(int k) {
         launch_qr<T>(dq, (int64_t)qd.size(), jbs, max_p, s_);
       }
       CopyTile<T>* dp = up.upload(work_, pk, s_);
-      int64_t* dpj = up.upload(work_, pj.ptr, s_);
-      launch_copy<T>(dp, dpj, dp ? (int64_t)pj.ptr.size() - 1 : 0, s_);
+      launch_copy<T>(dp, (int64_t)pk.size(), s_);
       ScaleFac<T>* dfac = up.upload(persist_, fac, s_);
       std::vector<ScaleBlk> sb;
       for (int64_t i = 0; i < nclu; ++i)
@@ -725,10 +705,10 @@ void Engine<T>::merge(int k) {
   DevArena& pa = pools_[(k - 1) & 1];
   pa.reset();
   T* pool2 = pa.alloc_n<T>(std::max<int64_t>(1, boff2.back()), s_);
-  // one job per new block: zero fill, then the child blocks
-  std::vector<int64_t> cnt(s2.all.size() + 1, 0);
-  std::vector<int64_t> tgt;
-  std::vector<CopyTile<T>> ctile;
+  // the new pool starts at zero (absent sub-blocks), then every child block
+  // lands in its own sub-block of the parent block: disjoint destinations
+  launch_fill<T>(pool2, boff2.back(), T(0), s_);
+  std::vector<CopyTile<T>> tiles;
   for (int64_t i = 0; i < ss.nclu; ++i)
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
       const int32_t j = ss.post.col[u];
@@ -737,32 +717,11 @@ void Engine<T>::merge(int k) {
       const int64_t B = s2.all.find(P, Q);
       SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
       const int64_t b = ss.all.find((int32_t)i, j);
-      ctile.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Q] + off[j], rank[i],
-                       rank[j], size_[j], size2[Q], 0, 0});
-      tgt.push_back(B);
-      cnt[B + 1]++;
+      tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Q] + off[j], rank[i], rank[j],
+                       size_[j], size2[Q], 0, 0});
     }
-  std::vector<CopyTile<T>> tiles;
-  Job jobs;
-  {
-    std::vector<int64_t> start(s2.all.size() + 1, 0);
-    for (int64_t B = 0; B < s2.all.size(); ++B) start[B + 1] = start[B] + cnt[B + 1];
-    std::vector<int64_t> order(ctile.size());
-    std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (size_t t = 0; t < ctile.size(); ++t) order[pos[tgt[t]]++] = (int64_t)t;
-    tiles.reserve(ctile.size() + s2.all.size());
-    for (int64_t i = 0; i < n2; ++i)
-      for (int64_t t = s2.all.rowptr[i]; t < s2.all.rowptr[i + 1]; ++t) {
-        const int32_t j = s2.all.col[t];
-        if (size2[i] == 0 || size2[j] == 0) continue;
-        tiles.push_back({nullptr, pool2 + boff2[t], size2[i], size2[j], 0, size2[j], 0, 0});
-        for (int64_t q = start[t]; q < start[t + 1]; ++q) tiles.push_back(ctile[order[q]]);
-        jobs.close(tiles);
-      }
-  }
   CopyTile<T>* dt = up.upload(work_, tiles, s_);
-  int64_t* dj = up.upload(work_, jobs.ptr, s_);
-  launch_copy<T>(dt, dj, dt ? (int64_t)jobs.ptr.size() - 1 : 0, s_);
+  launch_copy<T>(dt, (int64_t)tiles.size(), s_);
   pool_ = pool2;
   boff_.swap(boff2);
   size_.swap(size2);

@@ -180,25 +180,34 @@ __device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* 
 }
 
 // ---------------------------------------------------------------- kernels
+// One workgroup per tile.  Lanes run along the contiguous side of the
+// destination (columns for a plain copy, rows for a transpose), rounded up to
+// a power of two of at most 64, and the remaining threads take successive
+// rows (columns), so indices come from shifts and masks only.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles,
-                                             const int64_t* __restrict__ jobptr) {
-  const int64_t b = jobptr[blockIdx.x], e = jobptr[blockIdx.x + 1];
-  for (int64_t t = b; t < e; ++t) {
-    const CopyTile<T> c = tiles[t];
-    const int64_t tot = (int64_t)c.rows * c.cols;
-    if (c.mode == 0) {
-      for (int64_t q = threadIdx.x; q < tot; q += NT) {
-        const int64_t r = q / c.cols, cc = q - r * c.cols;
-        c.dst[r * c.ldd + cc] = c.src ? c.src[r * c.lds + cc] : T(0);
-      }
-    } else {
-      for (int64_t q = threadIdx.x; q < tot; q += NT) {
-        const int64_t cc = q / c.rows, r = q - cc * c.rows;
-        c.dst[cc * c.ldd + r] = c.src[r * c.lds + cc];
+__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles) {
+  const CopyTile<T> c = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int inner = c.mode == 0 ? c.cols : c.rows, outer = c.mode == 0 ? c.rows : c.cols;
+  int lg = 0;
+  while ((1 << lg) < inner && lg < 6) ++lg;
+  const int iw = 1 << lg, ostep = NT >> lg, ti = tid & (iw - 1), to = tid >> lg;
+  if (c.mode == 0) {
+    for (int r = to; r < outer; r += ostep) {
+      T* d = c.dst + (int64_t)r * c.ldd;
+      if (c.src) {
+        const T* sr = c.src + (int64_t)r * c.lds;
+        for (int q = ti; q < inner; q += iw) d[q] = sr[q];
+      } else {
+        for (int q = ti; q < inner; q += iw) d[q] = T(0);
       }
     }
-    __syncthreads();
+  } else {
+    for (int cc = to; cc < outer; cc += ostep) {
+      T* d = c.dst + (int64_t)cc * c.ldd;
+      const T* sc = c.src + cc;
+      for (int r = ti; r < inner; r += iw) d[r] = sc[(int64_t)r * c.lds];
+    }
   }
 }
 
@@ -1006,26 +1015,28 @@ __global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restr
 }
 
 // Register-resident partial CPQR of C = [A_np^T | A_pn] (Sections 2.5, 2.6;
-// rank rule of Section 4).  Thread tid owns columns tid + SP_NT j, j < CPT,
-// held in registers for the whole factorization (P <= PMAX rows each).
-// Columns are never moved: each carries its current position, and the swap of
-// the pivot with the column at position k only exchanges positions, so the
-// pivot choice (largest FP64 norm, ties to the lowest current position) is
-// the same as with physical swaps.  Per step: local and wavefront argmax,
-// the winning lane of each wavefront stages its column in LDS, one barrier,
-// the workgroup winner is picked, wavefront 0 forms the Householder vector
-// (dlarfg convention) in LDS, a second barrier, then every live column is
-// updated and its tail norm recomputed in FP64.  The pivot column keeps R
-// above the diagonal and becomes beta at row k.  After r steps rows 0..r-1 of
-// every column are W = Q^T C (zero below the diagonal of pivot columns) and
-// go back to the blocks.
+// rank rule of Section 4).  Thread tid owns columns tid + SP_NT j: j < CPT in
+// registers and, if LC, one more column in LDS (element q at
+// q * SP_NT + tid, conflict-free), for the whole factorization (P <= PMAX
+// rows each).  Columns are never moved: each carries its current position,
+// and the swap of the pivot with the column at position k only exchanges
+// positions, so the pivot choice (largest FP64 norm, ties to the lowest
+// current position) is the same as with physical swaps.  Per step: local and
+// wavefront argmax, the winning lane of each wavefront stages its column in
+// LDS, one barrier, the workgroup winner is picked, wavefront 0 forms the
+// Householder vector (dlarfg convention) in LDS, a second barrier, then every
+// live column is updated and its tail norm recomputed in FP64.  The pivot
+// column keeps R above the diagonal and becomes beta at row k.  After r steps
+// rows 0..r-1 of every column are W = Q^T C (zero below the diagonal of pivot
+// columns) and go back to the blocks.
 constexpr int SP_NT = 512;
 
-template <typename T, int PMAX, int CPT>
+template <typename T, int PMAX, int CPT, int LC>
 __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict__ descs,
                                                     const SpNbr* __restrict__ nbrs, T* pool, int* rank,
                                                     double eps, int max_nb) {
   constexpr int NW = SP_NT / 64;
+  constexpr int NC = CPT + LC;
   constexpr int VN = Vec16<T>::N;
   const SpDesc<T> d = descs[blockIdx.x];
   const int P = d.P, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1033,7 +1044,8 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
   extern __shared__ __align__(16) unsigned char smem[];
   T* slot = reinterpret_cast<T*>(smem);                       // 2 x NW x PMAX
   T* vbuf = slot + 2 * NW * PMAX;                             // PMAX
-  double* cb = reinterpret_cast<double*>(vbuf + PMAX);        // 2 x NW candidate norms
+  T* lcol = vbuf + PMAX;                                      // LC ? PMAX x SP_NT : 0
+  double* cb = reinterpret_cast<double*>(lcol + LC * PMAX * SP_NT);  // 2 x NW candidate norms
   double* hs = cb + 2 * NW;                                   // tau, beta
   int* cpz = reinterpret_cast<int*>(hs + 2);                  // 2 x NW candidate positions
   int* off = cpz + 2 * NW;                                    // max_nb + 1
@@ -1049,33 +1061,35 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
   }
   __syncthreads();
   const int m = off[nnb];
+  // column c of C: row ai of block (i, p) for a row neighbour, column ai of
+  // block (p, j) for a column neighbour
+  auto col_src = [&](int c, int64_t& str) -> T* {
+    int b = 0;
+    while (off[b + 1] <= c) ++b;
+    const int ai = c - off[b];
+    T* blk = pool + nb[b].blk;
+    const int64_t ld = nb[b].ld;
+    str = b < d.nrow ? 1 : ld;
+    return b < d.nrow ? blk + (int64_t)ai * ld : blk + ai;
+  };
   T a[CPT][PMAX];
-  double nr[CPT];
-  int pos[CPT], kel[CPT];
-  const T* src[CPT];
-  int64_t sstr[CPT];
+  double nr[NC];
+  int pos[NC], kel[NC];
+  T* lc = lcol + tid;  // the LDS column, stride SP_NT
 #pragma unroll
-  for (int j = 0; j < CPT; ++j) {
+  for (int j = 0; j < NC; ++j) {
     const int c = tid + SP_NT * j;
     pos[j] = c;
     kel[j] = -1;
-    src[j] = nullptr;
-    sstr[j] = 0;
-    if (c < m) {
-      int b = 0;
-      while (off[b + 1] <= c) ++b;
-      const int ai = c - off[b];
-      const T* blk = pool + nb[b].blk;
-      const int64_t ld = nb[b].ld;
-      // row neighbour: row ai of block (i, p); column neighbour: column ai of (p, j)
-      src[j] = b < d.nrow ? blk + (int64_t)ai * ld : blk + ai;
-      sstr[j] = b < d.nrow ? 1 : ld;
-    }
+    int64_t str = 0;
+    const T* src = c < m ? col_src(c, str) : nullptr;
     double s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < PMAX; ++q) {
-      a[j][q] = (src[j] && q < P) ? src[j][q * sstr[j]] : T(0);
-      s2 += (double)a[j][q] * (double)a[j][q];
+      const T x = (src && q < P) ? src[q * str] : T(0);
+      if (j < CPT) a[j < CPT ? j : 0][q] = x;
+      else lc[q * SP_NT] = x;
+      s2 += (double)x * (double)x;
     }
     nr[j] = c < m ? s2 : -1.0;
   }
@@ -1087,7 +1101,7 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
     double best = -1.0;
     int bp = 0x7fffffff;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j)
+    for (int j = 0; j < NC; ++j)
       if (kel[j] < 0 && nr[j] >= 0.0 && (nr[j] > best || (nr[j] == best && pos[j] < bp))) {
         best = nr[j];
         bp = pos[j];
@@ -1109,9 +1123,16 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
       merge(xshfl<1>(wb), xshfl<1>(wp));
     }
     if (wp != 0x7fffffff && bp == wp) {
+      T* sl = slot + (buf * NW + wv) * PMAX;
 #pragma unroll
-      for (int j = 0; j < CPT; ++j)
-        if (kel[j] < 0 && pos[j] == wp) lds_store_row<T, PMAX>(slot + (buf * NW + wv) * PMAX, a[j]);
+      for (int j = 0; j < NC; ++j)
+        if (kel[j] < 0 && pos[j] == wp) {
+          if (j < CPT) {
+            lds_store_row<T, PMAX>(sl, a[j < CPT ? j : 0]);
+          } else {
+            for (int q = 0; q < PMAX; ++q) sl[q] = lc[q * SP_NT];
+          }
+        }
     }
     if (lane == 0) {
       cb[buf * NW + wv] = wb;
@@ -1155,38 +1176,53 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
     __syncthreads();
     const T tau = (T)hs[0], beta = (T)hs[1];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
+    for (int j = 0; j < NC; ++j) {
       if (kel[j] >= 0 || nr[j] < 0.0) continue;
       if (pos[j] == gp) {
         // the pivot: beta at row k, reflector storage below (not part of W)
         kel[j] = k;
         pos[j] = k;
+        if (j < CPT) {
 #pragma unroll
-        for (int q = 0; q < PMAX; ++q) a[j][q] = q == k ? beta : a[j][q];
+          for (int q = 0; q < PMAX; ++q) a[j < CPT ? j : 0][q] = q == k ? beta : a[j < CPT ? j : 0][q];
+        } else {
+          lc[k * SP_NT] = beta;
+        }
         continue;
       }
       if (pos[j] == k) pos[j] = gp;
       T w = T(0);
-#pragma unroll
-      for (int q0 = 0; q0 < PMAX; q0 += VN) {
-        if (q0 + VN - 1 < k) continue;  // v is zero there (uniform)
-        T vv[VN];
-        Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
-#pragma unroll
-        for (int e = 0; e < VN; ++e) w += vv[e] * a[j][q0 + e];
-      }
-      const T tw = tau * w;
       double s2 = 0.0;
+      if (j < CPT) {
+        T(&aj)[PMAX] = a[j < CPT ? j : 0];
 #pragma unroll
-      for (int q0 = 0; q0 < PMAX; q0 += VN) {
-        if (q0 + VN - 1 < k) continue;
-        T vv[VN];
-        Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
+        for (int q0 = 0; q0 < PMAX; q0 += VN) {
+          if (q0 + VN - 1 < k) continue;  // v is zero there (uniform)
+          T vv[VN];
+          Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
 #pragma unroll
-        for (int e = 0; e < VN; ++e) {
-          a[j][q0 + e] -= tw * vv[e];
-          const double x = (double)a[j][q0 + e];
-          s2 += q0 + e > k ? x * x : 0.0;
+          for (int e = 0; e < VN; ++e) w += vv[e] * aj[q0 + e];
+        }
+        const T tw = tau * w;
+#pragma unroll
+        for (int q0 = 0; q0 < PMAX; q0 += VN) {
+          if (q0 + VN - 1 < k) continue;
+          T vv[VN];
+          Vec16<T>::put(*reinterpret_cast<const typename Vec16<T>::type*>(vbuf + q0), vv);
+#pragma unroll
+          for (int e = 0; e < VN; ++e) {
+            aj[q0 + e] -= tw * vv[e];
+            const double x = (double)aj[q0 + e];
+            s2 += q0 + e > k ? x * x : 0.0;
+          }
+        }
+      } else {
+        for (int q = k; q < PMAX; ++q) w += vbuf[q] * lc[q * SP_NT];
+        const T tw = tau * w;
+        for (int q = k; q < PMAX; ++q) {
+          const T x = lc[q * SP_NT] - tw * vbuf[q];
+          lc[q * SP_NT] = x;
+          if (q > k) s2 += (double)x * (double)x;
         }
       }
       nr[j] = s2;
@@ -1195,12 +1231,17 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
   }
   if (r < P) {
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      if (!src[j]) continue;
-      T* dst = const_cast<T*>(src[j]);
+    for (int j = 0; j < NC; ++j) {
+      const int c = tid + SP_NT * j;
+      if (c >= m) continue;
+      int64_t str = 0;
+      T* dst = col_src(c, str);
 #pragma unroll
       for (int q = 0; q < PMAX; ++q)
-        if (q < r) dst[q * sstr[j]] = (kel[j] >= 0 && q > kel[j]) ? T(0) : a[j][q];
+        if (q < r) {
+          const T x = j < CPT ? a[j < CPT ? j : 0][q] : lc[q * SP_NT];
+          dst[q * str] = (kel[j] >= 0 && q > kel[j]) ? T(0) : x;
+        }
     }
     if (tid == 0) rank[d.cluster] = r;
   }
@@ -1591,9 +1632,9 @@ static void check_launch(const char* what) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_copy(const CopyTile<T>* tiles, const int64_t* jobptr, int64_t njobs, hipStream_t s) {
-  if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)njobs), dim3(NT), 0, s, tiles, jobptr);
+void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s) {
+  if (ntiles <= 0) return;
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
   check_launch("k_copy");
 }
 
@@ -1784,45 +1825,64 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, in
   check_launch("k_sparsify");
 }
 
-// Register CPQR capacity: P <= PMAX and the interface's column bound mmax <=
-// SP_NT * CPT, with PMAX * CPT * sizeof(T) / 4 <= 192 registers per thread.
+// Register CPQR capacity: P <= PMAX, and the interface's column bound mmax <=
+// SP_NT * (CPT + LC) with PMAX * CPT * sizeof(T) / 4 <= 192 registers per
+// thread and at most one more column per thread in LDS.  Returns CPT + LC, or
+// 0 when the interface does not fit.
+static int sp_reg_cap(int eb, int pclass) { return std::min(4, 192 / (pclass * eb / 4)); }
+
 int sparsify_reg_cpt(int eb, int pmax, int mmax) {
   const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
   if (pmax > 64 || (eb == 8 && pclass == 64)) return 0;
-  const int cpt = (mmax + SP_NT - 1) / SP_NT;
-  const int cap = 192 / (pclass * eb / 4);
-  return cpt <= std::min(cap, 4) ? std::max(cpt, 1) : 0;
+  const int cpt = std::max(1, (mmax + SP_NT - 1) / SP_NT);
+  return cpt <= sp_reg_cap(eb, pclass) + 1 ? cpt : 0;
 }
 
 template <typename T>
 void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps, int pmax,
                          int mmax, int max_nb, hipStream_t s) {
   if (n <= 0) return;
-  const int cpt = sparsify_reg_cpt(sizeof(T), pmax, mmax);
-  if (cpt == 0) throw Error(SPAQR_EINVAL, "interface too large for the register CPQR");
+  const int tot = sparsify_reg_cpt(sizeof(T), pmax, mmax);
+  if (tot == 0) throw Error(SPAQR_EINVAL, "interface too large for the register CPQR");
   const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
+  const int cap = sp_reg_cap(sizeof(T), pclass);
+  const int cpt = std::min(tot, cap), lc = tot - cpt;
   constexpr int NW = SP_NT / 64;
-  const size_t lds = (size_t)(2 * NW + 1) * pclass * sizeof(T) + (2 * NW + 2) * sizeof(double) +
+  const size_t lds = (size_t)(2 * NW + 1 + lc * SP_NT) * pclass * sizeof(T) + (2 * NW + 2) * sizeof(double) +
                      (size_t)(2 * NW + max_nb + 1) * sizeof(int);
-#define SPAQR_SPR(PM, CP)                                                                                \
-  if (pclass == PM && cpt == CP) {                                                                      \
-    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, pool, rank, \
-                       eps, max_nb);                                                                    \
-    check_launch("k_cpqr_reg");                                                                         \
-    return;                                                                                             \
+#define SPAQR_SPR(PM, CP, L)                                                                              \
+  if (pclass == PM && cpt == CP && lc == L) {                                                            \
+    allow_lds(reinterpret_cast<const void*>(&k_cpqr_reg<T, PM, CP, L>), lds, "k_cpqr_reg");             \
+    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, pool, rank, \
+                       eps, max_nb);                                                                     \
+    check_launch("k_cpqr_reg");                                                                          \
+    return;                                                                                              \
   }
-  SPAQR_SPR(16, 1)
-  SPAQR_SPR(16, 2)
-  SPAQR_SPR(16, 3)
-  SPAQR_SPR(16, 4)
-  SPAQR_SPR(32, 1)
-  SPAQR_SPR(32, 2)
-  SPAQR_SPR(32, 3)
   if constexpr (sizeof(T) == 4) {
-    SPAQR_SPR(32, 4)
-    SPAQR_SPR(64, 1)
-    SPAQR_SPR(64, 2)
-    SPAQR_SPR(64, 3)
+    SPAQR_SPR(16, 1, 0)
+    SPAQR_SPR(16, 2, 0)
+    SPAQR_SPR(16, 3, 0)
+    SPAQR_SPR(16, 4, 0)
+    SPAQR_SPR(16, 4, 1)
+    SPAQR_SPR(32, 1, 0)
+    SPAQR_SPR(32, 2, 0)
+    SPAQR_SPR(32, 3, 0)
+    SPAQR_SPR(32, 4, 0)
+    SPAQR_SPR(32, 4, 1)
+    SPAQR_SPR(64, 1, 0)
+    SPAQR_SPR(64, 2, 0)
+    SPAQR_SPR(64, 3, 0)
+    SPAQR_SPR(64, 3, 1)
+  } else {
+    SPAQR_SPR(16, 1, 0)
+    SPAQR_SPR(16, 2, 0)
+    SPAQR_SPR(16, 3, 0)
+    SPAQR_SPR(16, 4, 0)
+    SPAQR_SPR(16, 4, 1)
+    SPAQR_SPR(32, 1, 0)
+    SPAQR_SPR(32, 2, 0)
+    SPAQR_SPR(32, 3, 0)
+    SPAQR_SPR(32, 3, 1)
   }
 #undef SPAQR_SPR
   throw Error(SPAQR_EINVAL, "unsupported register CPQR shape");
@@ -1914,7 +1974,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
 }
 
 #define SPAQR_INST(T)                                                                                  \
-  template void launch_copy<T>(const CopyTile<T>*, const int64_t*, int64_t, hipStream_t);            \
+  template void launch_copy<T>(const CopyTile<T>*, int64_t, hipStream_t);                             \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void launch_scatter_nz<T>(T*, const int64_t*, const double*, int64_t, hipStream_t);       \
   template void launch_scatter_scaled<T>(T*, const int64_t*, const double*, const int32_t*, const double*, \

@@ -11,7 +11,8 @@ namespace spaqr {
 
 // One rectangular copy: dst[r*ldd + c] = src[r*lds + c] (mode 0), or the
 // transpose dst[c*ldd + r] = src[r*lds + c] (mode 1); src == nullptr zero-fills
-// (mode 0 only).  Tiles of one job run in order, one workgroup per job.
+// (mode 0 only).  The tiles of one launch must have disjoint destinations:
+// they run concurrently, one workgroup per tile.
 template <typename T>
 struct CopyTile {
   const T* src;
@@ -104,7 +105,7 @@ struct ApIface {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_copy(const CopyTile<T>* tiles, const int64_t* jobptr, int64_t njobs, hipStream_t s);
+void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T>
