@@ -619,17 +619,33 @@ void Engine<T>::stage(int k) {
                            max_pc, max_nb, s_);
       }
     }
-    // apply descriptors of the interfaces
+    // apply descriptors of the interfaces; those of at most 64 unknowns get
+    // their dense forward and backward operators
     std::vector<ApIface<T>> ai;
     std::vector<int32_t> sl;
     std::vector<int64_t> sl_off;
+    int64_t dense_elems = 0;
+    for (int64_t t = 0; t < ni; ++t) {
+      const int64_t P = size_[rem[t]];
+      if (P > 0 && P <= 64) dense_elems += P * P;
+    }
+    T* MF = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
+    T* MB = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
+    int64_t dense_off = 0;
     for (int64_t t = 0; t < ni; ++t) {
       const int32_t p = rem[t], P = size_[p];
       if (P == 0) continue;
       sl_off.push_back((int64_t)sl.size());
       slot_list(std::vector<int32_t>{p}, sl);
+      T* mf = nullptr;
+      T* mb = nullptr;
+      if (P <= 64) {
+        mf = MF + dense_off;
+        mb = MB + dense_off;
+        dense_off += (int64_t)P * P;
+      }
       ai.push_back({VRU + u_off[t], TAUU + p_off[t], VQ + u_off[t], TAUQ + p_off[t], nullptr, d_rank + p,
-                    FLAGS + t, P, 0});
+                    FLAGS + t, mf, mb, P, 0});
       ap.max_p = std::max(ap.max_p, (int)P);
     }
     int32_t* dsl = up.upload(persist_, sl, s_);
@@ -639,6 +655,7 @@ void Engine<T>::stage(int k) {
     for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= 64 ? 1 : 0;
     ap.ifaces = up.upload(persist_, ai, s_);
     ap.nifaces = (int64_t)ai.size();
+    launch_iface_form<T>(ap.ifaces, ap.nifaces_small, s_);
     st_.s.interfaces_sparsified += (int64_t)ai.size();
   }
 
@@ -751,7 +768,7 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
     }
     if (a.nifaces) {
       ProfScope ps("apply_iface_fwd", s_, a.if_fwd_flops * nrhs, a.if_fwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_small<T>(a.ifaces, a.nifaces_small, false, xh, N, nrhs, s_);
+      launch_iface_dense<T>(a.ifaces, a.nifaces_small, false, xh, N, nrhs, s_);
       launch_iface_fwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s_);
     }
   }
@@ -759,7 +776,7 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
     const StageApply<T>& a = ap_[k];
     if (a.nifaces) {
       ProfScope ps("apply_iface_bwd", s_, a.if_bwd_flops * nrhs, a.if_bwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_small<T>(a.ifaces, a.nifaces_small, true, xh, N, nrhs, s_);
+      launch_iface_dense<T>(a.ifaces, a.nifaces_small, true, xh, N, nrhs, s_);
       launch_iface_bwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s_);
     }
     if (a.nfronts) {

@@ -1510,6 +1510,215 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
     for (int r = tid; r < n; r += 256) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = ys[r + c * n];
 }
 
+// Forward apply of a front, x[rows] <- H_s^T x[rows], with the rows held in
+// registers: thread tid owns front rows tid + 256 q, q < Q (m <= 256 Q), and
+// NR right-hand sides.  Per JB-reflector panel: w = V^T x is reduced over the
+// workgroup in one reduce-scatter and one barrier, lane t of each wavefront
+// forms u_t = (T^T w)_t from column t of the compact-WY factor, the u values
+// are broadcast with readlane, and x <- x - V u.  The next panel's V is
+// loaded while the current one is applied.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+template <typename T, int JB, int Q, int NR>
+__global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __restrict__ ds, double* x, int64_t ldx,
+                                                         int nrhs) {
+  constexpr int K = JB * NR;  // reduced values per panel, at most 64
+  constexpr int SH = 6 - ilog2c(K);
+  static_assert(K <= 64, "panel values exceed one wavefront");
+  __shared__ __align__(16) double red[2][4][K];
+  const ApFront<T> d = ds[blockIdx.x];
+  const int c0 = blockIdx.y * NR;
+  if (d.n == 0 || c0 >= nrhs) return;
+  const int nc = min(NR, nrhs - c0);
+  const int m = d.m, n = d.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double xr[Q][NR];
+  int sl[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = tid + 256 * q;
+    sl[q] = r < m ? d.rows[r] : 0;
+#pragma unroll
+    for (int c = 0; c < NR; ++c) xr[q][c] = (r < m && c < nc) ? x[sl[q] + (int64_t)(c0 + c) * ldx] : 0.0;
+  }
+  T vc[Q][JB], vn[Q][JB];
+  auto load_v = [&](int p0, T (&v)[Q][JB]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int r = tid + 256 * q, rr = r - p0;
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const bool col = p0 + t < n && r < m;
+        v[q][t] = (col && rr > t) ? d.vr[r + (int64_t)(p0 + t) * m] : ((col && rr == t) ? T(1) : T(0));
+      }
+    }
+  };
+  load_v(0, vc);
+  for (int p0 = 0, it = 0; p0 < n; p0 += JB, ++it) {
+    if (p0 + JB < n) load_v(p0 + JB, vn);
+    const int buf = it & 1;
+    // column `lane` of this panel's T (upper triangular, column-major JB x JB)
+    T tcol[JB];
+    const T* tp = d.tpan + (int64_t)(p0 / JB) * JB * JB;
+#pragma unroll
+    for (int q = 0; q < JB; ++q) tcol[q] = (lane < JB && q <= lane) ? tp[q + lane * JB] : T(0);
+    double w[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) w[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int t = 0; t < JB; ++t)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) w[t * NR + c] += (double)vc[q][t] * xr[q][c];
+    const double s = wave_reduce_scatter<double, K>(w);
+    if ((lane & ((1 << SH) - 1)) == 0) red[buf][wv][lane >> SH] = s;
+    __syncthreads();
+    double wt[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) wt[i] = red[buf][0][i] + red[buf][1][i] + red[buf][2][i] + red[buf][3][i];
+    double u[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) {
+      u[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < JB; ++q) u[c] += (double)tcol[q] * wt[q * NR + c];
+    }
+    double ua[K];
+#pragma unroll
+    for (int t = 0; t < JB; ++t)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) ua[t * NR + c] = readlane_d(u[c], t);
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < JB; ++t) acc += (double)vc[q][t] * ua[t * NR + c];
+        xr[q][c] -= acc;
+      }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int t = 0; t < JB; ++t) vc[q][t] = vn[q][t];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int r = tid + 256 * q;
+    if (r < m)
+#pragma unroll
+      for (int c = 0; c < NR; ++c)
+        if (c < nc) x[sl[q] + (int64_t)(c0 + c) * ldx] = xr[q][c];
+  }
+}
+
+// Dense operators of an interface of at most 64 unknowns (Section 2.8): the
+// forward sweep applies U_pp^T (scaling reflectors in order) then Q_pp^T
+// (sparsification reflectors in order); the backward sweep applies Q_pp
+// (reverse order) then R_pp^{-1}.  mf = Q^T U^T and mb = R^{-1} Q are formed
+// by applying those steps to the identity, held in LDS in FP64.  Four adjacent
+// lanes share a column (rows part, part + 4, ...): reflector dots reduce with
+// two lane swaps and no barrier, since a column is only touched by its own
+// lanes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_iface_form(const ApIface<T>* __restrict__ ds) {
+  constexpr int LX = 65;  // padded row stride of X: the four row parts fall in distinct banks
+  extern __shared__ __align__(16) unsigned char smem[];
+  const ApIface<T> d = ds[blockIdx.x];
+  const int P = d.P, tid = threadIdx.x, j = tid >> 2, part = tid & 3;
+  if (P == 0 || *d.flag != 0) return;
+  const int r = *d.rank;
+  const bool hasq = r < P;
+  double* X = reinterpret_cast<double*>(smem);  // 64 x LX
+  double* tu = X + 64 * LX;                     // 64
+  double* tq = tu + 64;                         // 64
+  T* vu = reinterpret_cast<T*>(tq + 64);        // P x P column-major
+  T* vq = vu + P * P;                           // P x P column-major (first r columns)
+  for (int e = tid; e < P * P; e += 256) {
+    vu[e] = d.vru[e];
+    vq[e] = (hasq && e < P * r) ? d.vq[e] : T(0);
+  }
+  if (tid < P) {
+    tu[tid] = (double)d.tauu[tid];
+    tq[tid] = (hasq && tid < r) ? (double)d.tauq[tid] : 0.0;
+  }
+  auto ident = [&]() {
+    if (j < P)
+      for (int q = part; q < P; q += 4) X[q * LX + j] = q == j ? 1.0 : 0.0;
+  };
+  // X[:, j] <- (I - tau v v^T) X[:, j]; v = column t of V with rows < t zero
+  // and, if unit, an implicit 1 at row t
+  auto reflect = [&](const T* V, int t, double tau, bool unit) {
+    double sdot = 0.0;
+    if (j < P)
+      for (int q = part; q < P; q += 4) {
+        const double v = q < t ? 0.0 : ((q == t && unit) ? 1.0 : (double)V[q + t * P]);
+        sdot += v * X[q * LX + j];
+      }
+    sdot += xshfl<1>(sdot);
+    sdot += xshfl<2>(sdot);
+    sdot *= tau;
+    if (j < P)
+      for (int q = part; q < P; q += 4) {
+        const double v = q < t ? 0.0 : ((q == t && unit) ? 1.0 : (double)V[q + t * P]);
+        X[q * LX + j] -= sdot * v;
+      }
+  };
+  auto store = [&](T* M) {
+    if (j < P)
+      for (int q = part; q < P; q += 4) M[q + (int64_t)j * P] = (T)X[q * LX + j];
+  };
+  ident();
+  __syncthreads();
+  for (int t = 0; t < P; ++t) reflect(vu, t, tu[t], true);
+  if (hasq)
+    for (int t = 0; t < r; ++t) reflect(vq, t, tq[t], false);
+  store(d.mf);
+  ident();
+  if (hasq)
+    for (int t = r - 1; t >= 0; --t) reflect(vq, t, tq[t], false);
+  // R^{-1}: R upper triangular on and above the diagonal of vu
+  for (int c = P - 1; c >= 0; --c) {
+    if (j < P) {
+      const double xc = X[c * LX + j] / (double)vu[c + c * P];
+      if ((c & 3) == part) X[c * LX + j] = xc;
+      for (int q = part; q < c; q += 4) X[q * LX + j] -= (double)vu[q + c * P] * xc;
+    }
+  }
+  store(d.mb);
+}
+
+// x_p <- M x_p for interfaces of at most 64 unknowns, one wavefront per
+// interface (four per workgroup): lane i forms row i, x_j broadcast by
+// readlane.  Unscaled interfaces are left alone.
+template <typename T>
+__global__ void __launch_bounds__(256) k_ap_iface_dense(const ApIface<T>* __restrict__ ds, int64_t n, int backward,
+                                                       double* x, int64_t ldx, int nrhs) {
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (it >= n) return;
+  const ApIface<T> d = ds[it];
+  const int P = d.P, lane = threadIdx.x & 63;
+  if (P == 0 || *d.flag != 0) return;
+  const T* M = backward ? d.mb : d.mf;
+  T mrow[64];
+#pragma unroll
+  for (int j = 0; j < 64; ++j) mrow[j] = (lane < P && j < P) ? M[lane + (int64_t)j * P] : T(0);
+  const int sl = lane < P ? d.slots[lane] : 0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double xl = lane < P ? x[sl + (int64_t)c * ldx] : 0.0;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < 64; ++j)
+      if (j < P) acc += (double)mrow[j] * readlane_d(xl, j);
+    if (lane < P) x[sl + (int64_t)c * ldx] = acc;
+  }
+}
+
 // Interfaces of at most 64 unknowns, one wavefront each, row `lane` of the
 // interface in one lane's registers: forward x_p <- Q^T U^T x_p, backward
 // x_p <- R_pp^{-1} Q x_p.  The lane's row of the U/R factor and of the Q
@@ -1920,6 +2129,33 @@ template <typename T>
 void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, double* x, int64_t ldx, int nrhs,
                          hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
+  if ((jb == 16 || jb == 8) && max_rows <= 1024) {
+    const int q = max_rows <= 256 ? 1 : (max_rows <= 512 ? 2 : 4);
+    const int nr = nrhs == 1 ? 1 : (nrhs == 2 || jb == 16 ? 2 : 4);
+    const dim3 grid((unsigned)n, (unsigned)((nrhs + nr - 1) / nr));
+#define SPAQR_FWR(J, Q, R)                                                                             \
+  if (jb == J && q == Q && nr == R) {                                                                  \
+    hipLaunchKernelGGL((k_ap_front_fwd_reg<T, J, Q, R>), grid, dim3(256), 0, s, d, x, ldx, nrhs);      \
+    check_launch("k_ap_front_fwd_reg");                                                               \
+    return;                                                                                           \
+  }
+    SPAQR_FWR(16, 1, 1)
+    SPAQR_FWR(16, 2, 1)
+    SPAQR_FWR(16, 4, 1)
+    SPAQR_FWR(16, 1, 2)
+    SPAQR_FWR(16, 2, 2)
+    SPAQR_FWR(16, 4, 2)
+    SPAQR_FWR(8, 1, 1)
+    SPAQR_FWR(8, 2, 1)
+    SPAQR_FWR(8, 4, 1)
+    SPAQR_FWR(8, 1, 2)
+    SPAQR_FWR(8, 2, 2)
+    SPAQR_FWR(8, 4, 2)
+    SPAQR_FWR(8, 1, 4)
+    SPAQR_FWR(8, 2, 4)
+    SPAQR_FWR(8, 4, 4)
+#undef SPAQR_FWR
+  }
   const int rb = apply_rhs_block(max_rows + 1, nrhs);
   if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
   const size_t lds = ((size_t)max_rows * rb + 6 * 32) * sizeof(double);
@@ -1949,6 +2185,24 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
   hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
                      d, x, ldx, nrhs, rb);
   check_launch("k_ap_front_bwd_reg");
+}
+
+template <typename T>
+void launch_iface_form(const ApIface<T>* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = (64 * 65 + 128) * sizeof(double) + 2 * 64 * 64 * sizeof(T);
+  allow_lds(reinterpret_cast<const void*>(&k_iface_form<T>), lds, "k_iface_form");
+  hipLaunchKernelGGL(k_iface_form<T>, dim3((unsigned)n), dim3(256), lds, s, d);
+  check_launch("k_iface_form");
+}
+
+template <typename T>
+void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
+                        hipStream_t s) {
+  if (n <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_ap_iface_dense<T>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, n, backward ? 1 : 0, x,
+                     ldx, nrhs);
+  check_launch("k_ap_iface_dense");
 }
 
 template <typename T>
@@ -1993,7 +2247,9 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_iface_bwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_fwd_wy<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_bwd_reg<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
-  template void launch_iface_small<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t);
+  template void launch_iface_small<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t); \
+  template void launch_iface_form<T>(const ApIface<T>*, int64_t, hipStream_t);                       \
+  template void launch_iface_dense<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t);
 SPAQR_INST(float)
 SPAQR_INST(double)
 #undef SPAQR_INST

@@ -100,6 +100,8 @@ struct ApIface {
   const int32_t* slots;  // P slots
   const int* rank;       // r (== P when nothing was dropped)
   const int* flag;       // nonzero: interface was not scaled
+  T* mf;                 // P x P column-major Q^T U^T (P <= 64), formed after the stage
+  T* mb;                 // P x P column-major R_pp^{-1} Q
   int32_t P, pad;
 };
 
@@ -152,6 +154,13 @@ template <typename T>
 void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
                           hipStream_t s);
 // Interfaces of at most 64 unknowns: one wavefront, one row per lane.
+// Dense interface operators (P <= 64): mf = Q^T U^T and mb = R_pp^{-1} Q,
+// one thread per column; then the apply multiplies by them.
+template <typename T>
+void launch_iface_form(const ApIface<T>* d, int64_t n, hipStream_t s);
+template <typename T>
+void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
+                        hipStream_t s);
 template <typename T>
 void launch_iface_small(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
                         hipStream_t s);
