@@ -36,10 +36,10 @@ PEAK = {
     "alu64": (78.6, "TFLOP/s"),
 }
 # bound of each kernel: HBM-bound data movement / apply, or vector-ALU
-# arithmetic (these kernels run on the VALU, not on MFMA)
+# arithmetic (the factorization kernels run on the VALU, not on MFMA; the
+# CPQR's work is counted from the ranks read back after each stage)
 KERNEL_BOUND = {
-    "front_qr": "alu", "scale_qr": "alu", "scale_blocks": "alu",
-    "sparsify": "hbm", "copy": "hbm",
+    "front_qr": "alu", "scale_qr": "alu", "scale_blocks": "alu", "sparsify": "alu",
     "apply_front_fwd": "hbm", "apply_front_bwd": "hbm", "apply_iface_fwd": "hbm", "apply_iface_bwd": "hbm",
 }
 
@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline (default: the slowest)")
+    ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
+                    help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
+                         "directory of this script's run and exit")
     return ap.parse_args()
 
 
@@ -64,6 +67,40 @@ def pct(v, q):
         return None
     i = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
     return v[i]
+
+
+# kernel symbols behind each profiler group (FP32 instantiations)
+GROUP_KERNELS = {
+    "sparsify": ("k_cpqr_reg<float", "k_sparsify_small<float", "k_sparsify<float"),
+    "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
+    "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
+    "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),
+}
+
+
+def rocprof_summary(d, fp32_steps):
+    """Markdown summary of a rocprofv3 CSV directory: the kernel table and,
+    per profiler group, the total kernel time per FP32 step."""
+    import csv
+    import glob
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(d, "*_kernel_stats.csv"))[0])))
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    out = ["| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:30]:
+        name = r["Name"].replace("spaqr::(anonymous namespace)::", "").replace("void ", "")
+        name = name.split("(spaqr::")[0].split("(double")[0].split("(long")[0]
+        out.append(f"| `{name[:70]}` | {int(r['Calls'])} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / tot:.1f} |")
+    out.append("")
+    out.append(f"Per FP32 step ({fp32_steps} FP32 steps in the run):")
+    out.append("")
+    out.append("| group | kernels | ms per step |")
+    out.append("|---|---|---|")
+    for g, pats in GROUP_KERNELS.items():
+        ms = sum(float(r["TotalDurationNs"]) for r in stats if any(p in r["Name"] for p in pats)) / 1e6
+        n = sum(int(r["Calls"]) for r in stats if any(p in r["Name"] for p in pats))
+        out.append(f"| {g} | {n} launches | {ms / fp32_steps:.3f} |")
+    return "\n".join(out)
 
 
 def cpu_baseline(prob, eps, tol):
@@ -90,6 +127,10 @@ def cpu_baseline(prob, eps, tol):
 
 def main():
     args = parse()
+    if args.rocprof_summary:
+        # FP32 steps of a run: 2 survey steps, the warmup and the timed steps
+        print(rocprof_summary(args.rocprof_summary, 2 + args.warmup + args.steps))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
               "(the nested-dissection tree would shard over GPUs, see the design notes)", file=sys.stderr)
@@ -173,6 +214,8 @@ def main():
     roof = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": None,
             "launches": prof["launches"], "avg_launch_us": 1e3 * prof["total_ms"] / max(1, prof["launches"]),
+            "ms_per_step": prof["total_ms"] / (args.steps + args.warmup),
+            "work_per_step": (prof["bytes"] if bound == "hbm" else prof["flops"]) / (args.steps + args.warmup),
             "survey_ms": {n: round(v["total_ms"], 3) for n, v in survey.items() if v["launches"]}}
 
     out = {

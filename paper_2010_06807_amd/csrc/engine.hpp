@@ -29,14 +29,15 @@ class DevArena {
   void* alloc(size_t bytes, hipStream_t s);
   template <typename X>
   X* alloc_n(size_t n, hipStream_t s) { return static_cast<X*>(alloc(n * sizeof(X), s)); }
-  void reset() { cur_ = 0; off_ = 0; }
+  void reset() { cur_ = 0; off_ = 0; used_ = 0; }
   void release(hipStream_t s);
   size_t reserved() const;
+  size_t used() const { return used_; }  // bytes handed out since the last reset
 
  private:
   struct Chunk { char* p; size_t size; };
   std::vector<Chunk> chunks_;
-  size_t chunk_, cur_ = 0, off_ = 0;
+  size_t chunk_, cur_ = 0, off_ = 0, used_ = 0;
   hipStream_t stream_ = nullptr;  // stream of the allocations (frees are ordered on it)
 };
 

@@ -38,6 +38,7 @@ DevArena::~DevArena() {
 void* DevArena::alloc(size_t bytes, hipStream_t s) {
   bytes = (bytes + 255) & ~size_t(255);
   if (bytes == 0) bytes = 256;
+  used_ += bytes;
   while (cur_ < chunks_.size()) {
     if (off_ + bytes <= chunks_[cur_].size) {
       void* p = chunks_[cur_].p + off_;
@@ -256,7 +257,7 @@ void Engine<T>::factor(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   }
   for (int k = L; k >= 1; --k) stage(k);
   SPAQR_HIP(hipStreamSynchronize(s_));
-  st_.s.factor_bytes = (int64_t)persist_.reserved();
+  st_.s.factor_bytes = (int64_t)persist_.used();
   pools_[0].release(s_);
   pools_[1].release(s_);
   work_.release(s_);
@@ -608,9 +609,7 @@ void Engine<T>::stage(int k) {
       SpDesc<T>* dsd = up.upload(work_, sd, s_);
       SpNbr* dnb = up.upload(work_, nb, s_);
       {
-        double by = 0.0;
-        for (const SpDesc<T>& q : sd) by += 2.0 * q.P * (double)q.mmax * sizeof(T);
-        ProfScope ps("sparsify", s_, 0.0, by);
+        ProfScope ps("sparsify", s_, 0.0, 0.0);  // work added after the rank readback
         for (const auto& g : groups)
           launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, pool_, d_rank, o_.eps, (int)g[2], (int)g[3], max_nb,
                                  s_);
@@ -675,17 +674,40 @@ void Engine<T>::stage(int k) {
   st_.stage_sizes[k].assign(pinned_ints_, pinned_ints_ + nclu);
   if (ss.sparsify) {
     const double eb = sizeof(T);
-    for (int32_t p : ss.remaining) {
+    std::vector<int32_t> iidx(nclu, -1);
+    for (size_t t = 0; t < ss.ifaces.size(); ++t) iidx[ss.ifaces[t].cluster] = (int32_t)t;
+    double sp_flops = 0.0, sp_bytes = 0.0;
+    for (size_t t = 0; t < ss.ifaces.size(); ++t) {
+      const IfaceSym& I = ss.ifaces[t];
+      const int32_t p = I.cluster;
       const double P = size_[p], r = pinned_ints_[p];
       if (P == 0) continue;
-      // U below the diagonal + tau, then the kept reflectors of Q
-      const double qel = r < P ? (P * r - r * (r - 1) / 2) : 0.0;
-      ap.if_fwd_fac_bytes += (P * (P - 1) / 2 + P + qel + (r < P ? r : 0)) * eb + 4 * P;
-      ap.if_bwd_fac_bytes += (P * (P + 1) / 2 + qel + (r < P ? r : 0)) * eb + 4 * P;
+      if (P <= 64) {
+        // dense operators Q^T U^T and R^{-1} Q
+        ap.if_fwd_fac_bytes += P * P * eb + 4 * P;
+        ap.if_bwd_fac_bytes += P * P * eb + 4 * P;
+        ap.if_fwd_flops += 2 * P * P;
+        ap.if_bwd_flops += 2 * P * P;
+      } else {
+        // U below the diagonal + tau, then the kept reflectors of Q
+        const double qel = r < P ? (P * r - r * (r - 1) / 2) : 0.0;
+        ap.if_fwd_fac_bytes += (P * (P - 1) / 2 + P + qel + (r < P ? r : 0)) * eb + 4 * P;
+        ap.if_bwd_fac_bytes += (P * (P + 1) / 2 + qel + (r < P ? r : 0)) * eb + 4 * P;
+        ap.if_fwd_flops += 4 * (P * (P + 1) / 2 + qel);
+        ap.if_bwd_flops += P * P + 4 * qel;
+      }
       ap.if_vec_bytes += 16 * P;
-      ap.if_fwd_flops += 4 * (P * (P + 1) / 2 + qel);
-      ap.if_bwd_flops += P * P + 4 * qel;
+      // CPQR work: the columns of C are the neighbours' current unknowns (a
+      // neighbour of an earlier colour already has its new rank); per step k,
+      // dot, update and FP64 tail norm of every live column, plus the reflector
+      double m = 0.0;
+      for (int32_t q : I.rowN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
+      for (int32_t q : I.colN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
+      sp_flops += 2.0 * P * m;
+      for (int k = 0; k < (int)r; ++k) sp_flops += (m - k - 1) * (6.0 * (P - k) - 2.0) + 3.0 * (P - k);
+      sp_bytes += (P * m + (r < P ? r * m : 0.0)) * eb;
     }
+    prof_add("sparsify", sp_flops, sp_bytes);
   }
   if (k > 1) merge(k);
 }

@@ -45,6 +45,14 @@ void prof_record(const char* name, hipStream_t, hipEvent_t a, hipEvent_t b, doub
   if (r.ev.size() > 4096) resolve(r);
 }
 
+void prof_add(const char* name, double flops, double bytes) {
+  if (!prof_wants(name)) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec& r = g_tab[name];
+  r.flops += flops;
+  r.bytes += bytes;
+}
+
 }  // namespace spaqr
 
 extern "C" {

@@ -10,6 +10,8 @@ namespace spaqr {
 bool prof_on();
 bool prof_wants(const char* name);
 void prof_record(const char* name, hipStream_t s, hipEvent_t a, hipEvent_t b, double flops, double bytes);
+// Work known only after the launches ran (e.g. from ranks read back later).
+void prof_add(const char* name, double flops, double bytes);
 
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s, double flops, double bytes)
