@@ -95,12 +95,26 @@ class EngineBase {
   virtual int64_t n() const = 0;
   virtual int opt_restart() const = 0;
   virtual int opt_maxit() const = 0;
+  virtual int stages_left() const = 0;  // 0 once the factorization is complete (or failed)
+  virtual int precision() const = 0;    // 32 or 64
+  virtual int error() const = 0;        // SPAQR_OK, or the status of a failed factorization
+  virtual const char* error_message() const = 0;
 };
 
 // A: host CSR (the pattern is always read; values only when Ad is null).
 // Ad: optional device copies of the same CSR, used instead of uploading.
 std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
                                         const spaqr_opts& o, hipStream_t stream);
+// The same, with the stages left to factor_stage_batch (A is read during the
+// call only).
+std::unique_ptr<EngineBase> make_engine_deferred(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                                 const spaqr_opts& o, hipStream_t stream);
+// Advances every factorization in es by one stage, concatenating their launch
+// lists phase by phase (cross-request batching); es share stream s.
+struct BatchDriver;
+BatchDriver* batch_driver_new();
+void batch_driver_free(BatchDriver* d);
+void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s);
 
 // FGMRES on the device (gmres.hip).
 int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,

@@ -19,6 +19,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <string>
 
 #include "engine.hpp"
 #include "profile.hpp"
@@ -98,6 +100,48 @@ void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, i
 
 namespace {
 
+struct ZeroOp {
+  void* p;
+  int64_t bytes;
+};
+
+// One stage of one factorization as host-side launch lists.  Every device
+// pointer in them is absolute, so the lists of several factorizations (each
+// at its own stage) concatenate into one launch per phase.
+template <typename T>
+struct StagePlan {
+  std::vector<ZeroOp> zero;  // runs first
+  struct FrontColour {
+    std::vector<CopyTile<T>> gather, scatter;
+    std::vector<QRDesc<T>> qr;
+    int max_m = 1;
+    double flops = 0.0, bytes = 0.0;
+  };
+  std::vector<FrontColour> fronts;
+  int jbf = 16;
+  std::vector<CopyTile<T>> pack;
+  // block-diagonal scaling
+  std::vector<CopyTile<T>> sgather, spack;
+  std::vector<QRDesc<T>> sqr;
+  int max_p = 1, jbs = 16;
+  std::vector<ScaleFac<T>> fac;
+  std::vector<ScaleBlk<T>> sblk;  // fi, fj index fac
+  // sparsification, colour by colour; SpDesc::nb indexes nb of its colour
+  struct SpColour {
+    std::vector<SpDesc<T>> sd;
+    std::vector<SpNbr> nb;
+  };
+  std::vector<SpColour> sp;
+  // interfaces whose dense apply operators are formed after the stage
+  std::vector<ApIface<T>> form;
+};
+
+template <typename T>
+struct MergePlan {
+  std::vector<ZeroOp> zero;
+  std::vector<CopyTile<T>> tiles;
+};
+
 template <typename T>
 class Engine final : public EngineBase {
  public:
@@ -108,14 +152,13 @@ class Engine final : public EngineBase {
     st_.s.levels = S.L;
     st_.s.precision = sizeof(T) == 4 ? 32 : 64;
     st_.stage_sizes.assign(S.L + 1, {});
-    const double t0 = now_ms();
+    t0_ = now_ms();
     try {
-      factor(A, Ad);
+      begin(A, Ad);
     } catch (...) {
       (void)hipStreamSynchronize(s_);
       throw;
     }
-    st_.s.ms_factor = now_ms() - t0;
   }
   ~Engine() override {
     dev_free(apply_ws_, s_);
@@ -132,17 +175,36 @@ class Engine final : public EngineBase {
   int64_t n() const override { return S_.n; }
   int opt_restart() const override { return o_.restart; }
   int opt_maxit() const override { return o_.maxit; }
+  int stages_left() const override { return k_; }
+  int precision() const override { return sizeof(T) == 4 ? 32 : 64; }
+  int error() const override { return err_; }
+  const char* error_message() const override { return err_msg_.c_str(); }
+
+  // stage k_ as launch lists, in three parts that the driver launches in
+  // turn: fronts (and the factor packing), scaling, sparsification (each
+  // allocates this factorization's buffers for its part)
+  void plan_fronts(StagePlan<T>& p);
+  void plan_scale(StagePlan<T>& p);
+  void plan_sparsify(StagePlan<T>& p);
+  // after the launches: copy the ranks and error flags to the host
+  void readback();
+  // after the stream synchronized: sizes and accounting of stage k_, the
+  // merge to stage k_ - 1 as launch lists, then k_ <- k_ - 1
+  void finish(MergePlan<T>& mp);
 
  private:
-  void factor(const spaqr_csr* A, const spaqr_csr_dev* Ad);
-  void stage(int k);
-  void merge(int k);
+  void begin(const spaqr_csr* A, const spaqr_csr_dev* Ad);
+  void complete();
   void begin_stage();
 
   const Symbolic& S_;
   spaqr_opts o_;
   hipStream_t s_;
   Stats st_;
+  double t0_ = 0.0;
+  int k_ = 0;  // next stage to run (L .. 1); 0 when the factorization is complete
+  int err_ = SPAQR_OK;  // a failed factorization stops with k_ = 0 and this status
+  std::string err_msg_;
   DevArena persist_{size_t(64) << 20};
   DevArena work_{size_t(64) << 20};
   DevArena pools_[2] = {DevArena(size_t(64) << 20), DevArena(size_t(64) << 20)};
@@ -151,6 +213,15 @@ class Engine final : public EngineBase {
   PinnedChunk pinned_;            // rank readback buffer
   int* pinned_ints_ = nullptr;
   int* d_zcol_ = nullptr;  // set by the device column-norm kernel for a zero column
+  int* d_flag_ = nullptr;  // zero R_ss diagonal in a front of the current stage
+  int* d_rank_ = nullptr;  // current cluster sizes of the current stage
+  // interfaces of the current stage: index by cluster, offsets and buffers
+  struct IfaceBufs {
+    std::vector<int32_t> fidx;
+    std::vector<int64_t> u_off, p_off, t_off;
+    T *vru = nullptr, *tauu = nullptr, *tpan = nullptr, *vq = nullptr, *tauq = nullptr;
+    int* flags = nullptr;
+  } ib_;
 
   // current stage state
   T* pool_ = nullptr;
@@ -178,7 +249,7 @@ void Engine<T>::begin_stage() {
 }
 
 template <typename T>
-void Engine<T>::factor(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
+void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   const int L = S_.L;
   const int64_t n = S_.n, nnz = S_.nnz;
   const Ordering& ord = S_.ord;
@@ -255,17 +326,24 @@ void Engine<T>::factor(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
     int64_t* d_dst = up.upload(work_, dst, s_);
     launch_scatter_scaled<T>(pool_, d_dst, d_val_, d_col_, d_dc_, nnz, s_);
   }
-  for (int k = L; k >= 1; --k) stage(k);
+  k_ = L;
+  pinned_ints_ = nullptr;
+}
+
+template <typename T>
+void Engine<T>::complete() {
   SPAQR_HIP(hipStreamSynchronize(s_));
   st_.s.factor_bytes = (int64_t)persist_.used();
   pools_[0].release(s_);
   pools_[1].release(s_);
   work_.release(s_);
   SPAQR_HIP(hipStreamSynchronize(s_));
+  st_.s.ms_factor = now_ms() - t0_;
 }
 
 template <typename T>
-void Engine<T>::stage(int k) {
+void Engine<T>::plan_fronts(StagePlan<T>& P) {
+  const int k = k_;
   if (k != S_.L) begin_stage();
   Stager& up = stager_[stager_cur_];
   const StageSym& ss = S_.st[k];
@@ -278,8 +356,8 @@ void Engine<T>::stage(int k) {
     const int64_t b = ss.all.find(i, j);
     return b < 0 ? nullptr : pool_ + boff_[b];
   };
-  int* d_flag = persist_.alloc_n<int>(1, s_);
-  launch_fill<int>(d_flag, 1, 0, s_);
+  d_flag_ = persist_.alloc_n<int>(1, s_);
+  P.zero.push_back({d_flag_, (int64_t)sizeof(int)});
 
   // ------------------------------------------------------------ fronts
   const int64_t nf = (int64_t)ss.fronts.size();
@@ -306,6 +384,7 @@ void Engine<T>::stage(int k) {
   }
   const int jbf = qr_panel_width(max_m, sizeof(T));
   SPAQR_REQUIRE(jbf > 0, SPAQR_ENOMEM, "front too tall for the LDS panel");
+  P.jbf = jbf;
   T* W = work_.alloc_n<T>(std::max<int64_t>(1, ws_off[nf]), s_);
   T* VR = persist_.alloc_n<T>(std::max<int64_t>(1, vr_off[nf]), s_);
   T* RSJ = persist_.alloc_n<T>(std::max<int64_t>(1, rsj_off[nf]), s_);
@@ -316,9 +395,7 @@ void Engine<T>::stage(int k) {
   T* TPF = persist_.alloc_n<T>(std::max<int64_t>(1, tp_off[nf]), s_);
   ap.jb = jbf;
   for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
-    std::vector<CopyTile<T>> g, sc;
-    std::vector<QRDesc<T>> qd;
-    double qr_flops = 0.0, qr_bytes = 0.0;
+    typename StagePlan<T>::FrontColour fc;
     for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
       const int32_t f = ss.front_order[oi];
       const FrontSym& F = ss.fronts[f];
@@ -334,11 +411,11 @@ void Engine<T>::stage(int k) {
         for (size_t b = 0; b < cols.size(); ++b) {
           const int32_t j = cols[b];
           if (size_[i] > 0 && size_[j] > 0) {
-            g.push_back({blk(i, j), Wf + (int64_t)ro * nc + co, size_[i], size_[j], size_[j], nc, 0, 0});
+            fc.gather.push_back({blk(i, j), Wf + (int64_t)ro * nc + co, size_[i], size_[j], size_[j], nc, 0, 0});
             if (a > 0 && b > 0) {
               T* dst = blk(i, j);
               SPAQR_REQUIRE(dst != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
-              sc.push_back({Wf + (int64_t)ro * nc + co, dst, size_[i], size_[j], nc, size_[j], 0, 0});
+              fc.scatter.push_back({Wf + (int64_t)ro * nc + co, dst, size_[i], size_[j], nc, size_[j], 0, 0});
             }
           }
           co += size_[j];
@@ -346,25 +423,17 @@ void Engine<T>::stage(int k) {
         ro += size_[i];
       }
       if (n > 0) {
-        qd.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag, fm[f], n, nc, 0});
+        fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, nc, 0});
+        fc.max_m = std::max(fc.max_m, fm[f]);
         const double mm = fm[f], nn = n, kk = nc - n;
-        qr_flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
-        qr_bytes += 2.0 * mm * nc * sizeof(T);
+        fc.flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
+        fc.bytes += 2.0 * mm * nc * sizeof(T);
       }
     }
-    CopyTile<T>* dg = up.upload(work_, g, s_);
-    launch_copy<T>(dg, (int64_t)g.size(), s_);
-    QRDesc<T>* dq = up.upload(work_, qd, s_);
-    {
-      ProfScope ps("front_qr", s_, qr_flops, qr_bytes);
-      launch_qr<T>(dq, (int64_t)qd.size(), jbf, max_m, s_);
-    }
-    CopyTile<T>* ds = up.upload(work_, sc, s_);
-    launch_copy<T>(ds, (int64_t)sc.size(), s_);
+    P.fronts.push_back(std::move(fc));
   }
   // pack factors column-major for the apply and build the apply descriptors
   {
-    std::vector<CopyTile<T>> pk;
     std::vector<ApFront<T>> af;
     std::vector<int32_t> rs, cs;
     std::vector<int64_t> rs_off, cs_off;
@@ -378,8 +447,8 @@ void Engine<T>::stage(int k) {
         const int32_t m = fm[f], n = fn[f], nc = fnc[f];
         if (n == 0) continue;
         T* Wf = W + ws_off[f];
-        pk.push_back({Wf, VR + vr_off[f], m, n, nc, m, 1, 0});
-        if (nc > n) pk.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, nc, n, 1, 0});
+        P.pack.push_back({Wf, VR + vr_off[f], m, n, nc, m, 1, 0});
+        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, nc, n, 1, 0});
         std::vector<int32_t> rows{F.cluster};
         rows.insert(rows.end(), F.n1.begin(), F.n1.end());
         rs_off.push_back((int64_t)rs.size());
@@ -408,8 +477,6 @@ void Engine<T>::stage(int k) {
       ap.fwd_vec_bytes.push_back(fvb);
       ap.fwd_flops.push_back(ffl);
     }
-    CopyTile<T>* dp = up.upload(work_, pk, s_);
-    launch_copy<T>(dp, (int64_t)pk.size(), s_);
     int32_t* drs = up.upload(persist_, rs, s_);
     int32_t* dcs = up.upload(persist_, cs, s_);
     for (size_t t = 0; t < af.size(); ++t) {
@@ -420,257 +487,210 @@ void Engine<T>::stage(int k) {
     ap.nfronts = (int64_t)af.size();
   }
 
-  // ------------------------------------------------ scaling + sparsification
-  int* d_rank = nullptr;
   {
     std::vector<int> r0(size_.begin(), size_.end());
     r0.push_back(0);
-    d_rank = up.upload(persist_, r0, s_);
+    d_rank_ = up.upload(persist_, r0, s_);
   }
-  if (ss.sparsify) {
-    const std::vector<int32_t>& rem = ss.remaining;
-    const int64_t ni = (int64_t)rem.size();
-    std::vector<int32_t> fidx(nclu, -1);
-    std::vector<int64_t> u_off(ni + 1, 0), t_off(ni + 1, 0), p_off(ni + 1, 0);
-    int max_p = 1;
-    for (int64_t t = 0; t < ni; ++t) {
-      fidx[rem[t]] = (int32_t)t;
-      const int64_t P = size_[rem[t]];
-      u_off[t + 1] = u_off[t] + P * P;
-      p_off[t + 1] = p_off[t] + P;
-      max_p = std::max<int>(max_p, (int)P);
-    }
-    const int jbs = qr_panel_width(max_p, sizeof(T));
-    SPAQR_REQUIRE(jbs > 0, SPAQR_ENOMEM, "interface too large for the LDS panel");
-    for (int64_t t = 0; t < ni; ++t) {
-      const int64_t P = size_[rem[t]];
-      t_off[t + 1] = t_off[t] + ((P + jbs - 1) / jbs) * jbs * jbs;
-      const double pp = P;
-      st_.s.flops_scale += 4.0 / 3.0 * pp * pp * pp;
-    }
-    T* SW = work_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
-    T* VRU = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
-    T* TAUU = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
-    T* TPAN = persist_.alloc_n<T>(std::max<int64_t>(1, t_off[ni]), s_);
-    T* VQ = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
-    T* TAUQ = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
-    int* FLAGS = persist_.alloc_n<int>(std::max<int64_t>(1, ni), s_);
-    launch_fill<int>(FLAGS, ni, 0, s_);
-    {
-      std::vector<CopyTile<T>> g, pk;
-      std::vector<QRDesc<T>> qd;
-      std::vector<ScaleFac<T>> fac(ni);
-      for (int64_t t = 0; t < ni; ++t) {
-        const int32_t p = rem[t], P = size_[p];
-        fac[t] = {VRU + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, P, 0};
-        if (P == 0) continue;
-        T* src = blk(p, p);
-        SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
-        g.push_back({src, SW + u_off[t], P, P, P, P, 0, 0});
-        qd.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, P, P, P, 0});
-        pk.push_back({SW + u_off[t], VRU + u_off[t], P, P, P, P, 1, 0});
-      }
-      CopyTile<T>* dg = up.upload(work_, g, s_);
-      launch_copy<T>(dg, (int64_t)g.size(), s_);
-      QRDesc<T>* dq = up.upload(work_, qd, s_);
-      {
-        double fl = 0.0, by = 0.0;
-        for (const QRDesc<T>& q : qd) {
-          fl += 4.0 / 3.0 * (double)q.n * q.n * q.n;
-          by += 2.0 * (double)q.n * q.n * sizeof(T);
-        }
-        ProfScope ps("scale_qr", s_, fl, by);
-        launch_qr<T>(dq, (int64_t)qd.size(), jbs, max_p, s_);
-      }
-      CopyTile<T>* dp = up.upload(work_, pk, s_);
-      launch_copy<T>(dp, (int64_t)pk.size(), s_);
-      ScaleFac<T>* dfac = up.upload(persist_, fac, s_);
-      std::vector<ScaleBlk> sb;
-      for (int64_t i = 0; i < nclu; ++i)
-        for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
-          const int32_t j = ss.post.col[u];
-          if (size_[i] == 0 || size_[j] == 0) continue;
-          const int64_t b = ss.all.find((int32_t)i, j);
-          sb.push_back({boff_[b], size_[i], size_[j], fidx[i], fidx[j]});
-          st_.s.flops_scale += 4.0 * size_[i] * size_[i] * size_[j] + (double)size_[i] * size_[j] * size_[j];
-        }
-      ScaleBlk* dsb = up.upload(work_, sb, s_);
-      {
-        double fl = 0.0, by = 0.0;
-        for (const ScaleBlk& q : sb) {
-          fl += 4.0 * q.rows * q.rows * (double)q.cols + (double)q.rows * q.cols * q.cols;
-          by += 2.0 * q.rows * (double)q.cols * sizeof(T);
-        }
-        ProfScope ps("scale_blocks", s_, fl, by);
-        launch_scale<T>(dsb, (int64_t)sb.size(), dfac, pool_, jbs, max_p, s_);
-      }
-    }
-    // sparsification, colour by colour
-    for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
-      std::vector<SpDesc<T>> sd;
-      std::vector<SpNbr> nb;
-      int64_t c_off = 0, n_off = 0;
-      std::vector<int64_t> cpos, npos;
-      int max_nb = 0, max_pc = 1;
-      for (int32_t oi = ss.iface_colour_ptr[c]; oi < ss.iface_colour_ptr[c + 1]; ++oi) {
-        const IfaceSym& I = ss.ifaces[ss.iface_order[oi]];
-        const int32_t p = I.cluster, P = size_[p];
-        if (P == 0) continue;
-        SpDesc<T> d{};
-        d.nb = (int64_t)nb.size();
-        int64_t mmax = 0;
-        for (int32_t i : I.rowN) {
-          const int64_t b = ss.all.find(i, p);
-          nb.push_back({boff_[b], i, P});
-          mmax += size_[i];
-        }
-        for (int32_t j : I.colN) {
-          const int64_t b = ss.all.find(p, j);
-          nb.push_back({boff_[b], j, size_[j]});
-          mmax += size_[j];
-        }
-        d.nrow = (int32_t)I.rowN.size();
-        d.ncol = (int32_t)I.colN.size();
-        d.cluster = p;
-        d.P = P;
-        d.mmax = (int32_t)std::max<int64_t>(1, mmax);
-        const int64_t t = fidx[p];
-        d.vq = VQ + u_off[t];
-        d.tauq = TAUQ + p_off[t];
-        d.flag = FLAGS + t;
-        cpos.push_back(0);
-        npos.push_back(0);
-        max_nb = std::max(max_nb, d.nrow + d.ncol);
-        max_pc = std::max<int>(max_pc, P);
-        sd.push_back(d);
-        const double pp = P, mm = (double)mmax;
-        st_.s.flops_sparsify += 4.0 * pp * mm * std::min(pp, mm);
-      }
-      if (sd.empty()) continue;
-      // interfaces whose columns fit in registers: register CPQR, one launch
-      // per (row class, columns per thread) when one shape does not fit all
-      std::stable_partition(sd.begin(), sd.end(),
-                            [](const SpDesc<T>& q) { return sparsify_reg_cpt(sizeof(T), q.P, q.mmax) > 0; });
-      int64_t nreg = 0;
-      int preg = 1, mreg = 1;
-      for (const SpDesc<T>& q : sd)
-        if (sparsify_reg_cpt(sizeof(T), q.P, q.mmax) > 0) {
-          ++nreg;
-          preg = std::max<int>(preg, q.P);
-          mreg = std::max<int>(mreg, q.mmax);
-        }
-      std::vector<std::array<int64_t, 4>> groups;  // begin, end, pmax, mmax
-      if (nreg > 0 && sparsify_reg_cpt(sizeof(T), preg, mreg) > 0) {
-        groups.push_back({0, nreg, preg, mreg});
-      } else if (nreg > 0) {
-        auto pcls = [](int P) { return P <= 16 ? 0 : (P <= 32 ? 1 : 2); };
-        std::stable_sort(sd.begin(), sd.begin() + nreg,
-                         [&](const SpDesc<T>& x, const SpDesc<T>& y) { return pcls(x.P) < pcls(y.P); });
-        for (int64_t b = 0; b < nreg;) {
-          int64_t e = b;
-          int pm = 1, mm = 1;
-          while (e < nreg && pcls(sd[e].P) == pcls(sd[b].P)) {
-            pm = std::max<int>(pm, sd[e].P);
-            mm = std::max<int>(mm, sd[e].mmax);
-            ++e;
-          }
-          groups.push_back({b, e, pm, mm});
-          b = e;
-        }
-      }
-      for (int64_t t = nreg; t < (int64_t)sd.size(); ++t) {
-        const int64_t P = sd[t].P;
-        cpos[t] = c_off;
-        npos[t] = n_off;
-        c_off += (P <= 64 ? 65 : P) * sd[t].mmax;
-        n_off += sd[t].mmax;
-      }
-      T* CW = work_.alloc_n<T>(std::max<int64_t>(1, c_off), s_);
-      double* NW = work_.alloc_n<double>(std::max<int64_t>(1, n_off), s_);
-      int32_t* IW = work_.alloc_n<int32_t>(std::max<int64_t>(1, 2 * n_off), s_);
-      for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
-        sd[t].C = CW + cpos[t];
-        sd[t].nrm = NW + npos[t];
-        sd[t].perm = IW + 2 * npos[t];
-      }
-      // the rest: small interfaces to the LDS kernel (FP32: P <= 64, FP64: P <= 32), then generic
-      constexpr int kSmallP = sizeof(T) == 4 ? 64 : 32;
-      std::stable_partition(sd.begin() + nreg, sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
-      int64_t nsmall = 0;
-      int pmax_small = 1, mmax_small = 1;
-      for (size_t t = (size_t)nreg; t < sd.size(); ++t)
-        if (sd[t].P <= kSmallP) {
-          ++nsmall;
-          pmax_small = std::max<int>(pmax_small, sd[t].P);
-          mmax_small = std::max<int>(mmax_small, sd[t].mmax);
-        }
-      const int pclass = pmax_small <= 16 ? 16 : (pmax_small <= 32 ? 32 : 64);
-      const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
-      SpDesc<T>* dsd = up.upload(work_, sd, s_);
-      SpNbr* dnb = up.upload(work_, nb, s_);
-      {
-        ProfScope ps("sparsify", s_, 0.0, 0.0);  // work added after the rank readback
-        for (const auto& g : groups)
-          launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, pool_, d_rank, o_.eps, (int)g[2], (int)g[3], max_nb,
-                                 s_);
-        launch_sparsify_small<T>(dsd + nreg, nsmall, dnb, pool_, d_rank, o_.eps, pmax_small, max_nb, cmax_small, s_);
-        launch_sparsify<T>(dsd + nreg + nsmall, (int64_t)sd.size() - nreg - nsmall, dnb, pool_, d_rank, o_.eps,
-                           max_pc, max_nb, s_);
-      }
-    }
-    // apply descriptors of the interfaces; those of at most 64 unknowns get
-    // their dense forward and backward operators
-    std::vector<ApIface<T>> ai;
-    std::vector<int32_t> sl;
-    std::vector<int64_t> sl_off;
-    int64_t dense_elems = 0;
-    for (int64_t t = 0; t < ni; ++t) {
-      const int64_t P = size_[rem[t]];
-      if (P > 0 && P <= 64) dense_elems += P * P;
-    }
-    T* MF = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
-    T* MB = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
-    int64_t dense_off = 0;
-    for (int64_t t = 0; t < ni; ++t) {
-      const int32_t p = rem[t], P = size_[p];
-      if (P == 0) continue;
-      sl_off.push_back((int64_t)sl.size());
-      slot_list(std::vector<int32_t>{p}, sl);
-      T* mf = nullptr;
-      T* mb = nullptr;
-      if (P <= 64) {
-        mf = MF + dense_off;
-        mb = MB + dense_off;
-        dense_off += (int64_t)P * P;
-      }
-      ai.push_back({VRU + u_off[t], TAUU + p_off[t], VQ + u_off[t], TAUQ + p_off[t], nullptr, d_rank + p,
-                    FLAGS + t, mf, mb, P, 0});
-      ap.max_p = std::max(ap.max_p, (int)P);
-    }
-    int32_t* dsl = up.upload(persist_, sl, s_);
-    for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
-    // interfaces of at most 64 unknowns first (one-wavefront apply kernel)
-    std::stable_partition(ai.begin(), ai.end(), [](const ApIface<T>& q) { return q.P <= 64; });
-    for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= 64 ? 1 : 0;
-    ap.ifaces = up.upload(persist_, ai, s_);
-    ap.nifaces = (int64_t)ai.size();
-    launch_iface_form<T>(ap.ifaces, ap.nifaces_small, s_);
-    st_.s.interfaces_sparsified += (int64_t)ai.size();
-  }
+}
 
-  // ------------------------------------------------ rank readback
+template <typename T>
+void Engine<T>::plan_scale(StagePlan<T>& P) {
+  const int k = k_;
+  const StageSym& ss = S_.st[k];
+  const int64_t nclu = ss.nclu;
+  if (!ss.sparsify) return;
+  auto blk = [&](int32_t i, int32_t j) -> T* {
+    const int64_t b = ss.all.find(i, j);
+    return b < 0 ? nullptr : pool_ + boff_[b];
+  };
+  const std::vector<int32_t>& rem = ss.remaining;
+  const int64_t ni = (int64_t)rem.size();
+  std::vector<int32_t>& fidx = ib_.fidx;
+  std::vector<int64_t>& u_off = ib_.u_off;
+  std::vector<int64_t>& t_off = ib_.t_off;
+  std::vector<int64_t>& p_off = ib_.p_off;
+  fidx.assign(nclu, -1);
+  u_off.assign(ni + 1, 0);
+  t_off.assign(ni + 1, 0);
+  p_off.assign(ni + 1, 0);
+  int max_p = 1;
+  for (int64_t t = 0; t < ni; ++t) {
+    fidx[rem[t]] = (int32_t)t;
+    const int64_t Pn = size_[rem[t]];
+    u_off[t + 1] = u_off[t] + Pn * Pn;
+    p_off[t + 1] = p_off[t] + Pn;
+    max_p = std::max<int>(max_p, (int)Pn);
+  }
+  const int jbs = qr_panel_width(max_p, sizeof(T));
+  SPAQR_REQUIRE(jbs > 0, SPAQR_ENOMEM, "interface too large for the LDS panel");
+  P.jbs = jbs;
+  P.max_p = max_p;
+  for (int64_t t = 0; t < ni; ++t) {
+    const int64_t Pn = size_[rem[t]];
+    t_off[t + 1] = t_off[t] + ((Pn + jbs - 1) / jbs) * jbs * jbs;
+    const double pp = Pn;
+    st_.s.flops_scale += 4.0 / 3.0 * pp * pp * pp;
+  }
+  T* SW = work_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+  T* VRU = ib_.vru = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+  T* TAUU = ib_.tauu = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
+  T* TPAN = ib_.tpan = persist_.alloc_n<T>(std::max<int64_t>(1, t_off[ni]), s_);
+  ib_.vq = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+  ib_.tauq = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
+  int* FLAGS = ib_.flags = persist_.alloc_n<int>(std::max<int64_t>(1, ni), s_);
+  P.zero.push_back({FLAGS, (int64_t)std::max<int64_t>(1, ni) * (int64_t)sizeof(int)});
+  P.fac.resize(ni);
+  for (int64_t t = 0; t < ni; ++t) {
+    const int32_t p = rem[t], Pn = size_[p];
+    P.fac[t] = {VRU + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, 0};
+    if (Pn == 0) continue;
+    T* src = blk(p, p);
+    SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
+    P.sgather.push_back({src, SW + u_off[t], Pn, Pn, Pn, Pn, 0, 0});
+    P.sqr.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, 0});
+    P.spack.push_back({SW + u_off[t], VRU + u_off[t], Pn, Pn, Pn, Pn, 1, 0});
+  }
+  for (int64_t i = 0; i < nclu; ++i)
+    for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
+      const int32_t j = ss.post.col[u];
+      if (size_[i] == 0 || size_[j] == 0) continue;
+      const int64_t b = ss.all.find((int32_t)i, j);
+      P.sblk.push_back({pool_ + boff_[b], size_[i], size_[j], fidx[i], fidx[j]});
+      st_.s.flops_scale += 4.0 * size_[i] * size_[i] * size_[j] + (double)size_[i] * size_[j] * size_[j];
+    }
+}
+
+template <typename T>
+void Engine<T>::plan_sparsify(StagePlan<T>& P) {
+  const int k = k_;
+  const StageSym& ss = S_.st[k];
+  if (!ss.sparsify) return;
+  Stager& up = stager_[stager_cur_];
+  StageApply<T>& ap = ap_[k];
+  auto slot_list = [&](const std::vector<int32_t>& cl, std::vector<int32_t>& out) {
+    for (int32_t c : cl) out.insert(out.end(), slots_.begin() + slot_ptr_[c], slots_.begin() + slot_ptr_[c + 1]);
+  };
+  const std::vector<int32_t>& rem = ss.remaining;
+  const int64_t ni = (int64_t)rem.size();
+  const std::vector<int32_t>& fidx = ib_.fidx;
+  const std::vector<int64_t>& u_off = ib_.u_off;
+  const std::vector<int64_t>& p_off = ib_.p_off;
+  T* VRU = ib_.vru;
+  T* TAUU = ib_.tauu;
+  T* VQ = ib_.vq;
+  T* TAUQ = ib_.tauq;
+  int* FLAGS = ib_.flags;
+  // sparsification, colour by colour
+  for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
+    typename StagePlan<T>::SpColour col;
+    for (int32_t oi = ss.iface_colour_ptr[c]; oi < ss.iface_colour_ptr[c + 1]; ++oi) {
+      const IfaceSym& I = ss.ifaces[ss.iface_order[oi]];
+      const int32_t p = I.cluster, Pn = size_[p];
+      if (Pn == 0) continue;
+      SpDesc<T> d{};
+      d.nb = (int64_t)col.nb.size();
+      int64_t mmax = 0;
+      for (int32_t i : I.rowN) {
+        const int64_t b = ss.all.find(i, p);
+        col.nb.push_back({boff_[b], i, Pn});
+        mmax += size_[i];
+      }
+      for (int32_t j : I.colN) {
+        const int64_t b = ss.all.find(p, j);
+        col.nb.push_back({boff_[b], j, size_[j]});
+        mmax += size_[j];
+      }
+      d.nrow = (int32_t)I.rowN.size();
+      d.ncol = (int32_t)I.colN.size();
+      d.cluster = p;
+      d.P = Pn;
+      d.mmax = (int32_t)std::max<int64_t>(1, mmax);
+      const int64_t t = fidx[p];
+      d.vq = VQ + u_off[t];
+      d.tauq = TAUQ + p_off[t];
+      d.flag = FLAGS + t;
+      d.pool = pool_;
+      d.rank = d_rank_;
+      d.eps = o_.eps;
+      // the LDS/global kernels need a workspace; the register kernel does not
+      if (sparsify_reg_cpt(sizeof(T), Pn, d.mmax) == 0) {
+        d.C = work_.alloc_n<T>((size_t)(Pn <= 64 ? 65 : Pn) * d.mmax, s_);
+        d.nrm = work_.alloc_n<double>((size_t)d.mmax, s_);
+        d.perm = work_.alloc_n<int32_t>(2 * (size_t)d.mmax, s_);
+      }
+      col.sd.push_back(d);
+      st_.s.flops_sparsify += 4.0 * Pn * (double)mmax * std::min<double>(Pn, (double)mmax);
+    }
+    P.sp.push_back(std::move(col));
+  }
+  // apply descriptors of the interfaces; those of at most 64 unknowns get
+  // their dense forward and backward operators
+  std::vector<ApIface<T>> ai;
+  std::vector<int32_t> sl;
+  std::vector<int64_t> sl_off;
+  int64_t dense_elems = 0;
+  for (int64_t t = 0; t < ni; ++t) {
+    const int64_t Pn = size_[rem[t]];
+    if (Pn > 0 && Pn <= 64) dense_elems += Pn * Pn;
+  }
+  T* MF = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
+  T* MB = persist_.alloc_n<T>(std::max<int64_t>(1, dense_elems), s_);
+  int64_t dense_off = 0;
+  for (int64_t t = 0; t < ni; ++t) {
+    const int32_t p = rem[t], Pn = size_[p];
+    if (Pn == 0) continue;
+    sl_off.push_back((int64_t)sl.size());
+    slot_list(std::vector<int32_t>{p}, sl);
+    T* mf = nullptr;
+    T* mb = nullptr;
+    if (Pn <= 64) {
+      mf = MF + dense_off;
+      mb = MB + dense_off;
+      dense_off += (int64_t)Pn * Pn;
+    }
+    ai.push_back({VRU + u_off[t], TAUU + p_off[t], VQ + u_off[t], TAUQ + p_off[t], nullptr, d_rank_ + p,
+                  FLAGS + t, mf, mb, Pn, 0});
+    ap.max_p = std::max(ap.max_p, (int)Pn);
+  }
+  int32_t* dsl = up.upload(persist_, sl, s_);
+  for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
+  // interfaces of at most 64 unknowns first (dense-operator apply)
+  std::stable_partition(ai.begin(), ai.end(), [](const ApIface<T>& q) { return q.P <= 64; });
+  for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= 64 ? 1 : 0;
+  ap.ifaces = up.upload(persist_, ai, s_);
+  ap.nifaces = (int64_t)ai.size();
+  P.form.assign(ai.begin(), ai.begin() + ap.nifaces_small);
+  st_.s.interfaces_sparsified += (int64_t)ai.size();
+}
+
+template <typename T>
+void Engine<T>::readback() {
+  const int64_t nclu = S_.st[k_].nclu;
   const size_t need = ((size_t)nclu + 2) * sizeof(int);
   if (pinned_.size < need) {
     pinned_release(pinned_);
     pinned_ = pinned_acquire(need);
     pinned_ints_ = reinterpret_cast<int*>(pinned_.p);
   }
-  if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
-  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag, sizeof(int), hipMemcpyDeviceToHost, s_));
+  if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank_, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
+  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag_, sizeof(int), hipMemcpyDeviceToHost, s_));
   SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu + 1, d_zcol_, sizeof(int), hipMemcpyDeviceToHost, s_));
-  SPAQR_HIP(hipStreamSynchronize(s_));
-  SPAQR_REQUIRE(pinned_ints_[nclu + 1] == 0, SPAQR_EINVAL, "A has a zero column");
-  SPAQR_REQUIRE(pinned_ints_[nclu] == 0, SPAQR_ESINGULAR, "a front produced an exactly zero R_ss diagonal");
+}
+
+template <typename T>
+void Engine<T>::finish(MergePlan<T>& mp) {
+  const int k = k_;
+  const StageSym& ss = S_.st[k];
+  const int64_t nclu = ss.nclu;
+  StageApply<T>& ap = ap_[k];
+  if (pinned_ints_[nclu + 1] != 0 || pinned_ints_[nclu] != 0) {
+    // recorded, not thrown: the other factorizations of a batch carry on
+    err_ = pinned_ints_[nclu + 1] != 0 ? SPAQR_EINVAL : SPAQR_ESINGULAR;
+    err_msg_ = pinned_ints_[nclu + 1] != 0 ? "A has a zero column" : "a front produced an exactly zero R_ss diagonal";
+    k_ = 0;
+    return;
+  }
   st_.stage_sizes[k].assign(pinned_ints_, pinned_ints_ + nclu);
   if (ss.sparsify) {
     const double eb = sizeof(T);
@@ -704,18 +724,17 @@ void Engine<T>::stage(int k) {
       for (int32_t q : I.rowN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
       for (int32_t q : I.colN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
       sp_flops += 2.0 * P * m;
-      for (int k = 0; k < (int)r; ++k) sp_flops += (m - k - 1) * (6.0 * (P - k) - 2.0) + 3.0 * (P - k);
+      for (int kk = 0; kk < (int)r; ++kk) sp_flops += (m - kk - 1) * (6.0 * (P - kk) - 2.0) + 3.0 * (P - kk);
       sp_bytes += (P * m + (r < P ? r * m : 0.0)) * eb;
     }
     prof_add("sparsify", sp_flops, sp_bytes);
   }
-  if (k > 1) merge(k);
-}
-
-template <typename T>
-void Engine<T>::merge(int k) {
-  Stager& up = stager_[stager_cur_];
-  const StageSym& ss = S_.st[k];
+  if (k == 1) {
+    k_ = 0;
+    complete();
+    return;
+  }
+  // ------------------------------------------------ merge to stage k - 1
   const StageSym& s2 = S_.st[k - 1];
   const std::vector<int64_t>& par = S_.ord.stages[k].parent;
   const std::vector<int32_t>& rank = st_.stage_sizes[k];
@@ -729,7 +748,7 @@ void Engine<T>::merge(int k) {
   }
   // slot lists of the merged clusters: children's surviving slots in order
   std::vector<int64_t> sp2(n2 + 1, 0);
-  for (int64_t P = 0; P < n2; ++P) sp2[P + 1] = sp2[P] + size2[P];
+  for (int64_t Pc = 0; Pc < n2; ++Pc) sp2[Pc + 1] = sp2[Pc] + size2[Pc];
   std::vector<int32_t> sl2(sp2[n2]);
   for (int64_t c = 0; c < ss.nclu; ++c) {
     if (par[c] < 0) continue;
@@ -746,26 +765,279 @@ void Engine<T>::merge(int k) {
   T* pool2 = pa.alloc_n<T>(std::max<int64_t>(1, boff2.back()), s_);
   // the new pool starts at zero (absent sub-blocks), then every child block
   // lands in its own sub-block of the parent block: disjoint destinations
-  launch_fill<T>(pool2, boff2.back(), T(0), s_);
-  std::vector<CopyTile<T>> tiles;
+  mp.zero.push_back({pool2, std::max<int64_t>(1, boff2.back()) * (int64_t)sizeof(T)});
   for (int64_t i = 0; i < ss.nclu; ++i)
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
       const int32_t j = ss.post.col[u];
       if (rank[i] == 0 || rank[j] == 0) continue;
-      const int32_t P = (int32_t)par[i], Q = (int32_t)par[j];
-      const int64_t B = s2.all.find(P, Q);
+      const int32_t Pc = (int32_t)par[i], Qc = (int32_t)par[j];
+      const int64_t B = s2.all.find(Pc, Qc);
       SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
       const int64_t b = ss.all.find((int32_t)i, j);
-      tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Q] + off[j], rank[i], rank[j],
-                       size_[j], size2[Q], 0, 0});
+      mp.tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Qc] + off[j], rank[i], rank[j],
+                          size_[j], size2[Qc], 0, 0});
     }
-  CopyTile<T>* dt = up.upload(work_, tiles, s_);
-  launch_copy<T>(dt, (int64_t)tiles.size(), s_);
   pool_ = pool2;
   boff_.swap(boff2);
   size_.swap(size2);
   slot_ptr_.swap(sp2);
   slots_.swap(sl2);
+  k_ = k - 1;
+}
+
+// ------------------------------------------------------------ batch driver
+// Launch lists of several factorizations (same precision, same stream)
+// concatenated phase by phase: zero fills, then the fronts colour by colour
+// (gather, QR, scatter), the factor packing, the scaling (gather, QR, pack,
+// block update), the sparsification colour by colour and the dense interface
+// operators; after one synchronization every factorization reads its ranks
+// and the merges run as one zero fill and one copy launch.
+struct BatchCtx {
+  Stager st[2];
+  DevArena work[2] = {DevArena(size_t(16) << 20), DevArena(size_t(16) << 20)};
+  int cur = 0;
+  void begin() {
+    cur ^= 1;
+    st[cur].reset();
+    work[cur].reset();
+  }
+};
+
+template <typename X>
+static void append(std::vector<X>& dst, const std::vector<X>& src) {
+  dst.insert(dst.end(), src.begin(), src.end());
+}
+
+static void launch_zero_ops(const std::vector<ZeroOp>& ops, Stager& up, DevArena& wk, hipStream_t s) {
+  if (ops.empty()) return;
+  std::vector<ZeroDesc> zd;
+  int64_t blocks = 0;
+  for (const ZeroOp& o : ops) {
+    const int64_t words = (o.bytes + 3) / 4;
+    if (words <= 0) continue;
+    zd.push_back({static_cast<uint32_t*>(o.p), words, blocks});
+    blocks += (words + kZeroWordsPerBlock - 1) / kZeroWordsPerBlock;
+  }
+  ZeroDesc* d = up.upload(wk, zd, s);
+  launch_zero(d, (int64_t)zd.size(), blocks, s);
+}
+
+// QR descriptors grouped by the register-kernel plan of each factorization,
+// so that every group shares a panel width: (jb, rows-per-thread class).
+template <typename T>
+static void launch_qr_groups(std::vector<std::pair<int, std::vector<QRDesc<T>>>>& parts, const char* prof_name,
+                             double flops, double bytes, Stager& up, DevArena& wk, hipStream_t s) {
+  std::map<std::pair<int, int>, std::pair<int, std::vector<QRDesc<T>>>> groups;
+  for (auto& pr : parts) {
+    if (pr.second.empty()) continue;
+    int mm = 1;
+    for (const QRDesc<T>& q : pr.second) mm = std::max(mm, (int)q.m);
+    const int jb = pr.first;
+    const int cls = mm <= 256 ? 1 : (mm <= 512 ? 2 : (mm <= 1024 ? 4 : 8 + mm));
+    auto& g = groups[{jb, cls}];
+    g.first = std::max(g.first, mm);
+    append(g.second, pr.second);
+  }
+  if (groups.empty()) return;
+  ProfScope ps(prof_name, s, flops, bytes);
+  for (auto& kv : groups) {
+    QRDesc<T>* d = up.upload(wk, kv.second.second, s);
+    launch_qr<T>(d, (int64_t)kv.second.second.size(), kv.first.first, kv.second.first, s);
+  }
+}
+
+template <typename T>
+static void copy_batch(const std::vector<CopyTile<T>>& tiles, Stager& up, DevArena& wk, hipStream_t s) {
+  if (tiles.empty()) return;
+  CopyTile<T>* d = up.upload(wk, tiles, s);
+  launch_copy<T>(d, (int64_t)tiles.size(), s);
+}
+
+template <typename T>
+static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>& nb, Stager& up, DevArena& wk,
+                           hipStream_t s) {
+  if (sd.empty()) return;
+  int max_nb = 0, max_pc = 1;
+  for (const SpDesc<T>& q : sd) {
+    max_nb = std::max(max_nb, q.nrow + q.ncol);
+    max_pc = std::max<int>(max_pc, q.P);
+  }
+  // interfaces whose columns fit in registers: register CPQR, one launch per
+  // (row class, columns per thread) when one shape does not fit all
+  const auto nreg_end = std::stable_partition(
+      sd.begin(), sd.end(), [](const SpDesc<T>& q) { return sparsify_reg_cpt(sizeof(T), q.P, q.mmax) > 0; });
+  const int64_t nreg = nreg_end - sd.begin();
+  int preg = 1, mreg = 1;
+  for (int64_t t = 0; t < nreg; ++t) {
+    preg = std::max<int>(preg, sd[t].P);
+    mreg = std::max<int>(mreg, sd[t].mmax);
+  }
+  std::vector<std::array<int64_t, 4>> groups;  // begin, end, pmax, mmax
+  if (nreg > 0 && sparsify_reg_cpt(sizeof(T), preg, mreg) > 0) {
+    groups.push_back({0, nreg, preg, mreg});
+  } else if (nreg > 0) {
+    auto pcls = [](int Pv) { return Pv <= 16 ? 0 : (Pv <= 32 ? 1 : 2); };
+    std::stable_sort(sd.begin(), sd.begin() + nreg,
+                     [&](const SpDesc<T>& x, const SpDesc<T>& y) { return pcls(x.P) < pcls(y.P); });
+    for (int64_t b = 0; b < nreg;) {
+      int64_t e = b;
+      int pm = 1, mm = 1;
+      while (e < nreg && pcls(sd[e].P) == pcls(sd[b].P)) {
+        pm = std::max<int>(pm, sd[e].P);
+        mm = std::max<int>(mm, sd[e].mmax);
+        ++e;
+      }
+      groups.push_back({b, e, pm, mm});
+      b = e;
+    }
+  }
+  // the rest: interfaces of at most 64 (FP32) or 32 (FP64) unknowns to the LDS
+  // kernel, the others to the generic one
+  constexpr int kSmallP = sizeof(T) == 4 ? 64 : 32;
+  std::stable_partition(sd.begin() + nreg, sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
+  int64_t nsmall = 0;
+  int pmax_small = 1, mmax_small = 1;
+  for (size_t t = (size_t)nreg; t < sd.size(); ++t)
+    if (sd[t].P <= kSmallP) {
+      ++nsmall;
+      pmax_small = std::max<int>(pmax_small, sd[t].P);
+      mmax_small = std::max<int>(mmax_small, sd[t].mmax);
+    }
+  const int pclass = pmax_small <= 16 ? 16 : (pmax_small <= 32 ? 32 : 64);
+  const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
+  SpDesc<T>* dsd = up.upload(wk, sd, s);
+  SpNbr* dnb = up.upload(wk, nb, s);
+  ProfScope ps("sparsify", s, 0.0, 0.0);  // work added after the rank readback
+  for (const auto& g : groups)
+    launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, (int)g[2], (int)g[3], max_nb, s);
+  launch_sparsify_small<T>(dsd + nreg, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
+  launch_sparsify<T>(dsd + nreg + nsmall, (int64_t)sd.size() - nreg - nsmall, dnb, max_pc, max_nb, s);
+}
+
+template <typename T>
+void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s) {
+  bx.begin();
+  Stager& up = bx.st[bx.cur];
+  DevArena& wk = bx.work[bx.cur];
+  const size_t ne = es.size();
+  std::vector<StagePlan<T>> pl(ne);
+  // zero fills requested by the plan parts so far, before their launches
+  auto flush_zero = [&]() {
+    std::vector<ZeroOp> z;
+    for (auto& p : pl) {
+      append(z, p.zero);
+      p.zero.clear();
+    }
+    launch_zero_ops(z, up, wk, s);
+  };
+  for (size_t e = 0; e < ne; ++e) es[e]->plan_fronts(pl[e]);
+  flush_zero();
+  // fronts, colour by colour
+  size_t nc = 0;
+  for (auto& p : pl) nc = std::max(nc, p.fronts.size());
+  for (size_t c = 0; c < nc; ++c) {
+    std::vector<CopyTile<T>> g, sc;
+    std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
+    double fl = 0.0, by = 0.0;
+    for (auto& p : pl) {
+      if (c >= p.fronts.size()) continue;
+      append(g, p.fronts[c].gather);
+      append(sc, p.fronts[c].scatter);
+      qparts.emplace_back(p.jbf, p.fronts[c].qr);
+      fl += p.fronts[c].flops;
+      by += p.fronts[c].bytes;
+    }
+    copy_batch(g, up, wk, s);
+    launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
+    copy_batch(sc, up, wk, s);
+  }
+  {
+    std::vector<CopyTile<T>> pk;
+    for (auto& p : pl) append(pk, p.pack);
+    copy_batch(pk, up, wk, s);
+  }
+  // block-diagonal scaling
+  for (size_t e = 0; e < ne; ++e) es[e]->plan_scale(pl[e]);
+  flush_zero();
+  {
+    std::vector<CopyTile<T>> g, pk;
+    std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
+    std::vector<ScaleFac<T>> fac;
+    std::map<int, std::pair<int, std::vector<ScaleBlk<T>>>> sgroups;  // jb -> (max P, blocks)
+    double qfl = 0.0, qby = 0.0, sfl = 0.0, sby = 0.0;
+    for (auto& p : pl) {
+      append(g, p.sgather);
+      append(pk, p.spack);
+      qparts.emplace_back(p.jbs, p.sqr);
+      for (const QRDesc<T>& q : p.sqr) {
+        qfl += 4.0 / 3.0 * (double)q.n * q.n * q.n;
+        qby += 2.0 * (double)q.n * q.n * sizeof(T);
+      }
+      const int base = (int)fac.size();
+      append(fac, p.fac);
+      auto& sg = sgroups[p.jbs];
+      sg.first = std::max(sg.first, p.max_p);
+      for (ScaleBlk<T> b : p.sblk) {
+        if (b.fi >= 0) b.fi += base;
+        if (b.fj >= 0) b.fj += base;
+        sg.second.push_back(b);
+        sfl += 4.0 * b.rows * b.rows * (double)b.cols + (double)b.rows * b.cols * b.cols;
+        sby += 2.0 * b.rows * (double)b.cols * sizeof(T);
+      }
+    }
+    copy_batch(g, up, wk, s);
+    launch_qr_groups<T>(qparts, "scale_qr", qfl, qby, up, wk, s);
+    copy_batch(pk, up, wk, s);
+    if (!fac.empty()) {
+      ScaleFac<T>* dfac = up.upload(wk, fac, s);
+      ProfScope ps("scale_blocks", s, sfl, sby);
+      for (auto& kv : sgroups) {
+        if (kv.second.second.empty()) continue;
+        ScaleBlk<T>* dsb = up.upload(wk, kv.second.second, s);
+        launch_scale<T>(dsb, (int64_t)kv.second.second.size(), dfac, kv.first, kv.second.first, s);
+      }
+    }
+  }
+  // sparsification, colour by colour
+  for (size_t e = 0; e < ne; ++e) es[e]->plan_sparsify(pl[e]);
+  flush_zero();
+  size_t nsc = 0;
+  for (auto& p : pl) nsc = std::max(nsc, p.sp.size());
+  for (size_t c = 0; c < nsc; ++c) {
+    std::vector<SpDesc<T>> sd;
+    std::vector<SpNbr> nb;
+    for (auto& p : pl) {
+      if (c >= p.sp.size()) continue;
+      const int64_t base = (int64_t)nb.size();
+      append(nb, p.sp[c].nb);
+      for (SpDesc<T> d : p.sp[c].sd) {
+        d.nb += base;
+        sd.push_back(d);
+      }
+    }
+    sparsify_batch<T>(sd, nb, up, wk, s);
+  }
+  {
+    std::vector<ApIface<T>> form;
+    for (auto& p : pl) append(form, p.form);
+    if (!form.empty()) {
+      ApIface<T>* d = up.upload(wk, form, s);
+      launch_iface_form<T>(d, (int64_t)form.size(), s);
+    }
+  }
+  // ranks back, merges
+  for (Engine<T>* e : es) e->readback();
+  SPAQR_HIP(hipStreamSynchronize(s));
+  std::vector<MergePlan<T>> mp(ne);
+  for (size_t e = 0; e < ne; ++e) es[e]->finish(mp[e]);
+  std::vector<ZeroOp> z;
+  std::vector<CopyTile<T>> tiles;
+  for (auto& m : mp) {
+    append(z, m.zero);
+    append(tiles, m.tiles);
+  }
+  launch_zero_ops(z, up, wk, s);
+  copy_batch(tiles, up, wk, s);
 }
 
 template <typename T>
@@ -812,13 +1084,57 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
 
 }  // namespace
 
-std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
-                                        const spaqr_opts& o, hipStream_t stream) {
+template <typename T>
+static void factor_all(Engine<T>* e) {
+  BatchCtx bx;
+  const std::vector<Engine<T>*> one{e};
+  try {
+    while (e->stages_left() > 0) run_stage_batch<T>(one, bx, e->stream());
+  } catch (...) {
+    (void)hipStreamSynchronize(e->stream());
+    throw;
+  }
+  SPAQR_HIP(hipStreamSynchronize(e->stream()));
+  if (e->error() != SPAQR_OK) throw Error(e->error(), e->error_message());
+}
+
+std::unique_ptr<EngineBase> make_engine_deferred(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                                 const spaqr_opts& o, hipStream_t stream) {
   SPAQR_REQUIRE(o.eps >= 0.0 && std::isfinite(o.eps), SPAQR_EINVAL, "eps must be finite and >= 0");
   SPAQR_REQUIRE(o.scale == 1, SPAQR_EINVAL, "only the scaled variant is implemented");
   SPAQR_REQUIRE(o.precision == 32 || o.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
   if (o.precision == 32) return std::unique_ptr<EngineBase>(new Engine<float>(A, Ad, S, o, stream));
   return std::unique_ptr<EngineBase>(new Engine<double>(A, Ad, S, o, stream));
+}
+
+std::unique_ptr<EngineBase> make_engine(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
+                                        const spaqr_opts& o, hipStream_t stream) {
+  std::unique_ptr<EngineBase> e = make_engine_deferred(A, Ad, S, o, stream);
+  if (o.precision == 32) factor_all(static_cast<Engine<float>*>(e.get()));
+  else factor_all(static_cast<Engine<double>*>(e.get()));
+  return e;
+}
+
+// One stage of every factorization in es (each at its own next stage), the
+// FP32 and FP64 ones in separate launches.  All must use stream s.
+struct BatchDriver {
+  BatchCtx b32, b64;
+};
+
+BatchDriver* batch_driver_new() { return new BatchDriver(); }
+void batch_driver_free(BatchDriver* d) { delete d; }
+
+void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s) {
+  std::vector<Engine<float>*> f32;
+  std::vector<Engine<double>*> f64;
+  for (EngineBase* e : es) {
+    if (e->stages_left() <= 0) continue;
+    SPAQR_REQUIRE(e->stream() == s, SPAQR_EINVAL, "batched factorizations must share one stream");
+    if (e->precision() == 32) f32.push_back(static_cast<Engine<float>*>(e));
+    else f64.push_back(static_cast<Engine<double>*>(e));
+  }
+  if (!f32.empty()) run_stage_batch<float>(f32, drv.b32, s);
+  if (!f64.empty()) run_stage_batch<double>(f64, drv.b64, s);
 }
 
 }  // namespace spaqr

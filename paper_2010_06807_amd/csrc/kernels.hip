@@ -211,6 +211,22 @@ __global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ til
   }
 }
 
+// Zero fills of several buffers in one launch; each descriptor owns the
+// workgroups block0 .. block0 + ceil(words / kZeroWordsPerBlock) - 1.
+__global__ void __launch_bounds__(256) k_zero(const ZeroDesc* __restrict__ ds, int64_t n) {
+  int64_t lo = 0, hi = n - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ds[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const ZeroDesc d = ds[lo];
+  const int64_t w0 = (b - d.block0) * kZeroWordsPerBlock;
+  const int64_t w1 = min(d.words, w0 + kZeroWordsPerBlock);
+  for (int64_t w = w0 + threadIdx.x; w < w1; w += 256) d.p[w] = 0u;
+}
+
 template <typename T>
 __global__ void k_fill(T* p, int64_t n, T v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -572,12 +588,12 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
 }
 
 template <typename T, int JB>
-__global__ void __launch_bounds__(NT) k_scale(const ScaleBlk* __restrict__ descs,
-                                              const ScaleFac<T>* __restrict__ fac, T* pool) {
+__global__ void __launch_bounds__(NT) k_scale(const ScaleBlk<T>* __restrict__ descs,
+                                              const ScaleFac<T>* __restrict__ fac) {
   using S = QRLds<T, JB>;
   constexpr int LDP = JB + 1;
-  const ScaleBlk d = descs[blockIdx.x];
-  T* B = pool + d.blk;
+  const ScaleBlk<T> d = descs[blockIdx.x];
+  T* B = d.B;
   const int rows = d.rows, cols = d.cols, tid = threadIdx.x;
   const bool si = d.fi >= 0 && *fac[d.fi].flag == 0;
   const bool sj = d.fj >= 0 && *fac[d.fj].flag == 0;
@@ -626,9 +642,11 @@ __global__ void __launch_bounds__(NT) k_scale(const ScaleBlk* __restrict__ descs
 
 template <typename T>
 __global__ void __launch_bounds__(NT) k_sparsify(const SpDesc<T>* __restrict__ descs,
-                                                 const SpNbr* __restrict__ nbrs, T* pool, int* rank,
-                                                 double eps) {
+                                                 const SpNbr* __restrict__ nbrs) {
   const SpDesc<T> d = descs[blockIdx.x];
+  const double eps = d.eps;
+  T* pool = d.pool;
+  int* rank = d.rank;
   const int P = d.P, tid = threadIdx.x;
   if (P == 0 || *d.flag != 0) return;  // not scaled: rank stays P
   extern __shared__ __align__(16) unsigned char smem[];
@@ -813,11 +831,14 @@ __global__ void __launch_bounds__(NT) k_sparsify(const SpDesc<T>* __restrict__ d
 // position (columns are physically swapped).
 template <typename T, int PMAX, int NTH>
 __global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restrict__ descs,
-                                                        const SpNbr* __restrict__ nbrs, T* pool, int* rank,
-                                                        double eps, int lds_c_elems, int max_nb) {
+                                                        const SpNbr* __restrict__ nbrs, int lds_c_elems,
+                                                        int max_nb) {
   constexpr int NW = NTH / 64;
   constexpr int LDQ = PMAX + 1;
   const SpDesc<T> d = descs[blockIdx.x];
+  const double eps = d.eps;
+  T* pool = d.pool;
+  int* rank = d.rank;
   const int P = d.P, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (P == 0 || *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1033,12 +1054,14 @@ constexpr int SP_NT = 512;
 
 template <typename T, int PMAX, int CPT, int LC>
 __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict__ descs,
-                                                    const SpNbr* __restrict__ nbrs, T* pool, int* rank,
-                                                    double eps, int max_nb) {
+                                                    const SpNbr* __restrict__ nbrs, int max_nb) {
   constexpr int NW = SP_NT / 64;
   constexpr int NC = CPT + LC;
   constexpr int VN = Vec16<T>::N;
   const SpDesc<T> d = descs[blockIdx.x];
+  const double eps = d.eps;
+  T* pool = d.pool;
+  int* rank = d.rank;
   const int P = d.P, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (P == 0 || *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1847,6 +1870,12 @@ void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s) {
   check_launch("k_copy");
 }
 
+void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, d, n);
+  check_launch("k_zero");
+}
+
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return;
@@ -1922,8 +1951,7 @@ template <typename T>
 void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) {
   if (n <= 0) return;
   const QRPlan pl = qr_plan(max_m, sizeof(T));
-  if (pl.jb != jb) throw Error(SPAQR_EINVAL, "QR panel width does not match the plan");
-  if (pl.q > 0) {
+  if (pl.q > 0 && pl.jb == jb) {
     const size_t lds = qr_reg_lds(max_m, jb, sizeof(T));
 #define SPAQR_QRR(J, Q)                                                                      \
   if (jb == J && pl.q == Q) {                                                               \
@@ -1946,8 +1974,11 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
   }
   const size_t lds = qr_bytes_jb(max_m, jb, sizeof(T));
   switch (jb) {
-#define SPAQR_QR_CASE(J) \
-  case J: hipLaunchKernelGGL((k_qr<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d); break;
+#define SPAQR_QR_CASE(J)                                                   \
+  case J:                                                                  \
+    allow_lds(reinterpret_cast<const void*>(&k_qr<T, J>), lds, "k_qr");  \
+    hipLaunchKernelGGL((k_qr<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d); \
+    break;
     SPAQR_QR_CASE(1)
     SPAQR_QR_CASE(2)
     SPAQR_QR_CASE(4)
@@ -1961,15 +1992,14 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
 }
 
 template <typename T>
-void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool, int jb, int max_p,
-                  hipStream_t s) {
+void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, hipStream_t s) {
   if (n <= 0) return;
   const size_t lds = qr_bytes_jb(max_p, jb, sizeof(T));
   switch (jb) {
 #define SPAQR_SC_CASE(J) \
   case J:                                                                                       \
     allow_lds(reinterpret_cast<const void*>(&k_scale<T, J>), lds, "k_scale");                 \
-    hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, pool);    \
+    hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac);          \
     break;
     SPAQR_SC_CASE(1)
     SPAQR_SC_CASE(2)
@@ -1997,8 +2027,8 @@ static size_t device_lds_limit() {
 }
 
 template <typename T, int PMAX, int NTH>
-static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank,
-                                    double eps, int max_nb, size_t c_bytes, hipStream_t s) {
+static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_nb, size_t c_bytes,
+                                    hipStream_t s) {
   constexpr int NW = NTH / 64;
   const size_t head = align16(align16((size_t)NW * 8 + 32 + (size_t)NW * 4) + PMAX * sizeof(T) +
                               (size_t)(max_nb + 1) * 4);
@@ -2006,31 +2036,30 @@ static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* 
   size_t cb = std::min(c_bytes, lim > head + 1024 ? lim - head - 512 : 0);
   const int lds_c_elems = (int)(cb / sizeof(T));
   const size_t lds = head + (size_t)lds_c_elems * sizeof(T);
-  hipLaunchKernelGGL((k_sparsify_small<T, PMAX, NTH>), dim3((unsigned)n), dim3(NTH), lds, s, d, nb, pool, rank,
-                     eps, lds_c_elems, max_nb);
+  hipLaunchKernelGGL((k_sparsify_small<T, PMAX, NTH>), dim3((unsigned)n), dim3(NTH), lds, s, d, nb, lds_c_elems,
+                     max_nb);
   check_launch("k_sparsify_small");
 }
 
 template <typename T>
-void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
-                           int pmax, int max_nb, size_t max_c_elems, hipStream_t s) {
+void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int max_nb,
+                           size_t max_c_elems, hipStream_t s) {
   if (n <= 0) return;
   const size_t cbytes = max_c_elems * sizeof(T);
   // thread counts keep the per-thread column in registers without spills
   constexpr bool F32 = sizeof(T) == 4;
-  if (pmax <= 16) launch_sparsify_small_t<T, 16, 1024>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
-  else if (pmax <= 32) launch_sparsify_small_t<T, 32, F32 ? 1024 : 512>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
-  else if (F32) launch_sparsify_small_t<T, 64, 512>(d, n, nb, pool, rank, eps, max_nb, cbytes, s);
+  if (pmax <= 16) launch_sparsify_small_t<T, 16, 1024>(d, n, nb, max_nb, cbytes, s);
+  else if (pmax <= 32) launch_sparsify_small_t<T, 32, F32 ? 1024 : 512>(d, n, nb, max_nb, cbytes, s);
+  else if (F32) launch_sparsify_small_t<T, 64, 512>(d, n, nb, max_nb, cbytes, s);
   else throw Error(SPAQR_EINVAL, "FP64 interfaces above 32 unknowns use the generic sparsify kernel");
 }
 
 template <typename T>
-void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
-                     int max_p, int max_nb, hipStream_t s) {
+void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_p, int max_nb, hipStream_t s) {
   if (n <= 0) return;
   const size_t lds = align16((size_t)(max_nb + 1) * sizeof(int)) + (size_t)max_p * sizeof(double) +
                      8 * sizeof(double) + NT * sizeof(double) + NT * sizeof(int);
-  hipLaunchKernelGGL(k_sparsify<T>, dim3((unsigned)n), dim3(NT), lds, s, d, nb, pool, rank, eps);
+  hipLaunchKernelGGL(k_sparsify<T>, dim3((unsigned)n), dim3(NT), lds, s, d, nb);
   check_launch("k_sparsify");
 }
 
@@ -2048,8 +2077,8 @@ int sparsify_reg_cpt(int eb, int pmax, int mmax) {
 }
 
 template <typename T>
-void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps, int pmax,
-                         int mmax, int max_nb, hipStream_t s) {
+void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int mmax, int max_nb,
+                         hipStream_t s) {
   if (n <= 0) return;
   const int tot = sparsify_reg_cpt(sizeof(T), pmax, mmax);
   if (tot == 0) throw Error(SPAQR_EINVAL, "interface too large for the register CPQR");
@@ -2062,8 +2091,7 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool
 #define SPAQR_SPR(PM, CP, L)                                                                              \
   if (pclass == PM && cpt == CP && lc == L) {                                                            \
     allow_lds(reinterpret_cast<const void*>(&k_cpqr_reg<T, PM, CP, L>), lds, "k_cpqr_reg");             \
-    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, pool, rank, \
-                       eps, max_nb);                                                                     \
+    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, max_nb);   \
     check_launch("k_cpqr_reg");                                                                          \
     return;                                                                                              \
   }
@@ -2234,13 +2262,10 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_scatter_scaled<T>(T*, const int64_t*, const double*, const int32_t*, const double*, \
                                          int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
-  template void launch_scale<T>(const ScaleBlk*, int64_t, const ScaleFac<T>*, T*, int, int, hipStream_t); \
-  template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
-                                   hipStream_t);                                                     \
-  template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, \
-                                         size_t, hipStream_t);                                       \
-  template void launch_sparsify_reg<T>(const SpDesc<T>*, int64_t, const SpNbr*, T*, int*, double, int, int, int, \
-                                       hipStream_t);                                                 \
+  template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, hipStream_t); \
+  template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, hipStream_t); \
+  template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, size_t, hipStream_t); \
+  template void launch_sparsify_reg<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, int, hipStream_t); \
   template void launch_front_fwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_bwd<T>(const ApFront<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \
   template void launch_iface_fwd<T>(const ApIface<T>*, int64_t, int, double*, int64_t, int, hipStream_t); \

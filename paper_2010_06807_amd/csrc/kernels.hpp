@@ -49,10 +49,19 @@ struct ScaleFac {
   int32_t P, pad;
 };
 
+template <typename T>
 struct ScaleBlk {
-  int64_t blk;      // element offset of the block in the pool
+  T* B;             // the block (row-major, ld = cols)
   int32_t rows, cols;
   int32_t fi, fj;   // index into the ScaleFac table, or -1
+};
+
+// Zero fill of words 32-bit words at p; block0 = first workgroup of this
+// descriptor in a launch over several descriptors.
+struct ZeroDesc {
+  uint32_t* p;
+  int64_t words;
+  int64_t block0;
 };
 
 // Sparsification of one interface p (Sections 2.5-2.6): gathers
@@ -61,7 +70,7 @@ struct ScaleBlk {
 // blocks back and stores the reflectors (column-major P x r, explicit unit
 // diagonal and zeros above) and tau.  rank[cluster] receives r.
 struct SpNbr {
-  int64_t blk;      // element offset of block (i, p) or (p, j) in the pool
+  int64_t blk;      // element offset of block (i, p) or (p, j) in the interface's pool
   int32_t cluster;  // the neighbour cluster (its current size is rank[cluster])
   int32_t ld;       // leading dimension of the block
 };
@@ -74,6 +83,9 @@ struct SpDesc {
   T* vq;            // P x P column-major (first r columns used)
   T* tauq;          // P
   const int* flag;  // scaling flag of p (nonzero: not scaled, not sparsified)
+  T* pool;          // block pool of the interface's factorization
+  int* rank;        // current cluster sizes of that factorization (rank[cluster] gets r)
+  double eps;       // truncation tolerance of that factorization
   int64_t nb;       // first neighbour in the SpNbr array
   int32_t nrow, ncol;
   int32_t cluster, P, mmax, pad;
@@ -123,22 +135,23 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s);
 int qr_panel_width(int max_m, int elem_bytes);
 size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
 template <typename T>
-void launch_scale(const ScaleBlk* d, int64_t n, const ScaleFac<T>* fac, T* pool, int jb, int max_p,
-                  hipStream_t s);
+void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, hipStream_t s);
+// Zero fills; blocks = total workgroups (block0 of the last descriptor plus its own).
+void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s);
+constexpr int64_t kZeroWordsPerBlock = 4096;
 template <typename T>
-void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
-                     int max_p, int max_nb, hipStream_t s);
+void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_p, int max_nb, hipStream_t s);
 // Interfaces of at most 64 unknowns; pmax = the largest P in the launch,
 // max_c_elems = the largest P x m of the launch (C is staged in LDS when it fits).
 // Register-resident CPQR (see k_cpqr_reg): columns per thread needed for
 // interfaces of at most pmax unknowns and mmax columns, or 0 if they do not fit.
 int sparsify_reg_cpt(int elem_bytes, int pmax, int mmax);
 template <typename T>
-void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps, int pmax,
-                         int mmax, int max_nb, hipStream_t s);
+void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int mmax, int max_nb,
+                         hipStream_t s);
 template <typename T>
-void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, T* pool, int* rank, double eps,
-                           int pmax, int max_nb, size_t max_c_elems, hipStream_t s);
+void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int max_nb,
+                           size_t max_c_elems, hipStream_t s);
 // Apply launches: max_rows = the largest number of FP64 rows one item keeps in
 // LDS per right-hand side (m for fronts forward, n + k backward, P for
 // interfaces).  Returns without launching when there is nothing to do.

@@ -1,6 +1,14 @@
-// Request loop of the serving path: requests are copied at submission, admitted
-// when their estimated device memory fits the budget, factorized, solved with
-// all of their right-hand sides at once, and retired.
+// Continuous-batching request loop.  Requests (matrix, ordering, options and
+// right-hand sides) are copied at submission and queued.  Every step:
+//   1. admits queued requests in arrival order while their estimated device
+//      memory fits the budget (symbolic analysis and matrix upload happen
+//      here);
+//   2. advances every admitted, still factoring request by one stage in one
+//      batched pass: their fronts, scalings and sparsifications share one
+//      launch per phase, whatever stage each request is at, so a request that
+//      arrives while others are half-way joins the running batch;
+//   3. solves every request whose factorization completed, all of its
+//      right-hand sides together (multi-RHS FGMRES), and retires it.
 #include <deque>
 #include <map>
 #include <memory>
@@ -46,6 +54,11 @@ struct spaqr_server {
   std::deque<std::unique_ptr<spaqr::Request>> queue;
   std::vector<std::unique_ptr<spaqr::Request>> active;
   std::map<uint64_t, std::unique_ptr<spaqr::Request>> done;
+  spaqr::BatchDriver* drv = nullptr;
+  ~spaqr_server() {
+    active.clear();
+    if (drv) spaqr::batch_driver_free(drv);
+  }
 };
 
 using namespace spaqr;
@@ -63,6 +76,34 @@ spaqr_status guard(F&& f) {
     return SPAQR_EINVAL;
   }
 }
+
+void retire(spaqr_server* srv, std::unique_ptr<Request> r, int status) {
+  r->status = status;
+  r->eng.reset();
+  r->sym.reset();
+  srv->used -= r->est;
+  srv->done[r->ticket] = std::move(r);
+}
+
+int solve(spaqr_server* srv, Request& r) {
+  const int64_t N = r.A.n;
+  double* db = static_cast<double*>(dev_alloc(N * r.nrhs * sizeof(double), srv->stream));
+  double* dx = static_cast<double*>(dev_alloc(N * r.nrhs * sizeof(double), srv->stream));
+  int st = SPAQR_OK;
+  try {
+    SPAQR_HIP(hipMemcpyAsync(db, r.b.data(), N * r.nrhs * sizeof(double), hipMemcpyHostToDevice, srv->stream));
+    r.info.assign(r.nrhs, spaqr_solve_info{});
+    st = fgmres_solve(*r.eng, db, N, dx, N, (int)r.nrhs, r.tol, r.info.data());
+    r.x.resize(N * r.nrhs);
+    SPAQR_HIP(hipMemcpyAsync(r.x.data(), dx, N * r.nrhs * sizeof(double), hipMemcpyDeviceToHost, srv->stream));
+    SPAQR_HIP(hipStreamSynchronize(srv->stream));
+  } catch (const Error& e) {
+    st = e.status;
+  }
+  dev_free(db, srv->stream);
+  dev_free(dx, srv->stream);
+  return st;
+}
 }  // namespace
 
 extern "C" {
@@ -73,6 +114,7 @@ spaqr_status spaqr_server_create(size_t mem_budget, void* hip_stream, spaqr_serv
     auto* s = new spaqr_server();
     s->budget = mem_budget;
     s->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    s->drv = batch_driver_new();
     *out = s;
     return SPAQR_OK;
   });
@@ -105,35 +147,49 @@ spaqr_status spaqr_submit(spaqr_server* srv, const spaqr_csr* A, const spaqr_ord
 spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
   return guard([&]() -> spaqr_status {
     SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
+    // 1. admission by estimated memory, in arrival order
     while (!srv->queue.empty() && srv->used + srv->queue.front()->est <= srv->budget) {
-      srv->used += srv->queue.front()->est;
-      srv->active.push_back(std::move(srv->queue.front()));
+      std::unique_ptr<Request> r = std::move(srv->queue.front());
       srv->queue.pop_front();
+      srv->used += r->est;
+      try {
+        r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
+        r->eng = make_engine_deferred(&r->A, nullptr, *r->sym, r->opts, srv->stream);
+        srv->active.push_back(std::move(r));
+      } catch (const Error& e) {
+        retire(srv, std::move(r), e.status);
+      } catch (const std::bad_alloc&) {
+        retire(srv, std::move(r), SPAQR_ENOMEM);
+      }
     }
+    // 2. one stage of every factoring request, batched across requests
+    std::vector<EngineBase*> es;
+    for (auto& r : srv->active)
+      if (r->eng->stages_left() > 0) es.push_back(r->eng.get());
+    if (!es.empty()) {
+      try {
+        factor_stage_batch(*srv->drv, es, srv->stream);
+      } catch (const Error& e) {
+        // a failure outside the per-request checks leaves the batch in an
+        // unknown state: every request of it fails with that status
+        (void)hipStreamSynchronize(srv->stream);
+        std::vector<std::unique_ptr<Request>> keep;
+        for (auto& r : srv->active) {
+          if (r->eng->stages_left() > 0) retire(srv, std::move(r), e.status);
+          else keep.push_back(std::move(r));
+        }
+        srv->active.swap(keep);
+      }
+    }
+    // 3. solve and retire the factored requests
     std::vector<std::unique_ptr<Request>> keep;
     for (auto& r : srv->active) {
-      if (!r->eng) {
-        r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
-        r->eng = make_engine(&r->A, nullptr, *r->sym, r->opts, srv->stream);
+      if (r->eng->stages_left() > 0) {
         keep.push_back(std::move(r));
         continue;
       }
-      const int64_t N = r->A.n;
-      double *db = nullptr, *dx = nullptr;
-      db = static_cast<double*>(dev_alloc(N * r->nrhs * sizeof(double), srv->stream));
-      dx = static_cast<double*>(dev_alloc(N * r->nrhs * sizeof(double), srv->stream));
-      SPAQR_HIP(hipMemcpyAsync(db, r->b.data(), N * r->nrhs * sizeof(double), hipMemcpyHostToDevice, srv->stream));
-      r->info.assign(r->nrhs, spaqr_solve_info{});
-      r->status = fgmres_solve(*r->eng, db, N, dx, N, (int)r->nrhs, r->tol, r->info.data());
-      r->x.resize(N * r->nrhs);
-      SPAQR_HIP(hipMemcpyAsync(r->x.data(), dx, N * r->nrhs * sizeof(double), hipMemcpyDeviceToHost, srv->stream));
-      SPAQR_HIP(hipStreamSynchronize(srv->stream));
-      dev_free(db, srv->stream);
-      dev_free(dx, srv->stream);
-      r->eng.reset();
-      r->sym.reset();
-      srv->used -= r->est;
-      srv->done[r->ticket] = std::move(r);
+      const int st = r->eng->error() != SPAQR_OK ? r->eng->error() : solve(srv, *r);
+      retire(srv, std::move(r), st);
     }
     srv->active.swap(keep);
     if (active) *active = (int)(srv->active.size() + srv->queue.size());

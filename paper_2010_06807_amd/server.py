@@ -52,3 +52,80 @@ class Server:
         del self._keep[ticket]
         return x, [dict(iterations=i.iterations, converged=bool(i.converged), relres=i.relres,
                         seconds=i.seconds) for i in info]
+
+
+def _percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(np.ceil(q / 100.0 * len(v))) - 1))
+    return v[i]
+
+
+def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_scale=1.0):
+    """Replay a request trace through the continuous-batching server.
+
+    jobs: list of dicts with `arrival` (seconds from the start), `A` (scipy
+    CSR), `ordering` (GridOrdering), `b` (n x nrhs) and `eps`.  Each request is
+    submitted once the wall clock passes its arrival time (scaled by
+    time_scale); the loop steps the server while requests are in flight.
+    Returns per-request dicts (latency_s = completion - arrival, iterations,
+    relres) and a summary with throughput (unknowns x right-hand sides per
+    second over the makespan) and p50/p99 latency."""
+    import time
+    srv = Server(mem_budget, stream)
+    order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
+    res = [None] * len(jobs)
+    pending = {}
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < len(order) or pending:
+        now = time.perf_counter() - t0
+        while nxt < len(order) and jobs[order[nxt]]["arrival"] * time_scale <= now:
+            j = jobs[order[nxt]]
+            t = srv.submit(j["A"], j["ordering"], j["b"], tol=tol, eps=j.get("eps", 1e-2), precision=precision)
+            pending[t] = order[nxt]
+            nxt += 1
+        if not pending:
+            time.sleep(max(0.0, jobs[order[nxt]]["arrival"] * time_scale - (time.perf_counter() - t0)))
+            continue
+        srv.step()
+        for t in list(pending):
+            out = srv.poll(t)
+            if out is None:
+                continue
+            i = pending.pop(t)
+            x, info = out
+            res[i] = dict(latency_s=time.perf_counter() - t0 - jobs[i]["arrival"] * time_scale, x=x,
+                          iterations=[d["iterations"] for d in info], relres=[d["relres"] for d in info])
+    span = time.perf_counter() - t0
+    work = sum(j["A"].shape[0] * (1 if np.ndim(j["b"]) == 1 else np.shape(j["b"])[1]) for j in jobs)
+    lat = [r["latency_s"] for r in res]
+    return res, dict(makespan_s=span, throughput=work / span, p50_ms=1e3 * _percentile(lat, 50),
+                     p99_ms=1e3 * _percentile(lat, 99), requests=len(jobs))
+
+
+def serve_sequential(jobs, tol=1e-10, precision=64, time_scale=1.0):
+    """The same trace without batching: requests run one at a time in arrival
+    order (factor, then solve all of the request's right-hand sides), each
+    starting no earlier than its arrival."""
+    import time
+    from . import factor
+    order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
+    res = [None] * len(jobs)
+    t0 = time.perf_counter()
+    for i in order:
+        j = jobs[i]
+        wait = j["arrival"] * time_scale - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        fac = factor(j["A"], j["ordering"], eps=j.get("eps", 1e-2), precision=precision)
+        x, info = fac.solve(j["b"], tol=tol)
+        del fac
+        res[i] = dict(latency_s=time.perf_counter() - t0 - j["arrival"] * time_scale, x=x,
+                      iterations=[d["iterations"] for d in info], relres=[d["relres"] for d in info])
+    span = time.perf_counter() - t0
+    work = sum(j["A"].shape[0] * (1 if np.ndim(j["b"]) == 1 else np.shape(j["b"])[1]) for j in jobs)
+    lat = [r["latency_s"] for r in res]
+    return res, dict(makespan_s=span, throughput=work / span, p50_ms=1e3 * _percentile(lat, 50),
+                     p99_ms=1e3 * _percentile(lat, 99), requests=len(jobs))
