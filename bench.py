@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline (default: the slowest)")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="requests of the serving trace replayed after the single-problem steps (0: skip)")
     ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
                     help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
                          "directory of this script's run and exit")
@@ -101,6 +103,39 @@ def rocprof_summary(d, fp32_steps):
         n = sum(int(r["Calls"]) for r in stats if any(p in r["Name"] for p in pats))
         out.append(f"| {g} | {n} launches | {ms / fp32_steps:.3f} |")
     return "\n".join(out)
+
+
+def serving(nreq, tol, seed=0):
+    """The serving workload: the first nreq requests of the seeded trace
+    (2D sides 64..512 or 3D sides 16..48, |beta| 1..200, 1..32 right-hand
+    sides, eps 1e-2).  A calibration pass runs the plain FP64 path over the
+    requests back to back; the arrival times are then scaled so that path
+    would be busy 70% of the time, and the trace is replayed through the
+    batched FP32 server and through the sequential FP64 path on the same
+    timestamps.  Throughput counts unknowns x right-hand sides per second of
+    makespan; latency runs from a request's arrival to its last solution."""
+    import numpy as np
+    import paper_2010_06807_amd as P
+    from paper_2010_06807_amd.server import serve_trace, serve_sequential
+    from problems.trace import serving_trace, build_request
+    reqs = serving_trace(nreq, seed=seed)
+    jobs = []
+    for r in reqs:
+        q = build_request(r)
+        jobs.append(dict(arrival=r["arrival"], A=q["A"], ordering=P.order_grid(q["dims"], q["levels"]), b=q["b"],
+                         eps=r["eps"]))
+    _, cal = serve_sequential(jobs, tol=tol, precision=64, time_scale=0.0)
+    service = cal["makespan_s"] / len(jobs)
+    mean_gap = float(np.mean(np.diff([0.0] + [r["arrival"] for r in reqs])))
+    scale = service / 0.7 / mean_gap
+    res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale)
+    res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale)
+    worst = max(max(r["relres"]) for r in res_b + res_s)
+    return {"requests": len(jobs), "unknowns_x_rhs": int(sum(j["A"].shape[0] * j["b"].shape[1] for j in jobs)),
+            "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": 0.7,
+            "batched_fp32": {k: batched[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
+            "plain_fp64": {k: plain[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
+            "max_relres": worst, "unit": "unknowns*rhs/s"}
 
 
 def cpu_baseline(prob, eps, tol):
@@ -236,6 +271,8 @@ def main():
                    "factor_bytes": st["factor_bytes"], "top_separator": st["top_separator"]},
         "roofline": roof,
     }
+    if args.serving_requests > 0:
+        out["serving"] = serving(args.serving_requests, args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, args.eps, args.tol)
     print(json.dumps(out), flush=True)

@@ -62,7 +62,9 @@ typedef struct {
  * m = lo + floor((w-2)/2), separator {m, m+1}; separator interfaces are the
  * classes of the pair of level-k ancestors of the deepest nodes touched on
  * each side (modified ND, Figs. mnd and mnd_multilvl).
- * nlevels <= 0 selects ceil(log2(N/64)) (Section 4, setup).
+ * nlevels <= 0 selects ceil(log2(N/64)) (Section 4, setup), capped at the
+ * deepest tree the grid allows (every box above the leaves needs a longest
+ * extent >= 4); an explicit nlevels deeper than that is EINVAL.
  * Errors: EINVAL if dim is not 2 or 3, a side is < 1, or a box above the
  * leaves has its longest extent < 4.  *out is library-owned; release it with
  * spaqr_ordering_free. */
@@ -221,18 +223,33 @@ spaqr_status spaqr_profile_query(const char* kernel, int64_t* launches, double* 
 void spaqr_free(spaqr_handle* h);
 
 /* ----------------------------------------------------------------- serving */
-/* Continuous-batching request loop.  Requests (a matrix, its grid ordering,
- * options and nrhs right-hand sides) are copied at submission, admitted when
- * their estimated factor memory fits the budget, and factorized stage by
- * stage together with every other admitted request: each stage's fronts,
- * scalings and sparsifications of all requests share one launch per phase.
- * Factored requests are solved with batched multi-RHS FGMRES and retired.
- * spaqr_submit returns ENOMEM only if the request alone exceeds the budget;
- * otherwise it is queued.  spaqr_server_step advances every in-flight request
- * by one stage (or solve) and admits new ones; spaqr_poll returns OK and
- * fills x (host, n x nrhs, ld = n) and info (nrhs entries) once the ticket
- * is done, ENOCONV-style warnings included, or SPAQR_EINVAL-free status 2
- * (SPAQR_PENDING) while it is not. */
+/* Continuous-batching request loop (no counterpart in the paper, which
+ * factors one matrix at a time).
+ *
+ * spaqr_server_create: mem_budget = bytes of device memory the resident
+ *   requests may use (by the estimate below); hip_stream = the stream every
+ *   request's work runs on (NULL: the default stream).  The server owns the
+ *   factors of its requests.
+ * spaqr_submit: copies A, the ordering, the options (NULL: defaults) and
+ *   b (host, n x nrhs column-major, ld = n) and queues the request; *ticket
+ *   names it.  Returns ENOMEM if the request's estimated memory (factors plus
+ *   FGMRES bases) alone exceeds the budget, EINVAL on bad arguments.
+ * spaqr_server_step: one round of the loop: (1) admits queued requests in
+ *   arrival order while the budget allows (symbolic analysis and upload);
+ *   (2) advances every admitted request that is still factoring by one stage,
+ *   all of them together: their fronts, scalings and sparsifications share
+ *   one launch per phase whatever stage each one is at, so a request that
+ *   arrives while others are half-way joins their batch; (3) solves every
+ *   request whose factorization is complete, all its right-hand sides at once
+ *   (multi-RHS FGMRES to its tol), and retires it.  *active (may be NULL)
+ *   receives the number of requests still queued or in flight.  A request
+ *   whose factorization fails (zero column, zero R_ss diagonal) is retired
+ *   with that status; the others continue.
+ * spaqr_poll: SPAQR_PENDING (2) while the ticket is not done; afterwards the
+ *   request's final status (OK, ENOCONV, or the error it failed with), with
+ *   x (host, n x nrhs, ld = n) and info (nrhs entries) filled when solved.
+ *   A ticket can be polled to completion once.
+ * One thread drives a server at a time. */
 #define SPAQR_PENDING 2
 typedef struct spaqr_server spaqr_server;
 spaqr_status spaqr_server_create(size_t mem_budget, void* hip_stream, spaqr_server** out);

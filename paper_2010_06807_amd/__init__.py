@@ -58,7 +58,8 @@ class GridOrdering:
         self.levels = lib.spaqr_ordering_levels(h)
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _abi is not None:
             _abi.load().spaqr_ordering_free(self._h)
             self._h = None
 
@@ -111,7 +112,8 @@ class Symbolic:
         self.levels = ordering.levels
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _abi is not None:
             _abi.load().spaqr_symbolic_free(self._h)
             self._h = None
 
@@ -191,7 +193,8 @@ class Factorization:
         self.n = A.shape[0]
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _abi is not None:
             _abi.load().spaqr_free(self._h)
             self._h = None
 

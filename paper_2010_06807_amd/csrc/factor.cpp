@@ -891,13 +891,48 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
       b = e;
     }
   }
+  // interfaces beyond one workgroup: the cooperative CPQR, several interfaces
+  // per launch (64 * cpt columns per one-wave workgroup; cpt grows until the
+  // whole set can be co-resident)
+  int64_t ncoop = 0;
+  std::vector<CoopItem> items;
+  int coop_cpt = 0, coop_blocks = 0, coop_maxp = 1, coop_kmax = 0;
+  if ((int64_t)sd.size() > nreg) {
+    int maxp = 1, maxnb = 0, kmax = 0;
+    for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
+      maxp = std::max<int>(maxp, sd[t].P);
+      maxnb = std::max(maxnb, sd[t].nrow + sd[t].ncol);
+      kmax = std::max(kmax, std::min<int>(sd[t].P, sd[t].mmax));
+    }
+    for (int cpt : {1, 2, 4, 8}) {
+      int64_t tot = 0;
+      for (size_t t = (size_t)nreg; t < sd.size(); ++t) tot += (sd[t].mmax + 64 * cpt - 1) / (64 * cpt);
+      if (tot <= 1024 && tot <= sparsify_coop_capacity<T>(cpt, maxp, maxnb)) {
+        coop_cpt = cpt;
+        coop_blocks = (int)tot;
+        break;
+      }
+    }
+    if (coop_cpt > 0) {
+      ncoop = (int64_t)sd.size() - nreg;
+      int first = 0;
+      for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
+        const int nb_t = (sd[t].mmax + 64 * coop_cpt - 1) / (64 * coop_cpt);
+        items.push_back({first, nb_t});
+        first += nb_t;
+      }
+      coop_maxp = maxp;
+      coop_kmax = kmax;
+    }
+  }
   // the rest: interfaces of at most 64 (FP32) or 32 (FP64) unknowns to the LDS
   // kernel, the others to the generic one
   constexpr int kSmallP = sizeof(T) == 4 ? 64 : 32;
-  std::stable_partition(sd.begin() + nreg, sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
+  const int64_t nrest0 = nreg + ncoop;
+  std::stable_partition(sd.begin() + nrest0, sd.end(), [](const SpDesc<T>& q) { return q.P <= kSmallP; });
   int64_t nsmall = 0;
   int pmax_small = 1, mmax_small = 1;
-  for (size_t t = (size_t)nreg; t < sd.size(); ++t)
+  for (size_t t = (size_t)nrest0; t < sd.size(); ++t)
     if (sd[t].P <= kSmallP) {
       ++nsmall;
       pmax_small = std::max<int>(pmax_small, sd[t].P);
@@ -907,11 +942,27 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
   SpDesc<T>* dsd = up.upload(wk, sd, s);
   SpNbr* dnb = up.upload(wk, nb, s);
+  double* ckey = nullptr;
+  int* cpos = nullptr;
+  T* ccol = nullptr;
+  int* done = nullptr;
+  CoopItem* ditems = nullptr;
+  if (ncoop > 0) {
+    ckey = wk.alloc_n<double>(2 * (size_t)coop_blocks, s);
+    cpos = wk.alloc_n<int>(2 * (size_t)coop_blocks, s);
+    ccol = wk.alloc_n<T>(2 * (size_t)coop_blocks * coop_maxp, s);
+    done = wk.alloc_n<int>(2 * (size_t)ncoop, s);
+    ditems = up.upload(wk, items, s);
+    launch_zero_ops({{done, 2 * ncoop * (int64_t)sizeof(int)}}, up, wk, s);
+  }
   ProfScope ps("sparsify", s, 0.0, 0.0);  // work added after the rank readback
   for (const auto& g : groups)
     launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, (int)g[2], (int)g[3], max_nb, s);
-  launch_sparsify_small<T>(dsd + nreg, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
-  launch_sparsify<T>(dsd + nreg + nsmall, (int64_t)sd.size() - nreg - nsmall, dnb, max_pc, max_nb, s);
+  if (ncoop > 0 && !launch_sparsify_coop<T>(dsd + nreg, ditems, (int)ncoop, coop_blocks, coop_cpt, dnb, coop_maxp,
+                                           max_nb, ckey, cpos, ccol, done, coop_kmax, s))
+    throw Error(SPAQR_EDEVICE, "cooperative CPQR no longer fits the device");
+  launch_sparsify_small<T>(dsd + nrest0, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
+  launch_sparsify<T>(dsd + nrest0 + nsmall, (int64_t)sd.size() - nrest0 - nsmall, dnb, max_pc, max_nb, s);
 }
 
 template <typename T>

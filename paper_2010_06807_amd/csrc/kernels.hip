@@ -12,6 +12,7 @@
 //   k_ap_*        the preconditioner apply (Section 2.8): one wavefront per
 //                 front or interface, FP64 vectors, coalesced reads of the
 //                 column-major factors
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1270,6 +1271,245 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
   }
 }
 
+// Cooperative partial CPQR (same method and pivot rule as k_cpqr_reg) for
+// interfaces whose columns do not fit one workgroup.  Every workgroup is one
+// wavefront owning columns (g cpt + j) 64 + lane of its interface; C is
+// row-major in global memory (coalesced rows, mostly L2-resident).  Per pivot
+// step: each workgroup publishes its best live column (FP64 norm, position,
+// values) in a double-buffered slot, one grid-wide barrier, then every
+// workgroup of the interface picks the same winner, forms the Householder
+// vector (dlarfg convention) in LDS and updates its own columns.  Interfaces
+// that stopped keep taking part in the barriers; the loop ends for the whole
+// grid once every interface has reported done (flags double-buffered by step
+// parity, so all workgroups read the same flags after a barrier).
+template <typename T, int CPT>
+__global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ descs, const SpNbr* __restrict__ nbrs,
+                                                 const CoopItem* __restrict__ items, int nitems, int total_blocks,
+                                                 int max_p, int max_nb, double* ckey, int* cpos, T* ccol, int* done,
+                                                 int kmax_all) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* vbuf = reinterpret_cast<T*>(smem);                      // max_p
+  int* off = reinterpret_cast<int*>(vbuf + ((max_p + 3) & ~3));  // max_nb + 1
+  const int b = blockIdx.x, lane = threadIdx.x;
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int it = lo;
+  const CoopItem ci = items[it];
+  const SpDesc<T> d = descs[it];
+  const int g = b - ci.first;
+  const int P = d.P;
+  const int64_t ldm = d.mmax;
+  T* C = d.C;
+  const int nnb = d.nrow + d.ncol;
+  const SpNbr* nb = nbrs + d.nb;
+  bool fin = !(P > 0 && *d.flag == 0);  // not scaled: rank stays P, nothing to do
+  if (lane == 0) {
+    int o = 0;
+    for (int q = 0; q < nnb; ++q) {
+      off[q] = o;
+      o += d.rank[nb[q].cluster];
+    }
+    off[nnb] = o;
+  }
+  __syncthreads();
+  const int m = off[nnb];
+  auto col_src = [&](int c, int64_t& str) -> T* {
+    int q = 0;
+    while (off[q + 1] <= c) ++q;
+    const int ai = c - off[q];
+    T* blk = d.pool + nb[q].blk;
+    const int64_t ld = nb[q].ld;
+    str = q < d.nrow ? 1 : ld;
+    return q < d.nrow ? blk + (int64_t)ai * ld : blk + ai;
+  };
+  double nr[CPT];
+  int pos[CPT], kel[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = (g * CPT + j) * 64 + lane;
+    pos[j] = c;
+    kel[j] = -1;
+    nr[j] = -1.0;
+    if (!fin && c < m) {
+      int64_t str = 0;
+      const T* src = col_src(c, str);
+      double s2 = 0.0;
+      for (int q0 = 0; q0 < P; q0 += 16) {
+        T x[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = q0 + e < P ? src[(int64_t)(q0 + e) * str] : T(0);
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+          if (q0 + e < P) {
+            C[(int64_t)(q0 + e) * ldm + c] = x[e];
+            s2 += (double)x[e] * (double)x[e];
+          }
+      }
+      nr[j] = s2;
+    }
+  }
+  if (fin && g == 0 && lane == 0) {
+    done[it] = 1;
+    done[nitems + it] = 1;
+  }
+  const int kmax = min(P, m);
+  int r = 0;
+  double R11 = 0.0;
+  for (int k = 0; k <= kmax_all; ++k) {
+    const int buf = k & 1;
+    // this workgroup's best live column: (norm desc, position asc)
+    double wb = -1.0;
+    int wp = 0x7fffffff, wc = -1;
+    if (!fin)
+#pragma unroll
+      for (int j = 0; j < CPT; ++j)
+        if (kel[j] < 0 && nr[j] >= 0.0 && (nr[j] > wb || (nr[j] == wb && pos[j] < wp))) {
+          wb = nr[j];
+          wp = pos[j];
+          wc = (g * CPT + j) * 64 + lane;
+        }
+    {
+      auto merge = [&](double ob, int op, int oc) {
+        if (ob > wb || (ob == wb && op < wp)) {
+          wb = ob;
+          wp = op;
+          wc = oc;
+        }
+      };
+      merge(xshfl<32>(wb), xshfl<32>(wp), xshfl<32>(wc));
+      merge(xshfl<16>(wb), xshfl<16>(wp), xshfl<16>(wc));
+      merge(xshfl<8>(wb), xshfl<8>(wp), xshfl<8>(wc));
+      merge(xshfl<4>(wb), xshfl<4>(wp), xshfl<4>(wc));
+      merge(xshfl<2>(wb), xshfl<2>(wp), xshfl<2>(wc));
+      merge(xshfl<1>(wb), xshfl<1>(wp), xshfl<1>(wc));
+    }
+    T* cc = ccol + ((int64_t)buf * total_blocks + b) * max_p;
+    if (wc >= 0)
+      for (int q = lane; q < P; q += 64) cc[q] = C[q * ldm + wc];
+    if (lane == 0) {
+      ckey[buf * total_blocks + b] = wb;
+      cpos[buf * total_blocks + b] = wp;
+    }
+    grid.sync();
+    // every interface done (flags written before this barrier): leave together
+    int notdone = 0;
+    for (int i = lane; i < nitems; i += 64) notdone |= done[buf * nitems + i] == 0;
+    if (__ballot(notdone) == 0ull) break;
+    if (!fin) {
+      // the interface's winner among its workgroups
+      double gb = -1.0;
+      int gp = 0x7fffffff, gw = -1;
+      for (int w = lane; w < ci.nblk; w += 64) {
+        const double ob = ckey[buf * total_blocks + ci.first + w];
+        const int op = cpos[buf * total_blocks + ci.first + w];
+        if (ob > gb || (ob == gb && op < gp)) {
+          gb = ob;
+          gp = op;
+          gw = w;
+        }
+      }
+      {
+        auto merge = [&](double ob, int op, int ow) {
+          if (ob > gb || (ob == gb && op < gp)) {
+            gb = ob;
+            gp = op;
+            gw = ow;
+          }
+        };
+        merge(xshfl<32>(gb), xshfl<32>(gp), xshfl<32>(gw));
+        merge(xshfl<16>(gb), xshfl<16>(gp), xshfl<16>(gw));
+        merge(xshfl<8>(gb), xshfl<8>(gp), xshfl<8>(gw));
+        merge(xshfl<4>(gb), xshfl<4>(gp), xshfl<4>(gw));
+        merge(xshfl<2>(gb), xshfl<2>(gp), xshfl<2>(gw));
+        merge(xshfl<1>(gb), xshfl<1>(gp), xshfl<1>(gw));
+      }
+      const double rkk = sqrt(max(gb, 0.0));
+      if (k == 0) R11 = rkk;
+      const bool stop = k >= kmax || gw < 0 || R11 == 0.0 || (d.eps > 0.0 && rkk < d.eps * R11);
+      if (stop) {
+        fin = true;
+      } else {
+        const T* xw = ccol + ((int64_t)buf * total_blocks + ci.first + gw) * max_p;
+        double s = 0.0, alpha = 0.0;
+        for (int q = lane; q < P; q += 64) {
+          const double x = (double)xw[q];
+          if (q > k) s += x * x;
+          if (q == k) alpha = x;
+        }
+        s = wave_sum(s);
+        alpha = wave_sum(alpha);
+        double beta, tau, scal;
+        householder(alpha, s, beta, tau, scal);
+        for (int q = lane; q < P; q += 64) {
+          const double v = q < k ? 0.0 : (q == k ? 1.0 : (double)xw[q] * scal);
+          vbuf[q] = (T)v;
+          if (g == 0) d.vq[(int64_t)q + (int64_t)k * P] = (T)v;
+        }
+        if (g == 0 && lane == 0) d.tauq[k] = (T)tau;
+        __syncthreads();
+        const T tt = (T)tau, bt = (T)beta;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          if (kel[j] >= 0 || nr[j] < 0.0) continue;
+          const int c = (g * CPT + j) * 64 + lane;
+          if (pos[j] == gp) {
+            kel[j] = k;
+            pos[j] = k;
+            C[(int64_t)k * ldm + c] = bt;
+            continue;
+          }
+          if (pos[j] == k) pos[j] = gp;
+          // rows k..P-1 in chunks of 16 independent loads
+          constexpr int CH = 16;
+          T w = T(0);
+          for (int q0 = k; q0 < P; q0 += CH) {
+            T x[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) x[e] = q0 + e < P ? C[(int64_t)(q0 + e) * ldm + c] : T(0);
+#pragma unroll
+            for (int e = 0; e < CH; ++e) w += (q0 + e < P ? vbuf[q0 + e] : T(0)) * x[e];
+          }
+          const T tw = tt * w;
+          double s2 = 0.0;
+          for (int q0 = k; q0 < P; q0 += CH) {
+            T x[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) x[e] = q0 + e < P ? C[(int64_t)(q0 + e) * ldm + c] : T(0);
+#pragma unroll
+            for (int e = 0; e < CH; ++e)
+              if (q0 + e < P) {
+                const T y = x[e] - tw * vbuf[q0 + e];
+                C[(int64_t)(q0 + e) * ldm + c] = y;
+                if (q0 + e > k) s2 += (double)y * (double)y;
+              }
+          }
+          nr[j] = s2;
+        }
+        r = k + 1;
+        __syncthreads();
+      }
+    }
+    if (fin && g == 0 && lane == 0) done[((k + 1) & 1) * nitems + it] = 1;
+  }
+  if (P > 0 && *d.flag == 0 && r < P) {
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int c = (g * CPT + j) * 64 + lane;
+      if (c >= m) continue;
+      int64_t str = 0;
+      T* dst = col_src(c, str);
+      for (int q = 0; q < r; ++q) dst[q * str] = (kel[j] >= 0 && q > kel[j]) ? T(0) : C[q * ldm + c];
+    }
+    if (g == 0 && lane == 0) d.rank[d.cluster] = r;
+  }
+}
+
 // ---------------------------------------------------------------- apply
 // Rows of a work vector are owned by lane (row % 64) for the whole kernel, so
 // a wavefront needs no barrier between reflectors.
@@ -2125,6 +2365,57 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pma
   throw Error(SPAQR_EINVAL, "unsupported register CPQR shape");
 }
 
+static size_t coop_lds(int max_p, int max_nb, int eb) {
+  return (size_t)((max_p + 3) & ~3) * eb + (size_t)(max_nb + 1) * sizeof(int);
+}
+
+template <typename T, int CPT>
+static int coop_capacity_t(int max_p, int max_nb) {
+  int per_cu = 0, dev = 0, cus = 0;
+  const size_t lds = coop_lds(max_p, max_nb, sizeof(T));
+  if (lds > 64 * 1024) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_cpqr_coop<T, CPT>), 64,
+                                                   lds) != hipSuccess)
+    return 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
+template <typename T>
+int sparsify_coop_capacity(int cpt, int max_p, int max_nb) {
+  switch (cpt) {
+    case 1: return coop_capacity_t<T, 1>(max_p, max_nb);
+    case 2: return coop_capacity_t<T, 2>(max_p, max_nb);
+    case 4: return coop_capacity_t<T, 4>(max_p, max_nb);
+    case 8: return coop_capacity_t<T, 8>(max_p, max_nb);
+    default: return 0;
+  }
+}
+
+template <typename T>
+bool launch_sparsify_coop(const SpDesc<T>* d, const CoopItem* items, int nitems, int total_blocks, int cpt,
+                          const SpNbr* nb, int max_p, int max_nb, double* ckey, int* cpos, T* ccol, int* done,
+                          int kmax_all, hipStream_t s) {
+  if (nitems <= 0) return true;
+  if (total_blocks > sparsify_coop_capacity<T>(cpt, max_p, max_nb)) return false;
+  const size_t lds = coop_lds(max_p, max_nb, sizeof(T));
+  void* args[] = {(void*)&d, (void*)&nb, (void*)&items, (void*)&nitems, (void*)&total_blocks, (void*)&max_p,
+                  (void*)&max_nb, (void*)&ckey, (void*)&cpos, (void*)&ccol, (void*)&done, (void*)&kmax_all};
+  const void* fn = nullptr;
+  switch (cpt) {
+    case 1: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 1>); break;
+    case 2: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 2>); break;
+    case 4: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 4>); break;
+    case 8: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 8>); break;
+    default: throw Error(SPAQR_EINVAL, "unsupported columns per thread in the cooperative CPQR");
+  }
+  const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)total_blocks), dim3(64), args, lds, s);
+  if (e != hipSuccess)
+    throw Error(SPAQR_EDEVICE, std::string("cooperative launch of k_cpqr_coop failed: ") + hipGetErrorString(e));
+  return true;
+}
+
 static constexpr size_t kApplyLds = 64 * 1024;
 
 int apply_rhs_block(int max_rows, int nrhs) {
@@ -2274,6 +2565,9 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_front_bwd_reg<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
   template void launch_iface_small<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t); \
   template void launch_iface_form<T>(const ApIface<T>*, int64_t, hipStream_t);                       \
+  template int sparsify_coop_capacity<T>(int, int, int);                                               \
+  template bool launch_sparsify_coop<T>(const SpDesc<T>*, const CoopItem*, int, int, int, const SpNbr*, int, int, \
+                                        double*, int*, T*, int*, int, hipStream_t);                    \
   template void launch_iface_dense<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t);
 SPAQR_INST(float)
 SPAQR_INST(double)

@@ -167,6 +167,24 @@ template <typename T>
 void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
                           hipStream_t s);
 // Interfaces of at most 64 unknowns: one wavefront, one row per lane.
+// Cooperative CPQR for interfaces too large for one workgroup: interface i
+// owns workgroups [first, first + nblk) of one cooperative launch (64 threads
+// each, 64 * cpt columns per workgroup); C lives row-major in the
+// interface's workspace (d.C, leading dimension d.mmax).
+struct CoopItem {
+  int32_t first, nblk;
+};
+// Returns false (nothing launched) if the items cannot be co-resident; then
+// the caller falls back to the single-workgroup kernels.
+template <typename T>
+bool launch_sparsify_coop(const SpDesc<T>* d, const CoopItem* items, int nitems, int total_blocks, int cpt,
+                          const SpNbr* nb, int max_p, int max_nb, double* ckey, int* cpos, T* ccol, int* done,
+                          int kmax_all, hipStream_t s);
+// Largest number of one-wave workgroups that can be co-resident for the
+// cooperative CPQR with columns-per-thread cpt and rows max_p.
+template <typename T>
+int sparsify_coop_capacity(int cpt, int max_p, int max_nb);
+
 // Dense interface operators (P <= 64): mf = Q^T U^T and mb = R_pp^{-1} Q,
 // one thread per column; then the apply multiplies by them.
 template <typename T>

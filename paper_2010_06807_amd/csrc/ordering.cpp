@@ -17,6 +17,7 @@
 // lexicographically) and listing points in natural order inside each triple
 // gives the permutation, and every coarser cluster is a run of triples.
 #include <algorithm>
+#include <array>
 #include <memory>
 #include <numeric>
 
@@ -63,6 +64,34 @@ Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
     L = 0;
     while ((int64_t(64) << L) < n) ++L;
     L = std::max(1, L);
+    // capped at the deepest tree whose boxes above the leaves all split
+    // (longest extent >= 4); the extents of a box's children follow the
+    // split rule below, so the boxes of each level are simulated in turn
+    std::vector<std::array<int64_t, 3>> box{{sides[0], dim > 1 ? sides[1] : 1, dim > 2 ? sides[2] : 1}};
+    int depth = 1;
+    while (depth < L) {
+      std::vector<std::array<int64_t, 3>> next;
+      bool ok = true;
+      for (const auto& e : box) {
+        int ax = 0;
+        for (int a = 1; a < dim; ++a)
+          if (e[a] > e[ax]) ax = a;
+        if (e[ax] < 4) {
+          ok = false;
+          break;
+        }
+        const int64_t lw = (e[ax] - 2) / 2;
+        auto c0 = e, c1 = e;
+        c0[ax] = lw;
+        c1[ax] = e[ax] - 2 - lw;
+        next.push_back(c0);
+        next.push_back(c1);
+      }
+      if (!ok) break;
+      box.swap(next);
+      ++depth;
+    }
+    L = std::min(L, depth);
   }
   SPAQR_REQUIRE(L >= 1 && L <= 30, SPAQR_EINVAL, "levels out of range");
 

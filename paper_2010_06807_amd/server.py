@@ -20,7 +20,8 @@ class Server:
         self._keep = {}
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "_h", None) and _abi is not None:
             _abi.load().spaqr_server_destroy(self._h)
             self._h = None
 

@@ -7,7 +7,7 @@ import math
 
 import numpy as np
 
-from .grids import convdiff, default_levels, make_rhs
+from .grids import convdiff, make_rhs
 
 
 def serving_trace(nreq=512, seed=0, rate=100.0, side2d=(64, 512), side3d=(16, 48),
@@ -44,4 +44,6 @@ def build_request(req):
     A = convdiff(dims, req["beta"])
     N = A.shape[0]
     b = make_rhs(N, req["nrhs"], req["rhs_seed"])
-    return dict(A=A, dims=dims, levels=default_levels(N), b=b)
+    # levels 0: the solver's default depth, ceil(log2(N / 64)) capped at the
+    # deepest tree the grid allows (some 3D sides cannot take the full depth)
+    return dict(A=A, dims=dims, levels=0, b=b)

@@ -59,6 +59,20 @@ def test_default_levels():
     assert P.order_grid((64, 64, 64)).levels == 12
 
 
+def test_default_levels_capped_by_the_grid():
+    """ceil(log2(N/64)) = 8 for 21^3, but a box of the 8th level would need a
+    split of a box narrower than 4: the default stops at 7, and asking for 8
+    explicitly is an error."""
+    assert P.order_grid((21, 21, 21)).levels == 7
+    assert P.order_grid((44, 44, 44)).levels == 10
+    with pytest.raises(_abi.SpaqrError):
+        P.order_grid((21, 21, 21), 8)
+    # the capped default is a valid ordering: the oracle builds the same one
+    o = P.order_grid((21, 21, 21))
+    ob = oracle_order((21, 21, 21), 7)
+    assert np.array_equal(o.perm(), ob.perm)
+
+
 @pytest.mark.parametrize("dims,L,eps", [((32, 32), 5, 1e-3), ((24, 24), 5, 1e-2), ((8, 8, 8), 4, 1e-2),
                                         ((16, 16, 16), 6, 1e-2), ((64, 64), 7, 1e-2), ((20, 13), 4, 1e-2)])
 def test_symbolic_bit_exact(dims, L, eps):

@@ -209,3 +209,28 @@ def test_kernel_profiler_counts_launches():
     assert P.profile_query("front_qr")["launches"] == 0
     assert P.profile_query("sparsify")["launches"] > 0
     P.profile_enable(False)
+
+
+def test_3d_wide_interfaces_against_oracle():
+    """20^3 grid: the coarse interfaces have more than 64 unknowns and
+    thousands of columns, so the sparsification runs in the cooperative
+    multi-workgroup CPQR.  FP64 ranks within +-1 of the oracle, iteration
+    counts within the 10% bar, both solves at 1e-10."""
+    print("case 3d 20^3 fp64 eps=1e-2", flush=True)
+    dims = (20, 20, 20)
+    A = convdiff(dims, (5.0, 5.0, 5.0))
+    N = A.shape[0]
+    L = P.order_grid(dims).levels
+    F = _oracle(A, dims, L, 1e-2)
+    assert max(max(r for r in F.stages[k]["ranks"].values()) for k in F.stages
+               if F.stages[k]["sparsified"]) > 64
+    fac = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=64)
+    _ranks_agree(fac, F, L, 1)
+    b = make_rhs(N, 1, seed=3)[:, 0]
+    x, info = fac.solve(b, tol=1e-10)
+    it_o, rel_o = _oracle_its(A, F, b)
+    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 1e-10
+    assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o))
+    fac32 = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=32)
+    x32, info32 = fac32.solve(b, tol=1e-10)
+    assert np.linalg.norm(A @ x32 - b) / np.linalg.norm(b) <= 1e-10
