@@ -1282,7 +1282,7 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
 // that stopped keep taking part in the barriers; the loop ends for the whole
 // grid once every interface has reported done (flags double-buffered by step
 // parity, so all workgroups read the same flags after a barrier).
-template <typename T, int CPT>
+template <typename T, int CPT, bool LC>
 __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ descs, const SpNbr* __restrict__ nbrs,
                                                  const CoopItem* __restrict__ items, int nitems, int total_blocks,
                                                  int max_p, int max_nb, double* ckey, int* cpos, T* ccol, int* done,
@@ -1291,7 +1291,8 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
   cg::grid_group grid = cg::this_grid();
   extern __shared__ __align__(16) unsigned char smem[];
   T* vbuf = reinterpret_cast<T*>(smem);                      // max_p
-  int* off = reinterpret_cast<int*>(vbuf + ((max_p + 3) & ~3));  // max_nb + 1
+  T* cl = vbuf + ((max_p + 3) & ~3);                          // LC: P x 64 CPT, this workgroup's columns
+  int* off = reinterpret_cast<int*>(cl + (LC ? (size_t)max_p * 64 * CPT : 0));  // max_nb + 1
   const int b = blockIdx.x, lane = threadIdx.x;
   int lo = 0, hi = nitems - 1;
   while (lo < hi) {
@@ -1304,8 +1305,11 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
   const SpDesc<T> d = descs[it];
   const int g = b - ci.first;
   const int P = d.P;
-  const int64_t ldm = d.mmax;
-  T* C = d.C;
+  // columns live in LDS (LC: local index j 64 + lane, leading dimension
+  // 64 CPT) or in the row-major global workspace (global index)
+  const int64_t ldm = LC ? 64 * CPT : d.mmax;
+  T* C = LC ? cl : d.C;
+  auto cidx = [&](int j) { return LC ? j * 64 + lane : (g * CPT + j) * 64 + lane; };
   const int nnb = d.nrow + d.ncol;
   const SpNbr* nb = nbrs + d.nb;
   bool fin = !(P > 0 && *d.flag == 0);  // not scaled: rank stays P, nothing to do
@@ -1340,6 +1344,7 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
       int64_t str = 0;
       const T* src = col_src(c, str);
       double s2 = 0.0;
+      const int ci = cidx(j);
       for (int q0 = 0; q0 < P; q0 += 16) {
         T x[16];
 #pragma unroll
@@ -1347,7 +1352,7 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
 #pragma unroll
         for (int e = 0; e < 16; ++e)
           if (q0 + e < P) {
-            C[(int64_t)(q0 + e) * ldm + c] = x[e];
+            C[(int64_t)(q0 + e) * ldm + ci] = x[e];
             s2 += (double)x[e] * (double)x[e];
           }
       }
@@ -1372,7 +1377,7 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
         if (kel[j] < 0 && nr[j] >= 0.0 && (nr[j] > wb || (nr[j] == wb && pos[j] < wp))) {
           wb = nr[j];
           wp = pos[j];
-          wc = (g * CPT + j) * 64 + lane;
+          wc = cidx(j);
         }
     {
       auto merge = [&](double ob, int op, int oc) {
@@ -1391,7 +1396,7 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
     }
     T* cc = ccol + ((int64_t)buf * total_blocks + b) * max_p;
     if (wc >= 0)
-      for (int q = lane; q < P; q += 64) cc[q] = C[q * ldm + wc];
+      for (int q = lane; q < P; q += 64) cc[q] = C[(int64_t)q * ldm + wc];
     if (lane == 0) {
       ckey[buf * total_blocks + b] = wb;
       cpos[buf * total_blocks + b] = wp;
@@ -1457,7 +1462,7 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
 #pragma unroll
         for (int j = 0; j < CPT; ++j) {
           if (kel[j] >= 0 || nr[j] < 0.0) continue;
-          const int c = (g * CPT + j) * 64 + lane;
+          const int c = cidx(j);
           if (pos[j] == gp) {
             kel[j] = k;
             pos[j] = k;
@@ -1504,7 +1509,8 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
       if (c >= m) continue;
       int64_t str = 0;
       T* dst = col_src(c, str);
-      for (int q = 0; q < r; ++q) dst[q * str] = (kel[j] >= 0 && q > kel[j]) ? T(0) : C[q * ldm + c];
+      const int ci = cidx(j);
+      for (int q = 0; q < r; ++q) dst[q * str] = (kel[j] >= 0 && q > kel[j]) ? T(0) : C[(int64_t)q * ldm + ci];
     }
     if (g == 0 && lane == 0) d.rank[d.cluster] = r;
   }
@@ -2365,32 +2371,43 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pma
   throw Error(SPAQR_EINVAL, "unsupported register CPQR shape");
 }
 
-static size_t coop_lds(int max_p, int max_nb, int eb) {
-  return (size_t)((max_p + 3) & ~3) * eb + (size_t)(max_nb + 1) * sizeof(int);
+static size_t coop_lds(int max_p, int max_nb, int eb, int cpt, bool lc) {
+  return (size_t)((max_p + 3) & ~3) * eb + (lc ? (size_t)max_p * 64 * cpt * eb : 0) +
+         (size_t)(max_nb + 1) * sizeof(int);
 }
 
-template <typename T, int CPT>
-static int coop_capacity_t(int max_p, int max_nb) {
-  int per_cu = 0, dev = 0, cus = 0;
-  const size_t lds = coop_lds(max_p, max_nb, sizeof(T));
-  if (lds > 64 * 1024) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_cpqr_coop<T, CPT>), 64,
-                                                   lds) != hipSuccess)
-    return 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return per_cu * cus;
+// columns stay in LDS when a workgroup's slice fits in 144 KB
+static bool coop_in_lds(int max_p, int cpt, int eb) { return (size_t)max_p * 64 * cpt * eb <= (size_t)144 * 1024; }
+
+template <typename T, int CPT, bool LC>
+static const void* coop_fn() {
+  return reinterpret_cast<const void*>(&k_cpqr_coop<T, CPT, LC>);
+}
+
+template <typename T>
+static const void* coop_kernel(int cpt, bool lc) {
+  switch (cpt) {
+    case 1: return lc ? coop_fn<T, 1, true>() : coop_fn<T, 1, false>();
+    case 2: return lc ? coop_fn<T, 2, true>() : coop_fn<T, 2, false>();
+    case 4: return lc ? coop_fn<T, 4, true>() : coop_fn<T, 4, false>();
+    case 8: return lc ? coop_fn<T, 8, true>() : coop_fn<T, 8, false>();
+    default: return nullptr;
+  }
 }
 
 template <typename T>
 int sparsify_coop_capacity(int cpt, int max_p, int max_nb) {
-  switch (cpt) {
-    case 1: return coop_capacity_t<T, 1>(max_p, max_nb);
-    case 2: return coop_capacity_t<T, 2>(max_p, max_nb);
-    case 4: return coop_capacity_t<T, 4>(max_p, max_nb);
-    case 8: return coop_capacity_t<T, 8>(max_p, max_nb);
-    default: return 0;
-  }
+  const bool lc = coop_in_lds(max_p, cpt, sizeof(T));
+  const void* fn = coop_kernel<T>(cpt, lc);
+  if (!fn) return 0;
+  const size_t lds = coop_lds(max_p, max_nb, sizeof(T), cpt, lc);
+  int per_cu = 0, dev = 0, cus = 0;
+  if (lds > 160 * 1024) return 0;
+  allow_lds(fn, lds, "k_cpqr_coop");
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, lds) != hipSuccess) return 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 template <typename T>
@@ -2399,17 +2416,12 @@ bool launch_sparsify_coop(const SpDesc<T>* d, const CoopItem* items, int nitems,
                           int kmax_all, hipStream_t s) {
   if (nitems <= 0) return true;
   if (total_blocks > sparsify_coop_capacity<T>(cpt, max_p, max_nb)) return false;
-  const size_t lds = coop_lds(max_p, max_nb, sizeof(T));
+  const bool lc = coop_in_lds(max_p, cpt, sizeof(T));
+  const size_t lds = coop_lds(max_p, max_nb, sizeof(T), cpt, lc);
   void* args[] = {(void*)&d, (void*)&nb, (void*)&items, (void*)&nitems, (void*)&total_blocks, (void*)&max_p,
                   (void*)&max_nb, (void*)&ckey, (void*)&cpos, (void*)&ccol, (void*)&done, (void*)&kmax_all};
-  const void* fn = nullptr;
-  switch (cpt) {
-    case 1: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 1>); break;
-    case 2: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 2>); break;
-    case 4: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 4>); break;
-    case 8: fn = reinterpret_cast<const void*>(&k_cpqr_coop<T, 8>); break;
-    default: throw Error(SPAQR_EINVAL, "unsupported columns per thread in the cooperative CPQR");
-  }
+  const void* fn = coop_kernel<T>(cpt, lc);
+  if (!fn) throw Error(SPAQR_EINVAL, "unsupported columns per thread in the cooperative CPQR");
   const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)total_blocks), dim3(64), args, lds, s);
   if (e != hipSuccess)
     throw Error(SPAQR_EDEVICE, std::string("cooperative launch of k_cpqr_coop failed: ") + hipGetErrorString(e));
