@@ -55,12 +55,17 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline (default: the slowest)")
-    ap.add_argument("--serving-requests", type=int, default=32,
+    ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the serving trace replayed after the single-problem steps (0: skip)")
     ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
                     help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
                          "directory of this script's run and exit")
     return ap.parse_args()
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def pct(v, q):
@@ -124,12 +129,16 @@ def serving(nreq, tol, seed=0):
         q = build_request(r)
         jobs.append(dict(arrival=r["arrival"], A=q["A"], ordering=P.order_grid(q["dims"], q["levels"]), b=q["b"],
                          eps=r["eps"]))
-    _, cal = serve_sequential(jobs, tol=tol, precision=64, time_scale=0.0)
+    log(f"serving: {len(jobs)} requests built; calibration pass (FP64, back to back)")
+    _, cal = serve_sequential(jobs, tol=tol, precision=64, time_scale=0.0, log=log)
+    log(f"serving: calibration {cal['makespan_s']:.1f} s")
     service = cal["makespan_s"] / len(jobs)
     mean_gap = float(np.mean(np.diff([0.0] + [r["arrival"] for r in reqs])))
     scale = service / 0.7 / mean_gap
-    res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale)
-    res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale)
+    res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale, log=log)
+    log(f"serving: batched FP32 makespan {batched['makespan_s']:.1f} s")
+    res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale, log=log)
+    log(f"serving: sequential FP64 makespan {plain['makespan_s']:.1f} s")
     worst = max(max(r["relres"]) for r in res_b + res_s)
     return {"requests": len(jobs), "unknowns_x_rhs": int(sum(j["A"].shape[0] * j["b"].shape[1] for j in jobs)),
             "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": 0.7,
@@ -216,6 +225,7 @@ def main():
         dt = time.perf_counter() - t0
         return dt, lat, infos, fac, x
 
+    log(f"{prob['name']}: N={N}, {L} levels; survey step")
     # which kernel dominates: one untimed step with every launch timed
     step(32)
     P.profile_enable(True)
@@ -227,8 +237,10 @@ def main():
     kern = args.kernel or max(survey, key=lambda n: survey[n]["total_ms"])
 
     # timed region: FP32 factors + FP64 GMRES, only the roofline kernel timed
+    log(f"timed FP32 steps (roofline kernel: {kern})")
     P.profile_enable(True, only=kern)
     dt, lat, infos, fac, x = run(32, args.steps, args.warmup)
+    log(f"FP32: {1e3 * dt / args.steps:.2f} ms/step")
     prof = P.profile_query(kern)
     P.profile_enable(False)
     res = float(np.linalg.norm(A @ x.cpu().numpy()[:, 0] - b.cpu().numpy()[:, 0]) / np.linalg.norm(b.cpu().numpy()))
@@ -237,6 +249,7 @@ def main():
 
     # plain FP64 GPU path
     dt64, lat64, infos64, fac64, x64 = run(64, args.fp64_steps, 1)
+    log(f"FP64 plain: {1e3 * dt64 / args.fp64_steps:.2f} ms/step")
     value64 = N * args.fp64_steps / dt64
 
     bound = KERNEL_BOUND[kern]
@@ -274,6 +287,7 @@ def main():
     if args.serving_requests > 0:
         out["serving"] = serving(args.serving_requests, args.tol)
     if not args.no_cpu_baseline:
+        log("oracle on the host (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(prob, args.eps, args.tol)
     print(json.dumps(out), flush=True)
 

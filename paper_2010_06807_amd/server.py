@@ -63,7 +63,7 @@ def _percentile(v, q):
     return v[i]
 
 
-def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_scale=1.0):
+def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_scale=1.0, log=None):
     """Replay a request trace through the continuous-batching server.
 
     jobs: list of dicts with `arrival` (seconds from the start), `A` (scipy
@@ -72,7 +72,8 @@ def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_sca
     time_scale); the loop steps the server while requests are in flight.
     Returns per-request dicts (latency_s = completion - arrival, iterations,
     relres) and a summary with throughput (unknowns x right-hand sides per
-    second over the makespan) and p50/p99 latency."""
+    second over the makespan) and p50/p99 latency.  log(str), if given, is
+    called as each request completes."""
     import time
     srv = Server(mem_budget, stream)
     order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
@@ -99,6 +100,8 @@ def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_sca
             x, info = out
             res[i] = dict(latency_s=time.perf_counter() - t0 - jobs[i]["arrival"] * time_scale, x=x,
                           iterations=[d["iterations"] for d in info], relres=[d["relres"] for d in info])
+            if log:
+                log(f"request {i} done, latency {res[i]['latency_s']:.3f} s")
     span = time.perf_counter() - t0
     work = sum(j["A"].shape[0] * (1 if np.ndim(j["b"]) == 1 else np.shape(j["b"])[1]) for j in jobs)
     lat = [r["latency_s"] for r in res]
@@ -106,7 +109,7 @@ def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_sca
                      p99_ms=1e3 * _percentile(lat, 99), requests=len(jobs))
 
 
-def serve_sequential(jobs, tol=1e-10, precision=64, time_scale=1.0):
+def serve_sequential(jobs, tol=1e-10, precision=64, time_scale=1.0, log=None):
     """The same trace without batching: requests run one at a time in arrival
     order (factor, then solve all of the request's right-hand sides), each
     starting no earlier than its arrival."""
@@ -125,6 +128,8 @@ def serve_sequential(jobs, tol=1e-10, precision=64, time_scale=1.0):
         del fac
         res[i] = dict(latency_s=time.perf_counter() - t0 - j["arrival"] * time_scale, x=x,
                       iterations=[d["iterations"] for d in info], relres=[d["relres"] for d in info])
+        if log:
+            log(f"request {i} done, latency {res[i]['latency_s']:.3f} s")
     span = time.perf_counter() - t0
     work = sum(j["A"].shape[0] * (1 if np.ndim(j["b"]) == 1 else np.shape(j["b"])[1]) for j in jobs)
     lat = [r["latency_s"] for r in res]
