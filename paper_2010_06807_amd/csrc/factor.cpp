@@ -114,6 +114,10 @@ struct StagePlan {
   struct FrontColour {
     std::vector<CopyTile<T>> gather, scatter;
     std::vector<QRDesc<T>> qr;
+    // fronts with many trailing columns or rows: pivot block factored alone,
+    // trailing columns updated slice by slice
+    std::vector<TrailDesc<T>> trail;
+    int trail_cw = 0, trail_max_m = 1;
     int max_m = 1;
     double flops = 0.0, bytes = 0.0;
   };
@@ -361,8 +365,9 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
 
   // ------------------------------------------------------------ fronts
   const int64_t nf = (int64_t)ss.fronts.size();
-  std::vector<int32_t> fm(nf), fn(nf), fnc(nf);
+  std::vector<int32_t> fm(nf), fn(nf), fnc(nf), fld(nf);
   std::vector<int64_t> ws_off(nf + 1, 0), vr_off(nf + 1, 0), rsj_off(nf + 1, 0), tau_off(nf + 1, 0);
+  constexpr int VA = 16 / (int)sizeof(T);  // workspace rows start on 16-byte boundaries
   int max_m = 1;
   for (int64_t f = 0; f < nf; ++f) {
     const FrontSym& F = ss.fronts[f];
@@ -372,7 +377,10 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
     fm[f] = m;
     fn[f] = size_[F.cluster];
     fnc[f] = nc;
-    ws_off[f + 1] = ws_off[f] + (int64_t)m * nc;
+    // rows hold whole 16-column panels of the pivot block, so the trailing
+    // update of a split front reads its V rows as aligned vectors in bounds
+    fld[f] = std::max((nc + VA - 1) / VA * VA, (size_[F.cluster] + 15) / 16 * 16);
+    ws_off[f + 1] = ws_off[f] + (int64_t)m * fld[f];
     vr_off[f + 1] = vr_off[f] + (int64_t)m * fn[f];
     rsj_off[f + 1] = rsj_off[f] + (int64_t)fn[f] * (nc - fn[f]);
     tau_off[f + 1] = tau_off[f] + fn[f];
@@ -396,11 +404,23 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
   ap.jb = jbf;
   for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
     typename StagePlan<T>::FrontColour fc;
+    // slice width of this colour's split fronts
+    {
+      int mm = 0;
+      for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
+        const int32_t f = ss.front_order[oi];
+        if (fn[f] > 0 && (fm[f] > 1024 || fnc[f] - fn[f] >= 256)) mm = std::max(mm, fm[f]);
+      }
+      if (mm > 0) {
+        fc.trail_cw = trail_width(mm, sizeof(T));
+        fc.trail_max_m = mm;
+      }
+    }
     for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
       const int32_t f = ss.front_order[oi];
       const FrontSym& F = ss.fronts[f];
       T* Wf = W + ws_off[f];
-      const int32_t nc = fnc[f], n = fn[f];
+      const int32_t nc = fnc[f], n = fn[f], ldw = fld[f];
       std::vector<int32_t> rows{F.cluster}, cols{F.cluster};
       rows.insert(rows.end(), F.n1.begin(), F.n1.end());
       cols.insert(cols.end(), F.cols.begin(), F.cols.end());
@@ -411,11 +431,11 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         for (size_t b = 0; b < cols.size(); ++b) {
           const int32_t j = cols[b];
           if (size_[i] > 0 && size_[j] > 0) {
-            fc.gather.push_back({blk(i, j), Wf + (int64_t)ro * nc + co, size_[i], size_[j], size_[j], nc, 0, 0});
+            fc.gather.push_back({blk(i, j), Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw, 0, 0});
             if (a > 0 && b > 0) {
               T* dst = blk(i, j);
               SPAQR_REQUIRE(dst != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
-              fc.scatter.push_back({Wf + (int64_t)ro * nc + co, dst, size_[i], size_[j], nc, size_[j], 0, 0});
+              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, dst, size_[i], size_[j], ldw, size_[j], 0, 0});
             }
           }
           co += size_[j];
@@ -423,7 +443,11 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         ro += size_[i];
       }
       if (n > 0) {
-        fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, nc, 0});
+        const bool split = fc.trail_cw > 0 && (fm[f] > 1024 || nc - n >= 256);
+        fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, split ? n : nc, ldw});
+        if (split)
+          for (int c0 = n; c0 < nc; c0 += fc.trail_cw)
+            fc.trail.push_back({Wf, TPF + tp_off[f], fm[f], n, ldw, c0, std::min(fc.trail_cw, nc - c0), 0});
         fc.max_m = std::max(fc.max_m, fm[f]);
         const double mm = fm[f], nn = n, kk = nc - n;
         fc.flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
@@ -447,8 +471,8 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         const int32_t m = fm[f], n = fn[f], nc = fnc[f];
         if (n == 0) continue;
         T* Wf = W + ws_off[f];
-        P.pack.push_back({Wf, VR + vr_off[f], m, n, nc, m, 1, 0});
-        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, nc, n, 1, 0});
+        P.pack.push_back({Wf, VR + vr_off[f], m, n, fld[f], m, 1, 0});
+        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, fld[f], n, 1, 0});
         std::vector<int32_t> rows{F.cluster};
         rows.insert(rows.end(), F.n1.begin(), F.n1.end());
         rs_off.push_back((int64_t)rs.size());
@@ -548,7 +572,7 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
     T* src = blk(p, p);
     SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
     P.sgather.push_back({src, SW + u_off[t], Pn, Pn, Pn, Pn, 0, 0});
-    P.sqr.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, 0});
+    P.sqr.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, Pn});
     P.spack.push_back({SW + u_off[t], VRU + u_off[t], Pn, Pn, Pn, Pn, 1, 0});
   }
   for (int64_t i = 0; i < nclu; ++i)
@@ -1000,6 +1024,23 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     }
     copy_batch(g, up, wk, s);
     launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
+    {
+      // trailing slices of split fronts, grouped by (panel width, slice width)
+      std::map<std::pair<int, int>, std::pair<int, std::vector<TrailDesc<T>>>> tg;
+      for (auto& p : pl) {
+        if (c >= p.fronts.size() || p.fronts[c].trail.empty()) continue;
+        auto& e = tg[{p.jbf, p.fronts[c].trail_cw}];
+        e.first = std::max(e.first, p.fronts[c].trail_max_m);
+        append(e.second, p.fronts[c].trail);
+      }
+      if (!tg.empty()) {
+        ProfScope ps("front_trail", s, 0.0, 0.0);
+        for (auto& kv : tg) {
+          TrailDesc<T>* d = up.upload(wk, kv.second.second, s);
+          launch_trail<T>(d, (int64_t)kv.second.second.size(), kv.first.first, kv.first.second, kv.second.first, s);
+        }
+      }
+    }
     copy_batch(sc, up, wk, s);
   }
   {

@@ -248,6 +248,7 @@ __global__ void __launch_bounds__(NT) k_qr(const QRDesc<T>* __restrict__ descs) 
   const QRDesc<T> d = descs[blockIdx.x];
   extern __shared__ __align__(16) unsigned char smem[];
   const int m = d.m, n = d.n, nc = d.nc;
+  const int64_t ld = d.ld ? d.ld : nc;
   T* Ps = reinterpret_cast<T*>(smem);
   T* Tm = reinterpret_cast<T*>(smem + S::off_t(m));
   double* zz = reinterpret_cast<double*>(smem + S::off_zz(m));
@@ -258,16 +259,16 @@ __global__ void __launch_bounds__(NT) k_qr(const QRDesc<T>* __restrict__ descs) 
   for (int j0 = 0; j0 < n; j0 += JB) {
     const int jb = min(JB, n - j0);
     const int mp = m - j0;
-    T* A0 = d.a + (int64_t)j0 * nc + j0;
+    T* A0 = d.a + (int64_t)j0 * ld + j0;
     for (int q = tid; q < mp * JB; q += NT) {
       const int r = q / JB, t = q - r * JB;
-      Ps[r * LDP + t] = t < jb ? A0[(int64_t)r * nc + t] : T(0);
+      Ps[r * LDP + t] = t < jb ? A0[(int64_t)r * ld + t] : T(0);
     }
     __syncthreads();
     zero_diag |= factor_panel<T, JB>(Ps, mp, jb, taus, red);
     for (int q = tid; q < mp * jb; q += NT) {
       const int r = q / jb, t = q - r * jb;
-      A0[(int64_t)r * nc + t] = Ps[r * LDP + t];
+      A0[(int64_t)r * ld + t] = Ps[r * LDP + t];
     }
     if (tid < jb) d.tau[j0 + tid] = (T)taus[tid];
     __syncthreads();
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(NT) k_qr(const QRDesc<T>* __restrict__ descs) 
     form_t<T, JB>(Ps, mp, jb, taus, zz, Tm);
     if (d.tpan)
       for (int q = tid; q < JB * JB; q += NT) d.tpan[(int64_t)(j0 / JB) * JB * JB + q] = Tm[q];
-    wy_apply_left<T, JB>(Ps, Tm, mp, A0 + jb, nc, nc - j0 - jb);
+    wy_apply_left<T, JB>(Ps, Tm, mp, A0 + jb, ld, nc - j0 - jb);
     __syncthreads();
   }
   if (tid == 0 && zero_diag && d.flag) *d.flag = 1;
@@ -442,6 +443,7 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
   const QRDesc<T> d = descs[blockIdx.x];
   extern __shared__ __align__(16) unsigned char smem[];
   const int m = d.m, n = d.n, nc = d.nc, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t ld = d.ld ? d.ld : nc;
   T* Vs = reinterpret_cast<T*>(smem);  // m x JB row-major, explicit unit diagonal
   T* Ts = Vs + (size_t)m * JB;         // JB x JB, row i of T at i * JB
   T* red = Ts + JB * JB;               // 2 buffers x 4 waves x JB
@@ -449,13 +451,13 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
   bool zero_diag = false;
   for (int j0 = 0; j0 < n; j0 += JB) {
     const int jb = min(JB, n - j0), mp = m - j0;
-    T* A0 = d.a + (int64_t)j0 * nc + j0;
+    T* A0 = d.a + (int64_t)j0 * ld + j0;
     T a[Q][JB];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int r = tid + NT * q;
 #pragma unroll
-      for (int c = 0; c < JB; ++c) a[q][c] = (r < mp && c < jb) ? A0[(int64_t)r * nc + c] : T(0);
+      for (int c = 0; c < JB; ++c) a[q][c] = (r < mp && c < jb) ? A0[(int64_t)r * ld + c] : T(0);
     }
     T trow[JB];
 #pragma unroll
@@ -526,7 +528,7 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
         T vrow[JB];
 #pragma unroll
         for (int c = 0; c < JB; ++c) {
-          if (c < jb) A0[(int64_t)r * nc + c] = a[q][c];
+          if (c < jb) A0[(int64_t)r * ld + c] = a[q][c];
           vrow[c] = c >= jb ? T(0) : (r > c ? a[q][c] : (r == c ? T(1) : T(0)));
         }
         lds_store_row<T, JB>(Vs + (size_t)r * JB, vrow);
@@ -555,11 +557,11 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
         for (; r + 28 < mp; r += 32) {
           T cv[8];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * nc];
+          for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * ld];
 #pragma unroll
           for (int e = 0; e < 8; ++e) lds_axpy_row<T, JB>(Vs + (size_t)(r + 4 * e) * JB, cv[e], w);
         }
-        for (; r < mp; r += 4) lds_axpy_row<T, JB>(Vs + (size_t)r * JB, Cc[(int64_t)r * nc], w);
+        for (; r < mp; r += 4) lds_axpy_row<T, JB>(Vs + (size_t)r * JB, Cc[(int64_t)r * ld], w);
       }
 #pragma unroll
       for (int c = 0; c < JB; ++c) {
@@ -576,16 +578,100 @@ __global__ void __launch_bounds__(NT) k_qr_reg(const QRDesc<T>* __restrict__ des
       for (; r + 28 < mp; r += 32) {
         T cv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * nc];
+        for (int e = 0; e < 8; ++e) cv[e] = Cc[(int64_t)(r + 4 * e) * ld];
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          Cc[(int64_t)(r + 4 * e) * nc] = cv[e] - lds_dot_row<T, JB>(Vs + (size_t)(r + 4 * e) * JB, u);
+          Cc[(int64_t)(r + 4 * e) * ld] = cv[e] - lds_dot_row<T, JB>(Vs + (size_t)(r + 4 * e) * JB, u);
       }
-      for (; r < mp; r += 4) Cc[(int64_t)r * nc] -= lds_dot_row<T, JB>(Vs + (size_t)r * JB, u);
+      for (; r < mp; r += 4) Cc[(int64_t)r * ld] -= lds_dot_row<T, JB>(Vs + (size_t)r * JB, u);
     }
     __syncthreads();
   }
   if (tid == 0 && zero_diag && d.flag) *d.flag = 1;
+}
+
+// Trailing update of a column slice of a front (TrailDesc): the slice
+// (m x CW) stays in LDS while every JB-reflector panel of the pivot block is
+// applied, C <- C - V T^T (V^T C).  Thread (c, g) = (tid % CW, tid / CW) owns
+// slice column c and rows g, g + TY, ...; V rows are read from the factored
+// pivot block (row stride a multiple of the vector width) and shared by the
+// CW lanes of a row group.  Per panel: partial V^T C over the row groups,
+// one LDS reduction, T^T W by JB row-group lanes, then the update.
+template <typename T, int JB, int CW>
+__global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ ds) {
+  constexpr int TY = NT / CW;
+  static_assert(TY >= JB, "row groups must cover the panel width");
+  using V = Vec16<T>;
+  const TrailDesc<T> d = ds[blockIdx.x];
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* red = reinterpret_cast<T*>(smem);     // TY x JB x CW partials
+  T* Ws = red + TY * JB * CW;              // JB x CW
+  T* Us = Ws + JB * CW;                    // JB x CW
+  T* Cs = Us + JB * CW;                    // m x (CW + 1)
+  constexpr int LC = CW + 1;
+  const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
+  const int m = d.m, n = d.n;
+  const int64_t ld = d.ld;
+  const bool live = c < d.cw;
+  T* col = d.a + d.c0 + c;
+  for (int r = g; r < m; r += TY) Cs[r * LC + c] = live ? col[(int64_t)r * ld] : T(0);
+  __syncthreads();
+  for (int p0 = 0; p0 < n; p0 += JB) {
+    const int jb = min(JB, n - p0);
+    const T* vp = d.a + p0;  // V of this panel: columns p0 .. p0 + jb - 1
+    T w[JB];
+#pragma unroll
+    for (int t = 0; t < JB; ++t) w[t] = T(0);
+    for (int r = p0 + g; r < m; r += TY) {
+      const T x = Cs[r * LC + c];
+      T v[JB];
+      const typename V::type* q = reinterpret_cast<const typename V::type*>(vp + (int64_t)r * ld);
+#pragma unroll
+      for (int i = 0; i < JB / V::N; ++i) V::put(q[i], v + i * V::N);
+      const int rr = r - p0;
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const T vt = t >= jb ? T(0) : (rr > t ? v[t] : (rr == t ? T(1) : T(0)));
+        w[t] += vt * x;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < JB; ++t) red[(g * JB + t) * CW + c] = w[t];
+    __syncthreads();
+    if (g < JB) {
+      T sum = T(0);
+      for (int h = 0; h < TY; ++h) sum += red[(h * JB + g) * CW + c];
+      Ws[g * CW + c] = sum;
+    }
+    __syncthreads();
+    if (g < JB) {
+      const T* tp = d.tpan + (int64_t)(p0 / JB) * JB * JB;  // T[q][g] at q + g JB
+      T u = T(0);
+      for (int q2 = 0; q2 <= g; ++q2) u += tp[q2 + g * JB] * Ws[q2 * CW + c];
+      Us[g * CW + c] = u;
+    }
+    __syncthreads();
+    T u[JB];
+#pragma unroll
+    for (int t = 0; t < JB; ++t) u[t] = Us[t * CW + c];
+    for (int r = p0 + g; r < m; r += TY) {
+      T v[JB];
+      const typename V::type* q = reinterpret_cast<const typename V::type*>(vp + (int64_t)r * ld);
+#pragma unroll
+      for (int i = 0; i < JB / V::N; ++i) V::put(q[i], v + i * V::N);
+      const int rr = r - p0;
+      T acc = T(0);
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const T vt = t >= jb ? T(0) : (rr > t ? v[t] : (rr == t ? T(1) : T(0)));
+        acc += vt * u[t];
+      }
+      Cs[r * LC + c] -= acc;
+    }
+    __syncthreads();
+  }
+  if (live)
+    for (int r = g; r < m; r += TY) col[(int64_t)r * ld] = Cs[r * LC + c];
 }
 
 template <typename T, int JB>
@@ -2108,6 +2194,19 @@ static void check_launch(const char* what) {
   if (e != hipSuccess) throw Error(SPAQR_EDEVICE, std::string("launch of ") + what + " failed: " + hipGetErrorString(e));
 }
 
+// Largest dynamic LDS a workgroup may use on the current device (bytes).
+static size_t device_lds_limit() {
+  static size_t lim = 0;
+  if (!lim) {
+    int dev = 0, v = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    lim = (size_t)v;
+  }
+  return lim;
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename T>
 void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s) {
@@ -2156,7 +2255,6 @@ static size_t qr_bytes_jb(int max_m, int jb, int eb) {
   return lds;
 }
 
-static constexpr size_t kLdsBudget = 64 * 1024;
 
 // Register-panel QR (k_qr_reg) for matrices of at most NT * Q rows; taller
 // ones use the LDS-panel kernel k_qr.  Returns the panel width and Q (0 when
@@ -2168,9 +2266,9 @@ static QRPlan qr_plan(int max_m, int eb) {
   if (max_m <= NT) return {16, 1};
   if (max_m <= 2 * NT) return {16, 2};
   if (max_m <= 4 * NT) return {eb == 8 ? 8 : 16, 4};
-  const int cap = eb == 8 ? 16 : 32;
-  for (int jb = cap; jb >= 1; jb >>= 1)
-    if (qr_bytes_jb(max_m, jb, eb) <= kLdsBudget) return {jb, 0};
+  const size_t budget = device_lds_limit();
+  for (int jb = 16; jb >= 1; jb >>= 1)
+    if (qr_bytes_jb(max_m, jb, eb) <= budget) return {jb, 0};
   return {0, 0};
 }
 
@@ -2237,6 +2335,42 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
   check_launch("k_qr");
 }
 
+static size_t trail_lds(int max_m, int jb, int cw, int eb) {
+  return ((size_t)(NT / cw) * jb * cw + 2 * (size_t)jb * cw + (size_t)max_m * (cw + 1)) * eb;
+}
+
+int trail_width(int max_m, int eb) {
+  const size_t lim = device_lds_limit();
+  for (int cw : {16, 8, 4})
+    if (trail_lds(max_m, 16, cw, eb) <= lim) return cw;
+  return 0;
+}
+
+template <typename T>
+void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, hipStream_t s) {
+  if (n <= 0) return;
+  const size_t lds = trail_lds(max_m, jb, cw, sizeof(T));
+  if (lds > device_lds_limit()) throw Error(SPAQR_ENOMEM, "front too tall for the trailing-update slice");
+#define SPAQR_TR(J, W)                                                                      \
+  if (jb == J && cw == W) {                                                                \
+    allow_lds(reinterpret_cast<const void*>(&k_trail<T, J, W>), lds, "k_trail");          \
+    hipLaunchKernelGGL((k_trail<T, J, W>), dim3((unsigned)n), dim3(NT), lds, s, d);       \
+    check_launch("k_trail");                                                               \
+    return;                                                                                \
+  }
+  SPAQR_TR(16, 16)
+  SPAQR_TR(16, 8)
+  SPAQR_TR(16, 4)
+  SPAQR_TR(8, 16)
+  SPAQR_TR(8, 8)
+  SPAQR_TR(8, 4)
+  SPAQR_TR(4, 16)
+  SPAQR_TR(4, 8)
+  SPAQR_TR(4, 4)
+#undef SPAQR_TR
+  throw Error(SPAQR_EINVAL, "unsupported panel width for the trailing update");
+}
+
 template <typename T>
 void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, hipStream_t s) {
   if (n <= 0) return;
@@ -2259,18 +2393,6 @@ void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int j
   check_launch("k_scale");
 }
 
-// Largest dynamic LDS a workgroup may use on the current device (bytes).
-static size_t device_lds_limit() {
-  static size_t lim = 0;
-  if (!lim) {
-    int dev = 0, v = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-      v = 64 * 1024;
-    lim = (size_t)v;
-  }
-  return lim;
-}
 
 template <typename T, int PMAX, int NTH>
 static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_nb, size_t c_bytes,
@@ -2428,13 +2550,16 @@ bool launch_sparsify_coop(const SpDesc<T>* d, const CoopItem* items, int nitems,
   return true;
 }
 
-static constexpr size_t kApplyLds = 64 * 1024;
+// FP64 rows an apply workgroup may stage in LDS: up to the device's limit
+// per workgroup (160 KB on gfx950), less room for the small work arrays.
+static size_t apply_lds_budget() { return device_lds_limit() - 2048; }
 
 int apply_rhs_block(int max_rows, int nrhs) {
+  const size_t lim = apply_lds_budget();
   int rb = RBMAX;
   if (rb > nrhs) rb = nrhs;
-  while (rb > 1 && (size_t)max_rows * rb * sizeof(double) > kApplyLds) --rb;
-  if ((size_t)max_rows * rb * sizeof(double) > kApplyLds) return 0;
+  while (rb > 1 && (size_t)max_rows * rb * sizeof(double) > lim) --rb;
+  if ((size_t)max_rows * rb * sizeof(double) > lim) return 0;
   return rb;
 }
 
@@ -2446,6 +2571,7 @@ int apply_rhs_block(int max_rows, int nrhs) {
     const int rb = apply_rhs_block(max_rows, nrhs);                                             \
     if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: item too large for LDS");                     \
     const size_t lds = (size_t)max_rows * rb * sizeof(double);                                  \
+    allow_lds(reinterpret_cast<const void*>(&k_ap_##KERNEL<T>), lds, "k_ap_" #KERNEL);         \
     hipLaunchKernelGGL(k_ap_##KERNEL<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)),  \
                        dim3(64), lds, s, d, x, ldx, nrhs, rb);                                  \
     check_launch("k_ap_" #KERNEL);                                                              \
@@ -2493,7 +2619,10 @@ void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, d
   const dim3 grid((unsigned)n, (unsigned)((nrhs + rb - 1) / rb));
   switch (jb) {
 #define SPAQR_FW_CASE(J) \
-  case J: hipLaunchKernelGGL((k_ap_front_fwd_wy<T, J>), grid, dim3(256), lds, s, d, x, ldx, nrhs, rb); break;
+  case J:                                                                                  \
+    allow_lds(reinterpret_cast<const void*>(&k_ap_front_fwd_wy<T, J>), lds, "k_ap_front_fwd_wy"); \
+    hipLaunchKernelGGL((k_ap_front_fwd_wy<T, J>), grid, dim3(256), lds, s, d, x, ldx, nrhs, rb); \
+    break;
     SPAQR_FW_CASE(1)
     SPAQR_FW_CASE(2)
     SPAQR_FW_CASE(4)
@@ -2513,6 +2642,7 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
   const int rb = apply_rhs_block(max_n + max_k, nrhs);
   if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
   const size_t lds = (size_t)(max_n + max_k) * rb * sizeof(double);
+  allow_lds(reinterpret_cast<const void*>(&k_ap_front_bwd_reg<T>), lds, "k_ap_front_bwd_reg");
   hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
                      d, x, ldx, nrhs, rb);
   check_launch("k_ap_front_bwd_reg");
@@ -2565,6 +2695,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_scatter_scaled<T>(T*, const int64_t*, const double*, const int32_t*, const double*, \
                                          int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
+  template void launch_trail<T>(const TrailDesc<T>*, int64_t, int, int, int, hipStream_t);           \
   template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, hipStream_t); \
   template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, hipStream_t); \
   template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, size_t, hipStream_t); \

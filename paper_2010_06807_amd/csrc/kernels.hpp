@@ -21,18 +21,30 @@ struct CopyTile {
   int32_t mode, pad;
 };
 
-// Blocked Householder QR of a row-major m x nc matrix (ld = nc): reflectors
-// for the first n columns, applied to all nc columns.  V (unit diagonal
-// implicit) is left below the diagonal and R on and above it; tau[0..n) and
-// the compact-WY factors of every JB-column panel (JB x JB, column-major,
-// zero-padded) are written.  If some |R_ii| is exactly zero, *flag = 1.
+// Blocked Householder QR of a row-major m x nc matrix (row stride ld, or nc
+// when ld == 0): reflectors for the first n columns, applied to all nc
+// columns.  V (unit diagonal implicit) is left below the diagonal and R on and
+// above it; tau[0..n) and the compact-WY factors of every JB-column panel
+// (JB x JB, column-major, zero-padded) are written.  If some |R_ii| is exactly
+// zero, *flag = 1.
 template <typename T>
 struct QRDesc {
   T* a;
   T* tau;
   T* tpan;
   int* flag;  // may be null
-  int32_t m, n, nc, pad;
+  int32_t m, n, nc, ld;
+};
+
+// Trailing update of one column slice of a front whose pivot block was
+// factored with nc = n: columns [c0, c0 + cw) of the row-major m x (row
+// stride ld) matrix a get H_{n-1}^T ... H_0^T, panel by panel from the
+// reflectors below the pivot block's diagonal and the panels' T factors.
+template <typename T>
+struct TrailDesc {
+  T* a;
+  const T* tpan;
+  int32_t m, n, ld, c0, cw, pad;
 };
 
 // One block B (row-major rows x cols, ld = cols) of the trailing matrix to be
@@ -132,6 +144,13 @@ void launch_scatter_scaled(T* pool, const int64_t* dst, const double* val, const
 // jb: panel width (power of two <= 32); lds_bytes: dynamic LDS per workgroup
 template <typename T>
 void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s);
+// Trailing updates (TrailDesc).  trail_width: the slice width (16, 8 or 4
+// columns) whose m x width slice fits LDS for fronts of at most max_m rows,
+// 0 if none.  launch_trail: slices of at most cw columns, pivot blocks
+// factored with panel width jb, at most max_m rows.
+int trail_width(int max_m, int elem_bytes);
+template <typename T>
+void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, hipStream_t s);
 int qr_panel_width(int max_m, int elem_bytes);
 size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
 template <typename T>
