@@ -915,38 +915,59 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
       b = e;
     }
   }
-  // interfaces beyond one workgroup: the cooperative CPQR, several interfaces
-  // per launch (64 * cpt columns per one-wave workgroup; cpt grows until the
-  // whole set can be co-resident)
-  int64_t ncoop = 0;
+  // interfaces beyond one workgroup: the cooperative CPQR (64 * cpt columns
+  // per one-wave workgroup), interfaces packed into launches whose workgroups
+  // can all be co-resident, the longest factorizations first; cpt is the
+  // smallest that needs the fewest launches
+  struct CoopLaunch {
+    int64_t begin, end;
+    int blocks, kmax;
+  };
+  std::vector<CoopLaunch> coop;
   std::vector<CoopItem> items;
-  int coop_cpt = 0, coop_blocks = 0, coop_maxp = 1, coop_kmax = 0;
+  int coop_cpt = 0, coop_maxp = 1, coop_maxnb = 0, coop_blocks = 1;
+  int64_t ncoop = 0;
   if ((int64_t)sd.size() > nreg) {
-    int maxp = 1, maxnb = 0, kmax = 0;
+    auto kmax_of = [](const SpDesc<T>& q) { return std::min<int>(q.P, q.mmax); };
+    std::stable_sort(sd.begin() + nreg, sd.end(),
+                     [&](const SpDesc<T>& x, const SpDesc<T>& y) { return kmax_of(x) > kmax_of(y); });
     for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
-      maxp = std::max<int>(maxp, sd[t].P);
-      maxnb = std::max(maxnb, sd[t].nrow + sd[t].ncol);
-      kmax = std::max(kmax, std::min<int>(sd[t].P, sd[t].mmax));
+      coop_maxp = std::max<int>(coop_maxp, sd[t].P);
+      coop_maxnb = std::max(coop_maxnb, sd[t].nrow + sd[t].ncol);
     }
+    size_t best = SIZE_MAX;
+    std::vector<CoopLaunch> cand;
     for (int cpt : {1, 2, 4, 8}) {
-      int64_t tot = 0;
-      for (size_t t = (size_t)nreg; t < sd.size(); ++t) tot += (sd[t].mmax + 64 * cpt - 1) / (64 * cpt);
-      if (tot <= 1024 && tot <= sparsify_coop_capacity<T>(cpt, maxp, maxnb)) {
+      const int cap = std::min(1024, sparsify_coop_capacity<T>(cpt, coop_maxp, coop_maxnb));
+      cand.clear();
+      bool ok = cap > 0;
+      for (size_t t = (size_t)nreg; ok && t < sd.size(); ++t) {
+        const int nb_t = (sd[t].mmax + 64 * cpt - 1) / (64 * cpt);
+        if (nb_t > cap) ok = false;
+        else if (cand.empty() || cand.back().blocks + nb_t > cap)
+          cand.push_back({(int64_t)t, (int64_t)t + 1, nb_t, kmax_of(sd[t])});
+        else {
+          cand.back().end = (int64_t)t + 1;
+          cand.back().blocks += nb_t;
+        }
+      }
+      if (ok && cand.size() < best) {
+        best = cand.size();
+        coop = cand;
         coop_cpt = cpt;
-        coop_blocks = (int)tot;
-        break;
       }
     }
     if (coop_cpt > 0) {
       ncoop = (int64_t)sd.size() - nreg;
-      int first = 0;
-      for (size_t t = (size_t)nreg; t < sd.size(); ++t) {
-        const int nb_t = (sd[t].mmax + 64 * coop_cpt - 1) / (64 * coop_cpt);
-        items.push_back({first, nb_t});
-        first += nb_t;
+      for (const CoopLaunch& L : coop) {
+        int first = 0;
+        for (int64_t t = L.begin; t < L.end; ++t) {
+          const int nb_t = (sd[t].mmax + 64 * coop_cpt - 1) / (64 * coop_cpt);
+          items.push_back({first, nb_t});
+          first += nb_t;
+        }
+        coop_blocks = std::max(coop_blocks, L.blocks);
       }
-      coop_maxp = maxp;
-      coop_kmax = kmax;
     }
   }
   // the rest: interfaces of at most 64 (FP32) or 32 (FP64) unknowns to the LDS
@@ -972,6 +993,8 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   int* done = nullptr;
   CoopItem* ditems = nullptr;
   if (ncoop > 0) {
+    // candidate slots are reused launch after launch (stream order); done
+    // flags are per launch
     ckey = wk.alloc_n<double>(2 * (size_t)coop_blocks, s);
     cpos = wk.alloc_n<int>(2 * (size_t)coop_blocks, s);
     ccol = wk.alloc_n<T>(2 * (size_t)coop_blocks * coop_maxp, s);
@@ -982,9 +1005,12 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   ProfScope ps("sparsify", s, 0.0, 0.0);  // work added after the rank readback
   for (const auto& g : groups)
     launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, (int)g[2], (int)g[3], max_nb, s);
-  if (ncoop > 0 && !launch_sparsify_coop<T>(dsd + nreg, ditems, (int)ncoop, coop_blocks, coop_cpt, dnb, coop_maxp,
-                                           max_nb, ckey, cpos, ccol, done, coop_kmax, s))
-    throw Error(SPAQR_EDEVICE, "cooperative CPQR no longer fits the device");
+  for (const CoopLaunch& L : coop) {
+    const int64_t i0 = L.begin - nreg, ni = L.end - L.begin;
+    if (!launch_sparsify_coop<T>(dsd + L.begin, ditems + i0, (int)ni, L.blocks, coop_cpt, dnb, coop_maxp, coop_maxnb,
+                                 ckey, cpos, ccol, done + 2 * i0, L.kmax, s))
+      throw Error(SPAQR_EDEVICE, "cooperative CPQR no longer fits the device");
+  }
   launch_sparsify_small<T>(dsd + nrest0, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
   launch_sparsify<T>(dsd + nrest0 + nsmall, (int64_t)sd.size() - nrest0 - nsmall, dnb, max_pc, max_nb, s);
 }
