@@ -1081,7 +1081,11 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     std::vector<CopyTile<T>> g, pk;
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     std::vector<ScaleFac<T>> fac;
-    std::map<int, std::pair<int, std::vector<ScaleBlk<T>>>> sgroups;  // jb -> (max P, blocks)
+    struct SGroup {
+      int max_p = 1, max_rows = 1, max_cols = 1;
+      std::vector<ScaleBlk<T>> blk;
+    };
+    std::map<int, SGroup> sgroups;  // by panel width
     double qfl = 0.0, qby = 0.0, sfl = 0.0, sby = 0.0;
     for (auto& p : pl) {
       append(g, p.sgather);
@@ -1093,12 +1097,14 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       }
       const int base = (int)fac.size();
       append(fac, p.fac);
-      auto& sg = sgroups[p.jbs];
-      sg.first = std::max(sg.first, p.max_p);
+      SGroup& sg = sgroups[p.jbs];
+      sg.max_p = std::max(sg.max_p, p.max_p);
       for (ScaleBlk<T> b : p.sblk) {
         if (b.fi >= 0) b.fi += base;
         if (b.fj >= 0) b.fj += base;
-        sg.second.push_back(b);
+        sg.max_rows = std::max(sg.max_rows, b.rows);
+        sg.max_cols = std::max(sg.max_cols, b.cols);
+        sg.blk.push_back(b);
         sfl += 4.0 * b.rows * b.rows * (double)b.cols + (double)b.rows * b.cols * b.cols;
         sby += 2.0 * b.rows * (double)b.cols * sizeof(T);
       }
@@ -1110,9 +1116,10 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       ScaleFac<T>* dfac = up.upload(wk, fac, s);
       ProfScope ps("scale_blocks", s, sfl, sby);
       for (auto& kv : sgroups) {
-        if (kv.second.second.empty()) continue;
-        ScaleBlk<T>* dsb = up.upload(wk, kv.second.second, s);
-        launch_scale<T>(dsb, (int64_t)kv.second.second.size(), dfac, kv.first, kv.second.first, s);
+        const SGroup& g = kv.second;
+        if (g.blk.empty()) continue;
+        ScaleBlk<T>* dsb = up.upload(wk, g.blk, s);
+        launch_scale<T>(dsb, (int64_t)g.blk.size(), dfac, kv.first, g.max_p, g.max_rows, g.max_cols, s);
       }
     }
   }

@@ -674,6 +674,10 @@ __global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ d
     for (int r = g; r < m; r += TY) col[(int64_t)r * ld] = Cs[r * LC + c];
 }
 
+// Scaling of the blocks touching an interface (Algorithm 2, scaling step):
+// B <- Q_i^T B for the block's row interface i.  Workgroup (block, y) owns
+// the block's columns y NT .. y NT + NT - 1; the compact-WY panels of Q_i
+// are staged in LDS one at a time.  A diagonal block becomes the identity.
 template <typename T, int JB>
 __global__ void __launch_bounds__(NT) k_scale(const ScaleBlk<T>* __restrict__ descs,
                                               const ScaleFac<T>* __restrict__ fac) {
@@ -682,48 +686,90 @@ __global__ void __launch_bounds__(NT) k_scale(const ScaleBlk<T>* __restrict__ de
   const ScaleBlk<T> d = descs[blockIdx.x];
   T* B = d.B;
   const int rows = d.rows, cols = d.cols, tid = threadIdx.x;
+  const int c0 = (int)blockIdx.y * NT;
+  if (c0 >= cols) return;
+  const int nc = min(NT, cols - c0);
   const bool si = d.fi >= 0 && *fac[d.fi].flag == 0;
-  const bool sj = d.fj >= 0 && *fac[d.fj].flag == 0;
   if (d.fi >= 0 && d.fi == d.fj) {
-    if (si)
-      for (int q = tid; q < rows * cols; q += NT) {
-        const int r = q / cols, c = q - r * cols;
-        B[q] = r == c ? T(1) : T(0);
-      }
+    if (si && tid < nc)
+      for (int r = 0; r < rows; ++r) B[(int64_t)r * cols + c0 + tid] = r == c0 + tid ? T(1) : T(0);
     return;
   }
-  if (si) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T* Vs = reinterpret_cast<T*>(smem);
-    T* Tm = reinterpret_cast<T*>(smem + S::off_t(rows));
-    const ScaleFac<T> f = fac[d.fi];
-    for (int j0 = 0; j0 < rows; j0 += JB) {
-      const int jb = min(JB, rows - j0), mp = rows - j0;
-      for (int q = tid; q < mp * JB; q += NT) {
-        const int r = q / JB, t = q - r * JB;
-        T v;
-        if (t >= jb || r < t) v = T(0);
-        else if (r == t) v = T(1);
-        else v = f.vr[(int64_t)(j0 + r) + (int64_t)(j0 + t) * rows];
-        Vs[r * LDP + t] = v;
-      }
-      for (int q = tid; q < JB * JB; q += NT) Tm[q] = f.tpan[(int64_t)(j0 / JB) * JB * JB + q];
-      __syncthreads();
-      wy_apply_left<T, JB>(Vs, Tm, mp, B + (int64_t)j0 * cols, cols, cols);
-      __syncthreads();
+  if (!si) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* Vs = reinterpret_cast<T*>(smem);
+  T* Tm = reinterpret_cast<T*>(smem + S::off_t(rows));
+  const ScaleFac<T> f = fac[d.fi];
+  for (int j0 = 0; j0 < rows; j0 += JB) {
+    const int jb = min(JB, rows - j0), mp = rows - j0;
+    for (int q = tid; q < mp * JB; q += NT) {
+      const int r = q / JB, t = q - r * JB;
+      T v;
+      if (t >= jb || r < t) v = T(0);
+      else if (r == t) v = T(1);
+      else v = f.vr[(int64_t)(j0 + r) + (int64_t)(j0 + t) * rows];
+      Vs[r * LDP + t] = v;
     }
+    for (int q = tid; q < JB * JB; q += NT) Tm[q] = f.tpan[(int64_t)(j0 / JB) * JB * JB + q];
+    __syncthreads();
+    wy_apply_left<T, JB>(Vs, Tm, mp, B + (int64_t)j0 * cols + c0, cols, nc);
+    __syncthreads();
   }
-  if (sj) {
-    const T* R = fac[d.fj].vr;
-    for (int r = tid; r < rows; r += NT) {
-      T* Br = B + (int64_t)r * cols;
-      for (int c = 0; c < cols; ++c) {
-        T s = Br[c];
-        const T* Rc = R + (int64_t)c * cols;
-        for (int q = 0; q < c; ++q) s -= Br[q] * Rc[q];
-        Br[c] = s / Rc[c];
+}
+
+// B <- B R_j^{-1} for the block's column interface j (the right factor of the
+// scaling step), R_j upper triangular with R[q][c] at q + c cols.  Workgroup
+// (block, y) owns rows 16 y .. 16 y + 15.  Columns go in panels of 16: a
+// panel is first reduced by the solved columns to its left (tiles of 64
+// through LDS, one output per thread), then solved against the panel's
+// diagonal block by forward substitution, one row per thread.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_scale_right(const ScaleBlk<T>* __restrict__ descs,
+                                                    const ScaleFac<T>* __restrict__ fac) {
+  constexpr int RB = 16, NB = 16, KC = 64;
+  static_assert(RB * NB == NT, "one output per thread");
+  const ScaleBlk<T> d = descs[blockIdx.x];
+  if (d.fj < 0 || d.fi == d.fj || *fac[d.fj].flag != 0) return;
+  const int rows = d.rows, cols = d.cols, r0 = (int)blockIdx.y * RB;
+  if (r0 >= rows) return;
+  const int rb = min(RB, rows - r0);
+  const T* R = fac[d.fj].vr;
+  T* B = d.B + (int64_t)r0 * cols;
+  __shared__ T Xs[RB][KC + 1];
+  __shared__ T Rs[KC][NB + 1];
+  __shared__ T Ps[RB][NB + 1];
+  __shared__ T Rt[NB][NB + 1];
+  const int tid = threadIdx.x, i = tid / NB, cc = tid - i * NB;
+  for (int p0 = 0; p0 < cols; p0 += NB) {
+    const int nb = min(NB, cols - p0);
+    T acc = T(0);
+    for (int q0 = 0; q0 < p0; q0 += KC) {
+      const int kq = min(KC, p0 - q0);
+      for (int e = tid; e < RB * KC; e += NT) {
+        const int ii = e / KC, k = e - ii * KC;
+        Xs[ii][k] = (ii < rb && k < kq) ? B[(int64_t)ii * cols + q0 + k] : T(0);
       }
+      for (int e = tid; e < KC * NB; e += NT) {
+        const int c = e / KC, k = e - c * KC;
+        Rs[k][c] = (c < nb && k < kq) ? R[(int64_t)(q0 + k) + (int64_t)(p0 + c) * cols] : T(0);
+      }
+      __syncthreads();
+#pragma unroll 16
+      for (int k = 0; k < KC; ++k) acc += Xs[i][k] * Rs[k][cc];
+      __syncthreads();
     }
+    Ps[i][cc] = (i < rb && cc < nb) ? B[(int64_t)i * cols + p0 + cc] - acc : T(0);
+    Rt[i][cc] = (i < nb && cc < nb) ? R[(int64_t)(p0 + i) + (int64_t)(p0 + cc) * cols] : T(0);
+    __syncthreads();
+    if (tid < rb)
+      for (int c = 0; c < nb; ++c) {
+        T x = Ps[tid][c];
+        for (int q = 0; q < c; ++q) x -= Ps[tid][q] * Rt[q][c];
+        Ps[tid][c] = x / Rt[c][c];
+      }
+    __syncthreads();
+    if (i < rb && cc < nb) B[(int64_t)i * cols + p0 + cc] = Ps[i][cc];
+    __syncthreads();  // the next panel reads these columns
   }
 }
 
@@ -2372,14 +2418,16 @@ void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, h
 }
 
 template <typename T>
-void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, hipStream_t s) {
+void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, int max_rows,
+                  int max_cols, hipStream_t s) {
   if (n <= 0) return;
   const size_t lds = qr_bytes_jb(max_p, jb, sizeof(T));
+  const dim3 grid((unsigned)n, (unsigned)((max_cols + NT - 1) / NT));
   switch (jb) {
 #define SPAQR_SC_CASE(J) \
   case J:                                                                                       \
     allow_lds(reinterpret_cast<const void*>(&k_scale<T, J>), lds, "k_scale");                 \
-    hipLaunchKernelGGL((k_scale<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac);          \
+    hipLaunchKernelGGL((k_scale<T, J>), grid, dim3(NT), lds, s, d, fac);                       \
     break;
     SPAQR_SC_CASE(1)
     SPAQR_SC_CASE(2)
@@ -2391,6 +2439,8 @@ void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int j
     default: throw Error(SPAQR_EINVAL, "unsupported QR panel width");
   }
   check_launch("k_scale");
+  hipLaunchKernelGGL(k_scale_right<T>, dim3((unsigned)n, (unsigned)((max_rows + 15) / 16)), dim3(NT), 0, s, d, fac);
+  check_launch("k_scale_right");
 }
 
 
@@ -2696,7 +2746,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
                                          int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
   template void launch_trail<T>(const TrailDesc<T>*, int64_t, int, int, int, hipStream_t);           \
-  template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, hipStream_t); \
+  template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, int, hipStream_t); \
   template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, hipStream_t); \
   template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, size_t, hipStream_t); \
   template void launch_sparsify_reg<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, int, hipStream_t); \

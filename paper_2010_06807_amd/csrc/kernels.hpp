@@ -153,8 +153,11 @@ template <typename T>
 void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, hipStream_t s);
 int qr_panel_width(int max_m, int elem_bytes);
 size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
+// Block scaling: B <- Q_i^T B R_j^{-1} (two launches); max_p bounds the
+// interfaces' sizes (LDS panel of Q_i), max_rows / max_cols the blocks'.
 template <typename T>
-void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, hipStream_t s);
+void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, int max_rows,
+                  int max_cols, hipStream_t s);
 // Zero fills; blocks = total workgroups (block0 of the last descriptor plus its own).
 void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s);
 constexpr int64_t kZeroWordsPerBlock = 4096;
