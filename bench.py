@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """spaQR on one MI355X: unknowns/s for one pass of the whole hot path.
 
-A step = grid ordering + symbolic analysis (host) + numeric factorization
-(FP32 blocks and factors on the GPU) + right-preconditioned FGMRES in FP64 to
-||Ax - b|| / ||b|| <= 1e-10, on the 256 x 256 variable-coefficient
-convection-diffusion workload (N = 65,536, eps = 1e-2, 10 levels).  A's CSR
-and b are resident in HBM when the timed region starts; the factorization
-reads the values from device memory and the host sees only the pattern.
+A step serves a batch of B requests of the 256 x 256 variable-coefficient
+convection-diffusion workload (N = 65,536 each, eps = 1e-2, 10 levels; the
+requests differ in their seeded coefficient field and flow direction): per
+request grid ordering + symbolic analysis (host, in parallel threads), then
+the numeric factorizations of all B advanced together stage by stage (FP32
+blocks and factors, one launch per phase for the whole batch), then FGMRES in
+FP64 to ||Ax - b|| / ||b|| <= 1e-10 for all B together (one launch per apply
+phase for the whole batch).  A's CSR and b are resident in HBM when the timed
+region starts; the factorization reads the values from device memory and the
+host sees only the pattern.
 
-Printed as one JSON line: throughput (value), the plain FP64 GPU path for
-comparison, per-step latency percentiles, the roofline of the dominant kernel
-(HIP events around its launches during the timed region) and the oracle
-timed on one host core on the same workload.
+Printed as one JSON line: batched throughput (value), the same path one
+request at a time, the plain FP64 GPU path one request at a time, per-step
+latency percentiles, the roofline of the dominant kernel (HIP events around
+its launches during the timed region), a replayed serving trace and the
+oracle timed on one host core on the same workload.
 """
 
 from __future__ import annotations
@@ -52,6 +57,8 @@ def parse():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--batch", type=int, default=8, help="requests per step (cross-request batching)")
+    ap.add_argument("--single-steps", type=int, default=5, help="steps of the one-request-at-a-time FP32 path")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default=None, help="kernel for the roofline (default: the slowest)")
@@ -184,73 +191,107 @@ def main():
     import paper_2010_06807_amd as P
     from problems import config_problem, make_rhs
 
-    prob = config_problem(args.workload, seed=0)
+    from concurrent.futures import ThreadPoolExecutor
+
+    B = max(1, args.batch)
+    probs = [config_problem(args.workload, seed=i) for i in range(B)]
+    prob = probs[0]
     A, dims, L = prob["A"], prob["dims"], prob["levels"]
     N = A.shape[0]
     dev = torch.device("cuda:0")
-    dA = P.DeviceCSR(A, dev)
-    b = torch.from_numpy(make_rhs(N, 1, seed=0)).to(dev)
+    dAs = [P.DeviceCSR(p["A"], dev) for p in probs]
+    bs = [torch.from_numpy(make_rhs(N, 1, seed=i)).to(dev) for i in range(B)]
     torch.cuda.synchronize()
+    pool = ThreadPoolExecutor(max_workers=min(B, 8))
 
-    phases = {"order": [], "analyze": [], "factor": [], "solve": []}
+    phases = {"host_order_analyze": [], "factor": [], "solve": []}
 
-    def step(precision, record=False):
+    def host_prep(i):
         t0 = time.perf_counter()
-        ordg = P.order_grid(dims, L)
+        o = P.order_grid(dims, L)
         t1 = time.perf_counter()
-        sym = P.analyze(A, ordg)
-        t2 = time.perf_counter()
-        fac = P.factor_device(A, sym, dA, eps=args.eps, precision=precision)
-        t3 = time.perf_counter()
-        x, info = fac.solve(b, tol=args.tol)
-        t4 = time.perf_counter()
-        if record:
-            for k, v in zip(phases, (t1 - t0, t2 - t1, t3 - t2, t4 - t3)):
-                phases[k].append(v)
-        return fac, x, info
+        sym = P.analyze(probs[i]["A"], o)
+        return sym, t1 - t0, time.perf_counter() - t1
 
-    def run(precision, steps, warmup):
+    def step_batch(precision, record=False):
+        """One batch of B requests: ordering + analysis per request (threads),
+        batched factorization, batched FGMRES."""
+        t0 = time.perf_counter()
+        prep = list(pool.map(host_prep, range(B)))
+        t1 = time.perf_counter()
+        syms = [p[0] for p in prep]
+        facs = P.factor_batch([p["A"] for p in probs], syms, dAs, eps=args.eps, precision=precision)
+        t2 = time.perf_counter()
+        xs, infos = P.solve_batch(facs, bs, tol=args.tol)
+        t3 = time.perf_counter()
+        if record:
+            phases["host_order_analyze"].append(t1 - t0)
+            phases["factor"].append(t2 - t1)
+            phases["solve"].append(t3 - t2)
+        return facs, xs, [inf[0] for inf in infos]
+
+    def step_one(precision, i=0):
+        """One request alone: ordering, analysis, factorization, FGMRES."""
+        ordg = P.order_grid(dims, L)
+        sym = P.analyze(probs[i]["A"], ordg)
+        fac = P.factor_device(probs[i]["A"], sym, dAs[i], eps=args.eps, precision=precision)
+        x, info = fac.solve(bs[i], tol=args.tol)
+        return [fac], [x], [info[0]]
+
+    def run(fn, precision, steps, warmup, record=False):
         for _ in range(warmup):
-            step(precision)
+            fn(precision)
         torch.cuda.synchronize()
         lat, infos = [], []
         t0 = time.perf_counter()
         for _ in range(steps):
             s0 = time.perf_counter()
-            fac, x, info = step(precision, record=precision == 32)
+            facs, xs, inf = fn(precision, record=True) if record else fn(precision)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - s0)
-            infos.append(info[0])
+            infos.append(inf)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return dt, lat, infos, fac, x
+        return dt, lat, infos, facs, xs
 
-    log(f"{prob['name']}: N={N}, {L} levels; survey step")
+    log(f"{prob['name']}: N={N}, {L} levels, batch {B}; survey step")
     # which kernel dominates: one untimed step with every launch timed
-    step(32)
+    step_batch(32)
     P.profile_enable(True)
-    fac, x, info = step(32)
+    step_batch(32)
     torch.cuda.synchronize()
     names = list(KERNEL_BOUND)
     survey = {n: P.profile_query(n) for n in names}
     P.profile_enable(False)
     kern = args.kernel or max(survey, key=lambda n: survey[n]["total_ms"])
 
-    # timed region: FP32 factors + FP64 GMRES, only the roofline kernel timed
-    log(f"timed FP32 steps (roofline kernel: {kern})")
+    # timed region: batches of B requests, FP32 factors + FP64 GMRES, only the
+    # roofline kernel timed
+    log(f"timed FP32 batched steps (roofline kernel: {kern})")
     P.profile_enable(True, only=kern)
-    dt, lat, infos, fac, x = run(32, args.steps, args.warmup)
-    log(f"FP32: {1e3 * dt / args.steps:.2f} ms/step")
+    dt, lat, infos, facs, xs = run(step_batch, 32, args.steps, args.warmup, record=True)
+    log(f"FP32 batch of {B}: {1e3 * dt / args.steps:.2f} ms/step")
     prof = P.profile_query(kern)
     P.profile_enable(False)
-    res = float(np.linalg.norm(A @ x.cpu().numpy()[:, 0] - b.cpu().numpy()[:, 0]) / np.linalg.norm(b.cpu().numpy()))
-    st = fac.stats()
-    value = N * args.steps / dt
+    res = 0.0
+    for p, b, x in zip(probs, bs, xs):
+        bb = b.cpu().numpy()[:, 0]
+        res = max(res, float(np.linalg.norm(p["A"] @ x.cpu().numpy()[:, 0] - bb) / np.linalg.norm(bb)))
+    st = facs[0].stats()
+    value = B * N * args.steps / dt
 
-    # plain FP64 GPU path
-    dt64, lat64, infos64, fac64, x64 = run(64, args.fp64_steps, 1)
-    log(f"FP64 plain: {1e3 * dt64 / args.fp64_steps:.2f} ms/step")
-    value64 = N * args.fp64_steps / dt64
+    def single(precision, steps, what):
+        """The path one request at a time (None when steps == 0)."""
+        if steps <= 0:
+            return None
+        dt1, lat1, infos1, _, _ = run(step_one, precision, steps, 1)
+        log(f"{what}: {1e3 * dt1 / steps:.2f} ms/step")
+        return {"value": N * steps / dt1, "ms_per_step": 1e3 * dt1 / steps,
+                "latency_ms": {"p50": 1e3 * pct(lat1, 50), "p99": 1e3 * pct(lat1, 99)},
+                "gmres_iterations": infos1[-1][0]["iterations"]}
+
+    one32 = single(32, args.single_steps, "FP32 one request")
+    plain64 = single(64, args.fp64_steps, "FP64 plain")
 
     bound = KERNEL_BOUND[kern]
     if bound == "hbm":
@@ -272,14 +313,14 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{prob['name']}: 2D variable-coefficient convection-diffusion "
                                f"{dims[0]}x{dims[1]} (N={N}), 5-point upwind, eps={args.eps}, "
-                               f"{L} ND levels, FP32 factors + FP64 FGMRES to {args.tol}, 1 RHS",
-                   "eps": args.eps, "levels": L, "n": N},
+                               f"{L} ND levels, FP32 factors + FP64 FGMRES to {args.tol}, 1 RHS per request, "
+                               f"{B} requests per step batched (seeds 0..{B - 1})",
+                   "eps": args.eps, "levels": L, "n": N, "batch": B},
         "latency_ms": {"p50": 1e3 * pct(lat, 50), "p99": 1e3 * pct(lat, 99)},
-        "gmres_iterations": infos[-1]["iterations"], "relres": res,
+        "gmres_iterations": max(i["iterations"] for i in infos[-1]), "relres": res,
         "phase_ms": {k: round(1e3 * sum(v) / max(1, len(v)), 3) for k, v in phases.items()},
-        "fp64_plain": {"value": value64, "ms_per_step": 1e3 * dt64 / args.fp64_steps,
-                       "latency_ms": {"p50": 1e3 * pct(lat64, 50), "p99": 1e3 * pct(lat64, 99)},
-                       "gmres_iterations": infos64[-1]["iterations"]},
+        "fp32_one_request": one32,
+        "fp64_plain": plain64,
         "factor": {"ms_symbolic_host": st["ms_symbolic"], "ms_factor": st["ms_factor"],
                    "factor_bytes": st["factor_bytes"], "top_separator": st["top_separator"]},
         "roofline": roof,

@@ -159,6 +159,21 @@ spaqr_status spaqr_factor_device(const spaqr_csr* A_pattern, const spaqr_csr_dev
                                  const spaqr_symbolic* sym, const spaqr_opts* opts,
                                  void* hip_stream, spaqr_handle** out);
 
+/* Several factorizations advanced together, stage by stage (cross-request
+ * batching; the paper factors one matrix at a time): at every stage the
+ * fronts, scalings and sparsifications of all nprob problems share one
+ * launch per phase.  Problem i: A[i] (host CSR; its values are read only if
+ * Ad is NULL or Ad[i] is NULL), Ad[i] (device copy as in
+ * spaqr_factor_device, or NULL), sym[i] (an analysis of A[i]'s pattern that
+ * must outlive the handle).  opts (NULL: defaults) applies to all; all run on
+ * hip_stream.  out[i] receives problem i's handle.  Returns OK when every
+ * problem factored; otherwise the status of the first that failed, with
+ * out[i] = NULL exactly for the failed ones (the others are valid handles
+ * the caller frees).  EINVAL for bad arguments before any work. */
+spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaqr_csr_dev* const* Ad,
+                                const spaqr_symbolic* const* sym, const spaqr_opts* opts,
+                                void* hip_stream, spaqr_handle** out);
+
 /* x = M^{-1} b = D_c P^T W^{-1} Q^T P b for nrhs columns (Section 2.8).
  * b and x: n x nrhs column-major with leading dimension ld; device pointers
  * if on_device != 0, else host pointers.  b and x may alias.  Runs on the
@@ -183,6 +198,19 @@ typedef struct {
 spaqr_status spaqr_solve(spaqr_handle* h, const double* b, double* x,
                          int64_t nrhs, int64_t ld, int on_device, double tol,
                          spaqr_solve_info* info);
+
+/* FGMRES for several handles at once (all made on one stream): the Arnoldi
+ * steps of every column of every problem advance together and each step's
+ * preconditioner applies and SpMVs run one launch per phase for all problems
+ * (Section 4's method per column, batched across requests).  Problem i:
+ * b[i] and x[i] hold nrhs[i] columns with leading dimension n_i (device
+ * pointers if on_device != 0, else host), solved to tol[i].  info (may be
+ * NULL) receives sum(nrhs) entries, problem by problem.  Returns ENOCONV if
+ * some column hit maxit (the largest restart and maxit of the handles
+ * apply), EINVAL (bad arguments, handles on different streams), EDEVICE. */
+spaqr_status spaqr_solve_batch(int nprob, spaqr_handle* const* h, const double* const* b,
+                               double* const* x, const int64_t* nrhs, int on_device,
+                               const double* tol, spaqr_solve_info* info);
 
 /* Factorization statistics. */
 typedef struct {

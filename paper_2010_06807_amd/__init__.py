@@ -18,8 +18,9 @@ import numpy as np
 from . import _abi
 from ._abi import CSR, Opts, SolveInfo, SpaqrError, check
 
-__all__ = ["order_grid", "analyze", "factor", "factor_device", "DeviceCSR", "GridOrdering", "Symbolic",
-           "Factorization", "Server", "SpaqrError", "load_library", "profile_enable", "profile_query"]
+__all__ = ["order_grid", "analyze", "factor", "factor_device", "factor_batch", "solve_batch", "DeviceCSR",
+           "GridOrdering", "Symbolic", "Factorization", "Server", "SpaqrError", "load_library", "profile_enable",
+           "profile_query"]
 
 
 def load_library():
@@ -172,7 +173,12 @@ class Factorization:
     """A spaQR factorization resident on the GPU (spaqr_factor)."""
 
     def __init__(self, A, ordering=None, symbolic=None, eps=1e-2, skip=2, precision=32, restart=100,
-                 maxit=1000, stream=None, device_csr=None):
+                 maxit=1000, stream=None, device_csr=None, _handle=None):
+        if _handle is not None:          # made by factor_batch
+            self._h = _handle
+            self._sym = symbolic
+            self.n = A.shape[0]
+            return
         lib = _abi.load()
         csr, keep = _csr_struct(A)
         o = make_opts(eps, skip, precision, restart, maxit)
@@ -190,6 +196,7 @@ class Factorization:
         check(st, "spaqr_factor")
         del keep
         self._h = h
+        self._sym = symbolic   # the handle reads the analysis it was made from
         self.n = A.shape[0]
 
     def __del__(self):
@@ -288,6 +295,87 @@ def factor_device(A, symbolic, dcsr, eps=1e-2, **kw):
     """Factorize with A's values taken from device memory (dcsr: DeviceCSR);
     A (host) supplies only the pattern the symbolic analysis was made from."""
     return Factorization(A, symbolic=symbolic, eps=eps, device_csr=dcsr, **kw)
+
+
+def factor_batch(As, symbolics, dcsrs=None, eps=1e-2, skip=2, precision=32, restart=100, maxit=1000,
+                 stream=None):
+    """Factorize several problems together (spaqr_factor_batch): stage by
+    stage, all their fronts, scalings and sparsifications share one launch per
+    phase.  As: scipy CSR matrices (the pattern; also the values when dcsrs is
+    None); symbolics: their analyses; dcsrs: DeviceCSR copies or None.
+    Returns one Factorization per problem."""
+    lib = _abi.load()
+    n = len(As)
+    if n == 0 or len(symbolics) != n or (dcsrs is not None and len(dcsrs) != n):
+        raise ValueError("factor_batch: one matrix and one analysis per problem")
+    keep, csrs, devs = [], [], []
+    for i, A in enumerate(As):
+        s, k = _csr_struct(A)
+        keep.append(k)
+        csrs.append(s)
+        if dcsrs is not None:
+            d = dcsrs[i]
+            devs.append(_abi.CSRDev(d.rowptr.data_ptr(), d.col.data_ptr(), d.val.data_ptr()))
+    csr_p = (C.POINTER(CSR) * n)(*[C.pointer(s) for s in csrs])
+    dev_p = (C.POINTER(_abi.CSRDev) * n)(*[C.pointer(d) for d in devs]) if dcsrs is not None else None
+    sym_p = (C.c_void_p * n)(*[s.handle.value if hasattr(s.handle, "value") else s.handle for s in symbolics])
+    out = (C.c_void_p * n)()
+    o = make_opts(eps, skip, precision, restart, maxit)
+    st = lib.spaqr_factor_batch(n, csr_p, dev_p, sym_p, C.byref(o), _stream_ptr(stream), out)
+    facs = [Factorization(As[i], symbolic=symbolics[i], _handle=C.c_void_p(out[i])) if out[i] else None
+            for i in range(n)]
+    del keep
+    check(st, "spaqr_factor_batch")
+    return facs
+
+
+def solve_batch(facs, bs, tol=1e-10):
+    """FGMRES for several factorizations at once (spaqr_solve_batch): every
+    Arnoldi step applies all their preconditioners in one launch per phase.
+    bs: torch CUDA tensors of shape (n_i,) or (n_i, nrhs_i) with contiguous
+    columns (all on the device), or numpy arrays (all on the host).
+    tol: one value or one per problem.  Returns (xs, infos)."""
+    lib = _abi.load()
+    n = len(facs)
+    if n == 0 or len(bs) != n:
+        raise ValueError("solve_batch: one right-hand side block per factorization")
+    tols = [float(tol)] * n if np.isscalar(tol) else [float(t) for t in tol]
+    on_dev = hasattr(bs[0], "is_cuda") and bs[0].is_cuda
+    xs, bp, xp, nr = [], [], [], []
+    if on_dev:
+        import torch
+        for f, b in zip(facs, bs):
+            b2 = b if b.ndim == 2 else b.reshape(-1, 1)
+            if b2.shape[0] != f.n or (b2.shape[1] > 1 and b2.stride(1) != f.n) or b2.stride(0) != 1:
+                raise ValueError("device right-hand sides must be n x nrhs with contiguous columns")
+            x = torch.empty_like(b)
+            xs.append(x)
+            bp.append(b.data_ptr())
+            xp.append(x.data_ptr())
+            nr.append(b2.shape[1])
+    else:
+        keep = []
+        for f, b in zip(facs, bs):
+            b = np.asarray(b, dtype=np.float64, order="F")
+            if b.shape[0] != f.n:
+                raise ValueError("right-hand side size differs from the factorization")
+            x = np.empty_like(b, order="F")
+            keep.append(b)
+            xs.append(x)
+            bp.append(b.ctypes.data)
+            xp.append(x.ctypes.data)
+            nr.append(1 if b.ndim == 1 else b.shape[1])
+    hs = (C.c_void_p * n)(*[f._h.value if hasattr(f._h, "value") else f._h for f in facs])
+    info = (SolveInfo * sum(nr))()
+    st = lib.spaqr_solve_batch(n, hs, (C.c_void_p * n)(*bp), (C.c_void_p * n)(*xp), (C.c_int64 * n)(*nr),
+                               1 if on_dev else 0, (C.c_double * n)(*tols), info)
+    check(st, "spaqr_solve_batch")
+    infos, c = [], 0
+    for k in nr:
+        infos.append([dict(iterations=i.iterations, converged=bool(i.converged), relres=i.relres,
+                           seconds=i.seconds) for i in info[c:c + k]])
+        c += k
+    return xs, infos
 
 
 def profile_enable(on=True, only=None):

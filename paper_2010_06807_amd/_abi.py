@@ -64,9 +64,13 @@ SIGNATURES = {
     "spaqr_factor_symbolic": (C.c_int, [C.POINTER(CSR), _P, C.POINTER(Opts), _P, C.POINTER(_P)]),
     "spaqr_factor_device": (C.c_int, [C.POINTER(CSR), C.POINTER(CSRDev), _P, C.POINTER(Opts), _P,
                                       C.POINTER(_P)]),
+    "spaqr_factor_batch": (C.c_int, [C.c_int, C.POINTER(C.POINTER(CSR)), C.POINTER(C.POINTER(CSRDev)),
+                                     C.POINTER(_P), C.POINTER(Opts), _P, C.POINTER(_P)]),
     "spaqr_apply": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_int]),
     "spaqr_solve": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, C.c_int, C.c_double,
                               C.POINTER(SolveInfo)]),
+    "spaqr_solve_batch": (C.c_int, [C.c_int, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), _I64P, C.c_int, _DP,
+                                    C.POINTER(SolveInfo)]),
     "spaqr_stats": (C.c_int, [_P, C.POINTER(Stats)]),
     "spaqr_stage_sizes": (C.c_int, [_P, C.c_int, _I32P, C.c_int64, _I64P]),
     "spaqr_free": (None, [_P]),

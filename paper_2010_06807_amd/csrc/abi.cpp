@@ -4,8 +4,11 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "engine.hpp"
+#include "pool.hpp"
 
 using namespace spaqr;
 
@@ -221,6 +224,124 @@ spaqr_status spaqr_factor_device(const spaqr_csr* A, const spaqr_csr_dev* Ad, co
   });
 }
 
+spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaqr_csr_dev* const* Ad,
+                                const spaqr_symbolic* const* sym, const spaqr_opts* opts, void* hip_stream,
+                                spaqr_handle** out) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(nprob >= 1 && A && sym && out, SPAQR_EINVAL, "NULL argument");
+    for (int i = 0; i < nprob; ++i) out[i] = nullptr;
+    require_device();
+    const spaqr_opts o = opts ? *opts : spaqr_opts_default();
+    SPAQR_REQUIRE(o.restart >= 1 && o.maxit >= 1, SPAQR_EINVAL, "restart and maxit must be >= 1");
+    const hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    std::vector<std::unique_ptr<spaqr_handle>> hs(nprob);
+    for (int i = 0; i < nprob; ++i) {
+      const spaqr_csr* a = A[i];
+      const spaqr_csr_dev* ad = Ad ? Ad[i] : nullptr;
+      SPAQR_REQUIRE(a && sym[i] && a->rowptr && a->col, SPAQR_EINVAL, "NULL problem argument");
+      SPAQR_REQUIRE(a->n == sym[i]->s.n && a->nnz == sym[i]->s.nnz, SPAQR_EINVAL,
+                    "matrix does not match the analysis");
+      SPAQR_REQUIRE(o.skip == sym[i]->s.skip, SPAQR_EINVAL, "skip differs from the symbolic analysis");
+      if (ad) SPAQR_REQUIRE(ad->rowptr && ad->col && ad->val, SPAQR_EINVAL, "NULL device array");
+      else SPAQR_REQUIRE(a->val, SPAQR_EINVAL, "NULL values");
+      hs[i].reset(new spaqr_handle());
+    }
+    // set-up (uploads, column scaling, first pool) of the problems in parallel
+    {
+      const unsigned hc = std::thread::hardware_concurrency();
+      HostPool pool(nprob > 1 ? (int)std::min<unsigned>(7, std::min<unsigned>(nprob - 1, hc > 1 ? hc - 1 : 0)) : 0);
+      pool.run(nprob, [&](int i) {
+        hs[i]->e = make_engine_deferred(A[i], Ad ? Ad[i] : nullptr, sym[i]->s, o, s);
+      });
+    }
+    std::vector<EngineBase*> es;
+    for (int i = 0; i < nprob; ++i) es.push_back(hs[i]->e.get());
+    BatchDriver* drv = batch_driver_new();
+    try {
+      for (;;) {
+        bool more = false;
+        for (EngineBase* e : es) more = more || e->stages_left() > 0;
+        if (!more) break;
+        factor_stage_batch(*drv, es, s);
+      }
+    } catch (...) {
+      batch_driver_free(drv);
+      (void)hipStreamSynchronize(s);
+      throw;
+    }
+    batch_driver_free(drv);
+    SPAQR_HIP(hipStreamSynchronize(s));
+    spaqr_status st = SPAQR_OK;
+    for (int i = 0; i < nprob; ++i) {
+      const int err = hs[i]->e->error();
+      if (err != SPAQR_OK) {
+        if (st == SPAQR_OK) {
+          st = err;
+          g_last_error = std::string("problem ") + std::to_string(i) + ": " + hs[i]->e->error_message();
+        }
+        hs[i].reset();
+      } else {
+        out[i] = hs[i].release();
+      }
+    }
+    return st;
+  });
+}
+
+spaqr_status spaqr_solve_batch(int nprob, spaqr_handle* const* h, const double* const* b, double* const* x,
+                               const int64_t* nrhs, int on_device, const double* tol, spaqr_solve_info* info) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(nprob >= 1 && h && b && x && nrhs && tol, SPAQR_EINVAL, "NULL argument");
+    std::vector<EngineBase*> es;
+    std::vector<int> nr;
+    std::vector<double> tl;
+    for (int i = 0; i < nprob; ++i) {
+      SPAQR_REQUIRE(h[i] && b[i] && x[i], SPAQR_EINVAL, "NULL problem argument");
+      SPAQR_REQUIRE(nrhs[i] >= 1 && nrhs[i] <= (1 << 16), SPAQR_EINVAL, "bad number of right-hand sides");
+      SPAQR_REQUIRE(tol[i] > 0.0 && std::isfinite(tol[i]), SPAQR_EINVAL, "tol must be > 0");
+      SPAQR_REQUIRE(!on_device || b[i] != x[i], SPAQR_EINVAL, "b and x must not alias");
+      es.push_back(h[i]->e.get());
+      nr.push_back((int)nrhs[i]);
+      tl.push_back(tol[i]);
+    }
+    const hipStream_t s = es[0]->stream();
+    if (on_device) {
+      std::vector<const double*> db(b, b + nprob);
+      std::vector<double*> dx(x, x + nprob);
+      return fgmres_solve_batch(es, nr, db, dx, tl, info, nullptr);
+    }
+    size_t tot = 0;
+    for (int i = 0; i < nprob; ++i) tot += (size_t)es[i]->n() * nr[i];
+    double* buf = static_cast<double*>(dev_alloc(2 * tot * sizeof(double), s));
+    std::vector<const double*> db;
+    std::vector<double*> dx;
+    size_t o = 0;
+    for (int i = 0; i < nprob; ++i) {
+      const size_t sz = (size_t)es[i]->n() * nr[i];
+      db.push_back(buf + o);
+      dx.push_back(buf + tot + o);
+      o += sz;
+    }
+    int st;
+    try {
+      for (int i = 0; i < nprob; ++i)
+        SPAQR_HIP(hipMemcpyAsync(const_cast<double*>(db[i]), b[i], (size_t)es[i]->n() * nr[i] * sizeof(double),
+                                 hipMemcpyHostToDevice, s));
+      st = fgmres_solve_batch(es, nr, db, dx, tl, info, nullptr);
+      for (int i = 0; i < nprob; ++i)
+        SPAQR_HIP(hipMemcpyAsync(x[i], dx[i], (size_t)es[i]->n() * nr[i] * sizeof(double), hipMemcpyDeviceToHost,
+                                 s));
+      SPAQR_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      dev_free(buf, s);
+      throw;
+    }
+    dev_free(buf, s);
+    return st;
+  });
+}
+
 static void to_device(spaqr_handle* h, const double* b, int64_t nrhs, int64_t ld, double** db) {
   const int64_t N = h->e->n();
   *db = static_cast<double*>(dev_alloc((size_t)N * nrhs * sizeof(double), h->e->stream()));
@@ -257,14 +378,16 @@ spaqr_status spaqr_solve(spaqr_handle* h, const double* b, double* x, int64_t nr
     const int64_t N = h->e->n();
     hipStream_t s = h->e->stream();
     int st;
+    const std::vector<double> tv((size_t)nrhs, tol);
+    EngineBase& e = *h->e;
     if (on_device) {
       SPAQR_REQUIRE(b != x, SPAQR_EINVAL, "b and x must not alias in spaqr_solve");
-      st = fgmres_solve(*h->e, b, ld, x, ld, (int)nrhs, tol, info);
+      st = fgmres_solve(e, b, ld, x, ld, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info);
     } else {
       double *db = nullptr, *dx = nullptr;
       to_device(h, b, nrhs, ld, &db);
       dx = static_cast<double*>(dev_alloc((size_t)N * nrhs * sizeof(double), s));
-      st = fgmres_solve(*h->e, db, N, dx, N, (int)nrhs, tol, info);
+      st = fgmres_solve(e, db, N, dx, N, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info);
       SPAQR_HIP(hipMemcpy2DAsync(x, ld * sizeof(double), dx, N * sizeof(double), N * sizeof(double), nrhs,
                                  hipMemcpyDeviceToHost, s));
       dev_free(db, s);

@@ -52,6 +52,15 @@ class Stager {
     return static_cast<X*>(upload_bytes(arena, v.data(), v.size() * sizeof(X), s));
   }
   void* upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s);
+  // two-step upload: stage() hands out a pinned host region and its device
+  // destination, the caller fills the host side, send() issues the copy
+  struct Region {
+    void* host;
+    void* dev;
+    size_t bytes;
+  };
+  Region stage(DevArena& arena, size_t bytes, hipStream_t s);
+  void send(const Region& r, hipStream_t s);
   void reset() { cur_ = 0; off_ = 0; }
 
  private:
@@ -77,6 +86,10 @@ struct StageApply {
   std::vector<double> fwd_fac_bytes, fwd_vec_bytes, fwd_flops;  // per colour
   double bwd_fac_bytes = 0, bwd_vec_bytes = 0, bwd_flops = 0;
   double if_fwd_fac_bytes = 0, if_bwd_fac_bytes = 0, if_vec_bytes = 0, if_fwd_flops = 0, if_bwd_flops = 0;
+  // host copies of the descriptors (fronts in colour order, interfaces with
+  // the dense-operator ones first), for applies batched across problems
+  std::vector<ApFront<T>> h_fronts;
+  std::vector<ApIface<T>> h_ifaces;
 };
 
 struct Stats {
@@ -84,15 +97,22 @@ struct Stats {
   std::vector<std::vector<int32_t>> stage_sizes;  // index k: sizes after stage k
 };
 
-class EngineBase {
+// What FGMRES needs of a system: n rows per column, the preconditioner and
+// the matrix applied to ncols columns at once (device pointers, column-major).
+class KrylovOp {
  public:
-  virtual ~EngineBase() = default;
-  // x = M^{-1} b; device pointers, column-major
-  virtual void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) = 0;
-  virtual void spmv_dev(const double* x, int64_t ldx, double* y, int64_t ldy, int nrhs) = 0;
-  virtual const Stats& stats() const = 0;
+  virtual ~KrylovOp() = default;
+  // x = M^{-1} b
+  virtual void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int ncols) = 0;
+  // y = A x
+  virtual void spmv_dev(const double* x, int64_t ldx, double* y, int64_t ldy, int ncols) = 0;
   virtual hipStream_t stream() const = 0;
   virtual int64_t n() const = 0;
+};
+
+class EngineBase : public KrylovOp {
+ public:
+  virtual const Stats& stats() const = 0;
   virtual int opt_restart() const = 0;
   virtual int opt_maxit() const = 0;
   virtual int stages_left() const = 0;  // 0 once the factorization is complete (or failed)
@@ -116,9 +136,24 @@ BatchDriver* batch_driver_new();
 void batch_driver_free(BatchDriver* d);
 void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s);
 
-// FGMRES on the device (gmres.hip).
-int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs,
-                 double tol, spaqr_solve_info* info);
+// Several factorizations as one block-diagonal operator for FGMRES: problem
+// i owns nrhs[i] consecutive columns, problems in the order of es; the
+// factorizations must share one stream.  n() is the largest n; rows of a
+// column beyond its problem's n are neither read nor written.  Every apply
+// runs one launch per phase for all problems (cross-request batching).
+std::unique_ptr<KrylovOp> make_batch_op(const std::vector<EngineBase*>& es, const std::vector<int>& nrhs);
+
+// FGMRES on the device (gmres.hip); tol holds one tolerance per column.
+int fgmres_solve(KrylovOp& op, const double* b, int64_t ldb, double* x, int64_t ldx, int ncols,
+                 const double* tol, int restart, int maxit, spaqr_solve_info* info);
+// FGMRES for several factored problems at once (make_batch_op): problem i
+// solves nrhs[i] columns b[i] -> x[i] (device, column-major, ld = its n) to
+// tol[i].  info receives one entry per column in problem order; status (may
+// be null) one per problem (OK or ENOCONV).  Returns ENOCONV if any column
+// did not converge.
+int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int>& nrhs,
+                       const std::vector<const double*>& b, const std::vector<double*>& x,
+                       const std::vector<double>& tol, spaqr_solve_info* info, std::vector<int>* status);
 
 double now_ms();
 

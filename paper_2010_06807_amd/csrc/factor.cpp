@@ -23,6 +23,7 @@
 #include <string>
 
 #include "engine.hpp"
+#include "pool.hpp"
 #include "profile.hpp"
 
 namespace spaqr {
@@ -76,7 +77,7 @@ Stager::~Stager() {
   for (auto& c : chunks_) pinned_release(c);
 }
 
-void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
+Stager::Region Stager::stage(DevArena& arena, size_t bytes, hipStream_t s) {
   void* dst = arena.alloc(bytes, s);
   size_t need = (bytes + 255) & ~size_t(255);
   while (cur_ < chunks_.size() && off_ + need > chunks_[cur_].size) {
@@ -90,9 +91,18 @@ void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipSt
   }
   char* h = chunks_[cur_].p + off_;
   off_ += need;
-  std::memcpy(h, src, bytes);
-  SPAQR_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s));
-  return dst;
+  return {h, dst, bytes};
+}
+
+void Stager::send(const Region& r, hipStream_t s) {
+  if (r.bytes) SPAQR_HIP(hipMemcpyAsync(r.dev, r.host, r.bytes, hipMemcpyHostToDevice, s));
+}
+
+void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
+  const Region r = stage(arena, bytes, s);
+  std::memcpy(r.host, src, bytes);
+  send(r, s);
+  return r.dev;
 }
 
 void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, int64_t n, const double* x,
@@ -183,6 +193,13 @@ class Engine final : public EngineBase {
   int precision() const override { return sizeof(T) == 4 ? 32 : 64; }
   int error() const override { return err_; }
   const char* error_message() const override { return err_msg_.c_str(); }
+
+  // what an apply batched across problems reads
+  const std::vector<StageApply<T>>& stage_apply() const { return ap_; }
+  int levels() const { return S_.L; }
+  const int64_t* perm_dev() const { return d_perm_; }
+  const double* colscale_dev() const { return d_dc_; }
+  SpmvCol spmv_col() const { return {d_rowptr_, d_col_, d_val_, S_.n}; }
 
   // stage k_ as launch lists, in three parts that the driver launches in
   // turn: fronts (and the factor packing), scaling, sparsification (each
@@ -509,6 +526,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
     }
     ap.fronts = up.upload(persist_, af, s_);
     ap.nfronts = (int64_t)af.size();
+    ap.h_fronts = std::move(af);
   }
 
   {
@@ -685,6 +703,7 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
   ap.ifaces = up.upload(persist_, ai, s_);
   ap.nifaces = (int64_t)ai.size();
   P.form.assign(ai.begin(), ai.begin() + ap.nifaces_small);
+  ap.h_ifaces = std::move(ai);
   st_.s.interfaces_sparsified += (int64_t)ai.size();
 }
 
@@ -820,10 +839,20 @@ struct BatchCtx {
   Stager st[2];
   DevArena work[2] = {DevArena(size_t(16) << 20), DevArena(size_t(16) << 20)};
   int cur = 0;
+  std::unique_ptr<HostPool> pool;  // per-problem planning of a batch, in parallel
   void begin() {
     cur ^= 1;
     st[cur].reset();
     work[cur].reset();
+  }
+  void each(size_t n, const std::function<void(int)>& fn) {
+    if (n > 1 && !pool) {
+      const unsigned hc = std::thread::hardware_concurrency();
+      pool.reset(new HostPool((int)std::min<unsigned>(7, hc > 1 ? hc - 1 : 0)));
+    }
+    if (pool) pool->run((int)n, fn);
+    else
+      for (size_t i = 0; i < n; ++i) fn((int)i);
   }
 };
 
@@ -868,6 +897,35 @@ static void launch_qr_groups(std::vector<std::pair<int, std::vector<QRDesc<T>>>>
     QRDesc<T>* d = up.upload(wk, kv.second.second, s);
     launch_qr<T>(d, (int64_t)kv.second.second.size(), kv.first.first, kv.second.first, s);
   }
+}
+
+// The concatenation of get(0), get(1), ... uploaded in one copy; large lists
+// are packed into the pinned staging buffer by the planning threads.
+template <typename X, typename Get>
+static X* upload_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, hipStream_t s,
+                        int64_t* count) {
+  std::vector<size_t> off(ne + 1, 0);
+  for (size_t e = 0; e < ne; ++e) off[e + 1] = off[e] + get(e).size();
+  *count = (int64_t)off[ne];
+  if (off[ne] == 0) return nullptr;
+  const Stager::Region r = up.stage(wk, off[ne] * sizeof(X), s);
+  X* h = static_cast<X*>(r.host);
+  auto put = [&](int e) {
+    const std::vector<X>& v = get(e);
+    if (!v.empty()) std::memcpy(h + off[e], v.data(), v.size() * sizeof(X));
+  };
+  if (ne > 1 && off[ne] * sizeof(X) > (size_t(1) << 20)) bx.each(ne, put);
+  else
+    for (size_t e = 0; e < ne; ++e) put((int)e);
+  up.send(r, s);
+  return static_cast<X*>(r.dev);
+}
+
+template <typename T, typename Get>
+static void copy_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, hipStream_t s) {
+  int64_t n = 0;
+  CopyTile<T>* d = upload_concat<CopyTile<T>>(bx, up, wk, ne, get, s, &n);
+  if (n > 0) launch_copy<T>(d, n, s);
 }
 
 template <typename T>
@@ -1007,6 +1065,11 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
     launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, (int)g[2], (int)g[3], max_nb, s);
   for (const CoopLaunch& L : coop) {
     const int64_t i0 = L.begin - nreg, ni = L.end - L.begin;
+    if (getenv("SPAQR_DEBUG_COOP")) {
+      double mp = 0; int pm = 0, mm = 0;
+      for (int64_t t = L.begin; t < L.end; ++t) { mp += (double)sd[t].mmax * sd[t].P; pm = std::max<int>(pm, sd[t].P); mm = std::max<int>(mm, sd[t].mmax); }
+      fprintf(stderr, "COOP ni %lld blocks %d cpt %d maxp %d maxm %d kmax %d sumMP %.3g MB\n", (long long)ni, L.blocks, coop_cpt, pm, mm, L.kmax, mp * sizeof(T) / 1e6);
+    }
     if (!launch_sparsify_coop<T>(dsd + L.begin, ditems + i0, (int)ni, L.blocks, coop_cpt, dnb, coop_maxp, coop_maxnb,
                                  ckey, cpos, ccol, done + 2 * i0, L.kmax, s))
       throw Error(SPAQR_EDEVICE, "cooperative CPQR no longer fits the device");
@@ -1031,24 +1094,31 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     }
     launch_zero_ops(z, up, wk, s);
   };
-  for (size_t e = 0; e < ne; ++e) es[e]->plan_fronts(pl[e]);
+  {
+    HostScope hs("host_plan_fronts");
+    bx.each(ne, [&](int e) { es[e]->plan_fronts(pl[e]); });
+  }
   flush_zero();
   // fronts, colour by colour
+  {
+  HostScope hs_fronts("host_launch_fronts");
   size_t nc = 0;
   for (auto& p : pl) nc = std::max(nc, p.fronts.size());
+  static const std::vector<CopyTile<T>> none;
   for (size_t c = 0; c < nc; ++c) {
-    std::vector<CopyTile<T>> g, sc;
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     double fl = 0.0, by = 0.0;
     for (auto& p : pl) {
       if (c >= p.fronts.size()) continue;
-      append(g, p.fronts[c].gather);
-      append(sc, p.fronts[c].scatter);
       qparts.emplace_back(p.jbf, p.fronts[c].qr);
       fl += p.fronts[c].flops;
       by += p.fronts[c].bytes;
     }
-    copy_batch(g, up, wk, s);
+    copy_concat<T>(bx, up, wk, ne,
+                   [&](int e) -> const std::vector<CopyTile<T>>& {
+                     return c < pl[e].fronts.size() ? pl[e].fronts[c].gather : none;
+                   },
+                   s);
     launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
     {
       // trailing slices of split fronts, grouped by (panel width, slice width)
@@ -1067,17 +1137,22 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
         }
       }
     }
-    copy_batch(sc, up, wk, s);
+    copy_concat<T>(bx, up, wk, ne,
+                   [&](int e) -> const std::vector<CopyTile<T>>& {
+                     return c < pl[e].fronts.size() ? pl[e].fronts[c].scatter : none;
+                   },
+                   s);
   }
-  {
-    std::vector<CopyTile<T>> pk;
-    for (auto& p : pl) append(pk, p.pack);
-    copy_batch(pk, up, wk, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, s);
   }
   // block-diagonal scaling
-  for (size_t e = 0; e < ne; ++e) es[e]->plan_scale(pl[e]);
+  {
+    HostScope hs("host_plan_scale");
+    bx.each(ne, [&](int e) { es[e]->plan_scale(pl[e]); });
+  }
   flush_zero();
   {
+    HostScope hs("host_launch_scale");
     std::vector<CopyTile<T>> g, pk;
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     std::vector<ScaleFac<T>> fac;
@@ -1124,8 +1199,13 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     }
   }
   // sparsification, colour by colour
-  for (size_t e = 0; e < ne; ++e) es[e]->plan_sparsify(pl[e]);
+  {
+    HostScope hs("host_plan_sparsify");
+    bx.each(ne, [&](int e) { es[e]->plan_sparsify(pl[e]); });
+  }
   flush_zero();
+  {
+  HostScope hs_sp("host_launch_sparsify");
   size_t nsc = 0;
   for (auto& p : pl) nsc = std::max(nsc, p.sp.size());
   for (size_t c = 0; c < nsc; ++c) {
@@ -1150,19 +1230,23 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       launch_iface_form<T>(d, (int64_t)form.size(), s);
     }
   }
-  // ranks back, merges
-  for (Engine<T>* e : es) e->readback();
-  SPAQR_HIP(hipStreamSynchronize(s));
-  std::vector<MergePlan<T>> mp(ne);
-  for (size_t e = 0; e < ne; ++e) es[e]->finish(mp[e]);
-  std::vector<ZeroOp> z;
-  std::vector<CopyTile<T>> tiles;
-  for (auto& m : mp) {
-    append(z, m.zero);
-    append(tiles, m.tiles);
   }
+  // ranks back, merges
+  {
+    HostScope hs("host_wait_gpu");
+    for (Engine<T>* e : es) e->readback();
+    SPAQR_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<MergePlan<T>> mp(ne);
+  {
+    HostScope hs("host_finish");
+    bx.each(ne, [&](int e) { es[e]->finish(mp[e]); });
+  }
+  HostScope hs_merge("host_launch_merge");
+  std::vector<ZeroOp> z;
+  for (auto& m : mp) append(z, m.zero);
   launch_zero_ops(z, up, wk, s);
-  copy_batch(tiles, up, wk, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, s);
 }
 
 template <typename T>
@@ -1207,6 +1291,220 @@ void Engine<T>::apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, 
   SPAQR_HIP(hipGetLastError());
 }
 
+// ------------------------------------------------- apply across problems
+// The preconditioners of several factorizations, each applied to its own
+// columns, with one launch per phase of the apply: the descriptors of every
+// problem's stage k (colour c) are concatenated, each carrying the offset of
+// its problem's permuted vector in one shared buffer, so an apply costs the
+// launches of the deepest problem alone.
+template <typename T>
+class BatchApply {
+ public:
+  // cols[i]: the columns of problem i (indices into the caller's b and x)
+  BatchApply(const std::vector<Engine<T>*>& es, const std::vector<std::vector<int>>& cols, hipStream_t s)
+      : s_(s) {
+    const size_t ne = es.size();
+    std::vector<int64_t> off(ne, 0);
+    int R = 1, L = 0;
+    for (size_t i = 0; i < ne; ++i) {
+      off[i] = Ntot_;
+      Ntot_ += es[i]->n();
+      R = std::max<int>(R, (int)cols[i].size());
+      L = std::max(L, es[i]->levels());
+      max_n_ = std::max(max_n_, es[i]->n());
+    }
+    SPAQR_REQUIRE(Ntot_ < (int64_t(1) << 31), SPAQR_EINVAL, "batched apply: too many unknowns in one batch");
+    R_ = R;
+    std::vector<PermCol> pc;
+    for (size_t i = 0; i < ne; ++i)
+      for (size_t r = 0; r < cols[i].size(); ++r)
+        pc.push_back({cols[i][r], off[i] + (int64_t)r * Ntot_, es[i]->perm_dev(), es[i]->colscale_dev(), es[i]->n()});
+    ncols_ = (int)pc.size();
+    lv_.assign(L + 1, Level());
+    for (int k = 1; k <= L; ++k) {
+      Level& v = lv_[k];
+      std::map<int, std::vector<ApFront<T>>> fwd_by_c_jb;  // key: colour * 64 + jb
+      std::map<int, int> fwd_max_m;
+      std::vector<ApFront<T>> bwd;
+      std::vector<ApIface<T>> dense, other;
+      for (size_t i = 0; i < ne; ++i) {
+        if (k > es[i]->levels()) continue;
+        const StageApply<T>& a = es[i]->stage_apply()[k];
+        for (size_t c = 0; c + 1 < a.colour_ptr.size(); ++c)
+          for (int64_t t = a.colour_ptr[c]; t < a.colour_ptr[c + 1]; ++t) {
+            ApFront<T> d = a.h_fronts[t];
+            d.xoff = (int32_t)off[i];
+            const int key = (int)c * 64 + a.jb;
+            fwd_by_c_jb[key].push_back(d);
+            int& mm = fwd_max_m[key];
+            mm = std::max(mm, a.colour_max_m[c]);
+          }
+        for (ApFront<T> d : a.h_fronts) {
+          d.xoff = (int32_t)off[i];
+          bwd.push_back(d);
+        }
+        v.max_n = std::max(v.max_n, a.max_n);
+        v.max_k = std::max(v.max_k, a.max_k);
+        for (int64_t t = 0; t < (int64_t)a.h_ifaces.size(); ++t) {
+          ApIface<T> d = a.h_ifaces[t];
+          d.xoff = (int32_t)off[i];
+          (t < a.nifaces_small ? dense : other).push_back(d);
+        }
+        v.max_p = std::max(v.max_p, a.max_p);
+        for (size_t c = 0; c < a.fwd_flops.size(); ++c) {
+          v.fwd_flops += a.fwd_flops[c];
+          v.fwd_fac_bytes += a.fwd_fac_bytes[c];
+          v.fwd_vec_bytes += a.fwd_vec_bytes[c];
+        }
+        v.bwd_flops += a.bwd_flops;
+        v.bwd_fac_bytes += a.bwd_fac_bytes;
+        v.bwd_vec_bytes += a.bwd_vec_bytes;
+        v.if_fwd_flops += a.if_fwd_flops;
+        v.if_bwd_flops += a.if_bwd_flops;
+        v.if_fwd_fac_bytes += a.if_fwd_fac_bytes;
+        v.if_bwd_fac_bytes += a.if_bwd_fac_bytes;
+        v.if_vec_bytes += a.if_vec_bytes;
+      }
+      for (auto& kv : fwd_by_c_jb)
+        v.fwd.push_back({st_.upload(ar_, kv.second, s_), (int64_t)kv.second.size(), kv.first % 64,
+                         fwd_max_m[kv.first]});
+      v.nbwd = (int64_t)bwd.size();
+      v.bwd = st_.upload(ar_, bwd, s_);
+      v.nif_dense = (int64_t)dense.size();
+      v.nif = v.nif_dense + (int64_t)other.size();
+      dense.insert(dense.end(), other.begin(), other.end());
+      v.ifs = st_.upload(ar_, dense, s_);
+    }
+    pc_ = st_.upload(ar_, pc, s_);
+    X_ = ar_.alloc_n<double>((size_t)Ntot_ * R_, s_);
+    SPAQR_HIP(hipMemsetAsync(X_, 0, (size_t)Ntot_ * R_ * sizeof(double), s_));
+    SPAQR_HIP(hipStreamSynchronize(s_));  // staged uploads done
+  }
+  ~BatchApply() { (void)hipStreamSynchronize(s_); }
+
+  // x[:, cols] = M^{-1} b[:, cols] for this batch's columns
+  void apply(const double* b, int64_t ldb, double* x, int64_t ldx) {
+    launch_gather_cols(X_, b, ldb, pc_, ncols_, max_n_, s_);
+    const int L = (int)lv_.size() - 1;
+    const int nr = R_;
+    for (int k = L; k >= 1; --k) {
+      const Level& v = lv_[k];
+      if (!v.fwd.empty()) {
+        ProfScope ps("apply_front_fwd", s_, v.fwd_flops * nr, v.fwd_fac_bytes + v.fwd_vec_bytes * nr);
+        for (const FwdLaunch& f : v.fwd) launch_front_fwd_wy<T>(f.d, f.n, f.jb, f.max_m, X_, Ntot_, nr, s_);
+      }
+      if (v.nif) {
+        ProfScope ps("apply_iface_fwd", s_, v.if_fwd_flops * nr, v.if_fwd_fac_bytes + v.if_vec_bytes * nr);
+        launch_iface_dense<T>(v.ifs, v.nif_dense, false, X_, Ntot_, nr, s_);
+        launch_iface_fwd<T>(v.ifs + v.nif_dense, v.nif - v.nif_dense, v.max_p, X_, Ntot_, nr, s_);
+      }
+    }
+    for (int k = 1; k <= L; ++k) {
+      const Level& v = lv_[k];
+      if (v.nif) {
+        ProfScope ps("apply_iface_bwd", s_, v.if_bwd_flops * nr, v.if_bwd_fac_bytes + v.if_vec_bytes * nr);
+        launch_iface_dense<T>(v.ifs, v.nif_dense, true, X_, Ntot_, nr, s_);
+        launch_iface_bwd<T>(v.ifs + v.nif_dense, v.nif - v.nif_dense, v.max_p, X_, Ntot_, nr, s_);
+      }
+      if (v.nbwd) {
+        ProfScope ps("apply_front_bwd", s_, v.bwd_flops * nr, v.bwd_fac_bytes + v.bwd_vec_bytes * nr);
+        launch_front_bwd_reg<T>(v.bwd, v.nbwd, v.max_n, v.max_k, X_, Ntot_, nr, s_);
+      }
+    }
+    launch_scatter_cols(x, ldx, X_, pc_, ncols_, max_n_, s_);
+    SPAQR_HIP(hipGetLastError());
+  }
+
+ private:
+  struct FwdLaunch {
+    const ApFront<T>* d;
+    int64_t n;
+    int jb, max_m;
+  };
+  struct Level {
+    std::vector<FwdLaunch> fwd;  // colour by colour, one launch per panel width
+    const ApFront<T>* bwd = nullptr;
+    int64_t nbwd = 0;
+    int max_n = 0, max_k = 0;
+    const ApIface<T>* ifs = nullptr;  // dense-operator interfaces first
+    int64_t nif = 0, nif_dense = 0;
+    int max_p = 0;
+    double fwd_flops = 0, fwd_fac_bytes = 0, fwd_vec_bytes = 0, bwd_flops = 0, bwd_fac_bytes = 0, bwd_vec_bytes = 0;
+    double if_fwd_flops = 0, if_bwd_flops = 0, if_fwd_fac_bytes = 0, if_bwd_fac_bytes = 0, if_vec_bytes = 0;
+  };
+  hipStream_t s_;
+  DevArena ar_{size_t(8) << 20};
+  Stager st_;
+  std::vector<Level> lv_;
+  const PermCol* pc_ = nullptr;
+  double* X_ = nullptr;
+  int64_t Ntot_ = 0, max_n_ = 0;
+  int R_ = 1, ncols_ = 0;
+};
+
+// FGMRES operator over the columns of several problems (FP32 and FP64
+// factorizations in separate batched applies, one SpMV launch for all).
+class MultiOp final : public KrylovOp {
+ public:
+  MultiOp(const std::vector<EngineBase*>& es, const std::vector<int>& nrhs) {
+    SPAQR_REQUIRE(!es.empty() && es.size() == nrhs.size(), SPAQR_EINVAL, "batched solve: bad problem list");
+    s_ = es[0]->stream();
+    std::vector<Engine<float>*> e32;
+    std::vector<Engine<double>*> e64;
+    std::vector<std::vector<int>> c32, c64;
+    std::vector<SpmvCol> sc;
+    int col = 0;
+    for (size_t i = 0; i < es.size(); ++i) {
+      EngineBase* e = es[i];
+      SPAQR_REQUIRE(e->stream() == s_, SPAQR_EINVAL, "batched problems must share one stream");
+      SPAQR_REQUIRE(e->stages_left() == 0 && e->error() == SPAQR_OK, SPAQR_EINVAL,
+                    "batched solve of an incomplete factorization");
+      SPAQR_REQUIRE(nrhs[i] >= 1, SPAQR_EINVAL, "batched solve: a problem without right-hand sides");
+      std::vector<int> cs;
+      for (int r = 0; r < nrhs[i]; ++r) cs.push_back(col++);
+      n_ = std::max(n_, e->n());
+      if (e->precision() == 32) {
+        auto* ef = static_cast<Engine<float>*>(e);
+        e32.push_back(ef);
+        c32.push_back(cs);
+        for (int r = 0; r < nrhs[i]; ++r) sc.push_back(ef->spmv_col());
+      } else {
+        auto* ed = static_cast<Engine<double>*>(e);
+        e64.push_back(ed);
+        c64.push_back(cs);
+        for (int r = 0; r < nrhs[i]; ++r) sc.push_back(ed->spmv_col());
+      }
+    }
+    ncols_ = col;
+    if (!e32.empty()) b32_.reset(new BatchApply<float>(e32, c32, s_));
+    if (!e64.empty()) b64_.reset(new BatchApply<double>(e64, c64, s_));
+    sc_ = st_.upload(ar_, sc, s_);
+    SPAQR_HIP(hipStreamSynchronize(s_));
+  }
+  ~MultiOp() override { (void)hipStreamSynchronize(s_); }
+  void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int ncols) override {
+    SPAQR_REQUIRE(ncols == ncols_, SPAQR_EINVAL, "batched apply: column count differs from the batch");
+    if (b32_) b32_->apply(b, ldb, x, ldx);
+    if (b64_) b64_->apply(b, ldb, x, ldx);
+  }
+  void spmv_dev(const double* x, int64_t ldx, double* y, int64_t ldy, int ncols) override {
+    SPAQR_REQUIRE(ncols == ncols_, SPAQR_EINVAL, "batched SpMV: column count differs from the batch");
+    launch_spmv_cols(sc_, ncols_, n_, x, ldx, y, ldy, s_);
+  }
+  hipStream_t stream() const override { return s_; }
+  int64_t n() const override { return n_; }
+
+ private:
+  hipStream_t s_ = nullptr;
+  int64_t n_ = 0;
+  int ncols_ = 0;
+  std::unique_ptr<BatchApply<float>> b32_;
+  std::unique_ptr<BatchApply<double>> b64_;
+  DevArena ar_{size_t(1) << 20};
+  Stager st_;
+  const SpmvCol* sc_ = nullptr;
+};
+
 }  // namespace
 
 template <typename T>
@@ -1248,6 +1546,10 @@ struct BatchDriver {
 
 BatchDriver* batch_driver_new() { return new BatchDriver(); }
 void batch_driver_free(BatchDriver* d) { delete d; }
+
+std::unique_ptr<KrylovOp> make_batch_op(const std::vector<EngineBase*>& es, const std::vector<int>& nrhs) {
+  return std::unique_ptr<KrylovOp>(new MultiOp(es, nrhs));
+}
 
 void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s) {
   std::vector<Engine<float>*> f32;

@@ -37,6 +37,19 @@ __global__ void k_spmv(const int64_t* __restrict__ rp, const int32_t* __restrict
   }
 }
 
+// y[:, j] = A_j x[:, j] for column j's own CSR matrix (batched problems).
+__global__ void k_spmv_cols(const SpmvCol* __restrict__ sc, const double* __restrict__ x, int64_t ldx,
+                            double* __restrict__ y, int64_t ldy) {
+  const int j = blockIdx.y;
+  const SpmvCol a = sc[j];
+  const double* xj = x + (int64_t)j * ldx;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < a.n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int64_t t = a.rowptr[r]; t < a.rowptr[r + 1]; ++t) s += a.val[t] * xj[a.col[t]];
+    y[r + (int64_t)j * ldy] = s;
+  }
+}
+
 // partial[(c * nblk + blk) * J + j] = sum over the block's rows of
 // X[i + j*sj + c*sc] * w[i + c*ldw]; one wavefront per j, no barriers.
 __global__ void k_dots(const double* __restrict__ X, int64_t sj, int64_t sc, int J, const double* __restrict__ w,
@@ -119,6 +132,12 @@ void launch_spmv(const int64_t* rowptr, const int32_t* col, const double* val, i
   hipLaunchKernelGGL(k_spmv, dim3(gx(n), nrhs), dim3(256), 0, s, rowptr, col, val, n, x, ldx, y, ldy);
 }
 
+void launch_spmv_cols(const SpmvCol* sc, int ncols, int64_t max_n, const double* x, int64_t ldx, double* y,
+                      int64_t ldy, hipStream_t s) {
+  if (ncols <= 0) return;
+  hipLaunchKernelGGL(k_spmv_cols, dim3(gx(max_n), (unsigned)ncols), dim3(256), 0, s, sc, x, ldx, y, ldy);
+}
+
 // h[c*J + j] = X[:, j, c] . w[:, c]
 static void dots(const double* X, int64_t sj, int64_t sc, int J, const double* w, int64_t ldw, int64_t n,
                  int nrhs, double* partial, double* out, hipStream_t s) {
@@ -127,16 +146,18 @@ static void dots(const double* X, int64_t sj, int64_t sc, int J, const double* w
   hipLaunchKernelGGL(k_reduce, dim3((J * nrhs + 255) / 256), dim3(256), 0, s, partial, nblk, J, nrhs, out);
 }
 
-int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, double tol,
-                 spaqr_solve_info* info) {
+int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, const double* tol,
+                 int restart, int maxit_in, spaqr_solve_info* info) {
   const double t0 = now_ms();
   hipStream_t s = e.stream();
   const int64_t N = e.n();
-  const int m = std::max(1, e.opt_restart());
-  const int maxit = std::max(1, e.opt_maxit());
+  const int m = std::max(1, restart);
+  const int maxit = std::max(1, maxit_in);
   const int nblk = (int)((N + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
   Dev V(s), Z(s), W(s), part(s), hd(s);
   V.ensure((size_t)N * (m + 1) * nrhs);
+  // (rows of a column beyond its problem's size, with batched problems, are
+  // written by nothing but x += Z y and read by nothing: W and V stay zero there)
   Z.ensure((size_t)N * m * nrhs);
   W.ensure((size_t)N * nrhs);
   part.ensure((size_t)nblk * (m + 2) * nrhs);
@@ -173,7 +194,7 @@ int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t
     for (int c = 0; c < nrhs; ++c) {
       const double beta = std::sqrt(hhn[c]);
       rel[c] = bnorm[c] > 0 ? beta / bnorm[c] : 0.0;
-      done[c] = rel[c] <= tol || bnorm[c] == 0.0;
+      done[c] = rel[c] <= tol[c] || bnorm[c] == 0.0;
       active[c] = !done[c] && its[c] < maxit;
       any = any || active[c];
       std::fill(g.begin() + (size_t)c * (m + 1), g.begin() + (size_t)(c + 1) * (m + 1), 0.0);
@@ -231,7 +252,7 @@ int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t
         its[c]++;
         jend[c] = j + 1;
         const double est = std::fabs(gc[j + 1]) / bnorm[c];
-        if (est <= tol || its[c] >= maxit || col[j] == 0.0) active[c] = 0;
+        if (est <= tol[c] || its[c] >= maxit || col[j] == 0.0) active[c] = 0;
         still = still || active[c];
       }
       total = *std::max_element(its.begin(), its.end());
@@ -263,7 +284,7 @@ int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t
       SPAQR_HIP(hipStreamSynchronize(s));
       for (int c = 0; c < nrhs; ++c) {
         rel[c] = bnorm[c] > 0 ? std::sqrt(hhn[c]) / bnorm[c] : 0.0;
-        done[c] = rel[c] <= tol || bnorm[c] == 0.0;
+        done[c] = rel[c] <= tol[c] || bnorm[c] == 0.0;
       }
       break;
     }
@@ -282,6 +303,54 @@ int fgmres_solve(EngineBase& e, const double* b, int64_t ldb, double* x, int64_t
   }
   (void)total;
   return status;
+}
+
+int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int>& nrhs,
+                       const std::vector<const double*>& b, const std::vector<double*>& x,
+                       const std::vector<double>& tol, spaqr_solve_info* info, std::vector<int>* status) {
+  const size_t np = es.size();
+  SPAQR_REQUIRE(np > 0 && nrhs.size() == np && b.size() == np && x.size() == np && tol.size() == np, SPAQR_EINVAL,
+                "batched solve: argument lists differ in length");
+  std::unique_ptr<KrylovOp> op = make_batch_op(es, nrhs);
+  hipStream_t s = op->stream();
+  const int64_t N = op->n();
+  int C = 0, restart = 1, maxit = 1;
+  std::vector<int> c0(np);
+  std::vector<double> tc;
+  for (size_t i = 0; i < np; ++i) {
+    c0[i] = C;
+    C += nrhs[i];
+    restart = std::max(restart, es[i]->opt_restart());
+    maxit = std::max(maxit, es[i]->opt_maxit());
+    tc.insert(tc.end(), (size_t)nrhs[i], tol[i]);
+  }
+  Dev B(s), X(s);
+  B.ensure((size_t)N * C);
+  X.ensure((size_t)N * C);
+  // columns padded to the largest n with zeros
+  SPAQR_HIP(hipMemsetAsync(B.p, 0, (size_t)N * C * sizeof(double), s));
+  for (size_t i = 0; i < np; ++i) {
+    const int64_t n = es[i]->n();
+    SPAQR_HIP(hipMemcpy2DAsync(B.p + (size_t)c0[i] * N, N * sizeof(double), b[i], n * sizeof(double),
+                               n * sizeof(double), nrhs[i], hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<spaqr_solve_info> inf((size_t)C);
+  fgmres_solve(*op, B.p, N, X.p, N, C, tc.data(), restart, maxit, inf.data());
+  int st = SPAQR_OK;
+  if (status) status->assign(np, SPAQR_OK);
+  for (size_t i = 0; i < np; ++i) {
+    const int64_t n = es[i]->n();
+    SPAQR_HIP(hipMemcpy2DAsync(x[i], n * sizeof(double), X.p + (size_t)c0[i] * N, N * sizeof(double),
+                               n * sizeof(double), nrhs[i], hipMemcpyDeviceToDevice, s));
+    for (int r = 0; r < nrhs[i]; ++r)
+      if (!inf[(size_t)c0[i] + r].converged) {
+        st = SPAQR_ENOCONV;
+        if (status) (*status)[i] = SPAQR_ENOCONV;
+      }
+  }
+  SPAQR_HIP(hipStreamSynchronize(s));
+  if (info) std::copy(inf.begin(), inf.end(), info);
+  return st;
 }
 
 }  // namespace spaqr

@@ -1704,6 +1704,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_ap_front_fwd(const ApFront<T>* __restrict__ ds, double* x,
                                                     int64_t ldx, int nrhs, int rb) {
   const ApFront<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.n == 0 || nc <= 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1720,6 +1721,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_ap_front_bwd(const ApFront<T>* __restrict__ ds, double* x,
                                                     int64_t ldx, int nrhs, int rb) {
   const ApFront<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.n == 0 || nc <= 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1749,6 +1751,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_ap_iface_fwd(const ApIface<T>* __restrict__ ds, double* x,
                                                     int64_t ldx, int nrhs, int rb) {
   const ApIface<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.P == 0 || nc <= 0 || *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1766,6 +1769,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_ap_iface_bwd(const ApIface<T>* __restrict__ ds, double* x,
                                                     int64_t ldx, int nrhs, int rb) {
   const ApIface<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.P == 0 || nc <= 0 || *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1789,6 +1793,7 @@ template <typename T, int JB>
 __global__ void __launch_bounds__(256) k_ap_front_fwd_wy(const ApFront<T>* __restrict__ ds, double* x, int64_t ldx,
                                                         int nrhs, int rb) {
   const ApFront<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.n == 0 || nc <= 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1857,6 +1862,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __restrict__ ds, double* x,
                                                          int64_t ldx, int nrhs, int rb) {
   const ApFront<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
   if (d.n == 0 || nc <= 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1933,6 +1939,7 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
   static_assert(K <= 64, "panel values exceed one wavefront");
   __shared__ __align__(16) double red[2][4][K];
   const ApFront<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int c0 = blockIdx.y * NR;
   if (d.n == 0 || c0 >= nrhs) return;
   const int nc = min(NR, nrhs - c0);
@@ -2103,6 +2110,7 @@ __global__ void __launch_bounds__(256) k_ap_iface_dense(const ApIface<T>* __rest
   const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (it >= n) return;
   const ApIface<T> d = ds[it];
+  x += d.xoff;
   const int P = d.P, lane = threadIdx.x & 63;
   if (P == 0 || *d.flag != 0) return;
   const T* M = backward ? d.mb : d.mf;
@@ -2129,6 +2137,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_ap_iface_small(const ApIface<T>* __restrict__ ds, double* x, int64_t ldx,
                                                       int nrhs, int backward) {
   const ApIface<T> d = ds[blockIdx.x];
+  x += d.xoff;
   const int P = d.P, lane = threadIdx.x;
   if (P == 0 || *d.flag != 0) return;
   const int r = *d.rank;
@@ -2182,6 +2191,24 @@ __global__ void k_gather_perm(double* xhat, const double* __restrict__ b, int64_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = i / N, r = i - c * N;
     xhat[i] = b[perm[r] + c * ldb];
+  }
+}
+
+__global__ void k_gather_cols(double* xhat, const double* __restrict__ b, int64_t ldb,
+                              const PermCol* __restrict__ pc) {
+  const int j = blockIdx.y;
+  const PermCol c = pc[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += (int64_t)gridDim.x * blockDim.x)
+    xhat[c.xoff + i] = b[c.perm[i] + c.col * ldb];
+}
+
+__global__ void k_scatter_cols(double* x, int64_t ldx, const double* __restrict__ xhat,
+                               const PermCol* __restrict__ pc) {
+  const int j = blockIdx.y;
+  const PermCol c = pc[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c.n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = c.perm[i];
+    x[o + c.col * ldx] = xhat[c.xoff + i] * c.dc[o];
   }
 }
 
@@ -2242,14 +2269,13 @@ static void check_launch(const char* what) {
 
 // Largest dynamic LDS a workgroup may use on the current device (bytes).
 static size_t device_lds_limit() {
-  static size_t lim = 0;
-  if (!lim) {
+  static const size_t lim = [] {
     int dev = 0, v = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
       v = 64 * 1024;
-    lim = (size_t)v;
-  }
+    return (size_t)v;
+  }();
   return lim;
 }
 
@@ -2729,6 +2755,22 @@ void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_
   hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, xhat, b, ldb, perm,
                      N, nrhs);
   check_launch("k_gather_perm");
+}
+
+void launch_gather_cols(double* xhat, const double* b, int64_t ldb, const PermCol* pc, int ncols, int64_t max_n,
+                        hipStream_t s) {
+  if (ncols <= 0 || max_n <= 0) return;
+  const unsigned gxn = (unsigned)std::min<int64_t>(1024, (max_n + 255) / 256);
+  hipLaunchKernelGGL(k_gather_cols, dim3(gxn, (unsigned)ncols), dim3(256), 0, s, xhat, b, ldb, pc);
+  check_launch("k_gather_cols");
+}
+
+void launch_scatter_cols(double* x, int64_t ldx, const double* xhat, const PermCol* pc, int ncols, int64_t max_n,
+                         hipStream_t s) {
+  if (ncols <= 0 || max_n <= 0) return;
+  const unsigned gxn = (unsigned)std::min<int64_t>(1024, (max_n + 255) / 256);
+  hipLaunchKernelGGL(k_scatter_cols, dim3(gxn, (unsigned)ncols), dim3(256), 0, s, x, ldx, xhat, pc);
+  check_launch("k_scatter_cols");
 }
 
 void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,

@@ -113,6 +113,8 @@ struct ApFront {
   const int32_t* rows;  // m slots: the front's row clusters
   const int32_t* cols;  // k slots: the ancestor column clusters
   int32_t m, n, k, jb;
+  int32_t xoff;         // offset of the owning problem's vector in x (batched apply; 0 alone)
+  int32_t pad;
 };
 
 template <typename T>
@@ -126,7 +128,8 @@ struct ApIface {
   const int* flag;       // nonzero: interface was not scaled
   T* mf;                 // P x P column-major Q^T U^T (P <= 64), formed after the stage
   T* mb;                 // P x P column-major R_pp^{-1} Q
-  int32_t P, pad;
+  int32_t P;
+  int32_t xoff;          // offset of the owning problem's vector in x (batched apply; 0 alone)
 };
 
 // ------------------------------------------------------------------ launchers
@@ -229,5 +232,32 @@ void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_
 // x[perm[i] + c*ldx] = xhat[i + c*N] * dc[perm[i]]
 void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,
                          const double* dc, int64_t N, int nrhs, hipStream_t s);
+
+// One column of an apply batched across problems: column col of b and x; its
+// problem has n unknowns, permutation perm and column scaling dc; its
+// permuted vector lives at xhat + xoff.
+struct PermCol {
+  int64_t col, xoff;
+  const int64_t* perm;
+  const double* dc;
+  int64_t n;
+};
+// xhat[pc[j].xoff + i] = b[pc[j].perm[i] + pc[j].col*ldb] for every j < ncols
+void launch_gather_cols(double* xhat, const double* b, int64_t ldb, const PermCol* pc, int ncols, int64_t max_n,
+                        hipStream_t s);
+// x[pc[j].perm[i] + pc[j].col*ldx] = xhat[pc[j].xoff + i] * pc[j].dc[pc[j].perm[i]]
+void launch_scatter_cols(double* x, int64_t ldx, const double* xhat, const PermCol* pc, int ncols, int64_t max_n,
+                         hipStream_t s);
+
+// CSR matrix of one column of a batched SpMV.
+struct SpmvCol {
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  int64_t n;
+};
+// y[:, j] = A_j x[:, j] over the first sc[j].n rows (the rest untouched)
+void launch_spmv_cols(const SpmvCol* sc, int ncols, int64_t max_n, const double* x, int64_t ldx, double* y,
+                      int64_t ldy, hipStream_t s);
 
 }  // namespace spaqr

@@ -45,6 +45,13 @@ void prof_record(const char* name, hipStream_t, hipEvent_t a, hipEvent_t b, doub
   if (r.ev.size() > 4096) resolve(r);
 }
 
+void prof_host(const char* name, double ms) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  Rec& r = g_tab[name];
+  r.launches++;
+  r.ms += ms;
+}
+
 void prof_add(const char* name, double flops, double bytes) {
   if (!prof_wants(name)) return;
   std::lock_guard<std::mutex> lk(g_mu);

@@ -12,6 +12,23 @@ bool prof_wants(const char* name);
 void prof_record(const char* name, hipStream_t s, hipEvent_t a, hipEvent_t b, double flops, double bytes);
 // Work known only after the launches ran (e.g. from ranks read back later).
 void prof_add(const char* name, double flops, double bytes);
+// Host wall time of a driver phase (recorded like a launch of `ms`).
+void prof_host(const char* name, double ms);
+double now_ms();
+
+struct HostScope {
+  explicit HostScope(const char* name) : name_(name), live_(prof_wants(name)), t0_(live_ ? now_ms() : 0.0) {}
+  ~HostScope() {
+    if (live_) prof_host(name_, now_ms() - t0_);
+  }
+  HostScope(const HostScope&) = delete;
+  HostScope& operator=(const HostScope&) = delete;
+
+ private:
+  const char* name_;
+  bool live_;
+  double t0_;
+};
 
 struct ProfScope {
   ProfScope(const char* name, hipStream_t s, double flops, double bytes)

@@ -7,8 +7,11 @@
 //      batched pass: their fronts, scalings and sparsifications share one
 //      launch per phase, whatever stage each request is at, so a request that
 //      arrives while others are half-way joins the running batch;
-//   3. solves every request whose factorization completed, all of its
-//      right-hand sides together (multi-RHS FGMRES), and retires it.
+//   3. solves the requests whose factorization completed, together: one
+//      FGMRES over all their right-hand sides whose preconditioner applies
+//      and SpMVs run one launch per phase for all of them (requests of very
+//      different sizes in separate groups), and retires them.
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <memory>
@@ -85,24 +88,74 @@ void retire(spaqr_server* srv, std::unique_ptr<Request> r, int status) {
   srv->done[r->ticket] = std::move(r);
 }
 
-int solve(spaqr_server* srv, Request& r) {
-  const int64_t N = r.A.n;
-  double* db = static_cast<double*>(dev_alloc(N * r.nrhs * sizeof(double), srv->stream));
-  double* dx = static_cast<double*>(dev_alloc(N * r.nrhs * sizeof(double), srv->stream));
-  int st = SPAQR_OK;
+// Solves the factored requests rs together (one batched FGMRES: their
+// preconditioner applies and SpMVs share launches), setting each one's
+// status, x and info.
+void solve_group(spaqr_server* srv, const std::vector<Request*>& rs, std::vector<int>& st) {
+  const size_t np = rs.size();
+  st.assign(np, SPAQR_OK);
+  std::vector<EngineBase*> es;
+  std::vector<int> nrhs;
+  std::vector<const double*> db;
+  std::vector<double*> dx;
+  std::vector<double> tol;
+  size_t tot = 0, cols = 0;
+  for (Request* r : rs) tot += (size_t)r->A.n * r->nrhs;
+  double* buf = static_cast<double*>(dev_alloc(std::max<size_t>(1, 2 * tot) * sizeof(double), srv->stream));
   try {
-    SPAQR_HIP(hipMemcpyAsync(db, r.b.data(), N * r.nrhs * sizeof(double), hipMemcpyHostToDevice, srv->stream));
-    r.info.assign(r.nrhs, spaqr_solve_info{});
-    st = fgmres_solve(*r.eng, db, N, dx, N, (int)r.nrhs, r.tol, r.info.data());
-    r.x.resize(N * r.nrhs);
-    SPAQR_HIP(hipMemcpyAsync(r.x.data(), dx, N * r.nrhs * sizeof(double), hipMemcpyDeviceToHost, srv->stream));
+    size_t o = 0;
+    for (Request* r : rs) {
+      const size_t sz = (size_t)r->A.n * r->nrhs;
+      SPAQR_HIP(hipMemcpyAsync(buf + o, r->b.data(), sz * sizeof(double), hipMemcpyHostToDevice, srv->stream));
+      es.push_back(r->eng.get());
+      nrhs.push_back((int)r->nrhs);
+      db.push_back(buf + o);
+      dx.push_back(buf + tot + o);
+      tol.push_back(r->tol);
+      cols += (size_t)r->nrhs;
+      o += sz;
+    }
+    std::vector<spaqr_solve_info> info(cols);
+    fgmres_solve_batch(es, nrhs, db, dx, tol, info.data(), &st);
+    size_t c = 0;
+    for (size_t i = 0; i < np; ++i) {
+      Request& r = *rs[i];
+      r.info.assign(info.begin() + c, info.begin() + c + r.nrhs);
+      c += r.nrhs;
+      r.x.resize((size_t)r.A.n * r.nrhs);
+      SPAQR_HIP(hipMemcpyAsync(r.x.data(), dx[i], r.x.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               srv->stream));
+    }
     SPAQR_HIP(hipStreamSynchronize(srv->stream));
   } catch (const Error& e) {
-    st = e.status;
+    (void)hipStreamSynchronize(srv->stream);
+    st.assign(np, e.status);
   }
-  dev_free(db, srv->stream);
-  dev_free(dx, srv->stream);
-  return st;
+  dev_free(buf, srv->stream);
+}
+
+// Groups of factored requests solved together: sizes sorted descending, a
+// group grows while the zero padding of its columns to the group's largest n
+// stays below half of the padded vectors.
+std::vector<std::vector<Request*>> solve_groups(std::vector<Request*> rs) {
+  std::sort(rs.begin(), rs.end(), [](const Request* a, const Request* b) { return a->A.n > b->A.n; });
+  std::vector<std::vector<Request*>> g;
+  double useful = 0, padded = 0;
+  for (Request* r : rs) {
+    const double u = (double)r->A.n * r->nrhs;
+    if (!g.empty()) {
+      const double p = (double)g.back().front()->A.n * r->nrhs;
+      if (2.0 * (useful + u) >= padded + p) {
+        g.back().push_back(r);
+        useful += u;
+        padded += p;
+        continue;
+      }
+    }
+    g.push_back({r});
+    useful = padded = u;
+  }
+  return g;
 }
 }  // namespace
 
@@ -181,14 +234,23 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
         srv->active.swap(keep);
       }
     }
-    // 3. solve and retire the factored requests
+    // 3. solve the factored requests together and retire them
+    std::vector<Request*> ready;
+    for (auto& r : srv->active)
+      if (r->eng->stages_left() == 0 && r->eng->error() == SPAQR_OK) ready.push_back(r.get());
+    std::map<Request*, int> result;
+    for (const auto& g : solve_groups(ready)) {
+      std::vector<int> st;
+      solve_group(srv, g, st);
+      for (size_t i = 0; i < g.size(); ++i) result[g[i]] = st[i];
+    }
     std::vector<std::unique_ptr<Request>> keep;
     for (auto& r : srv->active) {
       if (r->eng->stages_left() > 0) {
         keep.push_back(std::move(r));
         continue;
       }
-      const int st = r->eng->error() != SPAQR_OK ? r->eng->error() : solve(srv, *r);
+      const int st = r->eng->error() != SPAQR_OK ? r->eng->error() : result[r.get()];
       retire(srv, std::move(r), st);
     }
     srv->active.swap(keep);
