@@ -464,7 +464,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, split ? n : nc, ldw});
         if (split)
           for (int c0 = n; c0 < nc; c0 += fc.trail_cw)
-            fc.trail.push_back({Wf, TPF + tp_off[f], fm[f], n, ldw, c0, std::min(fc.trail_cw, nc - c0), 0});
+            fc.trail.push_back({Wf, TPF + tp_off[f], Wf, nullptr, fm[f], n, ldw, c0, std::min(fc.trail_cw, nc - c0), ldw});
         fc.max_m = std::max(fc.max_m, fm[f]);
         const double mm = fm[f], nn = n, kk = nc - n;
         fc.flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
@@ -574,7 +574,14 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
     const double pp = Pn;
     st_.s.flops_scale += 4.0 / 3.0 * pp * pp * pp;
   }
-  T* SW = work_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
+  // the scaling QRs work row-major with rows padded to whole 16-column
+  // panels (aligned vector reads of V by the trailing-update kernel)
+  std::vector<int64_t> sw_off(ni + 1, 0);
+  for (int64_t t = 0; t < ni; ++t) {
+    const int64_t Pn = size_[rem[t]];
+    sw_off[t + 1] = sw_off[t] + Pn * ((Pn + 15) / 16 * 16);
+  }
+  T* SW = work_.alloc_n<T>(std::max<int64_t>(1, sw_off[ni]), s_);
   T* VRU = ib_.vru = persist_.alloc_n<T>(std::max<int64_t>(1, u_off[ni]), s_);
   T* TAUU = ib_.tauu = persist_.alloc_n<T>(std::max<int64_t>(1, p_off[ni]), s_);
   T* TPAN = ib_.tpan = persist_.alloc_n<T>(std::max<int64_t>(1, t_off[ni]), s_);
@@ -585,13 +592,14 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
   P.fac.resize(ni);
   for (int64_t t = 0; t < ni; ++t) {
     const int32_t p = rem[t], Pn = size_[p];
-    P.fac[t] = {VRU + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, 0};
+    const int32_t Pld = (Pn + 15) / 16 * 16;
+    P.fac[t] = {VRU + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, 0, SW + sw_off[t], Pld, 0};
     if (Pn == 0) continue;
     T* src = blk(p, p);
     SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
-    P.sgather.push_back({src, SW + u_off[t], Pn, Pn, Pn, Pn, 0, 0});
-    P.sqr.push_back({SW + u_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, Pn});
-    P.spack.push_back({SW + u_off[t], VRU + u_off[t], Pn, Pn, Pn, Pn, 1, 0});
+    P.sgather.push_back({src, SW + sw_off[t], Pn, Pn, Pn, Pld, 0, 0});
+    P.sqr.push_back({SW + sw_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, Pld});
+    P.spack.push_back({SW + sw_off[t], VRU + u_off[t], Pn, Pn, Pld, Pn, 1, 0});
   }
   for (int64_t i = 0; i < nclu; ++i)
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
@@ -1157,10 +1165,10 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     std::vector<ScaleFac<T>> fac;
     struct SGroup {
-      int max_p = 1, max_rows = 1, max_cols = 1;
-      std::vector<ScaleBlk<T>> blk;
+      int max_p = 1, max_rows = 1, max_cols = 1, small_rows = 1, small_cols = 1;
+      std::vector<ScaleBlk<T>> blk, small;
     };
-    std::map<int, SGroup> sgroups;  // by panel width
+    std::map<int, SGroup> sgroups;  // by panel width; blocks of at most 64 x 64 apart
     double qfl = 0.0, qby = 0.0, sfl = 0.0, sby = 0.0;
     for (auto& p : pl) {
       append(g, p.sgather);
@@ -1177,9 +1185,15 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       for (ScaleBlk<T> b : p.sblk) {
         if (b.fi >= 0) b.fi += base;
         if (b.fj >= 0) b.fj += base;
-        sg.max_rows = std::max(sg.max_rows, b.rows);
-        sg.max_cols = std::max(sg.max_cols, b.cols);
-        sg.blk.push_back(b);
+        if (b.rows <= kScaleSmall && b.cols <= kScaleSmall) {
+          sg.small_rows = std::max(sg.small_rows, b.rows);
+          sg.small_cols = std::max(sg.small_cols, b.cols);
+          sg.small.push_back(b);
+        } else {
+          sg.max_rows = std::max(sg.max_rows, b.rows);
+          sg.max_cols = std::max(sg.max_cols, b.cols);
+          sg.blk.push_back(b);
+        }
         sfl += 4.0 * b.rows * b.rows * (double)b.cols + (double)b.rows * b.cols * b.cols;
         sby += 2.0 * b.rows * (double)b.cols * sizeof(T);
       }
@@ -1192,9 +1206,47 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       ProfScope ps("scale_blocks", s, sfl, sby);
       for (auto& kv : sgroups) {
         const SGroup& g = kv.second;
+        if (!g.small.empty()) {
+          ScaleBlk<T>* dsb = up.upload(wk, g.small, s);
+          launch_scale_small<T>(dsb, (int64_t)g.small.size(), dfac, kv.first, g.small_rows, g.small_cols, s);
+        }
         if (g.blk.empty()) continue;
-        ScaleBlk<T>* dsb = up.upload(wk, g.blk, s);
-        launch_scale<T>(dsb, (int64_t)g.blk.size(), dfac, kv.first, g.max_p, g.max_rows, g.max_cols, s);
+        const int cw = kv.first >= 4 ? trail_width(g.max_rows, sizeof(T)) : 0;
+        if (cw == 0) {
+          ScaleBlk<T>* dsb = up.upload(wk, g.blk, s);
+          launch_scale<T>(dsb, (int64_t)g.blk.size(), dfac, kv.first, g.max_p, g.max_rows, g.max_cols, s);
+          continue;
+        }
+        // larger blocks: Q_i^T by 16-column slices (the trailing-update
+        // kernel reading V row-major from the scaling QR's workspace), the
+        // diagonal blocks set to I, then B R_j^{-1}
+        std::vector<ScaleBlk<T>> ident, rest;
+        std::vector<TrailDesc<T>> left;
+        int lm = 1;
+        for (const ScaleBlk<T>& b : g.blk) {
+          if (b.fi >= 0 && b.fi == b.fj) {
+            ident.push_back(b);
+            continue;
+          }
+          rest.push_back(b);
+          if (b.fi < 0) continue;
+          const ScaleFac<T>& f = fac[b.fi];
+          lm = std::max(lm, b.rows);
+          for (int c0 = 0; c0 < b.cols; c0 += cw)
+            left.push_back({f.vw, f.tpan, b.B, f.flag, b.rows, b.rows, f.ldw, c0, std::min(cw, b.cols - c0), b.cols});
+        }
+        if (!left.empty()) {
+          TrailDesc<T>* dl = up.upload(wk, left, s);
+          launch_trail<T>(dl, (int64_t)left.size(), kv.first, cw, lm, s);
+        }
+        if (!ident.empty()) {
+          ScaleBlk<T>* di = up.upload(wk, ident, s);
+          launch_scale_small<T>(di, (int64_t)ident.size(), dfac, kv.first, 1, 1, s);  // identity fill only
+        }
+        if (!rest.empty()) {
+          ScaleBlk<T>* dr = up.upload(wk, rest, s);
+          launch_scale_right<T>(dr, (int64_t)rest.size(), dfac, g.max_rows, s);
+        }
       }
     }
   }

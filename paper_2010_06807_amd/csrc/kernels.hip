@@ -603,6 +603,7 @@ __global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ d
   static_assert(TY >= JB, "row groups must cover the panel width");
   using V = Vec16<T>;
   const TrailDesc<T> d = ds[blockIdx.x];
+  if (d.flag && *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* red = reinterpret_cast<T*>(smem);     // TY x JB x CW partials
   T* Ws = red + TY * JB * CW;              // JB x CW
@@ -611,10 +612,10 @@ __global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ d
   constexpr int LC = CW + 1;
   const int tid = threadIdx.x, c = tid % CW, g = tid / CW;
   const int m = d.m, n = d.n;
-  const int64_t ld = d.ld;
+  const int64_t ld = d.ld, ldc = d.ldc;
   const bool live = c < d.cw;
-  T* col = d.a + d.c0 + c;
-  for (int r = g; r < m; r += TY) Cs[r * LC + c] = live ? col[(int64_t)r * ld] : T(0);
+  T* col = d.c + d.c0 + c;
+  for (int r = g; r < m; r += TY) Cs[r * LC + c] = live ? col[(int64_t)r * ldc] : T(0);
   __syncthreads();
   for (int p0 = 0; p0 < n; p0 += JB) {
     const int jb = min(JB, n - p0);
@@ -671,7 +672,7 @@ __global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ d
     __syncthreads();
   }
   if (live)
-    for (int r = g; r < m; r += TY) col[(int64_t)r * ld] = Cs[r * LC + c];
+    for (int r = g; r < m; r += TY) col[(int64_t)r * ldc] = Cs[r * LC + c];
 }
 
 // Scaling of the blocks touching an interface (Algorithm 2, scaling step):
@@ -714,6 +715,100 @@ __global__ void __launch_bounds__(NT) k_scale(const ScaleBlk<T>* __restrict__ de
     __syncthreads();
     wy_apply_left<T, JB>(Vs, Tm, mp, B + (int64_t)j0 * cols + c0, cols, nc);
     __syncthreads();
+  }
+}
+
+// Both factors of the scaling step for a block of at most 64 x 64: the block
+// is loaded into LDS once, Q_i^T applied panel by panel (W = V^T B and
+// B -= V (T^T W), all products spread over the workgroup), then B R_j^{-1}
+// by forward substitution along each row (R_j staged in LDS), and the block
+// written back once.
+template <typename T, int JB>
+__global__ void __launch_bounds__(NT) k_scale_small(const ScaleBlk<T>* __restrict__ descs,
+                                                    const ScaleFac<T>* __restrict__ fac, int max_rows,
+                                                    int max_cols) {
+  const ScaleBlk<T> d = descs[blockIdx.x];
+  T* B = d.B;
+  const int rows = d.rows, cols = d.cols, tid = threadIdx.x;
+  const bool si = d.fi >= 0 && *fac[d.fi].flag == 0;
+  if (d.fi >= 0 && d.fi == d.fj) {
+    if (si)
+      for (int q = tid; q < rows * cols; q += NT) {
+        const int r = q / cols, c = q - r * cols;
+        B[q] = r == c ? T(1) : T(0);
+      }
+    return;
+  }
+  const bool sj = d.fj >= 0 && *fac[d.fj].flag == 0;
+  if (!si && !sj) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int LB = max_cols + 1;
+  T* Bs = reinterpret_cast<T*>(smem);                 // max_rows x LB
+  T* Vs = Bs + (size_t)max_rows * LB;                 // max_rows x (JB + 1)
+  T* Tm = Vs + (size_t)max_rows * (JB + 1);           // JB x JB
+  T* W = Tm + JB * JB;                                // JB x max_cols
+  T* U = W + (size_t)JB * max_cols;                   // JB x max_cols
+  T* Rs = U + (size_t)JB * max_cols;                  // max_cols x LB
+  for (int q = tid; q < rows * cols; q += NT) {
+    const int r = q / cols, c = q - r * cols;
+    Bs[r * LB + c] = B[q];
+  }
+  if (si) {
+    const ScaleFac<T> f = fac[d.fi];
+    for (int j0 = 0; j0 < rows; j0 += JB) {
+      const int jb = min(JB, rows - j0), mp = rows - j0;
+      for (int q = tid; q < mp * JB; q += NT) {
+        const int r = q / JB, t = q - r * JB;
+        T v;
+        if (t >= jb || r < t) v = T(0);
+        else if (r == t) v = T(1);
+        else v = f.vr[(int64_t)(j0 + r) + (int64_t)(j0 + t) * rows];
+        Vs[r * (JB + 1) + t] = v;
+      }
+      for (int q = tid; q < JB * JB; q += NT) Tm[q] = f.tpan[(int64_t)(j0 / JB) * JB * JB + q];
+      __syncthreads();
+      for (int q = tid; q < JB * cols; q += NT) {
+        const int t = q / cols, c = q - t * cols;
+        T w = T(0);
+        for (int r = 0; r < mp; ++r) w += Vs[r * (JB + 1) + t] * Bs[(j0 + r) * LB + c];
+        W[t * max_cols + c] = w;
+      }
+      __syncthreads();
+      for (int q = tid; q < JB * cols; q += NT) {
+        const int t = q / cols, c = q - t * cols;
+        T u = T(0);
+        for (int q2 = 0; q2 <= t; ++q2) u += Tm[q2 + t * JB] * W[q2 * max_cols + c];
+        U[t * max_cols + c] = u;
+      }
+      __syncthreads();
+      for (int q = tid; q < mp * cols; q += NT) {
+        const int r = q / cols, c = q - r * cols;
+        T acc = T(0);
+#pragma unroll
+        for (int t = 0; t < JB; ++t) acc += Vs[r * (JB + 1) + t] * U[t * max_cols + c];
+        Bs[(j0 + r) * LB + c] -= acc;
+      }
+      __syncthreads();
+    }
+  }
+  if (sj) {
+    const T* R = fac[d.fj].vr;  // R[q][c] at q + c cols
+    for (int q = tid; q < cols * cols; q += NT) {
+      const int c = q / cols, r = q - c * cols;
+      Rs[r * LB + c] = R[q];
+    }
+    __syncthreads();
+    for (int r = tid; r < rows; r += NT)
+      for (int c = 0; c < cols; ++c) {
+        T x = Bs[r * LB + c];
+        for (int q = 0; q < c; ++q) x -= Bs[r * LB + q] * Rs[q * LB + c];
+        Bs[r * LB + c] = x / Rs[c * LB + c];
+      }
+  }
+  __syncthreads();
+  for (int q = tid; q < rows * cols; q += NT) {
+    const int r = q / cols, c = q - r * cols;
+    B[q] = Bs[r * LB + c];
   }
 }
 
@@ -1854,10 +1949,15 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_wy(const ApFront<T>* __res
 }
 
 // Backward sweep of the fronts of one level: x_s <- R_ss^{-1} (x_s - R_sj x_j).
-// The R_sj product accumulates in registers (one row per thread, independent
-// loads over j); the triangular solve runs in 64-row blocks from the bottom,
-// each diagonal block by one wavefront with shuffles, the rows above it
-// updated by all threads.
+// The R_sj product: the rows of the front spread over the workgroup's
+// threads and, when the front has fewer than 256 rows, its columns j over
+// G = 256 / rows' groups (shorter load chains), partial sums combined in LDS;
+// the triangular solve runs in 64-row blocks from the bottom, each diagonal
+// block by one wavefront with shuffles, the rows above it updated by all
+// threads.
+constexpr int kBwdTile = 128;   // rows of the LDS tile of R_ss in the backward apply
+constexpr int kBwdChunk = 1024; // ancestor unknowns x_j staged in LDS at a time
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __restrict__ ds, double* x,
                                                          int64_t ldx, int nrhs, int rb) {
@@ -1868,50 +1968,86 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = d.n, k = d.k, m = d.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* ys = reinterpret_cast<double*>(smem);  // n x nc
-  double* xc = ys + (size_t)n * rb;              // k x nc
-  for (int c = 0; c < nc; ++c) {
+  double* xc = ys + (size_t)n * rb;              // kBwdChunk x nc: x_j, chunk by chunk
+  double* part = xc + (size_t)kBwdChunk * rb;    // 256 partial sums
+  for (int c = 0; c < nc; ++c)
     for (int r = tid; r < n; r += 256) ys[r + c * n] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
-    for (int r = tid; r < k; r += 256) xc[r + c * k] = x[d.cols[r] + (int64_t)(c0 + c) * ldx];
+  {
+    // rows per pass RP (64, 128 or 256: a divisor of the workgroup size, so
+    // every thread has exactly one row and group), column groups G = 256 / RP
+    const int RP = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
+    const int G = 256 / RP, r0 = tid % RP, g = tid / RP;
+    for (int j0 = 0; j0 < k; j0 += kBwdChunk) {
+      const int kc = min(kBwdChunk, k - j0);
+      for (int c = 0; c < nc; ++c)
+        for (int r = tid; r < kc; r += 256) xc[r + c * kBwdChunk] = x[d.cols[j0 + r] + (int64_t)(c0 + c) * ldx];
+      __syncthreads();
+      for (int c = 0; c < nc; ++c)
+        for (int rbase = 0; rbase < n; rbase += RP) {
+          const int r = rbase + r0;
+          double acc = 0.0;
+          if (r < n) {
+            const T* rc = d.rsj + r + (int64_t)j0 * n;
+#pragma unroll 8
+            for (int j = g; j < kc; j += G) acc += (double)rc[(int64_t)j * n] * xc[j + c * kBwdChunk];
+          }
+          if (G == 1) {
+            if (r < n) ys[r + c * n] -= acc;
+          } else {
+            part[g * RP + r0] = acc;
+            __syncthreads();
+            if (g == 0 && r < n) {
+              double t = 0.0;
+              for (int h = 0; h < G; ++h) t += part[h * RP + r0];
+              ys[r + c * n] -= t;
+            }
+            __syncthreads();
+          }
+        }
+      __syncthreads();
+    }
   }
   __syncthreads();
-  for (int c = 0; c < nc; ++c)
-    for (int r = tid; r < n; r += 256) {
-      double s = ys[r + c * n];
-#pragma unroll 8
-      for (int j = 0; j < k; ++j) s -= (double)d.rsj[r + (int64_t)j * n] * xc[j + c * k];
-      ys[r + c * n] = s;
-    }
-  __syncthreads();
+  // R_ss (column-major in vr, leading dimension m) is staged through an LDS
+  // tile of kBwdTile rows x 64 columns: every load of a block is issued at
+  // once by the whole workgroup instead of one dependent chain per thread
   const T* R = d.vr;
+  T* Rt = reinterpret_cast<T*>(part + 256);  // kBwdTile x 65
   for (int b0 = ((n - 1) / 64) * 64; b0 >= 0; b0 -= 64) {
-    const int b1 = min(n, b0 + 64);
+    const int b1 = min(n, b0 + 64), bw = b1 - b0;
+    for (int q = tid; q < 64 * 64; q += 256) {
+      const int r = q & 63, cc = q >> 6;
+      Rt[r * 65 + cc] = (r < bw && cc < bw) ? R[(b0 + r) + (int64_t)(b0 + cc) * m] : T(0);
+    }
+    __syncthreads();
     if (wv == 0) {
       const int row = b0 + lane;
-      double Rrow[64];
-#pragma unroll
-      for (int lc = 0; lc < 64; ++lc)
-        Rrow[lc] = (row < b1 && b0 + lc < b1) ? (double)R[row + (int64_t)(b0 + lc) * m] : 0.0;
       for (int c = 0; c < nc; ++c) {
         double yl = row < b1 ? ys[row + c * n] : 0.0;
-#pragma unroll
-        for (int lc = 63; lc >= 0; --lc) {
-          if (b0 + lc < b1) {
-            if (lane == lc) yl = yl / Rrow[lc];
-            const double yc = __shfl(yl, lc, 64);
-            if (lane < lc) yl -= Rrow[lc] * yc;
-          }
+        for (int lc = bw - 1; lc >= 0; --lc) {
+          if (lane == lc) yl = yl / (double)Rt[lc * 65 + lc];
+          const double yc = __shfl(yl, lc, 64);
+          if (lane < lc) yl -= (double)Rt[lane * 65 + lc] * yc;
         }
         if (row < b1) ys[row + c * n] = yl;
       }
     }
     __syncthreads();
-    for (int c = 0; c < nc; ++c)
-      for (int r = tid; r < b0; r += 256) {
-        double s = 0.0;
-        for (int cc = b0; cc < b1; ++cc) s += (double)R[r + (int64_t)cc * m] * ys[cc + c * n];
-        ys[r + c * n] -= s;
+    for (int rs = 0; rs < b0; rs += kBwdTile) {
+      const int nr = min(kBwdTile, b0 - rs);
+      for (int q = tid; q < nr * bw; q += 256) {
+        const int cc = q / nr, r = q - cc * nr;
+        Rt[r * 65 + cc] = R[(rs + r) + (int64_t)(b0 + cc) * m];
       }
-    __syncthreads();
+      __syncthreads();
+      for (int c = 0; c < nc; ++c)
+        for (int r = tid; r < nr; r += 256) {
+          double sacc = 0.0;
+          for (int cc = 0; cc < bw; ++cc) sacc += (double)Rt[r * 65 + cc] * ys[b0 + cc + c * n];
+          ys[rs + r + c * n] -= sacc;
+        }
+      __syncthreads();
+    }
   }
   for (int c = 0; c < nc; ++c)
     for (int r = tid; r < n; r += 256) x[d.rows[r] + (int64_t)(c0 + c) * ldx] = ys[r + c * n];
@@ -2443,6 +2579,36 @@ void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, h
   throw Error(SPAQR_EINVAL, "unsupported panel width for the trailing update");
 }
 
+static size_t scale_small_lds(int max_rows, int max_cols, int jb, int eb) {
+  const size_t lb = (size_t)max_cols + 1;
+  return ((size_t)max_rows * lb + (size_t)max_rows * (jb + 1) + (size_t)jb * jb + 2 * (size_t)jb * max_cols +
+          (size_t)max_cols * lb) * eb;
+}
+
+template <typename T>
+void launch_scale_small(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_rows, int max_cols,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  SPAQR_REQUIRE(max_rows <= kScaleSmall && max_cols <= kScaleSmall, SPAQR_EINVAL, "block too large for k_scale_small");
+  const size_t lds = scale_small_lds(max_rows, max_cols, jb, sizeof(T));
+  switch (jb) {
+#define SPAQR_SS_CASE(J)                                                                              \
+  case J:                                                                                             \
+    allow_lds(reinterpret_cast<const void*>(&k_scale_small<T, J>), lds, "k_scale_small");              \
+    hipLaunchKernelGGL((k_scale_small<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, max_rows, max_cols); \
+    break;
+    SPAQR_SS_CASE(1)
+    SPAQR_SS_CASE(2)
+    SPAQR_SS_CASE(4)
+    SPAQR_SS_CASE(8)
+    SPAQR_SS_CASE(16)
+    SPAQR_SS_CASE(32)
+#undef SPAQR_SS_CASE
+    default: throw Error(SPAQR_EINVAL, "unsupported QR panel width");
+  }
+  check_launch("k_scale_small");
+}
+
 template <typename T>
 void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, int max_rows,
                   int max_cols, hipStream_t s) {
@@ -2465,6 +2631,12 @@ void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int j
     default: throw Error(SPAQR_EINVAL, "unsupported QR panel width");
   }
   check_launch("k_scale");
+  launch_scale_right<T>(d, n, fac, max_rows, s);
+}
+
+template <typename T>
+void launch_scale_right(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int max_rows, hipStream_t s) {
+  if (n <= 0) return;
   hipLaunchKernelGGL(k_scale_right<T>, dim3((unsigned)n, (unsigned)((max_rows + 15) / 16)), dim3(NT), 0, s, d, fac);
   check_launch("k_scale_right");
 }
@@ -2715,9 +2887,16 @@ template <typename T>
 void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
                           hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
-  const int rb = apply_rhs_block(max_n + max_k, nrhs);
-  if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
-  const size_t lds = (size_t)(max_n + max_k) * rb * sizeof(double);
+  // LDS: y_s and a chunk of x_j (rb columns each), 256 partial sums, the
+  // R_ss tile
+  (void)max_k;
+  const size_t tile = (size_t)kBwdTile * 65 * sizeof(T) + 256 * sizeof(double);
+  const size_t lim = apply_lds_budget() - tile;
+  const size_t per_rhs = (size_t)(max_n + kBwdChunk) * sizeof(double);
+  int rb = std::min(RBMAX, nrhs);
+  while (rb > 1 && per_rhs * rb > lim) --rb;
+  if (per_rhs * rb > lim) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
+  const size_t lds = per_rhs * rb + tile;
   allow_lds(reinterpret_cast<const void*>(&k_ap_front_bwd_reg<T>), lds, "k_ap_front_bwd_reg");
   hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
                      d, x, ldx, nrhs, rb);
@@ -2788,7 +2967,9 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
                                          int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
   template void launch_trail<T>(const TrailDesc<T>*, int64_t, int, int, int, hipStream_t);           \
-  template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, int, hipStream_t); \
+  template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, int, hipStream_t);                                                                      \
+  template void launch_scale_right<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, hipStream_t);                                                                      \
+  template void launch_scale_small<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, hipStream_t); \
   template void launch_sparsify<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, hipStream_t); \
   template void launch_sparsify_small<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, size_t, hipStream_t); \
   template void launch_sparsify_reg<T>(const SpDesc<T>*, int64_t, const SpNbr*, int, int, int, hipStream_t); \

@@ -37,14 +37,19 @@ struct QRDesc {
 };
 
 // Trailing update of one column slice of a front whose pivot block was
-// factored with nc = n: columns [c0, c0 + cw) of the row-major m x (row
-// stride ld) matrix a get H_{n-1}^T ... H_0^T, panel by panel from the
-// reflectors below the pivot block's diagonal and the panels' T factors.
+// factored with nc = n: columns [c0, c0 + cw) of the row-major m-row matrix
+// c (row stride ldc) get H_{n-1}^T ... H_0^T, panel by panel from the
+// reflectors below the diagonal of the factored pivot block a (row-major, row
+// stride ld, a multiple of 16) and the panels' T factors.  For a front c is a
+// itself; for the scaling step c is a block to the right of an interface.
+// flag (may be null): nonzero skips the item.
 template <typename T>
 struct TrailDesc {
-  T* a;
+  const T* a;
   const T* tpan;
-  int32_t m, n, ld, c0, cw, pad;
+  T* c;
+  const int* flag;
+  int32_t m, n, ld, c0, cw, ldc;
 };
 
 // One block B (row-major rows x cols, ld = cols) of the trailing matrix to be
@@ -59,6 +64,8 @@ struct ScaleFac {
   const T* tpan;
   const int* flag;  // nonzero: R_pp had a zero diagonal, interface not scaled
   int32_t P, pad;
+  const T* vw;      // the same V row-major (row stride ldw, a multiple of 16), during the stage
+  int32_t ldw, pad2;
 };
 
 template <typename T>
@@ -161,6 +168,15 @@ size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
 template <typename T>
 void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_p, int max_rows,
                   int max_cols, hipStream_t s);
+// The right factor alone (B <- B R_j^{-1}); identity blocks are left alone.
+template <typename T>
+void launch_scale_right(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int max_rows, hipStream_t s);
+// The same for blocks of at most kScaleSmall x kScaleSmall, one launch (the
+// block staged in LDS once).
+constexpr int kScaleSmall = 64;
+template <typename T>
+void launch_scale_small(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int jb, int max_rows, int max_cols,
+                        hipStream_t s);
 // Zero fills; blocks = total workgroups (block0 of the last descriptor plus its own).
 void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s);
 constexpr int64_t kZeroWordsPerBlock = 4096;

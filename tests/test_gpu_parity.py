@@ -62,6 +62,12 @@ CASES = [
     ((8, 8, 8), 4, (20.0, -5.0, 3.0), 1e-2),
     ((12, 12, 12), 6, (5.0, 5.0, 5.0), 1e-3),
     ((64, 64), 7, (50.0, -20.0), 1e-4),
+    # exact factorizations whose fronts span the apply kernels' row classes
+    # (up to 64, 65-128, 129-192, 193-256 and more than 256 pivots, with and
+    # without ancestor columns): the apply alone must invert A
+    ((11, 11, 11), 3, (5.0, 5.0, 5.0), 0.0),
+    ((14, 14, 14), 4, (2.0, -3.0, 1.0), 0.0),
+    ((13, 13), 1, (4.0, 1.0), 0.0),
 ]
 
 
