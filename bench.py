@@ -44,7 +44,7 @@ PEAK = {
 # arithmetic (the factorization kernels run on the VALU, not on MFMA; the
 # CPQR's work is counted from the ranks read back after each stage)
 KERNEL_BOUND = {
-    "front_qr": "alu", "scale_qr": "alu", "scale_blocks": "alu", "sparsify": "alu",
+    "front_qr": "alu", "front_trail": "alu", "scale_qr": "alu", "scale_blocks": "alu", "sparsify": "alu",
     "apply_front_fwd": "hbm", "apply_front_bwd": "hbm", "apply_iface_fwd": "hbm", "apply_iface_bwd": "hbm",
 }
 
@@ -85,7 +85,10 @@ def pct(v, q):
 
 # kernel symbols behind each profiler group (FP32 instantiations)
 GROUP_KERNELS = {
-    "sparsify": ("k_cpqr_reg<float", "k_sparsify_small<float", "k_sparsify<float"),
+    "front_qr": ("k_qr_reg<float", "k_qr<float"),
+    "trailing updates (fronts and scaling)": ("k_trail<float",),
+    "scale_blocks": ("k_scale<float", "k_scale_small<float", "k_scale_right<float"),
+    "sparsify": ("k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
     "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
     "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),

@@ -1131,14 +1131,20 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     {
       // trailing slices of split fronts, grouped by (panel width, slice width)
       std::map<std::pair<int, int>, std::pair<int, std::vector<TrailDesc<T>>>> tg;
+      double tfl = 0.0, tby = 0.0;
       for (auto& p : pl) {
         if (c >= p.fronts.size() || p.fronts[c].trail.empty()) continue;
         auto& e = tg[{p.jbf, p.fronts[c].trail_cw}];
         e.first = std::max(e.first, p.fronts[c].trail_max_m);
         append(e.second, p.fronts[c].trail);
+        for (const TrailDesc<T>& t : p.fronts[c].trail) {
+          // V^T C and C - V (T^T W) over the slice: 4 m n cw; C read and written once
+          tfl += 4.0 * t.m * (double)t.n * t.cw;
+          tby += 2.0 * t.m * (double)t.cw * sizeof(T);
+        }
       }
       if (!tg.empty()) {
-        ProfScope ps("front_trail", s, 0.0, 0.0);
+        ProfScope ps("front_trail", s, tfl, tby);
         for (auto& kv : tg) {
           TrailDesc<T>* d = up.upload(wk, kv.second.second, s);
           launch_trail<T>(d, (int64_t)kv.second.second.size(), kv.first.first, kv.first.second, kv.second.first, s);
@@ -1165,8 +1171,12 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     std::vector<ScaleFac<T>> fac;
     struct SGroup {
-      int max_p = 1, max_rows = 1, max_cols = 1, small_rows = 1, small_cols = 1;
-      std::vector<ScaleBlk<T>> blk, small;
+      int max_p = 1, max_rows = 1, max_cols = 1;
+      std::vector<ScaleBlk<T>> blk;
+      // blocks of at most 16, 32 and 64 rows and columns: one launch per
+      // class so that small blocks do not pay LDS sized for the largest
+      int small_rows[3] = {1, 1, 1}, small_cols[3] = {1, 1, 1};
+      std::vector<ScaleBlk<T>> small[3];
     };
     std::map<int, SGroup> sgroups;  // by panel width; blocks of at most 64 x 64 apart
     double qfl = 0.0, qby = 0.0, sfl = 0.0, sby = 0.0;
@@ -1186,9 +1196,10 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
         if (b.fi >= 0) b.fi += base;
         if (b.fj >= 0) b.fj += base;
         if (b.rows <= kScaleSmall && b.cols <= kScaleSmall) {
-          sg.small_rows = std::max(sg.small_rows, b.rows);
-          sg.small_cols = std::max(sg.small_cols, b.cols);
-          sg.small.push_back(b);
+          const int e = std::max(b.rows, b.cols), cl = e <= 16 ? 0 : (e <= 32 ? 1 : 2);
+          sg.small_rows[cl] = std::max(sg.small_rows[cl], b.rows);
+          sg.small_cols[cl] = std::max(sg.small_cols[cl], b.cols);
+          sg.small[cl].push_back(b);
         } else {
           sg.max_rows = std::max(sg.max_rows, b.rows);
           sg.max_cols = std::max(sg.max_cols, b.cols);
@@ -1206,10 +1217,12 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       ProfScope ps("scale_blocks", s, sfl, sby);
       for (auto& kv : sgroups) {
         const SGroup& g = kv.second;
-        if (!g.small.empty()) {
-          ScaleBlk<T>* dsb = up.upload(wk, g.small, s);
-          launch_scale_small<T>(dsb, (int64_t)g.small.size(), dfac, kv.first, g.small_rows, g.small_cols, s);
-        }
+        for (int cl = 0; cl < 3; ++cl)
+          if (!g.small[cl].empty()) {
+            ScaleBlk<T>* dsb = up.upload(wk, g.small[cl], s);
+            launch_scale_small<T>(dsb, (int64_t)g.small[cl].size(), dfac, kv.first, g.small_rows[cl],
+                                  g.small_cols[cl], s);
+          }
         if (g.blk.empty()) continue;
         const int cw = kv.first >= 4 ? trail_width(g.max_rows, sizeof(T)) : 0;
         if (cw == 0) {
@@ -1275,12 +1288,15 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
     sparsify_batch<T>(sd, nb, up, wk, s);
   }
   {
-    std::vector<ApIface<T>> form;
-    for (auto& p : pl) append(form, p.form);
-    if (!form.empty()) {
-      ApIface<T>* d = up.upload(wk, form, s);
-      launch_iface_form<T>(d, (int64_t)form.size(), s);
-    }
+    // dense interface operators, one launch per size class (16, 32, 64)
+    std::vector<ApIface<T>> form[3];
+    for (auto& p : pl)
+      for (const ApIface<T>& q : p.form) form[q.P <= 16 ? 0 : (q.P <= 32 ? 1 : 2)].push_back(q);
+    for (int cl = 0; cl < 3; ++cl)
+      if (!form[cl].empty()) {
+        ApIface<T>* d = up.upload(wk, form[cl], s);
+        launch_iface_form<T>(d, (int64_t)form[cl].size(), 16 << cl, s);
+      }
   }
   }
   // ranks back, merges

@@ -181,19 +181,20 @@ __device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* 
 }
 
 // ---------------------------------------------------------------- kernels
-// One workgroup per tile.  Lanes run along the contiguous side of the
-// destination (columns for a plain copy, rows for a transpose), rounded up to
-// a power of two of at most 64, and the remaining threads take successive
-// rows (columns), so indices come from shifts and masks only.
+// One wavefront per tile.  A plain copy runs its lanes along the rows
+// (rounded up to a power of two of at most 64; the remaining lanes take
+// successive rows).  A transpose (row-major source, column-major
+// destination) goes through a 64 x 65 LDS tile so that both the reads of
+// source rows and the writes of destination columns are contiguous.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles) {
+__global__ void __launch_bounds__(64) k_copy(const CopyTile<T>* __restrict__ tiles) {
   const CopyTile<T> c = tiles[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int inner = c.mode == 0 ? c.cols : c.rows, outer = c.mode == 0 ? c.rows : c.cols;
-  int lg = 0;
-  while ((1 << lg) < inner && lg < 6) ++lg;
-  const int iw = 1 << lg, ostep = NT >> lg, ti = tid & (iw - 1), to = tid >> lg;
+  const int lane = threadIdx.x;
   if (c.mode == 0) {
+    const int inner = c.cols, outer = c.rows;
+    int lg = 0;
+    while ((1 << lg) < inner && lg < 6) ++lg;
+    const int iw = 1 << lg, ostep = 64 >> lg, ti = lane & (iw - 1), to = lane >> lg;
     for (int r = to; r < outer; r += ostep) {
       T* d = c.dst + (int64_t)r * c.ldd;
       if (c.src) {
@@ -203,11 +204,25 @@ __global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ til
         for (int q = ti; q < inner; q += iw) d[q] = T(0);
       }
     }
-  } else {
-    for (int cc = to; cc < outer; cc += ostep) {
-      T* d = c.dst + (int64_t)cc * c.ldd;
-      const T* sc = c.src + cc;
-      for (int r = ti; r < inner; r += iw) d[r] = sc[(int64_t)r * c.lds];
+    return;
+  }
+  __shared__ T t[64 * 65];
+  for (int r0 = 0; r0 < c.rows; r0 += 64) {
+    const int nr = min(64, c.rows - r0);
+    for (int c0 = 0; c0 < c.cols; c0 += 64) {
+      const int ncb = min(64, c.cols - c0);
+      const T* sb = c.src + (int64_t)r0 * c.lds + c0;
+      if (lane < ncb) {
+#pragma unroll 8
+        for (int r = 0; r < nr; ++r) t[lane * 65 + r] = sb[(int64_t)r * c.lds + lane];
+      }
+      __syncthreads();
+      T* db = c.dst + (int64_t)c0 * c.ldd + r0;
+      if (lane < nr) {
+#pragma unroll 8
+        for (int cc = 0; cc < ncb; ++cc) db[(int64_t)cc * c.ldd + lane] = t[cc * 65 + lane];
+      }
+      __syncthreads();
     }
   }
 }
@@ -798,12 +813,27 @@ __global__ void __launch_bounds__(NT) k_scale_small(const ScaleBlk<T>* __restric
       Rs[r * LB + c] = R[q];
     }
     __syncthreads();
-    for (int r = tid; r < rows; r += NT)
-      for (int c = 0; c < cols; ++c) {
-        T x = Bs[r * LB + c];
-        for (int q = 0; q < c; ++q) x -= Bs[r * LB + q] * Rs[q * LB + c];
-        Bs[r * LB + c] = x / Rs[c * LB + c];
-      }
+    // column panels of 16: the panel's entries are first reduced by the
+    // solved columns to their left (all rows x 16 entries in parallel), then
+    // each row solves the panel's 16 x 16 triangle
+    for (int p0 = 0; p0 < cols; p0 += 16) {
+      const int pw = min(16, cols - p0);
+      if (p0 > 0)
+        for (int q = tid; q < rows * pw; q += NT) {
+          const int r = q / pw, c = p0 + (q - r * pw);
+          T x = Bs[r * LB + c];
+          for (int q2 = 0; q2 < p0; ++q2) x -= Bs[r * LB + q2] * Rs[q2 * LB + c];
+          Bs[r * LB + c] = x;
+        }
+      __syncthreads();
+      for (int r = tid; r < rows; r += NT)
+        for (int c = p0; c < p0 + pw; ++c) {
+          T x = Bs[r * LB + c];
+          for (int q2 = p0; q2 < c; ++q2) x -= Bs[r * LB + q2] * Rs[q2 * LB + c];
+          Bs[r * LB + c] = x / Rs[c * LB + c];
+        }
+      __syncthreads();
+    }
   }
   __syncthreads();
   for (int q = tid; q < rows * cols; q += NT) {
@@ -2169,21 +2199,23 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
 // lanes share a column (rows part, part + 4, ...): reflector dots reduce with
 // two lane swaps and no barrier, since a column is only touched by its own
 // lanes.
-template <typename T>
-__global__ void __launch_bounds__(256) k_iface_form(const ApIface<T>* __restrict__ ds) {
-  constexpr int LX = 65;  // padded row stride of X: the four row parts fall in distinct banks
+// PM (16, 32 or 64) bounds P; the workgroup has 4 PM threads.
+template <typename T, int PM>
+__global__ void __launch_bounds__(4 * PM) k_iface_form(const ApIface<T>* __restrict__ ds) {
+  constexpr int LX = PM + 1;  // padded row stride of X: the four row parts fall in distinct banks
+  constexpr int NTH = 4 * PM;
   extern __shared__ __align__(16) unsigned char smem[];
   const ApIface<T> d = ds[blockIdx.x];
   const int P = d.P, tid = threadIdx.x, j = tid >> 2, part = tid & 3;
   if (P == 0 || *d.flag != 0) return;
   const int r = *d.rank;
   const bool hasq = r < P;
-  double* X = reinterpret_cast<double*>(smem);  // 64 x LX
-  double* tu = X + 64 * LX;                     // 64
-  double* tq = tu + 64;                         // 64
-  T* vu = reinterpret_cast<T*>(tq + 64);        // P x P column-major
+  double* X = reinterpret_cast<double*>(smem);  // PM x LX
+  double* tu = X + PM * LX;                     // PM
+  double* tq = tu + PM;                         // PM
+  T* vu = reinterpret_cast<T*>(tq + PM);        // P x P column-major
   T* vq = vu + P * P;                           // P x P column-major (first r columns)
-  for (int e = tid; e < P * P; e += 256) {
+  for (int e = tid; e < P * P; e += NTH) {
     vu[e] = d.vru[e];
     vq[e] = (hasq && e < P * r) ? d.vq[e] : T(0);
   }
@@ -2419,7 +2451,7 @@ static size_t device_lds_limit() {
 template <typename T>
 void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
+  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(64), 0, s, tiles);
   check_launch("k_copy");
 }
 
@@ -2903,13 +2935,21 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
   check_launch("k_ap_front_bwd_reg");
 }
 
-template <typename T>
-void launch_iface_form(const ApIface<T>* d, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  const size_t lds = (64 * 65 + 128) * sizeof(double) + 2 * 64 * 64 * sizeof(T);
-  allow_lds(reinterpret_cast<const void*>(&k_iface_form<T>), lds, "k_iface_form");
-  hipLaunchKernelGGL(k_iface_form<T>, dim3((unsigned)n), dim3(256), lds, s, d);
+template <typename T, int PM>
+static void launch_iface_form_t(const ApIface<T>* d, int64_t n, hipStream_t s) {
+  const size_t lds = ((size_t)PM * (PM + 1) + 2 * PM) * sizeof(double) + 2 * (size_t)PM * PM * sizeof(T);
+  allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM>), lds, "k_iface_form");
+  hipLaunchKernelGGL((k_iface_form<T, PM>), dim3((unsigned)n), dim3(4 * PM), lds, s, d);
   check_launch("k_iface_form");
+}
+
+template <typename T>
+void launch_iface_form(const ApIface<T>* d, int64_t n, int max_p, hipStream_t s) {
+  if (n <= 0) return;
+  SPAQR_REQUIRE(max_p <= 64, SPAQR_EINVAL, "dense interface operators need P <= 64");
+  if (max_p <= 16) launch_iface_form_t<T, 16>(d, n, s);
+  else if (max_p <= 32) launch_iface_form_t<T, 32>(d, n, s);
+  else launch_iface_form_t<T, 64>(d, n, s);
 }
 
 template <typename T>
@@ -2980,7 +3020,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template void launch_front_fwd_wy<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
   template void launch_front_bwd_reg<T>(const ApFront<T>*, int64_t, int, int, double*, int64_t, int, hipStream_t); \
   template void launch_iface_small<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t); \
-  template void launch_iface_form<T>(const ApIface<T>*, int64_t, hipStream_t);                       \
+  template void launch_iface_form<T>(const ApIface<T>*, int64_t, int, hipStream_t);                  \
   template int sparsify_coop_capacity<T>(int, int, int);                                               \
   template bool launch_sparsify_coop<T>(const SpDesc<T>*, const CoopItem*, int, int, int, const SpNbr*, int, int, \
                                         double*, int*, T*, int*, int, hipStream_t);                    \

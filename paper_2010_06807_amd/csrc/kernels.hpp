@@ -229,7 +229,7 @@ int sparsify_coop_capacity(int cpt, int max_p, int max_nb);
 // Dense interface operators (P <= 64): mf = Q^T U^T and mb = R_pp^{-1} Q,
 // one thread per column; then the apply multiplies by them.
 template <typename T>
-void launch_iface_form(const ApIface<T>* d, int64_t n, hipStream_t s);
+void launch_iface_form(const ApIface<T>* d, int64_t n, int max_p, hipStream_t s);  // max_p <= 64
 template <typename T>
 void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
                         hipStream_t s);
