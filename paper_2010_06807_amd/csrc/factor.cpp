@@ -848,6 +848,13 @@ struct BatchCtx {
   DevArena work[2] = {DevArena(size_t(16) << 20), DevArena(size_t(16) << 20)};
   int cur = 0;
   std::unique_ptr<HostPool> pool;  // per-problem planning of a batch, in parallel
+  hipEvent_t ev = nullptr;          // end of the enqueued part of the current stage
+  BatchCtx() = default;
+  BatchCtx(const BatchCtx&) = delete;
+  BatchCtx& operator=(const BatchCtx&) = delete;
+  ~BatchCtx() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
   void begin() {
     cur ^= 1;
     st[cur].reset();
@@ -929,18 +936,20 @@ static X* upload_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get g
   return static_cast<X*>(r.dev);
 }
 
+// transpose: the lists hold packs (mode 1) only, else plain copies only
 template <typename T, typename Get>
-static void copy_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, hipStream_t s) {
+static void copy_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, bool transpose, hipStream_t s) {
   int64_t n = 0;
   CopyTile<T>* d = upload_concat<CopyTile<T>>(bx, up, wk, ne, get, s, &n);
-  if (n > 0) launch_copy<T>(d, n, s);
+  if (n > 0) launch_copy<T>(d, n, transpose, s);
 }
 
 template <typename T>
-static void copy_batch(const std::vector<CopyTile<T>>& tiles, Stager& up, DevArena& wk, hipStream_t s) {
+static void copy_batch(const std::vector<CopyTile<T>>& tiles, bool transpose, Stager& up, DevArena& wk,
+                       hipStream_t s) {
   if (tiles.empty()) return;
   CopyTile<T>* d = up.upload(wk, tiles, s);
-  launch_copy<T>(d, (int64_t)tiles.size(), s);
+  launch_copy<T>(d, (int64_t)tiles.size(), transpose, s);
 }
 
 template <typename T>
@@ -1086,8 +1095,13 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   launch_sparsify<T>(dsd + nrest0 + nsmall, (int64_t)sd.size() - nrest0 - nsmall, dnb, max_pc, max_nb, s);
 }
 
+// One stage of every factorization in es, in two halves: stage_launch plans
+// and enqueues everything up to the rank readback and records bx.ev;
+// stage_finish waits for that event, finishes the stage on the host and
+// enqueues the merges.  Between the two the host is free to plan another
+// batch whose work then queues behind this one.
 template <typename T>
-void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s) {
+void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s) {
   bx.begin();
   Stager& up = bx.st[bx.cur];
   DevArena& wk = bx.work[bx.cur];
@@ -1126,7 +1140,7 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
                    [&](int e) -> const std::vector<CopyTile<T>>& {
                      return c < pl[e].fronts.size() ? pl[e].fronts[c].gather : none;
                    },
-                   s);
+                   false, s);
     launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
     {
       // trailing slices of split fronts, grouped by (panel width, slice width)
@@ -1155,9 +1169,9 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
                    [&](int e) -> const std::vector<CopyTile<T>>& {
                      return c < pl[e].fronts.size() ? pl[e].fronts[c].scatter : none;
                    },
-                   s);
+                   false, s);
   }
-  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, true, s);
   }
   // block-diagonal scaling
   {
@@ -1209,9 +1223,9 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
         sby += 2.0 * b.rows * (double)b.cols * sizeof(T);
       }
     }
-    copy_batch(g, up, wk, s);
+    copy_batch(g, false, up, wk, s);
     launch_qr_groups<T>(qparts, "scale_qr", qfl, qby, up, wk, s);
-    copy_batch(pk, up, wk, s);
+    copy_batch(pk, true, up, wk, s);
     if (!fac.empty()) {
       ScaleFac<T>* dfac = up.upload(wk, fac, s);
       ProfScope ps("scale_blocks", s, sfl, sby);
@@ -1299,11 +1313,20 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
       }
   }
   }
-  // ranks back, merges
+  // ranks back
+  for (Engine<T>* e : es) e->readback();
+  if (!bx.ev) SPAQR_HIP(hipEventCreateWithFlags(&bx.ev, hipEventDisableTiming));
+  SPAQR_HIP(hipEventRecord(bx.ev, s));
+}
+
+template <typename T>
+void stage_finish(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s) {
+  Stager& up = bx.st[bx.cur];
+  DevArena& wk = bx.work[bx.cur];
+  const size_t ne = es.size();
   {
     HostScope hs("host_wait_gpu");
-    for (Engine<T>* e : es) e->readback();
-    SPAQR_HIP(hipStreamSynchronize(s));
+    SPAQR_HIP(hipEventSynchronize(bx.ev));
   }
   std::vector<MergePlan<T>> mp(ne);
   {
@@ -1314,7 +1337,13 @@ void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_
   std::vector<ZeroOp> z;
   for (auto& m : mp) append(z, m.zero);
   launch_zero_ops(z, up, wk, s);
-  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, false, s);
+}
+
+template <typename T>
+void run_stage_batch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s) {
+  stage_launch<T>(es, bx, s);
+  stage_finish<T>(es, bx, s);
 }
 
 template <typename T>
@@ -1619,17 +1648,23 @@ std::unique_ptr<KrylovOp> make_batch_op(const std::vector<EngineBase*>& es, cons
   return std::unique_ptr<KrylovOp>(new MultiOp(es, nrhs));
 }
 
-void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s) {
-  std::vector<Engine<float>*> f32;
-  std::vector<Engine<double>*> f64;
+static void split_precision(const std::vector<EngineBase*>& es, hipStream_t s, std::vector<Engine<float>*>& f32,
+                            std::vector<Engine<double>*>& f64) {
   for (EngineBase* e : es) {
     if (e->stages_left() <= 0) continue;
     SPAQR_REQUIRE(e->stream() == s, SPAQR_EINVAL, "batched factorizations must share one stream");
     if (e->precision() == 32) f32.push_back(static_cast<Engine<float>*>(e));
     else f64.push_back(static_cast<Engine<double>*>(e));
   }
+}
+
+void factor_stage_batch(BatchDriver& drv, const std::vector<EngineBase*>& es, hipStream_t s) {
+  std::vector<Engine<float>*> f32;
+  std::vector<Engine<double>*> f64;
+  split_precision(es, s, f32, f64);
   if (!f32.empty()) run_stage_batch<float>(f32, drv.b32, s);
   if (!f64.empty()) run_stage_batch<double>(f64, drv.b64, s);
 }
+
 
 }  // namespace spaqr

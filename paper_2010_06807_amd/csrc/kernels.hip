@@ -181,47 +181,48 @@ __device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* 
 }
 
 // ---------------------------------------------------------------- kernels
-// One wavefront per tile.  A plain copy runs its lanes along the rows
-// (rounded up to a power of two of at most 64; the remaining lanes take
-// successive rows).  A transpose (row-major source, column-major
-// destination) goes through a 64 x 65 LDS tile so that both the reads of
-// source rows and the writes of destination columns are contiguous.
+// Plain copies (mode 0), one workgroup per tile: lanes run along the rows
+// (rounded up to a power of two of at most 64), the remaining threads take
+// successive rows, so indices come from shifts and masks only.
 template <typename T>
-__global__ void __launch_bounds__(64) k_copy(const CopyTile<T>* __restrict__ tiles) {
+__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles) {
   const CopyTile<T> c = tiles[blockIdx.x];
-  const int lane = threadIdx.x;
-  if (c.mode == 0) {
-    const int inner = c.cols, outer = c.rows;
-    int lg = 0;
-    while ((1 << lg) < inner && lg < 6) ++lg;
-    const int iw = 1 << lg, ostep = 64 >> lg, ti = lane & (iw - 1), to = lane >> lg;
-    for (int r = to; r < outer; r += ostep) {
-      T* d = c.dst + (int64_t)r * c.ldd;
-      if (c.src) {
-        const T* sr = c.src + (int64_t)r * c.lds;
-        for (int q = ti; q < inner; q += iw) d[q] = sr[q];
-      } else {
-        for (int q = ti; q < inner; q += iw) d[q] = T(0);
-      }
+  const int tid = threadIdx.x;
+  const int inner = c.cols, outer = c.rows;
+  int lg = 0;
+  while ((1 << lg) < inner && lg < 6) ++lg;
+  const int iw = 1 << lg, ostep = NT >> lg, ti = tid & (iw - 1), to = tid >> lg;
+  for (int r = to; r < outer; r += ostep) {
+    T* d = c.dst + (int64_t)r * c.ldd;
+    if (c.src) {
+      const T* sr = c.src + (int64_t)r * c.lds;
+      for (int q = ti; q < inner; q += iw) d[q] = sr[q];
+    } else {
+      for (int q = ti; q < inner; q += iw) d[q] = T(0);
     }
-    return;
   }
+}
+
+// Transposing copies (mode 1: row-major source, column-major destination),
+// one workgroup per tile, through a 64 x 65 LDS tile: each wavefront reads
+// every fourth row of a 64 x 64 sub-tile (contiguous along the row) and then
+// writes every fourth column (contiguous along the column).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_copy_t(const CopyTile<T>* __restrict__ tiles) {
+  const CopyTile<T> c = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __shared__ T t[64 * 65];
   for (int r0 = 0; r0 < c.rows; r0 += 64) {
     const int nr = min(64, c.rows - r0);
     for (int c0 = 0; c0 < c.cols; c0 += 64) {
       const int ncb = min(64, c.cols - c0);
       const T* sb = c.src + (int64_t)r0 * c.lds + c0;
-      if (lane < ncb) {
-#pragma unroll 8
-        for (int r = 0; r < nr; ++r) t[lane * 65 + r] = sb[(int64_t)r * c.lds + lane];
-      }
+      if (lane < ncb)
+        for (int r = wv; r < nr; r += 4) t[lane * 65 + r] = sb[(int64_t)r * c.lds + lane];
       __syncthreads();
       T* db = c.dst + (int64_t)c0 * c.ldd + r0;
-      if (lane < nr) {
-#pragma unroll 8
-        for (int cc = 0; cc < ncb; ++cc) db[(int64_t)cc * c.ldd + lane] = t[cc * 65 + lane];
-      }
+      if (lane < nr)
+        for (int cc = wv; cc < ncb; cc += 4) db[(int64_t)cc * c.ldd + lane] = t[cc * 65 + lane];
       __syncthreads();
     }
   }
@@ -2449,10 +2450,15 @@ static size_t device_lds_limit() {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s) {
+void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipStream_t s) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(64), 0, s, tiles);
-  check_launch("k_copy");
+  if (transpose) {
+    hipLaunchKernelGGL(k_copy_t<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
+    check_launch("k_copy_t");
+  } else {
+    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
+    check_launch("k_copy");
+  }
 }
 
 void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s) {
@@ -3000,7 +3006,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
 }
 
 #define SPAQR_INST(T)                                                                                  \
-  template void launch_copy<T>(const CopyTile<T>*, int64_t, hipStream_t);                             \
+  template void launch_copy<T>(const CopyTile<T>*, int64_t, bool, hipStream_t);                       \
   template void launch_fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void launch_scatter_nz<T>(T*, const int64_t*, const double*, int64_t, hipStream_t);       \
   template void launch_scatter_scaled<T>(T*, const int64_t*, const double*, const int32_t*, const double*, \

@@ -140,8 +140,9 @@ struct ApIface {
 };
 
 // ------------------------------------------------------------------ launchers
+// Copy tiles; transpose: every tile has mode 1 (else every tile has mode 0).
 template <typename T>
-void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, hipStream_t s);
+void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T>

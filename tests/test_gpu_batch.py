@@ -104,3 +104,16 @@ def test_batch_of_one_matches_plain_solve_exactly():
     # same launches, same kernels: bit-identical factors and iterates
     assert ia[0]["iterations"] == ib[0]["iterations"]
     assert np.array_equal(xa.reshape(-1), xb.reshape(-1))
+
+
+def test_factor_batch_mixed_shapes_one_eps():
+    """Five problems of different shapes (2D and 3D, different depths) in one
+    batched factorization and one batched solve: every problem must match
+    its factorization alone."""
+    probs = [((40, 40), (10.0, 5.0)), ((12, 12, 12), (5.0, 5.0, 5.0)), ((64, 40), (-30.0, 20.0)),
+             ((10, 10, 14), (2.0, -3.0, 1.0)), ((56, 56), (1.0, 20.0))]
+    jobs = [_setup(i, d, bt, 1e-2, 1) for i, (d, bt) in enumerate(probs)]
+    dcsrs = [P.DeviceCSR(j["A"]) for j in jobs]
+    facs = P.factor_batch([j["A"] for j in jobs], [j["sym"] for j in jobs], dcsrs, eps=1e-2, precision=32)
+    xs, infos = P.solve_batch(facs, [j["b"] for j in jobs], tol=1e-10)
+    _compare(jobs, facs, xs, infos, 32)
