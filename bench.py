@@ -36,6 +36,13 @@ if ROOT not in sys.path:
 
 METRIC = "unknowns/s factor+GMRES to 1e-10, batched FP32 vs plain FP64; p50/p99 latency"
 
+WORKLOAD_TEXT = {
+    "c1": "2D convection-diffusion, 5-point upwind,",
+    "c2": "2D variable-coefficient convection-diffusion, 5-point upwind,",
+    "c3": "3D convection-diffusion, 7-point upwind,",
+    "c4": "2D advection-dominated, 5-point upwind with perturbed entries,",
+}
+
 # Published MI355X peaks used for the roofline fractions.
 PEAK = {
     "hbm": (8000.0, "GB/s"),
@@ -66,6 +73,8 @@ def parse():
     ap.add_argument("--kernel", default=None, help="kernel for the roofline (default: the slowest)")
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the serving trace replayed after the single-problem steps (0: skip)")
+    ap.add_argument("--serving-load", type=float, default=1.0,
+                    help="arrival rate of the serving trace as a fraction of the plain FP64 path's capacity")
     ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
                     help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
                          "directory of this script's run and exit")
@@ -122,12 +131,13 @@ def rocprof_summary(d, fp32_steps):
     return "\n".join(out)
 
 
-def serving(nreq, tol, seed=0):
+def serving(nreq, tol, load=1.0, seed=0):
     """The serving workload: the first nreq requests of the seeded trace
     (2D sides 64..512 or 3D sides 16..48, |beta| 1..200, 1..32 right-hand
     sides, eps 1e-2).  A calibration pass runs the plain FP64 path over the
     requests back to back; the arrival times are then scaled so that path
-    would be busy 70% of the time, and the trace is replayed through the
+    would be busy a fraction `load` of the time (1.0: exactly saturated), and
+    the trace is replayed through the
     batched FP32 server and through the sequential FP64 path on the same
     timestamps.  Throughput counts unknowns x right-hand sides per second of
     makespan; latency runs from a request's arrival to its last solution."""
@@ -146,14 +156,14 @@ def serving(nreq, tol, seed=0):
     log(f"serving: calibration {cal['makespan_s']:.1f} s")
     service = cal["makespan_s"] / len(jobs)
     mean_gap = float(np.mean(np.diff([0.0] + [r["arrival"] for r in reqs])))
-    scale = service / 0.7 / mean_gap
+    scale = service / load / mean_gap
     res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale, log=log)
     log(f"serving: batched FP32 makespan {batched['makespan_s']:.1f} s")
     res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale, log=log)
     log(f"serving: sequential FP64 makespan {plain['makespan_s']:.1f} s")
     worst = max(max(r["relres"]) for r in res_b + res_s)
     return {"requests": len(jobs), "unknowns_x_rhs": int(sum(j["A"].shape[0] * j["b"].shape[1] for j in jobs)),
-            "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": 0.7,
+            "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": load,
             "batched_fp32": {k: batched[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
             "plain_fp64": {k: plain[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
             "max_relres": worst, "unit": "unknowns*rhs/s"}
@@ -353,8 +363,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{prob['name']}: 2D variable-coefficient convection-diffusion "
-                               f"{dims[0]}x{dims[1]} (N={N}), 5-point upwind, eps={args.eps}, "
+        "config": {"workload": f"{prob['name']}: {WORKLOAD_TEXT.get(prob['name'], 'convection-diffusion')} "
+                               f"{'x'.join(str(d) for d in dims)} (N={N}), eps={args.eps}, "
                                f"{L} ND levels, FP32 factors + FP64 FGMRES to {args.tol}, 1 RHS per request, "
                                f"{B} requests per step batched (seeds 0..{B - 1})",
                    "eps": args.eps, "levels": L, "n": N, "batch": B},
@@ -368,7 +378,7 @@ def main():
         "roofline": roof,
     }
     if args.serving_requests > 0:
-        out["serving"] = serving(args.serving_requests, args.tol)
+        out["serving"] = serving(args.serving_requests, args.tol, args.serving_load)
     if not args.no_cpu_baseline:
         log("oracle on the host (cpu_baseline)")
         out["cpu_baseline"] = cpu_baseline(prob, args.eps, args.tol)
