@@ -2,7 +2,7 @@
 // right-hand sides) are copied at submission and queued.  Every step:
 //   1. admits queued requests in arrival order while their estimated device
 //      memory fits the budget (symbolic analysis and matrix upload happen
-//      here);
+//      here, the admitted requests in parallel host threads);
 //   2. advances every admitted, still factoring request by one stage in one
 //      batched pass: their fronts, scalings and sparsifications share one
 //      launch per phase, whatever stage each request is at, so a request that
@@ -17,6 +17,7 @@
 #include <memory>
 
 #include "engine.hpp"
+#include "pool.hpp"
 
 namespace spaqr {
 
@@ -58,6 +59,7 @@ struct spaqr_server {
   std::vector<std::unique_ptr<spaqr::Request>> active;
   std::map<uint64_t, std::unique_ptr<spaqr::Request>> done;
   spaqr::BatchDriver* drv = nullptr;
+  std::unique_ptr<spaqr::HostPool> pool;  // admission of several requests in parallel
   ~spaqr_server() {
     active.clear();
     if (drv) spaqr::batch_driver_free(drv);
@@ -200,20 +202,38 @@ spaqr_status spaqr_submit(spaqr_server* srv, const spaqr_csr* A, const spaqr_ord
 spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
   return guard([&]() -> spaqr_status {
     SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
-    // 1. admission by estimated memory, in arrival order
+    // 1. admission by estimated memory, in arrival order; the admitted
+    // requests' symbolic analyses and set-ups run in parallel host threads
+    std::vector<std::unique_ptr<Request>> adm;
     while (!srv->queue.empty() && srv->used + srv->queue.front()->est <= srv->budget) {
-      std::unique_ptr<Request> r = std::move(srv->queue.front());
+      adm.push_back(std::move(srv->queue.front()));
       srv->queue.pop_front();
-      srv->used += r->est;
-      try {
-        r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
-        r->eng = make_engine_deferred(&r->A, nullptr, *r->sym, r->opts, srv->stream);
-        srv->active.push_back(std::move(r));
-      } catch (const Error& e) {
-        retire(srv, std::move(r), e.status);
-      } catch (const std::bad_alloc&) {
-        retire(srv, std::move(r), SPAQR_ENOMEM);
+      srv->used += adm.back()->est;
+    }
+    std::vector<int> adm_st(adm.size(), SPAQR_OK);
+    if (!adm.empty()) {
+      if (!srv->pool && adm.size() > 1) {
+        const unsigned hc = std::thread::hardware_concurrency();
+        srv->pool.reset(new HostPool((int)std::min<unsigned>(7, hc > 1 ? hc - 1 : 0)));
       }
+      auto setup = [&](int i) {
+        Request& r = *adm[i];
+        try {
+          r.sym.reset(analyze(&r.A, r.ord, r.opts.skip));
+          r.eng = make_engine_deferred(&r.A, nullptr, *r.sym, r.opts, srv->stream);
+        } catch (const Error& e) {
+          adm_st[i] = e.status;
+        } catch (const std::bad_alloc&) {
+          adm_st[i] = SPAQR_ENOMEM;
+        }
+      };
+      if (srv->pool) srv->pool->run((int)adm.size(), setup);
+      else
+        for (size_t i = 0; i < adm.size(); ++i) setup((int)i);
+    }
+    for (size_t i = 0; i < adm.size(); ++i) {
+      if (adm_st[i] == SPAQR_OK) srv->active.push_back(std::move(adm[i]));
+      else retire(srv, std::move(adm[i]), adm_st[i]);
     }
     // 2. one stage of every factoring request, batched across requests
     std::vector<EngineBase*> es;
