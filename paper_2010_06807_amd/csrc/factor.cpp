@@ -426,7 +426,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
       int mm = 0;
       for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
         const int32_t f = ss.front_order[oi];
-        if (fn[f] > 0 && (fm[f] > 1024 || fnc[f] - fn[f] >= 256)) mm = std::max(mm, fm[f]);
+        if (fn[f] > 0 && (fm[f] > 1024 || fnc[f] - fn[f] >= 1024)) mm = std::max(mm, fm[f]);
       }
       if (mm > 0) {
         fc.trail_cw = trail_width(mm, sizeof(T));
@@ -460,7 +460,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         ro += size_[i];
       }
       if (n > 0) {
-        const bool split = fc.trail_cw > 0 && (fm[f] > 1024 || nc - n >= 256);
+        const bool split = fc.trail_cw > 0 && (fm[f] > 1024 || nc - n >= 1024);
         fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, split ? n : nc, ldw});
         if (split)
           for (int c0 = n; c0 < nc; c0 += fc.trail_cw)
