@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "profile.hpp"
 
 namespace spaqr {
 
@@ -311,7 +312,12 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
   const size_t np = es.size();
   SPAQR_REQUIRE(np > 0 && nrhs.size() == np && b.size() == np && x.size() == np && tol.size() == np, SPAQR_EINVAL,
                 "batched solve: argument lists differ in length");
-  std::unique_ptr<KrylovOp> op = make_batch_op(es, nrhs);
+  std::unique_ptr<KrylovOp> op;
+  {
+    HostScope hs("host_solve_setup");
+    op = make_batch_op(es, nrhs);
+  }
+  HostScope hs_all("host_solve_krylov");
   hipStream_t s = op->stream();
   const int64_t N = op->n();
   int C = 0, restart = 1, maxit = 1;

@@ -1986,12 +1986,12 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_wy(const ApFront<T>* __res
 // the triangular solve runs in 64-row blocks from the bottom, each diagonal
 // block by one wavefront with shuffles, the rows above it updated by all
 // threads.
-constexpr int kBwdTile = 128;   // rows of the LDS tile of R_ss in the backward apply
-constexpr int kBwdChunk = 1024; // ancestor unknowns x_j staged in LDS at a time
+constexpr int kBwdTile = 128;   // largest number of rows of the LDS tile of R_ss in the backward apply
+constexpr int kBwdChunk = 1024; // largest number of ancestor unknowns x_j staged in LDS at a time
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __restrict__ ds, double* x,
-                                                         int64_t ldx, int nrhs, int rb) {
+                                                         int64_t ldx, int nrhs, int rb, int chunk, int tile_rows) {
   const ApFront<T> d = ds[blockIdx.x];
   x += d.xoff;
   const int c0 = blockIdx.y * rb, nc = min(rb, nrhs - c0);
@@ -1999,8 +1999,8 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
   extern __shared__ __align__(16) unsigned char smem[];
   const int n = d.n, k = d.k, m = d.m, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double* ys = reinterpret_cast<double*>(smem);  // n x nc
-  double* xc = ys + (size_t)n * rb;              // kBwdChunk x nc: x_j, chunk by chunk
-  double* part = xc + (size_t)kBwdChunk * rb;    // 256 partial sums
+  double* xc = ys + (size_t)n * rb;              // chunk x nc: x_j, chunk by chunk
+  double* part = xc + (size_t)chunk * rb;        // 256 partial sums
   for (int c = 0; c < nc; ++c)
     for (int r = tid; r < n; r += 256) ys[r + c * n] = x[d.rows[r] + (int64_t)(c0 + c) * ldx];
   {
@@ -2008,10 +2008,10 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
     // every thread has exactly one row and group), column groups G = 256 / RP
     const int RP = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
     const int G = 256 / RP, r0 = tid % RP, g = tid / RP;
-    for (int j0 = 0; j0 < k; j0 += kBwdChunk) {
-      const int kc = min(kBwdChunk, k - j0);
+    for (int j0 = 0; j0 < k; j0 += chunk) {
+      const int kc = min(chunk, k - j0);
       for (int c = 0; c < nc; ++c)
-        for (int r = tid; r < kc; r += 256) xc[r + c * kBwdChunk] = x[d.cols[j0 + r] + (int64_t)(c0 + c) * ldx];
+        for (int r = tid; r < kc; r += 256) xc[r + c * chunk] = x[d.cols[j0 + r] + (int64_t)(c0 + c) * ldx];
       __syncthreads();
       for (int c = 0; c < nc; ++c)
         for (int rbase = 0; rbase < n; rbase += RP) {
@@ -2020,7 +2020,7 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
           if (r < n) {
             const T* rc = d.rsj + r + (int64_t)j0 * n;
 #pragma unroll 8
-            for (int j = g; j < kc; j += G) acc += (double)rc[(int64_t)j * n] * xc[j + c * kBwdChunk];
+            for (int j = g; j < kc; j += G) acc += (double)rc[(int64_t)j * n] * xc[j + c * chunk];
           }
           if (G == 1) {
             if (r < n) ys[r + c * n] -= acc;
@@ -2040,10 +2040,11 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
   }
   __syncthreads();
   // R_ss (column-major in vr, leading dimension m) is staged through an LDS
-  // tile of kBwdTile rows x 64 columns: every load of a block is issued at
-  // once by the whole workgroup instead of one dependent chain per thread
+  // tile of tile_rows (64 or 128) rows x 64 columns: every load of a block is
+  // issued at once by the whole workgroup instead of one dependent chain per
+  // thread
   const T* R = d.vr;
-  T* Rt = reinterpret_cast<T*>(part + 256);  // kBwdTile x 65
+  T* Rt = reinterpret_cast<T*>(part + 256);  // tile_rows x 65
   for (int b0 = ((n - 1) / 64) * 64; b0 >= 0; b0 -= 64) {
     const int b1 = min(n, b0 + 64), bw = b1 - b0;
     for (int q = tid; q < 64 * 64; q += 256) {
@@ -2064,8 +2065,8 @@ __global__ void __launch_bounds__(256) k_ap_front_bwd_reg(const ApFront<T>* __re
       }
     }
     __syncthreads();
-    for (int rs = 0; rs < b0; rs += kBwdTile) {
-      const int nr = min(kBwdTile, b0 - rs);
+    for (int rs = 0; rs < b0; rs += tile_rows) {
+      const int nr = min(tile_rows, b0 - rs);
       for (int q = tid; q < nr * bw; q += 256) {
         const int cc = q / nr, r = q - cc * nr;
         Rt[r * 65 + cc] = R[(rs + r) + (int64_t)(b0 + cc) * m];
@@ -2925,19 +2926,21 @@ template <typename T>
 void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, double* x, int64_t ldx, int nrhs,
                           hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
-  // LDS: y_s and a chunk of x_j (rb columns each), 256 partial sums, the
-  // R_ss tile
-  (void)max_k;
-  const size_t tile = (size_t)kBwdTile * 65 * sizeof(T) + 256 * sizeof(double);
+  // LDS, sized for the launch's fronts (occupancy): y_s and a chunk of x_j
+  // (rb columns each), 256 partial sums, the R_ss tile (the rows above a
+  // 64-row diagonal block are at most max_n - 64)
+  const int chunk = std::max(1, std::min(kBwdChunk, (max_k + 63) / 64 * 64));
+  const int tile_rows = max_n - 64 > 64 ? kBwdTile : 64;
+  const size_t tile = (size_t)tile_rows * 65 * sizeof(T) + 256 * sizeof(double);
   const size_t lim = apply_lds_budget() - tile;
-  const size_t per_rhs = (size_t)(max_n + kBwdChunk) * sizeof(double);
+  const size_t per_rhs = (size_t)(max_n + chunk) * sizeof(double);
   int rb = std::min(RBMAX, nrhs);
   while (rb > 1 && per_rhs * rb > lim) --rb;
   if (per_rhs * rb > lim) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
   const size_t lds = per_rhs * rb + tile;
   allow_lds(reinterpret_cast<const void*>(&k_ap_front_bwd_reg<T>), lds, "k_ap_front_bwd_reg");
   hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
-                     d, x, ldx, nrhs, rb);
+                     d, x, ldx, nrhs, rb, chunk, tile_rows);
   check_launch("k_ap_front_bwd_reg");
 }
 
