@@ -923,15 +923,23 @@ static X* upload_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get g
   for (size_t e = 0; e < ne; ++e) off[e + 1] = off[e] + get(e).size();
   *count = (int64_t)off[ne];
   if (off[ne] == 0) return nullptr;
-  const Stager::Region r = up.stage(wk, off[ne] * sizeof(X), s);
+  Stager::Region r;
+  {
+    HostScope hs("host_upload_stage");
+    r = up.stage(wk, off[ne] * sizeof(X), s);
+  }
   X* h = static_cast<X*>(r.host);
   auto put = [&](int e) {
     const std::vector<X>& v = get(e);
     if (!v.empty()) std::memcpy(h + off[e], v.data(), v.size() * sizeof(X));
   };
-  if (ne > 1 && off[ne] * sizeof(X) > (size_t(1) << 20)) bx.each(ne, put);
-  else
-    for (size_t e = 0; e < ne; ++e) put((int)e);
+  {
+    HostScope hs("host_upload_pack");
+    if (ne > 1 && off[ne] * sizeof(X) > (size_t(1) << 20)) bx.each(ne, put);
+    else
+      for (size_t e = 0; e < ne; ++e) put((int)e);
+  }
+  HostScope hs("host_upload_send");
   up.send(r, s);
   return static_cast<X*>(r.dev);
 }
@@ -1141,7 +1149,10 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
                      return c < pl[e].fronts.size() ? pl[e].fronts[c].gather : none;
                    },
                    false, s);
-    launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
+    {
+      HostScope hs("host_launch_qr");
+      launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
+    }
     {
       // trailing slices of split fronts, grouped by (panel width, slice width)
       std::map<std::pair<int, int>, std::pair<int, std::vector<TrailDesc<T>>>> tg;
