@@ -433,26 +433,32 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         fc.trail_max_m = mm;
       }
     }
+    {
+      size_t np = 0;
+      for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi)
+        np += ss.fronts[ss.front_order[oi]].blk.size();
+      fc.gather.reserve(np);
+      fc.scatter.reserve(np);
+    }
     for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
       const int32_t f = ss.front_order[oi];
       const FrontSym& F = ss.fronts[f];
       T* Wf = W + ws_off[f];
       const int32_t nc = fnc[f], n = fn[f], ldw = fld[f];
-      std::vector<int32_t> rows{F.cluster}, cols{F.cluster};
-      rows.insert(rows.end(), F.n1.begin(), F.n1.end());
-      cols.insert(cols.end(), F.cols.begin(), F.cols.end());
+      const size_t nr = 1 + F.n1.size(), ncl = 1 + F.cols.size();
       int ro = 0;
-      for (size_t a = 0; a < rows.size(); ++a) {
+      for (size_t a = 0; a < nr; ++a) {
         int co = 0;
-        const int32_t i = rows[a];
-        for (size_t b = 0; b < cols.size(); ++b) {
-          const int32_t j = cols[b];
+        const int32_t i = a == 0 ? F.cluster : F.n1[a - 1];
+        const int64_t* brow = F.blk.data() + a * ncl;
+        for (size_t b = 0; b < ncl; ++b) {
+          const int32_t j = b == 0 ? F.cluster : F.cols[b - 1];
           if (size_[i] > 0 && size_[j] > 0) {
-            fc.gather.push_back({blk(i, j), Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw, 0, 0});
+            T* blkp = brow[b] < 0 ? nullptr : pool_ + boff_[brow[b]];
+            fc.gather.push_back({blkp, Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw, 0, 0});
             if (a > 0 && b > 0) {
-              T* dst = blk(i, j);
-              SPAQR_REQUIRE(dst != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
-              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, dst, size_[i], size_[j], ldw, size_[j], 0, 0});
+              SPAQR_REQUIRE(blkp != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
+              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, blkp, size_[i], size_[j], ldw, size_[j], 0, 0});
             }
           }
           co += size_[j];
@@ -821,10 +827,10 @@ void Engine<T>::finish(MergePlan<T>& mp) {
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
       const int32_t j = ss.post.col[u];
       if (rank[i] == 0 || rank[j] == 0) continue;
-      const int32_t Pc = (int32_t)par[i], Qc = (int32_t)par[j];
-      const int64_t B = s2.all.find(Pc, Qc);
+      const int32_t Qc = (int32_t)par[j];
+      const int64_t B = ss.post_next[u];
       SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
-      const int64_t b = ss.all.find((int32_t)i, j);
+      const int64_t b = ss.post_all[u];
       mp.tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Qc] + off[j], rank[i], rank[j],
                           size_[j], size2[Qc], 0, 0});
     }

@@ -236,6 +236,16 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
       allp.insert(allp.end(), inp.begin(), inp.end());
       ss.all = BlockSet::from_pairs(ss.nclu, allp);
     }
+    // block indices of every front's gather (pattern only: the numeric
+    // planning reads them instead of searching the block set)
+    for (FrontSym& f : ss.fronts) {
+      const size_t nr = 1 + f.n1.size(), ncl = 1 + f.cols.size();
+      f.blk.resize(nr * ncl);
+      for (size_t a = 0; a < nr; ++a) {
+        const int32_t i = a == 0 ? f.cluster : f.n1[a - 1];
+        for (size_t b = 0; b < ncl; ++b) f.blk[a * ncl + b] = ss.all.find(i, b == 0 ? f.cluster : f.cols[b - 1]);
+      }
+    }
     for (int64_t c = 0; c < ss.nclu; ++c)
       if (sc.level[c] < k) ss.remaining.push_back((int32_t)c);
     // ---- interfaces
@@ -280,6 +290,23 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
       }
       cur = BlockSet::from_pairs(ord.stages[k - 1].count(), up);
     }
+  }
+
+  // ---- merge maps (the parent stage's block set exists only now)
+  for (int k = L; k >= 1; --k) {
+    StageSym& ss = S->st[k];
+    const int64_t np = ss.post.size();
+    ss.post_all.assign(np, -1);
+    ss.post_next.assign(np, -1);
+    for (int64_t i = 0; i < ss.nclu; ++i)
+      for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
+        const int32_t j = ss.post.col[u];
+        ss.post_all[u] = ss.all.find((int32_t)i, j);
+        if (k > 1) {
+          const std::vector<int64_t>& par = ord.stages[k].parent;
+          ss.post_next[u] = S->st[k - 1].all.find((int32_t)par[i], (int32_t)par[j]);
+        }
+      }
   }
 
   // ---- where each nonzero lands at stage L

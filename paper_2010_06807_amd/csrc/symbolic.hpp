@@ -30,6 +30,9 @@ struct FrontSym {
   int32_t colour = 0;
   std::vector<int32_t> n1;    // row clusters i != s with a block (i, s), ascending
   std::vector<int32_t> cols;  // ancestor column clusters j (excluding s), ascending
+  // index in the stage's `all` set of block (rows[a], cols[b]) at a * |cols'| + b,
+  // rows' = [s, n1...], cols' = [s, cols...]; -1 where the block is absent
+  std::vector<int64_t> blk;
 };
 
 struct IfaceSym {
@@ -53,6 +56,10 @@ struct StageSym {
   std::vector<int32_t> iface_order;    // (colour, cluster) order
   std::vector<int32_t> iface_colour_ptr;
   std::vector<int32_t> remaining;      // clusters of level < k, ascending
+  // merge map of the post-front blocks, in `post` order: index of the block
+  // in this stage's `all` set and of its parent block in stage k-1's `all`
+  // set (-1 at stage 1)
+  std::vector<int64_t> post_all, post_next;
 };
 
 struct Symbolic {
