@@ -238,10 +238,14 @@ spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf,
 
 /* Per-kernel timing (HIP events recorded on the launching stream around every
  * launch) and the algorithmic flops/bytes of those launches.  enable(1, only)
- * clears the table and starts recording every kernel (only == NULL) or just
- * the kernel named `only`; enable(0, NULL) stops.  Kernel names:
+ * clears the table and starts recording every kernel (only == NULL), just
+ * the kernel named `only`, or, when `only` ends in '*', every name with that
+ * prefix; enable(0, NULL) stops.  Kernel names:
  * "front_qr", "scale_qr", "scale_blocks", "sparsify", "copy",
  * "apply_front_fwd", "apply_front_bwd", "apply_iface_fwd", "apply_iface_bwd".
+ * Host phases of the batched driver are recorded the same way (wall time as
+ * the duration, zero work) under names starting with "host_", e.g.
+ * "host_setup", "host_wait_gpu", "host_solve_setup", "host_solve_krylov".
  * Unknown names report zero launches. */
 spaqr_status spaqr_profile_enable(int on, const char* only);
 spaqr_status spaqr_profile_query(const char* kernel, int64_t* launches, double* total_ms,

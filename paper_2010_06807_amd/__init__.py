@@ -379,7 +379,8 @@ def solve_batch(facs, bs, tol=1e-10):
 
 
 def profile_enable(on=True, only=None):
-    """Record per-launch HIP-event timings of every kernel, or only of `only`."""
+    """Record per-launch HIP-event timings of every kernel, or only of `only`
+    (one name, or a prefix ending in '*', e.g. 'host_*' for the host phases)."""
     check(_abi.load().spaqr_profile_enable(1 if on else 0, only.encode() if only else None),
           "spaqr_profile_enable")
 

@@ -9,6 +9,7 @@
 
 #include "engine.hpp"
 #include "pool.hpp"
+#include "profile.hpp"
 
 using namespace spaqr;
 
@@ -248,6 +249,7 @@ spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaq
     }
     // set-up (uploads, column scaling, first pool) of the problems in parallel
     {
+      HostScope hsetup("host_setup");
       const unsigned hc = std::thread::hardware_concurrency();
       HostPool pool(nprob > 1 ? (int)std::min<unsigned>(7, std::min<unsigned>(nprob - 1, hc > 1 ? hc - 1 : 0)) : 0);
       pool.run(nprob, [&](int i) {
@@ -270,7 +272,10 @@ spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaq
       throw;
     }
     batch_driver_free(drv);
-    SPAQR_HIP(hipStreamSynchronize(s));
+    {
+      HostScope hsync("host_final_sync");
+      SPAQR_HIP(hipStreamSynchronize(s));
+    }
     spaqr_status st = SPAQR_OK;
     for (int i = 0; i < nprob; ++i) {
       const int err = hs[i]->e->error();

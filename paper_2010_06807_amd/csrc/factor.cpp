@@ -177,7 +177,6 @@ class Engine final : public EngineBase {
   ~Engine() override {
     dev_free(apply_ws_, s_);
     (void)hipStreamSynchronize(s_);
-    pinned_release(pinned_);
   }
 
   void apply_dev(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs) override;
@@ -207,8 +206,12 @@ class Engine final : public EngineBase {
   void plan_fronts(StagePlan<T>& p);
   void plan_scale(StagePlan<T>& p);
   void plan_sparsify(StagePlan<T>& p);
-  // after the launches: copy the ranks and error flags to the host
-  void readback();
+  // after the launches: the ranks and error flags of the stage, as copies
+  // into a batch-wide buffer from offset base (readback_ints() of them);
+  // finish() reads them at `host` once the stream has passed the copy
+  int readback_ints() const { return (int)S_.st[k_].nclu + 2; }
+  void readback_ops(std::vector<IntCopy>& ops, int32_t base) const;
+  void readback_to(const int* host) { rb_ = host; }
   // after the stream synchronized: sizes and accounting of stage k_, the
   // merge to stage k_ - 1 as launch lists, then k_ <- k_ - 1
   void finish(MergePlan<T>& mp);
@@ -231,8 +234,7 @@ class Engine final : public EngineBase {
   DevArena pools_[2] = {DevArena(size_t(64) << 20), DevArena(size_t(64) << 20)};
   Stager stager_[2];
   int stager_cur_ = 0;
-  PinnedChunk pinned_;            // rank readback buffer
-  int* pinned_ints_ = nullptr;
+  const int* rb_ = nullptr;  // ranks, zero-diagonal flag, zero-column flag of the stage (host)
   int* d_zcol_ = nullptr;  // set by the device column-norm kernel for a zero column
   int* d_flag_ = nullptr;  // zero R_ss diagonal in a front of the current stage
   int* d_rank_ = nullptr;  // current cluster sizes of the current stage
@@ -281,6 +283,7 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   d_zcol_ = persist_.alloc_n<int>(1, s_);
   launch_fill<int>(d_zcol_, 1, 0, s_);
   std::vector<double> dc;
+  HostScope hs_csr("host_setup_csr");
   if (Ad) {
     // values already on the device: copy the CSR (device to device) for the
     // SpMV and compute the column scaling there, in a fixed summation order
@@ -290,15 +293,8 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
     SPAQR_HIP(hipMemcpyAsync(d_rowptr_, Ad->rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s_));
     SPAQR_HIP(hipMemcpyAsync(d_col_, Ad->col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s_));
     SPAQR_HIP(hipMemcpyAsync(d_val_, Ad->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s_));
-    std::vector<int64_t> cptr(n + 1, 0), cidx(nnz);
-    for (int64_t t = 0; t < nnz; ++t) cptr[A->col[t] + 1]++;
-    for (int64_t j = 0; j < n; ++j) cptr[j + 1] += cptr[j];
-    {
-      std::vector<int64_t> pos(cptr.begin(), cptr.end() - 1);
-      for (int64_t t = 0; t < nnz; ++t) cidx[pos[A->col[t]]++] = t;
-    }
-    int64_t* d_cptr = up.upload(work_, cptr, s_);
-    int64_t* d_cidx = up.upload(work_, cidx, s_);
+    int64_t* d_cptr = up.upload(work_, S_.col_ptr, s_);
+    int64_t* d_cidx = up.upload(work_, S_.col_nz, s_);
     d_dc_ = persist_.alloc_n<double>(n, s_);
     launch_colnorm(d_cptr, d_cidx, d_val_, n, d_dc_, d_zcol_, s_);
   } else {
@@ -311,16 +307,16 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
       dc[j] = 1.0 / std::sqrt(cn[j]);
     }
     d_dc_ = up.upload(persist_, dc, s_);
-    std::vector<int64_t> rp(A->rowptr, A->rowptr + n + 1);
-    std::vector<int32_t> ci(A->col, A->col + nnz);
-    std::vector<double> va(A->val, A->val + nnz);
-    d_rowptr_ = up.upload(persist_, rp, s_);
-    d_col_ = up.upload(persist_, ci, s_);
-    d_val_ = up.upload(persist_, va, s_);
+    d_rowptr_ = static_cast<int64_t*>(up.upload_bytes(persist_, A->rowptr, (size_t)(n + 1) * sizeof(int64_t), s_));
+    d_col_ = nnz ? static_cast<int32_t*>(up.upload_bytes(persist_, A->col, (size_t)nnz * sizeof(int32_t), s_))
+                 : persist_.alloc_n<int32_t>(1, s_);
+    d_val_ = nnz ? static_cast<double*>(up.upload_bytes(persist_, A->val, (size_t)nnz * sizeof(double), s_))
+                 : persist_.alloc_n<double>(1, s_);
   }
+  hs_csr.stop();
+  HostScope hs_pool("host_setup_pool");
   // stage-L clusters, slots and pool
   const StageClusters& cl = ord.stages[L];
-  const StageSym& sL = S_.st[L];
   size_.resize(cl.count());
   slot_ptr_.assign(cl.count() + 1, 0);
   slots_.resize(n);
@@ -329,26 +325,16 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
     slot_ptr_[c + 1] = slot_ptr_[c] + size_[c];
     for (int64_t p = cl.start[c]; p < cl.end[c]; ++p) slots_[p] = (int32_t)p;
   }
-  boff_.assign(sL.all.size() + 1, 0);
-  for (int64_t i = 0; i < sL.nclu; ++i)
-    for (int64_t t = sL.all.rowptr[i]; t < sL.all.rowptr[i + 1]; ++t)
-      boff_[t + 1] = boff_[t] + (int64_t)size_[i] * size_[sL.all.col[t]];
+  boff_ = S_.pool_off_L;
   pools_[L & 1].reset();
   pool_ = pools_[L & 1].alloc_n<T>(std::max<int64_t>(1, boff_.back()), s_);
   launch_fill<T>(pool_, boff_.back(), T(0), s_);
   {
-    std::vector<int64_t> dst(nnz);
-    for (int64_t r = 0; r < n; ++r)
-      for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
-        const int64_t b = S_.nz_block[t];
-        const int32_t cj = S_.cluster_of_pos_L[ord.iperm[A->col[t]]];
-        dst[t] = boff_[b] + (int64_t)S_.nz_r[t] * size_[cj] + S_.nz_c[t];
-      }
-    int64_t* d_dst = up.upload(work_, dst, s_);
+    int64_t* d_dst = up.upload(work_, S_.nz_dst, s_);
     launch_scatter_scaled<T>(pool_, d_dst, d_val_, d_col_, d_dc_, nnz, s_);
   }
   k_ = L;
-  pinned_ints_ = nullptr;
+  rb_ = nullptr;
 }
 
 template <typename T>
@@ -717,22 +703,16 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
   ap.ifaces = up.upload(persist_, ai, s_);
   ap.nifaces = (int64_t)ai.size();
   P.form.assign(ai.begin(), ai.begin() + ap.nifaces_small);
-  ap.h_ifaces = std::move(ai);
   st_.s.interfaces_sparsified += (int64_t)ai.size();
+  ap.h_ifaces = std::move(ai);
 }
 
 template <typename T>
-void Engine<T>::readback() {
-  const int64_t nclu = S_.st[k_].nclu;
-  const size_t need = ((size_t)nclu + 2) * sizeof(int);
-  if (pinned_.size < need) {
-    pinned_release(pinned_);
-    pinned_ = pinned_acquire(need);
-    pinned_ints_ = reinterpret_cast<int*>(pinned_.p);
-  }
-  if (nclu) SPAQR_HIP(hipMemcpyAsync(pinned_ints_, d_rank_, nclu * sizeof(int), hipMemcpyDeviceToHost, s_));
-  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu, d_flag_, sizeof(int), hipMemcpyDeviceToHost, s_));
-  SPAQR_HIP(hipMemcpyAsync(pinned_ints_ + nclu + 1, d_zcol_, sizeof(int), hipMemcpyDeviceToHost, s_));
+void Engine<T>::readback_ops(std::vector<IntCopy>& ops, int32_t base) const {
+  const int32_t nclu = (int32_t)S_.st[k_].nclu;
+  ops.push_back({d_rank_, base, nclu});
+  ops.push_back({d_flag_, base + nclu, 1});
+  ops.push_back({d_zcol_, base + nclu + 1, 1});
 }
 
 template <typename T>
@@ -741,14 +721,14 @@ void Engine<T>::finish(MergePlan<T>& mp) {
   const StageSym& ss = S_.st[k];
   const int64_t nclu = ss.nclu;
   StageApply<T>& ap = ap_[k];
-  if (pinned_ints_[nclu + 1] != 0 || pinned_ints_[nclu] != 0) {
+  if (rb_[nclu + 1] != 0 || rb_[nclu] != 0) {
     // recorded, not thrown: the other factorizations of a batch carry on
-    err_ = pinned_ints_[nclu + 1] != 0 ? SPAQR_EINVAL : SPAQR_ESINGULAR;
-    err_msg_ = pinned_ints_[nclu + 1] != 0 ? "A has a zero column" : "a front produced an exactly zero R_ss diagonal";
+    err_ = rb_[nclu + 1] != 0 ? SPAQR_EINVAL : SPAQR_ESINGULAR;
+    err_msg_ = rb_[nclu + 1] != 0 ? "A has a zero column" : "a front produced an exactly zero R_ss diagonal";
     k_ = 0;
     return;
   }
-  st_.stage_sizes[k].assign(pinned_ints_, pinned_ints_ + nclu);
+  st_.stage_sizes[k].assign(rb_, rb_ + nclu);
   if (ss.sparsify) {
     const double eb = sizeof(T);
     std::vector<int32_t> iidx(nclu, -1);
@@ -757,7 +737,7 @@ void Engine<T>::finish(MergePlan<T>& mp) {
     for (size_t t = 0; t < ss.ifaces.size(); ++t) {
       const IfaceSym& I = ss.ifaces[t];
       const int32_t p = I.cluster;
-      const double P = size_[p], r = pinned_ints_[p];
+      const double P = size_[p], r = rb_[p];
       if (P == 0) continue;
       if (P <= 64) {
         // dense operators Q^T U^T and R^{-1} Q
@@ -778,8 +758,8 @@ void Engine<T>::finish(MergePlan<T>& mp) {
       // neighbour of an earlier colour already has its new rank); per step k,
       // dot, update and FP64 tail norm of every live column, plus the reflector
       double m = 0.0;
-      for (int32_t q : I.rowN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
-      for (int32_t q : I.colN) m += ss.ifaces[iidx[q]].colour < I.colour ? pinned_ints_[q] : size_[q];
+      for (int32_t q : I.rowN) m += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
+      for (int32_t q : I.colN) m += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
       sp_flops += 2.0 * P * m;
       for (int kk = 0; kk < (int)r; ++kk) sp_flops += (m - kk - 1) * (6.0 * (P - kk) - 2.0) + 3.0 * (P - kk);
       sp_bytes += (P * m + (r < P ? r * m : 0.0)) * eb;
@@ -855,11 +835,16 @@ struct BatchCtx {
   int cur = 0;
   std::unique_ptr<HostPool> pool;  // per-problem planning of a batch, in parallel
   hipEvent_t ev = nullptr;          // end of the enqueued part of the current stage
+  PinnedChunk rb;                   // ranks and flags of the current stage, all problems
   BatchCtx() = default;
   BatchCtx(const BatchCtx&) = delete;
   BatchCtx& operator=(const BatchCtx&) = delete;
   ~BatchCtx() {
-    if (ev) (void)hipEventDestroy(ev);
+    if (ev) {
+      (void)hipEventSynchronize(ev);
+      (void)hipEventDestroy(ev);
+    }
+    pinned_release(rb);
   }
   void begin() {
     cur ^= 1;
@@ -1330,8 +1315,26 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
       }
   }
   }
-  // ranks back
-  for (Engine<T>* e : es) e->readback();
+  // ranks and flags of every factorization: one gather, one copy back
+  {
+    std::vector<IntCopy> ops;
+    std::vector<int32_t> base(es.size());
+    int32_t tot = 0;
+    for (size_t i = 0; i < es.size(); ++i) {
+      base[i] = tot;
+      es[i]->readback_ops(ops, tot);
+      tot += es[i]->readback_ints();
+    }
+    int32_t* d = wk.alloc_n<int32_t>((size_t)tot, s);
+    launch_gather_ints(ops.data(), (int)ops.size(), d, s);
+    if (bx.rb.size < (size_t)tot * sizeof(int32_t)) {
+      pinned_release(bx.rb);
+      bx.rb = pinned_acquire((size_t)tot * sizeof(int32_t));
+    }
+    int32_t* h = reinterpret_cast<int32_t*>(bx.rb.p);
+    SPAQR_HIP(hipMemcpyAsync(h, d, (size_t)tot * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    for (size_t i = 0; i < es.size(); ++i) es[i]->readback_to(h + base[i]);
+  }
   if (!bx.ev) SPAQR_HIP(hipEventCreateWithFlags(&bx.ev, hipEventDisableTiming));
   SPAQR_HIP(hipEventRecord(bx.ev, s));
 }
@@ -1435,6 +1438,16 @@ class BatchApply {
         pc.push_back({cols[i][r], off[i] + (int64_t)r * Ntot_, es[i]->perm_dev(), es[i]->colscale_dev(), es[i]->n()});
     ncols_ = (int)pc.size();
     lv_.assign(L + 1, Level());
+    // every descriptor list goes up in one staged copy: packed here, the
+    // device pointers set once the region is known
+    std::vector<char> pack;
+    std::vector<std::function<void(char*)>> fix;
+    auto put = [&pack](const void* p, size_t bytes) {
+      const size_t o = (pack.size() + 255) / 256 * 256;
+      pack.resize(o + bytes);
+      std::memcpy(pack.data() + o, p, bytes);
+      return o;
+    };
     for (int k = 1; k <= L; ++k) {
       Level& v = lv_[k];
       std::map<int, std::vector<ApFront<T>>> fwd_by_c_jb;  // key: colour * 64 + jb
@@ -1479,20 +1492,38 @@ class BatchApply {
         v.if_bwd_fac_bytes += a.if_bwd_fac_bytes;
         v.if_vec_bytes += a.if_vec_bytes;
       }
-      for (auto& kv : fwd_by_c_jb)
-        v.fwd.push_back({st_.upload(ar_, kv.second, s_), (int64_t)kv.second.size(), kv.first % 64,
-                         fwd_max_m[kv.first]});
+      for (auto& kv : fwd_by_c_jb) {
+        const size_t o = put(kv.second.data(), kv.second.size() * sizeof(ApFront<T>));
+        const size_t i = v.fwd.size();
+        v.fwd.push_back({nullptr, (int64_t)kv.second.size(), kv.first % 64, fwd_max_m[kv.first]});
+        fix.push_back([&v, i, o](char* b) { v.fwd[i].d = reinterpret_cast<const ApFront<T>*>(b + o); });
+      }
       v.nbwd = (int64_t)bwd.size();
-      v.bwd = st_.upload(ar_, bwd, s_);
+      if (!bwd.empty()) {
+        const size_t o = put(bwd.data(), bwd.size() * sizeof(ApFront<T>));
+        fix.push_back([&v, o](char* b) { v.bwd = reinterpret_cast<const ApFront<T>*>(b + o); });
+      }
       v.nif_dense = (int64_t)dense.size();
       v.nif = v.nif_dense + (int64_t)other.size();
       dense.insert(dense.end(), other.begin(), other.end());
-      v.ifs = st_.upload(ar_, dense, s_);
+      if (!dense.empty()) {
+        const size_t o = put(dense.data(), dense.size() * sizeof(ApIface<T>));
+        fix.push_back([&v, o](char* b) { v.ifs = reinterpret_cast<const ApIface<T>*>(b + o); });
+      }
     }
-    pc_ = st_.upload(ar_, pc, s_);
+    if (!pc.empty()) {
+      const size_t o = put(pc.data(), pc.size() * sizeof(PermCol));
+      fix.push_back([this, o](char* b) { pc_ = reinterpret_cast<const PermCol*>(b + o); });
+    }
+    if (!pack.empty()) {
+      const Stager::Region r = st_.stage(ar_, pack.size(), s_);
+      std::memcpy(r.host, pack.data(), pack.size());
+      st_.send(r, s_);
+      for (auto& f : fix) f(static_cast<char*>(r.dev));
+    }
     X_ = ar_.alloc_n<double>((size_t)Ntot_ * R_, s_);
     SPAQR_HIP(hipMemsetAsync(X_, 0, (size_t)Ntot_ * R_ * sizeof(double), s_));
-    SPAQR_HIP(hipStreamSynchronize(s_));  // staged uploads done
+    // (the staging region is released only after the destructor's sync)
   }
   ~BatchApply() { (void)hipStreamSynchronize(s_); }
 

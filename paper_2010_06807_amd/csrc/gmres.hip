@@ -118,12 +118,30 @@ __global__ void k_zero_cols(double* x, int64_t ldx, int64_t n) {
 unsigned gx(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
 
 // Solve-scoped device buffer from the stream-ordered pool.
+// A pinned host buffer from the recycled pool, returned to it on scope exit
+// once the stream has passed every copy that touches it.
+struct PinnedHost {
+  hipStream_t s;
+  PinnedChunk c;
+  PinnedHost(size_t bytes, hipStream_t st) : s(st), c(pinned_acquire(bytes)) {}
+  ~PinnedHost() {
+    (void)hipStreamSynchronize(s);
+    pinned_release(c);
+  }
+  PinnedHost(const PinnedHost&) = delete;
+  PinnedHost& operator=(const PinnedHost&) = delete;
+};
+
 struct Dev {
   hipStream_t s;
   double* p = nullptr;
   explicit Dev(hipStream_t st) : s(st) {}
   void ensure(size_t n) { p = static_cast<double*>(dev_alloc(std::max<size_t>(1, n) * sizeof(double), s)); }
-  ~Dev() { dev_free(p, s); }
+  void release() {
+    dev_free(p, s);
+    p = nullptr;
+  }
+  ~Dev() { release(); }
 };
 
 }  // namespace
@@ -150,12 +168,14 @@ static void dots(const double* X, int64_t sj, int64_t sc, int J, const double* w
 int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, const double* tol,
                  int restart, int maxit_in, spaqr_solve_info* info) {
   const double t0 = now_ms();
+  HostScope hs_body("host_solve_body");
   hipStream_t s = e.stream();
   const int64_t N = e.n();
   const int m = std::max(1, restart);
   const int maxit = std::max(1, maxit_in);
   const int nblk = (int)((N + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK);
   Dev V(s), Z(s), W(s), part(s), hd(s);
+  HostScope hs_alloc("host_solve_alloc");
   V.ensure((size_t)N * (m + 1) * nrhs);
   // (rows of a column beyond its problem's size, with batched problems, are
   // written by nothing but x += Z y and read by nothing: W and V stay zero there)
@@ -164,20 +184,26 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
   part.ensure((size_t)nblk * (m + 2) * nrhs);
   hd.ensure((size_t)(3 * (m + 2)) * nrhs);
   const int64_t sjV = N, scV = N * (m + 1), sjZ = N, scZ = N * m;
-  double* h1 = hd.p;
-  double* h2 = hd.p + (size_t)(m + 2) * nrhs;
-  double* hn = hd.p + (size_t)2 * (m + 2) * nrhs;
-  std::vector<double> hh1((size_t)(m + 2) * nrhs), hh2((size_t)(m + 2) * nrhs), hhn(nrhs);
+  // Step j leaves its projections (two CGS passes, (j + 1) per column each)
+  // and the new norms side by side at the start of hd, so one copy brings
+  // them to the pinned mirror; y goes up from a pinned region of its own.
+  PinnedHost pin((size_t)(3 * m + 3) * nrhs * sizeof(double), s);
+  hs_alloc.stop();
+  double* hm = reinterpret_cast<double*>(pin.c.p);
+  double* ym = hm + (size_t)(2 * m + 3) * nrhs;
   std::vector<double> bnorm(nrhs), rel(nrhs, 1.0);
   std::vector<int> its(nrhs, 0), done(nrhs, 0);
-  auto D2H = [&](std::vector<double>& dst, const double* src, size_t cnt) {
-    SPAQR_HIP(hipMemcpyAsync(dst.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+  auto D2H = [&](const double* src, size_t cnt) {
+    SPAQR_HIP(hipMemcpyAsync(hm, src, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
   };
   // ||b||
+  double* hn = hd.p;
+  HostScope hs_b("host_solve_bnorm");
   dots(b, 0, ldb, 1, b, ldb, N, nrhs, part.p, hn, s);
-  D2H(hhn, hn, nrhs);
+  D2H(hn, nrhs);
   SPAQR_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < nrhs; ++c) bnorm[c] = std::sqrt(hhn[c]);
+  hs_b.stop();
+  for (int c = 0; c < nrhs; ++c) bnorm[c] = std::sqrt(hm[c]);
   hipLaunchKernelGGL(k_zero_cols, dim3(gx(N), nrhs), dim3(256), 0, s, x, ldx, N);
   // r = b (x0 = 0)
   SPAQR_HIP(hipMemcpy2DAsync(W.p, N * sizeof(double), b, ldb * sizeof(double), N * sizeof(double), nrhs,
@@ -188,12 +214,14 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
   std::vector<int> jend(nrhs, 0), active(nrhs, 0);
   for (;;) {
     // beta = ||r||
+    HostScope hs_r("host_solve_restart");
     dots(W.p, 0, N, 1, W.p, N, N, nrhs, part.p, hn, s);
-    D2H(hhn, hn, nrhs);
+    D2H(hn, nrhs);
     SPAQR_HIP(hipStreamSynchronize(s));
+    hs_r.stop();
     bool any = false;
     for (int c = 0; c < nrhs; ++c) {
-      const double beta = std::sqrt(hhn[c]);
+      const double beta = std::sqrt(hm[c]);
       rel[c] = bnorm[c] > 0 ? beta / bnorm[c] : 0.0;
       done[c] = rel[c] <= tol[c] || bnorm[c] == 0.0;
       active[c] = !done[c] && its[c] < maxit;
@@ -207,8 +235,12 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
     hipLaunchKernelGGL(k_scale_cols, dim3(gx(N), nrhs), dim3(256), 0, s, W.p, N, hn, V.p, scV, N, 1);
     int j = 0;
     for (; j < m; ++j) {
+      HostScope hs_launch("host_solve_launch");
       double* Vj = V.p + (size_t)j * sjV;
       double* Zj = Z.p + (size_t)j * sjZ;
+      double* h1 = hd.p;
+      double* h2 = hd.p + (size_t)(j + 1) * nrhs;
+      double* hj = hd.p + (size_t)2 * (j + 1) * nrhs;
       e.apply_dev(Vj, scV, Zj, scZ, nrhs);
       e.spmv_dev(Zj, scZ, W.p, N, nrhs);
       // CGS2
@@ -216,13 +248,18 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
       hipLaunchKernelGGL(k_gemv_acc, dim3(gx(N), nrhs), dim3(256), 0, s, V.p, sjV, scV, j + 1, h1, -1.0, W.p, N, N);
       dots(V.p, sjV, scV, j + 1, W.p, N, N, nrhs, part.p, h2, s);
       hipLaunchKernelGGL(k_gemv_acc, dim3(gx(N), nrhs), dim3(256), 0, s, V.p, sjV, scV, j + 1, h2, -1.0, W.p, N, N);
-      dots(W.p, 0, N, 1, W.p, N, N, nrhs, part.p, hn, s);
-      hipLaunchKernelGGL(k_scale_cols, dim3(gx(N), nrhs), dim3(256), 0, s, W.p, N, hn, V.p + (size_t)(j + 1) * sjV,
+      dots(W.p, 0, N, 1, W.p, N, N, nrhs, part.p, hj, s);
+      hipLaunchKernelGGL(k_scale_cols, dim3(gx(N), nrhs), dim3(256), 0, s, W.p, N, hj, V.p + (size_t)(j + 1) * sjV,
                          scV, N, 1);
-      D2H(hh1, h1, (size_t)(j + 1) * nrhs);
-      D2H(hh2, h2, (size_t)(j + 1) * nrhs);
-      D2H(hhn, hn, nrhs);
-      SPAQR_HIP(hipStreamSynchronize(s));
+      D2H(hd.p, (size_t)(2 * (j + 1) + 1) * nrhs);
+      hs_launch.stop();
+      {
+        HostScope hs_sync("host_solve_sync");
+        SPAQR_HIP(hipStreamSynchronize(s));
+      }
+      const double* hh1 = hm;
+      const double* hh2 = hm + (size_t)(j + 1) * nrhs;
+      const double* hhn = hm + (size_t)2 * (j + 1) * nrhs;
       bool still = false;
       for (int c = 0; c < nrhs; ++c) {
         if (!active[c]) continue;
@@ -260,8 +297,10 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
       if (!still) break;
     }
     // x += Z y per column
+    HostScope hs_u("host_solve_update");
     const int J = std::min(m, std::max(1, *std::max_element(jend.begin(), jend.end())));
-    std::vector<double> y((size_t)J * nrhs, 0.0);
+    double* y = ym;
+    std::fill(y, y + (size_t)J * nrhs, 0.0);
     for (int c = 0; c < nrhs; ++c) {
       const double* Hc = H.data() + (size_t)c * (m + 1) * m;
       const double* gc = g.data() + (size_t)c * (m + 1);
@@ -271,20 +310,20 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
         y[(size_t)c * J + i] = Hc[i + (size_t)i * (m + 1)] != 0.0 ? sacc / Hc[i + (size_t)i * (m + 1)] : 0.0;
       }
     }
-    SPAQR_HIP(hipMemcpyAsync(h1, y.data(), y.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_gemv_acc, dim3(gx(N), nrhs), dim3(256), 0, s, Z.p, sjZ, scZ, J, h1, 1.0, x, ldx, N);
+    // (the pinned y is rewritten only after the next synchronization)
+    SPAQR_HIP(hipMemcpyAsync(hd.p, y, (size_t)J * nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_gemv_acc, dim3(gx(N), nrhs), dim3(256), 0, s, Z.p, sjZ, scZ, J, hd.p, 1.0, x, ldx, N);
     // r = b - A x
     e.spmv_dev(x, ldx, W.p, N, nrhs);
     hipLaunchKernelGGL(k_sub_from, dim3(gx(N), nrhs), dim3(256), 0, s, b, ldb, W.p, N, N);
-    SPAQR_HIP(hipStreamSynchronize(s));  // y is pageable host memory
     bool more = false;
     for (int c = 0; c < nrhs; ++c) more = more || its[c] < maxit;
     if (!more) {
       dots(W.p, 0, N, 1, W.p, N, N, nrhs, part.p, hn, s);
-      D2H(hhn, hn, nrhs);
+      D2H(hn, nrhs);
       SPAQR_HIP(hipStreamSynchronize(s));
       for (int c = 0; c < nrhs; ++c) {
-        rel[c] = bnorm[c] > 0 ? std::sqrt(hhn[c]) / bnorm[c] : 0.0;
+        rel[c] = bnorm[c] > 0 ? std::sqrt(hm[c]) / bnorm[c] : 0.0;
         done[c] = rel[c] <= tol[c] || bnorm[c] == 0.0;
       }
       break;
@@ -303,6 +342,7 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
     }
   }
   (void)total;
+  hs_body.stop();
   return status;
 }
 
@@ -330,6 +370,7 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
     maxit = std::max(maxit, es[i]->opt_maxit());
     tc.insert(tc.end(), (size_t)nrhs[i], tol[i]);
   }
+  HostScope hs_in("host_solve_in");
   Dev B(s), X(s);
   B.ensure((size_t)N * C);
   X.ensure((size_t)N * C);
@@ -341,7 +382,12 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
                                n * sizeof(double), nrhs[i], hipMemcpyDeviceToDevice, s));
   }
   std::vector<spaqr_solve_info> inf((size_t)C);
-  fgmres_solve(*op, B.p, N, X.p, N, C, tc.data(), restart, maxit, inf.data());
+  hs_in.stop();
+  {
+    HostScope hs_f("host_solve_fgmres");
+    fgmres_solve(*op, B.p, N, X.p, N, C, tc.data(), restart, maxit, inf.data());
+  }
+  HostScope hs_out("host_solve_out");
   int st = SPAQR_OK;
   if (status) status->assign(np, SPAQR_OK);
   for (size_t i = 0; i < np; ++i) {
@@ -355,6 +401,12 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
       }
   }
   SPAQR_HIP(hipStreamSynchronize(s));
+  hs_out.stop();
+  {
+    HostScope hs_free("host_solve_free");
+    X.release();
+    B.release();
+  }
   if (info) std::copy(inf.begin(), inf.end(), info);
   return st;
 }

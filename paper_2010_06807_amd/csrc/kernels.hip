@@ -2364,6 +2364,20 @@ __global__ void k_gather_perm(double* xhat, const double* __restrict__ b, int64_
   }
 }
 
+// Small integer arrays of several buffers into one (the ranks and error
+// flags of every factorization of a batch, so that one copy brings them to
+// the host).  One workgroup per operation; the list travels as a kernel
+// argument.
+constexpr int kIntCopyMax = 64;
+struct IntCopyList {
+  IntCopy op[kIntCopyMax];
+};
+
+__global__ void k_gather_ints(IntCopyList L, int32_t* __restrict__ out) {
+  const IntCopy c = L.op[blockIdx.x];
+  for (int i = threadIdx.x; i < c.n; i += blockDim.x) out[c.dst + i] = c.src[i];
+}
+
 __global__ void k_gather_cols(double* xhat, const double* __restrict__ b, int64_t ldb,
                               const PermCol* __restrict__ pc) {
   const int j = blockIdx.y;
@@ -2991,6 +3005,16 @@ void launch_gather_cols(double* xhat, const double* b, int64_t ldb, const PermCo
   const unsigned gxn = (unsigned)std::min<int64_t>(1024, (max_n + 255) / 256);
   hipLaunchKernelGGL(k_gather_cols, dim3(gxn, (unsigned)ncols), dim3(256), 0, s, xhat, b, ldb, pc);
   check_launch("k_gather_cols");
+}
+
+void launch_gather_ints(const IntCopy* ops, int nops, int32_t* out, hipStream_t s) {
+  for (int i0 = 0; i0 < nops; i0 += kIntCopyMax) {
+    IntCopyList L{};
+    const int n = std::min(kIntCopyMax, nops - i0);
+    for (int i = 0; i < n; ++i) L.op[i] = ops[i0 + i];
+    hipLaunchKernelGGL(k_gather_ints, dim3((unsigned)n), dim3(256), 0, s, L, out);
+    check_launch("k_gather_ints");
+  }
 }
 
 void launch_scatter_cols(double* x, int64_t ldx, const double* xhat, const PermCol* pc, int ncols, int64_t max_n,

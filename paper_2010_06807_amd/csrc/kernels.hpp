@@ -259,6 +259,12 @@ struct PermCol {
   const double* dc;
   int64_t n;
 };
+// out[op.dst + i] = op.src[i] for i < op.n, for every op of the list
+struct IntCopy {
+  const int32_t* src;
+  int32_t dst, n;
+};
+void launch_gather_ints(const IntCopy* ops, int nops, int32_t* out, hipStream_t s);
 // xhat[pc[j].xoff + i] = b[pc[j].perm[i] + pc[j].col*ldb] for every j < ncols
 void launch_gather_cols(double* xhat, const double* b, int64_t ldb, const PermCol* pc, int ncols, int64_t max_n,
                         hipStream_t s);

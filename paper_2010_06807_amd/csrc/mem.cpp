@@ -1,8 +1,10 @@
 #include "mem.hpp"
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <set>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -13,6 +15,32 @@ namespace {
 std::mutex g_mu;
 std::set<int> g_ready;
 std::vector<PinnedChunk> g_free;
+
+// Device blocks freed by the library are kept for reuse instead of going
+// back to the stream-ordered pool: returning a block there can block the
+// host for milliseconds once many blocks are live.  A freed block is handed
+// out again only on the stream it was freed on, so stream order keeps the
+// reuse after every earlier use.
+struct Block {
+  void* p;
+  hipStream_t s;
+};
+std::mutex g_dmu;
+std::multimap<size_t, Block> g_cache;         // free blocks by size
+std::unordered_map<void*, size_t> g_size;     // size of every live block
+
+size_t round_block(size_t b) {
+  if (b <= (size_t(1) << 20)) return (b + 4095) & ~size_t(4095);
+  return (b + (size_t(2) << 20) - 1) & ~((size_t(2) << 20) - 1);
+}
+
+// free blocks back to the pool (caller holds g_dmu); the memory is usable
+// by every stream once the device has synchronized
+void flush_cache() {
+  for (auto& kv : g_cache) (void)hipFreeAsync(kv.second.p, kv.second.s);
+  g_cache.clear();
+  (void)hipDeviceSynchronize();
+}
 }  // namespace
 
 void mem_setup(hipStream_t) {
@@ -29,14 +57,42 @@ void mem_setup(hipStream_t) {
 }
 
 void* dev_alloc(size_t bytes, hipStream_t s) {
+  const size_t sz = round_block(bytes ? bytes : 256);
+  std::lock_guard<std::mutex> lk(g_dmu);
+  // best fit on the same stream, wasting at most a quarter of the block
+  for (auto it = g_cache.lower_bound(sz); it != g_cache.end() && it->first - sz <= it->first / 4; ++it)
+    if (it->second.s == s) {
+      void* p = it->second.p;
+      g_size[p] = it->first;
+      g_cache.erase(it);
+      return p;
+    }
   void* p = nullptr;
-  const hipError_t e = hipMallocAsync(&p, bytes ? bytes : 256, s);
-  if (e != hipSuccess || !p) throw Error(SPAQR_ENOMEM, "device allocation failed");
+  hipError_t e = hipMallocAsync(&p, sz, s);
+  if ((e != hipSuccess || !p) && !g_cache.empty()) {
+    (void)hipGetLastError();
+    flush_cache();
+    p = nullptr;
+    e = hipMallocAsync(&p, sz, s);
+  }
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(SPAQR_ENOMEM, "device allocation failed");
+  }
+  g_size[p] = sz;
   return p;
 }
 
 void dev_free(void* p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_dmu);
+  auto it = g_size.find(p);
+  if (it == g_size.end()) {
+    (void)hipFreeAsync(p, s);
+    return;
+  }
+  g_cache.insert({it->second, Block{p, s}});
+  g_size.erase(it);
 }
 
 PinnedChunk pinned_acquire(size_t bytes) {

@@ -1,8 +1,11 @@
 // Device and pinned-host memory helpers.  Device memory comes from the
-// stream-ordered allocator with a release threshold high enough that freed
-// blocks are reused instead of being returned to the driver; pinned staging
-// chunks are recycled through a process-wide free list (allocating pinned
-// memory costs milliseconds).
+// stream-ordered allocator with a release threshold high enough that the
+// pool keeps what it maps; blocks the library frees stay in its own cache
+// and are reused on the stream they were freed on (the pool's own free path
+// can stall the host for milliseconds).  The cache goes back to the pool
+// only when an allocation fails.  Streams are expected to outlive the
+// blocks freed on them.  Pinned staging chunks are recycled through a
+// process-wide free list (allocating pinned memory costs milliseconds).
 #pragma once
 
 #include <hip/hip_runtime.h>

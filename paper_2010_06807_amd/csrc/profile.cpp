@@ -1,6 +1,7 @@
 #include "profile.hpp"
 
 #include <map>
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -33,7 +34,13 @@ void resolve(Rec& r) {
 }  // namespace
 
 bool prof_on() { return g_on; }
-bool prof_wants(const char* name) { return g_on && (g_only.empty() || g_only == name); }
+// `only` names one timer, or with a trailing '*' every timer of that prefix
+bool prof_wants(const char* name) {
+  if (!g_on) return false;
+  if (g_only.empty()) return true;
+  if (g_only.back() == '*') return std::strncmp(name, g_only.c_str(), g_only.size() - 1) == 0;
+  return g_only == name;
+}
 
 void prof_record(const char* name, hipStream_t, hipEvent_t a, hipEvent_t b, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);

@@ -18,8 +18,11 @@ double now_ms();
 
 struct HostScope {
   explicit HostScope(const char* name) : name_(name), live_(prof_wants(name)), t0_(live_ ? now_ms() : 0.0) {}
-  ~HostScope() {
+  ~HostScope() { stop(); }
+  // records now instead of at the end of the scope
+  void stop() {
     if (live_) prof_host(name_, now_ms() - t0_);
+    live_ = false;
   }
   HostScope(const HostScope&) = delete;
   HostScope& operator=(const HostScope&) = delete;

@@ -309,21 +309,32 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
       }
   }
 
-  // ---- where each nonzero lands at stage L
+  // ---- stage-L block storage and where each nonzero lands in it
   const StageSym& sL = S->st[L];
-  S->nz_block.resize(A->nnz);
-  S->nz_r.resize(A->nnz);
-  S->nz_c.resize(A->nnz);
+  S->pool_off_L.assign(sL.all.size() + 1, 0);
+  for (int64_t i = 0; i < sL.nclu; ++i)
+    for (int64_t t = sL.all.rowptr[i]; t < sL.all.rowptr[i + 1]; ++t)
+      S->pool_off_L[t + 1] = S->pool_off_L[t] + (cl.end[i] - cl.start[i]) *
+                                                    (cl.end[sL.all.col[t]] - cl.start[sL.all.col[t]]);
+  S->nz_dst.resize(A->nnz);
   for (int64_t r = 0; r < n; ++r) {
     int64_t pr = ord.iperm[r];
     int32_t ci = S->cluster_of_pos_L[pr];
     for (int64_t t = A->rowptr[r]; t < A->rowptr[r + 1]; ++t) {
       int64_t pc = ord.iperm[A->col[t]];
       int32_t cj = S->cluster_of_pos_L[pc];
-      S->nz_block[t] = sL.all.find(ci, cj);
-      S->nz_r[t] = (int32_t)(pr - cl.start[ci]);
-      S->nz_c[t] = (int32_t)(pc - cl.start[cj]);
+      const int64_t b = sL.all.find(ci, cj);
+      S->nz_dst[t] = S->pool_off_L[b] + (pr - cl.start[ci]) * (cl.end[cj] - cl.start[cj]) + (pc - cl.start[cj]);
     }
+  }
+  // ---- the nonzeros by column
+  S->col_ptr.assign(n + 1, 0);
+  S->col_nz.resize(A->nnz);
+  for (int64_t t = 0; t < A->nnz; ++t) S->col_ptr[A->col[t] + 1]++;
+  for (int64_t j = 0; j < n; ++j) S->col_ptr[j + 1] += S->col_ptr[j];
+  {
+    std::vector<int64_t> pos(S->col_ptr.begin(), S->col_ptr.end() - 1);
+    for (int64_t t = 0; t < A->nnz; ++t) S->col_nz[pos[A->col[t]]++] = t;
   }
   guard.release();
   return S;

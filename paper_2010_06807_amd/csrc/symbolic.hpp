@@ -67,10 +67,15 @@ struct Symbolic {
   int L = 0, skip = 2;
   int64_t n = 0, nnz = 0;
   std::vector<StageSym> st;    // index k = 1..L
-  // stage-L position of every nonzero of A (CSR order): block index in
-  // st[L].all and the row/column offset inside the block
-  std::vector<int64_t> nz_block;
-  std::vector<int32_t> nz_r, nz_c;
+  // stage-L block storage: block t of st[L].all (row-major, its clusters'
+  // sizes) starts at pool_off_L[t] of one pool of pool_off_L.back() entries
+  std::vector<int64_t> pool_off_L;
+  // where every nonzero of A (CSR order) lands in that pool
+  std::vector<int64_t> nz_dst;
+  // the nonzeros of A by column (column c: entries col_nz[col_ptr[c] ..
+  // col_ptr[c + 1]) of CSR order, rows ascending), for column norms summed
+  // in a fixed order
+  std::vector<int64_t> col_ptr, col_nz;
   std::vector<int32_t> cluster_of_pos_L;  // stage-L cluster of each permuted index
 };
 

@@ -116,6 +116,8 @@ def test_fp32_factor_fp64_gmres(dims, L, beta, eps):
     F = _oracle(A, dims, L, eps)
     fac = P.factor(A, P.order_grid(dims, L), eps=eps, precision=32)
     _ranks_agree(fac, F, L, 1 if eps >= 1e-4 else 10 ** 6)
+    # every scaled interface of every sparsified stage is counted once
+    assert fac.stats()["interfaces_sparsified"] == sum(1 for op in F.ops if op[0] == "scale")
     b = make_rhs(N, 1, seed=3)
     it_o, _ = _oracle_its(A, F, b[:, 0])
     x, info = fac.solve(_dev(b), tol=1e-10)
