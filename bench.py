@@ -217,7 +217,9 @@ def main():
     dAs = [P.DeviceCSR(p["A"], dev) for p in probs]
     bs = [torch.from_numpy(make_rhs(N, 1, seed=i)).to(dev) for i in range(B)]
     torch.cuda.synchronize()
-    pool = ThreadPoolExecutor(max_workers=min(B, 8))
+    # one analysis per host core (16 per GPU), so that a batch's analyses
+    # fit in the previous batch's solve
+    pool = ThreadPoolExecutor(max_workers=min(B, 16))
 
     phases = {"host_order_analyze": [], "factor": [], "solve": []}
 
@@ -245,7 +247,8 @@ def main():
         facs = P.factor_batch([p["A"] for p in probs], syms, dAs, eps=args.eps, precision=precision)
         t2 = time.perf_counter()
         # the next batch's analyses overlap this batch's solve (the FGMRES
-        # loop leaves the host cores idle, the factorization's planning does not)
+        # loop leaves the host cores idle, the factorization's planning does
+        # not); started earlier they would add a step to every latency
         nxt = (prep_batch(), time.perf_counter()) if next_prep else None
         xs, infos = P.solve_batch(facs, bs, tol=args.tol)
         t3 = time.perf_counter()

@@ -61,11 +61,27 @@ class Stager {
   };
   Region stage(DevArena& arena, size_t bytes, hipStream_t s);
   void send(const Region& r, hipStream_t s);
-  void reset() { cur_ = 0; off_ = 0; }
+  // like upload(), but the copy is held back and merged with the next
+  // held-back upload when both are contiguous on the host and the device
+  // (consecutive uploads into one arena chunk): flush() must be called
+  // before anything on the stream reads the data
+  template <typename X>
+  X* upload_held(DevArena& arena, const std::vector<X>& v, hipStream_t s) {
+    if (v.empty()) return nullptr;
+    return static_cast<X*>(upload_held_bytes(arena, v.data(), v.size() * sizeof(X), s));
+  }
+  void* upload_held_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s);
+  void flush(hipStream_t s);
+  void reset() {
+    cur_ = 0;
+    off_ = 0;
+    held_ = Region{nullptr, nullptr, 0};
+  }
 
  private:
   std::vector<PinnedChunk> chunks_;
   size_t cur_ = 0, off_ = 0;
+  Region held_{nullptr, nullptr, 0};
 };
 
 template <typename T>

@@ -98,6 +98,28 @@ void Stager::send(const Region& r, hipStream_t s) {
   if (r.bytes) SPAQR_HIP(hipMemcpyAsync(r.dev, r.host, r.bytes, hipMemcpyHostToDevice, s));
 }
 
+void* Stager::upload_held_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
+  const Region r = stage(arena, bytes, s);
+  std::memcpy(r.host, src, bytes);
+  if (held_.bytes) {
+    // both sides hand out 256-byte granules, so the held region ends where
+    // its padded size ends
+    const size_t pad = (held_.bytes + 255) & ~size_t(255);
+    if (static_cast<char*>(held_.host) + pad == r.host && static_cast<char*>(held_.dev) + pad == r.dev) {
+      held_.bytes = pad + bytes;
+      return r.dev;
+    }
+    flush(s);
+  }
+  held_ = r;
+  return r.dev;
+}
+
+void Stager::flush(hipStream_t s) {
+  if (held_.bytes) send(held_, s);
+  held_ = Region{nullptr, nullptr, 0};
+}
+
 void* Stager::upload_bytes(DevArena& arena, const void* src, size_t bytes, hipStream_t s) {
   const Region r = stage(arena, bytes, s);
   std::memcpy(r.host, src, bytes);
@@ -510,13 +532,13 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
       ap.fwd_vec_bytes.push_back(fvb);
       ap.fwd_flops.push_back(ffl);
     }
-    int32_t* drs = up.upload(persist_, rs, s_);
-    int32_t* dcs = up.upload(persist_, cs, s_);
+    int32_t* drs = up.upload_held(persist_, rs, s_);
+    int32_t* dcs = up.upload_held(persist_, cs, s_);
     for (size_t t = 0; t < af.size(); ++t) {
       af[t].rows = drs + rs_off[t];
       af[t].cols = dcs ? dcs + cs_off[t] : nullptr;
     }
-    ap.fronts = up.upload(persist_, af, s_);
+    ap.fronts = up.upload_held(persist_, af, s_);
     ap.nfronts = (int64_t)af.size();
     ap.h_fronts = std::move(af);
   }
@@ -524,8 +546,9 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
   {
     std::vector<int> r0(size_.begin(), size_.end());
     r0.push_back(0);
-    d_rank_ = up.upload(persist_, r0, s_);
+    d_rank_ = up.upload_held(persist_, r0, s_);
   }
+  up.flush(s_);
 }
 
 template <typename T>
@@ -695,12 +718,13 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
                   FLAGS + t, mf, mb, Pn, 0});
     ap.max_p = std::max(ap.max_p, (int)Pn);
   }
-  int32_t* dsl = up.upload(persist_, sl, s_);
+  int32_t* dsl = up.upload_held(persist_, sl, s_);
   for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
   // interfaces of at most 64 unknowns first (dense-operator apply)
   std::stable_partition(ai.begin(), ai.end(), [](const ApIface<T>& q) { return q.P <= 64; });
   for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= 64 ? 1 : 0;
-  ap.ifaces = up.upload(persist_, ai, s_);
+  ap.ifaces = up.upload_held(persist_, ai, s_);
+  up.flush(s_);
   ap.nifaces = (int64_t)ai.size();
   P.form.assign(ai.begin(), ai.begin() + ap.nifaces_small);
   st_.s.interfaces_sparsified += (int64_t)ai.size();
