@@ -243,6 +243,10 @@ spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf,
  * prefix; enable(0, NULL) stops.  Kernel names:
  * "front_qr", "scale_qr", "scale_blocks", "sparsify", "copy",
  * "apply_front_fwd", "apply_front_bwd", "apply_iface_fwd", "apply_iface_bwd".
+ * Block copies are recorded under "copy" and under their role
+ * ("copy_front_gather", "copy_front_scatter", "copy_front_pack",
+ * "copy_scale_gather", "copy_scale_pack", "copy_merge"), the role records
+ * counting tiles in place of flops.
  * Host phases of the batched driver are recorded the same way (wall time as
  * the duration, zero work) under names starting with "host_", e.g.
  * "host_setup", "host_wait_gpu", "host_solve_setup", "host_solve_krylov".

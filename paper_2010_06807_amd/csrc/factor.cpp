@@ -960,18 +960,37 @@ static X* upload_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get g
 }
 
 // transpose: the lists hold packs (mode 1) only, else plain copies only
+// bytes a list of copies must move (read and write, or write for a fill)
+template <typename T>
+static double copy_bytes(const std::vector<CopyTile<T>>& tiles) {
+  double b = 0.0;
+  for (const CopyTile<T>& c : tiles) b += (c.src ? 2.0 : 1.0) * c.rows * (double)c.cols * sizeof(T);
+  return b;
+}
+
+// (profiled under "copy" and under the name of the copy's role)
 template <typename T, typename Get>
-static void copy_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, bool transpose, hipStream_t s) {
+static void copy_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get get, bool transpose, hipStream_t s,
+                        const char* role) {
   int64_t n = 0;
   CopyTile<T>* d = upload_concat<CopyTile<T>>(bx, up, wk, ne, get, s, &n);
-  if (n > 0) launch_copy<T>(d, n, transpose, s);
+  if (n <= 0) return;
+  double by = 0.0;
+  if (prof_wants("copy") || prof_wants(role))
+    for (size_t e = 0; e < ne; ++e) by += copy_bytes<T>(get(e));
+  ProfScope ps("copy", s, 0.0, by);
+  ProfScope pr(role, s, (double)n, by);
+  launch_copy<T>(d, n, transpose, s);
 }
 
 template <typename T>
 static void copy_batch(const std::vector<CopyTile<T>>& tiles, bool transpose, Stager& up, DevArena& wk,
-                       hipStream_t s) {
+                       hipStream_t s, const char* role) {
   if (tiles.empty()) return;
   CopyTile<T>* d = up.upload(wk, tiles, s);
+  const double by = prof_wants("copy") || prof_wants(role) ? copy_bytes<T>(tiles) : 0.0;
+  ProfScope ps("copy", s, 0.0, by);
+  ProfScope pr(role, s, (double)tiles.size(), by);
   launch_copy<T>(d, (int64_t)tiles.size(), transpose, s);
 }
 
@@ -1163,7 +1182,7 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
                    [&](int e) -> const std::vector<CopyTile<T>>& {
                      return c < pl[e].fronts.size() ? pl[e].fronts[c].gather : none;
                    },
-                   false, s);
+                   false, s, "copy_front_gather");
     {
       HostScope hs("host_launch_qr");
       launch_qr_groups<T>(qparts, "front_qr", fl, by, up, wk, s);
@@ -1195,9 +1214,10 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
                    [&](int e) -> const std::vector<CopyTile<T>>& {
                      return c < pl[e].fronts.size() ? pl[e].fronts[c].scatter : none;
                    },
-                   false, s);
+                   false, s, "copy_front_scatter");
   }
-  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, true, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, true, s,
+                 "copy_front_pack");
   }
   // block-diagonal scaling
   {
@@ -1249,9 +1269,9 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
         sby += 2.0 * b.rows * (double)b.cols * sizeof(T);
       }
     }
-    copy_batch(g, false, up, wk, s);
+    copy_batch(g, false, up, wk, s, "copy_scale_gather");
     launch_qr_groups<T>(qparts, "scale_qr", qfl, qby, up, wk, s);
-    copy_batch(pk, true, up, wk, s);
+    copy_batch(pk, true, up, wk, s, "copy_scale_pack");
     if (!fac.empty()) {
       ScaleFac<T>* dfac = up.upload(wk, fac, s);
       ProfScope ps("scale_blocks", s, sfl, sby);
@@ -1381,7 +1401,8 @@ void stage_finish(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   std::vector<ZeroOp> z;
   for (auto& m : mp) append(z, m.zero);
   launch_zero_ops(z, up, wk, s);
-  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, false, s);
+  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, false, s,
+                 "copy_merge");
 }
 
 template <typename T>

@@ -181,25 +181,97 @@ __device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* 
 }
 
 // ---------------------------------------------------------------- kernels
-// Plain copies (mode 0), one workgroup per tile: lanes run along the rows
-// (rounded up to a power of two of at most 64), the remaining threads take
-// successive rows, so indices come from shifts and masks only.
+// Plain copies (mode 0).  A tile is walked as one flat sequence of rows x
+// cols elements so that no lane idles on short rows, with 16-byte accesses
+// whenever the row length, both strides and both addresses allow them.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles) {
-  const CopyTile<T> c = tiles[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int inner = c.cols, outer = c.rows;
-  int lg = 0;
-  while ((1 << lg) < inner && lg < 6) ++lg;
-  const int iw = 1 << lg, ostep = NT >> lg, ti = tid & (iw - 1), to = tid >> lg;
-  for (int r = to; r < outer; r += ostep) {
-    T* d = c.dst + (int64_t)r * c.ldd;
-    if (c.src) {
-      const T* sr = c.src + (int64_t)r * c.lds;
-      for (int q = ti; q < inner; q += iw) d[q] = sr[q];
-    } else {
-      for (int q = ti; q < inner; q += iw) d[q] = T(0);
+struct Wide16;
+template <>
+struct Wide16<float> {
+  using type = float4;
+  static constexpr int N = 4;
+};
+template <>
+struct Wide16<double> {
+  using type = double2;
+  static constexpr int N = 2;
+};
+
+// rows x cols elements (row strides lds, ldd) by NTH threads (thread t of
+// them): element e of the tile goes to thread e mod NTH, its row and column
+// advanced incrementally; src == nullptr writes zeros
+template <int NTH, typename E>
+__device__ __forceinline__ void copy_tile(const E* __restrict__ src, E* __restrict__ dst, int rows, int cols,
+                                          int64_t lds, int64_t ldd, int t) {
+  const int dr = NTH / cols, dq = NTH - dr * cols;
+  int r = t / cols, q = t - r * cols;
+  auto next = [&]() {
+    q += dq;
+    r += dr;
+    if (q >= cols) {
+      q -= cols;
+      ++r;
     }
+  };
+  if (src) {
+    // four elements in flight per thread (the first always in range)
+    while (r < rows) {
+      const int r0 = r, q0 = q;
+      next();
+      const int r1 = r, q1 = q;
+      next();
+      const int r2 = r, q2 = q;
+      next();
+      const int r3 = r, q3 = q;
+      next();
+      const E v0 = src[(int64_t)r0 * lds + q0];
+      E v1{}, v2{}, v3{};
+      if (r1 < rows) v1 = src[(int64_t)r1 * lds + q1];
+      if (r2 < rows) v2 = src[(int64_t)r2 * lds + q2];
+      if (r3 < rows) v3 = src[(int64_t)r3 * lds + q3];
+      dst[(int64_t)r0 * ldd + q0] = v0;
+      if (r1 < rows) dst[(int64_t)r1 * ldd + q1] = v1;
+      if (r2 < rows) dst[(int64_t)r2 * ldd + q2] = v2;
+      if (r3 < rows) dst[(int64_t)r3 * ldd + q3] = v3;
+    }
+  } else {
+    for (; r < rows; next()) dst[(int64_t)r * ldd + q] = E{};
+  }
+}
+
+template <int NTH, typename T>
+__device__ __forceinline__ void copy_tile_any(const CopyTile<T> c, int t) {
+  using W = Wide16<T>;
+  constexpr int N = W::N;
+  const bool wide = c.cols % N == 0 && c.ldd % N == 0 && (reinterpret_cast<uintptr_t>(c.dst) & 15) == 0 &&
+                    (!c.src || (c.lds % N == 0 && (reinterpret_cast<uintptr_t>(c.src) & 15) == 0));
+  if (wide)
+    copy_tile<NTH>(reinterpret_cast<const typename W::type*>(c.src), reinterpret_cast<typename W::type*>(c.dst),
+                   c.rows, c.cols / N, c.lds / N, c.ldd / N, t);
+  else
+    copy_tile<NTH>(c.src, c.dst, c.rows, c.cols, c.lds, c.ldd, t);
+}
+
+// Tiles kCopyTiles at a time per workgroup: a tile of at most
+// kCopySmallBytes is copied by one wavefront, a larger one by the whole
+// workgroup (no barrier is needed: the tiles of a launch never overlap).
+constexpr int kCopyTiles = NT / 64;
+constexpr int kCopySmallBytes = 16384;
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ tiles, int64_t n) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t t0 = (int64_t)blockIdx.x * kCopyTiles;
+  const int64_t mine = t0 + wv;
+  if (mine < n) {
+    const CopyTile<T> c = tiles[mine];
+    if (c.rows > 0 && c.cols > 0 && (int64_t)c.rows * c.cols * (int64_t)sizeof(T) <= kCopySmallBytes)
+      copy_tile_any<64>(c, lane);
+  }
+  for (int w = 0; w < kCopyTiles && t0 + w < n; ++w) {
+    const CopyTile<T> c = tiles[t0 + w];
+    if (c.rows > 0 && c.cols > 0 && (int64_t)c.rows * c.cols * (int64_t)sizeof(T) > kCopySmallBytes)
+      copy_tile_any<NT>(c, (int)threadIdx.x);
   }
 }
 
@@ -2471,7 +2543,8 @@ void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipSt
     hipLaunchKernelGGL(k_copy_t<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
     check_launch("k_copy_t");
   } else {
-    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
+    hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((ntiles + kCopyTiles - 1) / kCopyTiles)), dim3(NT), 0, s, tiles,
+                       ntiles);
     check_launch("k_copy");
   }
 }
