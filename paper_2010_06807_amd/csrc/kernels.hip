@@ -836,7 +836,7 @@ __global__ void __launch_bounds__(NT) k_scale_small(const ScaleBlk<T>* __restric
   T* Tm = Vs + (size_t)max_rows * (JB + 1);           // JB x JB
   T* W = Tm + JB * JB;                                // JB x max_cols
   T* U = W + (size_t)JB * max_cols;                   // JB x max_cols
-  T* Rs = U + (size_t)JB * max_cols;                  // max_cols x LB
+  T* Rs = W;  // max_cols x LB, over W and U: the left factor is done with them by then
   for (int q = tid; q < rows * cols; q += NT) {
     const int r = q / cols, c = q - r * cols;
     Bs[r * LB + c] = B[q];
@@ -2707,8 +2707,8 @@ void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, h
 
 static size_t scale_small_lds(int max_rows, int max_cols, int jb, int eb) {
   const size_t lb = (size_t)max_cols + 1;
-  return ((size_t)max_rows * lb + (size_t)max_rows * (jb + 1) + (size_t)jb * jb + 2 * (size_t)jb * max_cols +
-          (size_t)max_cols * lb) * eb;
+  return ((size_t)max_rows * lb + (size_t)max_rows * (jb + 1) + (size_t)jb * jb +
+          std::max(2 * (size_t)jb * max_cols, (size_t)max_cols * lb)) * eb;
 }
 
 template <typename T>
