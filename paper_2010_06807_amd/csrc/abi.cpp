@@ -250,8 +250,7 @@ spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaq
     // set-up (uploads, column scaling, first pool) of the problems in parallel
     {
       HostScope hsetup("host_setup");
-      const unsigned hc = std::thread::hardware_concurrency();
-      HostPool pool(nprob > 1 ? (int)std::min<unsigned>(7, std::min<unsigned>(nprob - 1, hc > 1 ? hc - 1 : 0)) : 0);
+      HostPool pool(std::min(nprob - 1, host_pool_threads()));
       pool.run(nprob, [&](int i) {
         hs[i]->e = make_engine_deferred(A[i], Ad ? Ad[i] : nullptr, sym[i]->s, o, s);
       });

@@ -463,10 +463,10 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
           const int32_t j = b == 0 ? F.cluster : F.cols[b - 1];
           if (size_[i] > 0 && size_[j] > 0) {
             T* blkp = brow[b] < 0 ? nullptr : pool_ + boff_[brow[b]];
-            fc.gather.push_back({blkp, Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw, 0, 0});
+            fc.gather.push_back({blkp, Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw});
             if (a > 0 && b > 0) {
               SPAQR_REQUIRE(blkp != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
-              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, blkp, size_[i], size_[j], ldw, size_[j], 0, 0});
+              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, blkp, size_[i], size_[j], ldw, size_[j]});
             }
           }
           co += size_[j];
@@ -502,8 +502,8 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         const int32_t m = fm[f], n = fn[f], nc = fnc[f];
         if (n == 0) continue;
         T* Wf = W + ws_off[f];
-        P.pack.push_back({Wf, VR + vr_off[f], m, n, fld[f], m, 1, 0});
-        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, fld[f], n, 1, 0});
+        P.pack.push_back({Wf, VR + vr_off[f], m, n, fld[f], m});
+        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, fld[f], n});
         std::vector<int32_t> rows{F.cluster};
         rows.insert(rows.end(), F.n1.begin(), F.n1.end());
         rs_off.push_back((int64_t)rs.size());
@@ -612,9 +612,9 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
     if (Pn == 0) continue;
     T* src = blk(p, p);
     SPAQR_REQUIRE(src != nullptr, SPAQR_EINVAL, "interface without a diagonal block");
-    P.sgather.push_back({src, SW + sw_off[t], Pn, Pn, Pn, Pld, 0, 0});
+    P.sgather.push_back({src, SW + sw_off[t], Pn, Pn, Pn, Pld});
     P.sqr.push_back({SW + sw_off[t], TAUU + p_off[t], TPAN + t_off[t], FLAGS + t, Pn, Pn, Pn, Pld});
-    P.spack.push_back({SW + sw_off[t], VRU + u_off[t], Pn, Pn, Pld, Pn, 1, 0});
+    P.spack.push_back({SW + sw_off[t], VRU + u_off[t], Pn, Pn, Pld, Pn});
   }
   for (int64_t i = 0; i < nclu; ++i)
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
@@ -836,7 +836,7 @@ void Engine<T>::finish(MergePlan<T>& mp) {
       SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
       const int64_t b = ss.post_all[u];
       mp.tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Qc] + off[j], rank[i], rank[j],
-                          size_[j], size2[Qc], 0, 0});
+                          size_[j], size2[Qc]});
     }
   pool_ = pool2;
   boff_.swap(boff2);
@@ -877,8 +877,7 @@ struct BatchCtx {
   }
   void each(size_t n, const std::function<void(int)>& fn) {
     if (n > 1 && !pool) {
-      const unsigned hc = std::thread::hardware_concurrency();
-      pool.reset(new HostPool((int)std::min<unsigned>(7, hc > 1 ? hc - 1 : 0)));
+      pool.reset(new HostPool(host_pool_threads()));
     }
     if (pool) pool->run((int)n, fn);
     else
@@ -959,7 +958,7 @@ static X* upload_concat(BatchCtx& bx, Stager& up, DevArena& wk, size_t ne, Get g
   return static_cast<X*>(r.dev);
 }
 
-// transpose: the lists hold packs (mode 1) only, else plain copies only
+// transpose: the lists hold transposing packs only, else plain copies only
 // bytes a list of copies must move (read and write, or write for a fill)
 template <typename T>
 static double copy_bytes(const std::vector<CopyTile<T>>& tiles) {

@@ -181,7 +181,7 @@ __device__ void form_t(const T* Ps, int mp, int jb, const double* taus, double* 
 }
 
 // ---------------------------------------------------------------- kernels
-// Plain copies (mode 0).  A tile is walked as one flat sequence of rows x
+// Plain copies.  A tile is walked as one flat sequence of rows x
 // cols elements so that no lane idles on short rows, with 16-byte accesses
 // whenever the row length, both strides and both addresses allow them.
 template <typename T>
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(NT) k_copy(const CopyTile<T>* __restrict__ til
   }
 }
 
-// Transposing copies (mode 1: row-major source, column-major destination),
+// Transposing copies (row-major source, column-major destination),
 // one workgroup per tile, through a 64 x 65 LDS tile: each wavefront reads
 // every fourth row of a 64 x 64 sub-tile (contiguous along the row) and then
 // writes every fourth column (contiguous along the column).

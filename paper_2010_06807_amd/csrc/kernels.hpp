@@ -9,16 +9,15 @@
 
 namespace spaqr {
 
-// One rectangular copy: dst[r*ldd + c] = src[r*lds + c] (mode 0), or the
-// transpose dst[c*ldd + r] = src[r*lds + c] (mode 1); src == nullptr zero-fills
-// (mode 0 only).  The tiles of one launch must have disjoint destinations:
-// they run concurrently, one workgroup per tile.
+// One rectangular copy: dst[r*ldd + c] = src[r*lds + c] (a plain launch), or
+// the transpose dst[c*ldd + r] = src[r*lds + c] (a transposing launch);
+// src == nullptr zero-fills (plain launches only).  The tiles of one launch
+// must have disjoint destinations: they run concurrently.
 template <typename T>
 struct CopyTile {
   const T* src;
   T* dst;
   int32_t rows, cols, lds, ldd;
-  int32_t mode, pad;
 };
 
 // Blocked Householder QR of a row-major m x nc matrix (row stride ld, or nc
@@ -140,7 +139,7 @@ struct ApIface {
 };
 
 // ------------------------------------------------------------------ launchers
-// Copy tiles; transpose: every tile has mode 1 (else every tile has mode 0).
+// Copy tiles, all transposing (transpose) or all plain.
 template <typename T>
 void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipStream_t s);
 template <typename T>

@@ -14,6 +14,13 @@
 
 namespace spaqr {
 
+// Worker threads for per-problem host work: one per core beside the
+// calling thread, at most 15 (a GPU's share of a host is 16 cores).
+inline int host_pool_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::min<unsigned>(15, hc > 1 ? hc - 1 : 0);
+}
+
 class HostPool {
  public:
   explicit HostPool(int threads) {

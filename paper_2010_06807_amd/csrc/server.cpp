@@ -213,8 +213,7 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
     std::vector<int> adm_st(adm.size(), SPAQR_OK);
     if (!adm.empty()) {
       if (!srv->pool && adm.size() > 1) {
-        const unsigned hc = std::thread::hardware_concurrency();
-        srv->pool.reset(new HostPool((int)std::min<unsigned>(7, hc > 1 ? hc - 1 : 0)));
+        srv->pool.reset(new HostPool(host_pool_threads()));
       }
       auto setup = [&](int i) {
         Request& r = *adm[i];
