@@ -78,7 +78,94 @@ def parse():
     ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
                     help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
                          "directory of this script's run and exit")
+    ap.add_argument("--copy-calibration", metavar="BYTES", type=int, default=None,
+                    help="only run a plain device-to-device copy of BYTES bytes three times (the reference "
+                         "kernel for scaling the HBM counters) and exit")
+    ap.add_argument("--pmc-summary", metavar="DIR", default=None,
+                    help="from rocprofv3 --pmc runs in DIR/fetch and DIR/write (this script's run, counters "
+                         "FETCH_SIZE and WRITE_SIZE) and DIR/cal_fetch and DIR/cal_write (--copy-calibration "
+                         "runs), write the measured HBM traffic per launch of the roofline kernel to "
+                         f"{TRAFFIC_FILE} and exit")
     return ap.parse_args()
+
+
+# HBM traffic of the roofline kernel measured with rocprofv3 counters (see
+# pmc_summary); reported only while kernels.hip is the source it was measured on
+TRAFFIC_FILE = os.path.join("profiles", "sparsify_c2_256x256_traffic.json")
+KERNEL_SOURCE = os.path.join("paper_2010_06807_amd", "csrc", "kernels.hip")
+CAL_BYTES = 1 << 30
+
+
+def source_sha256():
+    import hashlib
+    with open(os.path.join(ROOT, KERNEL_SOURCE), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_calibration(nbytes):
+    """A plain copy of nbytes (read nbytes, write nbytes), three times."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {nbytes} bytes three times")
+
+
+def pmc_counters(d, counter, match):
+    """Per-dispatch values (KiB) of one counter for the kernels whose name
+    contains one of `match`, from a rocprofv3 --pmc CSV directory."""
+    import csv
+    import glob
+    vals = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter or not any(m in r.get("Kernel_Name", "") for m in match):
+                continue
+            key = (path, r.get("Dispatch_Id"))
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    return list(vals.values())
+
+
+def pmc_summary(d):
+    """Traffic per launch of the sparsification kernels: FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the factor that makes the same
+    counter read the known bytes of the calibration copy."""
+    import statistics
+    cal = CAL_BYTES / 1024.0
+    cf = pmc_counters(os.path.join(d, "cal_fetch"), "FETCH_SIZE", ("copy", "Copy", "elementwise"))
+    cw = pmc_counters(os.path.join(d, "cal_write"), "WRITE_SIZE", ("copy", "Copy", "elementwise"))
+    if not cf or not cw or max(cf) <= 0 or max(cw) <= 0:
+        raise SystemExit("pmc-summary: no calibration copy dispatch found")
+    # the copies of the calibration buffer are the run's largest dispatches
+    big_f = [v for v in cf if v >= 0.5 * max(cf)]
+    big_w = [v for v in cw if v >= 0.5 * max(cw)]
+    kf, kw = cal / statistics.median(big_f), cal / statistics.median(big_w)
+    pats = GROUP_KERNELS["sparsify"]
+    f = pmc_counters(os.path.join(d, "fetch"), "FETCH_SIZE", pats)
+    w = pmc_counters(os.path.join(d, "write"), "WRITE_SIZE", pats)
+    if not f or not w:
+        raise SystemExit("pmc-summary: no sparsification dispatch found")
+    out = {"kernel": "sparsify", "kernels": list(pats), "dispatches": [len(f), len(w)],
+           "fetch_KiB_per_launch_raw": sum(f) / len(f), "write_KiB_per_launch_raw": sum(w) / len(w),
+           "calibration_bytes": CAL_BYTES, "scale_fetch": kf, "scale_write": kw,
+           "traffic_bytes_per_launch": 1024.0 * (kf * sum(f) / len(f) + kw * sum(w) / len(w)),
+           "kernels_hip_sha256": source_sha256()}
+    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic():
+    """Bytes per launch of the roofline kernel from the counter runs, or None
+    when there are none or the kernels changed since."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as fh:
+            t = json.load(fh)
+        return t["traffic_bytes_per_launch"] if t.get("kernels_hip_sha256") == source_sha256() else None
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def log(msg):
@@ -98,6 +185,9 @@ def pct(v, q):
 GROUP_KERNELS = {
     "front_qr": ("k_qr_reg<float", "k_qr<float"),
     "trailing updates (fronts and scaling)": ("k_trail<float",),
+    "block copies and zero fills": ("k_copy<float", "k_copy_t<float", "k_zero", "k_fill<float"),
+    "descriptor uploads and readbacks": ("__amd_rocclr_copyBuffer", "k_gather_ints"),
+    "interface operators (forming)": ("k_iface_form<float",),
     "scale_blocks": ("k_scale<float", "k_scale_small<float", "k_scale_right<float"),
     "sparsify": ("k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
@@ -193,6 +283,12 @@ def cpu_baseline(prob, eps, tol):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary)
+        return
     if args.rocprof_summary:
         # FP32 steps of a run: 2 survey steps, the warmup and the timed steps
         print(rocprof_summary(args.rocprof_summary, 2 + args.warmup + args.steps))
@@ -356,7 +452,7 @@ def main():
         peak, unit = PEAK["alu32"]
         achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
     roof = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak, "traffic": measured_traffic() if kern == "sparsify" else None,
             "launches": prof["launches"], "avg_launch_us": 1e3 * prof["total_ms"] / max(1, prof["launches"]),
             "ms_per_step": prof["total_ms"] / (args.steps + args.warmup),
             "work_per_step": (prof["bytes"] if bound == "hbm" else prof["flops"]) / (args.steps + args.warmup),

@@ -1118,22 +1118,27 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
     ditems = up.upload(wk, items, s);
     launch_zero_ops({{done, 2 * ncoop * (int64_t)sizeof(int)}}, up, wk, s);
   }
-  ProfScope ps("sparsify", s, 0.0, 0.0);  // work added after the rank readback
-  for (const auto& g : groups)
+  // one profiler record per kernel launch (the work is added after the rank
+  // readback)
+  for (const auto& g : groups) {
+    ProfScope ps("sparsify", s, 0.0, 0.0);
     launch_sparsify_reg<T>(dsd + g[0], g[1] - g[0], dnb, (int)g[2], (int)g[3], max_nb, s);
+  }
   for (const CoopLaunch& L : coop) {
     const int64_t i0 = L.begin - nreg, ni = L.end - L.begin;
-    if (getenv("SPAQR_DEBUG_COOP")) {
-      double mp = 0; int pm = 0, mm = 0;
-      for (int64_t t = L.begin; t < L.end; ++t) { mp += (double)sd[t].mmax * sd[t].P; pm = std::max<int>(pm, sd[t].P); mm = std::max<int>(mm, sd[t].mmax); }
-      fprintf(stderr, "COOP ni %lld blocks %d cpt %d maxp %d maxm %d kmax %d sumMP %.3g MB\n", (long long)ni, L.blocks, coop_cpt, pm, mm, L.kmax, mp * sizeof(T) / 1e6);
-    }
+    ProfScope ps("sparsify", s, 0.0, 0.0);
     if (!launch_sparsify_coop<T>(dsd + L.begin, ditems + i0, (int)ni, L.blocks, coop_cpt, dnb, coop_maxp, coop_maxnb,
                                  ckey, cpos, ccol, done + 2 * i0, L.kmax, s))
       throw Error(SPAQR_EDEVICE, "cooperative CPQR no longer fits the device");
   }
-  launch_sparsify_small<T>(dsd + nrest0, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
-  launch_sparsify<T>(dsd + nrest0 + nsmall, (int64_t)sd.size() - nrest0 - nsmall, dnb, max_pc, max_nb, s);
+  if (nsmall > 0) {
+    ProfScope ps("sparsify", s, 0.0, 0.0);
+    launch_sparsify_small<T>(dsd + nrest0, nsmall, dnb, pmax_small, max_nb, cmax_small, s);
+  }
+  if ((int64_t)sd.size() > nrest0 + nsmall) {
+    ProfScope ps("sparsify", s, 0.0, 0.0);
+    launch_sparsify<T>(dsd + nrest0 + nsmall, (int64_t)sd.size() - nrest0 - nsmall, dnb, max_pc, max_nb, s);
+  }
 }
 
 // One stage of every factorization in es, in two halves: stage_launch plans

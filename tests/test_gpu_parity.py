@@ -216,6 +216,12 @@ def test_kernel_profiler_counts_launches():
     P.factor(A, P.order_grid(dims, L), eps=1e-3, precision=32)
     assert P.profile_query("front_qr")["launches"] == 0
     assert P.profile_query("sparsify")["launches"] > 0
+    # a prefix filter: the host phases only
+    P.profile_enable(True, only="host_*")
+    P.factor(A, P.order_grid(dims, L), eps=1e-3, precision=32)
+    assert P.profile_query("host_plan_fronts")["launches"] >= L
+    assert P.profile_query("host_wait_gpu")["total_ms"] > 0
+    assert P.profile_query("sparsify")["launches"] == 0
     P.profile_enable(False)
 
 
