@@ -1359,6 +1359,9 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
     for (int cl = 0; cl < 3; ++cl)
       if (!form[cl].empty()) {
         ApIface<T>* d = up.upload(wk, form[cl], s);
+        double by = 0.0;  // reflectors read, both operators written
+        for (const ApIface<T>& q : form[cl]) by += 4.0 * q.P * (double)q.P * sizeof(T);
+        ProfScope ps("iface_form", s, 0.0, by);
         launch_iface_form<T>(d, (int64_t)form[cl].size(), 16 << cl, s);
       }
   }

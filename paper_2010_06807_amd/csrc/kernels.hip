@@ -2269,18 +2269,20 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
 // forward sweep applies U_pp^T (scaling reflectors in order) then Q_pp^T
 // (sparsification reflectors in order); the backward sweep applies Q_pp
 // (reverse order) then R_pp^{-1}.  mf = Q^T U^T and mb = R^{-1} Q are formed
-// by applying those steps to the identity, held in LDS in FP64.  Four adjacent
-// lanes share a column (rows part, part + 4, ...): reflector dots reduce with
-// two lane swaps and no barrier, since a column is only touched by its own
-// lanes.
-// PM (16, 32 or 64) bounds P; the workgroup has 4 PM threads.
-template <typename T, int PM>
-__global__ void __launch_bounds__(4 * PM) k_iface_form(const ApIface<T>* __restrict__ ds) {
-  constexpr int LX = PM + 1;  // padded row stride of X: the four row parts fall in distinct banks
-  constexpr int NTH = 4 * PM;
+// by applying those steps to the identity, held in LDS in FP64.  LP adjacent
+// lanes share a column (rows part, part + LP, ...): reflector dots reduce
+// with log2(LP) lane swaps and no barrier, since a column is only touched by
+// its own lanes.
+// PM (16, 32 or 64) bounds P; the workgroup has LP PM threads, LP (4 or 8)
+// lanes per column.
+template <typename T, int PM, int LP>
+__global__ void __launch_bounds__(LP * PM) k_iface_form(const ApIface<T>* __restrict__ ds) {
+  constexpr int LX = PM + 1;  // padded row stride of X: the row parts of a column fall in distinct banks
+  constexpr int NTH = LP * PM;
+  static_assert(LP == 4 || LP == 8, "four or eight lanes per column");
   extern __shared__ __align__(16) unsigned char smem[];
   const ApIface<T> d = ds[blockIdx.x];
-  const int P = d.P, tid = threadIdx.x, j = tid >> 2, part = tid & 3;
+  const int P = d.P, tid = threadIdx.x, j = tid / LP, part = tid & (LP - 1);
   if (P == 0 || *d.flag != 0) return;
   const int r = *d.rank;
   const bool hasq = r < P;
@@ -2299,29 +2301,30 @@ __global__ void __launch_bounds__(4 * PM) k_iface_form(const ApIface<T>* __restr
   }
   auto ident = [&]() {
     if (j < P)
-      for (int q = part; q < P; q += 4) X[q * LX + j] = q == j ? 1.0 : 0.0;
+      for (int q = part; q < P; q += LP) X[q * LX + j] = q == j ? 1.0 : 0.0;
   };
   // X[:, j] <- (I - tau v v^T) X[:, j]; v = column t of V with rows < t zero
   // and, if unit, an implicit 1 at row t
   auto reflect = [&](const T* V, int t, double tau, bool unit) {
     double sdot = 0.0;
     if (j < P)
-      for (int q = part; q < P; q += 4) {
+      for (int q = part; q < P; q += LP) {
         const double v = q < t ? 0.0 : ((q == t && unit) ? 1.0 : (double)V[q + t * P]);
         sdot += v * X[q * LX + j];
       }
     sdot += xshfl<1>(sdot);
     sdot += xshfl<2>(sdot);
+    if (LP == 8) sdot += xshfl<4>(sdot);
     sdot *= tau;
     if (j < P)
-      for (int q = part; q < P; q += 4) {
+      for (int q = part; q < P; q += LP) {
         const double v = q < t ? 0.0 : ((q == t && unit) ? 1.0 : (double)V[q + t * P]);
         X[q * LX + j] -= sdot * v;
       }
   };
   auto store = [&](T* M) {
     if (j < P)
-      for (int q = part; q < P; q += 4) M[q + (int64_t)j * P] = (T)X[q * LX + j];
+      for (int q = part; q < P; q += LP) M[q + (int64_t)j * P] = (T)X[q * LX + j];
   };
   ident();
   __syncthreads();
@@ -2336,8 +2339,8 @@ __global__ void __launch_bounds__(4 * PM) k_iface_form(const ApIface<T>* __restr
   for (int c = P - 1; c >= 0; --c) {
     if (j < P) {
       const double xc = X[c * LX + j] / (double)vu[c + c * P];
-      if ((c & 3) == part) X[c * LX + j] = xc;
-      for (int q = part; q < c; q += 4) X[q * LX + j] -= (double)vu[q + c * P] * xc;
+      if ((c & (LP - 1)) == part) X[c * LX + j] = xc;
+      for (int q = part; q < c; q += LP) X[q * LX + j] -= (double)vu[q + c * P] * xc;
     }
   }
   store(d.mb);
@@ -3033,9 +3036,12 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
 
 template <typename T, int PM>
 static void launch_iface_form_t(const ApIface<T>* d, int64_t n, hipStream_t s) {
+  // eight lanes per column for the largest class: shorter chains per
+  // reflector where the LDS already limits the workgroups per CU
+  constexpr int LP = PM >= 64 ? 8 : 4;
   const size_t lds = ((size_t)PM * (PM + 1) + 2 * PM) * sizeof(double) + 2 * (size_t)PM * PM * sizeof(T);
-  allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM>), lds, "k_iface_form");
-  hipLaunchKernelGGL((k_iface_form<T, PM>), dim3((unsigned)n), dim3(4 * PM), lds, s, d);
+  allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM, LP>), lds, "k_iface_form");
+  hipLaunchKernelGGL((k_iface_form<T, PM, LP>), dim3((unsigned)n), dim3(LP * PM), lds, s, d);
   check_launch("k_iface_form");
 }
 
