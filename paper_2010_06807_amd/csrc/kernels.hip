@@ -3036,9 +3036,9 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
 
 template <typename T, int PM>
 static void launch_iface_form_t(const ApIface<T>* d, int64_t n, hipStream_t s) {
-  // eight lanes per column for the largest class: shorter chains per
+  // eight lanes per column for the two larger classes: shorter chains per
   // reflector where the LDS already limits the workgroups per CU
-  constexpr int LP = PM >= 64 ? 8 : 4;
+  constexpr int LP = PM >= 32 ? 8 : 4;
   const size_t lds = ((size_t)PM * (PM + 1) + 2 * PM) * sizeof(double) + 2 * (size_t)PM * PM * sizeof(T);
   allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM, LP>), lds, "k_iface_form");
   hipLaunchKernelGGL((k_iface_form<T, PM, LP>), dim3((unsigned)n), dim3(LP * PM), lds, s, d);
