@@ -2273,13 +2273,13 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
 // lanes share a column (rows part, part + LP, ...): reflector dots reduce
 // with log2(LP) lane swaps and no barrier, since a column is only touched by
 // its own lanes.
-// PM (16, 32 or 64) bounds P; the workgroup has LP PM threads, LP (4 or 8)
-// lanes per column.
+// PM (16, 32 or 64) bounds P; the workgroup has LP PM threads, LP (4, 8 or
+// 16) lanes per column.
 template <typename T, int PM, int LP>
 __global__ void __launch_bounds__(LP * PM) k_iface_form(const ApIface<T>* __restrict__ ds) {
   constexpr int LX = PM + 1;  // padded row stride of X: the row parts of a column fall in distinct banks
   constexpr int NTH = LP * PM;
-  static_assert(LP == 4 || LP == 8, "four or eight lanes per column");
+  static_assert(LP == 4 || LP == 8 || LP == 16, "four, eight or sixteen lanes per column");
   extern __shared__ __align__(16) unsigned char smem[];
   const ApIface<T> d = ds[blockIdx.x];
   const int P = d.P, tid = threadIdx.x, j = tid / LP, part = tid & (LP - 1);
@@ -2314,7 +2314,8 @@ __global__ void __launch_bounds__(LP * PM) k_iface_form(const ApIface<T>* __rest
       }
     sdot += xshfl<1>(sdot);
     sdot += xshfl<2>(sdot);
-    if (LP == 8) sdot += xshfl<4>(sdot);
+    if (LP >= 8) sdot += xshfl<4>(sdot);
+    if (LP >= 16) sdot += xshfl<8>(sdot);
     sdot *= tau;
     if (j < P)
       for (int q = part; q < P; q += LP) {
@@ -3036,9 +3037,9 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
 
 template <typename T, int PM>
 static void launch_iface_form_t(const ApIface<T>* d, int64_t n, hipStream_t s) {
-  // eight lanes per column for the two larger classes: shorter chains per
-  // reflector where the LDS already limits the workgroups per CU
-  constexpr int LP = PM >= 32 ? 8 : 4;
+  // more lanes per column than four: shorter chains per reflector where the
+  // LDS limits the workgroups per CU
+  constexpr int LP = PM >= 64 ? 16 : 8;
   const size_t lds = ((size_t)PM * (PM + 1) + 2 * PM) * sizeof(double) + 2 * (size_t)PM * PM * sizeof(T);
   allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM, LP>), lds, "k_iface_form");
   hipLaunchKernelGGL((k_iface_form<T, PM, LP>), dim3((unsigned)n), dim3(LP * PM), lds, s, d);
