@@ -678,8 +678,9 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
       d.pool = pool_;
       d.rank = d_rank_;
       d.eps = o_.eps;
-      // the LDS/global kernels need a workspace; the register kernel does not
-      if (sparsify_reg_cpt(sizeof(T), Pn, d.mmax) == 0) {
+      // the LDS/global kernels need a workspace; the register kernel needs
+      // one only for its columns in global memory
+      if (sparsify_reg_cpt(sizeof(T), Pn, d.mmax) == 0 || sparsify_reg_global(sizeof(T), Pn, d.mmax)) {
         d.C = work_.alloc_n<T>((size_t)(Pn <= 64 ? 65 : Pn) * d.mmax, s_);
         d.nrm = work_.alloc_n<double>((size_t)d.mmax, s_);
         d.perm = work_.alloc_n<int32_t>(2 * (size_t)d.mmax, s_);
@@ -1013,7 +1014,7 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
     mreg = std::max<int>(mreg, sd[t].mmax);
   }
   std::vector<std::array<int64_t, 4>> groups;  // begin, end, pmax, mmax
-  if (nreg > 0 && sparsify_reg_cpt(sizeof(T), preg, mreg) > 0) {
+  if (nreg > 0 && sparsify_reg_cpt(sizeof(T), preg, mreg) > 0 && !sparsify_reg_global(sizeof(T), preg, mreg)) {
     groups.push_back({0, nreg, preg, mreg});
   } else if (nreg > 0) {
     auto pcls = [](int Pv) { return Pv <= 16 ? 0 : (Pv <= 32 ? 1 : 2); };

@@ -1370,7 +1370,8 @@ __global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restr
 // rank rule of Section 4).  Thread tid owns columns tid + SP_NT j: j < CPT in
 // registers and, if LC, one more column in LDS (element q at
 // q * SP_NT + tid, conflict-free), for the whole factorization (P <= PMAX
-// rows each).  Columns are never moved: each carries its current position,
+// rows each), and, if GC, one more in global memory (the descriptor's
+// workspace C, element q at q * SP_NT + tid).  Columns are never moved: each carries its current position,
 // and the swap of the pivot with the column at position k only exchanges
 // positions, so the pivot choice (largest FP64 norm, ties to the lowest
 // current position) is the same as with physical swaps.  Per step: local and
@@ -1383,11 +1384,12 @@ __global__ void __launch_bounds__(NTH) k_sparsify_small(const SpDesc<T>* __restr
 // columns) and go back to the blocks.
 constexpr int SP_NT = 512;
 
-template <typename T, int PMAX, int CPT, int LC>
+template <typename T, int PMAX, int CPT, int LC, int GC>
 __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict__ descs,
                                                     const SpNbr* __restrict__ nbrs, int max_nb) {
   constexpr int NW = SP_NT / 64;
-  constexpr int NC = CPT + LC;
+  constexpr int NCL = CPT + LC;     // columns in registers and LDS
+  constexpr int NC = NCL + GC;      // and in global memory
   constexpr int VN = Vec16<T>::N;
   const SpDesc<T> d = descs[blockIdx.x];
   const double eps = d.eps;
@@ -1430,6 +1432,7 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
   double nr[NC];
   int pos[NC], kel[NC];
   T* lc = lcol + tid;  // the LDS column, stride SP_NT
+  T* gcp = GC ? d.C + tid : nullptr;  // the global column, stride SP_NT (touched only when it exists)
 #pragma unroll
   for (int j = 0; j < NC; ++j) {
     const int c = tid + SP_NT * j;
@@ -1442,7 +1445,8 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
     for (int q = 0; q < PMAX; ++q) {
       const T x = (src && q < P) ? src[q * str] : T(0);
       if (j < CPT) a[j < CPT ? j : 0][q] = x;
-      else lc[q * SP_NT] = x;
+      else if (j < NCL) lc[q * SP_NT] = x;
+      else if (c < m) gcp[q * SP_NT] = x;
       s2 += (double)x * (double)x;
     }
     nr[j] = c < m ? s2 : -1.0;
@@ -1483,8 +1487,10 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
         if (kel[j] < 0 && pos[j] == wp) {
           if (j < CPT) {
             lds_store_row<T, PMAX>(sl, a[j < CPT ? j : 0]);
-          } else {
+          } else if (j < NCL) {
             for (int q = 0; q < PMAX; ++q) sl[q] = lc[q * SP_NT];
+          } else {
+            for (int q = 0; q < PMAX; ++q) sl[q] = gcp[q * SP_NT];
           }
         }
     }
@@ -1539,8 +1545,10 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
         if (j < CPT) {
 #pragma unroll
           for (int q = 0; q < PMAX; ++q) a[j < CPT ? j : 0][q] = q == k ? beta : a[j < CPT ? j : 0][q];
-        } else {
+        } else if (j < NCL) {
           lc[k * SP_NT] = beta;
+        } else {
+          gcp[k * SP_NT] = beta;
         }
         continue;
       }
@@ -1571,11 +1579,12 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
           }
         }
       } else {
-        for (int q = k; q < PMAX; ++q) w += vbuf[q] * lc[q * SP_NT];
+        T* cp = j < NCL ? lc : gcp;
+        for (int q = k; q < PMAX; ++q) w += vbuf[q] * cp[q * SP_NT];
         const T tw = tau * w;
         for (int q = k; q < PMAX; ++q) {
-          const T x = lc[q * SP_NT] - tw * vbuf[q];
-          lc[q * SP_NT] = x;
+          const T x = cp[q * SP_NT] - tw * vbuf[q];
+          cp[q * SP_NT] = x;
           if (q > k) s2 += (double)x * (double)x;
         }
       }
@@ -1593,7 +1602,7 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
 #pragma unroll
       for (int q = 0; q < PMAX; ++q)
         if (q < r) {
-          const T x = j < CPT ? a[j < CPT ? j : 0][q] : lc[q * SP_NT];
+          const T x = j < CPT ? a[j < CPT ? j : 0][q] : (j < NCL ? lc[q * SP_NT] : gcp[q * SP_NT]);
           dst[q * str] = (kel[j] >= 0 && q > kel[j]) ? T(0) : x;
         }
     }
@@ -2819,7 +2828,17 @@ int sparsify_reg_cpt(int eb, int pmax, int mmax) {
   const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
   if (pmax > 64 || (eb == 8 && pclass == 64)) return 0;
   const int cpt = std::max(1, (mmax + SP_NT - 1) / SP_NT);
-  return cpt <= sp_reg_cap(eb, pclass) + 1 ? cpt : 0;
+  const int cap = sp_reg_cap(eb, pclass);
+  if (cpt <= cap + 1) return cpt;
+  // FP32 interfaces of 33-64 unknowns: one more column per thread in the
+  // descriptor's global workspace
+  return eb == 4 && pclass == 64 && cpt == cap + 2 ? cpt : 0;
+}
+
+bool sparsify_reg_global(int eb, int pmax, int mmax) {
+  const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
+  const int cpt = sparsify_reg_cpt(eb, pmax, mmax);
+  return cpt > 0 && cpt > sp_reg_cap(eb, pclass) + 1;
 }
 
 template <typename T>
@@ -2830,42 +2849,43 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pma
   if (tot == 0) throw Error(SPAQR_EINVAL, "interface too large for the register CPQR");
   const int pclass = pmax <= 16 ? 16 : (pmax <= 32 ? 32 : 64);
   const int cap = sp_reg_cap(sizeof(T), pclass);
-  const int cpt = std::min(tot, cap), lc = tot - cpt;
+  const int cpt = std::min(tot, cap), lc = std::min(tot - cpt, 1), gc = tot - cpt - lc;
   constexpr int NW = SP_NT / 64;
   const size_t lds = (size_t)(2 * NW + 1 + lc * SP_NT) * pclass * sizeof(T) + (2 * NW + 2) * sizeof(double) +
                      (size_t)(2 * NW + max_nb + 1) * sizeof(int);
-#define SPAQR_SPR(PM, CP, L)                                                                              \
-  if (pclass == PM && cpt == CP && lc == L) {                                                            \
-    allow_lds(reinterpret_cast<const void*>(&k_cpqr_reg<T, PM, CP, L>), lds, "k_cpqr_reg");             \
-    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, max_nb);   \
+#define SPAQR_SPR(PM, CP, L, G)                                                                           \
+  if (pclass == PM && cpt == CP && lc == L && gc == G) {                                                 \
+    allow_lds(reinterpret_cast<const void*>(&k_cpqr_reg<T, PM, CP, L, G>), lds, "k_cpqr_reg");          \
+    hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L, G>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, max_nb); \
     check_launch("k_cpqr_reg");                                                                          \
     return;                                                                                              \
   }
   if constexpr (sizeof(T) == 4) {
-    SPAQR_SPR(16, 1, 0)
-    SPAQR_SPR(16, 2, 0)
-    SPAQR_SPR(16, 3, 0)
-    SPAQR_SPR(16, 4, 0)
-    SPAQR_SPR(16, 4, 1)
-    SPAQR_SPR(32, 1, 0)
-    SPAQR_SPR(32, 2, 0)
-    SPAQR_SPR(32, 3, 0)
-    SPAQR_SPR(32, 4, 0)
-    SPAQR_SPR(32, 4, 1)
-    SPAQR_SPR(64, 1, 0)
-    SPAQR_SPR(64, 2, 0)
-    SPAQR_SPR(64, 3, 0)
-    SPAQR_SPR(64, 3, 1)
+    SPAQR_SPR(16, 1, 0, 0)
+    SPAQR_SPR(16, 2, 0, 0)
+    SPAQR_SPR(16, 3, 0, 0)
+    SPAQR_SPR(16, 4, 0, 0)
+    SPAQR_SPR(16, 4, 1, 0)
+    SPAQR_SPR(32, 1, 0, 0)
+    SPAQR_SPR(32, 2, 0, 0)
+    SPAQR_SPR(32, 3, 0, 0)
+    SPAQR_SPR(32, 4, 0, 0)
+    SPAQR_SPR(32, 4, 1, 0)
+    SPAQR_SPR(64, 1, 0, 0)
+    SPAQR_SPR(64, 2, 0, 0)
+    SPAQR_SPR(64, 3, 0, 0)
+    SPAQR_SPR(64, 3, 1, 0)
+    SPAQR_SPR(64, 3, 1, 1)
   } else {
-    SPAQR_SPR(16, 1, 0)
-    SPAQR_SPR(16, 2, 0)
-    SPAQR_SPR(16, 3, 0)
-    SPAQR_SPR(16, 4, 0)
-    SPAQR_SPR(16, 4, 1)
-    SPAQR_SPR(32, 1, 0)
-    SPAQR_SPR(32, 2, 0)
-    SPAQR_SPR(32, 3, 0)
-    SPAQR_SPR(32, 3, 1)
+    SPAQR_SPR(16, 1, 0, 0)
+    SPAQR_SPR(16, 2, 0, 0)
+    SPAQR_SPR(16, 3, 0, 0)
+    SPAQR_SPR(16, 4, 0, 0)
+    SPAQR_SPR(16, 4, 1, 0)
+    SPAQR_SPR(32, 1, 0, 0)
+    SPAQR_SPR(32, 2, 0, 0)
+    SPAQR_SPR(32, 3, 0, 0)
+    SPAQR_SPR(32, 3, 1, 0)
   }
 #undef SPAQR_SPR
   throw Error(SPAQR_EINVAL, "unsupported register CPQR shape");

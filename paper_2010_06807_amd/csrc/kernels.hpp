@@ -187,6 +187,9 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_p, 
 // Register-resident CPQR (see k_cpqr_reg): columns per thread needed for
 // interfaces of at most pmax unknowns and mmax columns, or 0 if they do not fit.
 int sparsify_reg_cpt(int elem_bytes, int pmax, int mmax);
+// whether that register CPQR also keeps a column per thread in the
+// descriptor's workspace C (which then needs PMAX * 512 entries)
+bool sparsify_reg_global(int elem_bytes, int pmax, int mmax);
 template <typename T>
 void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int mmax, int max_nb,
                          hipStream_t s);
