@@ -180,6 +180,25 @@ def test_c2_fp32_against_oracle():
         assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o)), (prec, info, it_o)
 
 
+def test_c2_fp32_tight_tolerance_against_oracle():
+    """The 256^2 workload at eps = 1e-4: some interfaces of 33-64 unknowns
+    reach 2049-2560 columns, so the register CPQR keeps a column per thread
+    in global memory (and a few wider ones take the cooperative kernel)."""
+    prob = config_problem("c2", seed=0)
+    A, dims, L = prob["A"], prob["dims"], prob["levels"]
+    N = A.shape[0]
+    F = _oracle(A, dims, L, 1e-4)
+    b = make_rhs(N, 1, seed=0)
+    it_o, _ = _oracle_its(A, F, b[:, 0])
+    print("case c2 eps=1e-4 precision=32", flush=True)
+    fac = P.factor(A, P.order_grid(dims, L), eps=1e-4, precision=32)
+    _ranks_agree(fac, F, L, 1)
+    x, info = fac.solve(_dev(b), tol=1e-10)
+    res = np.linalg.norm(A @ x.cpu().numpy() - b) / np.linalg.norm(b)
+    assert res <= 1e-10
+    assert info[0]["iterations"] <= it_o + max(1, math.ceil(0.1 * it_o)), (info, it_o)
+
+
 def test_device_resident_input_matches_host_input():
     """spaqr_factor_device (values read from HBM, column scaling on the GPU)
     against spaqr_factor (host values): same ranks, same M^{-1} b."""
