@@ -168,7 +168,6 @@ static void dots(const double* X, int64_t sj, int64_t sc, int J, const double* w
 int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, const double* tol,
                  int restart, int maxit_in, spaqr_solve_info* info) {
   const double t0 = now_ms();
-  HostScope hs_body("host_solve_body");
   hipStream_t s = e.stream();
   const int64_t N = e.n();
   const int m = std::max(1, restart);
@@ -198,11 +197,9 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
   };
   // ||b||
   double* hn = hd.p;
-  HostScope hs_b("host_solve_bnorm");
   dots(b, 0, ldb, 1, b, ldb, N, nrhs, part.p, hn, s);
   D2H(hn, nrhs);
   SPAQR_HIP(hipStreamSynchronize(s));
-  hs_b.stop();
   for (int c = 0; c < nrhs; ++c) bnorm[c] = std::sqrt(hm[c]);
   hipLaunchKernelGGL(k_zero_cols, dim3(gx(N), nrhs), dim3(256), 0, s, x, ldx, N);
   // r = b (x0 = 0)
@@ -214,11 +211,9 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
   std::vector<int> jend(nrhs, 0), active(nrhs, 0);
   for (;;) {
     // beta = ||r||
-    HostScope hs_r("host_solve_restart");
     dots(W.p, 0, N, 1, W.p, N, N, nrhs, part.p, hn, s);
     D2H(hn, nrhs);
     SPAQR_HIP(hipStreamSynchronize(s));
-    hs_r.stop();
     bool any = false;
     for (int c = 0; c < nrhs; ++c) {
       const double beta = std::sqrt(hm[c]);
@@ -297,7 +292,6 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
       if (!still) break;
     }
     // x += Z y per column
-    HostScope hs_u("host_solve_update");
     const int J = std::min(m, std::max(1, *std::max_element(jend.begin(), jend.end())));
     double* y = ym;
     std::fill(y, y + (size_t)J * nrhs, 0.0);
@@ -342,7 +336,6 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
     }
   }
   (void)total;
-  hs_body.stop();
   return status;
 }
 
@@ -370,7 +363,6 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
     maxit = std::max(maxit, es[i]->opt_maxit());
     tc.insert(tc.end(), (size_t)nrhs[i], tol[i]);
   }
-  HostScope hs_in("host_solve_in");
   Dev B(s), X(s);
   B.ensure((size_t)N * C);
   X.ensure((size_t)N * C);
@@ -382,12 +374,7 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
                                n * sizeof(double), nrhs[i], hipMemcpyDeviceToDevice, s));
   }
   std::vector<spaqr_solve_info> inf((size_t)C);
-  hs_in.stop();
-  {
-    HostScope hs_f("host_solve_fgmres");
-    fgmres_solve(*op, B.p, N, X.p, N, C, tc.data(), restart, maxit, inf.data());
-  }
-  HostScope hs_out("host_solve_out");
+  fgmres_solve(*op, B.p, N, X.p, N, C, tc.data(), restart, maxit, inf.data());
   int st = SPAQR_OK;
   if (status) status->assign(np, SPAQR_OK);
   for (size_t i = 0; i < np; ++i) {
@@ -401,12 +388,8 @@ int fgmres_solve_batch(const std::vector<EngineBase*>& es, const std::vector<int
       }
   }
   SPAQR_HIP(hipStreamSynchronize(s));
-  hs_out.stop();
-  {
-    HostScope hs_free("host_solve_free");
-    X.release();
-    B.release();
-  }
+  X.release();
+  B.release();
   if (info) std::copy(inf.begin(), inf.end(), info);
   return st;
 }
