@@ -306,6 +306,19 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   launch_fill<int>(d_zcol_, 1, 0, s_);
   std::vector<double> dc;
   HostScope hs_csr("host_setup_csr");
+  // the analysis's pattern maps in one copy, straight from its pinned buffer
+  // when it has one
+  const size_t maps_bytes = S_.maps_words() * sizeof(int64_t);
+  int64_t* d_maps = nullptr;
+  if (S_.maps.pinned()) {
+    d_maps = work_.alloc_n<int64_t>(S_.maps_words(), s_);
+    SPAQR_HIP(hipMemcpyAsync(d_maps, S_.maps.data(), maps_bytes, hipMemcpyHostToDevice, s_));
+  } else {
+    d_maps = static_cast<int64_t*>(up.upload_bytes(work_, S_.maps.data(), maps_bytes, s_));
+  }
+  int64_t* d_cptr = d_maps;
+  int64_t* d_cidx = d_cptr + (n + 1);
+  int64_t* d_dst = d_cidx + nnz;
   if (Ad) {
     // values already on the device: copy the CSR (device to device) for the
     // SpMV and compute the column scaling there, in a fixed summation order
@@ -315,8 +328,6 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
     SPAQR_HIP(hipMemcpyAsync(d_rowptr_, Ad->rowptr, (n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, s_));
     SPAQR_HIP(hipMemcpyAsync(d_col_, Ad->col, nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s_));
     SPAQR_HIP(hipMemcpyAsync(d_val_, Ad->val, nnz * sizeof(double), hipMemcpyDeviceToDevice, s_));
-    int64_t* d_cptr = up.upload(work_, S_.col_ptr, s_);
-    int64_t* d_cidx = up.upload(work_, S_.col_nz, s_);
     d_dc_ = persist_.alloc_n<double>(n, s_);
     launch_colnorm(d_cptr, d_cidx, d_val_, n, d_dc_, d_zcol_, s_);
   } else {
@@ -352,7 +363,6 @@ void Engine<T>::begin(const spaqr_csr* A, const spaqr_csr_dev* Ad) {
   pool_ = pools_[L & 1].alloc_n<T>(std::max<int64_t>(1, boff_.back()), s_);
   launch_fill<T>(pool_, boff_.back(), T(0), s_);
   {
-    int64_t* d_dst = up.upload(work_, S_.nz_dst, s_);
     launch_scatter_scaled<T>(pool_, d_dst, d_val_, d_col_, d_dc_, nnz, s_);
   }
   k_ = L;

@@ -118,4 +118,35 @@ void pinned_release(PinnedChunk c) {
   g_free.push_back(c);
 }
 
+HostBuffer::HostBuffer(size_t bytes) {
+  try {
+    c_ = pinned_acquire(bytes);
+    pinned_ = true;
+  } catch (const Error&) {
+    (void)hipGetLastError();
+    heap_ = new char[bytes ? bytes : 1];
+  }
+}
+
+HostBuffer& HostBuffer::operator=(HostBuffer&& o) noexcept {
+  if (this != &o) {
+    reset();
+    c_ = o.c_;
+    heap_ = o.heap_;
+    pinned_ = o.pinned_;
+    o.c_ = PinnedChunk{};
+    o.heap_ = nullptr;
+    o.pinned_ = false;
+  }
+  return *this;
+}
+
+void HostBuffer::reset() {
+  if (pinned_) pinned_release(c_);
+  delete[] heap_;
+  c_ = PinnedChunk{};
+  heap_ = nullptr;
+  pinned_ = false;
+}
+
 }  // namespace spaqr

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <utility>
 
 namespace spaqr {
 
@@ -24,5 +25,27 @@ struct PinnedChunk {
 };
 PinnedChunk pinned_acquire(size_t bytes);          // at least `bytes`
 void pinned_release(PinnedChunk c);
+
+// A host buffer in pinned memory from the recycled pool when pinned memory
+// can be had (copies from it need no staging), else in ordinary memory.
+// Moved, never copied; the pinned chunk goes back to the pool on release.
+class HostBuffer {
+ public:
+  HostBuffer() = default;
+  explicit HostBuffer(size_t bytes);
+  ~HostBuffer() { reset(); }
+  HostBuffer(HostBuffer&& o) noexcept { *this = std::move(o); }
+  HostBuffer& operator=(HostBuffer&& o) noexcept;
+  HostBuffer(const HostBuffer&) = delete;
+  HostBuffer& operator=(const HostBuffer&) = delete;
+  char* data() const { return pinned_ ? c_.p : heap_; }
+  bool pinned() const { return pinned_; }
+
+ private:
+  void reset();
+  PinnedChunk c_;
+  char* heap_ = nullptr;
+  bool pinned_ = false;
+};
 
 }  // namespace spaqr

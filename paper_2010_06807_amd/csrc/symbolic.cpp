@@ -316,7 +316,10 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
     for (int64_t t = sL.all.rowptr[i]; t < sL.all.rowptr[i + 1]; ++t)
       S->pool_off_L[t + 1] = S->pool_off_L[t] + (cl.end[i] - cl.start[i]) *
                                                     (cl.end[sL.all.col[t]] - cl.start[sL.all.col[t]]);
-  S->nz_dst.resize(A->nnz);
+  S->maps = HostBuffer(S->maps_words() * sizeof(int64_t));
+  S->col_ptr = reinterpret_cast<int64_t*>(S->maps.data());
+  S->col_nz = S->col_ptr + (n + 1);
+  S->nz_dst = S->col_nz + A->nnz;
   for (int64_t r = 0; r < n; ++r) {
     int64_t pr = ord.iperm[r];
     int32_t ci = S->cluster_of_pos_L[pr];
@@ -328,12 +331,11 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
     }
   }
   // ---- the nonzeros by column
-  S->col_ptr.assign(n + 1, 0);
-  S->col_nz.resize(A->nnz);
+  std::fill(S->col_ptr, S->col_ptr + n + 1, int64_t(0));
   for (int64_t t = 0; t < A->nnz; ++t) S->col_ptr[A->col[t] + 1]++;
   for (int64_t j = 0; j < n; ++j) S->col_ptr[j + 1] += S->col_ptr[j];
   {
-    std::vector<int64_t> pos(S->col_ptr.begin(), S->col_ptr.end() - 1);
+    std::vector<int64_t> pos(S->col_ptr, S->col_ptr + n);
     for (int64_t t = 0; t < A->nnz; ++t) S->col_nz[pos[A->col[t]]++] = t;
   }
   guard.release();

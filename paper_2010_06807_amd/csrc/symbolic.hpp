@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "mem.hpp"
 
 namespace spaqr {
 
@@ -70,12 +71,17 @@ struct Symbolic {
   // stage-L block storage: block t of st[L].all (row-major, its clusters'
   // sizes) starts at pool_off_L[t] of one pool of pool_off_L.back() entries
   std::vector<int64_t> pool_off_L;
-  // where every nonzero of A (CSR order) lands in that pool
-  std::vector<int64_t> nz_dst;
-  // the nonzeros of A by column (column c: entries col_nz[col_ptr[c] ..
-  // col_ptr[c + 1]) of CSR order, rows ascending), for column norms summed
-  // in a fixed order
-  std::vector<int64_t> col_ptr, col_nz;
+  // In one host buffer (pinned when possible, so the set-up's uploads need
+  // no staging copy), back to back: col_ptr (n + 1), col_nz (nnz), nz_dst
+  // (nnz).  The nonzeros of A by column: column c holds entries
+  // col_nz[col_ptr[c] .. col_ptr[c + 1]) of CSR order, rows ascending, for
+  // column norms summed in a fixed order; nz_dst: where every nonzero of A
+  // (CSR order) lands in the stage-L pool.
+  HostBuffer maps;
+  int64_t* col_ptr = nullptr;
+  int64_t* col_nz = nullptr;
+  int64_t* nz_dst = nullptr;
+  size_t maps_words() const { return (size_t)(n + 1) + 2 * (size_t)nnz; }
   std::vector<int32_t> cluster_of_pos_L;  // stage-L cluster of each permuted index
 };
 
