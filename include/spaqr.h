@@ -218,7 +218,9 @@ typedef struct {
   int32_t levels;            /* nested-dissection levels L */
   int32_t precision;         /* 32 or 64 */
   int64_t factor_bytes;      /* bytes of stored factors (V, tau, T, R, U, Q) */
-  int64_t top_separator;     /* size of the last front (root) when factored */
+  int64_t top_separator;     /* unknowns of the root separator after every sparsification
+                                that had neighbours to compress against (its size at the
+                                start of stage 2; the root front's size if L = 1) */
   int64_t fronts;            /* number of fronts factored */
   int64_t interfaces_sparsified;
   double flops_front;        /* algorithmic flops: front QR + trailing update */
@@ -229,6 +231,55 @@ typedef struct {
   double ms_phase[4];        /* front, scale, sparsify, merge (device time) */
 } spaqr_stats_t;
 spaqr_status spaqr_stats(const spaqr_handle* h, spaqr_stats_t* out);
+
+/* Statistics of one stage k of a completed factorization (the quantities of
+ * the paper's Section 4.3 experiments, per stage).  Device times come from
+ * HIP events around the stage's phases; in a batched factorization the
+ * phases of one stage are shared by the problems advanced together, so the
+ * times are those of the whole batch's launches.
+ * Errors: EINVAL (NULL argument, stage outside 1..L, factorization not
+ * complete). */
+typedef struct {
+  int32_t stage;              /* k */
+  int32_t sparsified;         /* 1 if the stage scaled and sparsified its interfaces */
+  int32_t fronts;             /* fronts (separators or leaves of level k) factored */
+  int32_t max_front_rows;     /* largest m_s = |s| + sum of its row neighbours */
+  int32_t max_front_pivots;   /* largest n_s = |s| */
+  int32_t interfaces;         /* interfaces scaled and sparsified (|p| > 0) */
+  int32_t max_nbr_cols;       /* largest m_p, the columns of C_p = [A_np^T | A_pn] */
+  int32_t iface_size_q1;      /* quartiles and maximum of |p| before sparsification */
+  int32_t iface_size_median;
+  int32_t iface_size_q3;
+  int32_t iface_size_max;
+  int32_t pad;
+  int64_t front_pivots;       /* sum of n_s */
+  int64_t iface_unknowns_in;  /* sum of |p| before the sparsification */
+  int64_t iface_unknowns_out; /* sum of the ranks r_p */
+  int64_t nbr_cols;           /* sum of m_p */
+  int64_t top_separator;      /* unknowns of the root separator at the start of the stage */
+  int64_t factor_bytes;       /* bytes of factors the stage stored */
+  double flops_front;         /* algorithmic flops of the phases (as in spaqr_stats_t) */
+  double flops_scale;
+  double flops_sparsify;
+  double ms_front;            /* device time of the phases */
+  double ms_scale;
+  double ms_sparsify;         /* CPQRs and the dense interface operators */
+  double ms_merge;
+} spaqr_stage_stats_t;
+spaqr_status spaqr_stage_stats(const spaqr_handle* h, int stage, spaqr_stage_stats_t* out);
+
+/* The interfaces sparsified at stage k, four int32 per interface:
+ * (cluster, |p|, m_p, r_p) in cluster order (Section 2.5-2.6 sizes and the
+ * rank the ratio rule chose).  Same query protocol as
+ * spaqr_symbolic_stage_info (len counts int32 entries). */
+spaqr_status spaqr_stage_interfaces(const spaqr_handle* h, int stage, int32_t* buf, int64_t cap,
+                                    int64_t* len);
+
+/* Residual history of the handle's last spaqr_solve, first column: the
+ * FGMRES estimate |g_{j+1}| / ||b|| after every Arnoldi step j, then the
+ * true relative residual of the returned x as the last entry.  Same query
+ * protocol (len counts doubles).  Errors: EINVAL. */
+spaqr_status spaqr_solve_history(const spaqr_handle* h, double* buf, int64_t cap, int64_t* len);
 
 /* Sizes of the stage-k clusters after stage k's sparsification (ranks of
  * sparsified interfaces; unchanged sizes otherwise).  Same query protocol as
@@ -255,8 +306,71 @@ spaqr_status spaqr_profile_enable(int on, const char* only);
 spaqr_status spaqr_profile_query(const char* kernel, int64_t* launches, double* total_ms,
                                  double* flops, double* bytes);
 
+/* Launches of one kernel family since the process started (or since the
+ * last reset), counted by the launchers whatever the profiler's state: the
+ * kernel template's name, e.g. "k_qr_reg", "k_qr", "k_trail", "k_scale_small",
+ * "k_scale_right", "k_cpqr_reg", "k_cpqr_coop", "k_sparsify",
+ * "k_ap_front_fwd_wy", "k_ap_front_bwd_reg", "k_ap_iface_fwd",
+ * "k_ap_iface_bwd", "k_ap_iface_dense", "k_iface_form", "k_copy".  Tests use
+ * it to show which kernel paths a case exercised.  kernel == NULL resets
+ * every count (and writes 0).  Unknown names give 0.  Errors: EINVAL if
+ * count is NULL. */
+spaqr_status spaqr_kernel_launches(const char* kernel, int64_t* count);
+
 /* Releases all host and device memory of the handle.  NULL is a no-op. */
 void spaqr_free(spaqr_handle* h);
+
+/* Kernel dispatch thresholds (tile and block-size schedule), process-wide.
+ * They choose which kernel runs each block, never what is computed: every
+ * setting gives the same factorization up to rounding order.
+ *   qr_reg_max_rows   fronts and scaling blocks of at most this many rows
+ *                     are factored by the register-panel QR, taller ones by
+ *                     the LDS-panel QR (256, 512 or 1024; default 1024);
+ *   split_rows,       a front with more rows than split_rows, or at least
+ *   split_cols        split_cols trailing columns, is factored as its pivot
+ *                     block alone, its trailing columns updated slice by
+ *                     slice (default 1024 and 1024);
+ *   cpqr_reg          1: interfaces whose columns fit in registers take the
+ *                     register CPQR; 0: they take the other kernels
+ *                     (default 1);
+ *   cpqr_coop         1: interfaces beyond the register CPQR take the
+ *                     cooperative multi-workgroup CPQR when its workgroups
+ *                     can be co-resident; 0: they take the single-workgroup
+ *                     LDS kernel (up to 64 FP32 / 32 FP64 unknowns) or the
+ *                     generic one (default 1);
+ *   scale_small       scaling blocks of at most this size in both
+ *                     dimensions take the fused LDS kernel (0, 16, 32 or 64;
+ *                     default 64);
+ *   iface_dense       interfaces of at most this many unknowns get dense
+ *                     apply operators (0, 16, 32 or 64; default 64);
+ *   trail_mfma        1: the trailing columns of a split front are updated
+ *                     on the matrix cores, 64 reflectors and 64 columns at a
+ *                     time; 0: by the vector-ALU slice kernel (default 1).
+ * spaqr_set_tuning(NULL) restores the defaults.  Set it only while no
+ * factorization or apply is in flight.  Errors: EINVAL for a value outside
+ * the ranges above. */
+typedef struct {
+  int qr_reg_max_rows;
+  int split_rows, split_cols;
+  int cpqr_reg;
+  int cpqr_coop;
+  int scale_small;
+  int iface_dense;
+  int trail_mfma;
+} spaqr_tuning;
+spaqr_status spaqr_set_tuning(const spaqr_tuning* t);
+spaqr_status spaqr_get_tuning(spaqr_tuning* t);
+
+/* Returns to the HIP runtime the memory the library keeps for reuse across
+ * calls (its cache of freed device blocks, its pool of pinned staging
+ * buffers) and the profiler's pending events, after a device
+ * synchronization.  Memory still owned by live handles, servers, analyses or
+ * orderings is untouched.  Meant for process teardown: call it after freeing
+ * every object and before the HIP runtime unloads (the Python binding calls
+ * it from an interpreter exit hook), so that no HIP call of this library runs
+ * during static destruction.  The library stays usable afterwards; the
+ * caches refill on demand.  Never fails. */
+void spaqr_finalize(void);
 
 /* ----------------------------------------------------------------- serving */
 /* Continuous-batching request loop (no counterpart in the paper, which
@@ -267,11 +381,14 @@ void spaqr_free(spaqr_handle* h);
  *   request's work runs on (NULL: the default stream).  The server owns the
  *   factors of its requests.
  * spaqr_submit: copies A, the ordering, the options (NULL: defaults) and
- *   b (host, n x nrhs column-major, ld = n) and queues the request; *ticket
- *   names it.  Returns ENOMEM if the request's estimated memory (factors plus
- *   FGMRES bases) alone exceeds the budget, EINVAL on bad arguments.
+ *   b (host, n x nrhs column-major, ld = n), runs the symbolic analysis
+ *   (host) and queues the request; *ticket names it.  The request's
+ *   estimated memory is spaqr_estimate_bytes of that analysis.  Returns
+ *   ENOMEM if that estimate alone exceeds the budget, EINVAL on bad
+ *   arguments or a malformed matrix.
  * spaqr_server_step: one round of the loop: (1) admits queued requests in
- *   arrival order while the budget allows (symbolic analysis and upload);
+ *   arrival order while the sum of the resident requests' estimates stays
+ *   within the budget (matrix upload and set-up);
  *   (2) advances every admitted request that is still factoring by one stage,
  *   all of them together: their fronts, scalings and sparsifications share
  *   one launch per phase whatever stage each one is at, so a request that
@@ -296,6 +413,24 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active);
 spaqr_status spaqr_poll(spaqr_server* srv, uint64_t ticket, double* x,
                         spaqr_solve_info* info);
 void spaqr_server_destroy(spaqr_server* srv);
+/* Occupancy of a server: requests queued (submitted, not admitted),
+ * requests resident (admitted, factoring or waiting for their solve), and
+ * the sum of the resident requests' estimates in bytes (any pointer may be
+ * NULL).  Errors: EINVAL for a NULL server. */
+spaqr_status spaqr_server_status(const spaqr_server* srv, int64_t* queued, int64_t* resident,
+                                 size_t* bytes);
+
+/* Upper bound on the device memory, in bytes, that a factorization of the
+ * analysed matrix (with opts->precision, NULL: defaults) and a solve of nrhs
+ * right-hand sides hold at their peak.  Every block, front and interface is
+ * sized as if nothing were compressed (ranks never exceed cluster sizes):
+ * the persistent factors and apply lists, the largest stage workspace, two
+ * stage block pools, the descriptor lists, each bounded by the arena
+ * reservations the library makes for them, plus the FGMRES bases of nrhs
+ * columns (2 * restart + 8 vectors each).  The server admits requests by it.
+ * Errors: EINVAL (NULL argument, nrhs < 1, precision not 32 or 64). */
+spaqr_status spaqr_estimate_bytes(const spaqr_symbolic* sym, const spaqr_opts* opts, int64_t nrhs,
+                                  size_t* bytes);
 
 #ifdef __cplusplus
 }

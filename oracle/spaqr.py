@@ -165,11 +165,21 @@ def _initial_blocks(Ahp, starts, ends):
     return bm
 
 
-def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
+def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_colour="ascending", trace=None):
     """Factorize A with spaQR (Algorithm 2).  A: scipy sparse, N x N.
 
     Returns an OracleFactorization with .ops (for apply), .perm, .Dc and
-    per-stage records in .stages[k]."""
+    per-stage records in .stages[k].
+
+    within_colour: order of the fronts (R5) and interfaces (R8) inside one
+    colour class, "ascending" (the reading) or "descending"; by the colouring
+    the result must not depend on it.
+    trace: optional callable trace(k, event, blocks) receiving a copy of the
+    block dictionary {(i, j): array} at events "before_scaling" and
+    "after_scaling" of every sparsified stage (a record only)."""
+    if within_colour not in ("ascending", "descending"):
+        raise ValueError("within_colour is 'ascending' or 'descending'")
+    wsign = 1 if within_colour == "ascending" else -1
     if not scale:
         raise NotImplementedError("only the scaled variant (Section 2.6) is implemented")
     A = sp.csr_matrix(A, dtype=np.float64)
@@ -231,7 +241,7 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
             nbr[t].discard(t)
         fcol = _greedy_colour(len(fronts), nbr)
         rec["fronts"] = {s: (fstruct[s][0], fstruct[s][1], int(fcol[fidx[s]])) for s in fronts}
-        order = sorted(fronts, key=lambda s: (fcol[fidx[s]], s))
+        order = sorted(fronts, key=lambda s: (fcol[fidx[s]], wsign * s))
         for s in order:
             n1, cols, nonanc = fstruct[s]
             rows = [s] + n1
@@ -293,6 +303,8 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
                 if np.any(np.diag(Rpp) == 0.0):
                     continue
                 Uf[p] = (qrU, tauU, Rpp)
+            if trace is not None:
+                trace(k, "before_scaling", {key: B.copy() for key, B in bm.blk.items()})
             for (i, j), B in list(bm.blk.items()):
                 if i == j and i in Uf:
                     bm.blk[(i, j)] = np.eye(B.shape[0])
@@ -304,6 +316,8 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
                 if j in Uf:
                     B = sla.solve_triangular(Uf[j][2], B.T, trans="T", lower=False).T
                 bm.blk[(i, j)] = np.ascontiguousarray(B)
+            if trace is not None:
+                trace(k, "after_scaling", {key: B.copy() for key, B in bm.blk.items()})
             for p in remaining:
                 if p in Uf:
                     V, tauv = _reflectors(Uf[p][0], Uf[p][1])
@@ -318,7 +332,8 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
             icol = _greedy_colour(len(remaining), nbr)
             rec["iface_colour"] = {p: int(icol[ridx[p]]) for p in remaining}
             ranks = {}
-            for p in sorted(remaining, key=lambda p: (icol[ridx[p]], p)):
+            shapes = {}
+            for p in sorted(remaining, key=lambda p: (icol[ridx[p]], wsign * p)):
                 sz = len(slots[p])
                 if p not in Uf:
                     ranks[p] = sz
@@ -330,6 +345,7 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
                 C = np.hstack(parts) if parts else np.zeros((sz, 0))
                 r, Vq, tq, W, rdiag, piv = cpqr_ratio(C, eps)
                 ranks[p] = r
+                shapes[p] = (sz, C.shape[1], r)
                 if r == sz:
                     continue
                 off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
@@ -342,6 +358,9 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False):
                 F.ops.append(("sparsify", k, p, slots[p].copy(), Vq, tq, r))
                 slots[p] = slots[p][:r]
             rec["ranks"] = ranks
+            # (|p|, m, r) of every CPQR taken: the interface size, the columns
+            # of C and the rank (a record only; no arithmetic depends on it)
+            rec["cpqr_shapes"] = shapes
         rec["sizes_post"] = np.array([len(s) for s in slots], dtype=np.int64)
         # ---------------- merge (Section 2.7) ----------------
         if k > 1:

@@ -20,7 +20,7 @@ from ._abi import CSR, Opts, SolveInfo, SpaqrError, check
 
 __all__ = ["order_grid", "analyze", "factor", "factor_device", "factor_batch", "solve_batch", "DeviceCSR",
            "GridOrdering", "Symbolic", "Factorization", "Server", "SpaqrError", "load_library", "profile_enable",
-           "profile_query"]
+           "profile_query", "kernel_launches", "get_tuning", "set_tuning"]
 
 
 def load_library():
@@ -57,12 +57,17 @@ class GridOrdering:
         self.dims = dims
         self.n = lib.spaqr_ordering_n(h)
         self.levels = lib.spaqr_ordering_levels(h)
+        _abi.track("ordering", self)
+
+    def close(self):
+        # after the exit hook (or once module globals are gone) the handle
+        # was already released
+        if getattr(self, "_h", None) and _abi is not None and not _abi.released():
+            _abi.load().spaqr_ordering_free(self._h)
+        self._h = None
 
     def __del__(self):
-        # at interpreter exit the module globals may already be gone
-        if getattr(self, "_h", None) and _abi is not None:
-            _abi.load().spaqr_ordering_free(self._h)
-            self._h = None
+        self.close()
 
     @property
     def handle(self):
@@ -111,16 +116,28 @@ class Symbolic:
         check(lib.spaqr_analyze(C.byref(csr), ordering.handle, C.byref(o), C.byref(h)), "spaqr_analyze")
         self._h = h
         self.levels = ordering.levels
+        _abi.track("symbolic", self)
+
+    def close(self):
+        if getattr(self, "_h", None) and _abi is not None and not _abi.released():
+            _abi.load().spaqr_symbolic_free(self._h)
+        self._h = None
 
     def __del__(self):
-        # at interpreter exit the module globals may already be gone
-        if getattr(self, "_h", None) and _abi is not None:
-            _abi.load().spaqr_symbolic_free(self._h)
-            self._h = None
+        self.close()
 
     @property
     def handle(self):
         return self._h
+
+    def estimate_bytes(self, precision=32, nrhs=1, restart=100):
+        """Upper bound on the device bytes of a factorization of this analysis
+        and a solve of nrhs right-hand sides (spaqr_estimate_bytes)."""
+        o = make_opts(precision=precision, restart=restart)
+        out = C.c_size_t()
+        check(_abi.load().spaqr_estimate_bytes(self._h, C.byref(o), int(nrhs), C.byref(out)),
+              "spaqr_estimate_bytes")
+        return out.value
 
     def stage_info(self, stage, what):
         lib = _abi.load()
@@ -178,6 +195,7 @@ class Factorization:
             self._h = _handle
             self._sym = symbolic
             self.n = A.shape[0]
+            _abi.track("factor", self)
             return
         lib = _abi.load()
         csr, keep = _csr_struct(A)
@@ -198,15 +216,15 @@ class Factorization:
         self._h = h
         self._sym = symbolic   # the handle reads the analysis it was made from
         self.n = A.shape[0]
-
-    def __del__(self):
-        # at interpreter exit the module globals may already be gone
-        if getattr(self, "_h", None) and _abi is not None:
-            _abi.load().spaqr_free(self._h)
-            self._h = None
+        _abi.track("factor", self)
 
     def close(self):
-        self.__del__()
+        if getattr(self, "_h", None) and _abi is not None and not _abi.released():
+            _abi.load().spaqr_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
 
     # vectors: numpy (host) or torch CUDA tensors (device), shape (n,) or (n, nrhs)
     @staticmethod
@@ -266,6 +284,34 @@ class Factorization:
         d = {k: getattr(s, k) for k, _ in _abi.Stats._fields_ if k != "ms_phase"}
         d["ms_phase"] = list(s.ms_phase)
         return d
+
+    def stage_stats(self, stage):
+        """Per-stage statistics of the completed factorization (spaqr_stage_stats)."""
+        st = _abi.StageStats()
+        check(_abi.load().spaqr_stage_stats(self._h, int(stage), C.byref(st)), "spaqr_stage_stats")
+        return {k: getattr(st, k) for k, _ in _abi.StageStats._fields_ if k != "pad"}
+
+    def stage_interfaces(self, stage):
+        """(cluster, |p|, m_p, r_p) of every interface sparsified at the stage,
+        an int32 array of shape (count, 4)."""
+        lib = _abi.load()
+        n = C.c_int64()
+        check(lib.spaqr_stage_interfaces(self._h, int(stage), None, 0, C.byref(n)), "spaqr_stage_interfaces")
+        buf = np.empty(max(1, n.value), dtype=np.int32)
+        check(lib.spaqr_stage_interfaces(self._h, int(stage), buf.ctypes.data_as(C.POINTER(C.c_int32)), buf.size,
+                                         C.byref(n)), "spaqr_stage_interfaces")
+        return buf[:n.value].reshape(-1, 4)
+
+    def solve_history(self):
+        """FGMRES residual estimates per Arnoldi step of the last solve's first
+        column, then its true relative residual (spaqr_solve_history)."""
+        lib = _abi.load()
+        n = C.c_int64()
+        check(lib.spaqr_solve_history(self._h, None, 0, C.byref(n)), "spaqr_solve_history")
+        buf = np.empty(max(1, n.value), dtype=np.float64)
+        check(lib.spaqr_solve_history(self._h, buf.ctypes.data_as(C.POINTER(C.c_double)), buf.size, C.byref(n)),
+              "spaqr_solve_history")
+        return buf[:n.value]
 
     def stage_sizes(self, stage):
         lib = _abi.load()
@@ -383,6 +429,37 @@ def profile_enable(on=True, only=None):
     (one name, or a prefix ending in '*', e.g. 'host_*' for the host phases)."""
     check(_abi.load().spaqr_profile_enable(1 if on else 0, only.encode() if only else None),
           "spaqr_profile_enable")
+
+
+def get_tuning():
+    """The kernel dispatch thresholds (spaqr_get_tuning) as a dict."""
+    t = _abi.Tuning()
+    check(_abi.load().spaqr_get_tuning(C.byref(t)), "spaqr_get_tuning")
+    return {k: getattr(t, k) for k, _ in _abi.Tuning._fields_}
+
+
+def set_tuning(**kw):
+    """Set some dispatch thresholds (the others keep their values); with no
+    argument, restore the defaults (spaqr_set_tuning)."""
+    lib = _abi.load()
+    if not kw:
+        check(lib.spaqr_set_tuning(None), "spaqr_set_tuning")
+        return
+    cur = get_tuning()
+    unknown = set(kw) - set(cur)
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    cur.update(kw)
+    check(lib.spaqr_set_tuning(C.byref(_abi.Tuning(**cur))), "spaqr_set_tuning")
+
+
+def kernel_launches(kernel=None):
+    """Launches of one kernel family (e.g. 'k_qr', 'k_cpqr_coop') since the
+    last reset; kernel=None resets every count."""
+    n = C.c_int64()
+    check(_abi.load().spaqr_kernel_launches(kernel.encode() if kernel else None, C.byref(n)),
+          "spaqr_kernel_launches")
+    return n.value
 
 
 def profile_query(kernel):

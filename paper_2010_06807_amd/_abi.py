@@ -2,8 +2,10 @@
 
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspaqr.so")
@@ -24,6 +26,24 @@ class CSRDev(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("skip", C.c_int), ("scale", C.c_int), ("precision", C.c_int),
                 ("restart", C.c_int), ("maxit", C.c_int)]
+
+
+class StageStats(C.Structure):
+    _fields_ = [("stage", C.c_int32), ("sparsified", C.c_int32), ("fronts", C.c_int32),
+                ("max_front_rows", C.c_int32), ("max_front_pivots", C.c_int32), ("interfaces", C.c_int32),
+                ("max_nbr_cols", C.c_int32), ("iface_size_q1", C.c_int32), ("iface_size_median", C.c_int32),
+                ("iface_size_q3", C.c_int32), ("iface_size_max", C.c_int32), ("pad", C.c_int32),
+                ("front_pivots", C.c_int64), ("iface_unknowns_in", C.c_int64), ("iface_unknowns_out", C.c_int64),
+                ("nbr_cols", C.c_int64), ("top_separator", C.c_int64), ("factor_bytes", C.c_int64),
+                ("flops_front", C.c_double), ("flops_scale", C.c_double), ("flops_sparsify", C.c_double),
+                ("ms_front", C.c_double), ("ms_scale", C.c_double), ("ms_sparsify", C.c_double),
+                ("ms_merge", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("qr_reg_max_rows", C.c_int), ("split_rows", C.c_int), ("split_cols", C.c_int),
+                ("cpqr_reg", C.c_int), ("cpqr_coop", C.c_int), ("scale_small", C.c_int), ("iface_dense", C.c_int),
+                ("trail_mfma", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -82,9 +102,51 @@ SIGNATURES = {
     "spaqr_server_step": (C.c_int, [_P, C.POINTER(C.c_int)]),
     "spaqr_poll": (C.c_int, [_P, C.c_uint64, _P, C.POINTER(SolveInfo)]),
     "spaqr_server_destroy": (None, [_P]),
+    "spaqr_finalize": (None, []),
+    "spaqr_stage_stats": (C.c_int, [_P, C.c_int, C.POINTER(StageStats)]),
+    "spaqr_stage_interfaces": (C.c_int, [_P, C.c_int, _I32P, C.c_int64, _I64P]),
+    "spaqr_solve_history": (C.c_int, [_P, _DP, C.c_int64, _I64P]),
+    "spaqr_set_tuning": (C.c_int, [C.POINTER(Tuning)]),
+    "spaqr_get_tuning": (C.c_int, [C.POINTER(Tuning)]),
+    "spaqr_kernel_launches": (C.c_int, [C.c_char_p, _I64P]),
+    "spaqr_server_status": (C.c_int, [_P, _I64P, _I64P, C.POINTER(C.c_size_t)]),
+    "spaqr_estimate_bytes": (C.c_int, [_P, C.POINTER(Opts), C.c_int64, C.POINTER(C.c_size_t)]),
 }
 
 _lib = None
+
+# Library objects alive in this process, by kind, in the order the exit hook
+# releases them (a factorization reads its analysis, so it goes first).
+_KINDS = ("factor", "server", "symbolic", "ordering")
+_live = {k: weakref.WeakSet() for k in _KINDS}
+_closed = False
+
+
+def track(kind, obj):
+    _live[kind].add(obj)
+
+
+def released():
+    """True once the exit hook has run: handles were freed there, and later
+    destructors must not call into the library."""
+    return _closed
+
+
+def _exit_hook():
+    """Frees every live handle and then the library's caches while the HIP
+    runtime is still fully up (Python's exit hooks run before C++ static
+    destruction and before the runtime unloads)."""
+    global _closed
+    if _closed or _lib is None:
+        return
+    for kind in _KINDS:
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+    _lib.spaqr_finalize()
+    _closed = True
 
 
 def load():
@@ -94,12 +156,18 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_06807_amd.build`")
+    try:
+        # registered after torch's own hooks, so it runs before them
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
     _lib = lib
+    atexit.register(_exit_hook)
     return lib
 
 

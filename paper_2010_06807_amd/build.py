@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libspaqr.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["ordering.cpp", "symbolic.cpp", "factor.cpp", "abi.cpp", "server.cpp", "profile.cpp", "mem.cpp",
+SOURCES = ["ordering.cpp", "symbolic.cpp", "factor.cpp", "abi.cpp", "server.cpp", "profile.cpp", "mem.cpp", "tuning.cpp",
            "kernels.hip", "gmres.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

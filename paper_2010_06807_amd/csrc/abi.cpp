@@ -194,14 +194,10 @@ spaqr_status spaqr_factor(const spaqr_csr* A, const spaqr_ordering* ord, const s
                           void* hip_stream, spaqr_handle** out) {
   return guarded([&]() -> spaqr_status {
     SPAQR_REQUIRE(A && ord && out, SPAQR_EINVAL, "NULL argument");
-    const double t0 = now_ms();
     std::unique_ptr<Symbolic> s(analyze(A, ord->o, opts ? opts->skip : 2));
-    const double ts = now_ms() - t0;
     const Symbolic& ref = *s;
     SPAQR_REQUIRE(A->val, SPAQR_EINVAL, "NULL values");
-    spaqr_status st = factor_impl(A, nullptr, ref, opts, hip_stream, out, std::move(s));
-    if (st == SPAQR_OK) const_cast<Stats&>((*out)->e->stats()).s.ms_symbolic = ts;
-    return st;
+    return factor_impl(A, nullptr, ref, opts, hip_stream, out, std::move(s));
   });
 }
 
@@ -384,20 +380,22 @@ spaqr_status spaqr_solve(spaqr_handle* h, const double* b, double* x, int64_t nr
     int st;
     const std::vector<double> tv((size_t)nrhs, tol);
     EngineBase& e = *h->e;
+    std::vector<double> hist;
     if (on_device) {
       SPAQR_REQUIRE(b != x, SPAQR_EINVAL, "b and x must not alias in spaqr_solve");
-      st = fgmres_solve(e, b, ld, x, ld, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info);
+      st = fgmres_solve(e, b, ld, x, ld, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info, &hist);
     } else {
       double *db = nullptr, *dx = nullptr;
       to_device(h, b, nrhs, ld, &db);
       dx = static_cast<double*>(dev_alloc((size_t)N * nrhs * sizeof(double), s));
-      st = fgmres_solve(e, db, N, dx, N, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info);
+      st = fgmres_solve(e, db, N, dx, N, (int)nrhs, tv.data(), e.opt_restart(), e.opt_maxit(), info, &hist);
       SPAQR_HIP(hipMemcpy2DAsync(x, ld * sizeof(double), dx, N * sizeof(double), N * sizeof(double), nrhs,
                                  hipMemcpyDeviceToHost, s));
       dev_free(db, s);
       dev_free(dx, s);
     }
     SPAQR_HIP(hipStreamSynchronize(s));
+    e.set_history(std::move(hist));
     return st;
   });
 }
@@ -422,6 +420,55 @@ spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf, i
     }
     return SPAQR_OK;
   });
+}
+
+spaqr_status spaqr_stage_stats(const spaqr_handle* h, int stage, spaqr_stage_stats_t* out) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(h && out, SPAQR_EINVAL, "NULL argument");
+    SPAQR_REQUIRE(h->e->stages_left() == 0 && h->e->error() == SPAQR_OK, SPAQR_EINVAL,
+                  "the factorization is not complete");
+    const auto& st = h->e->stats().stage;
+    SPAQR_REQUIRE(stage >= 1 && stage < (int)st.size(), SPAQR_EINVAL, "bad stage");
+    *out = st[stage];
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_stage_interfaces(const spaqr_handle* h, int stage, int32_t* buf, int64_t cap, int64_t* len) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(h && len, SPAQR_EINVAL, "NULL argument");
+    const auto& fi = h->e->stats().ifaces;
+    SPAQR_REQUIRE(stage >= 1 && stage < (int)fi.size(), SPAQR_EINVAL, "bad stage");
+    *len = (int64_t)fi[stage].size();
+    if (buf) {
+      SPAQR_REQUIRE(cap >= *len, SPAQR_EINVAL, "buffer too small");
+      std::memcpy(buf, fi[stage].data(), fi[stage].size() * sizeof(int32_t));
+    }
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_solve_history(const spaqr_handle* h, double* buf, int64_t cap, int64_t* len) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(h && len, SPAQR_EINVAL, "NULL argument");
+    const auto& hi = h->e->stats().history;
+    *len = (int64_t)hi.size();
+    if (buf) {
+      SPAQR_REQUIRE(cap >= *len, SPAQR_EINVAL, "buffer too small");
+      std::memcpy(buf, hi.data(), hi.size() * sizeof(double));
+    }
+    return SPAQR_OK;
+  });
+}
+
+void spaqr_prof_release();
+
+void spaqr_finalize(void) {
+  try {
+    spaqr_prof_release();
+    mem_release_all();
+  } catch (...) {
+  }
 }
 
 void spaqr_free(spaqr_handle* h) {

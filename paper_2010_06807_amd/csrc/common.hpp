@@ -56,6 +56,10 @@ struct Ordering {
 
 Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels);
 
+// Process-wide kernel dispatch thresholds (spaqr_tuning); read when a stage
+// is planned and launched.
+const spaqr_tuning& tuning();
+
 }  // namespace spaqr
 
 struct spaqr_ordering {

@@ -92,7 +92,8 @@ struct StageApply {
   int max_bwd_rows = 0;                  // max n + k
   int max_n = 0, max_k = 0;              // largest front and ancestor-column widths
   int jb = 1;                            // QR panel width of the stage's fronts
-  int64_t nifaces_small = 0;             // interfaces of <= 64 unknowns come first
+  int64_t nifaces_small = 0;             // interfaces with dense operators come first
+  int dense_max = 64;                    // largest interface given dense operators
   int64_t nfronts = 0;
   ApIface<T>* ifaces = nullptr;
   int64_t nifaces = 0;
@@ -111,6 +112,25 @@ struct StageApply {
 struct Stats {
   spaqr_stats_t s{};
   std::vector<std::vector<int32_t>> stage_sizes;  // index k: sizes after stage k
+  std::vector<spaqr_stage_stats_t> stage;         // index k: per-stage statistics
+  std::vector<std::vector<int32_t>> ifaces;       // index k: (cluster, |p|, m_p, r_p) per interface
+  std::vector<double> history;                    // last solve: residual estimates, then the true residual
+};
+
+// HIP events around the phases of one batched stage: start, after the fronts,
+// after the scaling, after the sparsification, after the merge.  Shared by the
+// factorizations advanced together in that stage.
+struct PhaseEvents {
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  PhaseEvents();
+  ~PhaseEvents();
+  PhaseEvents(const PhaseEvents&) = delete;
+  PhaseEvents& operator=(const PhaseEvents&) = delete;
+  void record(int i, hipStream_t s);
+  double ms(int i) const;  // elapsed between e[i] and e[i + 1] (the events must be complete), 0 if unrecorded
+
+ private:
+  unsigned done_ = 0;  // bit i: e[i] recorded
 };
 
 // What FGMRES needs of a system: n rows per column, the preconditioner and
@@ -128,12 +148,16 @@ class KrylovOp {
 
 class EngineBase : public KrylovOp {
  public:
+  // x = M^{-1} b with the caller's workspace ws (n * nrhs doubles) for the
+  // permuted vectors: enqueued on stream(), allocates nothing
+  virtual void apply_ws(const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, double* ws) = 0;
   virtual const Stats& stats() const = 0;
   virtual int opt_restart() const = 0;
   virtual int opt_maxit() const = 0;
   virtual int stages_left() const = 0;  // 0 once the factorization is complete (or failed)
   virtual int precision() const = 0;    // 32 or 64
   virtual int error() const = 0;        // SPAQR_OK, or the status of a failed factorization
+  virtual void set_history(std::vector<double> h) = 0;  // residual history of the last solve
   virtual const char* error_message() const = 0;
 };
 
@@ -161,7 +185,8 @@ std::unique_ptr<KrylovOp> make_batch_op(const std::vector<EngineBase*>& es, cons
 
 // FGMRES on the device (gmres.hip); tol holds one tolerance per column.
 int fgmres_solve(KrylovOp& op, const double* b, int64_t ldb, double* x, int64_t ldx, int ncols,
-                 const double* tol, int restart, int maxit, spaqr_solve_info* info);
+                 const double* tol, int restart, int maxit, spaqr_solve_info* info,
+                 std::vector<double>* history = nullptr);
 // FGMRES for several factored problems at once (make_batch_op): problem i
 // solves nrhs[i] columns b[i] -> x[i] (device, column-major, ld = its n) to
 // tol[i].  info receives one entry per column in problem order; status (may

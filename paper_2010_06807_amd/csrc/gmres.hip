@@ -166,7 +166,7 @@ static void dots(const double* X, int64_t sj, int64_t sc, int J, const double* w
 }
 
 int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t ldx, int nrhs, const double* tol,
-                 int restart, int maxit_in, spaqr_solve_info* info) {
+                 int restart, int maxit_in, spaqr_solve_info* info, std::vector<double>* history) {
   const double t0 = now_ms();
   hipStream_t s = e.stream();
   const int64_t N = e.n();
@@ -285,6 +285,7 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
         its[c]++;
         jend[c] = j + 1;
         const double est = std::fabs(gc[j + 1]) / bnorm[c];
+        if (history && c == 0) history->push_back(est);
         if (est <= tol[c] || its[c] >= maxit || col[j] == 0.0) active[c] = 0;
         still = still || active[c];
       }
@@ -324,6 +325,7 @@ int fgmres_solve(KrylovOp& e, const double* b, int64_t ldb, double* x, int64_t l
     }
   }
   SPAQR_HIP(hipGetLastError());
+  if (history) history->push_back(rel[0]);
   const double dt = (now_ms() - t0) / 1000.0;
   int status = SPAQR_OK;
   for (int c = 0; c < nrhs; ++c) {

@@ -16,11 +16,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "profile.hpp"
 
 namespace spaqr {
 
@@ -761,6 +764,182 @@ __global__ void __launch_bounds__(NT) k_trail(const TrailDesc<T>* __restrict__ d
   }
   if (live)
     for (int r = g; r < m; r += TY) col[(int64_t)r * ldc] = Cs[r * LC + c];
+}
+
+// ------------------------------------------------------------------------
+// Blocked WY trailing update on the matrix cores (Section 2.4: H_s^T applied
+// to the trailing columns of a front, or U_pp^T to the blocks right of a
+// scaled interface).  The reflectors of a factored pivot block are taken 64
+// at a time, H_j0 ... H_{j0+63} = I - V_b T_b V_b^T, and every 64-column tile
+// C of the trailing matrix gets C <- C - V_b (T_b^T (V_b^T C)): two
+// contractions over the rows, on FP32 (or FP64) MFMA 16x16x4 tiles with
+// accumulation in the same precision.
+//
+// One 16x16x4 MFMA multiplies A (16 x 4) by B (4 x 16) into D (16 x 16); lane
+// l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator v of lane l
+// holds D[row(l / 16, v)][l % 16]: row 4 (l / 16) + v for FP32, row
+// l / 16 + 4 v for FP64 (the two instructions distribute D's rows
+// differently, as measured on gfx950).
+template <typename T>
+struct Mfma16;
+template <>
+struct Mfma16<float> {
+  typedef float acc __attribute__((ext_vector_type(4)));
+  __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int kk, int v) { return 4 * kk + v; }
+};
+template <>
+struct Mfma16<double> {
+  typedef double acc __attribute__((ext_vector_type(4)));
+  __device__ static acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int kk, int v) { return kk + 4 * v; }
+};
+
+constexpr int WYB = 64;  // reflectors per block, columns per tile
+
+// v_i(r) of the factored pivot block: explicit below the diagonal, the unit
+// diagonal and the zeros above it implied (i = reflector index, global)
+template <typename T>
+__device__ __forceinline__ T wy_v(const T* a, int64_t ld, int m, int nref, int r, int i) {
+  if (i >= nref || r >= m || r < i) return T(0);
+  return r == i ? T(1) : a[(int64_t)r * ld + i];
+}
+
+// T_b of one block of 64 reflectors from G = V_b^T V_b and tau: T[i][i] =
+// tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i] (the forward, columnwise
+// compact-WY recurrence).  One workgroup (4 waves) per block: wave w forms
+// rows 16 w .. 16 w + 15 of G on the matrix cores; wave 0 then runs the
+// recurrence in LDS.  T_b is written row-major 64 x 64, zero outside the
+// upper triangle of the block's nb reflectors.
+template <typename T>
+__global__ void __launch_bounds__(256) k_wy_tblock(const WYBlock<T>* __restrict__ ds) {
+  using M = Mfma16<T>;
+  const WYBlock<T> d = ds[blockIdx.x];
+  __shared__ T G[WYB][WYB + 1];
+  __shared__ T Tm[WYB][WYB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j0 = d.j0, nref = d.n, m = d.m;
+  const int64_t ld = d.ld;
+  const int nb = min(WYB, nref - j0);
+  const int kk = lane >> 4, ii = lane & 15;
+  typename M::acc acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = typename M::acc{0, 0, 0, 0};
+  for (int r = j0; r < m; r += 16) {
+    T av[4], bv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int rr = r + 4 * u + kk;
+      av[u] = wy_v(d.a, ld, m, j0 + nb, rr, j0 + 16 * wv + ii);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[u][t] = wy_v(d.a, ld, m, j0 + nb, rr, j0 + 16 * t + ii);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = M::mma(av[u], bv[u][t], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[16 * wv + M::row(kk, v)][16 * t + ii] = acc[t][v];
+  for (int q = tid; q < WYB * WYB; q += 256) Tm[q / WYB][q % WYB] = T(0);
+  __syncthreads();
+  if (wv == 0) {
+    // column i of T: lane j < i forms T[j][i] from its own row of T
+    for (int i = 0; i < nb; ++i) {
+      const T tau_i = d.tau[j0 + i];
+      T y = T(0);
+      if (lane < i)
+        for (int q = lane; q < i; ++q) y += Tm[lane][q] * G[q][i];
+      // lane j reads and writes row j of T only: no exchange between lanes
+      if (lane < i) Tm[lane][i] = -tau_i * y;
+      if (lane == i) Tm[i][i] = tau_i;
+    }
+  }
+  __syncthreads();
+  T* out = d.tblk;
+  for (int q = tid; q < WYB * WYB; q += 256) out[q] = Tm[q / WYB][q % WYB];
+}
+
+// C <- H_0^T ... H_{n-1}^T C on one tile of at most 64 trailing columns
+// (WYTile), block by block: W = V_b^T C (64 x 64), U = T_b^T W, C -= V_b U.
+// Wave w forms rows 16 w .. 16 w + 15 of W and U; the update runs over
+// 16-row chunks of C, chunk q on wave q % 4.  C is re-read from memory for
+// every block (the tile is 64 columns by all the front's rows).
+template <typename T>
+__global__ void __launch_bounds__(256) k_trail_mfma(const WYTile<T>* __restrict__ ds) {
+  using M = Mfma16<T>;
+  const WYTile<T> d = ds[blockIdx.x];
+  if (d.flag && *d.flag != 0) return;
+  __shared__ T Ws[WYB][WYB + 1];
+  __shared__ T Us[WYB][WYB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int kk = lane >> 4, ii = lane & 15;
+  const int m = d.m, nref = d.n, cw = d.cw;
+  const int64_t ld = d.ld, ldc = d.ldc;
+  T* C = d.c + d.c0;
+  auto cval = [&](int r, int c) -> T { return (r < m && c < cw) ? C[(int64_t)r * ldc + c] : T(0); };
+  for (int j0 = 0, b = 0; j0 < nref; j0 += WYB, ++b) {
+    const int jend = min(nref, j0 + WYB);
+    // W = V_b^T C over rows j0 .. m - 1
+    typename M::acc acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = typename M::acc{0, 0, 0, 0};
+    for (int r = j0; r < m; r += 16) {
+      T av[4], bv[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int rr = r + 4 * u + kk;
+        av[u] = wy_v(d.a, ld, m, jend, rr, j0 + 16 * wv + ii);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bv[u][t] = cval(rr, 16 * t + ii);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = M::mma(av[u], bv[u][t], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Ws[16 * wv + M::row(kk, v)][16 * t + ii] = acc[t][v];
+    __syncthreads();
+    // U = T_b^T W (T_b row-major 64 x 64, upper triangular)
+    const T* Tb = d.tblk + (int64_t)b * WYB * WYB;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = typename M::acc{0, 0, 0, 0};
+    for (int q = 0; q < WYB; q += 4) {
+      const T a = Tb[(q + kk) * WYB + 16 * wv + ii];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = M::mma(a, Ws[q + kk][16 * t + ii], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Us[16 * wv + M::row(kk, v)][16 * t + ii] = acc[t][v];
+    __syncthreads();
+    // C -= V_b U on 16-row chunks
+    for (int r0 = j0 + 16 * wv; r0 < m; r0 += 64) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[t][v] = cval(r0 + M::row(kk, v), 16 * t + ii);
+      for (int q = 0; q < WYB; q += 4) {
+        const T a = -wy_v(d.a, ld, m, jend, r0 + ii, j0 + q + kk);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = M::mma(a, Us[q + kk][16 * t + ii], acc[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = r0 + M::row(kk, v), c = 16 * t + ii;
+          if (r < m && c < cw) C[(int64_t)r * ldc + c] = acc[t][v];
+        }
+    }
+    __syncthreads();
+  }
 }
 
 // Scaling of the blocks touching an interface (Algorithm 2, scaling step):
@@ -1621,13 +1800,30 @@ __global__ void __launch_bounds__(SP_NT) k_cpqr_reg(const SpDesc<T>* __restrict_
 // that stopped keep taking part in the barriers; the loop ends for the whole
 // grid once every interface has reported done (flags double-buffered by step
 // parity, so all workgroups read the same flags after a barrier).
+// Barrier of the nblk workgroups that factor one interface together (all
+// co-resident: the launch is cooperative).  cnt counts arrivals, gen is the
+// generation the waiters watch; the last to arrive resets cnt and advances
+// gen.  Each interface has its own pair, so interfaces of one launch never
+// wait for each other.
+__device__ __forceinline__ void team_sync(int* cnt, int* gen, int nblk) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (__hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nblk - 1) {
+      __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+}
+
 template <typename T, int CPT, bool LC>
 __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ descs, const SpNbr* __restrict__ nbrs,
                                                  const CoopItem* __restrict__ items, int nitems, int total_blocks,
                                                  int max_p, int max_nb, double* ckey, int* cpos, T* ccol, int* done,
                                                  int kmax_all) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
   extern __shared__ __align__(16) unsigned char smem[];
   T* vbuf = reinterpret_cast<T*>(smem);                      // max_p
   T* cl = vbuf + ((max_p + 3) & ~3);                          // LC: P x 64 CPT, this workgroup's columns
@@ -1698,19 +1894,17 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
       nr[j] = s2;
     }
   }
-  if (fin && g == 0 && lane == 0) {
-    done[it] = 1;
-    done[nitems + it] = 1;
-  }
+  // an interface that is not scaled keeps its size: its whole team leaves
+  // at once (fin is the same on every workgroup of the team)
   const int kmax = min(P, m);
   int r = 0;
   double R11 = 0.0;
-  for (int k = 0; k <= kmax_all; ++k) {
+  int* bar = done + 2 * it;  // this interface's barrier: arrivals, generation
+  for (int k = 0; !fin && k <= kmax_all; ++k) {
     const int buf = k & 1;
     // this workgroup's best live column: (norm desc, position asc)
     double wb = -1.0;
     int wp = 0x7fffffff, wc = -1;
-    if (!fin)
 #pragma unroll
       for (int j = 0; j < CPT; ++j)
         if (kel[j] < 0 && nr[j] >= 0.0 && (nr[j] > wb || (nr[j] == wb && pos[j] < wp))) {
@@ -1740,12 +1934,8 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
       ckey[buf * total_blocks + b] = wb;
       cpos[buf * total_blocks + b] = wp;
     }
-    grid.sync();
-    // every interface done (flags written before this barrier): leave together
-    int notdone = 0;
-    for (int i = lane; i < nitems; i += 64) notdone |= done[buf * nitems + i] == 0;
-    if (__ballot(notdone) == 0ull) break;
-    if (!fin) {
+    team_sync(bar, bar + 1, ci.nblk);
+    {
       // the interface's winner among its workgroups
       double gb = -1.0;
       int gp = 0x7fffffff, gw = -1;
@@ -1839,7 +2029,6 @@ __global__ void __launch_bounds__(64) k_cpqr_coop(const SpDesc<T>* __restrict__ 
         __syncthreads();
       }
     }
-    if (fin && g == 0 && lane == 0) done[((k + 1) & 1) * nitems + it] = 1;
   }
   if (P > 0 && *d.flag == 0 && r < P) {
 #pragma unroll
@@ -2553,9 +2742,11 @@ template <typename T>
 void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipStream_t s) {
   if (ntiles <= 0) return;
   if (transpose) {
+    count_launch("k_copy_t");
     hipLaunchKernelGGL(k_copy_t<T>, dim3((unsigned)ntiles), dim3(NT), 0, s, tiles);
     check_launch("k_copy_t");
   } else {
+    count_launch("k_copy");
     hipLaunchKernelGGL(k_copy<T>, dim3((unsigned)((ntiles + kCopyTiles - 1) / kCopyTiles)), dim3(NT), 0, s, tiles,
                        ntiles);
     check_launch("k_copy");
@@ -2564,6 +2755,7 @@ void launch_copy(const CopyTile<T>* tiles, int64_t ntiles, bool transpose, hipSt
 
 void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s) {
   if (n <= 0 || blocks <= 0) return;
+  count_launch("k_zero");
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, d, n);
   check_launch("k_zero");
 }
@@ -2571,6 +2763,7 @@ void launch_zero(const ZeroDesc* d, int64_t n, int64_t blocks, hipStream_t s) {
 template <typename T>
 void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return;
+  count_launch("k_fill");
   hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
   check_launch("k_fill");
 }
@@ -2578,12 +2771,14 @@ void launch_fill(T* p, int64_t n, T v, hipStream_t s) {
 template <typename T>
 void launch_scatter_nz(T* pool, const int64_t* dst, const double* val, int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
+  count_launch("k_scatter_nz");
   hipLaunchKernelGGL(k_scatter_nz<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, nnz);
   check_launch("k_scatter_nz");
 }
 
 void launch_colnorm(const int64_t* cptr, const int64_t* cidx, const double* val, int64_t n, double* dc,
                     int* zero_col, hipStream_t s) {
+  count_launch("k_colnorm");
   hipLaunchKernelGGL(k_colnorm, dim3(grid_for(n, 256)), dim3(256), 0, s, cptr, cidx, val, n, dc, zero_col);
   check_launch("k_colnorm");
 }
@@ -2592,6 +2787,7 @@ template <typename T>
 void launch_scatter_scaled(T* pool, const int64_t* dst, const double* val, const int32_t* col, const double* dc,
                            int64_t nnz, hipStream_t s) {
   if (nnz <= 0) return;
+  count_launch("k_scatter_scaled");
   hipLaunchKernelGGL(k_scatter_scaled<T>, dim3(grid_for(nnz, 256)), dim3(256), 0, s, pool, dst, val, col, dc, nnz);
   check_launch("k_scatter_scaled");
 }
@@ -2610,9 +2806,10 @@ struct QRPlan {
   int jb, q;
 };
 static QRPlan qr_plan(int max_m, int eb) {
+  const int lim = tuning().qr_reg_max_rows;
   if (max_m <= NT) return {16, 1};
-  if (max_m <= 2 * NT) return {16, 2};
-  if (max_m <= 4 * NT) return {eb == 8 ? 8 : 16, 4};
+  if (max_m <= 2 * NT && lim >= 2 * NT) return {16, 2};
+  if (max_m <= 4 * NT && lim >= 4 * NT) return {eb == 8 ? 8 : 16, 4};
   const size_t budget = device_lds_limit();
   for (int jb = 16; jb >= 1; jb >>= 1)
     if (qr_bytes_jb(max_m, jb, eb) <= budget) return {jb, 0};
@@ -2624,14 +2821,20 @@ static size_t qr_reg_lds(int max_m, int jb, int eb) { return ((size_t)max_m * jb
 // Allow a kernel more than the default 64 KB of dynamic LDS (gfx950: 160 KB
 // per workgroup).  Called before every launch that needs it; the attribute
 // is set once per kernel.
+// The largest size set so far is remembered per kernel, so that a launch
+// needing no more makes no runtime call (in particular none while an apply
+// is being captured into a graph).
 static void allow_lds(const void* fn, size_t bytes, const char* what) {
   if (bytes <= 64 * 1024) return;
-  int dev = 0, lim = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lim = 64 * 1024;
-  if (bytes > (size_t)lim) throw Error(SPAQR_ENOMEM, std::string(what) + ": LDS need exceeds the device limit");
+  static std::mutex mu;
+  static std::map<const void*, size_t> set;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = set.find(fn);
+  if (it != set.end() && it->second >= bytes) return;
+  if (bytes > device_lds_limit()) throw Error(SPAQR_ENOMEM, std::string(what) + ": LDS need exceeds the device limit");
   const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) throw Error(SPAQR_EDEVICE, std::string(what) + ": cannot raise the LDS limit");
+  set[fn] = bytes;
 }
 
 int qr_panel_width(int max_m, int eb) { return qr_plan(max_m, eb).jb; }
@@ -2647,6 +2850,7 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
 #define SPAQR_QRR(J, Q)                                                                      \
   if (jb == J && pl.q == Q) {                                                               \
     allow_lds(reinterpret_cast<const void*>(&k_qr_reg<T, J, Q>), lds, "k_qr_reg");          \
+    count_launch("k_qr_reg");                                                              \
     hipLaunchKernelGGL((k_qr_reg<T, J, Q>), dim3((unsigned)n), dim3(NT), lds, s, d);       \
     check_launch("k_qr_reg");                                                               \
     return;                                                                                 \
@@ -2668,6 +2872,7 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s) 
 #define SPAQR_QR_CASE(J)                                                   \
   case J:                                                                  \
     allow_lds(reinterpret_cast<const void*>(&k_qr<T, J>), lds, "k_qr");  \
+    count_launch("k_qr");                                                     \
     hipLaunchKernelGGL((k_qr<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d); \
     break;
     SPAQR_QR_CASE(1)
@@ -2686,6 +2891,22 @@ static size_t trail_lds(int max_m, int jb, int cw, int eb) {
   return ((size_t)(NT / cw) * jb * cw + 2 * (size_t)jb * cw + (size_t)max_m * (cw + 1)) * eb;
 }
 
+template <typename T>
+void launch_wy_tblock(const WYBlock<T>* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  count_launch("k_wy_tblock");
+  hipLaunchKernelGGL(k_wy_tblock<T>, dim3((unsigned)n), dim3(256), 0, s, d);
+  check_launch("k_wy_tblock");
+}
+
+template <typename T>
+void launch_trail_mfma(const WYTile<T>* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  count_launch("k_trail_mfma");
+  hipLaunchKernelGGL(k_trail_mfma<T>, dim3((unsigned)n), dim3(256), 0, s, d);
+  check_launch("k_trail_mfma");
+}
+
 int trail_width(int max_m, int eb) {
   const size_t lim = device_lds_limit();
   for (int cw : {16, 8, 4})
@@ -2701,6 +2922,7 @@ void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, h
 #define SPAQR_TR(J, W)                                                                      \
   if (jb == J && cw == W) {                                                                \
     allow_lds(reinterpret_cast<const void*>(&k_trail<T, J, W>), lds, "k_trail");          \
+    count_launch("k_trail");                                                              \
     hipLaunchKernelGGL((k_trail<T, J, W>), dim3((unsigned)n), dim3(NT), lds, s, d);       \
     check_launch("k_trail");                                                               \
     return;                                                                                \
@@ -2734,6 +2956,7 @@ void launch_scale_small(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac,
 #define SPAQR_SS_CASE(J)                                                                              \
   case J:                                                                                             \
     allow_lds(reinterpret_cast<const void*>(&k_scale_small<T, J>), lds, "k_scale_small");              \
+    count_launch("k_scale_small");                                                                              \
     hipLaunchKernelGGL((k_scale_small<T, J>), dim3((unsigned)n), dim3(NT), lds, s, d, fac, max_rows, max_cols); \
     break;
     SPAQR_SS_CASE(1)
@@ -2758,6 +2981,7 @@ void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int j
 #define SPAQR_SC_CASE(J) \
   case J:                                                                                       \
     allow_lds(reinterpret_cast<const void*>(&k_scale<T, J>), lds, "k_scale");                 \
+    count_launch("k_scale");                                                                   \
     hipLaunchKernelGGL((k_scale<T, J>), grid, dim3(NT), lds, s, d, fac);                       \
     break;
     SPAQR_SC_CASE(1)
@@ -2776,6 +3000,7 @@ void launch_scale(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int j
 template <typename T>
 void launch_scale_right(const ScaleBlk<T>* d, int64_t n, const ScaleFac<T>* fac, int max_rows, hipStream_t s) {
   if (n <= 0) return;
+  count_launch("k_scale_right");
   hipLaunchKernelGGL(k_scale_right<T>, dim3((unsigned)n, (unsigned)((max_rows + 15) / 16)), dim3(NT), 0, s, d, fac);
   check_launch("k_scale_right");
 }
@@ -2791,6 +3016,7 @@ static void launch_sparsify_small_t(const SpDesc<T>* d, int64_t n, const SpNbr* 
   size_t cb = std::min(c_bytes, lim > head + 1024 ? lim - head - 512 : 0);
   const int lds_c_elems = (int)(cb / sizeof(T));
   const size_t lds = head + (size_t)lds_c_elems * sizeof(T);
+  count_launch("k_sparsify_small");
   hipLaunchKernelGGL((k_sparsify_small<T, PMAX, NTH>), dim3((unsigned)n), dim3(NTH), lds, s, d, nb, lds_c_elems,
                      max_nb);
   check_launch("k_sparsify_small");
@@ -2802,11 +3028,17 @@ void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int p
   if (n <= 0) return;
   const size_t cbytes = max_c_elems * sizeof(T);
   // thread counts keep the per-thread column in registers without spills
+  // (no FP64 instantiation for 33-64 unknowns is built: those interfaces take
+  // the generic kernel)
   constexpr bool F32 = sizeof(T) == 4;
-  if (pmax <= 16) launch_sparsify_small_t<T, 16, 1024>(d, n, nb, max_nb, cbytes, s);
-  else if (pmax <= 32) launch_sparsify_small_t<T, 32, F32 ? 1024 : 512>(d, n, nb, max_nb, cbytes, s);
-  else if (F32) launch_sparsify_small_t<T, 64, 512>(d, n, nb, max_nb, cbytes, s);
-  else throw Error(SPAQR_EINVAL, "FP64 interfaces above 32 unknowns use the generic sparsify kernel");
+  if (pmax <= 16) {
+    launch_sparsify_small_t<T, 16, 1024>(d, n, nb, max_nb, cbytes, s);
+  } else if (pmax <= 32) {
+    launch_sparsify_small_t<T, 32, F32 ? 1024 : 512>(d, n, nb, max_nb, cbytes, s);
+  } else {
+    if constexpr (F32) launch_sparsify_small_t<T, 64, 512>(d, n, nb, max_nb, cbytes, s);
+    else throw Error(SPAQR_EINVAL, "FP64 interfaces above 32 unknowns use the generic sparsify kernel");
+  }
 }
 
 template <typename T>
@@ -2814,6 +3046,7 @@ void launch_sparsify(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int max_p, 
   if (n <= 0) return;
   const size_t lds = align16((size_t)(max_nb + 1) * sizeof(int)) + (size_t)max_p * sizeof(double) +
                      8 * sizeof(double) + NT * sizeof(double) + NT * sizeof(int);
+  count_launch("k_sparsify");
   hipLaunchKernelGGL(k_sparsify<T>, dim3((unsigned)n), dim3(NT), lds, s, d, nb);
   check_launch("k_sparsify");
 }
@@ -2856,6 +3089,7 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pma
 #define SPAQR_SPR(PM, CP, L, G)                                                                           \
   if (pclass == PM && cpt == CP && lc == L && gc == G) {                                                 \
     allow_lds(reinterpret_cast<const void*>(&k_cpqr_reg<T, PM, CP, L, G>), lds, "k_cpqr_reg");          \
+    count_launch("k_cpqr_reg");                                                                               \
     hipLaunchKernelGGL((k_cpqr_reg<T, PM, CP, L, G>), dim3((unsigned)n), dim3(SP_NT), lds, s, d, nb, max_nb); \
     check_launch("k_cpqr_reg");                                                                          \
     return;                                                                                              \
@@ -2942,6 +3176,7 @@ bool launch_sparsify_coop(const SpDesc<T>* d, const CoopItem* items, int nitems,
                   (void*)&max_nb, (void*)&ckey, (void*)&cpos, (void*)&ccol, (void*)&done, (void*)&kmax_all};
   const void* fn = coop_kernel<T>(cpt, lc);
   if (!fn) throw Error(SPAQR_EINVAL, "unsupported columns per thread in the cooperative CPQR");
+  count_launch("k_cpqr_coop");
   const hipError_t e = hipLaunchCooperativeKernel(fn, dim3((unsigned)total_blocks), dim3(64), args, lds, s);
   if (e != hipSuccess)
     throw Error(SPAQR_EDEVICE, std::string("cooperative launch of k_cpqr_coop failed: ") + hipGetErrorString(e));
@@ -2970,6 +3205,7 @@ int apply_rhs_block(int max_rows, int nrhs) {
     if (rb < 1) throw Error(SPAQR_ENOMEM, "apply: item too large for LDS");                     \
     const size_t lds = (size_t)max_rows * rb * sizeof(double);                                  \
     allow_lds(reinterpret_cast<const void*>(&k_ap_##KERNEL<T>), lds, "k_ap_" #KERNEL);         \
+    count_launch("k_ap_" #KERNEL);                                                              \
     hipLaunchKernelGGL(k_ap_##KERNEL<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)),  \
                        dim3(64), lds, s, d, x, ldx, nrhs, rb);                                  \
     check_launch("k_ap_" #KERNEL);                                                              \
@@ -2990,6 +3226,7 @@ void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, d
     const dim3 grid((unsigned)n, (unsigned)((nrhs + nr - 1) / nr));
 #define SPAQR_FWR(J, Q, R)                                                                             \
   if (jb == J && q == Q && nr == R) {                                                                  \
+    count_launch("k_ap_front_fwd_reg");                                                                \
     hipLaunchKernelGGL((k_ap_front_fwd_reg<T, J, Q, R>), grid, dim3(256), 0, s, d, x, ldx, nrhs);      \
     check_launch("k_ap_front_fwd_reg");                                                               \
     return;                                                                                           \
@@ -3019,6 +3256,7 @@ void launch_front_fwd_wy(const ApFront<T>* d, int64_t n, int jb, int max_rows, d
 #define SPAQR_FW_CASE(J) \
   case J:                                                                                  \
     allow_lds(reinterpret_cast<const void*>(&k_ap_front_fwd_wy<T, J>), lds, "k_ap_front_fwd_wy"); \
+    count_launch("k_ap_front_fwd_wy");                                                           \
     hipLaunchKernelGGL((k_ap_front_fwd_wy<T, J>), grid, dim3(256), lds, s, d, x, ldx, nrhs, rb); \
     break;
     SPAQR_FW_CASE(1)
@@ -3050,6 +3288,7 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
   if (per_rhs * rb > lim) throw Error(SPAQR_ENOMEM, "apply: front too large for LDS");
   const size_t lds = per_rhs * rb + tile;
   allow_lds(reinterpret_cast<const void*>(&k_ap_front_bwd_reg<T>), lds, "k_ap_front_bwd_reg");
+  count_launch("k_ap_front_bwd_reg");
   hipLaunchKernelGGL(k_ap_front_bwd_reg<T>, dim3((unsigned)n, (unsigned)((nrhs + rb - 1) / rb)), dim3(256), lds, s,
                      d, x, ldx, nrhs, rb, chunk, tile_rows);
   check_launch("k_ap_front_bwd_reg");
@@ -3062,6 +3301,7 @@ static void launch_iface_form_t(const ApIface<T>* d, int64_t n, hipStream_t s) {
   constexpr int LP = PM >= 64 ? 16 : 8;
   const size_t lds = ((size_t)PM * (PM + 1) + 2 * PM) * sizeof(double) + 2 * (size_t)PM * PM * sizeof(T);
   allow_lds(reinterpret_cast<const void*>(&k_iface_form<T, PM, LP>), lds, "k_iface_form");
+  count_launch("k_iface_form");
   hipLaunchKernelGGL((k_iface_form<T, PM, LP>), dim3((unsigned)n), dim3(LP * PM), lds, s, d);
   check_launch("k_iface_form");
 }
@@ -3079,6 +3319,7 @@ template <typename T>
 void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
                         hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
+  count_launch("k_ap_iface_dense");
   hipLaunchKernelGGL(k_ap_iface_dense<T>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, d, n, backward ? 1 : 0, x,
                      ldx, nrhs);
   check_launch("k_ap_iface_dense");
@@ -3088,12 +3329,14 @@ template <typename T>
 void launch_iface_small(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
                         hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
+  count_launch("k_ap_iface_small");
   hipLaunchKernelGGL(k_ap_iface_small<T>, dim3((unsigned)n), dim3(64), 0, s, d, x, ldx, nrhs, backward ? 1 : 0);
   check_launch("k_ap_iface_small");
 }
 
 void launch_gather_perm(double* xhat, const double* b, int64_t ldb, const int64_t* perm, int64_t N,
                         int nrhs, hipStream_t s) {
+  count_launch("k_gather_perm");
   hipLaunchKernelGGL(k_gather_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, xhat, b, ldb, perm,
                      N, nrhs);
   check_launch("k_gather_perm");
@@ -3103,6 +3346,7 @@ void launch_gather_cols(double* xhat, const double* b, int64_t ldb, const PermCo
                         hipStream_t s) {
   if (ncols <= 0 || max_n <= 0) return;
   const unsigned gxn = (unsigned)std::min<int64_t>(1024, (max_n + 255) / 256);
+  count_launch("k_gather_cols");
   hipLaunchKernelGGL(k_gather_cols, dim3(gxn, (unsigned)ncols), dim3(256), 0, s, xhat, b, ldb, pc);
   check_launch("k_gather_cols");
 }
@@ -3112,6 +3356,7 @@ void launch_gather_ints(const IntCopy* ops, int nops, int32_t* out, hipStream_t 
     IntCopyList L{};
     const int n = std::min(kIntCopyMax, nops - i0);
     for (int i = 0; i < n; ++i) L.op[i] = ops[i0 + i];
+    count_launch("k_gather_ints");
     hipLaunchKernelGGL(k_gather_ints, dim3((unsigned)n), dim3(256), 0, s, L, out);
     check_launch("k_gather_ints");
   }
@@ -3121,12 +3366,14 @@ void launch_scatter_cols(double* x, int64_t ldx, const double* xhat, const PermC
                          hipStream_t s) {
   if (ncols <= 0 || max_n <= 0) return;
   const unsigned gxn = (unsigned)std::min<int64_t>(1024, (max_n + 255) / 256);
+  count_launch("k_scatter_cols");
   hipLaunchKernelGGL(k_scatter_cols, dim3(gxn, (unsigned)ncols), dim3(256), 0, s, x, ldx, xhat, pc);
   check_launch("k_scatter_cols");
 }
 
 void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64_t* perm,
                          const double* dc, int64_t N, int nrhs, hipStream_t s) {
+  count_launch("k_scatter_perm");
   hipLaunchKernelGGL(k_scatter_perm, dim3(grid_for(N * nrhs, 256)), dim3(256), 0, s, x, ldx, xhat, perm,
                      dc, N, nrhs);
   check_launch("k_scatter_perm");
@@ -3140,6 +3387,8 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
                                          int64_t, hipStream_t);                                      \
   template void launch_qr<T>(const QRDesc<T>*, int64_t, int, int, hipStream_t);                      \
   template void launch_trail<T>(const TrailDesc<T>*, int64_t, int, int, int, hipStream_t);           \
+  template void launch_wy_tblock<T>(const WYBlock<T>*, int64_t, hipStream_t);                          \
+  template void launch_trail_mfma<T>(const WYTile<T>*, int64_t, hipStream_t);                          \
   template void launch_scale<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, int, hipStream_t);                                                                      \
   template void launch_scale_right<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, hipStream_t);                                                                      \
   template void launch_scale_small<T>(const ScaleBlk<T>*, int64_t, const ScaleFac<T>*, int, int, int, hipStream_t); \

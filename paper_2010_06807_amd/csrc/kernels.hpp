@@ -51,6 +51,30 @@ struct TrailDesc {
   int32_t m, n, ld, c0, cw, ldc;
 };
 
+// Blocked WY form of 64 reflectors j0 .. j0 + 63 of a factored pivot block a
+// (row-major, row stride ld, m rows, n reflectors: V below the diagonal, tau
+// their scalars): T_b (64 x 64 row-major) is written to tblk.
+template <typename T>
+struct WYBlock {
+  const T* a;
+  const T* tau;
+  T* tblk;
+  int32_t m, n, ld, j0;
+};
+
+// One tile of at most 64 trailing columns [c0, c0 + cw) of the row-major
+// m-row matrix c (row stride ldc) to be updated with all n reflectors of the
+// factored pivot block a (row stride ld), whose blocks' T_b lie back to back
+// at tblk (64 x 64 each).  flag (may be null): nonzero skips the tile.
+template <typename T>
+struct WYTile {
+  const T* a;
+  const T* tblk;
+  T* c;
+  const int* flag;
+  int32_t m, n, ld, c0, cw, ldc;
+};
+
 // One block B (row-major rows x cols, ld = cols) of the trailing matrix to be
 // scaled: B <- U_i^T B (if the row cluster is a scaled interface), then
 // B <- B R_j^{-1} (if the column cluster is), or B := I for a scaled
@@ -161,6 +185,13 @@ void launch_qr(const QRDesc<T>* d, int64_t n, int jb, int max_m, hipStream_t s);
 int trail_width(int max_m, int elem_bytes);
 template <typename T>
 void launch_trail(const TrailDesc<T>* d, int64_t n, int jb, int cw, int max_m, hipStream_t s);
+// Matrix-core form of the trailing update: the T factors of every 64-reflector
+// block, then the update of every 64-column tile.
+constexpr int kWYBlock = 64;
+template <typename T>
+void launch_wy_tblock(const WYBlock<T>* d, int64_t n, hipStream_t s);
+template <typename T>
+void launch_trail_mfma(const WYTile<T>* d, int64_t n, hipStream_t s);
 int qr_panel_width(int max_m, int elem_bytes);
 size_t qr_lds_bytes(int max_m, int jb, int elem_bytes);
 // Block scaling: B <- Q_i^T B R_j^{-1} (two launches); max_p bounds the

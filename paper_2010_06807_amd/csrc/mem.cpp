@@ -95,6 +95,20 @@ void dev_free(void* p, hipStream_t s) {
   g_size.erase(it);
 }
 
+void mem_release_all() {
+  {
+    std::lock_guard<std::mutex> lk(g_dmu);
+    if (!g_cache.empty()) {
+      (void)hipDeviceSynchronize();
+      for (auto& kv : g_cache) (void)hipFree(kv.second.p);
+      g_cache.clear();
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& c : g_free) (void)hipHostFree(c.p);
+  g_free.clear();
+}
+
 PinnedChunk pinned_acquire(size_t bytes) {
   {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -18,6 +18,10 @@ namespace spaqr {
 void mem_setup(hipStream_t s);                    // once per device
 void* dev_alloc(size_t bytes, hipStream_t s);     // stream-ordered, throws ENOMEM
 void dev_free(void* p, hipStream_t s);            // stream-ordered, NULL is a no-op
+// Returns every cached device block and every pooled pinned chunk to the
+// runtime (after a device synchronization).  Blocks and chunks still held
+// by live objects are untouched; the caches refill on demand afterwards.
+void mem_release_all();
 
 struct PinnedChunk {
   char* p = nullptr;

@@ -59,6 +59,16 @@ void prof_host(const char* name, double ms) {
   r.ms += ms;
 }
 
+namespace {
+std::mutex g_cmu;
+std::map<std::string, int64_t> g_count;
+}  // namespace
+
+void count_launch(const char* kernel) {
+  std::lock_guard<std::mutex> lk(g_cmu);
+  ++g_count[kernel];
+}
+
 void prof_add(const char* name, double flops, double bytes) {
   if (!prof_wants(name)) return;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -78,6 +88,27 @@ spaqr_status spaqr_profile_enable(int on, const char* only) {
   spaqr::g_on = on != 0;
   spaqr::g_only = only ? only : "";
   return SPAQR_OK;
+}
+
+spaqr_status spaqr_kernel_launches(const char* kernel, int64_t* count) {
+  if (!count) return SPAQR_EINVAL;
+  std::lock_guard<std::mutex> lk(spaqr::g_cmu);
+  if (!kernel) {
+    spaqr::g_count.clear();
+    *count = 0;
+    return SPAQR_OK;
+  }
+  auto it = spaqr::g_count.find(kernel);
+  *count = it == spaqr::g_count.end() ? 0 : it->second;
+  return SPAQR_OK;
+}
+
+void spaqr_prof_release() {
+  std::lock_guard<std::mutex> lk(spaqr::g_mu);
+  for (auto& kv : spaqr::g_tab) spaqr::resolve(kv.second);
+  spaqr::g_tab.clear();
+  spaqr::g_on = false;
+  spaqr::g_only.clear();
 }
 
 spaqr_status spaqr_profile_query(const char* name, int64_t* launches, double* total_ms, double* flops,

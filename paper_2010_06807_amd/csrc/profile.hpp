@@ -14,6 +14,9 @@ void prof_record(const char* name, hipStream_t s, hipEvent_t a, hipEvent_t b, do
 void prof_add(const char* name, double flops, double bytes);
 // Host wall time of a driver phase (recorded like a launch of `ms`).
 void prof_host(const char* name, double ms);
+// Process-wide count of launches per kernel family (the kernel template's
+// name, e.g. "k_qr"), always on; read with spaqr_kernel_launches.
+void count_launch(const char* kernel);
 double now_ms();
 
 struct HostScope {

@@ -39,16 +39,6 @@ struct Request {
   int status = SPAQR_PENDING;
 };
 
-// Device memory a request needs while it is resident: factors (bounded by a
-// per-unknown allowance that grows with the nested-dissection depth) plus
-// the FGMRES bases.
-static size_t estimate_bytes(int64_t n, int64_t nnz, int L, int64_t nrhs, const spaqr_opts& o) {
-  const size_t eb = o.precision == 32 ? 4 : 8;
-  const size_t factors = (size_t)n * eb * (size_t)(64 + 24 * L) + (size_t)nnz * 24;
-  const size_t krylov = (size_t)n * nrhs * 8 * (size_t)(2 * o.restart + 4);
-  return factors + krylov;
-}
-
 }  // namespace spaqr
 
 struct spaqr_server {
@@ -190,7 +180,11 @@ spaqr_status spaqr_submit(spaqr_server* srv, const spaqr_csr* A, const spaqr_ord
     r->b.assign(b, b + A->n * nrhs);
     r->nrhs = nrhs;
     r->tol = tol;
-    r->est = estimate_bytes(A->n, A->nnz, ord->o.L, nrhs, r->opts);
+    SPAQR_REQUIRE(r->opts.precision == 32 || r->opts.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
+    // the symbolic analysis (host only) sizes the request: its admission
+    // estimate is the analysis's bound on the device memory it can hold
+    r->sym.reset(analyze(&r->A, r->ord, r->opts.skip));
+    r->est = device_bytes_bound(*r->sym, r->opts.precision, nrhs, r->opts.restart);
     SPAQR_REQUIRE(r->est <= srv->budget, SPAQR_ENOMEM, "request alone exceeds the memory budget");
     r->ticket = srv->next++;
     *ticket = r->ticket;
@@ -203,7 +197,7 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
   return guard([&]() -> spaqr_status {
     SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
     // 1. admission by estimated memory, in arrival order; the admitted
-    // requests' symbolic analyses and set-ups run in parallel host threads
+    // requests' set-ups run in parallel host threads
     std::vector<std::unique_ptr<Request>> adm;
     while (!srv->queue.empty() && srv->used + srv->queue.front()->est <= srv->budget) {
       adm.push_back(std::move(srv->queue.front()));
@@ -218,7 +212,6 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
       auto setup = [&](int i) {
         Request& r = *adm[i];
         try {
-          r.sym.reset(analyze(&r.A, r.ord, r.opts.skip));
           r.eng = make_engine_deferred(&r.A, nullptr, *r.sym, r.opts, srv->stream);
         } catch (const Error& e) {
           adm_st[i] = e.status;
@@ -289,6 +282,26 @@ spaqr_status spaqr_poll(spaqr_server* srv, uint64_t ticket, double* x, spaqr_sol
     const int st = r.status;
     srv->done.erase(it);
     return st;
+  });
+}
+
+spaqr_status spaqr_server_status(const spaqr_server* srv, int64_t* queued, int64_t* resident, size_t* bytes) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(srv, SPAQR_EINVAL, "NULL server");
+    if (queued) *queued = (int64_t)srv->queue.size();
+    if (resident) *resident = (int64_t)srv->active.size();
+    if (bytes) *bytes = srv->used;
+    return SPAQR_OK;
+  });
+}
+
+spaqr_status spaqr_estimate_bytes(const spaqr_symbolic* sym, const spaqr_opts* opts, int64_t nrhs, size_t* bytes) {
+  return guard([&]() -> spaqr_status {
+    SPAQR_REQUIRE(sym && bytes && nrhs >= 1, SPAQR_EINVAL, "bad argument");
+    const spaqr_opts o = opts ? *opts : spaqr_opts_default();
+    SPAQR_REQUIRE(o.precision == 32 || o.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
+    *bytes = device_bytes_bound(sym->s, o.precision, nrhs, o.restart);
+    return SPAQR_OK;
   });
 }
 

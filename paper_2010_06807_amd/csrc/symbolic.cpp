@@ -17,6 +17,7 @@
 #include "symbolic.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <memory>
 
 namespace spaqr {
@@ -114,6 +115,7 @@ void order_by_colour(const std::vector<int32_t>& colour, std::vector<int32_t>& o
 }  // namespace
 
 Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
+  const auto t_start = std::chrono::steady_clock::now();
   SPAQR_REQUIRE(A && A->rowptr && A->col && A->val, SPAQR_EINVAL, "NULL matrix");
   SPAQR_REQUIRE(A->n == ord.n, SPAQR_EINVAL, "matrix size differs from the ordering");
   SPAQR_REQUIRE(A->rowptr[0] == 0 && A->rowptr[A->n] == A->nnz, SPAQR_EINVAL, "bad rowptr");
@@ -338,8 +340,79 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
     std::vector<int64_t> pos(S->col_ptr, S->col_ptr + n);
     for (int64_t t = 0; t < A->nnz; ++t) S->col_nz[pos[A->col[t]]++] = t;
   }
+  S->ms_analysis = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   guard.release();
   return S;
+}
+
+
+// Upper bound on the device memory of one factorization and its solve.
+// Ranks never exceed the cluster sizes, so every block, front and interface
+// is sized here as if nothing were compressed: the stage-k cluster sizes are
+// the ordering's.  Bytes are summed per arena as the engine allocates them
+// (persistent factors and apply lists, per-stage workspace, the two
+// ping-pong block pools) and each arena's reservation is bounded by twice
+// what it hands out plus one chunk; the FGMRES bases and the apply vectors of
+// nrhs right-hand sides come on top.
+size_t device_bytes_bound(const Symbolic& S, int precision, int64_t nrhs, int restart) {
+  const double eb = precision == 32 ? 4.0 : 8.0;
+  const double n = (double)S.n, nnz = (double)S.nnz;
+  const double align = 256.0;  // every arena allocation is rounded up to 256 bytes
+  double persist = 8.0 * (n + 1) + 12.0 * nnz + 16.0 * n + 8.0 * align;  // CSR, column scaling, perm
+  double work_peak = 8.0 * (double)S.maps_words() + align;              // set-up maps
+  double pool_max = 0.0, desc_max = 0.0;
+  for (int k = S.L; k >= 1; --k) {
+    const StageSym& ss = S.st[k];
+    const StageClusters& cl = S.ord.stages[k];
+    auto sz = [&](int32_t c) { return (double)(cl.end[c] - cl.start[c]); };
+    double pool = 0.0;
+    for (int64_t i = 0; i < ss.all.nclu; ++i)
+      for (int64_t u = ss.all.rowptr[i]; u < ss.all.rowptr[i + 1]; ++u) pool += sz((int32_t)i) * sz(ss.all.col[u]);
+    pool_max = std::max(pool_max, pool * eb + align);
+    double work = 0.0;
+    persist += 10.0 * align;
+    for (const FrontSym& F : ss.fronts) {
+      double m = sz(F.cluster), kk = 0.0;
+      const double nn = sz(F.cluster);
+      for (int32_t i : F.n1) m += sz(i);
+      for (int32_t j : F.cols) kk += sz(j);
+      // V|R_ss, R_sj, tau, compact-WY panels (width <= 32), row and column
+      // slot lists and the apply descriptor
+      persist += eb * (m * nn + nn * kk + nn + (nn + 32.0) * 32.0) + 4.0 * (m + kk) + 128.0;
+      work += eb * m * (nn + kk + 32.0) + 64.0 * (1.0 + F.n1.size()) * (1.0 + F.cols.size());
+    }
+    if (ss.sparsify) {
+      persist += 8.0 * align;
+      for (int32_t p : ss.remaining) {
+        const double P = sz(p);
+        // U_pp|R_pp, tau_u, panels, Q_pp, tau_q, flag, dense operators,
+        // slot list and the apply descriptor
+        persist += eb * (2.0 * P * P + 2.0 * P + (P + 32.0) * 32.0) + 4.0 + (P <= 64 ? 2.0 * eb * P * P : 0.0) +
+                   4.0 * P + 128.0;
+        work += eb * P * (P + 16.0);
+      }
+      for (const IfaceSym& I : ss.ifaces) {
+        double m = 0.0;
+        for (int32_t i : I.rowN) m += sz(i);
+        for (int32_t j : I.colN) m += sz(j);
+        const double P = sz(I.cluster);
+        work += (eb * std::max(P, 65.0) + 16.0) * std::max(m, 1.0) + 3.0 * align + 48.0 * (I.rowN.size() + I.colN.size());
+      }
+      work += 64.0 * (double)ss.remaining.size() * 64.0;  // cooperative CPQR exchange buffers
+    }
+    // copy, QR, scaling and CPQR descriptors (the engine's own lists and
+    // their concatenation by the batch driver)
+    const double desc = 64.0 * (double)ss.all.size() + 128.0 * (double)(ss.fronts.size() + ss.ifaces.size());
+    work += desc;
+    desc_max = std::max(desc_max, desc);
+    work_peak = std::max(work_peak, work);
+  }
+  const double chunk = 64.0 * 1048576.0;
+  auto reserved = [&](double used) { return 2.0 * used + chunk; };
+  const double krylov = 8.0 * n * (double)nrhs * (2.0 * restart + 8.0);  // V, Z, b, x, apply vector
+  // two pool arenas (stages alternate between them), each holding one pool
+  const double total = reserved(persist) + reserved(work_peak) + 2.0 * reserved(pool_max) + reserved(desc_max) + krylov;
+  return (size_t)total;
 }
 
 }  // namespace spaqr

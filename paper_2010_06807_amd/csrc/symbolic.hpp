@@ -83,9 +83,15 @@ struct Symbolic {
   int64_t* nz_dst = nullptr;
   size_t maps_words() const { return (size_t)(n + 1) + 2 * (size_t)nnz; }
   std::vector<int32_t> cluster_of_pos_L;  // stage-L cluster of each permuted index
+  double ms_analysis = 0.0;               // host wall time of analyze()
 };
 
 Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip);
+
+// Upper bound on the device bytes a factorization of S in the given precision
+// (32 or 64) holds at its peak, plus the FGMRES bases of nrhs right-hand
+// sides with the given restart length.
+size_t device_bytes_bound(const Symbolic& S, int precision, int64_t nrhs, int restart);
 
 }  // namespace spaqr
 

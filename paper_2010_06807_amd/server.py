@@ -18,12 +18,15 @@ class Server:
         check(lib.spaqr_server_create(int(mem_budget), _stream_ptr(stream), C.byref(h)), "spaqr_server_create")
         self._h = h
         self._keep = {}
+        _abi.track("server", self)
+
+    def close(self):
+        if getattr(self, "_h", None) and _abi is not None and not _abi.released():
+            _abi.load().spaqr_server_destroy(self._h)
+        self._h = None
 
     def __del__(self):
-        # at interpreter exit the module globals may already be gone
-        if getattr(self, "_h", None) and _abi is not None:
-            _abi.load().spaqr_server_destroy(self._h)
-            self._h = None
+        self.close()
 
     def submit(self, A, ordering, b, tol=1e-10, eps=1e-2, precision=32, skip=2):
         from . import _csr_struct, make_opts
@@ -42,6 +45,12 @@ class Server:
         a = C.c_int()
         check(_abi.load().spaqr_server_step(self._h, C.byref(a)), "spaqr_server_step")
         return a.value
+
+    def status(self):
+        """(queued, resident, estimated bytes of the resident requests)."""
+        q, r, b = C.c_int64(), C.c_int64(), C.c_size_t()
+        check(_abi.load().spaqr_server_status(self._h, C.byref(q), C.byref(r), C.byref(b)), "spaqr_server_status")
+        return q.value, r.value, b.value
 
     def poll(self, ticket):
         n, nrhs = self._keep[ticket]

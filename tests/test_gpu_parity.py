@@ -3,12 +3,15 @@
 Bars (the tolerances the method's hot path is held to):
   * eps = 0 (exact nested-dissection QR): ||A x - b|| / ||b|| <= 1e-12 for
     the FP64 engine, and M^{-1} b equal to the oracle's element by element;
-  * eps > 0: per-interface ranks within +-1 (identical ranks are then checked
-    element by element on M^{-1} b), GMRES iteration counts within
+  * eps > 0: FP64 per-interface ranks equal to the oracle's on every case
+    here, so M^{-1} b is checked element by element on every case (max
+    difference <= 1e-11 of the largest entry), GMRES iteration counts within
     max(1, ceil(0.1 * oracle)) and both solves at <= 1e-10;
-  * FP32 factors with FP64 GMRES: same rank and iteration bars, residual
-    <= 1e-10; the FP32 apply's distance to the oracle's is reported and bounded
-    by a multiple of FP32 unit roundoff times the preconditioner's growth.
+  * FP32 factors with FP64 GMRES: ranks within +-1, iteration counts within
+    the same window in both directions, residual <= 1e-10, and the FP32
+    M^{-1} b within 1e-3 (relative 2-norm) of the oracle's: FP32 unit
+    roundoff 6e-8 times the apply's error growth, which the FP64 comparison
+    bounds below 1e3 on these grids.
 """
 
 import math
@@ -78,13 +81,13 @@ def test_fp64_apply_matches_oracle(dims, L, beta, eps):
     N = A.shape[0]
     F = _oracle(A, dims, L, eps)
     fac = P.factor(A, P.order_grid(dims, L), eps=eps, precision=64)
-    worst = _ranks_agree(fac, F, L, 1)
+    _ranks_agree(fac, F, L, 0)
     b = make_rhs(N, 3, seed=5)
     xo = oracle_spaqr.apply(F, b)
     xg = fac.apply(_dev(b)).cpu().numpy()
-    if worst == 0:
-        err = np.abs(xg - xo).max() / np.abs(xo).max()
-        assert err <= 1e-11, err
+    err = np.abs(xg - xo).max() / np.abs(xo).max()
+    print(f"fp64 apply max rel diff {err:.2e}", flush=True)
+    assert err <= 1e-11, err
     if eps == 0.0:
         res = np.linalg.norm(A @ xg - b, axis=0) / np.linalg.norm(b, axis=0)
         assert res.max() <= 1e-12, res
@@ -119,11 +122,16 @@ def test_fp32_factor_fp64_gmres(dims, L, beta, eps):
     # every scaled interface of every sparsified stage is counted once
     assert fac.stats()["interfaces_sparsified"] == sum(1 for op in F.ops if op[0] == "scale")
     b = make_rhs(N, 1, seed=3)
+    yo = oracle_spaqr.apply(F, b)
+    yg = fac.apply(_dev(b)).cpu().numpy()
+    dy = np.linalg.norm(yg - yo) / np.linalg.norm(yo)
+    print(f"fp32 apply rel diff {dy:.2e}", flush=True)
+    assert dy <= 1e-3, dy
     it_o, _ = _oracle_its(A, F, b[:, 0])
     x, info = fac.solve(_dev(b), tol=1e-10)
     res = np.linalg.norm(A @ x.cpu().numpy() - b) / np.linalg.norm(b)
     assert res <= 1e-10 and info[0]["converged"]
-    assert info[0]["iterations"] <= it_o + max(1, math.ceil(0.1 * it_o)), (info, it_o)
+    assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o)), (info, it_o)
 
 
 def test_multi_rhs_ragged():
@@ -160,43 +168,6 @@ def test_host_pointers_and_degenerate_grids():
         assert res.max() <= 1e-12
         xs, info = fac.solve(b, tol=1e-10)
         assert all(i["iterations"] == 1 for i in info)
-
-
-def test_c2_fp32_against_oracle():
-    """The 256^2 variable-coefficient workload at eps = 1e-2."""
-    prob = config_problem("c2", seed=0)
-    A, dims, L = prob["A"], prob["dims"], prob["levels"]
-    N = A.shape[0]
-    F = _oracle(A, dims, L, 1e-2)
-    b = make_rhs(N, 1, seed=0)
-    it_o, _ = _oracle_its(A, F, b[:, 0])
-    for prec in (64, 32):
-        print(f"case c2 precision={prec}", flush=True)
-        fac = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=prec)
-        _ranks_agree(fac, F, L, 1)
-        x, info = fac.solve(_dev(b), tol=1e-10)
-        res = np.linalg.norm(A @ x.cpu().numpy() - b) / np.linalg.norm(b)
-        assert res <= 1e-10
-        assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o)), (prec, info, it_o)
-
-
-def test_c2_fp32_tight_tolerance_against_oracle():
-    """The 256^2 workload at eps = 1e-4: some interfaces of 33-64 unknowns
-    reach 2049-2560 columns, so the register CPQR keeps a column per thread
-    in global memory (and a few wider ones take the cooperative kernel)."""
-    prob = config_problem("c2", seed=0)
-    A, dims, L = prob["A"], prob["dims"], prob["levels"]
-    N = A.shape[0]
-    F = _oracle(A, dims, L, 1e-4)
-    b = make_rhs(N, 1, seed=0)
-    it_o, _ = _oracle_its(A, F, b[:, 0])
-    print("case c2 eps=1e-4 precision=32", flush=True)
-    fac = P.factor(A, P.order_grid(dims, L), eps=1e-4, precision=32)
-    _ranks_agree(fac, F, L, 1)
-    x, info = fac.solve(_dev(b), tol=1e-10)
-    res = np.linalg.norm(A @ x.cpu().numpy() - b) / np.linalg.norm(b)
-    assert res <= 1e-10
-    assert info[0]["iterations"] <= it_o + max(1, math.ceil(0.1 * it_o)), (info, it_o)
 
 
 def test_device_resident_input_matches_host_input():
@@ -244,12 +215,31 @@ def test_kernel_profiler_counts_launches():
     P.profile_enable(False)
 
 
-def test_3d_wide_interfaces_against_oracle():
-    """20^3 grid: the coarse interfaces have more than 64 unknowns and
-    thousands of columns, so the sparsification runs in the cooperative
-    multi-workgroup CPQR.  FP64 ranks within +-1 of the oracle, iteration
-    counts within the 10% bar, both solves at 1e-10."""
-    print("case 3d 20^3 fp64 eps=1e-2", flush=True)
+# dispatch thresholds that send the blocks of a small 3D grid through every
+# kernel the large workloads use: the LDS-panel QR (fronts over 256 rows), the
+# matrix-core trailing update (64-reflector blocks), the general scaling
+# kernels (blocks over 16), the cooperative CPQR for every interface, the
+# reflector apply of interfaces over 16 unknowns; and with the cooperative
+# CPQR and the matrix cores off, the single-workgroup LDS and generic CPQR
+# kernels and the vector-ALU trailing-update slices
+FORCED = [
+    (dict(), ("k_qr_reg", "k_cpqr_coop", "k_scale_small", "k_ap_iface_dense", "k_wy_tblock", "k_trail_mfma")),
+    (dict(qr_reg_max_rows=256, split_rows=256, split_cols=256, cpqr_reg=0, scale_small=16, iface_dense=16),
+     ("k_qr", "k_wy_tblock", "k_trail_mfma", "k_scale_right", "k_cpqr_coop", "k_ap_iface_fwd", "k_ap_iface_bwd",
+      "k_ap_front_bwd_reg")),
+    (dict(cpqr_reg=0, cpqr_coop=0, scale_small=0, iface_dense=0, trail_mfma=0),
+     ("k_sparsify_small", "k_sparsify", "k_trail", "k_scale_right", "k_ap_iface_fwd", "k_ap_iface_bwd")),
+]
+
+
+def test_3d_every_kernel_path_against_oracle():
+    """20^3 grid (interfaces up to ~280 unknowns with ~4000 columns, fronts
+    up to ~540 rows and ~1500 trailing columns): the FP64 engine under the
+    default dispatch and under thresholds that force the other kernel of every
+    phase, each checked against the oracle -- ranks equal on every interface
+    and M^{-1} b element by element -- with launch counts showing the kernels
+    ran.  FP32 under the same dispatch variants: ranks within +-1 and M^{-1} b
+    within 1e-3; both precisions converge within the iteration window."""
     dims = (20, 20, 20)
     A = convdiff(dims, (5.0, 5.0, 5.0))
     N = A.shape[0]
@@ -257,13 +247,123 @@ def test_3d_wide_interfaces_against_oracle():
     F = _oracle(A, dims, L, 1e-2)
     assert max(max(r for r in F.stages[k]["ranks"].values()) for k in F.stages
                if F.stages[k]["sparsified"]) > 64
+    b = make_rhs(N, 2, seed=3)
+    yo = oracle_spaqr.apply(F, b)
+    it_o, _ = _oracle_its(A, F, b[:, 0])
+    families = ("k_qr_reg", "k_qr", "k_trail", "k_wy_tblock", "k_trail_mfma", "k_scale_small", "k_scale",
+                "k_scale_right", "k_cpqr_reg",
+                "k_cpqr_coop", "k_sparsify_small", "k_sparsify", "k_iface_form", "k_ap_front_fwd_reg",
+                "k_ap_front_fwd_wy", "k_ap_front_bwd_reg", "k_ap_iface_dense", "k_ap_iface_fwd", "k_ap_iface_bwd")
+    try:
+        for tune, kernels in FORCED:
+            for prec in (64, 32):
+                print(f"case 3d 20^3 precision={prec} tuning={tune}", flush=True)
+                P.set_tuning()
+                P.set_tuning(**tune)
+                P.kernel_launches(None)
+                fac = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=prec)
+                yg = fac.apply(_dev(b)).cpu().numpy()
+                counts = {k: P.kernel_launches(k) for k in families}
+                print(f"launches {counts}", flush=True)
+                if prec == 64:
+                    assert all(counts[k] > 0 for k in kernels), counts
+                    _ranks_agree(fac, F, L, 0)
+                    err = np.abs(yg - yo).max() / np.abs(yo).max()
+                    print(f"fp64 apply max rel diff {err:.2e}", flush=True)
+                    assert err <= 1e-10, err
+                else:
+                    _ranks_agree(fac, F, L, 1)
+                    err = np.linalg.norm(yg - yo) / np.linalg.norm(yo)
+                    print(f"fp32 apply rel diff {err:.2e}", flush=True)
+                    assert err <= 1e-3, err
+                x, info = fac.solve(_dev(b[:, :1]), tol=1e-10)
+                assert np.linalg.norm(A @ x.cpu().numpy()[:, 0] - b[:, 0]) / np.linalg.norm(b[:, 0]) <= 1e-10
+                assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o))
+    finally:
+        P.set_tuning()
+
+
+def test_stage_statistics_against_oracle():
+    """Per-stage statistics (Section 4.3 quantities): every sparsified
+    interface's (|p|, m_p, r_p) equals the oracle's CPQR shape, the counted
+    CPQR work equals the method's formula on the oracle's shapes, the
+    per-stage sums add up to the totals, the phase times are measured, and
+    the solve's residual history ends at the true residual."""
+    sys_path_golden()
+    from make_goldens import cpqr_flops
+    dims, L = (48, 40), 6
+    A = convdiff(dims, (-30.0, 15.0))
+    N = A.shape[0]
+    F = _oracle(A, dims, L, 1e-2)
     fac = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=64)
-    _ranks_agree(fac, F, L, 1)
-    b = make_rhs(N, 1, seed=3)[:, 0]
-    x, info = fac.solve(b, tol=1e-10)
-    it_o, rel_o = _oracle_its(A, F, b)
-    assert np.linalg.norm(A @ x - b) / np.linalg.norm(b) <= 1e-10
-    assert abs(info[0]["iterations"] - it_o) <= max(1, math.ceil(0.1 * it_o))
-    fac32 = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=32)
-    x32, info32 = fac32.solve(b, tol=1e-10)
-    assert np.linalg.norm(A @ x32 - b) / np.linalg.norm(b) <= 1e-10
+    st = fac.stats()
+    tot_if = tot_fs = tot_ff = tot_bytes = 0.0
+    shapes = []
+    ms = 0.0
+    for k in range(L, 0, -1):
+        g = fac.stage_stats(k)
+        assert g["stage"] == k
+        tot_ff += g["flops_front"]
+        tot_fs += g["flops_sparsify"]
+        tot_bytes += g["factor_bytes"]
+        ms += g["ms_front"] + g["ms_scale"] + g["ms_sparsify"] + g["ms_merge"]
+        rec = F.stages[k]
+        assert g["sparsified"] == int(rec["sparsified"])
+        assert g["fronts"] == len(rec["fronts"])
+        ifs = fac.stage_interfaces(k)
+        assert ifs.shape[0] == g["interfaces"]
+        tot_if += g["interfaces"]
+        if rec["sparsified"]:
+            want = {p: v for p, v in rec["cpqr_shapes"].items() if v[0] > 0}
+            got = {int(c): (int(p), int(m), int(r)) for c, p, m, r in ifs}
+            assert got == want
+            sizes = fac.stage_sizes(k)
+            assert all(sizes[c] == r for c, _, _, r in ifs)
+            assert g["iface_unknowns_out"] == int(ifs[:, 3].sum()) and g["nbr_cols"] == int(ifs[:, 2].sum())
+            assert g["iface_size_q1"] <= g["iface_size_median"] <= g["iface_size_q3"] <= g["iface_size_max"]
+            shapes.extend(want.values())
+    assert tot_if == st["interfaces_sparsified"]
+    assert abs(tot_ff - st["flops_front"]) <= 1e-9 * st["flops_front"]
+    assert abs(tot_fs - st["flops_sparsify"]) <= 1e-9 * max(1.0, st["flops_sparsify"])
+    assert abs(st["flops_sparsify"] - cpqr_flops(np.array(shapes))) <= 1e-9 * st["flops_sparsify"]
+    assert tot_bytes <= st["factor_bytes"] and ms > 0 and sum(st["ms_phase"]) > 0
+    assert st["top_separator"] == fac.stage_stats(2)["top_separator"] > 0
+    assert st["ms_symbolic"] > 0
+    b = make_rhs(N, 1, seed=2)
+    x, info = fac.solve(_dev(b), tol=1e-10)
+    h = fac.solve_history()
+    assert len(h) == info[0]["iterations"] + 1
+    assert h[-1] == pytest.approx(info[0]["relres"], rel=1e-12) and h[-2] <= 1e-10 and h[0] < 1.0
+
+
+def sys_path_golden():
+    import os
+    import sys
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    if d not in sys.path:
+        sys.path.insert(0, d)
+
+
+def test_apply_graph_replays_match_eager():
+    """From its second apply of a width on, a factorization replays its two
+    sweeps from a captured HIP graph: every replay, with other eager work
+    and synchronizations between them (a different width, a solve), equals
+    the first, eager apply bit for bit."""
+    dims, L = (40, 40), 6
+    A = convdiff(dims, (20.0, -10.0))
+    N = A.shape[0]
+    for prec in (32, 64):
+        fac = P.factor(A, P.order_grid(dims, L), eps=1e-2, precision=prec)
+        b = _dev(make_rhs(N, 2, seed=6))
+        b1 = _dev(make_rhs(N, 1, seed=7))
+        y0 = fac.apply(b).clone()
+        for rep in range(4):
+            y = fac.apply(b)
+            z = fac.apply(b1)            # another width: eager, then its own graph
+            torch.cuda.synchronize()
+            assert torch.equal(y, y0), (prec, rep)
+            if rep == 1:
+                fac.solve(b1, tol=1e-10)  # FGMRES applies in between
+            if rep >= 1:
+                assert torch.equal(z, z_prev), (prec, rep)
+            z_prev = z.clone()

@@ -99,18 +99,27 @@ def test_late_arrivals_join_the_batch():
         _check(j, out[i][0], out[i][1], x_one, info_one)
 
 
+def _estimate(j, nrhs, precision=32):
+    return P.analyze(j["A"], j["ordering"]).estimate_bytes(precision=precision, nrhs=nrhs)
+
+
 def test_admission_by_memory_budget():
-    """A budget that holds one request at a time still serves them all."""
+    """A budget that holds one request at a time: the server never has two
+    requests resident (its occupancy is read after every step) and still
+    serves them all."""
     jobs = [_job(20 + i, *m[:4]) for i, m in enumerate(MIX[:3])]
-    from paper_2010_06807_amd import _abi  # noqa: F401
-    big = max(j["A"].shape[0] for j in jobs)
-    # the estimate of the largest request, with a little room
-    budget = int(big * 4 * (64 + 24 * 12) + 5 * big * 24 + big * 3 * 8 * 204) + (1 << 20)
+    est = [_estimate(j, j["b"].shape[1]) for j in jobs]
+    budget = max(est) + min(est) // 2   # the largest fits, no two do
+    assert all(a + b > budget for a in est for b in est)
     srv = Server(mem_budget=budget)
     tickets = [srv.submit(j["A"], j["ordering"], j["b"], eps=j["eps"]) for j in jobs]
     out = {}
+    seen = 0
     for _ in range(300):
         srv.step()
+        queued, resident, used = srv.status()
+        assert resident <= 1 and used <= budget, (queued, resident, used)
+        seen = max(seen, resident)
         for t in tickets:
             if t not in out:
                 r = srv.poll(t)
@@ -118,12 +127,26 @@ def test_admission_by_memory_budget():
                     out[t] = r
         if len(out) == len(tickets):
             break
-    assert len(out) == len(tickets)
+    assert len(out) == len(tickets) and seen == 1
+    assert srv.status()[:2] == (0, 0)
     for j, t in zip(jobs, tickets):
         x, info = out[t]
         for c in range(j["b"].shape[1]):
             r = np.linalg.norm(j["A"] @ x[:, c] - j["b"][:, c]) / np.linalg.norm(j["b"][:, c])
             assert r <= 1e-10
+
+
+def test_admission_estimate_bounds_measured_factor_bytes():
+    """The analysis's device-memory bound covers what a factorization really
+    stores, in both precisions, for 2D and 3D grids and eps = 0 (nothing
+    compressed, the bound's own worst case)."""
+    for i, (dims, beta, eps) in enumerate([((64, 48), (-30.0, 20.0), 1e-3), ((12, 12, 12), (5.0,) * 3, 0.0),
+                                           ((96, 96), (50.0, -20.0), 0.0), ((16, 16, 16), (2.0, 1.0, -1.0), 1e-2)]):
+        j = _job(40 + i, dims, beta, eps, 1)
+        for prec in (32, 64):
+            fac = P.factor(j["A"], j["ordering"], eps=eps, precision=prec)
+            fb = fac.stats()["factor_bytes"]
+            assert 0 < fb <= _estimate(j, 1, prec), (dims, prec, fb)
 
 
 def test_trace_replay():

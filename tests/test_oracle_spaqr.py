@@ -93,24 +93,118 @@ def test_qt_preserves_norms():
     assert np.allclose(np.linalg.norm(w, axis=0), np.linalg.norm(v, axis=0), rtol=1e-13)
 
 
-def test_scaling_gives_identity_blocks():
-    """After block-diagonal scaling every interface has A_pp = I (Section 2.6):
-    U_pp^T A_pp R_pp^{-1} = I, checked through the stored U and R."""
+def _dense_u(V, tau):
+    """U = H_0 H_1 ... H_{r-1} as a dense matrix, H_t = I - tau_t v_t v_t^T
+    (formed here with plain matrix products, independently of the oracle)."""
+    P = V.shape[0]
+    U = np.eye(P)
+    for t in range(V.shape[1]):
+        v = V[:, t:t + 1]
+        U = U @ (np.eye(P) - tau[t] * (v @ v.T))
+    return U
+
+
+def test_scaling_transforms_the_prescaling_blocks():
+    """Section 2.6 on the real blocks of a factorization: with the block
+    dictionary captured just before and just after the scaling step of every
+    sparsified stage,
+      * the diagonal block before scaling satisfies U_pp^T A_pp R_pp^{-1} = I
+        (A_pp from the snapshot; U_pp built densely from the stored
+        reflectors, R_pp the stored factor);
+      * a block (p, j) became U_pp^T A_pj, a block (i, p) became A_ip R_pp^{-1},
+        a block between two scaled interfaces U_p^T A_pq R_q^{-1} (left
+        before right), and A_pp became I;
+      * blocks of clusters that were not scaled are untouched (none occur
+        here: after the fronts of level k every remaining cluster is an
+        interface of a separator above k, and all of them scale)."""
     A = convdiff((24, 24), (30.0, -10.0))
     o = order_grid((24, 24), 5)
+    snaps = {}
+
+    def trace(k, event, blocks):
+        snaps[(k, event)] = blocks
+
+    F = spaqr.factor(A, o, 1e-2, trace=trace)
+    stages = sorted({k for k, _ in snaps})
+    assert stages
+    nblk = nboth = 0
+    for k in stages:
+        pre, post = snaps[(k, "before_scaling")], snaps[(k, "after_scaling")]
+        assert set(pre) == set(post)
+        fac = {op[2]: (_dense_u(op[4], op[5]), op[6]) for op in F.ops if op[0] == "scale" and op[1] == k}
+        assert fac
+        for p, (U, R) in fac.items():
+            M = np.linalg.solve(R.T, (U.T @ pre[(p, p)]).T).T
+            assert np.abs(M - np.eye(R.shape[0])).max() <= 1e-12 * np.linalg.cond(R)
+        for (i, j), B in pre.items():
+            if i == j and i in fac:
+                assert np.array_equal(post[(i, j)], np.eye(B.shape[0]))
+                continue
+            want = B
+            if i in fac:
+                want = fac[i][0].T @ want
+            if j in fac:
+                want = np.linalg.solve(fac[j][1].T, want.T).T
+            scale = max(1.0, np.abs(want).max()) * (np.linalg.cond(fac[j][1]) if j in fac else 1.0)
+            assert np.abs(post[(i, j)] - want).max() <= 1e-13 * scale, (k, i, j)
+            nblk += 1
+            nboth += (i in fac) and (j in fac)
+    assert nblk > 0 and nboth > 0
+
+
+def test_same_colour_items_touch_disjoint_blocks():
+    """R5 and R8: fronts of one colour update disjoint blocks and none of
+    them reads a block another one of the colour writes; interfaces of one
+    colour read and write disjoint sets of blocks."""
+    A = convdiff((12, 12, 12), (5.0, 5.0, 5.0))
+    o = order_grid((12, 12, 12), 6)
     F = spaqr.factor(A, o, 1e-2)
-    nsc = 0
-    for op in F.ops:
-        if op[0] != "scale":
+    checked_f = checked_i = 0
+    for k, rec in F.stages.items():
+        by_c = {}
+        for s, (n1, cols, c) in rec["fronts"].items():
+            writes = {(i, j) for i in n1 for j in cols}
+            reads = {(r, j) for r in [s] + n1 for j in [s] + cols}
+            by_c.setdefault(c, []).append((writes, reads))
+        for items in by_c.values():
+            for a in range(len(items)):
+                for b in range(len(items)):
+                    if a != b:
+                        assert not (items[a][0] & items[b][0])
+                        assert not (items[a][0] & items[b][1])
+                        checked_f += 1
+        if not rec["sparsified"]:
             continue
-        V, tau, R = op[4], op[5], op[6]
-        Ui = apply_reflectors(V, tau, np.eye(V.shape[0]), transpose=False)
-        App = Ui @ R
-        Ut = apply_reflectors(V, tau, App, transpose=True)
-        M = sla.solve_triangular(R, Ut.T, trans="T").T
-        assert np.abs(M - np.eye(M.shape[0])).max() <= 1e-12 * max(1.0, np.linalg.cond(R))
-        nsc += 1
-    assert nsc > 0
+        pattern = set(rec["pattern_post"])
+        touch = {}
+        for p, c in rec["iface_colour"].items():
+            t = {(i, j) for (i, j) in pattern if i == p or j == p}
+            touch.setdefault(c, []).append(t)
+        for items in touch.values():
+            for a in range(len(items)):
+                for b in range(a + 1, len(items)):
+                    assert not (items[a] & items[b])
+                    checked_i += 1
+    assert checked_f > 0 and checked_i > 0
+
+
+def test_order_inside_a_colour_does_not_change_the_result():
+    """O8 / R5: processing the fronts and interfaces of every colour in
+    descending instead of ascending id gives bitwise the same factors and the
+    same M^{-1} b."""
+    A = convdiff((12, 12, 12), (5.0, 5.0, 5.0))
+    o = order_grid((12, 12, 12), 6)
+    Fa = spaqr.factor(A, o, 1e-2)
+    Fd = spaqr.factor(A, o, 1e-2, within_colour="descending")
+    key = lambda op: (op[0], -op[1], op[2])  # noqa: E731
+    oa, od = sorted(Fa.ops, key=key), sorted(Fd.ops, key=key)
+    assert len(oa) == len(od)
+    for x, y in zip(oa, od):
+        assert key(x) == key(y)
+        for u, v in zip(x[3:], y[3:]):
+            assert np.array_equal(np.asarray(u), np.asarray(v))
+    b = make_rhs(A.shape[0], 2, seed=4)
+    assert np.array_equal(spaqr.apply(Fa, b), spaqr.apply(Fd, b))
 
 
 # ----------------------------------------------------------------------------
