@@ -43,17 +43,20 @@ WORKLOAD_TEXT = {
     "c4": "2D advection-dominated, 5-point upwind with perturbed entries,",
 }
 
-# Published MI355X peaks used for the roofline fractions.
+# Published MI355X peaks used for the roofline fractions (dense matrix-core
+# FP32 and the FP32 vector rate are the same published figure).
 PEAK = {
     "hbm": (8000.0, "GB/s"),
     "alu32": (157.3, "TFLOP/s"),
     "alu64": (78.6, "TFLOP/s"),
+    "mfma32": (157.3, "TFLOP/s"),
 }
 # bound of each kernel: HBM-bound data movement / apply, or vector-ALU
 # arithmetic (the factorization kernels run on the VALU, not on MFMA; the
 # CPQR's work is counted from the ranks read back after each stage)
 KERNEL_BOUND = {
-    "front_qr": "alu", "front_trail": "alu", "scale_qr": "alu", "scale_blocks": "alu", "sparsify": "alu",
+    "front_qr": "alu", "front_trail": "mfma", "front_wy_blocks": "mfma", "scale_qr": "alu", "scale_blocks": "alu",
+    "sparsify": "alu",
     "apply_front_fwd": "hbm", "apply_front_bwd": "hbm", "apply_iface_fwd": "hbm", "apply_iface_bwd": "hbm",
 }
 
@@ -76,6 +79,9 @@ def parse():
     ap.add_argument("--cpu-side", type=int, default=256,
                     help="grid side of the bounded sample the oracle runs for cpu_baseline")
     ap.add_argument("--kernel", default=None, help="kernel group for the roofline (default: the slowest)")
+    ap.add_argument("--tuning", default=None,
+                    help="dispatch thresholds for the run, e.g. 'trail_mfma=0,split_rows=512' (spaqr_tuning); "
+                         "'table' applies the autotuned entry of the workload")
     ap.add_argument("--serving-requests", type=int, default=16,
                     help="requests of the serving trace replayed after the single-problem steps (0: skip)")
     ap.add_argument("--serving-load", type=float, default=0.7,
@@ -352,6 +358,13 @@ def main():
     import paper_2010_06807_amd as P
     from problems import config_problem, make_rhs
 
+    tuning = None
+    if args.tuning == "table":
+        from paper_2010_06807_amd import autotune
+        tuning = autotune.apply(args.workload)
+    elif args.tuning:
+        tuning = {k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))}
+        P.set_tuning(**tuning)
     S = max(1, args.seeds)
     probs = [config_problem(args.workload, seed=i) for i in range(S)]
     prob = probs[0]
@@ -433,13 +446,16 @@ def main():
                    "gmres_iterations": max(r64["its"]), "relres": max(r64["res"]),
                    "ms_factor": 1e3 * float(np.mean(r64["fac_t"])), "ms_solve": 1e3 * float(np.mean(r64["sol_t"]))}
 
+    def rate(bound, q):
+        """(achieved, peak, unit) of one profiler record under its bound."""
+        if bound == "hbm":
+            peak, unit = PEAK["hbm"]
+            return (q["bytes"] / (q["total_ms"] * 1e-3) / 1e9 if q["total_ms"] > 0 else 0.0), peak, unit
+        peak, unit = PEAK["mfma32" if bound == "mfma" else "alu32"]
+        return (q["flops"] / (q["total_ms"] * 1e-3) / 1e12 if q["total_ms"] > 0 else 0.0), peak, unit
+
     bound = KERNEL_BOUND[kern]
-    if bound == "hbm":
-        peak, unit = PEAK["hbm"]
-        achieved = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
-    else:
-        peak, unit = PEAK["alu32"]
-        achieved = prof["flops"] / (prof["total_ms"] * 1e-3) / 1e12 if prof["total_ms"] > 0 else 0.0
+    achieved, peak, unit = rate(bound, prof)
     nsteps = args.steps + args.warmup
     roof = {"bound": bound, "kernel": kern, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": measured_traffic(kern, args.workload),
@@ -447,7 +463,11 @@ def main():
             "ms_per_step": prof["total_ms"] / nsteps,
             "work_per_step": (prof["bytes"] if bound == "hbm" else prof["flops"]) / nsteps,
             "work_per_launch": (prof["bytes"] if bound == "hbm" else prof["flops"]) / max(1, prof["launches"]),
-            "survey_ms": {n: round(v["total_ms"], 3) for n, v in survey.items() if v["launches"]}}
+            "survey_ms": {n: round(v["total_ms"], 3) for n, v in survey.items() if v["launches"]},
+            # every group of the survey step: time, work and the rate against its bound's peak
+            "survey": {n: dict(zip(("achieved", "peak", "unit"), rate(KERNEL_BOUND[n], v)), ms=v["total_ms"],
+                               launches=v["launches"], bound=KERNEL_BOUND[n])
+                       for n, v in survey.items() if v["launches"]}}
     # achieved HBM rate of the apply and scaling phases in the survey step
     # (algorithmic bytes of the launches / their event time)
     phases = {}
@@ -468,7 +488,7 @@ def main():
                                f"{'x'.join(str(d) for d in dims)} (N={N}), eps={args.eps}, "
                                f"{L} ND levels, FP32 factors + FP64 FGMRES to {args.tol}, 1 RHS, one problem per "
                                f"step (seeds 0..{S - 1} in turn), analysis of the shared pattern made once",
-                   "eps": args.eps, "levels": L, "n": N},
+                   "eps": args.eps, "levels": L, "n": N, "tuning": tuning},
         "latency_ms": {"p50": 1e3 * pct(r32["lat"], 50), "p99": 1e3 * pct(r32["lat"], 99)},
         "phase_ms": {"factor": 1e3 * float(np.mean(r32["fac_t"])), "solve": 1e3 * float(np.mean(r32["sol_t"])),
                      "order_and_analysis": 1e3 * t_analysis},

@@ -223,12 +223,16 @@ def test_kernel_profiler_counts_launches():
 # CPQR and the matrix cores off, the single-workgroup LDS and generic CPQR
 # kernels and the vector-ALU trailing-update slices
 FORCED = [
-    (dict(), ("k_qr_reg", "k_cpqr_coop", "k_scale_small", "k_ap_iface_dense", "k_wy_tblock", "k_trail_mfma")),
+    # (thresholds, kernels an FP64 factorization + apply must launch, the same for FP32)
+    (dict(), ("k_qr_reg", "k_cpqr_coop", "k_scale_small", "k_ap_iface_dense", "k_wy_tblock", "k_trail_mfma"),
+     ("k_qr_reg", "k_cpqr_reg", "k_cpqr_coop", "k_wy_tblock", "k_trail_mfma")),
     (dict(qr_reg_max_rows=256, split_rows=256, split_cols=256, cpqr_reg=0, scale_small=16, iface_dense=16),
      ("k_qr", "k_wy_tblock", "k_trail_mfma", "k_scale_right", "k_cpqr_coop", "k_ap_iface_fwd", "k_ap_iface_bwd",
-      "k_ap_front_bwd_reg")),
+      "k_ap_front_bwd_reg"),
+     ("k_qr", "k_wy_tblock", "k_trail_mfma", "k_cpqr_coop")),
     (dict(cpqr_reg=0, cpqr_coop=0, scale_small=0, iface_dense=0, trail_mfma=0),
-     ("k_sparsify_small", "k_sparsify", "k_trail", "k_scale_right", "k_ap_iface_fwd", "k_ap_iface_bwd")),
+     ("k_sparsify", "k_trail", "k_scale_right", "k_ap_iface_fwd", "k_ap_iface_bwd"),
+     ("k_sparsify_small", "k_trail", "k_scale_right")),
 ]
 
 
@@ -255,8 +259,9 @@ def test_3d_every_kernel_path_against_oracle():
                 "k_cpqr_coop", "k_sparsify_small", "k_sparsify", "k_iface_form", "k_ap_front_fwd_reg",
                 "k_ap_front_fwd_wy", "k_ap_front_bwd_reg", "k_ap_iface_dense", "k_ap_iface_fwd", "k_ap_iface_bwd")
     try:
-        for tune, kernels in FORCED:
+        for tune, kernels64, kernels32 in FORCED:
             for prec in (64, 32):
+                kernels = kernels64 if prec == 64 else kernels32
                 print(f"case 3d 20^3 precision={prec} tuning={tune}", flush=True)
                 P.set_tuning()
                 P.set_tuning(**tune)
@@ -265,8 +270,8 @@ def test_3d_every_kernel_path_against_oracle():
                 yg = fac.apply(_dev(b)).cpu().numpy()
                 counts = {k: P.kernel_launches(k) for k in families}
                 print(f"launches {counts}", flush=True)
+                assert all(counts[k] > 0 for k in kernels), counts
                 if prec == 64:
-                    assert all(counts[k] > 0 for k in kernels), counts
                     _ranks_agree(fac, F, L, 0)
                     err = np.abs(yg - yo).max() / np.abs(yo).max()
                     print(f"fp64 apply max rel diff {err:.2e}", flush=True)
