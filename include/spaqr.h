@@ -182,6 +182,24 @@ spaqr_status spaqr_factor_batch(int nprob, const spaqr_csr* const* A, const spaq
 spaqr_status spaqr_apply(spaqr_handle* h, const double* b, double* x,
                          int64_t nrhs, int64_t ld, int on_device);
 
+/* The apply of spaqr_apply for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  b and x are device pointers (n x nrhs, column-major, leading
+ * dimension ld >= n; they may alias).  The only workspace, the permuted
+ * vectors, is a fixed array of 2^23 doubles (64 MiB) that the library holds on
+ * every GPU it runs on until the process ends (spaqr_apply_noalloc_max()
+ * returns that size): n * nrhs must not exceed it.  The call allocates
+ * nothing, enqueues the apply on the handle's stream and returns without
+ * waiting; the result is complete once that stream has passed it.  Every
+ * call on one GPU uses that GPU's one array, so calls whose work overlaps on
+ * one GPU (on different streams, or from several threads) race; calls on one
+ * stream are ordered.  The array's contents are overwritten by every call.
+ * Errors: EINVAL (NULL pointer, nrhs < 1, ld < n, n * nrhs above the array,
+ * a handle without a complete factorization), EDEVICE. */
+spaqr_status spaqr_apply_noalloc(spaqr_handle* h, const double* b, double* x,
+                                 int64_t nrhs, int64_t ld);
+int64_t spaqr_apply_noalloc_max(void);
+
 /* Per-column outcome of spaqr_solve. */
 typedef struct {
   int32_t iterations;  /* Arnoldi steps taken */

@@ -256,6 +256,18 @@ class Factorization:
               "spaqr_apply")
         return out
 
+    def apply_noalloc(self, b, out):
+        """out = M^{-1} b through spaqr_apply_noalloc (no device allocation;
+        b and out are device tensors, column-major); returns once the work
+        is enqueued on the factorization's stream."""
+        nrhs, ld = self._layout(b, self.n)
+        nrhs_o, ld_o = self._layout(out, self.n)
+        if (nrhs_o, ld_o) != (nrhs, ld):
+            raise ValueError("b and out must have the same layout")
+        check(_abi.load().spaqr_apply_noalloc(self._h, C.c_void_p(b.data_ptr()), C.c_void_p(out.data_ptr()),
+                                              nrhs, ld), "spaqr_apply_noalloc")
+        return out
+
     def solve(self, b, tol=1e-10, out=None):
         lib = _abi.load()
         on_dev = hasattr(b, "is_cuda") and b.is_cuda

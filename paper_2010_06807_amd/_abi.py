@@ -106,6 +106,8 @@ SIGNATURES = {
     "spaqr_stage_stats": (C.c_int, [_P, C.c_int, C.POINTER(StageStats)]),
     "spaqr_stage_interfaces": (C.c_int, [_P, C.c_int, _I32P, C.c_int64, _I64P]),
     "spaqr_solve_history": (C.c_int, [_P, _DP, C.c_int64, _I64P]),
+    "spaqr_apply_noalloc": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64]),
+    "spaqr_apply_noalloc_max": (C.c_int64, []),
     "spaqr_set_tuning": (C.c_int, [C.POINTER(Tuning)]),
     "spaqr_get_tuning": (C.c_int, [C.POINTER(Tuning)]),
     "spaqr_kernel_launches": (C.c_int, [C.c_char_p, _I64P]),
