@@ -202,12 +202,12 @@ def pct(v, q):
 # kernel symbols behind each profiler group (FP32 instantiations)
 GROUP_KERNELS = {
     "front_qr": ("k_qr_reg<float", "k_qr<float"),
-    "trailing updates (fronts and scaling)": ("k_trail<float",),
+    "trailing updates (fronts and scaling)": ("k_trail<float", "k_trail_mfma<float", "k_wy_tblock<float"),
     "block copies and zero fills": ("k_copy<float", "k_copy_t<float", "k_zero", "k_fill<float"),
     "descriptor uploads and readbacks": ("__amd_rocclr_copyBuffer", "k_gather_ints"),
     "interface operators (forming)": ("k_iface_form<float",),
     "scale_blocks": ("k_scale<float", "k_scale_small<float", "k_scale_right<float"),
-    "sparsify": ("k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
+    "sparsify": ("k_cpqr_dd", "k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
     "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
     "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),

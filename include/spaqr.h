@@ -363,7 +363,13 @@ void spaqr_free(spaqr_handle* h);
  *                     apply operators (0, 16, 32 or 64; default 64);
  *   trail_mfma        1: the trailing columns of a split front are updated
  *                     on the matrix cores, 64 reflectors and 64 columns at a
- *                     time; 0: by the vector-ALU slice kernel (default 1).
+ *                     time; 0: by the vector-ALU slice kernel (default 1);
+ *   cpqr_dd           1: FP32 interfaces of at most 64 unknowns whose
+ *                     columns fit one workgroup take the CPQR with
+ *                     downdated column norms (exact recomputation when a
+ *                     norm has lost three digits, exact norms for the rank
+ *                     rule), every interface of a colour in one launch;
+ *                     0: they take the exact-norm kernels above (default 1).
  * spaqr_set_tuning(NULL) restores the defaults.  Set it only while no
  * factorization or apply is in flight.  Errors: EINVAL for a value outside
  * the ranges above. */
@@ -375,6 +381,7 @@ typedef struct {
   int scale_small;
   int iface_dense;
   int trail_mfma;
+  int cpqr_dd;
 } spaqr_tuning;
 spaqr_status spaqr_set_tuning(const spaqr_tuning* t);
 spaqr_status spaqr_get_tuning(spaqr_tuning* t);

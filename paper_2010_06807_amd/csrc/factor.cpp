@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -1163,6 +1164,31 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
     max_nb = std::max(max_nb, q.nrow + q.ncol);
     max_pc = std::max<int>(max_pc, q.P);
   }
+  SpNbr* dnb = nullptr;
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32 interfaces of at most 64 unknowns whose columns fit one
+    // workgroup: the downdated-norm CPQR, all of them in one launch, the
+    // largest first
+    if (tuning().cpqr_dd) {
+      const auto dd_end = std::stable_partition(sd.begin(), sd.end(), [](const SpDesc<T>& q) {
+        return q.P >= 1 && q.P <= 64 && q.mmax <= sparsify_dd_capacity(q.P);
+      });
+      if (dd_end != sd.begin()) {
+        std::vector<SpDesc<T>> dd(sd.begin(), dd_end);
+        sd.erase(sd.begin(), dd_end);
+        std::stable_sort(dd.begin(), dd.end(), [](const SpDesc<T>& x, const SpDesc<T>& y) {
+          return (int64_t)x.P * x.mmax > (int64_t)y.P * y.mmax;
+        });
+        int lc_rows = 0;
+        for (const SpDesc<T>& q : dd) lc_rows = std::max(lc_rows, sparsify_dd_lc_rows(q.P, q.mmax));
+        SpDesc<T>* ddd = up.upload(wk, dd, s);
+        dnb = up.upload(wk, nb, s);
+        ProfScope ps("sparsify", s, 0.0, 0.0);
+        launch_sparsify_dd(ddd, (int64_t)dd.size(), dnb, max_nb, lc_rows, s);
+      }
+      if (sd.empty()) return;
+    }
+  }
   // interfaces whose columns fit in registers: register CPQR, one launch per
   // (row class, columns per thread) when one shape does not fit all
   const auto nreg_end = std::stable_partition(
@@ -1264,7 +1290,7 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   const int pclass = pmax_small <= 16 ? 16 : (pmax_small <= 32 ? 32 : 64);
   const size_t cmax_small = (size_t)(pclass + 1) * mmax_small;
   SpDesc<T>* dsd = up.upload(wk, sd, s);
-  SpNbr* dnb = up.upload(wk, nb, s);
+  if (!dnb) dnb = up.upload(wk, nb, s);
   double* ckey = nullptr;
   int* cpos = nullptr;
   T* ccol = nullptr;

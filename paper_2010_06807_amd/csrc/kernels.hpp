@@ -227,6 +227,13 @@ void launch_sparsify_reg(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pma
 template <typename T>
 void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int pmax, int max_nb,
                            size_t max_c_elems, hipStream_t s);
+// FP32 CPQR with downdated norms (k_cpqr_dd), every row class in one launch:
+// the most columns an interface of P unknowns may have (0: P outside 1..64),
+// and the LDS rows per thread a launch must provide for one of mmax columns
+// (0: its columns fit in registers).  lc_rows = the largest of the launch.
+int sparsify_dd_capacity(int P);
+int sparsify_dd_lc_rows(int P, int mmax);
+void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s);
 // Apply launches: max_rows = the largest number of FP64 rows one item keeps in
 // LDS per right-hand side (m for fronts forward, n + k backward, P for
 // interfaces).  Returns without launching when there is nothing to do.
