@@ -88,6 +88,11 @@ def parse():
                     help="arrival rate of the serving trace as a fraction of the plain FP64 path's capacity")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving trace and print its record")
+    ap.add_argument("--serving-calibration", type=float, default=None,
+                    help="makespan (s) of the FP64 calibration pass of the same trace, measured before: "
+                         "skips that pass")
+    ap.add_argument("--serving-leg", choices=("both", "batched", "sequential"), default="both",
+                    help="which replays of the serving trace to run")
     ap.add_argument("--rocprof-summary", metavar="DIR", default=None,
                     help="print a markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv "
                          "directory of this script's run and exit (--fp32-steps: FP32 steps in that run)")
@@ -207,7 +212,7 @@ GROUP_KERNELS = {
     "descriptor uploads and readbacks": ("__amd_rocclr_copyBuffer", "k_gather_ints"),
     "interface operators (forming)": ("k_iface_form<float",),
     "scale_blocks": ("k_scale<float", "k_scale_small<float", "k_scale_right<float"),
-    "sparsify": ("k_cpqr_dd", "k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
+    "sparsify": ("k_cpqr_dd", "k_cpqr_team", "k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
     "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
     "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),
@@ -239,42 +244,54 @@ def rocprof_summary(d, fp32_steps):
     return "\n".join(out)
 
 
-def serving(nreq, tol, load=1.0, seed=0):
+def serving(nreq, tol, load=1.0, seed=0, calibration=None, leg="both"):
     """The serving workload: the first nreq requests of the seeded trace
     (2D sides 64..512 or 3D sides 16..48, |beta| 1..200, 1..32 right-hand
     sides, eps 1e-2).  A calibration pass runs the plain FP64 path over the
-    requests back to back; the arrival times are then scaled so that path
-    would be busy a fraction `load` of the time (1.0: exactly saturated), and
-    the trace is replayed through the
-    batched FP32 server and through the sequential FP64 path on the same
-    timestamps.  Throughput counts unknowns x right-hand sides per second of
-    makespan; latency runs from a request's arrival to its last solution."""
+    requests back to back (or `calibration` gives its makespan from an
+    earlier run of the same trace); the arrival times are then scaled so that
+    path would be busy a fraction `load` of the time (1.0: exactly
+    saturated), and the trace is replayed through the batched FP32 server
+    and through the sequential FP64 path on the same timestamps (`leg`
+    selects one of the two).  Throughput counts unknowns x right-hand sides
+    per second of makespan; latency runs from a request's arrival to its
+    last solution."""
     import numpy as np
     import paper_2010_06807_amd as P
     from paper_2010_06807_amd.server import serve_trace, serve_sequential
     from problems.trace import serving_trace, build_request
     reqs = serving_trace(nreq, seed=seed)
     jobs = []
-    for r in reqs:
+    for i, r in enumerate(reqs):
         q = build_request(r)
         jobs.append(dict(arrival=r["arrival"], A=q["A"], ordering=P.order_grid(q["dims"], q["levels"]), b=q["b"],
                          eps=r["eps"]))
-    log(f"serving: {len(jobs)} requests built; calibration pass (FP64, back to back)")
-    _, cal = serve_sequential(jobs, tol=tol, precision=64, time_scale=0.0, log=log)
-    log(f"serving: calibration {cal['makespan_s']:.1f} s")
-    service = cal["makespan_s"] / len(jobs)
+        if (i + 1) % 32 == 0:
+            log(f"serving: {i + 1} requests built")
+    if calibration is None:
+        log(f"serving: {len(jobs)} requests built; calibration pass (FP64, back to back)")
+        _, cal = serve_sequential(jobs, tol=tol, precision=64, time_scale=0.0, log=log)
+        calibration = cal["makespan_s"]
+    log(f"serving: calibration {calibration:.1f} s")
+    service = calibration / len(jobs)
     mean_gap = float(np.mean(np.diff([0.0] + [r["arrival"] for r in reqs])))
     scale = service / load / mean_gap
-    res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale, log=log)
-    log(f"serving: batched FP32 makespan {batched['makespan_s']:.1f} s")
-    res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale, log=log)
-    log(f"serving: sequential FP64 makespan {plain['makespan_s']:.1f} s")
-    worst = max(max(r["relres"]) for r in res_b + res_s)
-    return {"requests": len(jobs), "unknowns_x_rhs": int(sum(j["A"].shape[0] * j["b"].shape[1] for j in jobs)),
-            "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": load,
-            "batched_fp32": {k: batched[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
-            "plain_fp64": {k: plain[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")},
-            "max_relres": worst, "unit": "unknowns*rhs/s"}
+    out = {"requests": len(jobs), "unknowns_x_rhs": int(sum(j["A"].shape[0] * j["b"].shape[1] for j in jobs)),
+           "arrival_rate_per_s": 1.0 / (mean_gap * scale), "load_fp64": load, "calibration_s": calibration,
+           "unit": "unknowns*rhs/s"}
+    worst = 0.0
+    if leg in ("both", "batched"):
+        res_b, batched = serve_trace(jobs, mem_budget=64 << 30, tol=tol, precision=32, time_scale=scale, log=log)
+        log(f"serving: batched FP32 makespan {batched['makespan_s']:.1f} s")
+        out["batched_fp32"] = {k: batched[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")}
+        worst = max(worst, max(max(r["relres"]) for r in res_b))
+    if leg in ("both", "sequential"):
+        res_s, plain = serve_sequential(jobs, tol=tol, precision=64, time_scale=scale, log=log)
+        log(f"serving: sequential FP64 makespan {plain['makespan_s']:.1f} s")
+        out["plain_fp64"] = {k: plain[k] for k in ("throughput", "p50_ms", "p99_ms", "makespan_s")}
+        worst = max(worst, max(max(r["relres"]) for r in res_s))
+    out["max_relres"] = worst
+    return out
 
 
 def cpu_info():
@@ -351,7 +368,8 @@ def main():
               "(the nested-dissection tree would shard over GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.serving_only:
-        print(json.dumps(serving(args.serving_requests, args.tol, args.serving_load)), flush=True)
+        print(json.dumps(serving(args.serving_requests, args.tol, args.serving_load,
+                                 calibration=args.serving_calibration, leg=args.serving_leg)), flush=True)
         return
     import numpy as np
     import torch

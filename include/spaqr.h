@@ -369,7 +369,12 @@ void spaqr_free(spaqr_handle* h);
  *                     downdated column norms (exact recomputation when a
  *                     norm has lost three digits, exact norms for the rank
  *                     rule), every interface of a colour in one launch;
- *                     0: they take the exact-norm kernels above (default 1).
+ *                     0: they take the exact-norm kernels above (default 1);
+ *   cpqr_team         1: FP32 interfaces of at most 896 unknowns beyond one
+ *                     workgroup take the team CPQR (a team of co-resident
+ *                     workgroups per interface, all columns in registers,
+ *                     downdated norms as for cpqr_dd); 0: they take the
+ *                     cooperative kernel (default 1).
  * spaqr_set_tuning(NULL) restores the defaults.  Set it only while no
  * factorization or apply is in flight.  Errors: EINVAL for a value outside
  * the ranges above. */
@@ -382,6 +387,7 @@ typedef struct {
   int iface_dense;
   int trail_mfma;
   int cpqr_dd;
+  int cpqr_team;
 } spaqr_tuning;
 spaqr_status spaqr_set_tuning(const spaqr_tuning* t);
 spaqr_status spaqr_get_tuning(spaqr_tuning* t);
@@ -419,7 +425,9 @@ void spaqr_finalize(void);
  *   one launch per phase whatever stage each one is at, so a request that
  *   arrives while others are half-way joins their batch; (3) solves every
  *   request whose factorization is complete, all its right-hand sides at once
- *   (multi-RHS FGMRES to its tol), and retires it.  *active (may be NULL)
+ *   (multi-RHS FGMRES to its tol), in groups of similar size that share one
+ *   batched FGMRES (at most 64 right-hand sides and 2^23 padded vector
+ *   entries per group), and retires it.  *active (may be NULL)
  *   receives the number of requests still queued or in flight.  A request
  *   whose factorization fails (zero column, zero R_ss diagonal) is retired
  *   with that status; the others continue.

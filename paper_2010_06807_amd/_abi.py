@@ -43,7 +43,8 @@ class StageStats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("qr_reg_max_rows", C.c_int), ("split_rows", C.c_int), ("split_cols", C.c_int),
                 ("cpqr_reg", C.c_int), ("cpqr_coop", C.c_int), ("scale_small", C.c_int), ("iface_dense", C.c_int),
-                ("trail_mfma", C.c_int), ("cpqr_dd", C.c_int)]
+                ("trail_mfma", C.c_int), ("cpqr_dd", C.c_int),
+                ("cpqr_team", C.c_int)]
 
 
 class SolveInfo(C.Structure):

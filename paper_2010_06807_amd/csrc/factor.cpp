@@ -1022,6 +1022,7 @@ struct BatchCtx {
   hipEvent_t ev = nullptr;          // end of the enqueued part of the current stage
   std::shared_ptr<PhaseEvents> pe;  // phase events of the current stage
   PinnedChunk rb;                   // ranks and flags of the current stage, all problems
+  int32_t team_err_at = -1;         // index in rb of the team CPQR timeout flag
   BatchCtx() = default;
   BatchCtx(const BatchCtx&) = delete;
   BatchCtx& operator=(const BatchCtx&) = delete;
@@ -1157,7 +1158,7 @@ static void copy_batch(const std::vector<CopyTile<T>>& tiles, bool transpose, St
 
 template <typename T>
 static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>& nb, Stager& up, DevArena& wk,
-                           hipStream_t s) {
+                           hipStream_t s, int* team_err) {
   if (sd.empty()) return;
   int max_nb = 0, max_pc = 1;
   for (const SpDesc<T>& q : sd) {
@@ -1185,6 +1186,52 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
         dnb = up.upload(wk, nb, s);
         ProfScope ps("sparsify", s, 0.0, 0.0);
         launch_sparsify_dd(ddd, (int64_t)dd.size(), dnb, max_nb, lc_rows, s);
+      }
+      if (sd.empty()) return;
+    }
+    // FP32 interfaces of at most 896 unknowns beyond one workgroup: a team of
+    // co-resident workgroups per interface, the interfaces packed into
+    // launches of at most the device's co-resident workgroups, the largest
+    // first
+    if (tuning().cpqr_team) {
+      const int cap = sparsify_team_capacity(max_nb);
+      const auto tm_end = std::stable_partition(sd.begin(), sd.end(), [&](const SpDesc<T>& q) {
+        const int nb_q = sparsify_team_blocks(q.P, q.mmax);
+        return nb_q > 0 && nb_q <= cap;
+      });
+      if (tm_end != sd.begin()) {
+        std::vector<SpDesc<T>> tm(sd.begin(), tm_end);
+        sd.erase(sd.begin(), tm_end);
+        std::stable_sort(tm.begin(), tm.end(), [](const SpDesc<T>& x, const SpDesc<T>& y) {
+          return sparsify_team_blocks(x.P, x.mmax) > sparsify_team_blocks(y.P, y.mmax);
+        });
+        struct TeamLaunch {
+          size_t begin, end;
+          int blocks;
+        };
+        std::vector<TeamLaunch> launches;
+        std::vector<CoopItem> items;
+        int max_blocks = 0;
+        for (size_t t = 0; t < tm.size(); ++t) {
+          const int nb_t = sparsify_team_blocks(tm[t].P, tm[t].mmax);
+          if (launches.empty() || launches.back().blocks + nb_t > cap) launches.push_back({t, t, 0});
+          items.push_back({launches.back().blocks, nb_t});
+          launches.back().blocks += nb_t;
+          launches.back().end = t + 1;
+          max_blocks = std::max(max_blocks, launches.back().blocks);
+        }
+        SpDesc<T>* dtm = up.upload(wk, tm, s);
+        CoopItem* ditems = up.upload(wk, items, s);
+        if (!dnb) dnb = up.upload(wk, nb, s);
+        int* sync = wk.alloc_n<int>(2 * tm.size(), s);
+        char* cand = wk.alloc_n<char>(sparsify_team_cand_bytes(max_blocks), s);
+        launch_zero_ops({{sync, (int64_t)(2 * tm.size() * sizeof(int))}}, up, wk, s);
+        for (const TeamLaunch& L : launches) {
+          ProfScope ps("sparsify", s, 0.0, 0.0);
+          if (!launch_sparsify_team(dtm + L.begin, ditems + L.begin, (int)(L.end - L.begin), L.blocks, dnb, max_nb,
+                                    sync + 2 * L.begin, cand, max_blocks, team_err, s))
+            throw Error(SPAQR_EDEVICE, "team CPQR no longer fits the device");
+        }
       }
       if (sd.empty()) return;
     }
@@ -1581,7 +1628,10 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
     }
   }
   bx.pe->record(2, s);
-  // sparsification, colour by colour
+  // sparsification, colour by colour; team_err: set by a team CPQR whose
+  // barrier wait ran out (read back with the ranks, thrown in stage_finish)
+  int* team_err = wk.alloc_n<int>(1, s);
+  launch_zero_ops({{team_err, (int64_t)sizeof(int)}}, up, wk, s);
   {
     HostScope hs("host_plan_sparsify");
     bx.each(ne, [&](int e) { es[e]->plan_sparsify(pl[e]); });
@@ -1603,7 +1653,7 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
         sd.push_back(d);
       }
     }
-    sparsify_batch<T>(sd, nb, up, wk, s);
+    sparsify_batch<T>(sd, nb, up, wk, s, team_err);
   }
   {
     // dense interface operators, one launch per size class (16, 32, 64)
@@ -1631,6 +1681,8 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
       es[i]->readback_ops(ops, tot);
       tot += es[i]->readback_ints();
     }
+    ops.push_back({team_err, tot, 1});
+    bx.team_err_at = tot++;
     int32_t* d = wk.alloc_n<int32_t>((size_t)tot, s);
     launch_gather_ints(ops.data(), (int)ops.size(), d, s);
     if (bx.rb.size < (size_t)tot * sizeof(int32_t)) {
@@ -1654,6 +1706,8 @@ void stage_finish(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
     HostScope hs("host_wait_gpu");
     SPAQR_HIP(hipEventSynchronize(bx.ev));
   }
+  if (bx.team_err_at >= 0 && reinterpret_cast<const int32_t*>(bx.rb.p)[bx.team_err_at] != 0)
+    throw Error(SPAQR_EDEVICE, "a team CPQR barrier wait ran out (results of the stage invalid)");
   std::vector<MergePlan<T>> mp(ne);
   {
     HostScope hs("host_finish");

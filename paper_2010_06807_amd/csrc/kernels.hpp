@@ -256,6 +256,21 @@ void launch_front_bwd_reg(const ApFront<T>* d, int64_t n, int max_n, int max_k, 
 struct CoopItem {
   int32_t first, nblk;
 };
+// FP32 CPQR of wide interfaces by teams of co-resident workgroups
+// (k_cpqr_team): workgroups a team needs for P unknowns and mmax columns (0:
+// P outside 1..896), workgroups one launch may hold, the bytes of the
+// candidate buffer for launches of at most max_blocks workgroups, and the
+// launch.  items: each team's first workgroup and size; sync: two zeroed ints
+// per team (left zeroed for reuse); cand: the candidate buffer, laid out for
+// cand_blocks workgroups; err: set to 1 if a team barrier wait ran out (the
+// kernel then still ends, with invalid results).  Returns false (nothing
+// launched) when the workgroups cannot be co-resident.
+int sparsify_team_blocks(int P, int mmax);
+int sparsify_team_capacity(int max_nb);
+size_t sparsify_team_cand_bytes(int max_blocks);
+bool launch_sparsify_team(const SpDesc<float>* d, const CoopItem* items, int nitems, int total_blocks,
+                          const SpNbr* nb, int max_nb, int* sync, void* cand, int cand_blocks, int* err,
+                          hipStream_t s);
 // Returns false (nothing launched) if the items cannot be co-resident; then
 // the caller falls back to the single-workgroup kernels.
 template <typename T>

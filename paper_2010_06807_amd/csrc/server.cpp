@@ -128,24 +128,32 @@ void solve_group(spaqr_server* srv, const std::vector<Request*>& rs, std::vector
 
 // Groups of factored requests solved together: sizes sorted descending, a
 // group grows while the zero padding of its columns to the group's largest n
-// stays below half of the padded vectors.
+// stays below half of the padded vectors, its right-hand sides stay within
+// kGroupCols and its padded vectors within kGroupElems entries (the Krylov
+// bases of a group take about 2 (restart + 1) times that many doubles, and a
+// group runs until its slowest column converges).
+constexpr size_t kGroupCols = 64;
+constexpr double kGroupElems = double(1 << 23);
 std::vector<std::vector<Request*>> solve_groups(std::vector<Request*> rs) {
   std::sort(rs.begin(), rs.end(), [](const Request* a, const Request* b) { return a->A.n > b->A.n; });
   std::vector<std::vector<Request*>> g;
   double useful = 0, padded = 0;
+  size_t cols = 0;
   for (Request* r : rs) {
     const double u = (double)r->A.n * r->nrhs;
     if (!g.empty()) {
       const double p = (double)g.back().front()->A.n * r->nrhs;
-      if (2.0 * (useful + u) >= padded + p) {
+      if (2.0 * (useful + u) >= padded + p && cols + r->nrhs <= kGroupCols && padded + p <= kGroupElems) {
         g.back().push_back(r);
         useful += u;
         padded += p;
+        cols += r->nrhs;
         continue;
       }
     }
     g.push_back({r});
     useful = padded = u;
+    cols = r->nrhs;
   }
   return g;
 }

@@ -82,7 +82,8 @@ def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_sca
     Returns per-request dicts (latency_s = completion - arrival, iterations,
     relres) and a summary with throughput (unknowns x right-hand sides per
     second over the makespan) and p50/p99 latency.  log(str), if given, is
-    called as each request completes."""
+    called as each request completes and after any server step longer than
+    5 s."""
     import time
     srv = Server(mem_budget, stream)
     order = sorted(range(len(jobs)), key=lambda i: jobs[i]["arrival"])
@@ -100,7 +101,11 @@ def serve_trace(jobs, mem_budget, tol=1e-10, precision=32, stream=None, time_sca
         if not pending:
             time.sleep(max(0.0, jobs[order[nxt]]["arrival"] * time_scale - (time.perf_counter() - t0)))
             continue
+        ts = time.perf_counter()
         srv.step()
+        dt = time.perf_counter() - ts
+        if log and dt > 5.0:
+            log(f"server step took {dt:.1f} s with {len(pending)} requests in flight")
         for t in list(pending):
             out = srv.poll(t)
             if out is None:

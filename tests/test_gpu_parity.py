@@ -219,20 +219,22 @@ def test_kernel_profiler_counts_launches():
 # kernel the large workloads use: the LDS-panel QR (fronts over 256 rows), the
 # matrix-core trailing update (64-reflector blocks), the general scaling
 # kernels (blocks over 16), the cooperative CPQR for every interface, the
-# reflector apply of interfaces over 16 unknowns; the exact-norm register
-# CPQR for FP32 with the downdated-norm one off; and with the cooperative
+# reflector apply of interfaces over 16 unknowns; the FP32 single-workgroup
+# and team CPQRs with downdated norms by default, the exact-norm register and
+# cooperative ones with those off; and with the cooperative
 # CPQR and the matrix cores off, the single-workgroup LDS and generic CPQR
 # kernels and the vector-ALU trailing-update slices
 FORCED = [
     # (thresholds, kernels an FP64 factorization + apply must launch, the same for FP32)
     (dict(), ("k_qr_reg", "k_cpqr_coop", "k_scale_small", "k_ap_iface_dense", "k_wy_tblock", "k_trail_mfma"),
-     ("k_qr_reg", "k_cpqr_dd", "k_cpqr_coop", "k_wy_tblock", "k_trail_mfma")),
-    (dict(qr_reg_max_rows=256, split_rows=256, split_cols=256, cpqr_reg=0, scale_small=16, iface_dense=16),
+     ("k_qr_reg", "k_cpqr_dd", "k_cpqr_team", "k_wy_tblock", "k_trail_mfma")),
+    (dict(qr_reg_max_rows=256, split_rows=256, split_cols=256, cpqr_reg=0, scale_small=16, iface_dense=16,
+          cpqr_team=0),
      ("k_qr", "k_wy_tblock", "k_trail_mfma", "k_scale_right", "k_cpqr_coop", "k_ap_iface_fwd", "k_ap_iface_bwd",
       "k_ap_front_bwd_reg"),
      ("k_qr", "k_wy_tblock", "k_trail_mfma", "k_cpqr_dd", "k_cpqr_coop")),
-    (dict(cpqr_dd=0), ("k_qr_reg", "k_cpqr_coop"), ("k_qr_reg", "k_cpqr_reg", "k_cpqr_coop")),
-    (dict(cpqr_reg=0, cpqr_coop=0, scale_small=0, iface_dense=0, trail_mfma=0, cpqr_dd=0),
+    (dict(cpqr_dd=0, cpqr_team=0), ("k_qr_reg", "k_cpqr_coop"), ("k_qr_reg", "k_cpqr_reg", "k_cpqr_coop")),
+    (dict(cpqr_reg=0, cpqr_coop=0, scale_small=0, iface_dense=0, trail_mfma=0, cpqr_dd=0, cpqr_team=0),
      ("k_sparsify", "k_trail", "k_scale_right", "k_ap_iface_fwd", "k_ap_iface_bwd"),
      ("k_sparsify_small", "k_trail", "k_scale_right")),
 ]
@@ -257,7 +259,7 @@ def test_3d_every_kernel_path_against_oracle():
     yo = oracle_spaqr.apply(F, b)
     it_o, _ = _oracle_its(A, F, b[:, 0])
     families = ("k_qr_reg", "k_qr", "k_trail", "k_wy_tblock", "k_trail_mfma", "k_scale_small", "k_scale",
-                "k_scale_right", "k_cpqr_reg", "k_cpqr_dd",
+                "k_scale_right", "k_cpqr_reg", "k_cpqr_dd", "k_cpqr_team",
                 "k_cpqr_coop", "k_sparsify_small", "k_sparsify", "k_iface_form", "k_ap_front_fwd_reg",
                 "k_ap_front_fwd_wy", "k_ap_front_bwd_reg", "k_ap_iface_dense", "k_ap_iface_fwd", "k_ap_iface_bwd")
     try:
