@@ -215,7 +215,8 @@ GROUP_KERNELS = {
     "sparsify": ("k_cpqr_dd", "k_cpqr_team", "k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
     "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
-    "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),
+    "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_dense_lat<float", "k_ap_iface_fwd<float",
+                    "k_ap_iface_bwd<float"),
 }
 
 
