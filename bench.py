@@ -120,9 +120,16 @@ CAL_BYTES = 1 << 30
 
 
 def source_sha256():
+    """SHA-256 over the device kernel sources (every .hip file beside
+    KERNEL_SOURCE, names and contents, in name order)."""
+    import glob
     import hashlib
-    with open(os.path.join(ROOT, KERNEL_SOURCE), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, os.path.dirname(KERNEL_SOURCE), "*.hip"))):
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def copy_calibration(nbytes):
