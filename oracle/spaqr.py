@@ -52,6 +52,25 @@ notes of the repository):
      blocks with zeros elsewhere; the block pattern is symbolic (a block of
      size zero still exists).
 
+The variant without scaling (Section 2.5, scale=False) replaces R6 and R7:
+  R10 no interface is scaled; interfaces are sparsified in the order of R8 and
+     sigma = 1 / sigma_min(A_p) is taken from the current blocks when p is
+     reached (A_p = [A_pp; A_np], the row-neighbour blocks (i, p) stacked
+     under A_pp by ascending i), so it sees the neighbours of earlier colours
+     already sparsified.  sigma_min(A_p) = 0 leaves p alone.
+  R11 C = [A_np^T | sigma A_pp^T A_pn], columns ordered as in R7; the partial
+     CPQR with the ratio rule gives r and Q_pp.  The first r columns of Q_pp
+     are the coarse unknowns c, the other |p| - r the fine ones f.  A_ip :=
+     A_ip Q_pp restricted to c (W_cn^T; the f part is dropped).  Householder
+     QR of the f columns of A_pp Q_pp gives H and R_ff; H^T is applied to the
+     rows of p: its first |p| - r rows hold [R_fc R_ff R_fn] (R_fn dropped),
+     its last r rows the new A_cc and A_cj.  The right factor R_f^{-1} makes
+     the f rows [0 I] and leaves the c columns unchanged.  If r = |p| nothing
+     is dropped and nothing is stored.
+  R12 the rows of p after H^T are stored coarse first: the forward sweep
+     applies H^T to b_p and moves its last r entries to the front, so rows and
+     columns of the new cluster share its first r slots.
+
 Vectors live in a fixed slot space of length N (the permuted index).  Each
 cluster owns a list of slots; after sparsification its first r slots carry
 the coarse unknowns and the rest hold final values.  A merge concatenates
@@ -165,6 +184,52 @@ def _initial_blocks(Ahp, starts, ends):
     return bm
 
 
+def _sparsify_unscaled(bm, p, rowN, colN, eps):
+    """Sparsification of interface p without scaling (Section 2.5, Lemma 1),
+    in place on the block dictionary; readings R10-R12.
+
+    Returns None when sigma_min(A_p) = 0 (p is left alone), else
+    (r, op, info): op = (Vq, tq, r, VH, tH, R_ff, R_fc) for the apply and info
+    the record of sigma, R_ff, the dropped R_fn and the f rows of Q_pp^T C."""
+    App = bm.get(p, p)
+    sz = App.shape[0]
+    rows = [bm.get(i, p) for i in rowN]
+    Ap = np.vstack([App] + rows)
+    smin = float(np.linalg.svd(Ap, compute_uv=False)[-1])
+    if smin == 0.0:
+        return None
+    sigma = 1.0 / smin
+    parts = [B.T for B in rows] + [sigma * (App.T @ bm.get(p, j)) for j in colN]
+    widths = [x.shape[1] for x in parts]
+    C = np.hstack(parts) if parts else np.zeros((sz, 0))
+    mr = int(sum(B.shape[0] for B in rows))
+    r, Vq, tq, W, rdiag, piv = cpqr_ratio(C, eps)
+    QtC = apply_reflectors(Vq, tq, C, transpose=True)
+    info = {"sigma": sigma, "m": int(C.shape[1]), "W_f1": QtC[r:, :mr].copy(), "W_f2": QtC[r:, mr:].copy()}
+    if r == sz:
+        return r, None, info
+    f = sz - r
+    # A_pp Q_pp: Q_pp acts on the columns of p
+    AQ = apply_reflectors(Vq, tq, App.T, transpose=True).T
+    # Householder QR of the f columns (rows of p only: A_np Q_pf is dropped)
+    qrH, tauH = _geqrf(AQ[:, r:])
+    VH, tH = _reflectors(qrH, tauH)
+    Rff = np.triu(qrH[:f, :f])
+    Hc = _ormqr_lt(qrH, tauH, AQ[:, :r])  # [R_fc; A_cc]
+    off = np.concatenate([[0], np.cumsum(widths)]).astype(np.int64)
+    for a, i in enumerate(rowN):
+        bm.set(i, p, np.ascontiguousarray(W[:, off[a]:off[a + 1]].T))
+    rfn = []
+    for j in colN:
+        Hj = _ormqr_lt(qrH, tauH, bm.get(p, j))
+        rfn.append(Hj[:f])
+        bm.set(p, j, np.ascontiguousarray(Hj[f:]))
+    bm.set(p, p, np.ascontiguousarray(Hc[f:]))
+    info["R_ff"] = Rff
+    info["R_fn"] = np.hstack(rfn) if rfn else np.zeros((f, 0))
+    return r, (Vq, tq, r, VH, tH, Rff, np.ascontiguousarray(Hc[:f])), info
+
+
 def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_colour="ascending", trace=None):
     """Factorize A with spaQR (Algorithm 2).  A: scipy sparse, N x N.
 
@@ -176,12 +241,13 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_col
     the result must not depend on it.
     trace: optional callable trace(k, event, blocks) receiving a copy of the
     block dictionary {(i, j): array} at events "before_scaling" and
-    "after_scaling" of every sparsified stage (a record only)."""
+    "after_scaling" of every sparsified stage, or "before_sparsification"
+    without scaling (a record only).
+    scale: True for the scaled variant (Sections 2.6, 2.8), False for the
+    sparsification without scaling of Section 2.5 (readings R10-R12)."""
     if within_colour not in ("ascending", "descending"):
         raise ValueError("within_colour is 'ascending' or 'descending'")
     wsign = 1 if within_colour == "ascending" else -1
-    if not scale:
-        raise NotImplementedError("only the scaled variant (Section 2.6) is implemented")
     A = sp.csr_matrix(A, dtype=np.float64)
     N = A.shape[0]
     L = ordering.L
@@ -294,34 +360,37 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_col
         if k <= L - skip and k > 1 and remaining:
             rec["sparsified"] = True
             Uf = {}
-            for p in remaining:
-                sz = len(slots[p])
-                if sz == 0:
-                    continue
-                qrU, tauU = _geqrf(bm.get(p, p))
-                Rpp = np.triu(qrU[:sz, :sz])
-                if np.any(np.diag(Rpp) == 0.0):
-                    continue
-                Uf[p] = (qrU, tauU, Rpp)
-            if trace is not None:
-                trace(k, "before_scaling", {key: B.copy() for key, B in bm.blk.items()})
-            for (i, j), B in list(bm.blk.items()):
-                if i == j and i in Uf:
-                    bm.blk[(i, j)] = np.eye(B.shape[0])
-                    continue
-                if B.size == 0:
-                    continue
-                if i in Uf:
-                    B = _ormqr_lt(Uf[i][0], Uf[i][1], B)
-                if j in Uf:
-                    B = sla.solve_triangular(Uf[j][2], B.T, trans="T", lower=False).T
-                bm.blk[(i, j)] = np.ascontiguousarray(B)
-            if trace is not None:
-                trace(k, "after_scaling", {key: B.copy() for key, B in bm.blk.items()})
-            for p in remaining:
-                if p in Uf:
-                    V, tauv = _reflectors(Uf[p][0], Uf[p][1])
-                    F.ops.append(("scale", k, p, slots[p].copy(), V, tauv, Uf[p][2]))
+            if scale:
+                for p in remaining:
+                    sz = len(slots[p])
+                    if sz == 0:
+                        continue
+                    qrU, tauU = _geqrf(bm.get(p, p))
+                    Rpp = np.triu(qrU[:sz, :sz])
+                    if np.any(np.diag(Rpp) == 0.0):
+                        continue
+                    Uf[p] = (qrU, tauU, Rpp)
+                if trace is not None:
+                    trace(k, "before_scaling", {key: B.copy() for key, B in bm.blk.items()})
+                for (i, j), B in list(bm.blk.items()):
+                    if i == j and i in Uf:
+                        bm.blk[(i, j)] = np.eye(B.shape[0])
+                        continue
+                    if B.size == 0:
+                        continue
+                    if i in Uf:
+                        B = _ormqr_lt(Uf[i][0], Uf[i][1], B)
+                    if j in Uf:
+                        B = sla.solve_triangular(Uf[j][2], B.T, trans="T", lower=False).T
+                    bm.blk[(i, j)] = np.ascontiguousarray(B)
+                if trace is not None:
+                    trace(k, "after_scaling", {key: B.copy() for key, B in bm.blk.items()})
+                for p in remaining:
+                    if p in Uf:
+                        V, tauv = _reflectors(Uf[p][0], Uf[p][1])
+                        F.ops.append(("scale", k, p, slots[p].copy(), V, tauv, Uf[p][2]))
+            elif trace is not None:
+                trace(k, "before_sparsification", {key: B.copy() for key, B in bm.blk.items()})
             # colouring of the interface graph (R8)
             ridx = {p: t for t, p in enumerate(remaining)}
             nbr = [set() for _ in remaining]
@@ -333,13 +402,30 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_col
             rec["iface_colour"] = {p: int(icol[ridx[p]]) for p in remaining}
             ranks = {}
             shapes = {}
+            unscaled = {}
             for p in sorted(remaining, key=lambda p: (icol[ridx[p]], wsign * p)):
                 sz = len(slots[p])
-                if p not in Uf:
+                if scale and p not in Uf:
                     ranks[p] = sz
                     continue
                 rowN = sorted(i for i in bm.cols[p] if i != p)
                 colN = sorted(j for j in bm.rows[p] if j != p)
+                if not scale:
+                    if sz == 0:
+                        ranks[p] = 0
+                        continue
+                    got = _sparsify_unscaled(bm, p, rowN, colN, eps)
+                    if got is None:
+                        ranks[p] = sz
+                        continue
+                    r, op, info = got
+                    ranks[p] = r
+                    shapes[p] = (sz, info["m"], r)
+                    unscaled[p] = info
+                    if r < sz:
+                        F.ops.append(("sparsify_u", k, p, slots[p].copy()) + op)
+                        slots[p] = slots[p][:r]
+                    continue
                 parts = [bm.get(i, p).T for i in rowN] + [bm.get(p, j) for j in colN]
                 widths = [x.shape[1] for x in parts]
                 C = np.hstack(parts) if parts else np.zeros((sz, 0))
@@ -361,6 +447,10 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_col
             # (|p|, m, r) of every CPQR taken: the interface size, the columns
             # of C and the rank (a record only; no arithmetic depends on it)
             rec["cpqr_shapes"] = shapes
+            if not scale:
+                # sigma, R_ff, the dropped R_fn and W_fn blocks of every
+                # interface without scaling (a record only)
+                rec["unscaled"] = unscaled
         rec["sizes_post"] = np.array([len(s) for s in slots], dtype=np.int64)
         # ---------------- merge (Section 2.7) ----------------
         if k > 1:
@@ -396,6 +486,14 @@ def factor(A, ordering, eps, skip=2, scale=True, check_skipped=False, within_col
     return F
 
 
+def _forward_unscaled(op, yp):
+    """H^T on the rows of p, then the last r rows (coarse) moved to the front (R12)."""
+    _, k, p, sl, Vq, tq, r, VH, tH, Rff, Rfc = op
+    z = apply_reflectors(VH, tH, yp, transpose=True)
+    f = len(sl) - r
+    return np.vstack([z[f:], z[:f]])
+
+
 def apply(F, b):
     """x = M^{-1} b = D_c P^T W^{-1} Q^T P b (Section 2.8), b of shape (N,) or (N, nrhs)."""
     b = np.asarray(b, dtype=np.float64)
@@ -412,6 +510,8 @@ def apply(F, b):
         elif kind == "scale":
             _, k, p, sl, V, tau, Rpp = op
             y[sl] = apply_reflectors(V, tau, y[sl], transpose=True)
+        elif kind == "sparsify_u":
+            y[op[3]] = _forward_unscaled(op, y[op[3]])
         else:
             _, k, p, sl, V, tau, r = op
             y[sl] = apply_reflectors(V, tau, y[sl], transpose=True)
@@ -427,6 +527,12 @@ def apply(F, b):
         elif kind == "scale":
             _, k, p, sl, V, tau, Rpp = op
             y[sl] = sla.solve_triangular(Rpp, y[sl], lower=False)
+        elif kind == "sparsify_u":
+            # R_f^{-1} on [x_c; z_f], then Q_pp
+            _, k, p, sl, Vq, tq, r, VH, tH, Rff, Rfc = op
+            z = y[sl]
+            xf = sla.solve_triangular(Rff, z[r:] - Rfc @ z[:r], lower=False)
+            y[sl] = apply_reflectors(Vq, tq, np.vstack([z[:r], xf]), transpose=False)
         else:
             _, k, p, sl, V, tau, r = op
             y[sl] = apply_reflectors(V, tau, y[sl], transpose=False)
@@ -445,18 +551,24 @@ def factor_bytes(F, itemsize=8):
             tot += (V.size + tau.size + Rss.size + Rsj.size) * itemsize
         elif op[0] == "scale":
             tot += (op[4].size + op[5].size + op[6].size) * itemsize
+        elif op[0] == "sparsify_u":
+            tot += sum(op[t].size for t in (4, 5, 7, 8, 9, 10)) * itemsize
         else:
             tot += (op[4].size + op[5].size) * itemsize
     return tot
 
 
 def apply_qt(F, y):
-    """Forward sweep only: y <- Q^T y in the permuted slot space (y: N x nrhs)."""
+    """Forward sweep only: y <- Q^T y in the permuted slot space (y: N x nrhs);
+    an interface sparsified without scaling contributes its H^T and the
+    coarse-first row order."""
     y = np.array(y, dtype=np.float64, copy=True).reshape(F.N, -1)
     for op in F.ops:
         if op[0] == "front":
             if op[4]:
                 y[op[3]] = apply_reflectors(op[5], op[6], y[op[3]], transpose=True)
+        elif op[0] == "sparsify_u":
+            y[op[3]] = _forward_unscaled(op, y[op[3]])
         else:
             y[op[3]] = apply_reflectors(op[4], op[5], y[op[3]], transpose=True)
     return y

@@ -350,3 +350,103 @@ def test_symbolic_pattern_invariants():
             for other in byc.get(c, []):
                 assert not (touched & other)
             byc.setdefault(c, []).append(touched)
+
+
+# ----------------------------------------------------------------------------
+# sparsification without scaling (Section 2.5, Lemma 1)
+def _unscaled_case(eps=1e-4, dims=(24, 24), L=5):
+    A = convdiff(dims, (25.0, 12.0))
+    o = order_grid(dims, L)
+    return A, o, spaqr.factor(A, o, eps, scale=False)
+
+
+def test_unscaled_sigma_is_the_inverse_smallest_singular_value():
+    """sigma = 1/sigma_min(A_p) (Lemma 1), checked against A_p assembled
+    densely: at the first sparsified stage the p columns of A_p are the p
+    columns of Q^T A_hat (the front reflectors applied to the dense permuted,
+    pre-scaled matrix) over the rows not yet eliminated.  Interfaces of the
+    first colour see no earlier sparsification."""
+    A, o, F = _unscaled_case()
+    k0 = max(k for k, rec in F.stages.items() if rec["sparsified"])
+    rec = F.stages[k0]
+    Ah = _ahat(A, F)
+    fronts = [op for op in F.ops if op[0] == "front" and op[1] >= k0]
+    Y = Ah.copy()
+    for op in fronts:
+        if op[4]:
+            Y[op[3]] = apply_reflectors(op[5], op[6], Y[op[3]], transpose=True)
+    elim = np.zeros(F.N, dtype=bool)
+    for op in fronts:
+        elim[op[3][:op[4]]] = True
+    st, en, _, _ = rec["clusters"]
+    checked = 0
+    for p, info in rec["unscaled"].items():
+        if rec["iface_colour"][p] != 0:
+            continue
+        cols = np.arange(st[p], en[p])  # stage-k0 clusters still own their initial slots here
+        cols = cols[~elim[cols]]
+        Ap = Y[np.ix_(~elim, cols)]
+        smin = np.linalg.svd(Ap, compute_uv=False)[-1]
+        assert abs(info["sigma"] * smin - 1.0) <= 1e-10
+        checked += 1
+    assert checked >= 2
+
+
+def test_unscaled_lemma1_identity_and_bound():
+    """Proof of Lemma 1: sigma R_ff^T R_fn = W_fn^(2) exactly (A_pp Q_pf = H_ff
+    R_ff), and ||R_fn|| <= ||W_fn^(2)|| / (1 - sigma ||W_fn^(1)||) because
+    sigma_min(R_ff) >= sigma_min(A_p) - ||A_np Q_pf||."""
+    n = 0
+    for eps in (1e-2, 1e-4):
+        A, o, F = _unscaled_case(eps)
+        for k, rec in F.stages.items():
+            for p, info in rec.get("unscaled", {}).items():
+                if "R_ff" not in info:
+                    continue
+                sig, Rff, Rfn, W1, W2 = info["sigma"], info["R_ff"], info["R_fn"], info["W_f1"], info["W_f2"]
+                if Rfn.size == 0:
+                    continue
+                lhs = sig * Rff.T @ Rfn
+                scale = sig * np.linalg.norm(Rff, 2) * np.linalg.norm(Rfn, 2) + np.linalg.norm(W2, 2) + 1e-300
+                assert np.abs(lhs - W2).max() <= 1e-12 * scale
+                w1 = sig * np.linalg.norm(W1, 2) if W1.size else 0.0
+                if w1 < 0.5:
+                    assert np.linalg.norm(Rfn, 2) <= np.linalg.norm(W2, 2) / (1.0 - w1) * (1 + 1e-10) + 1e-15
+                n += 1
+    assert n >= 6
+
+
+def test_unscaled_preconditioner_error_shrinks_with_eps():
+    """||I - M^{-1} A|| = O(eps) without scaling too; at eps = 0 M^{-1} = A^{-1}."""
+    dims = (20, 20)
+    A = convdiff(dims, (25.0, 12.0))
+    o = order_grid(dims, 5)
+    Ad = A.toarray()
+    errs = []
+    for eps in (1e-2, 1e-4, 1e-6, 1e-8):
+        F = spaqr.factor(A, o, eps, scale=False)
+        assert any(op[0] == "sparsify_u" for op in F.ops)
+        errs.append(np.linalg.norm(np.eye(A.shape[0]) - spaqr.apply(F, Ad), 2))
+    assert all(errs[t + 1] < 0.1 * errs[t] for t in range(3))
+    assert errs[3] <= 1e-4
+    F = spaqr.factor(A, o, 0.0, scale=False)
+    b = make_rhs(A.shape[0], 2, seed=5)
+    x = spaqr.apply(F, b)
+    assert (np.linalg.norm(A @ x - b, axis=0) / np.linalg.norm(b, axis=0)).max() <= 1e-13
+
+
+def test_unscaled_gmres_converges_and_scaling_helps():
+    """Both variants precondition FGMRES to 1e-10 (Section 4 setup); on this
+    advection-dominated case the scaled variant needs no more iterations
+    (the comparison of Section 4.1)."""
+    dims = (32, 32)
+    A = convdiff(dims, (40.0, -25.0))
+    o = order_grid(dims, 5)
+    b = make_rhs(A.shape[0], 1, seed=2)[:, 0]
+    its = {}
+    for sc in (True, False):
+        F = spaqr.factor(A, o, 1e-2, scale=sc)
+        x, it, rel = gmres.fgmres(lambda v: A @ v, lambda v: spaqr.apply(F, v), b, 1e-10)
+        assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
+        its[sc] = it
+    assert its[True] <= its[False]
