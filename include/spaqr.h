@@ -94,7 +94,12 @@ spaqr_status spaqr_ordering_merge_parents(const spaqr_ordering* ord, int stage,
 typedef struct {
   double eps;      /* sparsification tolerance (ratio rule |R_ii|/|R_11|), >= 0 */
   int skip;        /* levels above the leaves without sparsification (default 2) */
-  int scale;       /* block-diagonal scaling, Section 2.6 (must be 1) */
+  int scale;       /* 1: block-diagonal scaling of the interfaces before their
+                      sparsification (Section 2.6, the default); 0: the
+                      sparsification without scaling of Section 2.5, with
+                      sigma = 1/sigma_min(A_p) of Lemma 1 and a Householder QR
+                      of the fine unknowns (interfaces of at most 1024
+                      unknowns and 512 neighbour blocks, else SPAQR_EINVAL) */
   int precision;   /* 32: FP32 blocks and factors, 64: FP64 (default 32) */
   int restart;     /* GMRES restart length (default 100) */
   int maxit;       /* GMRES maximum Arnoldi steps (default 1000) */

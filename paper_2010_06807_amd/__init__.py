@@ -36,11 +36,13 @@ def _csr_struct(A):
     return s, (indptr, indices, data)
 
 
-def make_opts(eps=1e-2, skip=2, precision=32, restart=100, maxit=1000):
+def make_opts(eps=1e-2, skip=2, precision=32, restart=100, maxit=1000, scale=True):
+    """spaqr_opts; scale=False selects the sparsification without scaling of
+    Section 2.5 (sigma = 1/sigma_min(A_p), Householder on the fine unknowns)."""
     lib = _abi.load()
     o = lib.spaqr_opts_default()
-    o.eps, o.skip, o.scale, o.precision, o.restart, o.maxit = float(eps), int(skip), 1, int(precision), \
-        int(restart), int(maxit)
+    o.eps, o.skip, o.scale, o.precision, o.restart, o.maxit = float(eps), int(skip), 1 if scale else 0, \
+        int(precision), int(restart), int(maxit)
     return o
 
 
@@ -190,7 +192,7 @@ class Factorization:
     """A spaQR factorization resident on the GPU (spaqr_factor)."""
 
     def __init__(self, A, ordering=None, symbolic=None, eps=1e-2, skip=2, precision=32, restart=100,
-                 maxit=1000, stream=None, device_csr=None, _handle=None):
+                 maxit=1000, stream=None, device_csr=None, scale=True, _handle=None):
         if _handle is not None:          # made by factor_batch
             self._h = _handle
             self._sym = symbolic
@@ -199,7 +201,7 @@ class Factorization:
             return
         lib = _abi.load()
         csr, keep = _csr_struct(A)
-        o = make_opts(eps, skip, precision, restart, maxit)
+        o = make_opts(eps, skip, precision, restart, maxit, scale)
         h = C.c_void_p()
         sp = _stream_ptr(stream)
         if device_csr is not None:
@@ -356,7 +358,7 @@ def factor_device(A, symbolic, dcsr, eps=1e-2, **kw):
 
 
 def factor_batch(As, symbolics, dcsrs=None, eps=1e-2, skip=2, precision=32, restart=100, maxit=1000,
-                 stream=None):
+                 stream=None, scale=True):
     """Factorize several problems together (spaqr_factor_batch): stage by
     stage, all their fronts, scalings and sparsifications share one launch per
     phase.  As: scipy CSR matrices (the pattern; also the values when dcsrs is
@@ -378,7 +380,7 @@ def factor_batch(As, symbolics, dcsrs=None, eps=1e-2, skip=2, precision=32, rest
     dev_p = (C.POINTER(_abi.CSRDev) * n)(*[C.pointer(d) for d in devs]) if dcsrs is not None else None
     sym_p = (C.c_void_p * n)(*[s.handle.value if hasattr(s.handle, "value") else s.handle for s in symbolics])
     out = (C.c_void_p * n)()
-    o = make_opts(eps, skip, precision, restart, maxit)
+    o = make_opts(eps, skip, precision, restart, maxit, scale)
     st = lib.spaqr_factor_batch(n, csr_p, dev_p, sym_p, C.byref(o), _stream_ptr(stream), out)
     facs = [Factorization(As[i], symbolic=symbolics[i], _handle=C.c_void_p(out[i])) if out[i] else None
             for i in range(n)]

@@ -21,7 +21,8 @@ OUT = os.path.join(HERE, "libspaqr.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["ordering.cpp", "symbolic.cpp", "factor.cpp", "abi.cpp", "server.cpp", "profile.cpp", "mem.cpp", "tuning.cpp",
-           "kernels.hip", "cpqr_dd.hip", "cpqr_team.hip", "gmres.hip", "noalloc.hip"]
+           "kernels.hip", "cpqr_dd.hip", "cpqr_team.hip", "sparsify_unscaled.hip", "gmres.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPAQR_ARCH", "gfx950")

@@ -94,6 +94,7 @@ struct StageApply {
   int jb = 1;                            // QR panel width of the stage's fronts
   int64_t nifaces_small = 0;             // interfaces with dense operators come first
   int dense_max = 64;                    // largest interface given dense operators
+  int dense_max_p = 0;                   // largest interface that has them
   int64_t nfronts = 0;
   ApIface<T>* ifaces = nullptr;
   int64_t nifaces = 0;

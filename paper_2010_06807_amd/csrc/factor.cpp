@@ -194,6 +194,12 @@ struct StagePlan {
     std::vector<SpNbr> nb;
   };
   std::vector<SpColour> sp;
+  // sparsification without scaling, colour by colour; SpuDesc::nb indexes nb
+  struct SpuColour {
+    std::vector<SpuDesc<T>> sd;
+    std::vector<SpNbr> nb;
+  };
+  std::vector<SpuColour> spu;
   // interfaces whose dense apply operators are formed after the stage
   std::vector<ApIface<T>> form;
 };
@@ -297,6 +303,7 @@ class Engine final : public EngineBase {
   void plan_fronts(StagePlan<T>& p);
   void plan_scale(StagePlan<T>& p);
   void plan_sparsify(StagePlan<T>& p);
+  void plan_sparsify_unscaled(StagePlan<T>& p);
   // after the launches: the ranks and error flags of the stage, as copies
   // into a batch-wide buffer from offset base (readback_ints() of them);
   // finish() reads them at `host` once the stream has passed the copy
@@ -689,7 +696,7 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
   const int k = k_;
   const StageSym& ss = S_.st[k];
   const int64_t nclu = ss.nclu;
-  if (!ss.sparsify) return;
+  if (!ss.sparsify || !o_.scale) return;
   auto blk = [&](int32_t i, int32_t j) -> T* {
     const int64_t b = ss.all.find(i, j);
     return b < 0 ? nullptr : pool_ + boff_[b];
@@ -767,6 +774,10 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
   const int k = k_;
   const StageSym& ss = S_.st[k];
   if (!ss.sparsify) return;
+  if (!o_.scale) {
+    plan_sparsify_unscaled(P);
+    return;
+  }
   Stager& up = stager_[stager_cur_];
   StageApply<T>& ap = ap_[k];
   auto slot_list = [&](const std::vector<int32_t>& cl, std::vector<int32_t>& out) {
@@ -860,11 +871,117 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
   for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
   // interfaces with dense operators first (dense-operator apply)
   std::stable_partition(ai.begin(), ai.end(), [dmax](const ApIface<T>& q) { return q.P <= dmax; });
-  for (const ApIface<T>& q : ai) ap.nifaces_small += q.P <= dmax ? 1 : 0;
+  for (const ApIface<T>& q : ai)
+    if (q.P <= dmax) {
+      ap.nifaces_small++;
+      ap.dense_max_p = std::max(ap.dense_max_p, (int)q.P);
+    }
   ap.ifaces = up.upload_held(persist_, ai, s_);
   up.flush(s_);
   ap.nifaces = (int64_t)ai.size();
   P.form.assign(ai.begin(), ai.begin() + ap.nifaces_small);
+  st_.s.interfaces_sparsified += (int64_t)ai.size();
+  ap.h_ifaces = std::move(ai);
+}
+
+// Sparsification without scaling (Section 2.5): per colour, one workgroup per
+// interface (k_sparsify_unscaled), which also writes the interface's dense
+// forward and backward apply operators.  The FP64 workspaces of one colour
+// are reused by the next (colours run in stream order).
+template <typename T>
+void Engine<T>::plan_sparsify_unscaled(StagePlan<T>& P) {
+  const int k = k_;
+  const StageSym& ss = S_.st[k];
+  Stager& up = stager_[stager_cur_];
+  StageApply<T>& ap = ap_[k];
+  auto slot_list = [&](const std::vector<int32_t>& cl, std::vector<int32_t>& out) {
+    for (int32_t c : cl) out.insert(out.end(), slots_.begin() + slot_ptr_[c], slots_.begin() + slot_ptr_[c + 1]);
+  };
+  const std::vector<int32_t>& rem = ss.remaining;
+  const int64_t ni = (int64_t)rem.size();
+  st_.stage[k].sparsified = 1;
+  std::vector<int32_t> fidx(ss.nclu, -1);
+  std::vector<int64_t> op_off(ni + 1, 0);
+  for (int64_t t = 0; t < ni; ++t) {
+    fidx[rem[t]] = (int32_t)t;
+    op_off[t + 1] = op_off[t] + (int64_t)size_[rem[t]] * size_[rem[t]];
+  }
+  int* FLAGS = persist_.alloc_n<int>(std::max<int64_t>(1, ni), s_);
+  P.zero.push_back({FLAGS, (int64_t)std::max<int64_t>(1, ni) * (int64_t)sizeof(int)});
+  T* MF = persist_.alloc_n<T>(std::max<int64_t>(1, op_off[ni]), s_);
+  T* MB = persist_.alloc_n<T>(std::max<int64_t>(1, op_off[ni]), s_);
+  // descriptors colour by colour; workspace offsets restart with each colour
+  int64_t ws_max = 1;
+  std::vector<std::vector<int64_t>> ws_at(ss.iface_colour_ptr.size());
+  for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
+    typename StagePlan<T>::SpuColour col;
+    int64_t wo = 0;
+    for (int32_t oi = ss.iface_colour_ptr[c]; oi < ss.iface_colour_ptr[c + 1]; ++oi) {
+      const IfaceSym& I = ss.ifaces[ss.iface_order[oi]];
+      const int32_t p = I.cluster, Pn = size_[p];
+      if (Pn == 0) continue;
+      SPAQR_REQUIRE(Pn <= kSpuMaxP, SPAQR_EINVAL, "interface too large for the sparsification without scaling");
+      SPAQR_REQUIRE((int64_t)(I.rowN.size() + I.colN.size()) <= kSpuMaxNbr, SPAQR_EINVAL,
+                    "interface with too many neighbour blocks for the sparsification without scaling");
+      SpuDesc<T> d{};
+      d.nb = (int64_t)col.nb.size();
+      int64_t mr = 0, mc = 0;
+      for (int32_t i : I.rowN) {
+        col.nb.push_back({boff_[ss.all.find(i, p)], i, Pn});
+        mr += size_[i];
+      }
+      for (int32_t j : I.colN) {
+        col.nb.push_back({boff_[ss.all.find(p, j)], j, size_[j]});
+        mc += size_[j];
+      }
+      const int64_t t = fidx[p];
+      d.pool = pool_;
+      d.rank = d_rank_;
+      d.flag = FLAGS + t;
+      d.mf = MF + op_off[t];
+      d.mb = MB + op_off[t];
+      d.ws = nullptr;
+      d.eps = o_.eps;
+      const int64_t bpp = ss.all.find(p, p);
+      SPAQR_REQUIRE(bpp >= 0, SPAQR_EINVAL, "interface without a diagonal block");
+      d.app = boff_[bpp];
+      d.nrow = (int32_t)I.rowN.size();
+      d.ncol = (int32_t)I.colN.size();
+      d.cluster = p;
+      d.P = Pn;
+      d.mr_max = (int32_t)mr;
+      d.mc_max = (int32_t)mc;
+      ws_at[c].push_back(wo);
+      wo += (sparsify_unscaled_ws(Pn, (int)mr, (int)mc) + 31) / 32 * 32;
+      col.sd.push_back(d);
+    }
+    ws_max = std::max(ws_max, wo);
+    P.spu.push_back(std::move(col));
+  }
+  double* WS = work_.alloc_n<double>((size_t)ws_max, s_);
+  for (size_t c = 0; c < P.spu.size(); ++c)
+    for (size_t q = 0; q < P.spu[c].sd.size(); ++q) P.spu[c].sd[q].ws = WS + ws_at[c][q];
+  // every interface applies through its dense operators
+  std::vector<ApIface<T>> ai;
+  std::vector<int32_t> sl;
+  std::vector<int64_t> sl_off;
+  ap.dense_max = INT32_MAX;
+  for (int64_t t = 0; t < ni; ++t) {
+    const int32_t p = rem[t], Pn = size_[p];
+    if (Pn == 0) continue;
+    sl_off.push_back((int64_t)sl.size());
+    slot_list(std::vector<int32_t>{p}, sl);
+    ai.push_back({nullptr, nullptr, nullptr, nullptr, nullptr, d_rank_ + p, FLAGS + t, MF + op_off[t], MB + op_off[t],
+                  Pn, 0});
+    ap.max_p = std::max(ap.max_p, (int)Pn);
+    ap.dense_max_p = std::max(ap.dense_max_p, (int)Pn);
+  }
+  int32_t* dsl = up.upload_held(persist_, sl, s_);
+  for (size_t t = 0; t < ai.size(); ++t) ai[t].slots = dsl + sl_off[t];
+  ap.nifaces_small = (int64_t)ai.size();
+  ap.ifaces = up.upload_held(persist_, ai, s_);
+  up.flush(s_);
+  ap.nifaces = (int64_t)ai.size();
   st_.s.interfaces_sparsified += (int64_t)ai.size();
   ap.h_ifaces = std::move(ai);
 }
@@ -1657,6 +1774,26 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
     }
     sparsify_batch<T>(sd, nb, up, wk, s, team_err);
   }
+  size_t nsu = 0;
+  for (auto& p : pl) nsu = std::max(nsu, p.spu.size());
+  for (size_t c = 0; c < nsu; ++c) {
+    std::vector<SpuDesc<T>> sd;
+    std::vector<SpNbr> nb;
+    for (auto& p : pl) {
+      if (c >= p.spu.size()) continue;
+      const int64_t base = (int64_t)nb.size();
+      append(nb, p.spu[c].nb);
+      for (SpuDesc<T> d : p.spu[c].sd) {
+        d.nb += base;
+        sd.push_back(d);
+      }
+    }
+    if (sd.empty()) continue;
+    SpuDesc<T>* dsd = up.upload(wk, sd, s);
+    SpNbr* dnb = up.upload(wk, nb, s);
+    ProfScope ps("sparsify", s, 0.0, 0.0);
+    launch_sparsify_unscaled<T>(dsd, dnb, (int64_t)sd.size(), s);
+  }
   {
     // dense interface operators, one launch per size class (16, 32, 64)
     std::vector<ApIface<T>> form[3];
@@ -1801,7 +1938,7 @@ void Engine<T>::sweeps(double* xh, int nrhs, hipStream_t s) {
     }
     if (a.nifaces) {
       ProfScope ps("apply_iface_fwd", s, a.if_fwd_flops * nrhs, a.if_fwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_dense<T>(a.ifaces, a.nifaces_small, false, xh, N, nrhs, s);
+      launch_iface_dense<T>(a.ifaces, a.nifaces_small, false, xh, N, nrhs, s, a.dense_max_p);
       launch_iface_fwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s);
     }
   }
@@ -1809,7 +1946,7 @@ void Engine<T>::sweeps(double* xh, int nrhs, hipStream_t s) {
     const StageApply<T>& a = ap_[k];
     if (a.nifaces) {
       ProfScope ps("apply_iface_bwd", s, a.if_bwd_flops * nrhs, a.if_bwd_fac_bytes + a.if_vec_bytes * nrhs);
-      launch_iface_dense<T>(a.ifaces, a.nifaces_small, true, xh, N, nrhs, s);
+      launch_iface_dense<T>(a.ifaces, a.nifaces_small, true, xh, N, nrhs, s, a.dense_max_p);
       launch_iface_bwd<T>(a.ifaces + a.nifaces_small, a.nifaces - a.nifaces_small, a.max_p, xh, N, nrhs, s);
     }
     if (a.nfronts) {
@@ -1887,6 +2024,7 @@ class BatchApply {
           ApIface<T> d = a.h_ifaces[t];
           d.xoff = (int32_t)off[i];
           (t < a.nifaces_small ? dense : other).push_back(d);
+          if (t < a.nifaces_small) v.dense_max_p = std::max(v.dense_max_p, (int)d.P);
         }
         v.max_p = std::max(v.max_p, a.max_p);
         for (size_t c = 0; c < a.fwd_flops.size(); ++c) {
@@ -1969,7 +2107,7 @@ class BatchApply {
       }
       if (v.nif) {
         ProfScope ps("apply_iface_fwd", s, v.if_fwd_flops * nr, v.if_fwd_fac_bytes + v.if_vec_bytes * nr);
-        launch_iface_dense<T>(v.ifs, v.nif_dense, false, X_, Ntot_, nr, s);
+        launch_iface_dense<T>(v.ifs, v.nif_dense, false, X_, Ntot_, nr, s, v.dense_max_p);
         launch_iface_fwd<T>(v.ifs + v.nif_dense, v.nif - v.nif_dense, v.max_p, X_, Ntot_, nr, s);
       }
     }
@@ -1977,7 +2115,7 @@ class BatchApply {
       const Level& v = lv_[k];
       if (v.nif) {
         ProfScope ps("apply_iface_bwd", s, v.if_bwd_flops * nr, v.if_bwd_fac_bytes + v.if_vec_bytes * nr);
-        launch_iface_dense<T>(v.ifs, v.nif_dense, true, X_, Ntot_, nr, s);
+        launch_iface_dense<T>(v.ifs, v.nif_dense, true, X_, Ntot_, nr, s, v.dense_max_p);
         launch_iface_bwd<T>(v.ifs + v.nif_dense, v.nif - v.nif_dense, v.max_p, X_, Ntot_, nr, s);
       }
       if (v.nbwd) {
@@ -1999,7 +2137,7 @@ class BatchApply {
     int max_n = 0, max_k = 0;
     const ApIface<T>* ifs = nullptr;  // dense-operator interfaces first
     int64_t nif = 0, nif_dense = 0;
-    int max_p = 0;
+    int max_p = 0, dense_max_p = 0;
     double fwd_flops = 0, fwd_fac_bytes = 0, fwd_vec_bytes = 0, bwd_flops = 0, bwd_fac_bytes = 0, bwd_vec_bytes = 0;
     double if_fwd_flops = 0, if_bwd_flops = 0, if_fwd_fac_bytes = 0, if_bwd_fac_bytes = 0, if_vec_bytes = 0;
   };
@@ -2097,7 +2235,7 @@ static void factor_all(Engine<T>* e) {
 std::unique_ptr<EngineBase> make_engine_deferred(const spaqr_csr* A, const spaqr_csr_dev* Ad, const Symbolic& S,
                                                  const spaqr_opts& o, hipStream_t stream) {
   SPAQR_REQUIRE(o.eps >= 0.0 && std::isfinite(o.eps), SPAQR_EINVAL, "eps must be finite and >= 0");
-  SPAQR_REQUIRE(o.scale == 1, SPAQR_EINVAL, "only the scaled variant is implemented");
+  SPAQR_REQUIRE(o.scale == 0 || o.scale == 1, SPAQR_EINVAL, "scale is 0 or 1");
   SPAQR_REQUIRE(o.precision == 32 || o.precision == 64, SPAQR_EINVAL, "precision must be 32 or 64");
   if (o.precision == 32) return std::unique_ptr<EngineBase>(new Engine<float>(A, Ad, S, o, stream));
   return std::unique_ptr<EngineBase>(new Engine<double>(A, Ad, S, o, stream));

@@ -3362,8 +3362,12 @@ void launch_iface_form(const ApIface<T>* d, int64_t n, int max_p, hipStream_t s)
 
 template <typename T>
 void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
-                        hipStream_t s) {
+                        hipStream_t s, int max_p) {
   if (n <= 0 || nrhs <= 0) return;
+  if (max_p > 64) {
+    launch_iface_dense_big<T>(d, n, backward, x, ldx, nrhs, s);
+    return;
+  }
   // up to 2048 interfaces the LDS-broadcast kernel is faster (measured: 9 us
   // against 20 us for one to a few hundred interfaces of 64 unknowns); beyond,
   // the readlane kernel keeps more loads in flight
@@ -3461,7 +3465,7 @@ void launch_scatter_perm(double* x, int64_t ldx, const double* xhat, const int64
   template int sparsify_coop_capacity<T>(int, int, int);                                               \
   template bool launch_sparsify_coop<T>(const SpDesc<T>*, const CoopItem*, int, int, int, const SpNbr*, int, int, \
                                         double*, int*, T*, int*, int, hipStream_t);                    \
-  template void launch_iface_dense<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t);
+  template void launch_iface_dense<T>(const ApIface<T>*, int64_t, bool, double*, int64_t, int, hipStream_t, int);
 SPAQR_INST(float)
 SPAQR_INST(double)
 #undef SPAQR_INST

@@ -133,6 +133,28 @@ struct SpDesc {
   int32_t cluster, P, mmax, pad;
 };
 
+// Sparsification without scaling (Section 2.5): one interface per workgroup.
+constexpr int kSpuMaxP = 1024;   // largest interface
+constexpr int kSpuMaxNbr = 512;  // most neighbour blocks of one interface
+template <typename T>
+struct SpuDesc {
+  T* pool;        // block pool of the interface's factorization
+  int* rank;      // current cluster sizes (rank[cluster] gets r)
+  int* flag;      // set to 1 when p is left alone (sigma_min(A_p) = 0 or r = P)
+  T* mf;          // P x P column-major forward operator Pi H^T
+  T* mb;          // P x P column-major backward operator Q T
+  double* ws;     // sparsify_unscaled_ws(P, mr_max, mc_max) doubles
+  double eps;     // truncation tolerance
+  int64_t app;    // element offset of the block (p, p) in the pool
+  int64_t nb;     // first neighbour in the SpNbr array: nrow blocks (i, p), then ncol blocks (p, j)
+  int32_t nrow, ncol;
+  int32_t cluster, P;
+  int32_t mr_max, mc_max;  // sums of the row / column neighbours' sizes at the start of the stage
+};
+int64_t sparsify_unscaled_ws(int P, int mr_max, int mc_max);
+template <typename T>
+void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, hipStream_t s);
+
 // Apply descriptors (vectors are FP64, slots index the permuted vector).
 template <typename T>
 struct ApFront {
@@ -288,7 +310,11 @@ template <typename T>
 void launch_iface_form(const ApIface<T>* d, int64_t n, int max_p, hipStream_t s);  // max_p <= 64
 template <typename T>
 void launch_iface_dense(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
-                        hipStream_t s);
+                        hipStream_t s, int max_p);
+// the same for interfaces of any size up to kSpuMaxP, one workgroup each
+template <typename T>
+void launch_iface_dense_big(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
+                            hipStream_t s);
 template <typename T>
 void launch_iface_small(const ApIface<T>* d, int64_t n, bool backward, double* x, int64_t ldx, int nrhs,
                         hipStream_t s);

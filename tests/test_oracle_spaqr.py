@@ -450,3 +450,22 @@ def test_unscaled_gmres_converges_and_scaling_helps():
         assert np.linalg.norm(A @ x - b) <= 1e-9 * np.linalg.norm(b)
         its[sc] = it
     assert its[True] <= its[False]
+
+
+def test_unscaled_ranks_move_under_roundoff_level_perturbation():
+    """Without scaling, at eps = 1e-6 the ranks of later sparsified stages
+    change when A's entries are perturbed by 1e-13 relative, while the scaled
+    variant's do not (the robustness Section 2.6's scaling buys).  This sets
+    the GPU parity bar for the unscaled FP64 path at small eps to +-1."""
+    dims, L, eps = (96, 96), 7, 1e-6
+    A = sp.csr_matrix(convdiff(dims, (25.0, 12.0)))
+    A1 = A.copy()
+    A1.data = A1.data * (1 + 1e-13 * np.random.default_rng(0).standard_normal(A1.data.size))
+    o = order_grid(dims, L)
+    moved = {}
+    for sc in (True, False):
+        F0, F1 = spaqr.factor(A, o, eps, scale=sc), spaqr.factor(A1, o, eps, scale=sc)
+        moved[sc] = [abs(F1.stages[k]["ranks"][p] - r) for k, rec in F0.stages.items() if rec["sparsified"]
+                     for p, r in rec["ranks"].items()]
+    assert max(moved[True]) == 0
+    assert 0 < max(moved[False]) <= 1
