@@ -56,7 +56,7 @@ PEAK = {
 # CPQR's work is counted from the ranks read back after each stage)
 KERNEL_BOUND = {
     "front_qr": "alu", "front_trail": "mfma", "front_wy_blocks": "mfma", "scale_qr": "alu", "scale_blocks": "alu",
-    "sparsify": "alu",
+    "sparsify": "alu", "sparsify_unscaled": "alu64",
     "apply_front_fwd": "hbm", "apply_front_bwd": "hbm", "apply_iface_fwd": "hbm", "apply_iface_bwd": "hbm",
 }
 
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-2)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 path (0: skip)")
+    ap.add_argument("--unscaled-steps", type=int, default=2,
+                    help="steps of the sparsification without scaling, Section 2.5 (0: skip)")
     ap.add_argument("--batch-workload", default="c2",
                     help="workload of the cross-request batched figure ('' to skip)")
     ap.add_argument("--batch", type=int, default=16, help="requests per step of the batched figure")
@@ -220,10 +222,11 @@ GROUP_KERNELS = {
     "interface operators (forming)": ("k_iface_form<float",),
     "scale_blocks": ("k_scale<float", "k_scale_small<float", "k_scale_right<float"),
     "sparsify": ("k_cpqr_dd", "k_cpqr_team", "k_cpqr_reg<float", "k_cpqr_coop<float", "k_sparsify_small<float", "k_sparsify<float"),
+    "sparsify_unscaled": ("k_sparsify_unscaled<float",),
     "apply_front_fwd": ("k_ap_front_fwd_reg<float", "k_ap_front_fwd_wy<float"),
     "apply_front_bwd": ("k_ap_front_bwd_reg<float",),
-    "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_dense_lat<float", "k_ap_iface_fwd<float",
-                    "k_ap_iface_bwd<float"),
+    "apply_iface": ("k_ap_iface_dense<float", "k_ap_iface_dense_lat<float", "k_ap_iface_dense_big<float",
+                    "k_ap_iface_fwd<float", "k_ap_iface_bwd<float"),
 }
 
 
@@ -477,8 +480,47 @@ def main():
         if bound == "hbm":
             peak, unit = PEAK["hbm"]
             return (q["bytes"] / (q["total_ms"] * 1e-3) / 1e9 if q["total_ms"] > 0 else 0.0), peak, unit
-        peak, unit = PEAK["mfma32" if bound == "mfma" else "alu32"]
+        peak, unit = PEAK[{"mfma": "mfma32", "alu64": "alu64"}.get(bound, "alu32")]
         return (q["flops"] / (q["total_ms"] * 1e-3) / 1e12 if q["total_ms"] > 0 else 0.0), peak, unit
+
+    unscaled = None
+    if args.unscaled_steps > 0:
+        # the same workload with the sparsification without scaling
+        def ustep(i):
+            t0 = time.perf_counter()
+            fac = P.factor_device(probs[i % S]["A"], sym, dAs[i % S], eps=args.eps, precision=32, scale=False)
+            t1 = time.perf_counter()
+            x, info = fac.solve(bs[i % S], tol=args.tol)
+            torch.cuda.synchronize()
+            return info[0], t1 - t0, time.perf_counter() - t1
+
+        ustep(0)
+        torch.cuda.synchronize()
+        log("FP32 factors without scaling")
+        P.profile_enable(True, only="sparsify_unscaled")
+        uf, us, uit, ures = [], [], [], []
+        t0 = time.perf_counter()
+        for i in range(args.unscaled_steps):
+            info, tf, ts = ustep(i)
+            uf.append(tf)
+            us.append(ts)
+            uit.append(info["iterations"])
+            ures.append(info["relres"])
+        dtu = time.perf_counter() - t0
+        qu = P.profile_query("sparsify_unscaled")
+        P.profile_enable(False)
+        ach, pk, un = rate("alu64", qu)
+        log(f"without scaling: {1e3 * dtu / args.unscaled_steps:.2f} ms/step")
+        unscaled = {"value": N * args.unscaled_steps / dtu, "unit": "unknowns/s",
+                    "ms_per_step": 1e3 * dtu / args.unscaled_steps,
+                    "ms_factor": 1e3 * float(np.mean(uf)), "ms_solve": 1e3 * float(np.mean(us)),
+                    "gmres_iterations": max(uit), "relres": max(ures),
+                    "sparsify_kernel": {"kernel": "k_sparsify_unscaled", "bound": "alu64", "achieved": ach,
+                                        "peak": pk, "unit": un, "frac": ach / pk,
+                                        "ms_per_step": qu["total_ms"] / args.unscaled_steps,
+                                        "launches_per_step": qu["launches"] / args.unscaled_steps,
+                                        "avg_launch_us": 1e3 * qu["total_ms"] / max(1, qu["launches"]),
+                                        "flops_per_step": qu["flops"] / args.unscaled_steps}}
 
     bound = KERNEL_BOUND[kern]
     achieved, peak, unit = rate(bound, prof)
@@ -522,6 +564,7 @@ def main():
                        "note": "ordering + symbolic analysis included in every step"},
         "gmres_iterations": max(r32["its"]), "relres": max(max(r32["res"]), res_host),
         "fp64_plain": plain64,
+        "unscaled": unscaled,
         "factor": {"ms_factor": st["ms_factor"], "factor_bytes": st["factor_bytes"],
                    "top_separator": st["top_separator"], "flops_sparsify": st["flops_sparsify"]},
         "roofline": roof,

@@ -315,7 +315,8 @@ spaqr_status spaqr_stage_sizes(const spaqr_handle* h, int stage, int32_t* buf,
  * clears the table and starts recording every kernel (only == NULL), just
  * the kernel named `only`, or, when `only` ends in '*', every name with that
  * prefix; enable(0, NULL) stops.  Kernel names:
- * "front_qr", "scale_qr", "scale_blocks", "sparsify", "copy",
+ * "front_qr", "scale_qr", "scale_blocks", "sparsify", "sparsify_unscaled"
+ * (the sparsification without scaling, scale = 0), "copy",
  * "apply_front_fwd", "apply_front_bwd", "apply_iface_fwd", "apply_iface_bwd".
  * Block copies are recorded under "copy" and under their role
  * ("copy_front_gather", "copy_front_scatter", "copy_front_pack",
@@ -334,7 +335,8 @@ spaqr_status spaqr_profile_query(const char* kernel, int64_t* launches, double* 
  * kernel template's name, e.g. "k_qr_reg", "k_qr", "k_trail", "k_scale_small",
  * "k_scale_right", "k_cpqr_reg", "k_cpqr_coop", "k_sparsify",
  * "k_ap_front_fwd_wy", "k_ap_front_bwd_reg", "k_ap_iface_fwd",
- * "k_ap_iface_bwd", "k_ap_iface_dense", "k_iface_form", "k_copy".  Tests use
+ * "k_ap_iface_bwd", "k_ap_iface_dense", "k_ap_iface_dense_big",
+ * "k_sparsify_unscaled", "k_iface_form", "k_copy".  Tests use
  * it to show which kernel paths a case exercised.  kernel == NULL resets
  * every count (and writes 0).  Unknown names give 0.  Errors: EINVAL if
  * count is NULL. */

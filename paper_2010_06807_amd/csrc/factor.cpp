@@ -1014,7 +1014,7 @@ void Engine<T>::finish(MergePlan<T>& mp) {
     const double eb = sizeof(T);
     std::vector<int32_t> iidx(nclu, -1);
     for (size_t t = 0; t < ss.ifaces.size(); ++t) iidx[ss.ifaces[t].cluster] = (int32_t)t;
-    double sp_flops = 0.0, sp_bytes = 0.0;
+    double sp_flops = 0.0, sp_bytes = 0.0, ul_flops = 0.0, ul_bytes = 0.0;
     for (size_t t = 0; t < ss.ifaces.size(); ++t) {
       const IfaceSym& I = ss.ifaces[t];
       const int32_t p = I.cluster;
@@ -1041,10 +1041,29 @@ void Engine<T>::finish(MergePlan<T>& mp) {
       // columns of the |p| x m matrix with its trailing update,
       // 4|p|mr - 2r^2(|p| + m) + 4/3 r^3, plus one norm update per column
       // and step, m r
-      double m = 0.0;
-      for (int32_t q : I.rowN) m += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
-      for (int32_t q : I.colN) m += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
+      double mr = 0.0, mc = 0.0;
+      for (int32_t q : I.rowN) mr += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
+      for (int32_t q : I.colN) mc += ss.ifaces[iidx[q]].colour < I.colour ? rb_[q] : size_[q];
+      const double m = mr + mc;
       const double fl = 4.0 * P * m * r - 2.0 * r * r * (P + m) + 4.0 / 3.0 * r * r * r + m * r;
+      if (!o_.scale) {
+        // without scaling (Section 2.5), on top of the CPQR: bidiagonalization
+        // of the (P + m_r) x P matrix A_p for sigma_min, 4(P + m_r)P^2 -
+        // 4/3 P^3; sigma A_pp^T A_pn, 2 P^2 m_c; and when r < P (f = P - r):
+        // A_pp Q and the backward operator's Q, each 4P(Pr - r(r-1)/2); the QR
+        // of the f columns, 2Pf^2 - 2/3 f^3, with its reflectors applied to
+        // the r + m_c other columns and to the forward operator's P columns,
+        // 4(r + m_c + P)(Pf - f(f-1)/2); the backward operator's triangular
+        // solves, P f^2
+        const double f = P - r;
+        double ul = 4.0 * (P + mr) * P * P - 4.0 / 3.0 * P * P * P + 2.0 * P * P * mc + fl;
+        if (f > 0)
+          ul += 8.0 * P * (P * r - r * (r - 1) / 2) + 2.0 * P * f * f - 2.0 / 3.0 * f * f * f +
+                4.0 * (r + mc + P) * (P * f - f * (f - 1) / 2) + P * f * f;
+        ul_flops += ul;
+        // blocks read once and written once, both operators written
+        ul_bytes += (P * P + P * m) * eb * 2 + (f > 0 ? 2 * P * P * eb : 0.0);
+      }
       sp_flops += fl;
       st_.s.flops_sparsify += fl;
       sg.flops_sparsify += fl;
@@ -1056,7 +1075,8 @@ void Engine<T>::finish(MergePlan<T>& mp) {
       st_.ifaces[k].insert(st_.ifaces[k].end(), {p, (int32_t)P, (int32_t)m, (int32_t)r});
       sp_bytes += (P * m + (r < P ? r * m : 0.0)) * eb;
     }
-    prof_add("sparsify", sp_flops, sp_bytes);
+    if (o_.scale) prof_add("sparsify", sp_flops, sp_bytes);
+    else prof_add("sparsify_unscaled", ul_flops, ul_bytes);
     std::vector<int32_t> ps;
     for (size_t t = 1; t < st_.ifaces[k].size(); t += 4) ps.push_back(st_.ifaces[k][t]);
     if (!ps.empty()) {
@@ -1789,10 +1809,12 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
       }
     }
     if (sd.empty()) continue;
+    int max_p = 0;
+    for (const SpuDesc<T>& d : sd) max_p = std::max(max_p, (int)d.P);
     SpuDesc<T>* dsd = up.upload(wk, sd, s);
     SpNbr* dnb = up.upload(wk, nb, s);
-    ProfScope ps("sparsify", s, 0.0, 0.0);
-    launch_sparsify_unscaled<T>(dsd, dnb, (int64_t)sd.size(), s);
+    ProfScope ps("sparsify_unscaled", s, 0.0, 0.0);
+    launch_sparsify_unscaled<T>(dsd, dnb, (int64_t)sd.size(), max_p, s);
   }
   {
     // dense interface operators, one launch per size class (16, 32, 64)

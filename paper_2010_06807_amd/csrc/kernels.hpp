@@ -153,7 +153,7 @@ struct SpuDesc {
 };
 int64_t sparsify_unscaled_ws(int P, int mr_max, int mc_max);
 template <typename T>
-void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, hipStream_t s);
+void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, int max_p, hipStream_t s);
 
 // Apply descriptors (vectors are FP64, slots index the permuted vector).
 template <typename T>

@@ -46,7 +46,10 @@ namespace spaqr {
 
 namespace {
 
-constexpr int kNT = 256;  // threads per workgroup (four wavefronts)
+// threads per workgroup: 256 for colours of interfaces of at most 64
+// unknowns (many interfaces, one each), 1024 above (few wide interfaces: more
+// wavefronts in flight per reflector)
+constexpr int kNTSmall = 256, kNTWide = 1024;
 
 __device__ __forceinline__ double u_wave_sum(double v) {
 #pragma unroll
@@ -55,15 +58,20 @@ __device__ __forceinline__ double u_wave_sum(double v) {
 }
 
 // workgroup sum, returned to every thread (deterministic order)
+template <int NT>
 __device__ double u_wg_sum(double v, double* red) {
   v = u_wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return (red[0] + red[1]) + (red[2] + red[3]);
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) s += red[q];
+  return s;
 }
 
 // largest value, lowest index among equal values, returned to every thread
+template <int NT>
 __device__ void u_wg_argmax(double& v, int& i, double* sv, int* si) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -82,7 +90,7 @@ __device__ void u_wg_argmax(double& v, int& i, double* sv, int* si) {
   __syncthreads();
   v = sv[0];
   i = si[0];
-  for (int q = 1; q < kNT / 64; ++q)
+  for (int q = 1; q < NT / 64; ++q)
     if (sv[q] > v || (sv[q] == v && si[q] < i)) {
       v = sv[q];
       i = si[q];
@@ -93,20 +101,21 @@ __device__ void u_wg_argmax(double& v, int& i, double* sv, int* si) {
 // convention: beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
 // v = [1, x_tail / (alpha - beta)].  x[0] <- beta, the tail <- v[1:]; a zero
 // tail gives tau = 0 and leaves x unchanged.
+template <int NT>
 __device__ double u_larfg(double* x, int n, int64_t inc, double* red) {
   const int t = threadIdx.x;
   double s = 0.0;
-  for (int i = 1 + t; i < n; i += kNT) {
+  for (int i = 1 + t; i < n; i += NT) {
     const double v = x[i * inc];
     s += v * v;
   }
-  s = u_wg_sum(s, red);
+  s = u_wg_sum<NT>(s, red);
   const double alpha = x[0];
   if (s == 0.0) return 0.0;
   const double beta = -copysign(hypot(alpha, sqrt(s)), alpha);
   const double den = alpha - beta;
   __syncthreads();  // alpha read by every thread before x[0] changes
-  for (int i = 1 + t; i < n; i += kNT) x[i * inc] /= den;
+  for (int i = 1 + t; i < n; i += NT) x[i * inc] /= den;
   if (t == 0) x[0] = beta;
   __syncthreads();
   return (beta - alpha) / beta;
@@ -114,15 +123,24 @@ __device__ double u_larfg(double* x, int n, int64_t inc, double* red) {
 
 // A[0:n, j] -= tau v (v^T A[0:n, j]) for the ncols columns of a column-major
 // A (leading dimension lda), v[0] = 1, v[i] = vv[i]; a wavefront per column.
-__device__ void u_left(const double* vv, int n, double tau, double* A, int64_t lda, int ncols) {
+// v never overlaps the columns it is applied to.
+template <int NT>
+__device__ void u_left(const double* __restrict__ vv, int n, double tau, double* __restrict__ A, int64_t lda,
+                       int ncols) {
   if (tau != 0.0) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int j = w; j < ncols; j += kNT / 64) {
-      double* a = A + j * lda;
-      double s = 0.0;
-      for (int i = l; i < n; i += 64) s += (i == 0 ? 1.0 : vv[i]) * a[i];
-      s = u_wave_sum(s) * tau;
-      for (int i = l; i < n; i += 64) a[i] -= (i == 0 ? 1.0 : vv[i]) * s;
+    for (int j = w; j < ncols; j += NT / 64) {
+      double* __restrict__ a = A + j * lda;
+      double s0 = 0.0, s1 = 0.0;
+      int i = l;
+      for (; i + 64 < n; i += 128) {
+        s0 += (i == 0 ? 1.0 : vv[i]) * a[i];
+        s1 += vv[i + 64] * a[i + 64];
+      }
+      if (i < n) s0 += (i == 0 ? 1.0 : vv[i]) * a[i];
+      const double s = u_wave_sum(s0 + s1) * tau;
+#pragma unroll 4
+      for (int q = l; q < n; q += 64) a[q] -= (q == 0 ? 1.0 : vv[q]) * s;
     }
   }
   __syncthreads();
@@ -130,13 +148,21 @@ __device__ void u_left(const double* vv, int n, double tau, double* A, int64_t l
 
 // A[i, 0:n] -= tau (A[i, 0:n] v) v^T for the nrows rows of a column-major A,
 // v (v[0] = 1) in LDS; a thread per row.
-__device__ void u_right(const double* v, int n, double tau, double* A, int64_t lda, int nrows) {
+template <int NT>
+__device__ void u_right(const double* __restrict__ v, int n, double tau, double* __restrict__ A, int64_t lda,
+                        int nrows) {
   if (tau != 0.0) {
-    for (int i = threadIdx.x; i < nrows; i += kNT) {
-      double s = 0.0;
-      for (int q = 0; q < n; ++q) s += A[i + q * lda] * v[q];
-      s *= tau;
-      for (int q = 0; q < n; ++q) A[i + q * lda] -= s * v[q];
+    for (int i = threadIdx.x; i < nrows; i += NT) {
+      double s0 = 0.0, s1 = 0.0;
+      int q = 0;
+      for (; q + 1 < n; q += 2) {
+        s0 += A[i + q * lda] * v[q];
+        s1 += A[i + (q + 1) * lda] * v[q + 1];
+      }
+      if (q < n) s0 += A[i + q * lda] * v[q];
+      const double s = (s0 + s1) * tau;
+#pragma unroll 4
+      for (int u = 0; u < n; ++u) A[i + u * lda] -= s * v[u];
     }
   }
   __syncthreads();
@@ -194,12 +220,12 @@ __device__ double u_bidiag_smin(const double* d, const double* e, int n) {
   return 0.5 * (lo + hi);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __restrict__ ds,
-                                                          const SpNbr* __restrict__ nbs) {
-  __shared__ double red[kNT / 64];
-  __shared__ double sv[kNT / 64];
-  __shared__ int si[kNT / 64];
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_sparsify_unscaled(const SpuDesc<T>* __restrict__ ds,
+                                                         const SpNbr* __restrict__ nbs) {
+  __shared__ double red[NT / 64];
+  __shared__ double sv[NT / 64];
+  __shared__ int si[NT / 64];
   __shared__ double vbuf[kSpuMaxP];
   __shared__ int s_w[kSpuMaxNbr], s_off[kSpuMaxNbr + 1];
   __shared__ double s_smin;
@@ -210,7 +236,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   const int nn = d.nrow + d.ncol;
   const SpNbr* nb = nbs + d.nb;
   // current sizes of the neighbours (those of earlier colours were sparsified)
-  for (int q = t; q < nn; q += kNT) s_w[q] = d.rank[nb[q].cluster];
+  for (int q = t; q < nn; q += NT) s_w[q] = d.rank[nb[q].cluster];
   __syncthreads();
   if (t == 0) {
     int o = 0;
@@ -241,7 +267,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   const int mrows = P + mr;
 
   // ---- gather A_p (G), A_pp (B) and A_pn (N)
-  for (int e = t; e < P * P; e += kNT) {
+  for (int e = t; e < P * P; e += NT) {
     const int a = e / P, c = e - a * P;
     const double v = (double)app[e];
     G[a + c * ldg] = v;
@@ -250,7 +276,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   for (int q = 0; q < d.nrow; ++q) {
     const T* blk = pool + nb[q].blk;
     const int w = s_w[q], ld = nb[q].ld, o = s_off[q];
-    for (int e = t; e < w * P; e += kNT) {
+    for (int e = t; e < w * P; e += NT) {
       const int a = e / P, c = e - a * P;
       G[(P + o + a) + c * ldg] = (double)blk[(int64_t)a * ld + c];
     }
@@ -258,7 +284,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   for (int q = d.nrow; q < nn; ++q) {
     const T* blk = pool + nb[q].blk;
     const int w = s_w[q], ld = nb[q].ld, o = s_off[q] - mr;
-    for (int e = t; e < P * w; e += kNT) {
+    for (int e = t; e < P * w; e += NT) {
       const int a = e / w, c = e - a * w;
       N[a + (int64_t)(o + c) * P] = (double)blk[(int64_t)a * ld + c];
     }
@@ -268,16 +294,16 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   // ---- Golub-Kahan bidiagonalization of A_p (mrows >= P)
   for (int k = 0; k < P; ++k) {
     double* gk = G + k + (int64_t)k * ldg;
-    const double tl = u_larfg(gk, mrows - k, 1, red);
+    const double tl = u_larfg<NT>(gk, mrows - k, 1, red);
     if (t == 0) dd[k] = gk[0];
-    u_left(gk, mrows - k, tl, gk + ldg, ldg, P - k - 1);
+    u_left<NT>(gk, mrows - k, tl, gk + ldg, ldg, P - k - 1);
     if (k + 1 < P) {
       double* rk = G + k + (int64_t)(k + 1) * ldg;
-      const double tr = u_larfg(rk, P - k - 1, ldg, red);
+      const double tr = u_larfg<NT>(rk, P - k - 1, ldg, red);
       if (t == 0) ee[k] = rk[0];
-      for (int u = t; u < P - k - 1; u += kNT) vbuf[u] = u == 0 ? 1.0 : rk[(int64_t)u * ldg];
+      for (int u = t; u < P - k - 1; u += NT) vbuf[u] = u == 0 ? 1.0 : rk[(int64_t)u * ldg];
       __syncthreads();
-      u_right(vbuf, P - k - 1, tr, G + (k + 1) + (int64_t)(k + 1) * ldg, ldg, mrows - k - 1);
+      u_right<NT>(vbuf, P - k - 1, tr, G + (k + 1) + (int64_t)(k + 1) * ldg, ldg, mrows - k - 1);
     }
   }
   __syncthreads();
@@ -298,20 +324,25 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   for (int q = 0; q < d.nrow; ++q) {
     const T* blk = pool + nb[q].blk;
     const int w = s_w[q], ld = nb[q].ld, o = s_off[q];
-    for (int e = t; e < w * P; e += kNT) {
+    for (int e = t; e < w * P; e += NT) {
       const int b = e / P, a = e - b * P;
       Cw[(int64_t)a * M + o + b] = (double)blk[(int64_t)b * ld + a];
     }
   }
-  for (int e = t; e < P * mc; e += kNT) {
+  for (int e = t; e < P * mc; e += NT) {
     const int c = e / P, a = e - c * P;
     const double* ba = B + (int64_t)a * P;
     const double* nc = N + (int64_t)c * P;
-    double s = 0.0;
-    for (int q = 0; q < P; ++q) s += ba[q] * nc[q];
-    Cw[(int64_t)a * M + mr + c] = sigma * s;
+    double s0 = 0.0, s1 = 0.0;
+    int q = 0;
+    for (; q + 1 < P; q += 2) {
+      s0 += ba[q] * nc[q];
+      s1 += ba[q + 1] * nc[q + 1];
+    }
+    if (q < P) s0 += ba[q] * nc[q];
+    Cw[(int64_t)a * M + mr + c] = sigma * (s0 + s1);
   }
-  for (int j = t; j < m; j += kNT) perm[j] = j;
+  for (int j = t; j < m; j += NT) perm[j] = j;
   __syncthreads();
 
   // ---- partial CPQR with exact norms and the ratio rule
@@ -321,18 +352,25 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   for (int k = 0; k < kmax; ++k) {
     double bv = -1.0;
     int bi = INT_MAX;
-    for (int j = k + t; j < m; j += kNT) {
-      double s = 0.0;
-      for (int i = k; i < P; ++i) {
-        const double v = Cw[(int64_t)i * M + j];
-        s += v * v;
+    for (int j = k + t; j < m; j += NT) {
+      double s0 = 0.0, s1 = 0.0;
+      int i = k;
+      for (; i + 1 < P; i += 2) {
+        const double v0 = Cw[(int64_t)i * M + j], v1 = Cw[(int64_t)(i + 1) * M + j];
+        s0 += v0 * v0;
+        s1 += v1 * v1;
       }
+      if (i < P) {
+        const double v0 = Cw[(int64_t)i * M + j];
+        s0 += v0 * v0;
+      }
+      const double s = s0 + s1;
       if (s > bv) {
         bv = s;
         bi = j;
       }
     }
-    u_wg_argmax(bv, bi, sv, si);
+    u_wg_argmax<NT>(bv, bi, sv, si);
     const double rkk = sqrt(bv);
     if (k == 0) {
       R11 = rkk;
@@ -340,7 +378,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
     }
     if (d.eps > 0.0 && rkk < d.eps * R11) break;
     if (bi != k) {
-      for (int i = t; i < P; i += kNT) {
+      for (int i = t; i < P; i += NT) {
         const double a = Cw[(int64_t)i * M + k];
         Cw[(int64_t)i * M + k] = Cw[(int64_t)i * M + bi];
         Cw[(int64_t)i * M + bi] = a;
@@ -353,16 +391,22 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
       __syncthreads();
     }
     double* ck = Cw + (int64_t)k * M + k;
-    const double tau = u_larfg(ck, P - k, M, red);
+    const double tau = u_larfg<NT>(ck, P - k, M, red);
     if (t == 0) tq[k] = tau;
-    for (int u = t; u < P - k; u += kNT) vbuf[u] = u == 0 ? 1.0 : ck[(int64_t)u * M];
+    for (int u = t; u < P - k; u += NT) vbuf[u] = u == 0 ? 1.0 : ck[(int64_t)u * M];
     __syncthreads();
     if (tau != 0.0)
-      for (int j = k + 1 + t; j < m; j += kNT) {
-        double s = 0.0;
-        for (int u = 0; u < P - k; ++u) s += vbuf[u] * Cw[(int64_t)(k + u) * M + j];
-        s *= tau;
-        for (int u = 0; u < P - k; ++u) Cw[(int64_t)(k + u) * M + j] -= vbuf[u] * s;
+      for (int j = k + 1 + t; j < m; j += NT) {
+        double s0 = 0.0, s1 = 0.0;
+        int u = 0;
+        for (; u + 1 < P - k; u += 2) {
+          s0 += vbuf[u] * Cw[(int64_t)(k + u) * M + j];
+          s1 += vbuf[u + 1] * Cw[(int64_t)(k + u + 1) * M + j];
+        }
+        if (u < P - k) s0 += vbuf[u] * Cw[(int64_t)(k + u) * M + j];
+        const double s = (s0 + s1) * tau;
+#pragma unroll 4
+        for (int q = 0; q < P - k; ++q) Cw[(int64_t)(k + q) * M + j] -= vbuf[q] * s;
       }
     __syncthreads();
     r = k + 1;
@@ -375,16 +419,16 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   const int f = P - r;
 
   // ---- Q's reflectors (unit diagonal), inverse permutation, A_ip Q
-  for (int e = t; e < P * r; e += kNT) {
+  for (int e = t; e < P * r; e += NT) {
     const int c = e / P, i = e - c * P;
     Vq[e] = i < c ? 0.0 : (i == c ? 1.0 : Cw[(int64_t)i * M + c]);
   }
-  for (int j = t; j < m; j += kNT) iperm[perm[j]] = j;
+  for (int j = t; j < m; j += NT) iperm[perm[j]] = j;
   __syncthreads();
   for (int q = 0; q < d.nrow; ++q) {
     T* blk = pool + nb[q].blk;
     const int w = s_w[q], ld = nb[q].ld, o = s_off[q];
-    for (int e = t; e < w * r; e += kNT) {
+    for (int e = t; e < w * r; e += NT) {
       const int b = e / r, c = e - b * r;
       const int pos = iperm[o + b];
       blk[(int64_t)b * ld + c] = (T)(c > pos ? 0.0 : Cw[(int64_t)c * M + pos]);
@@ -393,40 +437,40 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
 
   // ---- A_pp Q = A_pp H_0 H_1 ... H_{r-1}
   for (int u = 0; u < r; ++u) {
-    for (int i = t; i < P - u; i += kNT) vbuf[i] = Vq[(u + i) + (int64_t)u * P];
+    for (int i = t; i < P - u; i += NT) vbuf[i] = Vq[(u + i) + (int64_t)u * P];
     __syncthreads();
-    u_right(vbuf, P - u, tq[u], B + (int64_t)u * P, P, P);
+    u_right<NT>(vbuf, P - u, tq[u], B + (int64_t)u * P, P, P);
   }
 
   // ---- Householder QR of the f columns; H^T on the c columns and on A_pn
   for (int u = 0; u < f; ++u) {
     double* bu = B + u + (int64_t)(r + u) * P;
-    const double th = u_larfg(bu, P - u, 1, red);
+    const double th = u_larfg<NT>(bu, P - u, 1, red);
     if (t == 0) tH[u] = th;
-    u_left(bu, P - u, th, bu + P, P, f - u - 1);
-    u_left(bu, P - u, th, B + u, P, r);
-    u_left(bu, P - u, th, N + u, P, mc);
+    u_left<NT>(bu, P - u, th, bu + P, P, f - u - 1);
+    u_left<NT>(bu, P - u, th, B + u, P, r);
+    u_left<NT>(bu, P - u, th, N + u, P, mc);
   }
 
   // ---- the new blocks of p: the last r rows, stored first
-  for (int e = t; e < r * r; e += kNT) {
+  for (int e = t; e < r * r; e += NT) {
     const int a = e / r, c = e - a * r;
     app[(int64_t)a * P + c] = (T)B[(f + a) + (int64_t)c * P];
   }
   for (int q = d.nrow; q < nn; ++q) {
     T* blk = pool + nb[q].blk;
     const int w = s_w[q], ld = nb[q].ld, o = s_off[q] - mr;
-    for (int e = t; e < r * w; e += kNT) {
+    for (int e = t; e < r * w; e += NT) {
       const int a = e / w, c = e - a * w;
       blk[(int64_t)a * ld + c] = (T)N[(f + a) + (int64_t)(o + c) * P];
     }
   }
 
   // ---- forward operator Pi H^T
-  for (int e = t; e < P * P; e += kNT) E[e] = (e % P == e / P) ? 1.0 : 0.0;
+  for (int e = t; e < P * P; e += NT) E[e] = (e % P == e / P) ? 1.0 : 0.0;
   __syncthreads();
-  for (int u = 0; u < f; ++u) u_left(B + u + (int64_t)(r + u) * P, P - u, tH[u], E + u, P, P);
-  for (int e = t; e < P * P; e += kNT) {
+  for (int u = 0; u < f; ++u) u_left<NT>(B + u + (int64_t)(r + u) * P, P - u, tH[u], E + u, P, P);
+  for (int e = t; e < P * P; e += NT) {
     const int c = e / P, a = e - c * P;
     const int src = a < r ? f + a : a - r;
     d.mf[e] = (T)E[src + (int64_t)c * P];
@@ -434,7 +478,7 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
   __syncthreads();
 
   // ---- backward operator Q T
-  for (int c = t; c < P; c += kNT) {
+  for (int c = t; c < P; c += NT) {
     double* col = E + (int64_t)c * P;
     for (int i = 0; i < r; ++i) col[i] = i == c ? 1.0 : 0.0;
     for (int b = 0; b < f; ++b) col[r + b] = c < r ? -B[b + (int64_t)c * P] : (b == c - r ? 1.0 : 0.0);
@@ -445,15 +489,15 @@ __global__ void __launch_bounds__(kNT) k_sparsify_unscaled(const SpuDesc<T>* __r
     }
   }
   __syncthreads();
-  for (int u = r - 1; u >= 0; --u) u_left(Vq + u + (int64_t)u * P, P - u, tq[u], E + u, P, P);
-  for (int e = t; e < P * P; e += kNT) d.mb[e] = (T)E[e];
+  for (int u = r - 1; u >= 0; --u) u_left<NT>(Vq + u + (int64_t)u * P, P - u, tq[u], E + u, P, P);
+  for (int e = t; e < P * P; e += NT) d.mb[e] = (T)E[e];
   if (t == 0) d.rank[d.cluster] = r;
 }
 
 // x_p <- M x_p for interfaces of any size up to kSpuMaxP, one workgroup per
 // interface: x_p staged in LDS, a thread per row (column-major M, coalesced).
 template <typename T>
-__global__ void __launch_bounds__(kNT) k_ap_iface_dense_big(const ApIface<T>* __restrict__ ds, int backward,
+__global__ void __launch_bounds__(kNTSmall) k_ap_iface_dense_big(const ApIface<T>* __restrict__ ds, int backward,
                                                            double* x, int64_t ldx, int nrhs) {
   __shared__ double xs[kSpuMaxP];
   const ApIface<T> d = ds[blockIdx.x];
@@ -462,9 +506,9 @@ __global__ void __launch_bounds__(kNT) k_ap_iface_dense_big(const ApIface<T>* __
   x += d.xoff;
   const T* Mx = backward ? d.mb : d.mf;
   for (int c = 0; c < nrhs; ++c) {
-    for (int i = threadIdx.x; i < P; i += kNT) xs[i] = x[d.slots[i] + (int64_t)c * ldx];
+    for (int i = threadIdx.x; i < P; i += kNTSmall) xs[i] = x[d.slots[i] + (int64_t)c * ldx];
     __syncthreads();
-    for (int i = threadIdx.x; i < P; i += kNT) {
+    for (int i = threadIdx.x; i < P; i += kNTSmall) {
       double acc = 0.0;
       for (int j = 0; j < P; ++j) acc += (double)Mx[i + (int64_t)j * P] * xs[j];
       x[d.slots[i] + (int64_t)c * ldx] = acc;
@@ -487,10 +531,13 @@ int64_t sparsify_unscaled_ws(int P, int mr_max, int mc_max) {
 }
 
 template <typename T>
-void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, hipStream_t s) {
+void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, int max_p, hipStream_t s) {
   if (n <= 0) return;
   count_launch("k_sparsify_unscaled");
-  hipLaunchKernelGGL(k_sparsify_unscaled<T>, dim3((unsigned)n), dim3(kNT), 0, s, d, nb);
+  if (max_p <= 64)
+    hipLaunchKernelGGL((k_sparsify_unscaled<T, kNTSmall>), dim3((unsigned)n), dim3(kNTSmall), 0, s, d, nb);
+  else
+    hipLaunchKernelGGL((k_sparsify_unscaled<T, kNTWide>), dim3((unsigned)n), dim3(kNTWide), 0, s, d, nb);
   spu_check_launch("k_sparsify_unscaled");
 }
 
@@ -499,13 +546,13 @@ void launch_iface_dense_big(const ApIface<T>* d, int64_t n, bool backward, doubl
                             hipStream_t s) {
   if (n <= 0 || nrhs <= 0) return;
   count_launch("k_ap_iface_dense_big");
-  hipLaunchKernelGGL(k_ap_iface_dense_big<T>, dim3((unsigned)n), dim3(kNT), 0, s, d, backward ? 1 : 0, x, ldx,
+  hipLaunchKernelGGL(k_ap_iface_dense_big<T>, dim3((unsigned)n), dim3(kNTSmall), 0, s, d, backward ? 1 : 0, x, ldx,
                      nrhs);
   spu_check_launch("k_ap_iface_dense_big");
 }
 
-template void launch_sparsify_unscaled<float>(const SpuDesc<float>*, const SpNbr*, int64_t, hipStream_t);
-template void launch_sparsify_unscaled<double>(const SpuDesc<double>*, const SpNbr*, int64_t, hipStream_t);
+template void launch_sparsify_unscaled<float>(const SpuDesc<float>*, const SpNbr*, int64_t, int, hipStream_t);
+template void launch_sparsify_unscaled<double>(const SpuDesc<double>*, const SpNbr*, int64_t, int, hipStream_t);
 template void launch_iface_dense_big<float>(const ApIface<float>*, int64_t, bool, double*, int64_t, int, hipStream_t);
 template void launch_iface_dense_big<double>(const ApIface<double>*, int64_t, bool, double*, int64_t, int,
                                              hipStream_t);

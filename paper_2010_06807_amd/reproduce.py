@@ -13,16 +13,17 @@ printed beside the counts the paper reports:
   ad3      3D, a = b = q = 1, eps in {1e-1, 1e-2}, n = 64, 80, 96
            (Fig. 3d_ad)
   hc       2D high contrast rho in {1, 10, 100}, b = q = 1, eps = 1e-2,
-           n = 128..512 (Section 4.1.1's problem; the paper's iteration
-           counts for it compare scaled and unscaled variants and are not
-           reproduced here)
+           n = 128..512 (Section 4.1.1's problem with scaling only)
+  hc_abl   the comparison of Section 4.1.1 (Fig. hc_ad_comparison): the
+           high-contrast problem with rho in {1, 10, 100} at eps in
+           {1e-3, 1e-5}, n = 127..1023, with and without scaling
 
 The partition differs from the paper's (its code is not public: this
 library's geometric nested dissection with two-layer separators), so the
 counts are a trend comparison, not parity.  Right-hand sides are U[-1, 1]
 from seed 0.
 
-    python -m paper_2010_06807_amd.reproduce [ad2_q ad2_eps ad3 hc] [--max-n 1024] [--json out.json]
+    python -m paper_2010_06807_amd.reproduce [ad2_q ad2_eps ad3 hc hc_abl] [--max-n 1024] [--json out.json]
 """
 
 from __future__ import annotations
@@ -49,6 +50,19 @@ PAPER = {
 }
 
 
+# GMRES counts of Fig. hc_ad_comparison, keyed by (rho, eps, scaled) then n;
+# None where the paper marks no convergence
+PAPER_HC = {
+    (1, 1e-3, True): (5, 6, 7, 7), (1, 1e-3, False): (17, 40, 81, 159),
+    (10, 1e-3, True): (5, 7, 8, 10), (10, 1e-3, False): (22, 90, 174, None),
+    (100, 1e-3, True): (6, 9, 13, 21), (100, 1e-3, False): (22, 121, None, None),
+    (1, 1e-5, True): (3, 3, 3, 3), (1, 1e-5, False): (8, 13, 23, 46),
+    (10, 1e-5, True): (3, 3, 4, 4), (10, 1e-5, False): (11, 27, 63, 123),
+    (100, 1e-5, True): (3, 4, 5, 5), (100, 1e-5, False): (13, 57, 259, None),
+}
+HC_N = (127, 255, 511, 1023)
+
+
 def run(series, max_n=1024, tol=1e-12, log=print):
     import numpy as np
     import torch
@@ -70,7 +84,12 @@ def run(series, max_n=1024, tol=1e-12, log=print):
                   if n ** 3 <= max_n ** 2]
     if "hc" in series:
         cases += [("hc", f"rho={r:g}", n, dict(rho=r), 1e-2) for r in (1.0, 10.0, 100.0) for n in ns2 if n <= 512]
-    for kind, label, n, kw, eps in cases:
+    cases = [c + (True,) for c in cases]
+    if "hc_abl" in series:
+        cases += [("hc", f"rho={r} eps={e:.0e} {'scaled' if sc else 'unscaled'}".replace("e-0", "e-"), n,
+                   dict(rho=float(r)), e, sc)
+                  for e in (1e-3, 1e-5) for r in (1, 10, 100) for sc in (True, False) for n in HC_N if n <= max_n]
+    for kind, label, n, kw, eps, scale in cases:
         prob = paper_problem(kind, n, **kw)
         A, dims = prob["A"], prob["dims"]
         N = A.shape[0]
@@ -80,17 +99,22 @@ def run(series, max_n=1024, tol=1e-12, log=print):
         b = torch.from_numpy(make_rhs(N, 1, seed=0)).to("cuda:0")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fac = P.factor(A, o, eps=eps, precision=64)
+        fac = P.factor(A, o, eps=eps, precision=64, scale=scale)
         torch.cuda.synchronize()
         tf = time.perf_counter() - t0
         x, info = fac.solve(b, tol=tol)
         res = float(np.linalg.norm(A @ x.cpu().numpy()[:, 0] - b.cpu().numpy()[:, 0]) /
                     np.linalg.norm(b.cpu().numpy()[:, 0]))
         st = fac.stats()
-        rec = dict(series=label, kind=kind, n=n, N=N, levels=L, eps=eps, iterations=info[0]["iterations"],
-                   converged=info[0]["converged"], relres=res, factor_s=tf, solve_s=info[0]["seconds"],
-                   top_separator=st["top_separator"], factor_bytes=st["factor_bytes"],
-                   paper_iterations=PAPER.get((label, n)))
+        if "scaled" in label:
+            r = int(kw["rho"])
+            pit = PAPER_HC[(r, eps, scale)][HC_N.index(n)]
+        else:
+            pit = PAPER.get((label, n))
+        rec = dict(series=label, kind=kind, n=n, N=N, levels=L, eps=eps, scale=scale,
+                   iterations=info[0]["iterations"], converged=info[0]["converged"], relres=res, factor_s=tf,
+                   solve_s=info[0]["seconds"], top_separator=st["top_separator"], factor_bytes=st["factor_bytes"],
+                   paper_iterations=pit)
         out.append(rec)
         log(json.dumps(rec))
         del fac
@@ -99,7 +123,7 @@ def run(series, max_n=1024, tol=1e-12, log=print):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("series", nargs="*", default=["ad2_q", "ad2_eps", "ad3", "hc"])
+    ap.add_argument("series", nargs="*", default=["ad2_q", "ad2_eps", "ad3", "hc", "hc_abl"])
     ap.add_argument("--max-n", type=int, default=1024)
     ap.add_argument("--json", default=None)
     a = ap.parse_args()
@@ -110,7 +134,8 @@ def main():
     print("| series | n | N | eps | GMRES (this build) | GMRES (paper) | factor s | relres |")
     print("|---|---|---|---|---|---|---|---|")
     for r in res:
-        print(f"| {r['series']} | {r['n']} | {r['N']} | {r['eps']:g} | {r['iterations']} | "
+        its = r["iterations"] if r["converged"] else f"{r['iterations']} (not converged)"
+        print(f"| {r['series']} | {r['n']} | {r['N']} | {r['eps']:g} | {its} | "
               f"{r['paper_iterations'] if r['paper_iterations'] is not None else '-'} | {r['factor_s']:.3f} | "
               f"{r['relres']:.1e} |")
 

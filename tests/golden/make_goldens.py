@@ -19,10 +19,14 @@ holding
   * an estimate of ||A^{-1}||_2 (oracle/conditioning.py), which turns the two
     residual bounds into a bound on ||x_engine - x_oracle||.
 
+With --unscaled the oracle runs the sparsification without scaling of
+Section 2.5 (scale=False) and the file is <workload>_s<seed>_eps<eps>_unscaled.json.
+
 Usage (from the repository root; one process per case, single-threaded BLAS):
   python tests/golden/make_goldens.py c2 --seeds 0 1 2 --eps 1e-2 1e-4 1e-6
   python tests/golden/make_goldens.py c4 --seeds 0 1 2
   python tests/golden/make_goldens.py c3 --seeds 0
+  python tests/golden/make_goldens.py c2 --seeds 0 --eps 1e-2 --unscaled
 """
 
 from __future__ import annotations
@@ -53,13 +57,13 @@ def unpack(s, dtype):
     return np.frombuffer(zlib.decompress(base64.b64decode(s)), dtype=dtype)
 
 
-def golden_path(workload, seed, eps):
-    return os.path.join(HERE, f"{workload}_s{seed}_eps{eps:g}.json")
+def golden_path(workload, seed, eps, scale=True):
+    return os.path.join(HERE, f"{workload}_s{seed}_eps{eps:g}{'' if scale else '_unscaled'}.json")
 
 
-def load(workload, seed, eps):
+def load(workload, seed, eps, scale=True):
     """The stored record of one case, with its arrays decoded (None if absent)."""
-    p = golden_path(workload, seed, eps)
+    p = golden_path(workload, seed, eps, scale)
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -83,7 +87,7 @@ def cpqr_flops(shapes):
     return tot
 
 
-def make_case(workload, seed, eps, tol=1e-10):
+def make_case(workload, seed, eps, tol=1e-10, scale=True):
     from threadpoolctl import threadpool_limits
     from problems import config_problem, make_rhs
     from oracle.ordering import order_grid
@@ -96,7 +100,7 @@ def make_case(workload, seed, eps, tol=1e-10):
     b = make_rhs(N, 1, seed=seed)[:, 0]
     t0 = time.perf_counter()
     with threadpool_limits(limits=1):
-        F = osq.factor(A, order_grid(dims, L), eps)
+        F = osq.factor(A, order_grid(dims, L), eps, scale=scale)
         t1 = time.perf_counter()
         y = osq.apply(F, b)
         x, it, rel = ogm.fgmres(lambda v: A @ v, lambda v: osq.apply(F, v), b, tol)
@@ -111,7 +115,7 @@ def make_case(workload, seed, eps, tol=1e-10):
     rng = np.random.default_rng([seed, 7])
     idx = np.sort(rng.choice(N, size=min(NSAMPLE, N), replace=False)).astype(np.int64)
     out = {
-        "workload": workload, "seed": seed, "eps": eps, "tol": tol, "n": N, "levels": L,
+        "workload": workload, "seed": seed, "eps": eps, "scale": bool(scale), "tol": tol, "n": N, "levels": L,
         "dims": list(dims),
         "stage_sizes": {str(k): pack(F.stages[k]["sizes_post"], np.int32) for k in range(L, 0, -1)},
         "sparsified_stages": [k for k in range(L, 0, -1) if F.stages[k]["sparsified"]],
@@ -130,7 +134,7 @@ def make_case(workload, seed, eps, tol=1e-10):
         "inv_norm2_est": inv,
         "oracle_seconds": {"factor": t1 - t0, "apply_and_gmres": t2 - t1},
     }
-    with open(golden_path(workload, seed, eps), "w") as f:
+    with open(golden_path(workload, seed, eps, scale), "w") as f:
         json.dump(out, f, indent=0)
     return out
 
@@ -140,13 +144,14 @@ def main():
     ap.add_argument("workload", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0])
     ap.add_argument("--eps", type=float, nargs="+", default=None)
+    ap.add_argument("--unscaled", action="store_true", help="the sparsification without scaling (Section 2.5)")
     a = ap.parse_args()
     from problems import config_problem
     eps_list = a.eps if a.eps else [e for e in config_problem(a.workload)["eps"] if e > 0]
     for s in a.seeds:
         for e in eps_list:
             t = time.perf_counter()
-            g = make_case(a.workload, s, e)
+            g = make_case(a.workload, s, e, scale=not a.unscaled)
             print(f"{a.workload} seed {s} eps {e:g}: {time.perf_counter() - t:.1f} s, "
                   f"{g['gmres_iterations']} its, relres {g['gmres_relres']:.2e}", flush=True)
 

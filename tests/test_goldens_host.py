@@ -16,8 +16,9 @@ from make_goldens import load, cpqr_flops  # noqa: E402
 def _cases():
     out = []
     for p in sorted(glob.glob(os.path.join(HERE, "golden", "c*_s*_eps*.json"))):
-        w, s, e = os.path.basename(p)[:-5].split("_")
-        out.append((w, int(s[1:]), float(e[3:])))
+        parts = os.path.basename(p)[:-5].split("_")
+        w, s, e = parts[:3]
+        out.append((w, int(s[1:]), float(e[3:]), len(parts) == 3))
     return out
 
 
@@ -25,16 +26,18 @@ def test_expected_cases_present():
     have = set(_cases())
     for s in (0, 1, 2):
         for e in (1e-2, 1e-4, 1e-6):
-            assert ("c2", s, e) in have
-    assert ("c4", 0, 1e-2) in have and ("c3", 0, 1e-2) in have
+            assert ("c2", s, e, True) in have
+    assert ("c4", 0, 1e-2, True) in have and ("c3", 0, 1e-2, True) in have
+    assert ("c2", 0, 1e-2, False) in have
 
 
 def test_records_are_consistent():
     from problems import config_problem
     from oracle.ordering import order_grid
     orderings = {}
-    for w, s, e in _cases():
-        g = load(w, s, e)
+    for w, s, e, scale in _cases():
+        g = load(w, s, e, scale)
+        assert g.get("scale", True) == scale
         assert g["gmres_relres"] <= 1e-10 and g["gmres_iterations"] >= 1
         assert abs(cpqr_flops(g["cpqr_shapes"]) - g["cpqr_flops"]) <= 1e-9 * g["cpqr_flops"]
         # ranks never exceed the interface size or the number of columns

@@ -2,8 +2,9 @@
 
 The files under tests/golden/ were written by tests/golden/make_goldens.py,
 which runs only the oracle.  For every stored case (the 256^2
-variable-coefficient workload at eps 1e-2, 1e-4 and 1e-6, seeds 0-2; the
-1024^2 advection-dominated workload, seeds 0-2; the 64^3 workload, seed 0)
+variable-coefficient workload at eps 1e-2, 1e-4 and 1e-6, seeds 0-2, and
+seed 0 at 1e-2 without scaling (Section 2.5); the 1024^2 advection-dominated
+workload, seeds 0-2; the 64^3 workload, seed 0)
 the engine factors the same seeded matrix through the path the benchmark
 times (values resident on the device, spaqr_factor_device) in FP64 and in
 FP32 and is held to these bars:
@@ -53,12 +54,14 @@ DEV = "cuda:0"
 
 CASES = []
 for _p in sorted(glob.glob(os.path.join(HERE, "golden", "c*_s*_eps*.json"))):
-    _b = os.path.basename(_p)[:-5]
-    _w, _s, _e = _b.split("_")
-    CASES.append((_w, int(_s[1:]), float(_e[3:])))
+    _parts = os.path.basename(_p)[:-5].split("_")
+    _w, _s, _e = _parts[:3]
+    # a "_unscaled" suffix: the sparsification without scaling (Section 2.5)
+    CASES.append((_w, int(_s[1:]), float(_e[3:]), len(_parts) == 3))
 
 # FP64 cases whose ranks equal the oracle's on every interface
-FP64_EXACT = {("c2", s, e) for s in (0, 1, 2) for e in (1e-2, 1e-4, 1e-6)} | {("c4", s, 1e-2) for s in (0, 1, 2)}
+FP64_EXACT = ({("c2", s, e, True) for s in (0, 1, 2) for e in (1e-2, 1e-4, 1e-6)}
+              | {("c4", s, 1e-2, True) for s in (0, 1, 2)} | {("c2", 0, 1e-2, False)})
 
 
 def _report(rec):
@@ -102,10 +105,10 @@ def _problem(cache, workload, seed):
     return cache[key]
 
 
-@pytest.mark.parametrize("workload,seed,eps", CASES)
-def test_against_oracle_golden(problems_cache, workload, seed, eps):
-    print(f"case golden {workload} seed={seed} eps={eps:g}", flush=True)
-    g = load_golden(workload, seed, eps)
+@pytest.mark.parametrize("workload,seed,eps,scale", CASES)
+def test_against_oracle_golden(problems_cache, workload, seed, eps, scale):
+    print(f"case golden {workload} seed={seed} eps={eps:g} scale={scale}", flush=True)
+    g = load_golden(workload, seed, eps, scale)
     c = _problem(problems_cache, workload, seed)
     A = c["prob"]["A"]
     N = A.shape[0]
@@ -118,7 +121,7 @@ def test_against_oracle_golden(problems_cache, workload, seed, eps):
     it_o = g["gmres_iterations"]
     window = max(1, math.ceil(0.1 * it_o))
     for prec in (64, 32):
-        fac = P.factor_device(A, c["sym"], c["dA"], eps=eps, precision=prec)
+        fac = P.factor_device(A, c["sym"], c["dA"], eps=eps, precision=prec, scale=scale)
         worst, ndiff, nint = _rank_diff(fac, g)
         y = fac.apply(bd).cpu().numpy()[:, 0]
         dy = y[idx] - yo
@@ -129,7 +132,7 @@ def test_against_oracle_golden(problems_cache, workload, seed, eps):
         res = float(np.linalg.norm(A @ x - b) / np.linalg.norm(b))
         dx = float(np.linalg.norm(x[idx] - xo))
         xbound = 2.0 * g["inv_norm2_est"] * (res + g["gmres_relres"]) * g["b_norm"]
-        rec = dict(case=f"{workload}_s{seed}_eps{eps:g}", precision=prec, rank_max_diff=worst,
+        rec = dict(case=f"{workload}_s{seed}_eps{eps:g}{'' if scale else '_unscaled'}", precision=prec, rank_max_diff=worst,
                    rank_diffs=ndiff, interfaces=nint, apply_rel_max=rel_y_max, apply_rel_2=rel_y_2,
                    iterations=info[0]["iterations"], iterations_oracle=it_o, relres=res,
                    x_rel_2=float(dx / np.linalg.norm(xo)), x_abs_2=dx, x_bound=xbound)
@@ -138,7 +141,7 @@ def test_against_oracle_golden(problems_cache, workload, seed, eps):
         assert dx <= xbound, rec
         if prec == 64:
             assert worst <= 1, rec
-            if (workload, seed, eps) in FP64_EXACT:
+            if (workload, seed, eps, scale) in FP64_EXACT:
                 assert ndiff == 0, rec
             if ndiff == 0:
                 assert rel_y_max <= 1e-10, rec
