@@ -71,6 +71,25 @@ typedef struct {
 typedef struct spaqr_ordering spaqr_ordering;
 spaqr_status spaqr_order_grid(int dim, const int32_t sides[3], int nlevels,
                               spaqr_ordering** out);
+/* Algebraic modified nested dissection of a square sparse matrix without a
+ * grid (Section 2.3, Fig. mnd; the paper partitions such matrices with a
+ * hypergraph partitioner, here the graph of A^T A is bisected instead).
+ * Graph: i ~ j (i != j) iff some row of A holds entries in columns i and j.
+ * A node's vertex set splits by a BFS level structure of its induced
+ * subgraph (root: the smallest vertex, moved up to four times to the
+ * smallest vertex of the last level while that lengthens the structure;
+ * further components append their levels); the separator is the level
+ * m in [1, h-2] minimizing (|#below - #above|, its size, m), below going to
+ * the low child.  A separator vertex's stage-k interface is the pair of
+ * level-k ancestors of the deepest common ancestors of its neighbours' nodes
+ * on each side.  Only A's pattern is read (A->val may be NULL); rows are
+ * clustered like columns.  nlevels <= 0 selects ceil(log2(N/64)), capped at
+ * the deepest tree whose nodes above the leaves all split (>= 3 BFS levels);
+ * an explicit deeper nlevels is EINVAL.  Errors: EINVAL for a NULL or
+ * inconsistent CSR or a column index outside [0, n).  *out is
+ * library-owned (spaqr_ordering_free); the result is used like that of
+ * spaqr_order_grid. */
+spaqr_status spaqr_order_graph(const spaqr_csr* A, int nlevels, spaqr_ordering** out);
 void spaqr_ordering_free(spaqr_ordering* ord);
 int64_t spaqr_ordering_n(const spaqr_ordering* ord);
 int spaqr_ordering_levels(const spaqr_ordering* ord);

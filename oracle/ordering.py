@@ -1,4 +1,6 @@
-"""Geometric modified nested dissection (MND) on a regular grid -- oracle.
+"""Modified nested dissection (MND) -- oracle: geometric on a regular grid,
+and algebraic (the graph of A^T A) for matrices without a grid (readings
+G1-G6 further down).
 
 Follows the paper's ordering and clustering (Section 2.3): nested dissection
 on the graph of A^T A defines separators (column partition); modified ND
@@ -143,6 +145,13 @@ class Ordering:
                 keys[k, 0, sp_idx] = _anc(dlow, k)
                 keys[k, 1, sp_idx] = _anc(dhigh, k)
         self.keys = keys
+        self._build_perm()
+
+    def _build_perm(self):
+        """perm from node, level and keys; every cluster of every stage is a
+        contiguous range of it."""
+        N, keys, node, level = self.N, self.keys, self.node, self.level
+        idx = np.arange(N, dtype=np.int64)
         # perm: level desc, node asc, key_2..key_L (low, high), natural index
         sort_keys = [idx]
         for k in range(self.L, 1, -1):
@@ -203,3 +212,185 @@ class Ordering:
 
 def order_grid(dims, L):
     return Ordering(dims, L)
+
+
+# ----------------------------------------------------------------------------
+# Algebraic MND for matrices without a grid (Section 2.3).
+#
+# The paper partitions general matrices with a hypergraph partitioner on the
+# structure of A (HUND, an external library) and defines interfaces by the
+# modified ND of Fig. "mnd".  The readings here, with the graph of A^T A in
+# place of the hypergraph:
+#   G1 the graph: i ~ j (i != j) iff some row r has A_ri != 0 and A_rj != 0,
+#      the pattern of A^T A, whose ND the paper's column ordering is.
+#   G2 node X of level l < L with vertex set V_X is split by a BFS level
+#      structure of the subgraph induced on V_X: the root r starts at min(V_X);
+#      up to four times, if the BFS from u = the smallest vertex of r's last
+#      level has more levels than the BFS from r, r <- u.  The levels of r's
+#      component come first; each further component, rooted at its smallest
+#      vertex, appends its levels after them.
+#   G3 with h >= 3 levels, the separator is the level m in [1, h-2] that
+#      minimizes |#below - #above|, then |level m|, then m; low child 2X =
+#      levels < m, high child 2X+1 = levels > m.  Edges of the induced graph
+#      join levels at most one apart, so the separator cuts A^T A inside V_X.
+#      h < 3 at a node above the leaves: too many levels.
+#   G4 interfaces: for a separator vertex q of node B and each child C of B,
+#      desc_C(q) is the deepest common ancestor of the nodes of q's
+#      neighbours inside C's subtree (C if there are none);
+#      key_k(q) = (anc_k(desc_2B(q)), anc_k(desc_2B+1(q))), as in the grid
+#      version, where desc is the deepest node touched on each side.
+#   G5 perm and the clusters of every stage follow the grid version.
+#   G6 the default number of levels is ceil(log2(N/64)) (at least 1), capped
+#      at the deepest tree whose nodes above the leaves all split.
+# ----------------------------------------------------------------------------
+def ata_graph(A):
+    """Pattern of A^T A without its diagonal, as CSR (indptr, indices) with
+    sorted neighbour lists (G1)."""
+    import scipy.sparse as sp
+    P = sp.csr_matrix((np.ones(A.nnz), A.indices, A.indptr), shape=A.shape)
+    G = (P.T @ P).tocsr()
+    G.setdiag(0)
+    G.eliminate_zeros()
+    G.sort_indices()
+    return G.indptr.astype(np.int64), G.indices.astype(np.int64)
+
+
+def _bfs_levels(indptr, indices, inset, root):
+    """BFS level sets (ascending arrays) from root inside the vertex mask inset."""
+    levels = []
+    seen = {int(root)}
+    front = np.array([root], dtype=np.int64)
+    while front.size:
+        levels.append(np.sort(front))
+        nb = np.concatenate([indices[indptr[v]:indptr[v + 1]] for v in front]) if front.size else front
+        nb = np.unique(nb)
+        nb = nb[inset[nb]]
+        nb = np.array([v for v in nb if int(v) not in seen], dtype=np.int64)
+        seen.update(int(v) for v in nb)
+        front = nb
+    return levels
+
+
+def _level_structure(indptr, indices, V, N):
+    """The level structure of G2 for the sorted vertex set V."""
+    inset = np.zeros(N, dtype=bool)
+    inset[V] = True
+    r = int(V[0])
+    lev = _bfs_levels(indptr, indices, inset, r)
+    for _ in range(4):
+        u = int(lev[-1][0])
+        lu = _bfs_levels(indptr, indices, inset, u)
+        if len(lu) > len(lev):
+            r, lev = u, lu
+        else:
+            break
+    done = np.zeros(N, dtype=bool)
+    for x in lev:
+        done[x] = True
+    while True:
+        rest = V[~done[V]]
+        if rest.size == 0:
+            break
+        more = _bfs_levels(indptr, indices, inset & ~done, int(rest[0]))
+        for x in more:
+            done[x] = True
+        lev = lev + more
+    return lev
+
+
+def _split_level(sizes):
+    """G3: the separator level m in [1, h-2] minimizing (|#below - #above|,
+    |level m|, m) for level sizes `sizes` (h >= 3)."""
+    h = len(sizes)
+    best = None
+    for m in range(1, h - 1):
+        lo, hi = sum(sizes[:m]), sum(sizes[m + 1:])
+        cand = (abs(lo - hi), sizes[m], m)
+        if best is None or cand < best:
+            best = cand
+    return best[2]
+
+
+def _lca(a, b):
+    la, lb = int(a).bit_length(), int(b).bit_length()
+    a >>= max(0, la - lb)
+    b >>= max(0, lb - la)
+    while a != b:
+        a >>= 1
+        b >>= 1
+    return a
+
+
+class GraphOrdering(Ordering):
+    """Algebraic MND of a square sparse matrix (readings G1-G6)."""
+
+    def __init__(self, A, L=0):
+        import scipy.sparse as sp
+        A = sp.csr_matrix(A)
+        N = A.shape[0]
+        self.N = N
+        self.dims = (N,)
+        indptr, indices = ata_graph(A)
+        self.graph = (indptr, indices)
+        if L <= 0:
+            L = 0
+            while (64 << L) < N:
+                L += 1
+            L = max(1, L)
+            cap = True
+        else:
+            cap = False
+        node = np.ones(N, dtype=np.int64)
+        sets = {1: np.arange(N, dtype=np.int64)}
+        # (BFS root, separator level) of every split node (a record only)
+        self.splits = {}
+        depth = 1
+        while depth < L:
+            new = {}
+            ok = True
+            for X in range(1 << (depth - 1), 1 << depth):
+                V = sets[X]
+                lev = _level_structure(indptr, indices, V, N) if V.size else []
+                h = len(lev)
+                if h < 3:
+                    ok = False
+                    break
+                m = _split_level([x.size for x in lev])
+                self.splits[X] = (int(lev[0][0]), m)
+                new[2 * X] = np.sort(np.concatenate(lev[:m]))
+                new[2 * X + 1] = np.sort(np.concatenate(lev[m + 1:]))
+                node[lev[m]] = X
+            if not ok:
+                if cap:
+                    L = depth
+                    break
+                raise GridOrderingError(f"too many levels: a node of level {depth} has fewer than 3 BFS levels")
+            for X, V in new.items():
+                node[V] = X
+            sets = new
+            depth += 1
+        self.L = int(L)
+        level = _level(node)
+        self.node, self.level = node, level
+        keys = np.zeros((self.L + 1, 2, N), dtype=np.int64)
+        for q in np.nonzero(level < self.L)[0]:
+            B = int(node[q])
+            nb = node[indices[indptr[q]:indptr[q + 1]]]
+            for side in (0, 1):
+                C = 2 * B + side
+                lc = C.bit_length()
+                lv = _level(nb)
+                inside = nb[(lv >= lc) & ((nb >> np.maximum(0, lv - lc)) == C)]
+                d = C
+                if inside.size:
+                    d = int(inside[0])
+                    for x in inside[1:]:
+                        d = _lca(d, int(x))
+                for k in range(1, self.L + 1):
+                    keys[k, side, q] = d >> max(0, d.bit_length() - k)
+        self.keys = keys
+        self._build_perm()
+
+
+def order_graph(A, L=0):
+    return GraphOrdering(A, L)

@@ -107,6 +107,27 @@ def order_grid(dims, levels=0):
     return GridOrdering(dims, levels)
 
 
+class GraphOrdering(GridOrdering):
+    """Algebraic modified nested dissection of a square sparse matrix without a
+    grid (spaqr_order_graph): BFS bisection of the graph of A^T A."""
+
+    def __init__(self, A, levels=0):
+        lib = _abi.load()
+        csr, keep = _csr_struct(A)
+        h = C.c_void_p()
+        check(lib.spaqr_order_graph(C.byref(csr), int(levels), C.byref(h)), "spaqr_order_graph")
+        del keep
+        self._h = h
+        self.dims = (A.shape[0],)
+        self.n = lib.spaqr_ordering_n(h)
+        self.levels = lib.spaqr_ordering_levels(h)
+        _abi.track("ordering", self)
+
+
+def order_graph(A, levels=0):
+    return GraphOrdering(A, levels)
+
+
 class Symbolic:
     """Host-only symbolic analysis (spaqr_analyze)."""
 

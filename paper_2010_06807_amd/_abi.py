@@ -70,6 +70,7 @@ SIGNATURES = {
     "spaqr_status_string": (C.c_char_p, [C.c_int]),
     "spaqr_last_error": (C.c_char_p, []),
     "spaqr_order_grid": (C.c_int, [C.c_int, _I32P, C.c_int, C.POINTER(_P)]),
+    "spaqr_order_graph": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(_P)]),
     "spaqr_ordering_free": (None, [_P]),
     "spaqr_ordering_n": (C.c_int64, [_P]),
     "spaqr_ordering_levels": (C.c_int, [_P]),

@@ -69,6 +69,19 @@ spaqr_status spaqr_order_grid(int dim, const int32_t sides[3], int nlevels, spaq
   });
 }
 
+spaqr_status spaqr_order_graph(const spaqr_csr* A, int nlevels, spaqr_ordering** out) {
+  return guarded([&]() -> spaqr_status {
+    SPAQR_REQUIRE(A && out && A->rowptr && A->col, SPAQR_EINVAL, "NULL argument");
+    SPAQR_REQUIRE(A->n >= 1 && A->rowptr[0] == 0 && A->rowptr[A->n] == A->nnz, SPAQR_EINVAL,
+                  "graph ordering: bad CSR row pointers");
+    std::unique_ptr<Ordering> o(build_graph_ordering(A->n, A->rowptr, A->col, nlevels));
+    auto* h = new spaqr_ordering();
+    h->o = std::move(*o);
+    *out = h;
+    return SPAQR_OK;
+  });
+}
+
 void spaqr_ordering_free(spaqr_ordering* o) { delete o; }
 
 int64_t spaqr_ordering_n(const spaqr_ordering* o) { return o ? o->o.n : -1; }

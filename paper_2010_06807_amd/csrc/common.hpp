@@ -55,6 +55,7 @@ struct Ordering {
 };
 
 Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels);
+Ordering* build_graph_ordering(int64_t n, const int64_t* rowptr, const int32_t* col, int nlevels);
 
 // Process-wide kernel dispatch thresholds (spaqr_tuning); read when a stage
 // is planned and launched.

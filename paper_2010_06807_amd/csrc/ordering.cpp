@@ -49,6 +49,8 @@ struct Finest {
   int64_t node, dl, dh;
 };
 
+void finish_ordering(Ordering* o, const std::vector<Finest>& fin);
+
 }  // namespace
 
 Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
@@ -153,6 +155,18 @@ Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
     fin[i] = f;
   }
 
+  finish_ordering(o, fin);
+  guard.release();
+  return o;
+}
+
+namespace {
+
+// perm, the clusters of every stage and the merge parents from each point's
+// (level, node, dl, dh); o->L and o->n are set
+void finish_ordering(Ordering* o, const std::vector<Finest>& fin) {
+  const int L = o->L;
+  const int64_t n = o->n;
   // ---- distinct finest clusters: stable radix sort of the packed key
   // (node, dl, dh), L bits each, keeps points in natural order inside a run
   SPAQR_REQUIRE(L <= 21, SPAQR_EINVAL, "at most 21 levels");
@@ -252,6 +266,231 @@ Ordering* build_grid_ordering(int dim, const int32_t sides[3], int nlevels) {
     }
   }
   o->stages[1].parent.assign(o->stages[1].count(), -1);
+}
+
+}  // namespace
+
+
+// ---------------------------------------------------------------------------
+// Algebraic modified nested dissection of a square sparse matrix (Section 2.3,
+// Fig. mnd), for inputs without a grid.  The paper partitions such matrices
+// with a hypergraph partitioner on A; here the graph of A^T A (whose ND the
+// column ordering is) is bisected by BFS level structures:
+//
+//   * graph: i ~ j (i != j) iff some row holds entries in columns i and j;
+//   * node X (vertex set V_X) splits by the BFS level structure of the
+//     subgraph induced on V_X: the root starts at min(V_X) and moves, up to
+//     four times, to the smallest vertex of its last level while that BFS
+//     has more levels; the root's component gives the first levels, each
+//     further component (rooted at its smallest vertex) appends its levels;
+//   * with h >= 3 levels the separator is the level m in [1, h-2] minimizing
+//     (|#below - #above|, |level m|, m); below goes to 2X, above to 2X+1.
+//     Induced edges join levels at most one apart, so the separator cuts
+//     A^T A inside V_X;
+//   * a separator vertex q of node B touches, on each side C of B, the nodes
+//     of its neighbours inside C's subtree; desc_C(q) is their deepest common
+//     ancestor (C when there are none), and the stage-k interface of q is
+//     (anc_k(desc_2B), anc_k(desc_2B+1)), as for grids;
+//   * nlevels <= 0: ceil(log2(n/64)) (at least 1), capped at the deepest tree
+//     whose nodes above the leaves all split.
+namespace {
+
+struct Graph {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> adj;  // sorted neighbour lists
+};
+
+Graph ata_graph(int64_t n, const int64_t* rowptr, const int32_t* col) {
+  // columns' rows (the transpose's pattern)
+  std::vector<int64_t> cptr(n + 1, 0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t) cptr[col[t] + 1]++;
+  for (int64_t c = 0; c < n; ++c) cptr[c + 1] += cptr[c];
+  std::vector<int32_t> crow(cptr[n]);
+  {
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t) crow[fill[col[t]]++] = (int32_t)r;
+  }
+  Graph g;
+  g.ptr.assign(n + 1, 0);
+  std::vector<int64_t> mark(n, -1);
+  std::vector<int32_t> nb;
+  for (int64_t i = 0; i < n; ++i) {
+    nb.clear();
+    for (int64_t u = cptr[i]; u < cptr[i + 1]; ++u) {
+      const int32_t r = crow[u];
+      for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t) {
+        const int32_t j = col[t];
+        if (j != i && mark[j] != i) {
+          mark[j] = i;
+          nb.push_back(j);
+        }
+      }
+    }
+    std::sort(nb.begin(), nb.end());
+    g.adj.insert(g.adj.end(), nb.begin(), nb.end());
+    g.ptr[i + 1] = (int64_t)g.adj.size();
+  }
+  return g;
+}
+
+// BFS level sets (each sorted) from root over the vertices v with
+// cur[v] == X not yet marked with stamp; marks what it visits
+void bfs_levels(const Graph& g, const std::vector<int64_t>& cur, int64_t X, int32_t root, std::vector<int64_t>& seen,
+                int64_t stamp, std::vector<std::vector<int32_t>>& levels) {
+  std::vector<int32_t> front{root};
+  seen[root] = stamp;
+  while (!front.empty()) {
+    std::sort(front.begin(), front.end());
+    levels.push_back(front);
+    std::vector<int32_t> next;
+    for (int32_t v : front)
+      for (int64_t t = g.ptr[v]; t < g.ptr[v + 1]; ++t) {
+        const int32_t w = g.adj[t];
+        if (cur[w] == X && seen[w] != stamp) {
+          seen[w] = stamp;
+          next.push_back(w);
+        }
+      }
+    front.swap(next);
+  }
+}
+
+int64_t lca(int64_t a, int64_t b) {
+  const int la = bit_length((uint64_t)a), lb = bit_length((uint64_t)b);
+  if (la > lb) a >>= (la - lb);
+  if (lb > la) b >>= (lb - la);
+  while (a != b) {
+    a >>= 1;
+    b >>= 1;
+  }
+  return a;
+}
+
+}  // namespace
+
+Ordering* build_graph_ordering(int64_t n, const int64_t* rowptr, const int32_t* col, int nlevels) {
+  SPAQR_REQUIRE(n >= 1 && rowptr && col, SPAQR_EINVAL, "graph ordering: empty or NULL matrix");
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t t = rowptr[r]; t < rowptr[r + 1]; ++t)
+      SPAQR_REQUIRE(col[t] >= 0 && col[t] < n, SPAQR_EINVAL, "graph ordering: column index out of range");
+  const Graph g = ata_graph(n, rowptr, col);
+  int L = nlevels;
+  const bool cap = L <= 0;
+  if (cap) {
+    L = 0;
+    while ((int64_t(64) << L) < n) ++L;
+    L = std::max(1, L);
+  }
+  SPAQR_REQUIRE(L >= 1 && L <= 21, SPAQR_EINVAL, "levels out of range");
+  std::vector<int64_t> cur(n, 1);  // node of each vertex so far
+  std::vector<int64_t> seen(n, -1);
+  int64_t stamp = 0;
+  // vertex sets of the nodes of the current depth, ascending
+  std::vector<std::vector<int32_t>> sets(1);
+  sets[0].resize(n);
+  std::iota(sets[0].begin(), sets[0].end(), 0);
+  int depth = 1;
+  while (depth < L) {
+    const int64_t first = int64_t(1) << (depth - 1);
+    std::vector<std::vector<int32_t>> next(2 * sets.size());
+    std::vector<std::pair<int64_t, std::vector<int32_t>>> seps;
+    bool ok = true;
+    for (size_t xi = 0; xi < sets.size() && ok; ++xi) {
+      const int64_t X = first + (int64_t)xi;
+      const std::vector<int32_t>& V = sets[xi];
+      if (V.empty()) {
+        ok = false;
+        break;
+      }
+      // pseudo-peripheral root of the component of min(V)
+      std::vector<std::vector<int32_t>> lev;
+      int32_t r = V[0];
+      bfs_levels(g, cur, X, r, seen, ++stamp, lev);
+      for (int it = 0; it < 4; ++it) {
+        const int32_t u = lev.back()[0];
+        std::vector<std::vector<int32_t>> lu;
+        bfs_levels(g, cur, X, u, seen, ++stamp, lu);
+        if (lu.size() > lev.size()) {
+          r = u;
+          lev.swap(lu);
+        } else {
+          break;
+        }
+      }
+      // mark the chosen structure's vertices, then the other components
+      const int64_t st = ++stamp;
+      for (const auto& lv : lev)
+        for (int32_t v : lv) seen[v] = st;
+      for (int32_t v : V)
+        if (seen[v] != st) bfs_levels(g, cur, X, v, seen, st, lev);
+      const int h = (int)lev.size();
+      if (h < 3) {
+        ok = false;
+        break;
+      }
+      std::vector<int64_t> below(h + 1, 0);
+      for (int q = 0; q < h; ++q) below[q + 1] = below[q] + (int64_t)lev[q].size();
+      int m = 1;
+      int64_t bi = -1, bs = 0;
+      for (int q = 1; q <= h - 2; ++q) {
+        const int64_t lo = below[q], hi = below[h] - below[q + 1];
+        const int64_t im = lo > hi ? lo - hi : hi - lo, sz = (int64_t)lev[q].size();
+        if (bi < 0 || im < bi || (im == bi && sz < bs)) {
+          bi = im;
+          bs = sz;
+          m = q;
+        }
+      }
+      std::vector<int32_t>& lowv = next[2 * xi];
+      std::vector<int32_t>& highv = next[2 * xi + 1];
+      for (int q = 0; q < m; ++q) lowv.insert(lowv.end(), lev[q].begin(), lev[q].end());
+      for (int q = m + 1; q < h; ++q) highv.insert(highv.end(), lev[q].begin(), lev[q].end());
+      std::sort(lowv.begin(), lowv.end());
+      std::sort(highv.begin(), highv.end());
+    }
+    if (!ok) {
+      SPAQR_REQUIRE(cap, SPAQR_EINVAL, "too many levels: a node above the leaves has fewer than 3 BFS levels");
+      L = depth;
+      break;
+    }
+    for (size_t xi = 0; xi < sets.size(); ++xi) {
+      const int64_t X = first + (int64_t)xi;
+      for (int32_t v : next[2 * xi]) cur[v] = 2 * X;
+      for (int32_t v : next[2 * xi + 1]) cur[v] = 2 * X + 1;
+    }
+    sets.swap(next);
+    ++depth;
+  }
+
+  auto* o = new Ordering();
+  std::unique_ptr<Ordering> guard(o);
+  o->dim = 0;
+  o->L = L;
+  o->n = n;
+  std::vector<Finest> fin(n);
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t B = cur[q];
+    const int lv = bit_length((uint64_t)B);
+    Finest f{lv, B, 0, 0};
+    if (lv < L) {
+      for (int side = 0; side < 2; ++side) {
+        const int64_t C = 2 * B + side;
+        const int lc = lv + 1;
+        int64_t d = -1;
+        for (int64_t t = g.ptr[q]; t < g.ptr[q + 1]; ++t) {
+          const int64_t w = cur[g.adj[t]];
+          const int lw = bit_length((uint64_t)w);
+          if (lw < lc || (w >> (lw - lc)) != C) continue;
+          d = d < 0 ? w : lca(d, w);
+        }
+        (side == 0 ? f.dl : f.dh) = d < 0 ? C : d;
+      }
+    }
+    fin[q] = f;
+  }
+  finish_ordering(o, fin);
   guard.release();
   return o;
 }

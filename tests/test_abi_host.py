@@ -107,3 +107,55 @@ def test_invalid_inputs_rejected():
         P.analyze(A, o2)            # size mismatch
     lib = _abi.load()
     assert lib.spaqr_status_string(-3).decode().startswith("exactly singular")
+
+
+# ---------------------------------------------------------------- graph MND
+from problems.unstructured import delaunay_convdiff, permuted  # noqa: E402
+from oracle.ordering import order_graph as oracle_order_graph  # noqa: E402
+
+GRAPH_MATS = {
+    "delaunay3000": lambda: delaunay_convdiff(3000, seed=3),
+    "delaunay20000": lambda: delaunay_convdiff(20000, seed=4),
+    "perm48": lambda: permuted(convdiff((48, 48), (5.0, -3.0)), seed=5)[0],
+    "grid3d": lambda: convdiff((10, 9, 8), (2.0, 1.0, 1.0)),
+}
+
+
+@pytest.mark.parametrize("name,L", [("delaunay3000", 0), ("delaunay3000", 4), ("delaunay20000", 0),
+                                    ("perm48", 0), ("grid3d", 0)])
+def test_graph_ordering_bit_exact(name, L):
+    A = GRAPH_MATS[name]()
+    o = P.order_graph(A, L)
+    ob = oracle_order_graph(A, L)
+    assert o.levels == ob.L and o.n == ob.N
+    assert np.array_equal(o.perm(), ob.perm)
+    for k in range(ob.L, 0, -1):
+        for a, b in zip(o.clusters(k), ob.stage_clusters(k)):
+            assert np.array_equal(a, b)
+        if k > 1:
+            assert np.array_equal(o.merge_parents(k), ob.merge_parents(k))
+
+
+@pytest.mark.parametrize("name,eps", [("delaunay3000", 1e-2), ("perm48", 1e-3)])
+def test_graph_symbolic_bit_exact(name, eps):
+    A = GRAPH_MATS[name]()
+    o = P.order_graph(A)
+    ob = oracle_order_graph(A)
+    sym = P.analyze(A, o)
+    F = oracle_spaqr.factor(A, ob, eps)
+    for k in range(ob.L, 0, -1):
+        rec = F.stages[k]
+        assert sym.pattern(k) == [tuple(x) for x in rec["pattern_in"]]
+        assert sym.pattern(k, post=True) == [tuple(x) for x in rec["pattern_post"]]
+        want = {s: (list(a), list(b), c) for s, (a, b, c) in rec["fronts"].items()}
+        assert sym.fronts(k) == want
+        assert sym.iface_colours(k) == (rec["iface_colour"] if rec["sparsified"] else {})
+
+
+def test_graph_ordering_rejects_bad_input():
+    import scipy.sparse as sp
+    with pytest.raises(P.SpaqrError):
+        P.order_graph(convdiff((6, 6), (1.0, 1.0)), 5)   # too many levels for 36 unknowns
+    B = sp.csr_matrix((np.ones(2), np.array([0, 1]), np.array([0, 1, 2, 2])), shape=(3, 3))
+    with pytest.raises(P.SpaqrError):
+        P.order_graph(B, 3)

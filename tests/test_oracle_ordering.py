@@ -116,3 +116,171 @@ def test_leaf_sizes_c4_shape():
     st, en, nd, lv = o.stage_clusters(14)
     leaf = (en - st)[lv == 14]
     assert leaf.min() == 84 and leaf.max() == 105 and leaf.size == 8192
+
+
+# ----------------------------------------------------------------------------
+# algebraic MND (readings G1-G6 in oracle/ordering.py)
+from problems.unstructured import delaunay_convdiff, permuted  # noqa: E402
+from oracle.ordering import order_graph  # noqa: E402
+
+GRAPH_CASES = {
+    "delaunay1500": lambda: delaunay_convdiff(1500, seed=1),
+    "perm24": lambda: permuted(convdiff((24, 24), (5.0, 5.0)), seed=2)[0],
+    "grid3d": lambda: convdiff((8, 8, 8), (3.0, 2.0, 1.0)),
+}
+
+
+def _dense_ata(A):
+    P = (A.toarray() != 0).astype(np.int64)
+    return (P.T @ P) != 0
+
+
+@pytest.mark.parametrize("name", sorted(GRAPH_CASES))
+def test_graph_separators_cut_ata(name):
+    """No entry of A^T A (a dense product of the pattern) couples the two
+    children's subtrees of any node."""
+    A = GRAPH_CASES[name]()
+    o = order_graph(A)
+    G = _dense_ata(A)
+    assert o.L >= 3
+    for node in range(1, 1 << (o.L - 1)):
+        lo = np.nonzero(_descendants(o, 2 * node))[0]
+        hi = np.nonzero(_descendants(o, 2 * node + 1))[0]
+        assert lo.size and hi.size
+        assert not G[np.ix_(lo, hi)].any()
+
+
+@pytest.mark.parametrize("name", sorted(GRAPH_CASES))
+def test_graph_split_rule_against_csgraph(name):
+    """G2/G3 recomputed from scipy's unweighted shortest paths on the induced
+    subgraph: the pseudo-peripheral root, the level structure, the chosen
+    separator level and both children."""
+    from scipy.sparse.csgraph import shortest_path
+    A = GRAPH_CASES[name]()
+    o = order_graph(A)
+    G = sp.csr_matrix(_dense_ata(A).astype(np.float64))
+    G.setdiag(0)
+    G.eliminate_zeros()
+    for X, (root, m) in o.splits.items():
+        if X.bit_length() >= o.L:
+            continue
+        V = np.nonzero(_descendants(o, X))[0]
+        S = G[V][:, V]
+        D = shortest_path(S, unweighted=True, directed=False)
+
+        def depth_of(i):
+            d = D[i]
+            return int(d[np.isfinite(d)].max())
+
+        r = 0  # index into V of min(V)
+        for _ in range(4):
+            d = D[r]
+            far = np.nonzero(d == depth_of(r))[0]
+            u = int(far.min())
+            if depth_of(u) > depth_of(r):
+                r = u
+            else:
+                break
+        assert V[r] == root
+        # levels: r's component, then the other components by smallest vertex
+        lev = np.full(V.size, -1, dtype=np.int64)
+        base = 0
+        seed = r
+        while True:
+            d = D[seed]
+            comp = np.isfinite(d)
+            lev[comp] = base + d[comp].astype(np.int64)
+            base = int(lev.max()) + 1
+            left = np.nonzero(lev < 0)[0]
+            if left.size == 0:
+                break
+            seed = int(left.min())
+        h = base
+        sizes = np.bincount(lev, minlength=h)
+        best = min((abs(int(sizes[:q].sum()) - int(sizes[q + 1:].sum())), int(sizes[q]), q) for q in range(1, h - 1))
+        assert best[2] == m
+        assert np.array_equal(np.sort(V[lev == m]), np.nonzero(o.node == X)[0])
+        assert np.array_equal(np.sort(V[lev < m]), np.nonzero(_descendants(o, 2 * X))[0])
+
+
+@pytest.mark.parametrize("name", sorted(GRAPH_CASES))
+def test_graph_interfaces_brute_force(name):
+    """G4: desc_C(q) is the deepest tree node that is an ancestor-or-self of
+    the node of every neighbour of q inside C's subtree (C if none), found by
+    trying every node id."""
+    A = GRAPH_CASES[name]()
+    o = order_graph(A)
+    G = _dense_ata(A)
+    np.fill_diagonal(G, False)
+    L = o.L
+    ids = np.arange(1, 1 << L)
+    for q in np.nonzero(o.level < L)[0]:
+        B = int(o.node[q])
+        for side in (0, 1):
+            C = 2 * B + side
+            nb = o.node[np.nonzero(G[q])[0]]
+            inside = [int(x) for x in nb if (int(x) >> max(0, int(x).bit_length() - C.bit_length())) == C
+                      and int(x).bit_length() >= C.bit_length()]
+            best = C
+            for D in ids:
+                D = int(D)
+                if D.bit_length() <= best.bit_length():
+                    continue
+                if all((x >> max(0, x.bit_length() - D.bit_length())) == D and x.bit_length() >= D.bit_length()
+                       for x in inside) and inside:
+                    best = D
+            assert o.keys[L, side, q] == best, (q, side)
+
+
+@pytest.mark.parametrize("name", sorted(GRAPH_CASES))
+def test_graph_partitions_nest(name):
+    A = GRAPH_CASES[name]()
+    o = order_graph(A)
+    assert np.array_equal(np.sort(o.perm), np.arange(o.N))
+    for k in range(o.L, 0, -1):
+        st, en, nd, lv = o.stage_clusters(k)
+        assert np.all(en > st) and np.all(st[1:] == en[:-1]) and en[-1] == o.N
+        assert (en - st).sum() == int((o.level <= k).sum())
+        assert np.array_equal(np.repeat(nd, en - st), o.node[o.perm[st[0]:]])
+        if k > 1:
+            par = o.merge_parents(k)
+            st2, en2, _, _ = o.stage_clusters(k - 1)
+            for c in range(st.size):
+                if lv[c] < k:
+                    assert st2[par[c]] <= st[c] and en[c] <= en2[par[c]]
+
+
+@pytest.mark.parametrize("name", ["delaunay1500", "perm24"])
+def test_graph_ordering_exact_at_eps0(name):
+    """The ordering is a valid nested dissection for the method: at eps = 0
+    spaQR with it solves A exactly (against a dense solve) and every update
+    skipped by reading R4 is zero."""
+    from oracle import spaqr
+    from problems import make_rhs
+    A = GRAPH_CASES[name]()
+    o = order_graph(A)
+    F = spaqr.factor(A, o, 0.0, check_skipped=True)
+    b = make_rhs(A.shape[0], 1, seed=4)[:, 0]
+    x = spaqr.apply(F, b)
+    xd = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    assert F.max_skipped_update <= 1e-13
+
+
+def test_graph_default_levels():
+    A = delaunay_convdiff(5000, seed=0)
+    o = order_graph(A)
+    assert o.L == 7  # ceil(log2(5000 / 64))
+    with pytest.raises(GridOrderingError):
+        order_graph(convdiff((6, 6), (1.0, 1.0)), 5)
+
+
+def test_graph_split_level_by_hand():
+    """G3 on level sizes worked out by hand: balance first, then the smaller
+    separator, then the lower level."""
+    from oracle.ordering import _split_level
+    assert _split_level([1, 2, 1, 3, 1]) == 2   # imbalances 4, 1, 3
+    assert _split_level([1, 3, 1, 2]) == 2      # imbalances 2, 2: separator 1 beats 3
+    assert _split_level([1, 1, 3, 2, 1]) == 2   # imbalances 5, 1, 3
+    assert _split_level([1, 1, 1, 1]) == 1      # a tie of equal separators: the lower level
+    assert _split_level([1, 5, 1]) == 1         # a single choice
