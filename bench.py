@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=3, help="steps of the plain FP64 path (0: skip)")
     ap.add_argument("--unscaled-steps", type=int, default=3,
                     help="steps of the sparsification without scaling, Section 2.5 (0: skip)")
+    ap.add_argument("--graph-points", type=int, default=65536,
+                    help="points of the unstructured leg (algebraic MND of a Delaunay mesh; 0: skip)")
+    ap.add_argument("--graph-steps", type=int, default=3)
     ap.add_argument("--unscaled-workload", default="c2",
                     help="workload of that leg (default c2: on c4 its FGMRES does not reach 1e-10 in 1000 steps)")
     ap.add_argument("--batch-workload", default="c2",
@@ -532,6 +535,51 @@ def main():
                                         "avg_launch_us": 1e3 * qu["total_ms"] / max(1, qu["launches"]),
                                         "flops_per_step": qu["flops"] / args.unscaled_steps}}
 
+    graph = None
+    if args.graph_points > 0 and args.graph_steps > 0:
+        # a matrix without a grid: convection-diffusion on a Delaunay mesh,
+        # ordered by the algebraic MND (ordering and analysis timed apart)
+        from problems.unstructured import delaunay_convdiff
+        log(f"unstructured leg: Delaunay mesh of {args.graph_points} points")
+        gA = [delaunay_convdiff(args.graph_points, seed=i) for i in range(min(S, 1))]
+        gN = gA[0].shape[0]
+        t0 = time.perf_counter()
+        gord = P.order_graph(gA[0])
+        t1 = time.perf_counter()
+        gsym = P.analyze(gA[0], gord)
+        t2 = time.perf_counter()
+        gdA = P.DeviceCSR(gA[0], dev)
+        gb = torch.from_numpy(make_rhs(gN, 1, seed=0)).to(dev)
+
+        def gstep():
+            s0 = time.perf_counter()
+            fac = P.factor_device(gA[0], gsym, gdA, eps=args.eps, precision=32)
+            s1 = time.perf_counter()
+            x, info = fac.solve(gb, tol=args.tol)
+            torch.cuda.synchronize()
+            return info[0], s1 - s0, time.perf_counter() - s1
+
+        gstep()
+        torch.cuda.synchronize()
+        gf, gs, git, gres = [], [], [], []
+        t3 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            info, tf, ts = gstep()
+            gf.append(tf)
+            gs.append(ts)
+            git.append(info["iterations"])
+            gres.append(info["relres"])
+        dtg = time.perf_counter() - t3
+        log(f"unstructured: {1e3 * dtg / args.graph_steps:.2f} ms/step")
+        graph = {"workload": f"convection-diffusion on the Delaunay mesh of {args.graph_points} uniform random "
+                             f"points (seed 0), eps={args.eps}, algebraic MND ({gord.levels} levels), FP32 factors + "
+                             f"FP64 FGMRES to {args.tol}",
+                 "value": gN * args.graph_steps / dtg, "unit": "unknowns/s",
+                 "ms_per_step": 1e3 * dtg / args.graph_steps,
+                 "ms_factor": 1e3 * float(np.mean(gf)), "ms_solve": 1e3 * float(np.mean(gs)),
+                 "gmres_iterations": max(git), "relres": max(gres),
+                 "ms_ordering": 1e3 * (t1 - t0), "ms_analysis": 1e3 * (t2 - t1), "nnz": int(gA[0].nnz)}
+
     bound = KERNEL_BOUND[kern]
     achieved, peak, unit = rate(bound, prof)
     nsteps = args.steps + args.warmup
@@ -575,6 +623,7 @@ def main():
         "gmres_iterations": max(r32["its"]), "relres": max(max(r32["res"]), res_host),
         "fp64_plain": plain64,
         "unscaled": unscaled,
+        "unstructured": graph,
         "factor": {"ms_factor": st["ms_factor"], "factor_bytes": st["factor_bytes"],
                    "top_separator": st["top_separator"], "flops_sparsify": st["flops_sparsify"]},
         "roofline": roof,
