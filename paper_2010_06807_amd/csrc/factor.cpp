@@ -159,6 +159,11 @@ struct ZeroOp {
   int64_t bytes;
 };
 
+template <typename X>
+void append(std::vector<X>& dst, const std::vector<X>& src) {
+  dst.insert(dst.end(), src.begin(), src.end());
+}
+
 // One stage of one factorization as host-side launch lists.  Every device
 // pointer in them is absolute, so the lists of several factorizations (each
 // at its own stage) concatenate into one launch per phase.
@@ -166,7 +171,8 @@ template <typename T>
 struct StagePlan {
   std::vector<ZeroOp> zero;  // runs first
   struct FrontColour {
-    std::vector<CopyTile<T>> gather, scatter;
+    // copy tiles in chunks (planned in parallel), launched as one list
+    std::vector<std::vector<CopyTile<T>>> gather, scatter;
     std::vector<QRDesc<T>> qr;
     // fronts with many trailing columns or rows: pivot block factored alone,
     // trailing columns updated slice by slice
@@ -207,7 +213,7 @@ struct StagePlan {
 template <typename T>
 struct MergePlan {
   std::vector<ZeroOp> zero;
-  std::vector<CopyTile<T>> tiles;
+  std::vector<std::vector<CopyTile<T>>> tiles;  // in chunks (planned in parallel), launched as one list
 };
 
 // A graph of the launches fn(stream) issues, captured on a private stream of
@@ -310,6 +316,8 @@ class Engine final : public EngineBase {
   int readback_ints() const { return (int)S_.st[k_].nclu + 2; }
   void readback_ops(std::vector<IntCopy>& ops, int32_t base) const;
   void readback_to(const int* host) { rb_ = host; }
+  // host threads the planning of this factorization may use (null: none)
+  void set_host_pool(HostPool* p) { inner_pool_ = p; }
   // after the stream synchronized: sizes and accounting of stage k_, the
   // merge to stage k_ - 1 as launch lists, then k_ <- k_ - 1
   void finish(MergePlan<T>& mp);
@@ -338,6 +346,7 @@ class Engine final : public EngineBase {
   int* d_zcol_ = nullptr;  // set by the device column-norm kernel for a zero column
   int* d_flag_ = nullptr;  // zero R_ss diagonal in a front of the current stage
   int* d_rank_ = nullptr;  // current cluster sizes of the current stage
+  HostPool* inner_pool_ = nullptr;  // threads for planning this factorization alone (batch of one)
   // interfaces of the current stage: index by cluster, offsets and buffers
   struct IfaceBufs {
     std::vector<int32_t> fidx;
@@ -508,6 +517,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
   P.zero.push_back({d_flag_, (int64_t)sizeof(int)});
 
   // ------------------------------------------------------------ fronts
+  std::unique_ptr<HostScope> hsub(new HostScope("host_pf_sizes"));
   const int64_t nf = (int64_t)ss.fronts.size();
   std::vector<int32_t> fm(nf), fn(nf), fnc(nf), fld(nf);
   std::vector<int64_t> ws_off(nf + 1, 0), vr_off(nf + 1, 0), rsj_off(nf + 1, 0), tau_off(nf + 1, 0);
@@ -559,6 +569,7 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
   for (int64_t f = 0; f < nf; ++f) tp_off[f + 1] = tp_off[f] + (int64_t)((fn[f] + jbf - 1) / jbf) * jbf * jbf;
   T* TPF = persist_.alloc_n<T>(std::max<int64_t>(1, tp_off[nf]), s_);
   ap.jb = jbf;
+  hsub.reset(new HostScope("host_pf_tiles"));
   for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
     typename StagePlan<T>::FrontColour fc;
     // slice width of this colour's split fronts
@@ -574,84 +585,112 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         fc.trail_max_m = mm;
       }
     }
-    {
+    // the colour's fronts in chunks planned in parallel (each chunk keeps
+    // its own copy tiles; the other lists are joined in order, so the
+    // descriptors are those of the sequential loop)
+    struct Chunk {
+      std::vector<CopyTile<T>> gather, scatter;
+      std::vector<QRDesc<T>> qr;
+      std::vector<TrailDesc<T>> trail;
+      std::vector<WYBlock<T>> wyb;
+      std::vector<WYTile<T>> wyt;
+      int max_m = 1;
+      double flops = 0.0, bytes = 0.0;
+    };
+    const int32_t o0 = ss.front_colour_ptr[c], o1 = ss.front_colour_ptr[c + 1];
+    const int nfc = o1 - o0;
+    const int nch = inner_pool_ && nfc >= 256 ? std::min(inner_pool_->size() + 1, nfc / 128) : 1;
+    std::vector<Chunk> chunks(nch);
+    const int trail_cw = fc.trail_cw;
+    auto plan_chunk = [&](int q) {
+      const int32_t ca = o0 + (int32_t)((int64_t)nfc * q / nch), cb = o0 + (int32_t)((int64_t)nfc * (q + 1) / nch);
+      Chunk& C = chunks[q];
       size_t np = 0;
-      for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi)
-        np += ss.fronts[ss.front_order[oi]].blk.size();
-      fc.gather.reserve(np);
-      fc.scatter.reserve(np);
-    }
-    for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
-      const int32_t f = ss.front_order[oi];
-      const FrontSym& F = ss.fronts[f];
-      T* Wf = W + ws_off[f];
-      const int32_t nc = fnc[f], n = fn[f], ldw = fld[f];
-      const size_t nr = 1 + F.n1.size(), ncl = 1 + F.cols.size();
-      int ro = 0;
-      for (size_t a = 0; a < nr; ++a) {
-        int co = 0;
-        const int32_t i = a == 0 ? F.cluster : F.n1[a - 1];
-        const int64_t* brow = F.blk.data() + a * ncl;
-        for (size_t b = 0; b < ncl; ++b) {
-          const int32_t j = b == 0 ? F.cluster : F.cols[b - 1];
-          if (size_[i] > 0 && size_[j] > 0) {
-            T* blkp = brow[b] < 0 ? nullptr : pool_ + boff_[brow[b]];
-            fc.gather.push_back({blkp, Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw});
-            if (a > 0 && b > 0) {
-              SPAQR_REQUIRE(blkp != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
-              fc.scatter.push_back({Wf + (int64_t)ro * ldw + co, blkp, size_[i], size_[j], ldw, size_[j]});
+      for (int32_t oi = ca; oi < cb; ++oi) np += ss.fronts[ss.front_order[oi]].blk.size();
+      C.gather.reserve(np);
+      C.scatter.reserve(np);
+      for (int32_t oi = ca; oi < cb; ++oi) {
+        const int32_t f = ss.front_order[oi];
+        const FrontSym& F = ss.fronts[f];
+        T* Wf = W + ws_off[f];
+        const int32_t nc = fnc[f], n = fn[f], ldw = fld[f];
+        const size_t nr = 1 + F.n1.size(), ncl = 1 + F.cols.size();
+        int ro = 0;
+        for (size_t a = 0; a < nr; ++a) {
+          int co = 0;
+          const int32_t i = a == 0 ? F.cluster : F.n1[a - 1];
+          const int64_t* brow = F.blk.data() + a * ncl;
+          for (size_t b = 0; b < ncl; ++b) {
+            const int32_t j = b == 0 ? F.cluster : F.cols[b - 1];
+            if (size_[i] > 0 && size_[j] > 0) {
+              T* blkp = brow[b] < 0 ? nullptr : pool_ + boff_[brow[b]];
+              C.gather.push_back({blkp, Wf + (int64_t)ro * ldw + co, size_[i], size_[j], size_[j], ldw});
+              if (a > 0 && b > 0) {
+                SPAQR_REQUIRE(blkp != nullptr, SPAQR_EINVAL, "fill block missing from the stage pattern");
+                C.scatter.push_back({Wf + (int64_t)ro * ldw + co, blkp, size_[i], size_[j], ldw, size_[j]});
+              }
             }
+            co += size_[j];
           }
-          co += size_[j];
+          ro += size_[i];
         }
-        ro += size_[i];
-      }
-      if (n > 0) {
-        const bool split = fc.trail_cw > 0 && (fm[f] > tuning().split_rows || nc - n >= tuning().split_cols);
-        fc.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, split ? n : nc, ldw});
-        if (split && mfma) {
-          T* tb = TB + tb_off[f];
-          for (int j0 = 0; j0 < n; j0 += kWYBlock)
-            fc.wyb.push_back({Wf, TAU + tau_off[f], tb + (int64_t)(j0 / kWYBlock) * kWYBlock * kWYBlock, fm[f], n, ldw, j0});
-          for (int c0 = n; c0 < nc; c0 += kWYBlock)
-            fc.wyt.push_back({Wf, tb, Wf, nullptr, fm[f], n, ldw, c0, std::min(kWYBlock, nc - c0), ldw});
-        } else if (split) {
-          for (int c0 = n; c0 < nc; c0 += fc.trail_cw)
-            fc.trail.push_back({Wf, TPF + tp_off[f], Wf, nullptr, fm[f], n, ldw, c0, std::min(fc.trail_cw, nc - c0), ldw});
+        if (n > 0) {
+          const bool split = trail_cw > 0 && (fm[f] > tuning().split_rows || nc - n >= tuning().split_cols);
+          C.qr.push_back({Wf, TAU + tau_off[f], TPF + tp_off[f], d_flag_, fm[f], n, split ? n : nc, ldw});
+          if (split && mfma) {
+            T* tb = TB + tb_off[f];
+            for (int j0 = 0; j0 < n; j0 += kWYBlock)
+              C.wyb.push_back({Wf, TAU + tau_off[f], tb + (int64_t)(j0 / kWYBlock) * kWYBlock * kWYBlock, fm[f], n, ldw,
+                               j0});
+            for (int c0 = n; c0 < nc; c0 += kWYBlock)
+              C.wyt.push_back({Wf, tb, Wf, nullptr, fm[f], n, ldw, c0, std::min(kWYBlock, nc - c0), ldw});
+          } else if (split) {
+            for (int c0 = n; c0 < nc; c0 += trail_cw)
+              C.trail.push_back({Wf, TPF + tp_off[f], Wf, nullptr, fm[f], n, ldw, c0, std::min(trail_cw, nc - c0), ldw});
+          }
+          C.max_m = std::max(C.max_m, fm[f]);
+          const double mm = fm[f], nn = n, kk = nc - n;
+          C.flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
+          C.bytes += 2.0 * mm * nc * sizeof(T);
         }
-        fc.max_m = std::max(fc.max_m, fm[f]);
-        const double mm = fm[f], nn = n, kk = nc - n;
-        fc.flops += 2.0 * mm * nn * nn - 2.0 / 3.0 * nn * nn * nn + 4.0 * mm * nn * kk;
-        fc.bytes += 2.0 * mm * nc * sizeof(T);
       }
+    };
+    if (nch > 1) inner_pool_->run(nch, plan_chunk);
+    else plan_chunk(0);
+    for (Chunk& C : chunks) {
+      fc.gather.push_back(std::move(C.gather));
+      fc.scatter.push_back(std::move(C.scatter));
+      append(fc.qr, C.qr);
+      append(fc.trail, C.trail);
+      append(fc.wyb, C.wyb);
+      append(fc.wyt, C.wyt);
+      fc.max_m = std::max(fc.max_m, C.max_m);
+      fc.flops += C.flops;
+      fc.bytes += C.bytes;
     }
     P.fronts.push_back(std::move(fc));
   }
   // pack factors column-major for the apply and build the apply descriptors
+  hsub.reset(new HostScope("host_pf_apply"));
   {
-    std::vector<ApFront<T>> af;
-    std::vector<int32_t> rs, cs;
-    std::vector<int64_t> rs_off, cs_off;
+    // the fronts with pivots in colour order; offsets of their row and
+    // column slot lists and pack tiles first, then every list filled in
+    // parallel chunks straight into the pinned staging buffers
+    std::vector<int32_t> act;
+    act.reserve(nf);
+    std::vector<int64_t> rs_off(1, 0), cs_off(1, 0), pk_off(1, 0);
     ap.colour_ptr.assign(1, 0);
     for (size_t c = 0; c + 1 < ss.front_colour_ptr.size(); ++c) {
       int cmax = 0;
       double ffb = 0, fvb = 0, ffl = 0;
       for (int32_t oi = ss.front_colour_ptr[c]; oi < ss.front_colour_ptr[c + 1]; ++oi) {
         const int32_t f = ss.front_order[oi];
-        const FrontSym& F = ss.fronts[f];
         const int32_t m = fm[f], n = fn[f], nc = fnc[f];
         if (n == 0) continue;
-        T* Wf = W + ws_off[f];
-        P.pack.push_back({Wf, VR + vr_off[f], m, n, fld[f], m});
-        if (nc > n) P.pack.push_back({Wf + n, RSJ + rsj_off[f], n, nc - n, fld[f], n});
-        std::vector<int32_t> rows{F.cluster};
-        rows.insert(rows.end(), F.n1.begin(), F.n1.end());
-        rs_off.push_back((int64_t)rs.size());
-        slot_list(rows, rs);
-        cs_off.push_back((int64_t)cs.size());
-        slot_list(F.cols, cs);
-        af.push_back({VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], TPF + tp_off[f], nullptr, nullptr, m, n,
-                      nc - n, jbf});
+        act.push_back(f);
+        rs_off.push_back(rs_off.back() + m);
+        cs_off.push_back(cs_off.back() + (nc - n));
+        pk_off.push_back(pk_off.back() + (nc > n ? 2 : 1));
         cmax = std::max(cmax, m);
         ap.max_bwd_rows = std::max(ap.max_bwd_rows, nc);
         ap.max_n = std::max(ap.max_n, n);
@@ -666,23 +705,56 @@ void Engine<T>::plan_fronts(StagePlan<T>& P) {
         ap.bwd_vec_bytes += 16 * nn + 8 * kk;
         ap.bwd_flops += nn * nn + 2 * nn * kk;
       }
-      ap.colour_ptr.push_back((int64_t)af.size());
+      ap.colour_ptr.push_back((int64_t)act.size());
       ap.colour_max_m.push_back(cmax);
       ap.fwd_fac_bytes.push_back(ffb);
       ap.fwd_vec_bytes.push_back(fvb);
       ap.fwd_flops.push_back(ffl);
     }
-    int32_t* drs = up.upload_held(persist_, rs, s_);
-    int32_t* dcs = up.upload_held(persist_, cs, s_);
-    for (size_t t = 0; t < af.size(); ++t) {
-      af[t].rows = drs + rs_off[t];
-      af[t].cols = dcs ? dcs + cs_off[t] : nullptr;
-    }
+    const int64_t na = (int64_t)act.size();
+    hsub.reset(new HostScope("host_pf_upload"));
+    Stager::Region rr{nullptr, nullptr, 0}, rc{nullptr, nullptr, 0};
+    if (rs_off[na] > 0) rr = up.stage(persist_, (size_t)rs_off[na] * sizeof(int32_t), s_);
+    if (cs_off[na] > 0) rc = up.stage(persist_, (size_t)cs_off[na] * sizeof(int32_t), s_);
+    std::vector<ApFront<T>> af((size_t)na);
+    P.pack.resize((size_t)pk_off[na]);
+    const int nch = inner_pool_ && na >= 512 ? (int)std::min<int64_t>(inner_pool_->size() + 1, na / 256) : 1;
+    auto fill = [&](int q) {
+      const int64_t t0 = na * q / nch, t1 = na * (q + 1) / nch;
+      auto put = [&](int32_t cl, int32_t*& dst) {
+        const int64_t a0 = slot_ptr_[cl], a1 = slot_ptr_[cl + 1];
+        std::memcpy(dst, slots_.data() + a0, (size_t)(a1 - a0) * sizeof(int32_t));
+        dst += a1 - a0;
+      };
+      for (int64_t t = t0; t < t1; ++t) {
+        const int32_t f = act[t];
+        const FrontSym& F = ss.fronts[f];
+        const int32_t m = fm[f], n = fn[f], nc = fnc[f];
+        T* Wf = W + ws_off[f];
+        P.pack[pk_off[t]] = {Wf, VR + vr_off[f], m, n, fld[f], m};
+        if (nc > n) P.pack[pk_off[t] + 1] = {Wf + n, RSJ + rsj_off[f], n, nc - n, fld[f], n};
+        int32_t* dr = static_cast<int32_t*>(rr.host) + rs_off[t];
+        put(F.cluster, dr);
+        for (int32_t i : F.n1) put(i, dr);
+        if (rc.host) {
+          int32_t* dc = static_cast<int32_t*>(rc.host) + cs_off[t];
+          for (int32_t j : F.cols) put(j, dc);
+        }
+        af[t] = {VR + vr_off[f], RSJ + rsj_off[f], TAU + tau_off[f], TPF + tp_off[f],
+                 static_cast<int32_t*>(rr.dev) + rs_off[t],
+                 rc.dev ? static_cast<int32_t*>(rc.dev) + cs_off[t] : nullptr, m, n, nc - n, jbf};
+      }
+    };
+    if (nch > 1) inner_pool_->run(nch, fill);
+    else fill(0);
+    if (rr.bytes) up.send(rr, s_);
+    if (rc.bytes) up.send(rc, s_);
     ap.fronts = up.upload_held(persist_, af, s_);
-    ap.nfronts = (int64_t)af.size();
+    ap.nfronts = na;
     ap.h_fronts = std::move(af);
   }
 
+  hsub.reset(new HostScope("host_pf_flush"));
   {
     std::vector<int> r0(size_.begin(), size_.end());
     r0.push_back(0);
@@ -762,7 +834,7 @@ void Engine<T>::plan_scale(StagePlan<T>& P) {
     for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
       const int32_t j = ss.post.col[u];
       if (size_[i] == 0 || size_[j] == 0) continue;
-      const int64_t b = ss.all.find((int32_t)i, j);
+      const int64_t b = ss.post_all[u];
       P.sblk.push_back({pool_ + boff_[b], size_[i], size_[j], fidx[i], fidx[j]});
       st_.s.flops_scale += 4.0 * size_[i] * size_[i] * size_[j] + (double)size_[i] * size_[j] * size_[j];
     }
@@ -803,14 +875,14 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
       SpDesc<T> d{};
       d.nb = (int64_t)col.nb.size();
       int64_t mmax = 0;
-      for (int32_t i : I.rowN) {
-        const int64_t b = ss.all.find(i, p);
-        col.nb.push_back({boff_[b], i, Pn});
+      for (size_t q = 0; q < I.rowN.size(); ++q) {
+        const int32_t i = I.rowN[q];
+        col.nb.push_back({boff_[I.rowB[q]], i, Pn});
         mmax += size_[i];
       }
-      for (int32_t j : I.colN) {
-        const int64_t b = ss.all.find(p, j);
-        col.nb.push_back({boff_[b], j, size_[j]});
+      for (size_t q = 0; q < I.colN.size(); ++q) {
+        const int32_t j = I.colN[q];
+        col.nb.push_back({boff_[I.colB[q]], j, size_[j]});
         mmax += size_[j];
       }
       d.nrow = (int32_t)I.rowN.size();
@@ -926,13 +998,13 @@ void Engine<T>::plan_sparsify_unscaled(StagePlan<T>& P) {
       SpuDesc<T> d{};
       d.nb = (int64_t)col.nb.size();
       int64_t mr = 0, mc = 0;
-      for (int32_t i : I.rowN) {
-        col.nb.push_back({boff_[ss.all.find(i, p)], i, Pn});
-        mr += size_[i];
+      for (size_t q = 0; q < I.rowN.size(); ++q) {
+        col.nb.push_back({boff_[I.rowB[q]], I.rowN[q], Pn});
+        mr += size_[I.rowN[q]];
       }
-      for (int32_t j : I.colN) {
-        col.nb.push_back({boff_[ss.all.find(p, j)], j, size_[j]});
-        mc += size_[j];
+      for (size_t q = 0; q < I.colN.size(); ++q) {
+        col.nb.push_back({boff_[I.colB[q]], I.colN[q], size_[I.colN[q]]});
+        mc += size_[I.colN[q]];
       }
       const int64_t t = fidx[p];
       d.pool = pool_;
@@ -942,7 +1014,7 @@ void Engine<T>::plan_sparsify_unscaled(StagePlan<T>& P) {
       d.mb = MB + op_off[t];
       d.ws = nullptr;
       d.eps = o_.eps;
-      const int64_t bpp = ss.all.find(p, p);
+      const int64_t bpp = I.ppB;
       SPAQR_REQUIRE(bpp >= 0, SPAQR_EINVAL, "interface without a diagonal block");
       d.app = boff_[bpp];
       d.nrow = (int32_t)I.rowN.size();
@@ -1125,17 +1197,36 @@ void Engine<T>::finish(MergePlan<T>& mp) {
   // the new pool starts at zero (absent sub-blocks), then every child block
   // lands in its own sub-block of the parent block: disjoint destinations
   mp.zero.push_back({pool2, std::max<int64_t>(1, boff2.back()) * (int64_t)sizeof(T)});
-  for (int64_t i = 0; i < ss.nclu; ++i)
-    for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
-      const int32_t j = ss.post.col[u];
-      if (rank[i] == 0 || rank[j] == 0) continue;
-      const int32_t Qc = (int32_t)par[j];
-      const int64_t B = ss.post_next[u];
-      SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
-      const int64_t b = ss.post_all[u];
-      mp.tiles.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Qc] + off[j], rank[i], rank[j],
-                          size_[j], size2[Qc]});
-    }
+  // the block copies, by chunks of block rows planned in parallel
+  const int64_t nrows = ss.nclu, nblk = ss.post.rowptr[nrows];
+  const int nch = inner_pool_ && nblk >= 65536 ? (int)std::min<int64_t>(inner_pool_->size() + 1, nblk / 16384) : 1;
+  mp.tiles.assign(nch, {});
+  auto tiles_of = [&](int q) {
+    std::vector<CopyTile<T>>& out = mp.tiles[q];
+    // block rows [row_at(q), row_at(q + 1)): the first row whose blocks
+    // start at or after the chunk's share of the blocks
+    auto row_at = [&](int c) -> int64_t {
+      if (c == 0) return 0;
+      if (c == nch) return nrows;
+      return std::lower_bound(ss.post.rowptr.begin(), ss.post.rowptr.begin() + nrows + 1, nblk * c / nch) -
+             ss.post.rowptr.begin();
+    };
+    const int64_t i0 = row_at(q), i1 = row_at(q + 1);
+    out.reserve((size_t)(ss.post.rowptr[i1] - ss.post.rowptr[i0]));
+    for (int64_t i = i0; i < i1; ++i)
+      for (int64_t u = ss.post.rowptr[i]; u < ss.post.rowptr[i + 1]; ++u) {
+        const int32_t j = ss.post.col[u];
+        if (rank[i] == 0 || rank[j] == 0) continue;
+        const int32_t Qc = (int32_t)par[j];
+        const int64_t B = ss.post_next[u];
+        SPAQR_REQUIRE(B >= 0, SPAQR_EINVAL, "merged block missing from the next stage pattern");
+        const int64_t b = ss.post_all[u];
+        out.push_back({pool_ + boff_[b], pool2 + boff2[B] + (int64_t)off[i] * size2[Qc] + off[j], rank[i], rank[j],
+                       size_[j], size2[Qc]});
+      }
+  };
+  if (nch > 1) inner_pool_->run(nch, tiles_of);
+  else tiles_of(0);
   pool_ = pool2;
   boff_.swap(boff2);
   size_.swap(size2);
@@ -1175,6 +1266,10 @@ struct BatchCtx {
     st[cur].reset();
     work[cur].reset();
   }
+  HostPool* host_pool() {
+    if (!pool) pool.reset(new HostPool(host_pool_threads()));
+    return pool.get();
+  }
   void each(size_t n, const std::function<void(int)>& fn) {
     if (n > 1 && !pool) {
       pool.reset(new HostPool(host_pool_threads()));
@@ -1185,10 +1280,6 @@ struct BatchCtx {
   }
 };
 
-template <typename X>
-static void append(std::vector<X>& dst, const std::vector<X>& src) {
-  dst.insert(dst.end(), src.begin(), src.end());
-}
 
 static void launch_zero_ops(const std::vector<ZeroOp>& ops, Stager& up, DevArena& wk, hipStream_t s) {
   if (ops.empty()) return;
@@ -1541,6 +1632,8 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   };
   {
     HostScope hs("host_plan_fronts");
+    // a batch of one plans its own fronts on the host threads
+    for (size_t e = 0; e < ne; ++e) es[e]->set_host_pool(ne == 1 ? bx.host_pool() : nullptr);
     bx.each(ne, [&](int e) { es[e]->plan_fronts(pl[e]); });
   }
   flush_zero();
@@ -1549,7 +1642,6 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   HostScope hs_fronts("host_launch_fronts");
   size_t nc = 0;
   for (auto& p : pl) nc = std::max(nc, p.fronts.size());
-  static const std::vector<CopyTile<T>> none;
   for (size_t c = 0; c < nc; ++c) {
     std::vector<std::pair<int, std::vector<QRDesc<T>>>> qparts;
     double fl = 0.0, by = 0.0;
@@ -1559,10 +1651,11 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
       fl += p.fronts[c].flops;
       by += p.fronts[c].bytes;
     }
-    copy_concat<T>(bx, up, wk, ne,
-                   [&](int e) -> const std::vector<CopyTile<T>>& {
-                     return c < pl[e].fronts.size() ? pl[e].fronts[c].gather : none;
-                   },
+    std::vector<const std::vector<CopyTile<T>>*> lists;
+    for (auto& p : pl)
+      if (c < p.fronts.size())
+        for (const auto& v : p.fronts[c].gather) lists.push_back(&v);
+    copy_concat<T>(bx, up, wk, lists.size(), [&](int i) -> const std::vector<CopyTile<T>>& { return *lists[i]; },
                    false, s, "copy_front_gather");
     {
       HostScope hs("host_launch_qr");
@@ -1617,11 +1710,14 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
         launch_trail_mfma<T>(dt, (int64_t)wyt.size(), s);
       }
     }
-    copy_concat<T>(bx, up, wk, ne,
-                   [&](int e) -> const std::vector<CopyTile<T>>& {
-                     return c < pl[e].fronts.size() ? pl[e].fronts[c].scatter : none;
-                   },
-                   false, s, "copy_front_scatter");
+    {
+      std::vector<const std::vector<CopyTile<T>>*> sl;
+      for (auto& p : pl)
+        if (c < p.fronts.size())
+          for (const auto& v : p.fronts[c].scatter) sl.push_back(&v);
+      copy_concat<T>(bx, up, wk, sl.size(), [&](int i) -> const std::vector<CopyTile<T>>& { return *sl[i]; }, false,
+                     s, "copy_front_scatter");
+    }
   }
   copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return pl[e].pack; }, true, s,
                  "copy_front_pack");
@@ -1872,14 +1968,18 @@ void stage_finish(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   std::vector<MergePlan<T>> mp(ne);
   {
     HostScope hs("host_finish");
+    for (size_t e = 0; e < ne; ++e) es[e]->set_host_pool(ne == 1 ? bx.host_pool() : nullptr);
     bx.each(ne, [&](int e) { es[e]->finish(mp[e]); });
   }
   HostScope hs_merge("host_launch_merge");
   std::vector<ZeroOp> z;
   for (auto& m : mp) append(z, m.zero);
   launch_zero_ops(z, up, wk, s);
-  copy_concat<T>(bx, up, wk, ne, [&](int e) -> const std::vector<CopyTile<T>>& { return mp[e].tiles; }, false, s,
-                 "copy_merge");
+  std::vector<const std::vector<CopyTile<T>>*> lists;
+  for (auto& m : mp)
+    for (const auto& v : m.tiles) lists.push_back(&v);
+  copy_concat<T>(bx, up, wk, lists.size(), [&](int i) -> const std::vector<CopyTile<T>>& { return *lists[i]; }, false,
+                 s, "copy_merge");
   if (bx.pe) bx.pe->record(4, s);
   bx.pe.reset();
 }

@@ -34,6 +34,7 @@ class HostPool {
     cv_.notify_all();
     for (auto& t : th_) t.join();
   }
+  int size() const { return (int)th_.size(); }  // worker threads (the caller also runs)
   HostPool(const HostPool&) = delete;
   HostPool& operator=(const HostPool&) = delete;
 

@@ -267,6 +267,9 @@ Symbolic* analyze(const spaqr_csr* A, const Ordering& ord, int skip) {
           if (prow[u] != p) f.rowN.push_back(prow[u]);
         for (int64_t u = ss.post.rowptr[p]; u < ss.post.rowptr[p + 1]; ++u)
           if (ss.post.col[u] != p) f.colN.push_back(ss.post.col[u]);
+        for (int32_t i : f.rowN) f.rowB.push_back(ss.all.find(i, p));
+        for (int32_t j : f.colN) f.colB.push_back(ss.all.find(p, j));
+        f.ppB = ss.all.find(p, p);
         std::vector<int32_t> nb;
         for (int32_t q : f.rowN) nb.push_back(idx[q]);
         for (int32_t q : f.colN) nb.push_back(idx[q]);

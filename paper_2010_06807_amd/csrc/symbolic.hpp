@@ -41,6 +41,10 @@ struct IfaceSym {
   int32_t colour = 0;
   std::vector<int32_t> rowN;  // i != p with a block (i, p), ascending
   std::vector<int32_t> colN;  // j != p with a block (p, j), ascending
+  // indices in the stage's `all` set of the blocks (i, p), (p, j) and (p, p)
+  // (-1 if (p, p) is absent)
+  std::vector<int64_t> rowB, colB;
+  int64_t ppB = -1;
 };
 
 struct StageSym {
