@@ -46,9 +46,8 @@ namespace spaqr {
 
 namespace {
 
-// threads per workgroup: 256 for colours of interfaces of at most 64
-// unknowns (many interfaces, one each), 1024 above (few wide interfaces: more
-// wavefronts in flight per reflector)
+// threads per workgroup: 256 for launches of more than 512 interfaces of at
+// most 64 unknowns, 1024 otherwise (more wavefronts in flight per reflector)
 constexpr int kNTSmall = 256, kNTWide = 1024;
 
 __device__ __forceinline__ double u_wave_sum(double v) {
@@ -131,6 +130,31 @@ __device__ void u_left(const double* __restrict__ vv, int n, double tau, double*
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     for (int j = w; j < ncols; j += NT / 64) {
       double* __restrict__ a = A + j * lda;
+      double s0 = 0.0, s1 = 0.0;
+      int i = l;
+      for (; i + 64 < n; i += 128) {
+        s0 += (i == 0 ? 1.0 : vv[i]) * a[i];
+        s1 += vv[i + 64] * a[i + 64];
+      }
+      if (i < n) s0 += (i == 0 ? 1.0 : vv[i]) * a[i];
+      const double s = u_wave_sum(s0 + s1) * tau;
+#pragma unroll 4
+      for (int q = l; q < n; q += 64) a[q] -= (q == 0 ? 1.0 : vv[q]) * s;
+    }
+  }
+  __syncthreads();
+}
+
+// The same reflector on three column-major blocks with one leading dimension
+// (n0, n1 and n2 columns of A0, A1, A2) in one pass: one barrier, and the
+// wavefronts share out all n0 + n1 + n2 columns.
+template <int NT>
+__device__ void u_left3(const double* __restrict__ vv, int n, double tau, int64_t lda, double* __restrict__ A0,
+                        int n0, double* __restrict__ A1, int n1, double* __restrict__ A2, int n2) {
+  if (tau != 0.0) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int j = w; j < n0 + n1 + n2; j += NT / 64) {
+      double* __restrict__ a = j < n0 ? A0 + j * lda : (j < n0 + n1 ? A1 + (j - n0) * lda : A2 + (j - n0 - n1) * lda);
       double s0 = 0.0, s1 = 0.0;
       int i = l;
       for (; i + 64 < n; i += 128) {
@@ -447,9 +471,7 @@ __global__ void __launch_bounds__(NT) k_sparsify_unscaled(const SpuDesc<T>* __re
     double* bu = B + u + (int64_t)(r + u) * P;
     const double th = u_larfg<NT>(bu, P - u, 1, red);
     if (t == 0) tH[u] = th;
-    u_left<NT>(bu, P - u, th, bu + P, P, f - u - 1);
-    u_left<NT>(bu, P - u, th, B + u, P, r);
-    u_left<NT>(bu, P - u, th, N + u, P, mc);
+    u_left3<NT>(bu, P - u, th, P, bu + P, f - u - 1, B + u, r, N + u, mc);
   }
 
   // ---- the new blocks of p: the last r rows, stored first
@@ -534,7 +556,10 @@ template <typename T>
 void launch_sparsify_unscaled(const SpuDesc<T>* d, const SpNbr* nb, int64_t n, int max_p, hipStream_t s) {
   if (n <= 0) return;
   count_launch("k_sparsify_unscaled");
-  if (max_p <= 64)
+  // the launch lasts as long as its slowest interface's chain of reflector
+  // steps: 1024 threads shorten every step, and two such workgroups fit a
+  // CU, so they pay off until the interfaces outnumber two per CU
+  if (max_p <= 64 && n > 512)
     hipLaunchKernelGGL((k_sparsify_unscaled<T, kNTSmall>), dim3((unsigned)n), dim3(kNTSmall), 0, s, d, nb);
   else
     hipLaunchKernelGGL((k_sparsify_unscaled<T, kNTWide>), dim3((unsigned)n), dim3(kNTWide), 0, s, d, nb);
