@@ -2393,7 +2393,7 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
 #pragma unroll
     for (int c = 0; c < NR; ++c) xr[q][c] = (r < m && c < nc) ? x[sl[q] + (int64_t)(c0 + c) * ldx] : 0.0;
   }
-  T vc[Q][JB], vn[Q][JB];
+  T vc[Q][JB];
   auto load_v = [&](int p0, T (&v)[Q][JB]) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -2405,9 +2405,8 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
       }
     }
   };
-  load_v(0, vc);
   for (int p0 = 0, it = 0; p0 < n; p0 += JB, ++it) {
-    if (p0 + JB < n) load_v(p0 + JB, vn);
+    load_v(p0, vc);
     const int buf = it & 1;
     // column `lane` of this panel's T (upper triangular, column-major JB x JB)
     T tcol[JB];
@@ -2426,34 +2425,31 @@ __global__ void __launch_bounds__(256) k_ap_front_fwd_reg(const ApFront<T>* __re
     const double s = wave_reduce_scatter<double, K>(w);
     if ((lane & ((1 << SH) - 1)) == 0) red[buf][wv][lane >> SH] = s;
     __syncthreads();
-    double wt[K];
-#pragma unroll
-    for (int i = 0; i < K; ++i) wt[i] = red[buf][0][i] + red[buf][1][i] + red[buf][2][i] + red[buf][3][i];
+    // u_t = (T^T w)_t on lane t, the reduced w read from LDS as broadcasts
     double u[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) {
       u[c] = 0.0;
 #pragma unroll
-      for (int q = 0; q < JB; ++q) u[c] += (double)tcol[q] * wt[q * NR + c];
+      for (int q = 0; q < JB; ++q)
+        u[c] += (double)tcol[q] *
+                (red[buf][0][q * NR + c] + red[buf][1][q * NR + c] + red[buf][2][q * NR + c] + red[buf][3][q * NR + c]);
     }
-    double ua[K];
+    // x <- x - V u, u_t broadcast from lane t (uniform, scalar registers)
 #pragma unroll
-    for (int t = 0; t < JB; ++t)
+    for (int c = 0; c < NR; ++c) {
+      double acc[Q];
 #pragma unroll
-      for (int c = 0; c < NR; ++c) ua[t * NR + c] = readlane_d(u[c], t);
+      for (int q = 0; q < Q; ++q) acc[q] = 0.0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
+      for (int t = 0; t < JB; ++t) {
+        const double ut = readlane_d(u[c], t);
 #pragma unroll
-      for (int c = 0; c < NR; ++c) {
-        double acc = 0.0;
-#pragma unroll
-        for (int t = 0; t < JB; ++t) acc += (double)vc[q][t] * ua[t * NR + c];
-        xr[q][c] -= acc;
+        for (int q = 0; q < Q; ++q) acc[q] += (double)vc[q][t] * ut;
       }
 #pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int t = 0; t < JB; ++t) vc[q][t] = vn[q][t];
+      for (int q = 0; q < Q; ++q) xr[q][c] -= acc[q];
+    }
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
