@@ -396,11 +396,12 @@ void spaqr_free(spaqr_handle* h);
  *                     norm has lost three digits, exact norms for the rank
  *                     rule), every interface of a colour in one launch;
  *                     0: they take the exact-norm kernels above (default 1);
- *   cpqr_team         1: FP32 interfaces of at most 896 unknowns beyond one
+ *   cpqr_team         1: FP32 interfaces of 65-896 unknowns beyond one
  *                     workgroup take the team CPQR (a team of co-resident
  *                     workgroups per interface, all columns in registers,
- *                     downdated norms as for cpqr_dd); 0: they take the
- *                     cooperative kernel (default 1).
+ *                     downdated norms as for cpqr_dd); 2: so do those of at
+ *                     most 64 unknowns with at least 16384 columns; 0: they
+ *                     take the cooperative kernel (default 2).
  * spaqr_set_tuning(NULL) restores the defaults.  Set it only while no
  * factorization or apply is in flight.  Errors: EINVAL for a value outside
  * the ranges above. */

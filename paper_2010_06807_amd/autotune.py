@@ -40,7 +40,7 @@ CANDIDATES = {
     "qr_reg_max_rows": [1024, 512, 256],
     "cpqr_coop": [1, 0],
     "cpqr_dd": [1, 0],
-    "cpqr_team": [1, 0],
+    "cpqr_team": [2, 1, 0],
     "scale_small": [64, 32],
     "iface_dense": [64, 32],
 }

@@ -1427,7 +1427,8 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
       const int cap = sparsify_team_capacity(max_nb);
       const auto tm_end = std::stable_partition(sd.begin(), sd.end(), [&](const SpDesc<T>& q) {
         const int nb_q = sparsify_team_blocks(q.P, q.mmax);
-        return q.P > 64 && nb_q > 0 && nb_q <= cap;
+        const bool wide = q.P > 64 || (tuning().cpqr_team == 2 && q.mmax >= 16384);
+        return wide && nb_q > 0 && nb_q <= cap;
       });
       if (tm_end != sd.begin()) {
         std::vector<SpDesc<T>> tm(sd.begin(), tm_end);

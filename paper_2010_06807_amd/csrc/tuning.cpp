@@ -4,7 +4,7 @@
 namespace spaqr {
 
 namespace {
-constexpr spaqr_tuning kDefault = {1024, 1024, 1024, 1, 1, 64, 64, 1, 1, 1};
+constexpr spaqr_tuning kDefault = {1024, 1024, 1024, 1, 1, 64, 64, 1, 1, 2};
 spaqr_tuning g_tuning = kDefault;
 
 bool valid(const spaqr_tuning& t) {
@@ -13,7 +13,7 @@ bool valid(const spaqr_tuning& t) {
          t.split_rows >= 1 && t.split_cols >= 1 && (t.cpqr_reg == 0 || t.cpqr_reg == 1) &&
          (t.cpqr_coop == 0 || t.cpqr_coop == 1) && cls(t.scale_small) &&
          cls(t.iface_dense) && (t.trail_mfma == 0 || t.trail_mfma == 1) && (t.cpqr_dd == 0 || t.cpqr_dd == 1) &&
-         (t.cpqr_team == 0 || t.cpqr_team == 1);
+         (t.cpqr_team >= 0 && t.cpqr_team <= 2);
 }
 }  // namespace
 
