@@ -75,16 +75,20 @@ spaqr_status spaqr_order_grid(int dim, const int32_t sides[3], int nlevels,
  * grid (Section 2.3, Fig. mnd; the paper partitions such matrices with a
  * hypergraph partitioner, here the graph of A^T A is bisected instead).
  * Graph: i ~ j (i != j) iff some row of A holds entries in columns i and j.
- * A node's vertex set splits by a BFS level structure of its induced
- * subgraph (root: the smallest vertex, moved up to four times to the
- * smallest vertex of the last level while that lengthens the structure;
- * further components append their levels); the separator is the level
- * m in [1, h-2] minimizing (|#below - #above|, its size, m), below going to
- * the low child.  A separator vertex's stage-k interface is the pair of
+ * A node's vertex set splits between two far vertices of its induced
+ * subgraph: r starts at the smallest vertex and moves up to four times to
+ * the smallest vertex of its last BFS level while that lengthens the level
+ * structure; u is then the smallest vertex of r's last level.  Each vertex
+ * of r's component gets the key d_r - d_u (BFS distances); the separator is
+ * the key pair {t, t+1} minimizing (|#low - #high|, its size, t), low =
+ * keys below t, high = keys above t+1 plus the other components.  The pair
+ * is then thinned: its vertices with no high neighbour join the low part,
+ * then those with no low neighbour join the high part.  A separator
+ * vertex's stage-k interface is the pair of
  * level-k ancestors of the deepest common ancestors of its neighbours' nodes
  * on each side.  Only A's pattern is read (A->val may be NULL); rows are
  * clustered like columns.  nlevels <= 0 selects ceil(log2(N/64)), capped at
- * the deepest tree whose nodes above the leaves all split (>= 3 BFS levels);
+ * the deepest tree whose nodes above the leaves all split (key range >= 3);
  * an explicit deeper nlevels is EINVAL.  Errors: EINVAL for a NULL or
  * inconsistent CSR or a column index outside [0, n).  *out is
  * library-owned (spaqr_ordering_free); the result is used like that of

@@ -223,17 +223,24 @@ def order_grid(dims, L):
 # place of the hypergraph:
 #   G1 the graph: i ~ j (i != j) iff some row r has A_ri != 0 and A_rj != 0,
 #      the pattern of A^T A, whose ND the paper's column ordering is.
-#   G2 node X of level l < L with vertex set V_X is split by a BFS level
-#      structure of the subgraph induced on V_X: the root r starts at min(V_X);
+#   G2 node X of level l < L with vertex set V_X is split between two far
+#      vertices of the subgraph induced on V_X: the root r starts at min(V_X);
 #      up to four times, if the BFS from u = the smallest vertex of r's last
-#      level has more levels than the BFS from r, r <- u.  The levels of r's
-#      component come first; each further component, rooted at its smallest
-#      vertex, appends its levels after them.
-#   G3 with h >= 3 levels, the separator is the level m in [1, h-2] that
-#      minimizes |#below - #above|, then |level m|, then m; low child 2X =
-#      levels < m, high child 2X+1 = levels > m.  Edges of the induced graph
-#      join levels at most one apart, so the separator cuts A^T A inside V_X.
-#      h < 3 at a node above the leaves: too many levels.
+#      level has more levels than the BFS from r, r <- u.  Then u is the
+#      smallest vertex of r's last level, and every vertex v of r's component
+#      gets key(v) = d_r(v) - d_u(v) (BFS distances in the induced subgraph):
+#      the classes of key are bands across the line from r to u, not rings
+#      around r.  Vertices outside r's component go to the high child.
+#   G3 keys run from kmin to kmax; with kmax - kmin >= 3 the separator is the
+#      key pair {t, t+1}, t in [kmin+1, kmax-2] minimizing (|#low - #high|,
+#      |separator|, t), low = key < t (child 2X), high = key > t+1 and the
+#      other components (child 2X+1).  Along an edge each distance changes by
+#      at most one, so key by at most two: the separator cuts A^T A inside V_X.
+#      The pair is then thinned: its vertices without a neighbour in the high
+#      part join the low part, then those without a neighbour in the low part
+#      join the high part (a band of equal keys can be wide in a graph
+#      metric; what remains still separates).
+#      kmax - kmin < 3 at a node above the leaves: too many levels.
 #   G4 interfaces: for a separator vertex q of node B and each child C of B,
 #      desc_C(q) is the deepest common ancestor of the nodes of q's
 #      neighbours inside C's subtree (C if there are none);
@@ -271,8 +278,9 @@ def _bfs_levels(indptr, indices, inset, root):
     return levels
 
 
-def _level_structure(indptr, indices, V, N):
-    """The level structure of G2 for the sorted vertex set V."""
+def _bisect(indptr, indices, V, N):
+    """G2/G3 for the sorted vertex set V: (low, separator, high, (r, u, t)),
+    or None when V cannot be split."""
     inset = np.zeros(N, dtype=bool)
     inset[V] = True
     r = int(V[0])
@@ -284,28 +292,46 @@ def _level_structure(indptr, indices, V, N):
             r, lev = u, lu
         else:
             break
-    done = np.zeros(N, dtype=bool)
-    for x in lev:
-        done[x] = True
-    while True:
-        rest = V[~done[V]]
-        if rest.size == 0:
-            break
-        more = _bfs_levels(indptr, indices, inset & ~done, int(rest[0]))
-        for x in more:
-            done[x] = True
-        lev = lev + more
-    return lev
+    u = int(lev[-1][0])
+    dr = np.full(N, -1, dtype=np.int64)
+    for d, x in enumerate(lev):
+        dr[x] = d
+    du = np.full(N, -1, dtype=np.int64)
+    for d, x in enumerate(_bfs_levels(indptr, indices, inset, u)):
+        du[x] = d
+    comp = V[dr[V] >= 0]
+    other = V[dr[V] < 0]
+    key = dr[comp] - du[comp]
+    kmin, kmax = int(key.min()), int(key.max())
+    if kmax - kmin < 3:
+        return None
+    counts = np.bincount(key - kmin, minlength=kmax - kmin + 1)
+    t = kmin + _split_keys(counts.tolist(), int(other.size))
+    side = np.zeros(N, dtype=np.int64)  # -1 low, 0 separator, 1 high (vertices of comp)
+    side[comp] = np.where(key < t, -1, np.where(key > t + 1, 1, 0))
+    band = comp[side[comp] == 0]
+    # thinning (G3): a separator vertex with no neighbour in the high part
+    # joins the low part, then one with no neighbour in the low part joins
+    # the high part
+    for want, to in ((1, -1), (-1, 1)):
+        move = [v for v in band if side[v] == 0 and
+                not np.any(side[indices[indptr[v]:indptr[v + 1]][inset[indices[indptr[v]:indptr[v + 1]]]]] == want)]
+        side[np.array(move, dtype=np.int64)] = to
+    low = comp[side[comp] == -1]
+    sep = comp[side[comp] == 0]
+    high = np.sort(np.concatenate([comp[side[comp] == 1], other]))
+    return low, sep, high, (r, u, t)
 
 
-def _split_level(sizes):
-    """G3: the separator level m in [1, h-2] minimizing (|#below - #above|,
-    |level m|, m) for level sizes `sizes` (h >= 3)."""
-    h = len(sizes)
+def _split_keys(counts, n_other):
+    """G3 on key class sizes counts[0..] (keys kmin, kmin+1, ...) and n_other
+    vertices outside the root's component: the offset t - kmin of the chosen
+    separator pair."""
+    h = len(counts)
     best = None
-    for m in range(1, h - 1):
-        lo, hi = sum(sizes[:m]), sum(sizes[m + 1:])
-        cand = (abs(lo - hi), sizes[m], m)
+    for q in range(1, h - 2):
+        lo, sep, hi = sum(counts[:q]), counts[q] + counts[q + 1], sum(counts[q + 2:]) + n_other
+        cand = (abs(lo - hi), sep, q)
         if best is None or cand < best:
             best = cand
     return best[2]
@@ -342,7 +368,7 @@ class GraphOrdering(Ordering):
             cap = False
         node = np.ones(N, dtype=np.int64)
         sets = {1: np.arange(N, dtype=np.int64)}
-        # (BFS root, separator level) of every split node (a record only)
+        # (r, u, t) of every split node (a record only)
         self.splits = {}
         depth = 1
         while depth < L:
@@ -350,21 +376,20 @@ class GraphOrdering(Ordering):
             ok = True
             for X in range(1 << (depth - 1), 1 << depth):
                 V = sets[X]
-                lev = _level_structure(indptr, indices, V, N) if V.size else []
-                h = len(lev)
-                if h < 3:
+                got = _bisect(indptr, indices, V, N) if V.size else None
+                if got is None:
                     ok = False
                     break
-                m = _split_level([x.size for x in lev])
-                self.splits[X] = (int(lev[0][0]), m)
-                new[2 * X] = np.sort(np.concatenate(lev[:m]))
-                new[2 * X + 1] = np.sort(np.concatenate(lev[m + 1:]))
-                node[lev[m]] = X
+                low, sep, high, rec = got
+                self.splits[X] = rec
+                new[2 * X] = low
+                new[2 * X + 1] = high
+                node[sep] = X
             if not ok:
                 if cap:
                     L = depth
                     break
-                raise GridOrderingError(f"too many levels: a node of level {depth} has fewer than 3 BFS levels")
+                raise GridOrderingError(f"too many levels: a node of level {depth} cannot be split")
             for X, V in new.items():
                 node[V] = X
             sets = new

@@ -109,7 +109,8 @@ def order_grid(dims, levels=0):
 
 class GraphOrdering(GridOrdering):
     """Algebraic modified nested dissection of a square sparse matrix without a
-    grid (spaqr_order_graph): BFS bisection of the graph of A^T A."""
+    grid (spaqr_order_graph): bisection of the graph of A^T A between two far
+    vertices, with separator thinning."""
 
     def __init__(self, A, levels=0):
         lib = _abi.load()

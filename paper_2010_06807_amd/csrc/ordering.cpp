@@ -18,6 +18,7 @@
 // gives the permutation, and every coarser cluster is a run of triples.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <memory>
 #include <numeric>
 
@@ -275,18 +276,22 @@ void finish_ordering(Ordering* o, const std::vector<Finest>& fin) {
 // Algebraic modified nested dissection of a square sparse matrix (Section 2.3,
 // Fig. mnd), for inputs without a grid.  The paper partitions such matrices
 // with a hypergraph partitioner on A; here the graph of A^T A (whose ND the
-// column ordering is) is bisected by BFS level structures:
+// column ordering is) is bisected between two far vertices:
 //
 //   * graph: i ~ j (i != j) iff some row holds entries in columns i and j;
-//   * node X (vertex set V_X) splits by the BFS level structure of the
-//     subgraph induced on V_X: the root starts at min(V_X) and moves, up to
-//     four times, to the smallest vertex of its last level while that BFS
-//     has more levels; the root's component gives the first levels, each
-//     further component (rooted at its smallest vertex) appends its levels;
-//   * with h >= 3 levels the separator is the level m in [1, h-2] minimizing
-//     (|#below - #above|, |level m|, m); below goes to 2X, above to 2X+1.
-//     Induced edges join levels at most one apart, so the separator cuts
-//     A^T A inside V_X;
+//   * node X (vertex set V_X): in the subgraph induced on V_X, the root r
+//     starts at min(V_X) and moves, up to four times, to the smallest vertex
+//     of its last BFS level while that BFS has more levels; u is then the
+//     smallest vertex of r's last level.  A vertex v of r's component gets
+//     key d_r(v) - d_u(v) (BFS distances); the other components join the
+//     high child;
+//   * keys run over [kmin, kmax]; with kmax - kmin >= 3 the separator is the
+//     key pair {t, t+1}, t in [kmin+1, kmax-2] minimizing (|#low - #high|,
+//     |pair|, t), low (key < t) going to 2X and high (key > t+1) to 2X+1.
+//     An edge changes each distance by at most one, so the pair cuts A^T A
+//     inside V_X.  The pair is then thinned: its vertices with no neighbour in
+//     the high part join the low part, then those with no neighbour in the
+//     low part join the high part;
 //   * a separator vertex q of node B touches, on each side C of B, the nodes
 //     of its neighbours inside C's subtree; desc_C(q) is their deepest common
 //     ancestor (C when there are none), and the stage-k interface of q is
@@ -387,6 +392,8 @@ Ordering* build_graph_ordering(int64_t n, const int64_t* rowptr, const int32_t* 
   std::vector<int64_t> cur(n, 1);  // node of each vertex so far
   std::vector<int64_t> seen(n, -1);
   int64_t stamp = 0;
+  std::vector<int32_t> dr(n, 0), du(n, 0);  // distances from the two far vertices of a node
+  std::vector<int8_t> side(n, 0);          // -1 low, 0 separator, 1 high within the node being split
   // vertex sets of the nodes of the current depth, ascending
   std::vector<std::vector<int32_t>> sets(1);
   sets[0].resize(n);
@@ -404,7 +411,8 @@ Ordering* build_graph_ordering(int64_t n, const int64_t* rowptr, const int32_t* 
         ok = false;
         break;
       }
-      // pseudo-peripheral root of the component of min(V)
+      // two far vertices of the component of min(V): r moved up to four
+      // times to the smallest vertex of its last BFS level, u that vertex
       std::vector<std::vector<int32_t>> lev;
       int32_t r = V[0];
       bfs_levels(g, cur, X, r, seen, ++stamp, lev);
@@ -419,39 +427,88 @@ Ordering* build_graph_ordering(int64_t n, const int64_t* rowptr, const int32_t* 
           break;
         }
       }
-      // mark the chosen structure's vertices, then the other components
-      const int64_t st = ++stamp;
-      for (const auto& lv : lev)
-        for (int32_t v : lv) seen[v] = st;
-      for (int32_t v : V)
-        if (seen[v] != st) bfs_levels(g, cur, X, v, seen, st, lev);
-      const int h = (int)lev.size();
-      if (h < 3) {
+      const int32_t u = lev.back()[0];
+      const int64_t comp_stamp = ++stamp;
+      for (size_t d = 0; d < lev.size(); ++d)
+        for (int32_t v : lev[d]) {
+          seen[v] = comp_stamp;
+          dr[v] = (int32_t)d;
+        }
+      {
+        std::vector<std::vector<int32_t>> lu;
+        bfs_levels(g, cur, X, u, seen, ++stamp, lu);
+        for (size_t d = 0; d < lu.size(); ++d)
+          for (int32_t v : lu[d]) du[v] = (int32_t)d;
+        // the BFS from u covers the same component; restore its marks
+        for (const auto& lv : lu)
+          for (int32_t v : lv) seen[v] = comp_stamp;
+      }
+      // keys d_r - d_u over the component; the rest of V joins the high side
+      int32_t kmin = INT32_MAX, kmax = INT32_MIN;
+      int64_t n_other = 0;
+      for (int32_t v : V) {
+        if (seen[v] != comp_stamp) {
+          ++n_other;
+          continue;
+        }
+        const int32_t key = dr[v] - du[v];
+        kmin = std::min(kmin, key);
+        kmax = std::max(kmax, key);
+      }
+      if (kmax - kmin < 3) {
         ok = false;
         break;
       }
+      const int h = kmax - kmin + 1;
+      std::vector<int64_t> cnt(h, 0);
+      for (int32_t v : V)
+        if (seen[v] == comp_stamp) cnt[dr[v] - du[v] - kmin]++;
       std::vector<int64_t> below(h + 1, 0);
-      for (int q = 0; q < h; ++q) below[q + 1] = below[q] + (int64_t)lev[q].size();
-      int m = 1;
+      for (int q = 0; q < h; ++q) below[q + 1] = below[q] + cnt[q];
+      int tq = 1;
       int64_t bi = -1, bs = 0;
-      for (int q = 1; q <= h - 2; ++q) {
-        const int64_t lo = below[q], hi = below[h] - below[q + 1];
-        const int64_t im = lo > hi ? lo - hi : hi - lo, sz = (int64_t)lev[q].size();
-        if (bi < 0 || im < bi || (im == bi && sz < bs)) {
+      for (int q = 1; q <= h - 3; ++q) {
+        const int64_t lo = below[q], sp = cnt[q] + cnt[q + 1], hi = below[h] - below[q + 2] + n_other;
+        const int64_t im = lo > hi ? lo - hi : hi - lo;
+        if (bi < 0 || im < bi || (im == bi && sp < bs)) {
           bi = im;
-          bs = sz;
-          m = q;
+          bs = sp;
+          tq = q;
         }
+      }
+      const int32_t t = kmin + tq;
+      // sides: -1 low, 0 separator, 1 high; then the separator is thinned
+      for (int32_t v : V) {
+        if (seen[v] != comp_stamp) {
+          side[v] = 1;
+          continue;
+        }
+        const int32_t key = dr[v] - du[v];
+        side[v] = key < t ? -1 : (key > t + 1 ? 1 : 0);
+      }
+      for (int pass = 0; pass < 2; ++pass) {
+        const int8_t want = pass == 0 ? 1 : -1, to = pass == 0 ? -1 : 1;
+        std::vector<int32_t> move;
+        for (int32_t v : V) {
+          if (side[v] != 0) continue;
+          bool touches = false;
+          for (int64_t e = g.ptr[v]; e < g.ptr[v + 1] && !touches; ++e) {
+            const int32_t w = g.adj[e];
+            touches = cur[w] == X && side[w] == want;
+          }
+          if (!touches) move.push_back(v);
+        }
+        for (int32_t v : move) side[v] = to;
       }
       std::vector<int32_t>& lowv = next[2 * xi];
       std::vector<int32_t>& highv = next[2 * xi + 1];
-      for (int q = 0; q < m; ++q) lowv.insert(lowv.end(), lev[q].begin(), lev[q].end());
-      for (int q = m + 1; q < h; ++q) highv.insert(highv.end(), lev[q].begin(), lev[q].end());
-      std::sort(lowv.begin(), lowv.end());
-      std::sort(highv.begin(), highv.end());
+      for (int32_t v : V) {
+        if (side[v] < 0) lowv.push_back(v);
+        else if (side[v] > 0) highv.push_back(v);
+      }
     }
     if (!ok) {
-      SPAQR_REQUIRE(cap, SPAQR_EINVAL, "too many levels: a node above the leaves has fewer than 3 BFS levels");
+      SPAQR_REQUIRE(cap, SPAQR_EINVAL, "too many levels: a node above the leaves cannot be split");
       L = depth;
       break;
     }

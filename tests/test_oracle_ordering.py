@@ -152,16 +152,17 @@ def test_graph_separators_cut_ata(name):
 
 @pytest.mark.parametrize("name", sorted(GRAPH_CASES))
 def test_graph_split_rule_against_csgraph(name):
-    """G2/G3 recomputed from scipy's unweighted shortest paths on the induced
-    subgraph: the pseudo-peripheral root, the level structure, the chosen
-    separator level and both children."""
+    """G2/G3 recomputed from scipy's unweighted shortest paths on each node's
+    induced subgraph: the two far vertices, the key classes d_r - d_u, the
+    chosen separator pair, its thinning on the dense adjacency, and both
+    children."""
     from scipy.sparse.csgraph import shortest_path
     A = GRAPH_CASES[name]()
     o = order_graph(A)
     G = sp.csr_matrix(_dense_ata(A).astype(np.float64))
     G.setdiag(0)
     G.eliminate_zeros()
-    for X, (root, m) in o.splits.items():
+    for X, (root, far, t) in o.splits.items():
         if X.bit_length() >= o.L:
             continue
         V = np.nonzero(_descendants(o, X))[0]
@@ -174,33 +175,36 @@ def test_graph_split_rule_against_csgraph(name):
 
         r = 0  # index into V of min(V)
         for _ in range(4):
-            d = D[r]
-            far = np.nonzero(d == depth_of(r))[0]
-            u = int(far.min())
+            u = int(np.nonzero(D[r] == depth_of(r))[0].min())
             if depth_of(u) > depth_of(r):
                 r = u
             else:
                 break
-        assert V[r] == root
-        # levels: r's component, then the other components by smallest vertex
-        lev = np.full(V.size, -1, dtype=np.int64)
-        base = 0
-        seed = r
-        while True:
-            d = D[seed]
-            comp = np.isfinite(d)
-            lev[comp] = base + d[comp].astype(np.int64)
-            base = int(lev.max()) + 1
-            left = np.nonzero(lev < 0)[0]
-            if left.size == 0:
-                break
-            seed = int(left.min())
-        h = base
-        sizes = np.bincount(lev, minlength=h)
-        best = min((abs(int(sizes[:q].sum()) - int(sizes[q + 1:].sum())), int(sizes[q]), q) for q in range(1, h - 1))
-        assert best[2] == m
-        assert np.array_equal(np.sort(V[lev == m]), np.nonzero(o.node == X)[0])
-        assert np.array_equal(np.sort(V[lev < m]), np.nonzero(_descendants(o, 2 * X))[0])
+        u = int(np.nonzero(D[r] == depth_of(r))[0].min())
+        assert V[r] == root and V[u] == far
+        comp = np.isfinite(D[r])
+        key = (D[r] - D[u])[comp].astype(np.int64)
+        kmin, kmax = int(key.min()), int(key.max())
+        n_other = int((~comp).sum())
+        best = min((abs(int((key < q).sum()) - int((key > q + 1).sum()) - n_other),
+                    int(((key == q) | (key == q + 1)).sum()), q) for q in range(kmin + 1, kmax - 1))
+        assert best[2] == t
+        # thinning on the dense adjacency of the induced subgraph
+        Sd = S.toarray() != 0
+        idx = np.nonzero(comp)[0]
+        low = np.zeros(V.size, dtype=bool)
+        high = ~comp.copy()
+        low[idx[key < t]] = True
+        high[idx[key > t + 1]] = True
+        band = np.zeros(V.size, dtype=bool)
+        band[idx[(key == t) | (key == t + 1)]] = True
+        to_low = band & ~(Sd[:, high].any(axis=1))
+        low |= to_low
+        band &= ~to_low
+        to_high = band & ~(Sd[:, low].any(axis=1))
+        band &= ~to_high
+        assert np.array_equal(np.sort(V[band]), np.nonzero(o.node == X)[0])
+        assert np.array_equal(np.sort(V[low]), np.nonzero(_descendants(o, 2 * X))[0])
 
 
 @pytest.mark.parametrize("name", sorted(GRAPH_CASES))
@@ -275,12 +279,16 @@ def test_graph_default_levels():
         order_graph(convdiff((6, 6), (1.0, 1.0)), 5)
 
 
-def test_graph_split_level_by_hand():
-    """G3 on level sizes worked out by hand: balance first, then the smaller
-    separator, then the lower level."""
-    from oracle.ordering import _split_level
-    assert _split_level([1, 2, 1, 3, 1]) == 2   # imbalances 4, 1, 3
-    assert _split_level([1, 3, 1, 2]) == 2      # imbalances 2, 2: separator 1 beats 3
-    assert _split_level([1, 1, 3, 2, 1]) == 2   # imbalances 5, 1, 3
-    assert _split_level([1, 1, 1, 1]) == 1      # a tie of equal separators: the lower level
-    assert _split_level([1, 5, 1]) == 1         # a single choice
+def test_graph_split_keys_by_hand():
+    """G3 on key class sizes worked out by hand: balance first, then the
+    smaller separator pair, then the lower key."""
+    from oracle.ordering import _split_keys
+    # keys 0..4 of sizes 2, 1, 1, 3, 1: t = 1 splits 2 | 2 | 4, t = 2 splits 3 | 4 | 1
+    assert _split_keys([2, 1, 1, 3, 1], 0) == 1
+    # keys -3..3: t = -1 and t = 0 both leave imbalance 3 with separators of 7: the lower key
+    assert _split_keys([1, 2, 3, 4, 3, 2, 1], 0) == 2
+    # keys 0..5 of sizes 2, 1, 3, 1, 1, 2: imbalances 2, 0, 4
+    assert _split_keys([2, 1, 3, 1, 1, 2], 0) == 2
+    # vertices outside the root's component count on the high side
+    assert _split_keys([3, 1, 1, 1, 1, 1], 0) == 1
+    assert _split_keys([3, 1, 1, 1, 1, 1], 3) == 2  # imbalances 3, 1, 1: the lower key
