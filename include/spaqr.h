@@ -399,7 +399,10 @@ void spaqr_free(spaqr_handle* h);
  *                     downdated column norms (exact recomputation when a
  *                     norm has lost three digits, exact norms for the rank
  *                     rule), every interface of a colour in one launch;
- *                     0: they take the exact-norm kernels above (default 1);
+ *                     2: as 1, with the interfaces of consecutive colours
+ *                     in one launch, each waiting only for its adjacent
+ *                     interfaces of earlier colours (the same results);
+ *                     0: they take the exact-norm kernels above (default 2);
  *   cpqr_team         1: FP32 interfaces of 65-896 unknowns beyond one
  *                     workgroup take the team CPQR (a team of co-resident
  *                     workgroups per interface, all columns in registers,

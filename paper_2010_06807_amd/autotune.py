@@ -39,7 +39,7 @@ CANDIDATES = {
     "split_cols": [1024, 512, 2048],
     "qr_reg_max_rows": [1024, 512, 256],
     "cpqr_coop": [1, 0],
-    "cpqr_dd": [1, 0],
+    "cpqr_dd": [2, 1, 0],
     "cpqr_team": [2, 1, 0],
     "scale_small": [64, 32],
     "iface_dense": [64, 32],

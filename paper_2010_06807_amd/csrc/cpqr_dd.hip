@@ -25,6 +25,16 @@
 // workgroup's winner on its own, so no second barrier is needed before the
 // update.  Every row class (P rounded up to 8) is a separate unrolled body of
 // the one kernel, so the interfaces of a colour take a single launch.
+//
+// A launch may also span several colours (DDFlow): the sequential order of
+// the sparsification only orders interfaces that share a block, so an
+// interface waits for its adjacent interfaces of earlier colours alone, not
+// for whole colours.  Workgroups take items in ticket order from a counter,
+// and every item waits only on items of smaller tickets, whose workgroups
+// are already running and wait only on smaller tickets still: the waits
+// cannot form a cycle, whatever the residency of the launch.  An item
+// publishes its write-back and rank with an agent-scope release before it
+// marks itself done; a waiter acquires before it reads them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -452,9 +462,50 @@ __device__ __forceinline__ void cpqr_dd_body(const SpDesc<float>& d, const SpNbr
   }
 }
 
+// Bound on the polls of one dependency wait (each a load and a short sleep,
+// seconds in all): a wait that runs out sets *err for the host and goes on,
+// so the kernel always ends.
+constexpr int DD_SPIN = 1 << 24;
+
+__device__ void cpqr_dd_item(const SpDesc<float>& d, const SpNbr* __restrict__ nbrs, int max_nb, int lc_rows,
+                             bool flow);
+
 __global__ void __launch_bounds__(DD_NT) k_cpqr_dd(const SpDesc<float>* __restrict__ descs,
-                                                   const SpNbr* __restrict__ nbrs, int max_nb, int lc_rows) {
-  const SpDesc<float> d = descs[blockIdx.x];
+                                                   const SpNbr* __restrict__ nbrs, int max_nb, int lc_rows,
+                                                   DDFlow fl) {
+  __shared__ int s_item;
+  int item = blockIdx.x;
+  if (fl.ticket) {
+    if (threadIdx.x == 0) {
+      const int t = __hip_atomic_fetch_add(fl.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int q = fl.pred_ptr[t]; q < fl.pred_ptr[t + 1]; ++q) {
+        const int* f = fl.done + fl.pred[q];
+        for (int spin = 0; __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0; ++spin) {
+          if (spin >= DD_SPIN) {
+            __hip_atomic_store(fl.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_item = t;
+    }
+    __syncthreads();
+    item = dd_uni(s_item);
+  }
+  const SpDesc<float> d = descs[item];
+  cpqr_dd_item(d, nbrs, max_nb, lc_rows, fl.ticket != nullptr);
+  if (fl.ticket) {
+    // every thread's stores, then the done mark
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(fl.done + item, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ void cpqr_dd_item(const SpDesc<float>& d, const SpNbr* __restrict__ nbrs, int max_nb, int lc_rows,
+                             bool flow) {
   if (d.P == 0 || *d.flag != 0) return;
   extern __shared__ __align__(16) unsigned char smem[];
   DDShared sh;
@@ -470,7 +521,9 @@ __global__ void __launch_bounds__(DD_NT) k_cpqr_dd(const SpDesc<float>* __restri
     int o = 0;
     for (int b = 0; b < nnb; ++b) {
       sh.off[b] = o;
-      o += d.rank[nb[b].cluster];
+      // ranks of earlier items of a dataflow launch change during it
+      o += flow ? __hip_atomic_load(d.rank + nb[b].cluster, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                : d.rank[nb[b].cluster];
     }
     sh.off[nnb] = o;
   }
@@ -519,8 +572,10 @@ int sparsify_dd_lc_rows(int P, int mmax) {
   return mmax > DD_NT * dd_nc(ps) ? ps : 0;
 }
 
-void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s) {
+void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s,
+                        const DDFlow* flow) {
   if (n <= 0) return;
+  const DDFlow fl = flow ? *flow : DDFlow{nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t lds = dd_lc_offset(max_nb) + (size_t)lc_rows * DD_NT * sizeof(float);
   if (lds > 64 * 1024) {
     static std::mutex mu;
@@ -539,7 +594,7 @@ void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int 
     }
   }
   count_launch("k_cpqr_dd");
-  hipLaunchKernelGGL(k_cpqr_dd, dim3((unsigned)n), dim3(DD_NT), lds, s, d, nb, max_nb, lc_rows);
+  hipLaunchKernelGGL(k_cpqr_dd, dim3((unsigned)n), dim3(DD_NT), lds, s, d, nb, max_nb, lc_rows, fl);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(SPAQR_EDEVICE, std::string("launch of k_cpqr_dd failed: ") + hipGetErrorString(e));
 }

@@ -1607,6 +1607,85 @@ static void sparsify_batch(std::vector<SpDesc<T>>& sd, const std::vector<SpNbr>&
   }
 }
 
+// FP32 interfaces the downdated-norm CPQR takes (as in sparsify_batch).
+static bool dd_takes(const SpDesc<float>& q) {
+  return q.P >= 1 && q.P <= 64 && q.mmax <= sparsify_dd_capacity(q.P);
+}
+
+// Interfaces of consecutive colours gathered for one dataflow launch of the
+// downdated-norm CPQR (cpqr_dd = 2).
+struct DDSegment {
+  std::vector<SpDesc<float>> sd;
+  std::vector<SpNbr> nb;
+  std::vector<int> colour;
+  void add(SpDesc<float> d, const std::vector<SpNbr>& src, int c) {
+    const int64_t o = (int64_t)nb.size();
+    nb.insert(nb.end(), src.begin() + d.nb, src.begin() + d.nb + d.nrow + d.ncol);
+    d.nb = o;
+    sd.push_back(d);
+    colour.push_back(c);
+  }
+};
+
+// Launches a segment: a single colour as before; several colours as one
+// launch in which an interface waits only for its adjacent interfaces of
+// earlier colours (the sequential order of Section 2.6 orders nothing
+// else: an interface's sparsification reads and writes only the blocks it
+// shares with its neighbours, and the ranks of those neighbours).  Items are
+// ordered by colour, then largest first within a colour.
+static void flush_dd_segment(DDSegment& g, Stager& up, DevArena& wk, hipStream_t s, int* err) {
+  if (g.sd.empty()) return;
+  if (g.colour.front() == g.colour.back()) {
+    sparsify_batch<float>(g.sd, g.nb, up, wk, s, err);
+    g = DDSegment{};
+    return;
+  }
+  const size_t n = g.sd.size();
+  std::vector<size_t> ord(n);
+  for (size_t t = 0; t < n; ++t) ord[t] = t;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+    if (g.colour[a] != g.colour[b]) return g.colour[a] < g.colour[b];
+    return (int64_t)g.sd[a].P * g.sd[a].mmax > (int64_t)g.sd[b].P * g.sd[b].mmax;
+  });
+  std::vector<SpDesc<float>> sd(n);
+  std::vector<int> col(n);
+  // an interface is identified by its factorization's size table and cluster
+  std::map<std::pair<const int*, int32_t>, int> at;
+  for (size_t t = 0; t < n; ++t) {
+    sd[t] = g.sd[ord[t]];
+    col[t] = g.colour[ord[t]];
+    at.emplace(std::make_pair(static_cast<const int*>(sd[t].rank), sd[t].cluster), (int)t);
+  }
+  std::vector<int> pp(n + 1, 0), pr;
+  int max_nb = 0, lc_rows = 0;
+  for (size_t t = 0; t < n; ++t) {
+    const SpDesc<float>& q = sd[t];
+    max_nb = std::max(max_nb, q.nrow + q.ncol);
+    lc_rows = std::max(lc_rows, sparsify_dd_lc_rows(q.P, q.mmax));
+    const size_t b0 = pr.size();
+    for (int b = 0; b < q.nrow + q.ncol; ++b) {
+      const auto it = at.find({q.rank, g.nb[q.nb + b].cluster});
+      if (it != at.end() && col[it->second] < col[t]) pr.push_back(it->second);
+    }
+    std::sort(pr.begin() + b0, pr.end());
+    pr.erase(std::unique(pr.begin() + b0, pr.end()), pr.end());
+    pp[t + 1] = (int)pr.size();
+  }
+  if (pr.empty()) pr.push_back(0);
+  SpDesc<float>* dsd = up.upload(wk, sd, s);
+  SpNbr* dnb = up.upload(wk, g.nb, s);
+  int* dpp = up.upload(wk, pp, s);
+  int* dpr = up.upload(wk, pr, s);
+  int* cnt = wk.alloc_n<int>(n + 1, s);
+  launch_zero_ops({{cnt, (int64_t)((n + 1) * sizeof(int))}}, up, wk, s);
+  const DDFlow fl{cnt, cnt + 1, dpp, dpr, err};
+  {
+    ProfScope ps("sparsify", s, 0.0, 0.0);
+    launch_sparsify_dd(dsd, (int64_t)n, dnb, max_nb, lc_rows, s, &fl);
+  }
+  g = DDSegment{};
+}
+
 // One stage of every factorization in es, in two halves: stage_launch plans
 // and enqueues everything up to the rank readback and records bx.ev;
 // stage_finish waits for that event, finishes the stage on the host and
@@ -1865,7 +1944,8 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   }
   bx.pe->record(2, s);
   // sparsification, colour by colour; team_err: set by a team CPQR whose
-  // barrier wait ran out (read back with the ranks, thrown in stage_finish)
+  // barrier wait ran out or a dataflow CPQR whose dependency wait ran out
+  // (read back with the ranks, thrown in stage_finish)
   int* team_err = wk.alloc_n<int>(1, s);
   launch_zero_ops({{team_err, (int64_t)sizeof(int)}}, up, wk, s);
   {
@@ -1877,6 +1957,14 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
   HostScope hs_sp("host_launch_sparsify");
   size_t nsc = 0;
   for (auto& p : pl) nsc = std::max(nsc, p.sp.size());
+  // cpqr_dd = 2: the FP32 interfaces the downdated-norm CPQR takes are
+  // gathered over consecutive colours of fewer such interfaces than the
+  // device has CUs (where one launch per colour leaves most of them idle)
+  // into one dataflow launch, cut before a colour's other interfaces or a
+  // larger colour launch; larger colours keep one launch each, whose host
+  // planning overlaps the previous launch
+  constexpr int kDDFlowMaxColour = 256;
+  DDSegment seg;
   for (size_t c = 0; c < nsc; ++c) {
     std::vector<SpDesc<T>> sd;
     std::vector<SpNbr> nb;
@@ -1889,8 +1977,26 @@ void stage_launch(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
         sd.push_back(d);
       }
     }
+    if constexpr (std::is_same<T, float>::value) {
+      int ndd = 0;
+      for (const SpDesc<T>& d : sd) ndd += dd_takes(d) ? 1 : 0;
+      if (tuning().cpqr_dd == 2 && ndd < kDDFlowMaxColour) {
+        std::vector<SpDesc<T>> rest;
+        for (const SpDesc<T>& d : sd) {
+          if (dd_takes(d)) seg.add(d, nb, (int)c);
+          else rest.push_back(d);
+        }
+        if (!rest.empty()) {
+          flush_dd_segment(seg, up, wk, s, team_err);
+          sparsify_batch<T>(rest, nb, up, wk, s, team_err);
+        }
+        continue;
+      }
+      flush_dd_segment(seg, up, wk, s, team_err);
+    }
     sparsify_batch<T>(sd, nb, up, wk, s, team_err);
   }
+  if constexpr (std::is_same<T, float>::value) flush_dd_segment(seg, up, wk, s, team_err);
   size_t nsu = 0;
   for (auto& p : pl) nsu = std::max(nsu, p.spu.size());
   for (size_t c = 0; c < nsu; ++c) {
@@ -1965,7 +2071,7 @@ void stage_finish(const std::vector<Engine<T>*>& es, BatchCtx& bx, hipStream_t s
     SPAQR_HIP(hipEventSynchronize(bx.ev));
   }
   if (bx.team_err_at >= 0 && reinterpret_cast<const int32_t*>(bx.rb.p)[bx.team_err_at] != 0)
-    throw Error(SPAQR_EDEVICE, "a team CPQR barrier wait ran out (results of the stage invalid)");
+    throw Error(SPAQR_EDEVICE, "a CPQR team barrier or dependency wait ran out (results of the stage invalid)");
   std::vector<MergePlan<T>> mp(ne);
   {
     HostScope hs("host_finish");

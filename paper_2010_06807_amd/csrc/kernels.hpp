@@ -255,7 +255,21 @@ void launch_sparsify_small(const SpDesc<T>* d, int64_t n, const SpNbr* nb, int p
 // (0: its columns fit in registers).  lc_rows = the largest of the launch.
 int sparsify_dd_capacity(int P);
 int sparsify_dd_lc_rows(int P, int mmax);
-void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s);
+// A launch over several colours: workgroups take items in the order of the
+// counter *ticket; item t first waits until done[pred[q]] != 0 for every q in
+// [pred_ptr[t], pred_ptr[t + 1]) (all of them items before t: its adjacent
+// interfaces of earlier colours), then sets done[t] once its results are
+// visible device-wide.  ticket and done[0 .. n) start at zero; *err is set
+// when a bounded wait runs out.
+struct DDFlow {
+  int* ticket;
+  int* done;
+  const int* pred_ptr;
+  const int* pred;
+  int* err;
+};
+void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s,
+                        const DDFlow* flow = nullptr);
 // Apply launches: max_rows = the largest number of FP64 rows one item keeps in
 // LDS per right-hand side (m for fronts forward, n + k backward, P for
 // interfaces).  Returns without launching when there is nothing to do.

@@ -4,7 +4,7 @@
 namespace spaqr {
 
 namespace {
-constexpr spaqr_tuning kDefault = {1024, 1024, 1024, 1, 1, 64, 64, 1, 1, 2};
+constexpr spaqr_tuning kDefault = {1024, 1024, 1024, 1, 1, 64, 64, 1, 2, 2};
 spaqr_tuning g_tuning = kDefault;
 
 bool valid(const spaqr_tuning& t) {
@@ -12,7 +12,7 @@ bool valid(const spaqr_tuning& t) {
   return (t.qr_reg_max_rows == 256 || t.qr_reg_max_rows == 512 || t.qr_reg_max_rows == 1024) &&
          t.split_rows >= 1 && t.split_cols >= 1 && (t.cpqr_reg == 0 || t.cpqr_reg == 1) &&
          (t.cpqr_coop == 0 || t.cpqr_coop == 1) && cls(t.scale_small) &&
-         cls(t.iface_dense) && (t.trail_mfma == 0 || t.trail_mfma == 1) && (t.cpqr_dd == 0 || t.cpqr_dd == 1) &&
+         cls(t.iface_dense) && (t.trail_mfma == 0 || t.trail_mfma == 1) && (t.cpqr_dd >= 0 && t.cpqr_dd <= 2) &&
          (t.cpqr_team >= 0 && t.cpqr_team <= 2);
 }
 }  // namespace
