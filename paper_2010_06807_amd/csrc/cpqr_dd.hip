@@ -78,11 +78,19 @@ __device__ __forceinline__ void dd_for(F&& f) {
 // Butterfly partner for offsets below 16 by DPP lane moves inside a row of
 // 16 lanes (row_mirror, row_half_mirror, two quad permutations); the
 // combination of the four pairings covers all 16 lanes of a row, which is
-// all an all-reduce needs.  Offsets 16 and 32 go through ds_bpermute.
+// all an all-reduce needs.  Offsets 16 and 32 are the exact xor partners,
+// taken with the gfx950 lane swaps (v_permlane16_swap swaps the odd 16-lane
+// rows of its first operand with the even rows of its second,
+// v_permlane32_swap the upper half of the first with the lower half of the
+// second), vector-ALU moves instead of an LDS round trip.
 template <int OFF>
 __device__ __forceinline__ int dd_partner(int v) {
-  if constexpr (OFF >= 16) {
-    return __shfl_xor(v, OFF, 64);
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+  } else if constexpr (OFF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 16) ? r[0] : r[1]);
   } else {
     constexpr int CTRL = OFF == 8 ? 0x140 : (OFF == 4 ? 0x141 : (OFF == 2 ? 0x4E : 0xB1));
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
@@ -108,10 +116,24 @@ __device__ __forceinline__ void dd_level(double& b, int& p) {
   dd_better(dd_partner<OFF>(b), dd_partner<OFF>(p), b, p);
 }
 
+// Sum over the wavefront, the same value on every lane (each level adds a
+// pair of lanes' values in both lanes; addition commutes).
 __device__ __forceinline__ double dd_wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v += dd_partner<32>(v);
+  v += dd_partner<16>(v);
+  v += dd_partner<8>(v);
+  v += dd_partner<4>(v);
+  v += dd_partner<2>(v);
+  v += dd_partner<1>(v);
   return v;
+}
+
+// Lane k's value (k uniform), read into scalar registers.
+__device__ __forceinline__ double dd_lane(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 
 // Makes this wavefront's LDS writes visible to its own later LDS reads.
@@ -303,7 +325,7 @@ __device__ __forceinline__ void cpqr_dd_body(const SpDesc<float>& d, const SpNbr
     const float* xs = sh.slot + (buf * DD_NW + ws) * 64;
     const double x = lane < P ? (double)xs[lane] : 0.0;
     const double s = dd_uni(dd_wave_sum(lane > k ? x * x : 0.0));
-    const double alpha = dd_uni(__shfl(x, k, 64));
+    const double alpha = dd_lane(x, k);
     const double n2 = alpha * alpha + s;
     const double rkk = sqrt(n2);
     if (dd_uni((int)(!fresh && (fabs(n2 - gb) > DD_TRUST * gb || (eps > 0.0 && rkk < eps * R11))))) {
