@@ -69,11 +69,18 @@ __host__ __device__ constexpr int tm_pow2(int x) { return x <= 1 ? 1 : 2 * tm_po
 
 // Partner lane for a butterfly level: DPP lane moves inside a row of 16 lanes
 // for offsets below 16 (row_mirror, row_half_mirror, two quad permutations;
-// together they cover a row), ds_bpermute for 16 and 32.
+// together they cover a row); the exact xor partners for 16 and 32 by the
+// gfx950 lane swaps (v_permlane16_swap: odd 16-lane rows of the first
+// operand with even rows of the second; v_permlane32_swap: upper half of the
+// first with lower half of the second), vector-ALU moves, no LDS.
 template <int OFF>
 __device__ __forceinline__ int tm_partner(int v) {
-  if constexpr (OFF >= 16) {
-    return __shfl_xor(v, OFF, 64);
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+  } else if constexpr (OFF == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 16) ? r[0] : r[1]);
   } else {
     constexpr int CTRL = OFF == 8 ? 0x140 : (OFF == 4 ? 0x141 : (OFF == 2 ? 0x4E : 0xB1));
     return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
