@@ -34,9 +34,35 @@ constexpr int RBMAX = 8; // right-hand sides per apply workgroup
 
 __host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// Exact xor partner at offset 16 or 32 by the gfx950 lane swaps
+// (v_permlane16_swap: odd 16-lane rows of the first operand with even rows of
+// the second; v_permlane32_swap: upper half of the first with lower half of
+// the second), vector-ALU moves instead of an LDS round trip.
+template <int OFF>
+__device__ __forceinline__ int swap_partner(int v) {
+  static_assert(OFF == 16 || OFF == 32, "lane swaps exist for offsets 16 and 32");
+  if constexpr (OFF == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 32) ? r[0] : r[1]);
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+    return (int)((threadIdx.x & 16) ? r[0] : r[1]);
+  }
+}
+template <int OFF>
+__device__ __forceinline__ double swap_partner(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = swap_partner<OFF>((int)(b & 0xffffffffLL));
+  const int hi = swap_partner<OFF>((int)(b >> 32));
+  return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+
+// xor butterfly over the wavefront (every lane gets the same sum)
 __device__ __forceinline__ double wave_sum(double v) {
+  v += swap_partner<32>(v);
+  v += swap_partner<16>(v);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
@@ -471,7 +497,13 @@ __device__ __forceinline__ int dpp_partner(int v) {
 template <int OFF, typename T>
 __device__ __forceinline__ T xshfl(T v) {
   if constexpr (OFF >= 16) {
-    return __shfl_xor(v, OFF, 64);
+    if constexpr (std::is_same<T, int>::value) {
+      return swap_partner<OFF>(v);
+    } else if constexpr (sizeof(T) == 4) {
+      return __int_as_float(swap_partner<OFF>(__float_as_int(v)));
+    } else {
+      return swap_partner<OFF>((double)v);
+    }
   } else if constexpr (std::is_same<T, int>::value) {
     return dpp_partner<OFF>(v);
   } else if constexpr (sizeof(T) == 4) {
