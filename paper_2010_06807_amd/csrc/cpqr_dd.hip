@@ -500,7 +500,8 @@ __global__ void __launch_bounds__(DD_NT) k_cpqr_dd(const SpDesc<float>* __restri
   if (fl.ticket) {
     if (threadIdx.x == 0) {
       const int t = __hip_atomic_fetch_add(fl.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      for (int q = fl.pred_ptr[t]; q < fl.pred_ptr[t + 1]; ++q) {
+      const int q0 = fl.pred_ptr[t], q1 = fl.pred_ptr[t + 1];
+      for (int q = q0; q < q1; ++q) {
         const int* f = fl.done + fl.pred[q];
         for (int spin = 0; __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0; ++spin) {
           if (spin >= DD_SPIN) {
@@ -510,7 +511,8 @@ __global__ void __launch_bounds__(DD_NT) k_cpqr_dd(const SpDesc<float>* __restri
           __builtin_amdgcn_s_sleep(2);
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      // an item that waited on nothing reads only what the launch found
+      if (q1 > q0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_item = t;
     }
     __syncthreads();
@@ -518,8 +520,9 @@ __global__ void __launch_bounds__(DD_NT) k_cpqr_dd(const SpDesc<float>* __restri
   }
   const SpDesc<float> d = descs[item];
   cpqr_dd_item(d, nbrs, max_nb, lc_rows, fl.ticket != nullptr);
-  if (fl.ticket) {
-    // every thread's stores, then the done mark
+  // every thread's stores, then the done mark, for an item that a later
+  // item waits on (fl.succ[item] != 0)
+  if (fl.ticket && dd_uni(fl.succ[item]) != 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(fl.done + item, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -597,7 +600,7 @@ int sparsify_dd_lc_rows(int P, int mmax) {
 void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s,
                         const DDFlow* flow) {
   if (n <= 0) return;
-  const DDFlow fl = flow ? *flow : DDFlow{nullptr, nullptr, nullptr, nullptr, nullptr};
+  const DDFlow fl = flow ? *flow : DDFlow{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const size_t lds = dd_lc_offset(max_nb) + (size_t)lc_rows * DD_NT * sizeof(float);
   if (lds > 64 * 1024) {
     static std::mutex mu;

@@ -1671,14 +1671,17 @@ static void flush_dd_segment(DDSegment& g, Stager& up, DevArena& wk, hipStream_t
     pr.erase(std::unique(pr.begin() + b0, pr.end()), pr.end());
     pp[t + 1] = (int)pr.size();
   }
+  std::vector<int> succ(n, 0);
+  for (int q : pr) succ[q] = 1;
   if (pr.empty()) pr.push_back(0);
   SpDesc<float>* dsd = up.upload(wk, sd, s);
   SpNbr* dnb = up.upload(wk, g.nb, s);
   int* dpp = up.upload(wk, pp, s);
   int* dpr = up.upload(wk, pr, s);
+  int* dsu = up.upload(wk, succ, s);
   int* cnt = wk.alloc_n<int>(n + 1, s);
   launch_zero_ops({{cnt, (int64_t)((n + 1) * sizeof(int))}}, up, wk, s);
-  const DDFlow fl{cnt, cnt + 1, dpp, dpr, err};
+  const DDFlow fl{cnt, cnt + 1, dpp, dpr, dsu, err};
   {
     ProfScope ps("sparsify", s, 0.0, 0.0);
     launch_sparsify_dd(dsd, (int64_t)n, dnb, max_nb, lc_rows, s, &fl);

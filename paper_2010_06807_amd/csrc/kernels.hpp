@@ -258,14 +258,16 @@ int sparsify_dd_lc_rows(int P, int mmax);
 // A launch over several colours: workgroups take items in the order of the
 // counter *ticket; item t first waits until done[pred[q]] != 0 for every q in
 // [pred_ptr[t], pred_ptr[t + 1]) (all of them items before t: its adjacent
-// interfaces of earlier colours), then sets done[t] once its results are
-// visible device-wide.  ticket and done[0 .. n) start at zero; *err is set
-// when a bounded wait runs out.
+// interfaces of earlier colours), then, when succ[t] != 0 (some later item
+// waits on it), sets done[t] once its results are visible device-wide.
+// ticket and done[0 .. n) start at zero; *err is set when a bounded wait runs
+// out.
 struct DDFlow {
   int* ticket;
   int* done;
   const int* pred_ptr;
   const int* pred;
+  const int* succ;
   int* err;
 };
 void launch_sparsify_dd(const SpDesc<float>* d, int64_t n, const SpNbr* nb, int max_nb, int lc_rows, hipStream_t s,
