@@ -865,8 +865,12 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
   T* VQ = ib_.vq;
   T* TAUQ = ib_.tauq;
   int* FLAGS = ib_.flags;
-  // sparsification, colour by colour
+  // sparsification, colour by colour; CPQR workspaces: (colour, index,
+  // offsets of C, the norms and the permutation)
+  std::vector<std::array<int64_t, 5>> ws_at;
+  int64_t wc_max = 0, wn_max = 0, wp_max = 0;
   for (size_t c = 0; c + 1 < ss.iface_colour_ptr.size(); ++c) {
+    int64_t wc = 0, wn = 0, wp = 0;
     typename StagePlan<T>::SpColour col;
     for (int32_t oi = ss.iface_colour_ptr[c]; oi < ss.iface_colour_ptr[c + 1]; ++oi) {
       const IfaceSym& I = ss.ifaces[ss.iface_order[oi]];
@@ -898,16 +902,33 @@ void Engine<T>::plan_sparsify(StagePlan<T>& P) {
       d.rank = d_rank_;
       d.eps = o_.eps;
       // the LDS/global kernels need a workspace; the register kernel needs
-      // one only for its columns in global memory
+      // one only for its columns in global memory.  Offsets restart with
+      // each colour: the colours run in stream order, so one region sized
+      // for the largest colour serves them all
       if (!tuning().cpqr_reg || sparsify_reg_cpt(sizeof(T), Pn, d.mmax) == 0 ||
           sparsify_reg_global(sizeof(T), Pn, d.mmax)) {
-        d.C = work_.alloc_n<T>((size_t)(Pn <= 64 ? 65 : Pn) * d.mmax, s_);
-        d.nrm = work_.alloc_n<double>((size_t)d.mmax, s_);
-        d.perm = work_.alloc_n<int32_t>(2 * (size_t)d.mmax, s_);
+        ws_at.push_back({(int64_t)P.sp.size(), (int64_t)col.sd.size(), wc, wn, wp});
+        wc += (int64_t)(Pn <= 64 ? 65 : Pn) * d.mmax;
+        wn += d.mmax;
+        wp += 2 * (int64_t)d.mmax;
       }
       col.sd.push_back(d);
     }
+    wc_max = std::max(wc_max, wc);
+    wn_max = std::max(wn_max, wn);
+    wp_max = std::max(wp_max, wp);
     P.sp.push_back(std::move(col));
+  }
+  if (!ws_at.empty()) {
+    T* WC = work_.alloc_n<T>((size_t)wc_max, s_);
+    double* WN = work_.alloc_n<double>((size_t)wn_max, s_);
+    int32_t* WP = work_.alloc_n<int32_t>((size_t)wp_max, s_);
+    for (const auto& w : ws_at) {
+      SpDesc<T>& d = P.sp[w[0]].sd[w[1]];
+      d.C = WC + w[2];
+      d.nrm = WN + w[3];
+      d.perm = WP + w[4];
+    }
   }
   // apply descriptors of the interfaces; those of at most 64 unknowns get
   // their dense forward and backward operators

@@ -5,6 +5,7 @@
 #include <mutex>
 #include <set>
 #include <unordered_map>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -77,7 +78,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
   }
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
-    throw Error(SPAQR_ENOMEM, "device allocation failed");
+    throw Error(SPAQR_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed");
   }
   g_size[p] = sz;
   return p;

@@ -63,7 +63,8 @@ PAPER_HC = {
 HC_N = (127, 255, 511, 1023)
 
 
-def run(series, max_n=1024, tol=1e-12, log=print):
+def run(series, max_n=1024, tol=1e-12, log=print, only_n=None, only_eps=None):
+    import gc
     import numpy as np
     import torch
     import paper_2010_06807_amd as P
@@ -85,6 +86,10 @@ def run(series, max_n=1024, tol=1e-12, log=print):
     if "hc" in series:
         cases += [("hc", f"rho={r:g}", n, dict(rho=r), 1e-2) for r in (1.0, 10.0, 100.0) for n in ns2 if n <= 512]
     cases = [c + (True,) for c in cases]
+    if only_n:
+        cases = [c for c in cases if c[2] in only_n]
+    if only_eps:
+        cases = [c for c in cases if any(abs(c[4] - e) <= 1e-3 * e for e in only_eps)]
     if "hc_abl" in series:
         cases += [("hc", f"rho={r} eps={e:.0e} {'scaled' if sc else 'unscaled'}".replace("e-0", "e-"), n,
                    dict(rho=float(r)), e, sc)
@@ -117,7 +122,10 @@ def run(series, max_n=1024, tol=1e-12, log=print):
                    paper_iterations=pit)
         out.append(rec)
         log(json.dumps(rec))
-        del fac
+        del fac, x
+        gc.collect()
+        print(f"[reproduce] device memory free after the case: {torch.cuda.mem_get_info()[0] / 2**30:.1f} GiB",
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -126,8 +134,13 @@ def main():
     ap.add_argument("series", nargs="*", default=["ad2_q", "ad2_eps", "ad3", "hc", "hc_abl"])
     ap.add_argument("--max-n", type=int, default=1024)
     ap.add_argument("--json", default=None)
+    ap.add_argument("--n", type=int, nargs="*", default=None,
+                    help="run only the cases of these sizes (the largest 3D cases each want a fresh process: "
+                         "device memory freed by one factorization stays in the library's cache and the "
+                         "stream-ordered pool, in blocks a differently sized factorization may not reuse)")
+    ap.add_argument("--eps", type=float, nargs="*", default=None, help="run only the cases of these tolerances")
     a = ap.parse_args()
-    res = run(a.series, a.max_n, log=lambda s: print(s, file=sys.stderr, flush=True))
+    res = run(a.series, a.max_n, log=lambda s: print(s, file=sys.stderr, flush=True), only_n=a.n, only_eps=a.eps)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(res, f, indent=1)
