@@ -487,6 +487,7 @@ void spaqr_finalize(void) {
 void spaqr_free(spaqr_handle* h) {
   try {
     delete h;
+    spaqr::mem_trim_if_large();
   } catch (...) {
   }
 }

@@ -29,6 +29,7 @@ struct Block {
 std::mutex g_dmu;
 std::multimap<size_t, Block> g_cache;         // free blocks by size
 std::unordered_map<void*, size_t> g_size;     // size of every live block
+size_t g_cached = 0;                          // bytes in g_cache
 
 size_t round_block(size_t b) {
   if (b <= (size_t(1) << 20)) return (b + 4095) & ~size_t(4095);
@@ -40,6 +41,7 @@ size_t round_block(size_t b) {
 void flush_cache() {
   for (auto& kv : g_cache) (void)hipFreeAsync(kv.second.p, kv.second.s);
   g_cache.clear();
+  g_cached = 0;
   (void)hipDeviceSynchronize();
 }
 }  // namespace
@@ -65,6 +67,7 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     if (it->second.s == s) {
       void* p = it->second.p;
       g_size[p] = it->first;
+      g_cached -= it->first;
       g_cache.erase(it);
       return p;
     }
@@ -93,7 +96,23 @@ void dev_free(void* p, hipStream_t s) {
     return;
   }
   g_cache.insert({it->second, Block{p, s}});
+  g_cached += it->second;
   g_size.erase(it);
+}
+
+void mem_trim_if_large() {
+  std::lock_guard<std::mutex> lk(g_dmu);
+  size_t fr = 0, total = 0;
+  if (g_cache.empty() || hipMemGetInfo(&fr, &total) != hipSuccess || g_cached <= total / 4) {
+    (void)hipGetLastError();
+    return;
+  }
+  flush_cache();
+  int dev = 0;
+  hipMemPool_t mp = nullptr;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&mp, dev) == hipSuccess && mp)
+    (void)hipMemPoolTrimTo(mp, 0);
+  (void)hipGetLastError();
 }
 
 void mem_release_all() {
@@ -103,6 +122,7 @@ void mem_release_all() {
       (void)hipDeviceSynchronize();
       for (auto& kv : g_cache) (void)hipFree(kv.second.p);
       g_cache.clear();
+      g_cached = 0;
     }
   }
   std::lock_guard<std::mutex> lk(g_mu);

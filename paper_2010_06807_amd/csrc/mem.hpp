@@ -22,6 +22,11 @@ void dev_free(void* p, hipStream_t s);            // stream-ordered, NULL is a n
 // runtime (after a device synchronization).  Blocks and chunks still held
 // by live objects are untouched; the caches refill on demand afterwards.
 void mem_release_all();
+// When the freed blocks the library keeps for reuse exceed a quarter of the
+// device's memory (a large factorization just ended), returns them to the
+// stream-ordered pool and the pool's unused pages to the device, so that a
+// differently sized factorization can map them (synchronizes the device).
+void mem_trim_if_large();
 
 struct PinnedChunk {
   char* p = nullptr;

@@ -135,9 +135,7 @@ def main():
     ap.add_argument("--max-n", type=int, default=1024)
     ap.add_argument("--json", default=None)
     ap.add_argument("--n", type=int, nargs="*", default=None,
-                    help="run only the cases of these sizes (the largest 3D cases each want a fresh process: "
-                         "device memory freed by one factorization stays in the library's cache and the "
-                         "stream-ordered pool, in blocks a differently sized factorization may not reuse)")
+                    help="run only the cases of these sizes")
     ap.add_argument("--eps", type=float, nargs="*", default=None, help="run only the cases of these tolerances")
     a = ap.parse_args()
     res = run(a.series, a.max_n, log=lambda s: print(s, file=sys.stderr, flush=True), only_n=a.n, only_eps=a.eps)
