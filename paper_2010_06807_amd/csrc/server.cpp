@@ -273,7 +273,11 @@ spaqr_status spaqr_server_step(spaqr_server* srv, int* active) {
       const int st = r->eng->error() != SPAQR_OK ? r->eng->error() : result[r.get()];
       retire(srv, std::move(r), st);
     }
+    const bool retired = keep.size() < srv->active.size();
     srv->active.swap(keep);
+    // requests of many sizes pass through one server: return what the
+    // retired ones freed once the cache holds a large share of the device
+    if (retired) mem_trim_if_large();
     if (active) *active = (int)(srv->active.size() + srv->queue.size());
     return SPAQR_OK;
   });
